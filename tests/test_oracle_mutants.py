@@ -1,0 +1,62 @@
+"""The pins must notice plausible mistakes: each test here plants one mistake in a
+copy of the oracle source (on the CPU), rebuilds it, and requires at least one
+pin to fail against it."""
+import os
+
+import pytest
+
+from oracle import oracle as O
+from tests import test_oracle_pins as pins
+
+SRC = open(O.SRC).read()
+
+MUTANTS = {
+    "fill_rule_flipped": ("topleft[e] = (dy < 0) || (dy == 0 && dx < 0);",
+                          "topleft[e] = (dy > 0) || (dy == 0 && dx > 0);"),
+    "pixel_centre_offset": ("int64_t px = i * 256 + 128;", "int64_t px = i * 256;"),
+    "anchor_uses_wrong_gradient": ("za = (Z[0] + gx * (((double)i0 + 0.5)", "za = (Z[0] + gy * (((double)i0 + 0.5)"),
+    "depth_fraction_bits": ("(j - j0) * gyf, 16);", "(j - j0) * gyf, 15);"),
+    "farthest_depth_wins": ("if ((uint32_t)D < map[j * (int64_t)n + i])", "if ((uint32_t)D > map[j * (int64_t)n + i] || map[j * (int64_t)n + i] == OR_DMAX)"),
+    "constant_bias_only": ("double b = ceil((0.5 + 1.0 / 512.0) * (gxs + gys)) + 2.0;", "double b = 2.0;"),
+    "shade_test_reversed": ("int shaded = zs > ", "int shaded = zs < "),
+    "sample_index_mixup": ("double fu = ((double)(k * cu + a) + 0.5)", "double fu = ((double)(k * cu + b) + 0.5)"),
+    "view_toward_sun": ("V->d = mk(-s.x, -s.y, -s.z);", "V->d = mk(s.x, s.y, s.z);"),
+    "window_without_margin": ("V->itx = (double)(n - 2) / su;", "V->itx = (double)(n) / su;"),
+    "clip_midpoint": ("out[m][k] = p[k] + (r[k] - p[k]) * t;", "out[m][k] = p[k] + (r[k] - p[k]) * 0.5;"),
+    "string_count_off_by_one": ("double p = (double)(j + 1) * caps[j];", "double p = (double)(j) * caps[j];"),
+    "diffuse_dropped": ("double g = beam[m] * (1.0 - f) + d_poa;", "double g = beam[m] * (1.0 - f);"),
+    "back_lit_tested": ("if (!(cm > 0.0) || !V.valid) continue;\n        double nx = dot3(nh, V.e1), ny = dot3(nh, V.e2), nz = dot3(nh, V.d);\n        double gxs",
+                        "if (!V.valid) continue;\n        double nx = dot3(nh, V.e1), ny = dot3(nh, V.e2), nz = dot3(nh, V.d);\n        double gxs"),
+    "far_cull_inverted": ("if (zmin > (double)OR_DMAX) return;", "if (zmin < (double)OR_DMAX) return;"),
+}
+
+PINS = [
+    (pins.test_c1_matches_exact_ray_casting, {}),
+    (pins.test_c1_loss_closed_form, {"d_poa": 100.0, "want": 0.04670964}),
+    (pins.test_string_power_is_best_operating_current, {}),
+    (pins.test_fill_rule_covers_each_centre_once, {"seed": 0, "x0": 10.5, "y0": 7.5, "step": 4.0, "jitter": 0.0}),
+    (pins.test_fill_rule_covers_each_centre_once, {"seed": 1, "x0": 10.5, "y0": 7.5, "step": 3.0, "jitter": 0.6}),
+    (pins.test_depth_within_one_unit_of_exact_plane, {}),
+    (pins.test_nearest_depth_wins_and_order_does_not_matter, {}),
+    (pins.test_guard_band_clip_keeps_coverage_and_plane, {}),
+    (pins.test_generator_alone_is_never_shaded, {}),
+    (pins.test_back_lit_module_is_not_tested, {}),
+    (pins.test_pole_shadow_length_on_flat_receiver, {"day": 355}),
+    (pins.test_agrees_with_ray_casting_outside_band, {"seed": 21}),
+]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTANTS[name]
+    assert SRC.count(old) == 1, f"mutation site for {name} not found once"
+    lib = O.build_variant(SRC.replace(old, new), str(tmp_path / f"mut_{name}.so"))
+    caught = []
+    with O.use_library(lib):
+        for fn, kw in PINS:
+            try:
+                fn(O, **kw)
+            except (AssertionError, ValueError, IndexError):
+                caught.append(fn.__name__)
+                break
+    assert caught, f"no pin fails when the oracle has mistake '{name}'"
