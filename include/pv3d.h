@@ -1,0 +1,195 @@
+/*
+ * pv3d.h -- C ABI of libpv3d: GPU shadow-map shading losses of PV generators
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Robledo, Leloux & Lorenzo, arXiv:1410.5780, Sec. 2. The library
+ * follows the paper's four steps:
+ *   Step 1  import the 3D scene            -> pv3d_scene_load
+ *   Step 2  define the PV system           -> pv3d_generator_define
+ *   Step 3  evaluate the shadows           -> pv3d_evaluate (depth picture from
+ *           the sun, limited to the generator; depth check of sub-cell samples)
+ *   Step 4  translate shading into losses  -> pv3d_evaluate (beam removed from
+ *           shaded areas, bypass-diode string model, integration over time)
+ * plus a batched form (all suns of many jobs in one persistent launch) and a
+ * serving form (jobs submitted while others run).
+ *
+ * Conventions shared by every call:
+ *  - Coordinates are ENU metres (x east, y north, z up), binary64.
+ *  - Every call returns pv3d_status: 0 on success, a negative code on error.
+ *    Nothing throws or aborts across the ABI; pv3d_last_error() describes the
+ *    last failure of the calling thread.
+ *  - Input arrays are host memory and are copied before the call returns; the
+ *    caller keeps ownership.
+ *  - Output arrays are caller-allocated; pv3d_outputs.on_device tells whether
+ *    they are host memory or device memory of the context's GPU.
+ *  - Handles (scenes, generators, tickets) belong to the context and are freed
+ *    by pv3d_destroy.
+ *  - Limits: 16 <= map_n <= 16384; 1 <= k <= 255; n_cu, n_cv in [1, 4096];
+ *    n_vert, n_tri < 2^31; at least one module; all modules share n_cu, n_cv.
+ *
+ * Threading: a context may be used from one thread at a time, except that
+ * pv3d_poll / pv3d_wait / pv3d_cancel may be called from any thread while the
+ * serving loop runs.
+ */
+#ifndef PV3D_H
+#define PV3D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pv3d_status;
+#define PV3D_OK 0
+#define PV3D_EINVAL (-1)     /* bad argument (NaN/Inf, sizes, unknown flags, non-unit sun) */
+#define PV3D_ENOMEM (-2)     /* does not fit the context's HBM budget (or device memory) */
+#define PV3D_ENOENT (-3)     /* unknown scene / generator / ticket handle */
+#define PV3D_EDEVICE (-4)    /* HIP runtime error */
+#define PV3D_ERANGE (-5)     /* a documented limit was exceeded */
+#define PV3D_EBUSY (-6)      /* serving queue full, retry later */
+#define PV3D_ECANCELED (-7)  /* job was cancelled */
+
+typedef struct pv3d_ctx pv3d_ctx;
+
+/* Create a context on HIP device `device`. hbm_budget_bytes caps the device
+ * memory the context may hold (scenes, generators, work buffers); 0 means 90%
+ * of the device's free memory. The context owns one HIP stream. */
+pv3d_status pv3d_create(int32_t device, uint64_t hbm_budget_bytes, pv3d_ctx** out);
+
+/* Free every scene, generator, job and buffer of the context (waits for the
+ * device first). NULL is ignored. */
+void pv3d_destroy(pv3d_ctx* ctx);
+
+/* Text of the calling thread's last error; valid until its next call. */
+const char* pv3d_last_error(const pv3d_ctx* ctx);
+
+/* Step 1 (Sec. 2, "Import the 3D scene"): a triangle soup.
+ * xyz: [n_vert][3] vertex positions; tri: [n_tri][3] vertex indices.
+ * Both faces of a triangle cast shadows. Copied to device memory.
+ * EINVAL: non-finite coordinate, index out of range, n_vert/n_tri < 0.
+ * ENOMEM: does not fit the budget. */
+pv3d_status pv3d_scene_load(pv3d_ctx* ctx, const double* xyz, int64_t n_vert,
+                            const int32_t* tri, int64_t n_tri, uint64_t* scene_out);
+pv3d_status pv3d_scene_release(pv3d_ctx* ctx, uint64_t scene);
+
+/* Step 2 (Sec. 2, "Define the PV system"; Fig. 2): rectangular modules split
+ * into cells, cells grouped into bypass-diode substrings, modules in series
+ * strings.
+ * Module m covers origin + a*edge_u + b*edge_v, a, b in [0, 1]; its front
+ * face is the side edge_u x edge_v points to. It holds n_cu cells along
+ * edge_u and n_cv along edge_v; cell (cu, cv) has index cv*n_cu + cu.
+ * cell_substring: [n_cu*n_cv] substring (0 .. n_sub_per_module-1) of each
+ *   cell, the same for every module; every substring must own a cell.
+ * module_string: [n_mod] series string of each module (0 .. n_string-1, every
+ *   string non-empty); within a string, modules count in array order.
+ * add_as_occluders: 1 = each module is also drawn as two triangles
+ *   (origin, +u, +u+v) and (origin, +u+v, +v) so modules shade each other.
+ * EINVAL: degenerate module, mixed n_cu/n_cv, bad maps. */
+typedef struct {
+    double origin[3];
+    double edge_u[3];
+    double edge_v[3];
+    int32_t n_cu, n_cv;
+} pv3d_module;
+
+pv3d_status pv3d_generator_define(pv3d_ctx* ctx, const pv3d_module* mods, int64_t n_mod,
+                                  const int32_t* cell_substring, int32_t n_sub_per_module,
+                                  const int32_t* module_string, int32_t add_as_occluders,
+                                  uint64_t* gen_out);
+pv3d_status pv3d_generator_release(pv3d_ctx* ctx, uint64_t gen);
+
+/* Helper (host): sun unit vectors for day-of-year and local solar hour at a
+ * latitude, with Cooper's declination and 15 degrees of hour angle per hour
+ * (the paper only states that the solar position is defined, Sec. 2 Step 3).
+ * sun_xyz_out: [n][3]; s_z <= 0 means the sun is not above the horizon. */
+pv3d_status pv3d_sun_cooper(double lat_deg, const int32_t* day, const double* solar_hour,
+                            int64_t n, double* sun_xyz_out);
+
+/* Steps 3 and 4 (Sec. 2). flags: */
+#define PV3D_EXPORT_DEPTH 1u   /* write every sun's depth picture to outputs.depth_maps */
+#define PV3D_EXPORT_BITS 2u    /* write every sample's shaded flag to outputs.shaded_bits */
+
+typedef struct {
+    int32_t map_n;     /* depth picture is map_n x map_n texels */
+    int32_t k;         /* k x k sample points per cell (Sec. 2 Step 3 uses 3 x 3) */
+    uint32_t flags;    /* PV3D_EXPORT_* */
+    int32_t tile;      /* raster tile edge in texels: 0 = library's choice, else 32/64/128 */
+} pv3d_params;
+
+/* Outputs (all optional except power, power_ref, energy):
+ * cell_counts: [n_sun][n_cells] shaded samples per cell (cells in module,
+ *   then cell-index order); a cell's shaded fraction is count / k^2.
+ * power, power_ref: [n_sun] generator power with and without shading
+ *   (W, with current proportional to irradiance and unit substring voltage).
+ * energy: [2] sum over suns of power * dt_h and power_ref * dt_h, in sun
+ *   order; the shading loss is 1 - energy[0] / energy[1].
+ * depth_maps: [n_sun][map_n][map_n] 24-bit depths in uint32 (row j = image
+ *   axis e2, column i = image axis e1); suns below the horizon read 2^24-1.
+ * shaded_bits: [n_sun][n_cells][ceil(k*k/32)] uint32 words; bit t of word w
+ *   is sample 32*w + t of the cell, sample index b*k + a (a along edge_u).
+ * on_device: 1 = every pointer is device memory of this context's GPU; then
+ *   the call is asynchronous in stream order on hip_stream. 0 = host memory;
+ *   the call returns when the results are in place. */
+typedef struct {
+    uint32_t* cell_counts;
+    double* power;
+    double* power_ref;
+    double* energy;
+    uint32_t* depth_maps;
+    uint32_t* shaded_bits;
+    int32_t on_device;
+} pv3d_outputs;
+
+/* Evaluate one generator in one scene for a sweep of sun positions, one sun
+ * at a time (a launch sequence per sun).
+ * sun_xyz: [n_sun][3] unit vectors toward the sun (|s| = 1 within 1e-9);
+ * dni: [n_sun] direct normal irradiance; d_poa: [n_sun] diffuse irradiance on
+ * the module plane; dt_h: [n_sun] hours each sun stands for. Host memory.
+ * hip_stream: a hipStream_t of this device, or NULL for the context stream.
+ * EINVAL: bad params or inputs; ENOENT: bad handle; ENOMEM: budget. */
+pv3d_status pv3d_evaluate(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const double* sun_xyz,
+                          const double* dni, const double* d_poa, const double* dt_h,
+                          int64_t n_sun, const pv3d_params* params, pv3d_outputs* out,
+                          void* hip_stream);
+
+/* One job = one (scene, generator, sweep) evaluation. Its input arrays must
+ * stay valid until the call that takes the job returns; its outputs until the
+ * job completes. */
+typedef struct {
+    uint64_t scene;
+    uint64_t gen;
+    const double* sun_xyz;
+    const double* dni;
+    const double* d_poa;
+    const double* dt_h;
+    int64_t n_sun;
+    pv3d_params params;
+    pv3d_outputs out;
+} pv3d_job;
+
+/* All suns of all jobs in one persistent launch: workgroups pull (job, sun)
+ * items from a device queue, so uneven scenes balance across the GPU. Results
+ * are identical to pv3d_evaluate on each job. EXPORT flags are not accepted
+ * here (EINVAL). */
+pv3d_status pv3d_evaluate_batched(pv3d_ctx* ctx, const pv3d_job* jobs, int64_t n_jobs,
+                                  void* hip_stream);
+
+/* Serving: submit a job to the context's running service loop. It is
+ * admitted when its working set fits the HBM budget, then its suns join the
+ * device queue that is already being drained; results are identical to
+ * pv3d_evaluate. EBUSY when the pending queue is full; ENOMEM when the job
+ * can never fit. ticket identifies the job. */
+pv3d_status pv3d_submit(pv3d_ctx* ctx, const pv3d_job* job, uint64_t* ticket);
+/* done = 1 once the job's outputs are in place, 0 while it runs. */
+pv3d_status pv3d_poll(pv3d_ctx* ctx, uint64_t ticket, int32_t* done);
+/* Block until the job is done; ECANCELED if it was cancelled. Forgets the ticket. */
+pv3d_status pv3d_wait(pv3d_ctx* ctx, uint64_t ticket);
+/* Cancel a job that has not completed; its outputs are left undefined. */
+pv3d_status pv3d_cancel(pv3d_ctx* ctx, uint64_t ticket);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PV3D_H */

@@ -1,0 +1,116 @@
+// Device-side data layout and kernel entry points of libpv3d (gfx950).
+//
+// Light space of one sun (Sec. 2, Step 3 of arXiv:1410.5780): an orthographic
+// view along d = -s whose window is the generator's footprint seen from the
+// sun. x, y are texel coordinates along the image axes e1, e2; z is depth in
+// units of 2^-24 of the range [near side of the scene's bounding sphere,
+// generator's farthest corner]. Pixel (i, j) is sampled at its centre
+// (i + 1/2, j + 1/2); the depth picture keeps the nearest depth per pixel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pv3d {
+
+constexpr int kSubBits = 8;                    // vertices snap to 1/256 texel
+constexpr uint32_t kDepthMax = 0xFFFFFFu;      // 24-bit depth, 2^24 - 1 = farthest
+constexpr double kGuard = 2097152.0;           // 2^21 texels: clip square for huge triangles
+constexpr int kWave = 64;
+
+// Per-sun view: 128 bytes.
+struct View {
+    double e1[3], e2[3], d[3];
+    double ox, oy, itx, ity;   // texel x = (p.e1 - ox) * itx, y = (p.e2 - oy) * ity
+    double znear, izd;         // depth z = (p.d - znear) * izd
+    int32_t valid;             // 0: nothing drawn or tested (sun down / all modules back-lit)
+    int32_t pad;
+};
+
+// Per-module generator data, 128 bytes: geometry and unit front normal.
+struct Module {
+    double o[3], u[3], v[3];
+    double n[3];
+    double pad[4];
+};
+
+// Set-up triangle ready for raster: 80 bytes.
+// Edge k at pixel (i, j): E = e0[k] + 256 * (a[k] * i + b[k] * j); the pixel
+// centre is inside when all three are >= 0 (the -1 of non top-left edges is
+// folded into e0). Depth: floor((z0 + i * gx + j * gy) / 2^16), clamped.
+struct TriRec {
+    int64_t e0[3];
+    int64_t z0, gx, gy;
+    int32_t a[3], b[3];
+    int16_t ilo, ihi, jlo, jhi;   // covered pixels lie in [ilo, ihi] x [jlo, jhi]
+};
+static_assert(sizeof(TriRec) == 80, "TriRec layout");
+
+// Per-sun scratch counters, one slot per sun.
+struct SunCounters {
+    int32_t n_rec;      // set-up triangles written
+    int32_t n_large;    // triangles handled by every tile instead of binned
+    int32_t overflow;   // 1 if a buffer was too small for this sun
+    int32_t pad;
+};
+
+// Where one sun's triangle set-up and binning write.
+struct BinBuffers {
+    TriRec* rec;
+    int32_t rec_cap;
+    int32_t* large;        // [rec_cap] record ids of large triangles
+    int32_t* tile_count;   // [n_tiles] (zero between suns)
+    int32_t* tile_start;   // [n_tiles + 1]
+    int32_t* tile_cursor;  // [n_tiles]
+    int32_t* bins;         // [bin_cap]
+    int32_t bin_cap;
+    int32_t tile;          // tile edge in texels
+    int32_t ntx;           // tiles per row
+    int32_t large_tiles;   // triangles touching more tiles than this go to the large list
+};
+
+// Generator as the kernels see it.
+struct GenDev {
+    const Module* mods;
+    int32_t n_mod, n_cu, n_cv, n_sub, n_str;
+    int32_t occluders;
+    const int32_t* cell_sub;    // [n_cu*n_cv]
+    const int32_t* str_start;   // [n_str + 1] CSR of modules per string
+    const int32_t* str_mods;    // [n_mod]
+};
+
+struct SceneDev {
+    const double* xyz;
+    const int32_t* tri;
+    int64_t n_vert, n_tri;
+};
+
+// ---- launch wrappers (pv3d_kernels.hip) -----------------------------------
+hipError_t launch_module_normals(Module* mods, int32_t n_mod, hipStream_t st);
+hipError_t launch_bounds(const SceneDev& sc, const GenDev& g, double* partial, int32_t n_part,
+                         double* sphere, hipStream_t st);
+int32_t bounds_partials(int64_t n_points);
+hipError_t launch_sample_tables(double* fu, double* fv, int32_t k, int32_t n_cu, int32_t n_cv,
+                                hipStream_t st);
+hipError_t launch_setup(const double* sun, int64_t n_sun, const double* dni, const GenDev& g,
+                        const double* sphere, int32_t n, View* views, double* beam, int32_t* bias,
+                        hipStream_t st);
+hipError_t launch_tri_setup(int64_t s, const View* views, const SceneDev& sc, const GenDev& g,
+                            int32_t n, const BinBuffers& bb, SunCounters* ctr, hipStream_t st);
+hipError_t launch_bin_scan(int32_t n_tiles, const BinBuffers& bb, hipStream_t st);
+hipError_t launch_bin_scatter(int64_t s, const BinBuffers& bb, int32_t n_tiles,
+                              SunCounters* ctr, hipStream_t st);
+hipError_t launch_raster(int64_t s, const View* views, const BinBuffers& bb, const SunCounters* ctr,
+                         int32_t n, uint32_t* map, hipStream_t st);
+hipError_t launch_sample_test(int64_t s, const View* views, const GenDev& g, const double* beam,
+                              const int32_t* bias, const double* fu, const double* fv, int32_t k,
+                              const uint32_t* map, int32_t n, uint32_t* counts, uint32_t* bits,
+                              hipStream_t st);
+hipError_t launch_loss(int64_t n_sun, const double* sun, const double* beam, const uint32_t* counts,
+                       const double* d_poa, const GenDev& g, int32_t k, double* power,
+                       double* power_ref, hipStream_t st);
+hipError_t launch_energy(int64_t n_sun, const double* power, const double* power_ref,
+                         const double* dt, double* energy, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+
+}  // namespace pv3d

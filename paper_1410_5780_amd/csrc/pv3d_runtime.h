@@ -1,0 +1,115 @@
+// Host-side state of libpv3d (internal; the public ABI is include/pv3d.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/pv3d.h"
+#include "pv3d_device.h"
+
+namespace pv3d {
+
+struct Ctx;
+
+pv3d_status fail(pv3d_status code, const char* fmt, ...);
+pv3d_status hip_fail(hipError_t e, const char* what);
+pv3d_status check_params(const pv3d_params* p);
+pv3d_status check_sweep(const double* sun, const double* dni, const double* dpoa, const double* dt, int64_t n);
+
+// Grow-only device buffer.
+struct Buf {
+    void* ptr = nullptr;
+    size_t cap = 0;
+    pv3d_status ensure(Ctx* c, size_t bytes, const char* what);
+    void release(Ctx* c);
+};
+
+struct Scene {
+    double* xyz = nullptr;
+    int32_t* tri = nullptr;
+    int64_t n_vert = 0, n_tri = 0;
+};
+
+struct Gen {
+    Module* mods = nullptr;
+    int32_t* cell_sub = nullptr;
+    int32_t* str_start = nullptr;
+    int32_t* str_mods = nullptr;
+    int64_t n_mod = 0;
+    int32_t n_cu = 0, n_cv = 0, n_sub = 0, n_str = 0, occluders = 0;
+};
+
+struct PathSizes {
+    int32_t tile, ntx, n_tiles, large_tiles, words;
+    int64_t tri_total, rec_cap, bin_cap, cells, n_sun;
+};
+
+struct Work {
+    Buf rec, large, bins, tile_count, tile_start, tile_cursor, map;
+    Buf views, ctr, beam, bias, sweep, sphere, partial, fu, fv;
+    Buf counts, outd, maps, bits;
+    void release_all(Ctx* c) {
+        Buf* all[] = {&rec, &large, &bins, &tile_count, &tile_start, &tile_cursor, &map, &views, &ctr, &beam,
+                      &bias, &sweep, &sphere, &partial, &fu, &fv, &counts, &outd, &maps, &bits};
+        for (Buf* b : all) b->release(c);
+    }
+};
+
+struct BatchState;
+struct Server;
+
+PathSizes path_sizes(const Scene& sc, const Gen& g, const pv3d_params& p, int64_t n_sun);
+SceneDev scene_dev(const Scene& sc);
+GenDev gen_dev(const Gen& g);
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t stream_in_use = nullptr;
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    std::map<void*, size_t> sizes;
+    std::map<uint64_t, Scene> scenes;
+    std::map<uint64_t, Gen> gens;
+    uint64_t next_handle = 0;
+    Work w;
+    std::recursive_mutex mu;
+    // pinned staging of host inputs
+    void* staging = nullptr;
+    size_t staging_cap = 0, staging_used = 0;
+    bool staging_busy = false;
+    hipEvent_t staging_done = nullptr;
+    BatchState* batch = nullptr;
+    Server* server = nullptr;
+
+    pv3d_status dalloc(void** p, size_t bytes, const char* what);
+    void dfree(void* p);
+    pv3d_status stage(const void* host, size_t bytes, void* dev, hipStream_t st);
+    pv3d_status stage_reserve(size_t bytes);
+    pv3d_status stage_done(hipStream_t st);
+    pv3d_status ensure_path(const PathSizes& z, const Gen& g, int32_t map_n, bool own_map);
+    pv3d_status ensure_tables(const Gen& g, int32_t k);
+    BinBuffers bin_buffers(const PathSizes& z);
+    pv3d_status run_path(const Scene& sc, const Gen& g, const pv3d_params& p, const double* sun_host, int64_t n_sun,
+                         const double* d_sun, const double* d_dni, const double* d_dpoa, const double* d_dt,
+                         uint32_t* counts, double* power, double* power_ref, double* energy, uint32_t* maps,
+                         uint32_t* bits, hipStream_t st);
+    pv3d_status read_overflow(int64_t n_sun, hipStream_t st, bool* overflow);
+    bool scene_in_use(uint64_t h);
+    bool gen_in_use(uint64_t h);
+    void release_batched();
+};
+
+}  // namespace pv3d
+
+struct pv3d_ctx : pv3d::Ctx {};
+
+void pv3d_server_stop(pv3d_ctx* ctx);

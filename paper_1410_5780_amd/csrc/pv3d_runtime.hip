@@ -1,0 +1,649 @@
+// Host runtime of libpv3d: the C ABI declared in include/pv3d.h.
+//
+// Owns the HIP stream, the device copies of scenes and generators, the work
+// buffers of the per-sun path, and the HBM budget. Every step of the
+// shading path runs in the kernels of pv3d_kernels.hip; the host validates
+// arguments, sizes buffers and sequences launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/pv3d.h"
+#include "pv3d_device.h"
+#include "pv3d_runtime.h"
+
+using namespace pv3d;
+
+namespace pv3d {
+
+static thread_local std::string g_err;
+
+pv3d_status fail(pv3d_status code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+pv3d_status hip_fail(hipError_t e, const char* what) {
+    return fail(PV3D_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// device memory with budget accounting
+// ---------------------------------------------------------------------------
+pv3d_status Ctx::dalloc(void** p, size_t bytes, const char* what) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (used + bytes > budget)
+        return fail(PV3D_ENOMEM, "%s: %zu bytes exceed the HBM budget (%zu of %zu in use)", what, bytes,
+                    (size_t)used, (size_t)budget);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(PV3D_ENOMEM, "%s: hipMalloc(%zu): %s", what, bytes, hipGetErrorString(e));
+    }
+    sizes[*p] = bytes;
+    used += bytes;
+    return PV3D_OK;
+}
+
+void Ctx::dfree(void* p) {
+    if (!p) return;
+    auto it = sizes.find(p);
+    if (it != sizes.end()) {
+        used -= it->second;
+        sizes.erase(it);
+    }
+    (void)hipFree(p);
+}
+
+pv3d_status Buf::ensure(Ctx* c, size_t bytes, const char* what) {
+    if (bytes <= cap && ptr) return PV3D_OK;
+    if (ptr) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "synchronize before regrowing a work buffer");
+        c->dfree(ptr);
+        ptr = nullptr;
+        cap = 0;
+    }
+    size_t want = std::max(bytes, cap + cap / 2);
+    pv3d_status st = c->dalloc(&ptr, want, what);
+    if (st != PV3D_OK) {
+        st = c->dalloc(&ptr, bytes, what);
+        if (st != PV3D_OK) return st;
+        want = bytes;
+    }
+    cap = want;
+    return PV3D_OK;
+}
+
+void Buf::release(Ctx* c) {
+    if (ptr) c->dfree(ptr);
+    ptr = nullptr;
+    cap = 0;
+}
+
+pv3d_status Ctx::stage(const void* host, size_t bytes, void* dev, hipStream_t st) {
+    // pinned staging so the caller's host arrays can be reused once we return
+    if (staging_busy) {
+        hipError_t e = hipEventSynchronize(staging_done);
+        if (e != hipSuccess) return hip_fail(e, "wait for the staging buffer");
+        staging_busy = false;
+        staging_used = 0;
+    }
+    if (staging_used + bytes > staging_cap) {
+        size_t need = staging_used + bytes;
+        if (staging_used > 0) return fail(PV3D_EINVAL, "staging overflow");  // callers reserve first
+        if (staging) (void)hipHostFree(staging);
+        staging = nullptr;
+        size_t cap = std::max(need, (size_t)1 << 20);
+        hipError_t e = hipHostMalloc(&staging, cap, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "hipHostMalloc staging");
+        staging_cap = cap;
+    }
+    char* p = static_cast<char*>(staging) + staging_used;
+    memcpy(p, host, bytes);
+    staging_used += (bytes + 255) & ~(size_t)255;
+    hipError_t e = hipMemcpyAsync(dev, p, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync staging");
+    return PV3D_OK;
+}
+
+pv3d_status Ctx::stage_reserve(size_t bytes) {
+    if (staging_busy) {
+        hipError_t e = hipEventSynchronize(staging_done);
+        if (e != hipSuccess) return hip_fail(e, "wait for the staging buffer");
+        staging_busy = false;
+    }
+    staging_used = 0;
+    if (bytes > staging_cap) {
+        if (staging) (void)hipHostFree(staging);
+        staging = nullptr;
+        staging_cap = 0;
+        size_t cap = std::max(bytes + 4096, (size_t)1 << 20);
+        hipError_t e = hipHostMalloc(&staging, cap, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "hipHostMalloc staging");
+        staging_cap = cap;
+    }
+    return PV3D_OK;
+}
+
+pv3d_status Ctx::stage_done(hipStream_t st) {
+    hipError_t e = hipEventRecord(staging_done, st);
+    if (e != hipSuccess) return hip_fail(e, "record staging event");
+    staging_busy = true;
+    return PV3D_OK;
+}
+
+// ---------------------------------------------------------------------------
+// validation helpers
+// ---------------------------------------------------------------------------
+static bool finite3(const double* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+constexpr double kMaxCoord = 1.0e7;   // metres; keeps every light-space value far from overflow
+
+pv3d_status check_sweep(const double* sun, const double* dni, const double* dpoa, const double* dt, int64_t n) {
+    if (n < 0) return fail(PV3D_EINVAL, "n_sun < 0");
+    if (n > 0 && (!sun || !dni || !dpoa || !dt)) return fail(PV3D_EINVAL, "null sweep array");
+    for (int64_t t = 0; t < n; t++) {
+        const double* s = sun + 3 * t;
+        if (!finite3(s)) return fail(PV3D_EINVAL, "sun %lld is not finite", (long long)t);
+        double l2 = (s[0] * s[0] + s[1] * s[1]) + s[2] * s[2];
+        if (std::fabs(std::sqrt(l2) - 1.0) > 1e-9) return fail(PV3D_EINVAL, "sun %lld is not a unit vector", (long long)t);
+        if (!std::isfinite(dni[t]) || dni[t] < 0 || !std::isfinite(dpoa[t]) || dpoa[t] < 0 || !std::isfinite(dt[t]))
+            return fail(PV3D_EINVAL, "irradiance or dt of sun %lld out of range", (long long)t);
+    }
+    return PV3D_OK;
+}
+
+pv3d_status check_params(const pv3d_params* p) {
+    if (!p) return fail(PV3D_EINVAL, "params is NULL");
+    if (p->map_n < 16 || p->map_n > 16384) return fail(PV3D_EINVAL, "map_n %d outside [16, 16384]", p->map_n);
+    if (p->k < 1 || p->k > 255) return fail(PV3D_EINVAL, "k %d outside [1, 255]", p->k);
+    if (p->flags & ~(PV3D_EXPORT_DEPTH | PV3D_EXPORT_BITS)) return fail(PV3D_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->tile != 0 && p->tile != 32 && p->tile != 64 && p->tile != 128)
+        return fail(PV3D_EINVAL, "tile %d not in {0, 32, 64, 128}", p->tile);
+    return PV3D_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-sun path
+// ---------------------------------------------------------------------------
+int32_t choose_tile(const pv3d_params& p) { return p.tile ? p.tile : 64; }
+
+PathSizes path_sizes(const Scene& sc, const Gen& g, const pv3d_params& p, int64_t n_sun) {
+    PathSizes z;
+    z.tile = choose_tile(p);
+    z.ntx = (p.map_n + z.tile - 1) / z.tile;
+    z.n_tiles = z.ntx * z.ntx;
+    z.large_tiles = 16;
+    z.tri_total = sc.n_tri + (g.occluders ? 2 * g.n_mod : 0);
+    // a clipped triangle becomes at most 5 (a triangle cut by four half-planes
+    // is a polygon of at most 7 corners); a binned one touches <= large_tiles tiles
+    z.rec_cap = 5 * z.tri_total + 64;
+    z.bin_cap = (int64_t)z.large_tiles * z.rec_cap;
+    z.cells = (int64_t)g.n_mod * g.n_cu * g.n_cv;
+    z.words = (p.k * p.k + 31) / 32;
+    z.n_sun = n_sun;
+    return z;
+}
+
+pv3d_status Ctx::ensure_path(const PathSizes& z, const Gen& g, int32_t map_n, bool own_map) {
+    pv3d_status st;
+    if (z.rec_cap > INT32_MAX || z.bin_cap > INT32_MAX)
+        return fail(PV3D_ERANGE, "scene too large for 32-bit bin indices");
+    if ((st = w.rec.ensure(this, sizeof(TriRec) * (size_t)z.rec_cap, "triangle records"))) return st;
+    if ((st = w.large.ensure(this, 4 * (size_t)z.rec_cap, "large-triangle list"))) return st;
+    if ((st = w.bins.ensure(this, 4 * (size_t)z.bin_cap, "tile bins"))) return st;
+    if ((st = w.tile_count.ensure(this, 4 * (size_t)z.n_tiles, "tile counts"))) return st;
+    if ((st = w.tile_start.ensure(this, 4 * (size_t)(z.n_tiles + 1), "tile starts"))) return st;
+    if ((st = w.tile_cursor.ensure(this, 4 * (size_t)z.n_tiles, "tile cursors"))) return st;
+    if (own_map && (st = w.map.ensure(this, 4 * (size_t)map_n * map_n, "depth picture"))) return st;
+    if ((st = w.views.ensure(this, sizeof(View) * (size_t)std::max<int64_t>(z.n_sun, 1), "views"))) return st;
+    if ((st = w.ctr.ensure(this, sizeof(SunCounters) * (size_t)std::max<int64_t>(z.n_sun, 1), "counters"))) return st;
+    if ((st = w.beam.ensure(this, 8 * (size_t)std::max<int64_t>(z.n_sun * g.n_mod, 1), "module beam"))) return st;
+    if ((st = w.bias.ensure(this, 4 * (size_t)std::max<int64_t>(z.n_sun * g.n_mod, 1), "module bias"))) return st;
+    if ((st = w.sweep.ensure(this, 8 * 6 * (size_t)std::max<int64_t>(z.n_sun, 1), "sweep"))) return st;
+    if ((st = w.sphere.ensure(this, 64, "bounding sphere"))) return st;
+    if ((st = w.partial.ensure(this, 8 * 6 * 1024, "bounds partials"))) return st;
+    return PV3D_OK;
+}
+
+BinBuffers Ctx::bin_buffers(const PathSizes& z) {
+    BinBuffers bb;
+    bb.rec = static_cast<TriRec*>(w.rec.ptr);
+    bb.rec_cap = (int32_t)z.rec_cap;
+    bb.large = static_cast<int32_t*>(w.large.ptr);
+    bb.tile_count = static_cast<int32_t*>(w.tile_count.ptr);
+    bb.tile_start = static_cast<int32_t*>(w.tile_start.ptr);
+    bb.tile_cursor = static_cast<int32_t*>(w.tile_cursor.ptr);
+    bb.bins = static_cast<int32_t*>(w.bins.ptr);
+    bb.bin_cap = (int32_t)z.bin_cap;
+    bb.tile = z.tile;
+    bb.ntx = z.ntx;
+    bb.large_tiles = z.large_tiles;
+    return bb;
+}
+
+SceneDev scene_dev(const Scene& sc) {
+    SceneDev d;
+    d.xyz = sc.xyz;
+    d.tri = sc.tri;
+    d.n_vert = sc.n_vert;
+    d.n_tri = sc.n_tri;
+    return d;
+}
+
+GenDev gen_dev(const Gen& g) {
+    GenDev d;
+    d.mods = g.mods;
+    d.n_mod = (int32_t)g.n_mod;
+    d.n_cu = g.n_cu;
+    d.n_cv = g.n_cv;
+    d.n_sub = g.n_sub;
+    d.n_str = g.n_str;
+    d.occluders = g.occluders;
+    d.cell_sub = g.cell_sub;
+    d.str_start = g.str_start;
+    d.str_mods = g.str_mods;
+    return d;
+}
+
+// Everything of one evaluation that lives on the device.
+pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, const double* sun_host,
+                          int64_t n_sun, const double* d_sun, const double* d_dni, const double* d_dpoa,
+                          const double* d_dt, uint32_t* counts, double* power, double* power_ref,
+                          double* energy, uint32_t* maps, uint32_t* bits, hipStream_t st) {
+    PathSizes z = path_sizes(sc, g, p, n_sun);
+    pv3d_status rs = ensure_path(z, g, p.map_n, maps == nullptr);
+    if (rs) return rs;
+    hipError_t e;
+    if ((rs = ensure_tables(g, p.k))) return rs;
+    SceneDev sd = scene_dev(sc);
+    GenDev gd = gen_dev(g);
+    View* views = static_cast<View*>(w.views.ptr);
+    SunCounters* ctr = static_cast<SunCounters*>(w.ctr.ptr);
+    double* beam = static_cast<double*>(w.beam.ptr);
+    int32_t* bias = static_cast<int32_t*>(w.bias.ptr);
+    double* sphere = static_cast<double*>(w.sphere.ptr);
+    const int64_t N2 = (int64_t)p.map_n * p.map_n;
+
+    if ((e = hipMemsetAsync(ctr, 0, sizeof(SunCounters) * (size_t)std::max<int64_t>(n_sun, 1), st)))
+        return hip_fail(e, "clear counters");
+    // tile counts start at zero; the scan of every sun leaves them at zero again
+    if ((e = hipMemsetAsync(w.tile_count.ptr, 0, 4 * (size_t)z.n_tiles, st))) return hip_fail(e, "clear tile counts");
+    if (counts && (e = hipMemsetAsync(counts, 0, 4 * (size_t)(n_sun * z.cells), st))) return hip_fail(e, "clear counts");
+    if (bits && (e = hipMemsetAsync(bits, 0, 4 * (size_t)(n_sun * z.cells * z.words), st))) return hip_fail(e, "clear bits");
+    if (maps && (e = launch_fill_u32(maps, kDepthMax, n_sun * N2, st))) return hip_fail(e, "fill depth maps");
+
+    int32_t n_part = bounds_partials(sc.n_vert + 4 * g.n_mod);
+    if ((e = launch_bounds(sd, gd, static_cast<double*>(w.partial.ptr), n_part, sphere, st)))
+        return hip_fail(e, "bounds");
+    if ((e = launch_setup(d_sun, n_sun, d_dni, gd, sphere, p.map_n, views, beam, bias, st)))
+        return hip_fail(e, "setup");
+    BinBuffers bb = bin_buffers(z);
+    uint32_t* scratch_counts = counts;
+    for (int64_t s = 0; s < n_sun; s++) {
+        if (!(sun_host[3 * s + 2] > 0.0)) continue;        // below the horizon: outputs stay zero
+        uint32_t* map = maps ? maps + s * N2 : static_cast<uint32_t*>(w.map.ptr);
+        if ((e = launch_tri_setup(s, views, sd, gd, p.map_n, bb, ctr, st))) return hip_fail(e, "tri_setup");
+        if ((e = launch_bin_scan(z.n_tiles, bb, st))) return hip_fail(e, "bin_scan");
+        if ((e = launch_bin_scatter(s, bb, z.n_tiles, ctr, st))) return hip_fail(e, "bin_scatter");
+        if ((e = launch_raster(s, views, bb, ctr, p.map_n, map, st))) return hip_fail(e, "raster");
+        if ((e = launch_sample_test(s, views, gd, beam, bias, static_cast<double*>(w.fu.ptr),
+                                    static_cast<double*>(w.fv.ptr), p.k, map, p.map_n,
+                                    scratch_counts + s * z.cells, bits ? bits + s * z.cells * z.words : nullptr, st)))
+            return hip_fail(e, "sample_test");
+    }
+    if ((e = launch_loss(n_sun, d_sun, beam, counts, d_dpoa, gd, p.k, power, power_ref, st)))
+        return hip_fail(e, "loss");
+    if ((e = launch_energy(n_sun, power, power_ref, d_dt, energy, st))) return hip_fail(e, "energy");
+    return PV3D_OK;
+}
+
+pv3d_status Ctx::ensure_tables(const Gen& g, int32_t k) {
+    pv3d_status st;
+    size_t n = (size_t)k * std::max(g.n_cu, g.n_cv);
+    if ((st = w.fu.ensure(this, 8 * n, "sample table u"))) return st;
+    if ((st = w.fv.ensure(this, 8 * n, "sample table v"))) return st;
+    hipError_t e = launch_sample_tables(static_cast<double*>(w.fu.ptr), static_cast<double*>(w.fv.ptr), k,
+                                        g.n_cu, g.n_cv, stream_in_use);
+    if (e != hipSuccess) return hip_fail(e, "sample tables");
+    return PV3D_OK;
+}
+
+pv3d_status Ctx::read_overflow(int64_t n_sun, hipStream_t st, bool* overflow) {
+    *overflow = false;
+    std::vector<SunCounters> h((size_t)std::max<int64_t>(n_sun, 1));
+    hipError_t e = hipMemcpyAsync(h.data(), w.ctr.ptr, sizeof(SunCounters) * (size_t)n_sun,
+                                  hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(e, "read counters");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "synchronize");
+    for (int64_t s = 0; s < n_sun; s++)
+        if (h[(size_t)s].overflow) *overflow = true;
+    return PV3D_OK;
+}
+
+}  // namespace pv3d
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+pv3d_status pv3d_create(int32_t device, uint64_t hbm_budget_bytes, pv3d_ctx** out) {
+    if (!out) return fail(PV3D_EINVAL, "out is NULL");
+    *out = nullptr;
+    int nd = 0;
+    hipError_t e = hipGetDeviceCount(&nd);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= nd) return fail(PV3D_EINVAL, "device %d of %d", device, nd);
+    if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    size_t fr = 0, tot = 0;
+    if ((e = hipMemGetInfo(&fr, &tot)) != hipSuccess) return hip_fail(e, "hipMemGetInfo");
+    std::unique_ptr<pv3d_ctx> c(new pv3d_ctx());
+    c->device = device;
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)fr);
+    if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "hipStreamCreate");
+    if ((e = hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "hipEventCreate");
+    c->stream_in_use = c->stream;
+    *out = c.release();
+    return PV3D_OK;
+}
+
+void pv3d_destroy(pv3d_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    pv3d_server_stop(ctx);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : ctx->scenes) {
+        ctx->dfree(kv.second.xyz);
+        ctx->dfree(kv.second.tri);
+    }
+    for (auto& kv : ctx->gens) {
+        ctx->dfree(kv.second.mods);
+        ctx->dfree(kv.second.cell_sub);
+        ctx->dfree(kv.second.str_start);
+        ctx->dfree(kv.second.str_mods);
+    }
+    ctx->w.release_all(ctx);
+    ctx->release_batched();
+    if (ctx->staging) (void)hipHostFree(ctx->staging);
+    (void)hipEventDestroy(ctx->staging_done);
+    (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char* pv3d_last_error(const pv3d_ctx* ctx) {
+    (void)ctx;
+    return pv3d::g_err.c_str();
+}
+
+pv3d_status pv3d_scene_load(pv3d_ctx* ctx, const double* xyz, int64_t n_vert, const int32_t* tri, int64_t n_tri,
+                            uint64_t* scene_out) {
+    if (!ctx || !scene_out) return fail(PV3D_EINVAL, "null argument");
+    if (n_vert < 0 || n_tri < 0 || n_vert >= INT32_MAX || n_tri >= INT32_MAX / 8)
+        return fail(PV3D_EINVAL, "bad sizes n_vert=%lld n_tri=%lld", (long long)n_vert, (long long)n_tri);
+    if ((n_vert && !xyz) || (n_tri && !tri)) return fail(PV3D_EINVAL, "null array");
+    for (int64_t i = 0; i < n_vert; i++) {
+        if (!finite3(xyz + 3 * i)) return fail(PV3D_EINVAL, "vertex %lld is not finite", (long long)i);
+        for (int c = 0; c < 3; c++)
+            if (std::fabs(xyz[3 * i + c]) > kMaxCoord)
+                return fail(PV3D_ERANGE, "vertex %lld beyond %.0e m", (long long)i, kMaxCoord);
+    }
+    for (int64_t i = 0; i < 3 * n_tri; i++)
+        if (tri[i] < 0 || tri[i] >= n_vert) return fail(PV3D_EINVAL, "triangle index %lld out of range", (long long)i / 3);
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    Scene s;
+    s.n_vert = n_vert;
+    s.n_tri = n_tri;
+    pv3d_status st;
+    if ((st = ctx->dalloc((void**)&s.xyz, 24 * (size_t)n_vert, "scene vertices"))) return st;
+    if ((st = ctx->dalloc((void**)&s.tri, 12 * (size_t)n_tri, "scene triangles"))) {
+        ctx->dfree(s.xyz);
+        return st;
+    }
+    hipError_t e;
+    if (n_vert && (e = hipMemcpy(s.xyz, xyz, 24 * (size_t)n_vert, hipMemcpyHostToDevice))) return hip_fail(e, "copy vertices");
+    if (n_tri && (e = hipMemcpy(s.tri, tri, 12 * (size_t)n_tri, hipMemcpyHostToDevice))) return hip_fail(e, "copy triangles");
+    uint64_t h = ++ctx->next_handle;
+    ctx->scenes[h] = s;
+    *scene_out = h;
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_scene_release(pv3d_ctx* ctx, uint64_t scene) {
+    if (!ctx) return fail(PV3D_EINVAL, "null context");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->scenes.find(scene);
+    if (it == ctx->scenes.end()) return fail(PV3D_ENOENT, "unknown scene %llu", (unsigned long long)scene);
+    if (ctx->scene_in_use(scene)) return fail(PV3D_EBUSY, "scene %llu is used by a running job", (unsigned long long)scene);
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->dfree(it->second.xyz);
+    ctx->dfree(it->second.tri);
+    ctx->scenes.erase(it);
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_generator_define(pv3d_ctx* ctx, const pv3d_module* mods, int64_t n_mod, const int32_t* cell_substring,
+                                  int32_t n_sub, const int32_t* module_string, int32_t add_as_occluders,
+                                  uint64_t* gen_out) {
+    if (!ctx || !mods || !cell_substring || !module_string || !gen_out) return fail(PV3D_EINVAL, "null argument");
+    if (n_mod < 1 || n_mod >= INT32_MAX / 8) return fail(PV3D_EINVAL, "n_mod %lld", (long long)n_mod);
+    const int32_t n_cu = mods[0].n_cu, n_cv = mods[0].n_cv;
+    if (n_cu < 1 || n_cv < 1 || n_cu > 4096 || n_cv > 4096) return fail(PV3D_EINVAL, "cells per module %d x %d", n_cu, n_cv);
+    if (n_sub < 1 || n_sub > n_cu * n_cv) return fail(PV3D_EINVAL, "n_sub %d", n_sub);
+    std::vector<Module> hm((size_t)n_mod);
+    for (int64_t m = 0; m < n_mod; m++) {
+        const pv3d_module& M = mods[m];
+        if (M.n_cu != n_cu || M.n_cv != n_cv) return fail(PV3D_EINVAL, "module %lld: all modules must share n_cu, n_cv", (long long)m);
+        if (!finite3(M.origin) || !finite3(M.edge_u) || !finite3(M.edge_v))
+            return fail(PV3D_EINVAL, "module %lld is not finite", (long long)m);
+        for (int c = 0; c < 3; c++)
+            if (std::fabs(M.origin[c]) > kMaxCoord || std::fabs(M.edge_u[c]) > kMaxCoord || std::fabs(M.edge_v[c]) > kMaxCoord)
+                return fail(PV3D_ERANGE, "module %lld beyond %.0e m", (long long)m, kMaxCoord);
+        double cx = M.edge_u[1] * M.edge_v[2] - M.edge_u[2] * M.edge_v[1];
+        double cy = M.edge_u[2] * M.edge_v[0] - M.edge_u[0] * M.edge_v[2];
+        double cz = M.edge_u[0] * M.edge_v[1] - M.edge_u[1] * M.edge_v[0];
+        if (!((cx * cx + cy * cy) + cz * cz > 0.0)) return fail(PV3D_EINVAL, "module %lld is degenerate", (long long)m);
+        Module& D = hm[(size_t)m];
+        memset(&D, 0, sizeof(D));
+        for (int c = 0; c < 3; c++) {
+            D.o[c] = M.origin[c];
+            D.u[c] = M.edge_u[c];
+            D.v[c] = M.edge_v[c];
+        }
+    }
+    std::vector<int32_t> seen((size_t)n_sub, 0);
+    for (int32_t c = 0; c < n_cu * n_cv; c++) {
+        if (cell_substring[c] < 0 || cell_substring[c] >= n_sub) return fail(PV3D_EINVAL, "cell %d: substring out of range", c);
+        seen[(size_t)cell_substring[c]] = 1;
+    }
+    for (int32_t q = 0; q < n_sub; q++)
+        if (!seen[(size_t)q]) return fail(PV3D_EINVAL, "substring %d owns no cell", q);
+    int32_t n_str = 0;
+    for (int64_t m = 0; m < n_mod; m++) {
+        if (module_string[m] < 0 || module_string[m] >= n_mod) return fail(PV3D_EINVAL, "module %lld: bad string", (long long)m);
+        n_str = std::max(n_str, module_string[m] + 1);
+    }
+    std::vector<int32_t> start((size_t)n_str + 1, 0), order((size_t)n_mod);
+    for (int64_t m = 0; m < n_mod; m++) start[(size_t)module_string[m] + 1]++;
+    for (int32_t q = 0; q < n_str; q++) {
+        if (start[(size_t)q + 1] == 0) return fail(PV3D_EINVAL, "string %d has no module", q);
+        if ((int64_t)start[(size_t)q + 1] * n_sub > 4096)
+            return fail(PV3D_ERANGE, "string %d has more than 4096 substrings", q);
+        start[(size_t)q + 1] += start[(size_t)q];
+    }
+    {
+        std::vector<int32_t> cur(start.begin(), start.end() - 1);
+        for (int64_t m = 0; m < n_mod; m++) order[(size_t)cur[(size_t)module_string[m]]++] = (int32_t)m;
+    }
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    Gen g;
+    g.n_mod = n_mod;
+    g.n_cu = n_cu;
+    g.n_cv = n_cv;
+    g.n_sub = n_sub;
+    g.n_str = n_str;
+    g.occluders = add_as_occluders ? 1 : 0;
+    pv3d_status st;
+    if ((st = ctx->dalloc((void**)&g.mods, sizeof(Module) * (size_t)n_mod, "modules"))) return st;
+    if ((st = ctx->dalloc((void**)&g.cell_sub, 4 * (size_t)(n_cu * n_cv), "cell map"))) return st;
+    if ((st = ctx->dalloc((void**)&g.str_start, 4 * (size_t)(n_str + 1), "string starts"))) return st;
+    if ((st = ctx->dalloc((void**)&g.str_mods, 4 * (size_t)n_mod, "string modules"))) return st;
+    hipError_t e;
+    if ((e = hipMemcpy(g.mods, hm.data(), sizeof(Module) * (size_t)n_mod, hipMemcpyHostToDevice))) return hip_fail(e, "copy modules");
+    if ((e = hipMemcpy(g.cell_sub, cell_substring, 4 * (size_t)(n_cu * n_cv), hipMemcpyHostToDevice))) return hip_fail(e, "copy cell map");
+    if ((e = hipMemcpy(g.str_start, start.data(), 4 * (size_t)(n_str + 1), hipMemcpyHostToDevice))) return hip_fail(e, "copy strings");
+    if ((e = hipMemcpy(g.str_mods, order.data(), 4 * (size_t)n_mod, hipMemcpyHostToDevice))) return hip_fail(e, "copy strings");
+    if ((e = launch_module_normals(g.mods, (int32_t)n_mod, ctx->stream))) return hip_fail(e, "module normals");
+    if ((e = hipStreamSynchronize(ctx->stream))) return hip_fail(e, "module normals");
+    uint64_t h = ++ctx->next_handle;
+    ctx->gens[h] = g;
+    *gen_out = h;
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_generator_release(pv3d_ctx* ctx, uint64_t gen) {
+    if (!ctx) return fail(PV3D_EINVAL, "null context");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->gens.find(gen);
+    if (it == ctx->gens.end()) return fail(PV3D_ENOENT, "unknown generator %llu", (unsigned long long)gen);
+    if (ctx->gen_in_use(gen)) return fail(PV3D_EBUSY, "generator %llu is used by a running job", (unsigned long long)gen);
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->dfree(it->second.mods);
+    ctx->dfree(it->second.cell_sub);
+    ctx->dfree(it->second.str_start);
+    ctx->dfree(it->second.str_mods);
+    ctx->gens.erase(it);
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_sun_cooper(double lat_deg, const int32_t* day, const double* solar_hour, int64_t n, double* out) {
+    if (n < 0 || (n && (!day || !solar_hour || !out))) return fail(PV3D_EINVAL, "bad arguments");
+    const double deg = M_PI / 180.0;
+    const double phi = lat_deg * deg;
+    for (int64_t i = 0; i < n; i++) {
+        double decl = 23.45 * std::sin(360.0 * (284.0 + (double)day[i]) / 365.0 * deg) * deg;
+        double om = 15.0 * (solar_hour[i] - 12.0) * deg;
+        out[3 * i + 0] = -std::cos(decl) * std::sin(om);
+        out[3 * i + 1] = std::sin(decl) * std::cos(phi) - std::cos(decl) * std::sin(phi) * std::cos(om);
+        out[3 * i + 2] = std::sin(decl) * std::sin(phi) + std::cos(decl) * std::cos(phi) * std::cos(om);
+    }
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_evaluate(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const double* sun_xyz, const double* dni,
+                          const double* d_poa, const double* dt_h, int64_t n_sun, const pv3d_params* params,
+                          pv3d_outputs* out, void* hip_stream) {
+    if (!ctx || !out) return fail(PV3D_EINVAL, "null argument");
+    pv3d_status st;
+    if ((st = check_params(params))) return st;
+    if ((st = check_sweep(sun_xyz, dni, d_poa, dt_h, n_sun))) return st;
+    if (!out->power || !out->power_ref || !out->energy) return fail(PV3D_EINVAL, "power, power_ref and energy are required");
+    if ((params->flags & PV3D_EXPORT_DEPTH) && !out->depth_maps) return fail(PV3D_EINVAL, "EXPORT_DEPTH needs depth_maps");
+    if ((params->flags & PV3D_EXPORT_BITS) && !out->shaded_bits) return fail(PV3D_EINVAL, "EXPORT_BITS needs shaded_bits");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto si = ctx->scenes.find(scene);
+    if (si == ctx->scenes.end()) return fail(PV3D_ENOENT, "unknown scene %llu", (unsigned long long)scene);
+    auto gi = ctx->gens.find(gen);
+    if (gi == ctx->gens.end()) return fail(PV3D_ENOENT, "unknown generator %llu", (unsigned long long)gen);
+    (void)hipSetDevice(ctx->device);
+    hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->stream;
+    ctx->stream_in_use = s;
+    const Scene& sc = si->second;
+    const Gen& g = gi->second;
+    const pv3d_params& p = *params;
+    const int64_t cells = g.n_mod * g.n_cu * g.n_cv;
+    const int64_t words = (p.k * p.k + 31) / 32;
+    const bool want_maps = (p.flags & PV3D_EXPORT_DEPTH) != 0, want_bits = (p.flags & PV3D_EXPORT_BITS) != 0;
+    const int64_t N2 = (int64_t)p.map_n * p.map_n;
+    hipError_t e;
+
+    // device views of the outputs: the caller's arrays, or context buffers copied back at the end
+    uint32_t *d_counts, *d_maps = nullptr, *d_bits = nullptr;
+    double *d_pw, *d_pr, *d_en;
+    if (out->on_device) {
+        if ((st = ctx->w.counts.ensure(ctx, 4 * (size_t)std::max<int64_t>(n_sun * cells, 1), "counts"))) return st;
+        d_counts = out->cell_counts ? out->cell_counts : static_cast<uint32_t*>(ctx->w.counts.ptr);
+        d_pw = out->power;
+        d_pr = out->power_ref;
+        d_en = out->energy;
+        d_maps = want_maps ? out->depth_maps : nullptr;
+        d_bits = want_bits ? out->shaded_bits : nullptr;
+    } else {
+        if ((st = ctx->w.counts.ensure(ctx, 4 * (size_t)std::max<int64_t>(n_sun * cells, 1), "counts"))) return st;
+        if ((st = ctx->w.outd.ensure(ctx, 8 * (size_t)(2 * n_sun + 2), "power"))) return st;
+        d_counts = static_cast<uint32_t*>(ctx->w.counts.ptr);
+        d_pw = static_cast<double*>(ctx->w.outd.ptr);
+        d_pr = d_pw + n_sun;
+        d_en = d_pr + n_sun;
+        if (want_maps) {
+            if ((st = ctx->w.maps.ensure(ctx, 4 * (size_t)std::max<int64_t>(n_sun * N2, 1), "exported depth maps"))) return st;
+            d_maps = static_cast<uint32_t*>(ctx->w.maps.ptr);
+        }
+        if (want_bits) {
+            if ((st = ctx->w.bits.ensure(ctx, 4 * (size_t)std::max<int64_t>(n_sun * cells * words, 1), "exported bits"))) return st;
+            d_bits = static_cast<uint32_t*>(ctx->w.bits.ptr);
+        }
+    }
+    PathSizes z = path_sizes(sc, g, p, n_sun);
+    if ((st = ctx->ensure_path(z, g, p.map_n, !want_maps))) return st;
+    double* d_sweep = static_cast<double*>(ctx->w.sweep.ptr);
+    double *d_sun = d_sweep, *d_dni = d_sweep + 3 * n_sun, *d_dpoa = d_dni + n_sun, *d_dt = d_dpoa + n_sun;
+    if (n_sun > 0) {
+        if ((st = ctx->stage_reserve(8 * 6 * (size_t)n_sun + 4 * 256))) return st;
+        if ((st = ctx->stage(sun_xyz, 24 * (size_t)n_sun, d_sun, s))) return st;
+        if ((st = ctx->stage(dni, 8 * (size_t)n_sun, d_dni, s))) return st;
+        if ((st = ctx->stage(d_poa, 8 * (size_t)n_sun, d_dpoa, s))) return st;
+        if ((st = ctx->stage(dt_h, 8 * (size_t)n_sun, d_dt, s))) return st;
+        if ((st = ctx->stage_done(s))) return st;
+    }
+    if ((st = ctx->run_path(sc, g, p, sun_xyz, n_sun, d_sun, d_dni, d_dpoa, d_dt, d_counts, d_pw, d_pr, d_en,
+                            d_maps, d_bits, s)))
+        return st;
+    if (!out->on_device) {
+        bool ovf = false;
+        if ((st = ctx->read_overflow(n_sun, s, &ovf))) return st;
+        if (ovf) return fail(PV3D_ERANGE, "internal buffer overflow");
+        if (out->cell_counts && n_sun &&
+            (e = hipMemcpyAsync(out->cell_counts, d_counts, 4 * (size_t)(n_sun * cells), hipMemcpyDeviceToHost, s)))
+            return hip_fail(e, "copy counts");
+        if (n_sun && (e = hipMemcpyAsync(out->power, d_pw, 8 * (size_t)n_sun, hipMemcpyDeviceToHost, s))) return hip_fail(e, "copy power");
+        if (n_sun && (e = hipMemcpyAsync(out->power_ref, d_pr, 8 * (size_t)n_sun, hipMemcpyDeviceToHost, s)))
+            return hip_fail(e, "copy power_ref");
+        if ((e = hipMemcpyAsync(out->energy, d_en, 16, hipMemcpyDeviceToHost, s))) return hip_fail(e, "copy energy");
+        if (want_maps && n_sun &&
+            (e = hipMemcpyAsync(out->depth_maps, d_maps, 4 * (size_t)(n_sun * N2), hipMemcpyDeviceToHost, s)))
+            return hip_fail(e, "copy depth maps");
+        if (want_bits && n_sun &&
+            (e = hipMemcpyAsync(out->shaded_bits, d_bits, 4 * (size_t)(n_sun * cells * words), hipMemcpyDeviceToHost, s)))
+            return hip_fail(e, "copy bits");
+        if ((e = hipStreamSynchronize(s))) return hip_fail(e, "synchronize");
+    } else {
+        if ((e = hipGetLastError())) return hip_fail(e, "launch");
+    }
+    return PV3D_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,219 @@
+"""ctypes binding of libpv3d (include/pv3d.h): argument marshalling only.
+
+Every step of the shading path runs in the library's HIP kernels; this module
+converts numpy arrays and torch device tensors to pointers, checks status
+codes, and shapes the results. It raises if the shared library is missing:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpv3d.so")
+
+OK, EINVAL, ENOMEM, ENOENT, EDEVICE, ERANGE, EBUSY, ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7
+EXPORT_DEPTH, EXPORT_BITS = 1, 2
+DEPTH_MAX = (1 << 24) - 1
+
+_P = ctypes.c_void_p
+_i32, _i64, _u32, _u64, _f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+
+
+class Module(ctypes.Structure):
+    _fields_ = [("origin", _f64 * 3), ("edge_u", _f64 * 3), ("edge_v", _f64 * 3), ("n_cu", _i32), ("n_cv", _i32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("map_n", _i32), ("k", _i32), ("flags", _u32), ("tile", _i32)]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("cell_counts", _P), ("power", _P), ("power_ref", _P), ("energy", _P),
+                ("depth_maps", _P), ("shaded_bits", _P), ("on_device", _i32)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("scene", _u64), ("gen", _u64), ("sun_xyz", _P), ("dni", _P), ("d_poa", _P), ("dt_h", _P),
+                ("n_sun", _i64), ("params", Params), ("out", Outputs)]
+
+
+class Pv3dError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pv3d error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libpv3d.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python paper_1410_5780_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        L.pv3d_create.argtypes = [_i32, _u64, ctypes.POINTER(_P)]
+        L.pv3d_destroy.argtypes = [_P]
+        L.pv3d_destroy.restype = None
+        L.pv3d_last_error.argtypes = [_P]
+        L.pv3d_last_error.restype = ctypes.c_char_p
+        L.pv3d_scene_load.argtypes = [_P, _P, _i64, _P, _i64, ctypes.POINTER(_u64)]
+        L.pv3d_scene_release.argtypes = [_P, _u64]
+        L.pv3d_generator_define.argtypes = [_P, _P, _i64, _P, _i32, _P, _i32, ctypes.POINTER(_u64)]
+        L.pv3d_generator_release.argtypes = [_P, _u64]
+        L.pv3d_sun_cooper.argtypes = [_f64, _P, _P, _i64, _P]
+        L.pv3d_evaluate.argtypes = [_P, _u64, _u64, _P, _P, _P, _P, _i64, ctypes.POINTER(Params),
+                                    ctypes.POINTER(Outputs), _P]
+        L.pv3d_evaluate_batched.argtypes = [_P, ctypes.POINTER(Job), _i64, _P]
+        L.pv3d_submit.argtypes = [_P, ctypes.POINTER(Job), ctypes.POINTER(_u64)]
+        L.pv3d_poll.argtypes = [_P, _u64, ctypes.POINTER(_i32)]
+        L.pv3d_wait.argtypes = [_P, _u64]
+        L.pv3d_cancel.argtypes = [_P, _u64]
+        for f in ("pv3d_create", "pv3d_scene_load", "pv3d_scene_release", "pv3d_generator_define",
+                  "pv3d_generator_release", "pv3d_sun_cooper", "pv3d_evaluate", "pv3d_evaluate_batched",
+                  "pv3d_submit", "pv3d_poll", "pv3d_wait", "pv3d_cancel"):
+            getattr(L, f).restype = _i32
+        _lib = L
+    return _lib
+
+
+def _ptr(a) -> Optional[int]:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return int(a.data_ptr())            # torch tensor
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _check(code: int, ctx=None):
+    if code != OK:
+        raise Pv3dError(code, lib().pv3d_last_error(ctx).decode(errors="replace"))
+
+
+def sun_cooper(lat_deg: float, day, hour) -> np.ndarray:
+    day = _c(day, np.int32).ravel()
+    hour = _c(hour, np.float64).ravel()
+    out = np.zeros((day.shape[0], 3))
+    _check(lib().pv3d_sun_cooper(lat_deg, _ptr(day), _ptr(hour), day.shape[0], _ptr(out)))
+    return out
+
+
+class Result:
+    def __init__(self, counts, power, power_ref, energy, maps=None, bits=None):
+        self.counts, self.power, self.power_ref, self.energy = counts, power, power_ref, energy
+        self.maps, self.bits = maps, bits
+
+    @property
+    def loss(self) -> float:
+        e = np.asarray(self.energy if isinstance(self.energy, np.ndarray) else self.energy.cpu().numpy())
+        return float(1.0 - e[0] / e[1]) if e[1] > 0 else 0.0
+
+
+def modules_of(gen) -> ctypes.Array:
+    arr = (Module * gen.n_mod)()
+    for m in range(gen.n_mod):
+        arr[m].origin[:] = [float(x) for x in gen.origin[m]]
+        arr[m].edge_u[:] = [float(x) for x in gen.edge_u[m]]
+        arr[m].edge_v[:] = [float(x) for x in gen.edge_v[m]]
+        arr[m].n_cu, arr[m].n_cv = int(gen.n_cu), int(gen.n_cv)
+    return arr
+
+
+class Context:
+    """One library context on one device (owns a HIP stream and an HBM budget)."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        h = _P()
+        _check(lib().pv3d_create(device, budget_bytes, ctypes.byref(h)))
+        self.h = h
+        self._keep = []
+
+    def close(self):
+        if self.h:
+            lib().pv3d_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_scene(self, scene) -> int:
+        xyz = _c(scene.xyz, np.float64).reshape(-1, 3)
+        tri = _c(scene.tri, np.int32).reshape(-1, 3)
+        h = _u64()
+        _check(lib().pv3d_scene_load(self.h, _ptr(xyz), xyz.shape[0], _ptr(tri), tri.shape[0], ctypes.byref(h)), self.h)
+        return h.value
+
+    def release_scene(self, h: int):
+        _check(lib().pv3d_scene_release(self.h, h), self.h)
+
+    def define_generator(self, gen) -> int:
+        mods = modules_of(gen)
+        cs = _c(gen.cell_substring, np.int32)
+        ms = _c(gen.module_string, np.int32)
+        h = _u64()
+        _check(lib().pv3d_generator_define(self.h, ctypes.addressof(mods), gen.n_mod, _ptr(cs), int(gen.n_sub),
+                                           _ptr(ms), 1 if gen.add_as_occluders else 0, ctypes.byref(h)), self.h)
+        return h.value
+
+    def release_generator(self, h: int):
+        _check(lib().pv3d_generator_release(self.h, h), self.h)
+
+    @staticmethod
+    def params(map_n: int, k: int, export_depth=False, export_bits=False, tile: int = 0) -> Params:
+        return Params(map_n, k, (EXPORT_DEPTH if export_depth else 0) | (EXPORT_BITS if export_bits else 0), tile)
+
+    def evaluate(self, scene_h: int, gen_h: int, gen, sweep, map_n: int, k: int, export_depth=False,
+                 export_bits=False, tile: int = 0) -> Result:
+        """Host outputs (synchronous)."""
+        s = _c(sweep.sun_xyz, np.float64)
+        dni, dp, dt = (_c(a, np.float64) for a in (sweep.dni, sweep.d_poa, sweep.dt_h))
+        n = s.shape[0]
+        cells = gen.n_cells
+        words = (k * k + 31) // 32
+        counts = np.zeros((n, cells), np.uint32)
+        pw, pr, en = np.zeros(n), np.zeros(n), np.zeros(2)
+        maps = np.zeros((n, map_n, map_n), np.uint32) if export_depth else None
+        bits = np.zeros((n, cells, words), np.uint32) if export_bits else None
+        out = Outputs(_ptr(counts), _ptr(pw), _ptr(pr), _ptr(en), _ptr(maps), _ptr(bits), 0)
+        p = self.params(map_n, k, export_depth, export_bits, tile)
+        _check(lib().pv3d_evaluate(self.h, scene_h, gen_h, _ptr(s), _ptr(dni), _ptr(dp), _ptr(dt), n,
+                                   ctypes.byref(p), ctypes.byref(out), None), self.h)
+        return Result(counts, pw, pr, en, maps, bits)
+
+    def evaluate_device(self, scene_h: int, gen_h: int, gen, sweep, map_n: int, k: int, stream=None,
+                        counts=None, tile: int = 0) -> Result:
+        """Device outputs as torch tensors, asynchronous on `stream` (default: torch's current stream)."""
+        import torch
+        s = _c(sweep.sun_xyz, np.float64)
+        dni, dp, dt = (_c(a, np.float64) for a in (sweep.dni, sweep.d_poa, sweep.dt_h))
+        n = s.shape[0]
+        dev = torch.device("cuda", torch.cuda.current_device())
+        pw = torch.empty(n, dtype=torch.float64, device=dev)
+        pr = torch.empty(n, dtype=torch.float64, device=dev)
+        en = torch.empty(2, dtype=torch.float64, device=dev)
+        out = Outputs(_ptr(counts), _ptr(pw), _ptr(pr), _ptr(en), None, None, 1)
+        p = self.params(map_n, k, tile=tile)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().pv3d_evaluate(self.h, scene_h, gen_h, _ptr(s), _ptr(dni), _ptr(dp), _ptr(dt), n,
+                                   ctypes.byref(p), ctypes.byref(out), ctypes.c_void_p(st.cuda_stream)), self.h)
+        return Result(counts, pw, pr, en)

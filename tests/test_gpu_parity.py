@@ -1,0 +1,177 @@
+"""HIP path vs the CPU oracle, through the C ABI (needs an MI355X).
+
+Depth pictures, shaded flags and per-cell counts must be bit-exact; powers and
+energies within 1e-6 relative (the arithmetic is the same sequence of IEEE
+operations on both sides, so they are expected to agree exactly).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1410_5780_amd import workloads as W
+from tests.conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_1410_5780_amd import pv3d
+    c = pv3d.Context(0)
+    yield c
+    c.close()
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def compare(ctx, oracle_lib, w, maps=True, bits=True, tile=0, threads=0):
+    _say(f"[parity] {w.name}: tris={w.scene.n_tri} cells={w.gen.n_cells} suns={w.sweep.n} "
+         f"N={w.map_n} k={w.k} tile={tile}")
+    sh = ctx.load_scene(w.scene)
+    gh = ctx.define_generator(w.gen)
+    try:
+        got = ctx.evaluate(sh, gh, w.gen, w.sweep, w.map_n, w.k, export_depth=maps, export_bits=bits, tile=tile)
+    finally:
+        ctx.release_scene(sh)
+        ctx.release_generator(gh)
+    ref = oracle_lib.evaluate(w.scene, w.gen, w.sweep, w.map_n, w.k, export_maps=maps, export_bits=bits,
+                              threads=threads)
+    assert ref.outside == 0
+    if maps:
+        bad = np.nonzero((got.maps != ref.maps).reshape(w.sweep.n, -1).any(axis=1))[0]
+        assert bad.size == 0, f"depth pictures differ at suns {bad[:10]}: " \
+            f"{int((got.maps[bad[0]] != ref.maps[bad[0]]).sum())} texels"
+    if bits:
+        assert np.array_equal(got.bits, ref.bits)
+    assert np.array_equal(got.counts, ref.counts)
+    np.testing.assert_allclose(got.power, ref.power, rtol=REL, atol=0)
+    np.testing.assert_allclose(got.power_ref, ref.power_ref, rtol=REL, atol=0)
+    np.testing.assert_allclose(got.energy, ref.energy, rtol=REL, atol=0)
+    exact = np.array_equal(got.power, ref.power) and np.array_equal(got.energy, ref.energy)
+    _say(f"[parity] {w.name}: ok (powers bit-identical: {exact}); shaded={int(got.counts.sum())}")
+    return got, ref
+
+
+def test_c1_tiny_full(ctx, oracle_lib):
+    for d in (0.0, 100.0):
+        got, ref = compare(ctx, oracle_lib, W.c1_tiny(d_poa=d))
+        assert int(got.counts[12].sum()) == 3200
+    assert got.loss == pytest.approx(0.04670964, abs=5e-9)
+
+
+@pytest.mark.parametrize("seed,n,k,tile", [(31, 200, 3, 64), (32, 130, 4, 32), (33, 257, 1, 128),
+                                           (34, 64, 16, 0), (35, 16, 2, 64), (36, 333, 5, 32)])
+def test_random_tiny_ragged(ctx, oracle_lib, seed, n, k, tile):
+    w = W.random_tiny(seed, n_boxes=10, n_loose=40, n_mod_side=3, map_n=n, k=k, n_sun=8)
+    compare(ctx, oracle_lib, w, tile=tile)
+
+
+def test_tile_sizes_give_identical_results(ctx):
+    w = W.random_tiny(41, n_boxes=12, n_loose=60, n_mod_side=3, map_n=300, k=4, n_sun=5)
+    sh, gh = ctx.load_scene(w.scene), ctx.define_generator(w.gen)
+    outs = [ctx.evaluate(sh, gh, w.gen, w.sweep, w.map_n, w.k, export_depth=True, export_bits=True, tile=t)
+            for t in (32, 64, 128)]
+    for o in outs[1:]:
+        assert np.array_equal(o.maps, outs[0].maps) and np.array_equal(o.bits, outs[0].bits)
+        assert np.array_equal(o.power, outs[0].power)
+
+
+def test_empty_scene_and_backlit_and_below_horizon(ctx, oracle_lib):
+    c1 = W.c1_tiny(d_poa=30.0)
+    empty = W.Workload("empty_scene", W.Scene(np.zeros((0, 3)), np.zeros((0, 3), np.int32)), c1.gen,
+                       W.make_sweep(40.4, [1, 172, 355], np.arange(0.0, 24.0, 1.0), d_poa=30.0), 256, 4)
+    got, _ = compare(ctx, oracle_lib, empty)
+    assert got.counts.sum() == 0
+    # north-facing module at winter noon: back-lit above the horizon
+    g = W.c1_tiny().gen
+    g.edge_v = g.edge_v * np.array([[1.0, -1.0, 1.0]])
+    g.edge_u = -g.edge_u
+    back = W.Workload("backlit", c1.scene, g, W.make_sweep(40.4, [355], [10.0, 12.0, 14.0, 23.0], d_poa=30.0), 128, 3)
+    got, _ = compare(ctx, oracle_lib, back)
+    assert got.counts.sum() == 0 and np.all(got.maps == (1 << 24) - 1)
+
+
+def test_guard_band_clip_path(ctx, oracle_lib):
+    """A vertical module seen almost edge-on makes the window very thin, so scene geometry a
+    few metres away lies millions of texels out and goes through the guard-band clip."""
+    gen = W.Generator(np.array([[0.0, 0.0, 0.5]]), np.array([[0.936, 0.0, 0.0]]), np.array([[0.0, 0.0, 1.56]]),
+                      6, 10, W.portrait_substrings(), 3, np.zeros(1, np.int32))
+    assert np.allclose(np.cross(gen.edge_u[0], gen.edge_v[0]) / 1.46016, [0, -1, 0])
+    s = np.array([[1.0, -0.001, 0.05], [1.0, -0.002, 0.3], [0.6, -0.8, 0.2]])
+    s /= np.linalg.norm(s, axis=1, keepdims=True)
+    sw = W.Sweep(s, np.full(3, 1000.0), np.full(3, 20.0), np.ones(3), np.zeros(3, np.int32), np.zeros(3))
+    m = W._Mesh()
+    m.add(*W.ground_plane(-100, -100, 100, 100, 0.0))
+    m.add(*W.boxes(0.5, -3.0, 0.2, 0.2, 0.0, 4.0, 0.0))
+    m.add(*W.boxes(-2.0, -1.0, 0.5, 0.5, 0.0, 2.0, 0.3))
+    w = W.Workload("clip", m.scene(), gen, sw, 512, 4)
+    compare(ctx, oracle_lib, w)
+
+
+def test_device_outputs_match_host_outputs(ctx):
+    import torch
+    w = W.random_tiny(51, n_boxes=8, n_loose=30, n_mod_side=3, map_n=192, k=4, n_sun=6)
+    sh, gh = ctx.load_scene(w.scene), ctx.define_generator(w.gen)
+    host = ctx.evaluate(sh, gh, w.gen, w.sweep, w.map_n, w.k)
+    counts = torch.zeros((w.sweep.n, w.gen.n_cells), dtype=torch.int32, device="cuda")
+    dev = ctx.evaluate_device(sh, gh, w.gen, w.sweep, w.map_n, w.k, counts=counts)
+    torch.cuda.synchronize()
+    assert np.array_equal(counts.cpu().numpy().view(np.uint32), host.counts)
+    assert np.array_equal(dev.power.cpu().numpy(), host.power)
+    assert np.array_equal(dev.energy.cpu().numpy(), host.energy)
+
+
+def test_argument_errors(ctx):
+    from paper_1410_5780_amd import pv3d
+    w = W.c1_tiny()
+    sh, gh = ctx.load_scene(w.scene), ctx.define_generator(w.gen)
+    with pytest.raises(pv3d.Pv3dError) as e:
+        ctx.evaluate(sh, gh, w.gen, w.sweep, 8, 4)
+    assert e.value.code == pv3d.EINVAL
+    with pytest.raises(pv3d.Pv3dError) as e:
+        ctx.evaluate(sh, gh, w.gen, w.sweep, 64, 0)
+    assert e.value.code == pv3d.EINVAL
+    bad = w.sweep.subset([12])
+    bad.sun_xyz = bad.sun_xyz * 1.01
+    with pytest.raises(pv3d.Pv3dError) as e:
+        ctx.evaluate(sh, gh, w.gen, bad, 64, 2)
+    assert e.value.code == pv3d.EINVAL
+    with pytest.raises(pv3d.Pv3dError) as e:
+        ctx.evaluate(sh + 1000, gh, w.gen, w.sweep, 64, 2)
+    assert e.value.code == pv3d.ENOENT
+    nan = W.Scene(np.array([[0.0, 0.0, np.nan], [1, 0, 0], [0, 1, 0]]), np.array([[0, 1, 2]], np.int32))
+    with pytest.raises(pv3d.Pv3dError) as e:
+        ctx.load_scene(nan)
+    assert e.value.code == pv3d.EINVAL
+    small = pv3d.Context(0, budget_bytes=1 << 20)
+    with pytest.raises(pv3d.Pv3dError) as e:
+        small.load_scene(W.c2_row_plant(sweep=w.sweep.subset([12])).scene)
+    assert e.value.code == pv3d.ENOMEM
+    small.close()
+
+
+# ---------------------------------------------------------------------------
+# full-size configurations on sampled suns
+# ---------------------------------------------------------------------------
+def test_c2_row_plant_full_size_sampled_suns(ctx, oracle_lib):
+    yr = W.year_sweep()
+    idx = [0, 100, 1500, 2200, 3000, 4378]          # low winter, morning, spring, summer dusk, afternoon, last
+    w = W.c2_row_plant(sweep=yr.subset(idx))
+    got, ref = compare(ctx, oracle_lib, w)
+    assert got.counts.sum() > 0
+
+
+def test_c3_rooftop_full_size_sampled_suns(ctx, oracle_lib):
+    yr = W.year_sweep()
+    w = W.c3_rooftop(sweep=yr.subset([700, 2200]))
+    got, ref = compare(ctx, oracle_lib, w, bits=False)
+    assert got.counts.sum() > 0
