@@ -24,7 +24,8 @@
  *    they are host memory or device memory of the context's GPU.
  *  - Handles (scenes, generators, tickets) belong to the context and are freed
  *    by pv3d_destroy.
- *  - Limits: 16 <= map_n <= 16384; 1 <= k <= 255; n_cu, n_cv in [1, 4096];
+ *  - Limits: 16 <= map_n <= 16384; 1 <= k <= 255; n_cu, n_cv in [1, 4096] with
+ *    k*n_cu and k*n_cv at most 4095;
  *    n_vert, n_tri < 2^31; at least one module; all modules share n_cu, n_cv.
  *
  * Threading: a context may be used from one thread at a time, except that
@@ -109,12 +110,19 @@ pv3d_status pv3d_sun_cooper(double lat_deg, const int32_t* day, const double* so
 /* Steps 3 and 4 (Sec. 2). flags: */
 #define PV3D_EXPORT_DEPTH 1u   /* write every sun's depth picture to outputs.depth_maps */
 #define PV3D_EXPORT_BITS 2u    /* write every sample's shaded flag to outputs.shaded_bits */
+#define PV3D_SEPARATE_TEST 4u  /* depth-check samples in a second kernel that reads the
+                                  materialised picture (default: inside the raster tile);
+                                  results are identical, this route exists for cross-checks */
+#define PV3D_FULL_RASTER 8u    /* raster every texel of the picture even when it is not
+                                  exported (default: only texels that hold a sample); results
+                                  are identical, this route exists for cross-checks */
 
 typedef struct {
     int32_t map_n;     /* depth picture is map_n x map_n texels */
     int32_t k;         /* k x k sample points per cell (Sec. 2 Step 3 uses 3 x 3) */
     uint32_t flags;    /* PV3D_EXPORT_* */
-    int32_t tile;      /* raster tile edge in texels: 0 = library's choice, else 32/64/128 */
+    int32_t tile;      /* raster tile edge in texels: 0 = library's choice (64 up to map_n
+                          4096, else 128), else 32/64/128 */
 } pv3d_params;
 
 /* Outputs (all optional except power, power_ref, energy):
@@ -187,6 +195,23 @@ pv3d_status pv3d_poll(pv3d_ctx* ctx, uint64_t ticket, int32_t* done);
 pv3d_status pv3d_wait(pv3d_ctx* ctx, uint64_t ticket);
 /* Cancel a job that has not completed; its outputs are left undefined. */
 pv3d_status pv3d_cancel(pv3d_ctx* ctx, uint64_t ticket);
+
+/* Kernel timing, a profiling aid. With bit i of stage_mask set, the per-sun
+ * path records a pair of HIP events on its stream around every launch of
+ * stage i (0 tri_setup, 1 bin_scan, 2 bin_scatter, 3 raster, 4 sample_test,
+ * 5 setup, 6 loss); mask 0 turns recording off and clears the sums.
+ * pv3d_profile_read waits for the recorded work and returns, for one stage,
+ * the summed event-measured duration in milliseconds and the launch count. */
+#define PV3D_STAGE_TRI_SETUP 0
+#define PV3D_STAGE_BIN_SCAN 1
+#define PV3D_STAGE_BIN_SCATTER 2
+#define PV3D_STAGE_RASTER 3
+#define PV3D_STAGE_SAMPLE_TEST 4
+#define PV3D_STAGE_SETUP 5
+#define PV3D_STAGE_LOSS 6
+#define PV3D_N_STAGES 7
+pv3d_status pv3d_profile_enable(pv3d_ctx* ctx, uint32_t stage_mask);
+pv3d_status pv3d_profile_read(pv3d_ctx* ctx, int32_t stage, double* total_ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

@@ -54,19 +54,38 @@ struct SunCounters {
     int32_t pad;
 };
 
-// Where one sun's triangle set-up and binning write.
+// Where one sun's triangle set-up and binning write. A bin entry is a
+// triangle record id (>= 0) or a module -(m + 1) whose samples may fall in
+// the tile.
 struct BinBuffers {
     TriRec* rec;
     int32_t rec_cap;
-    int32_t* large;        // [rec_cap] record ids of large triangles
+    int32_t* large;        // [rec_cap] record ids of triangles every tile checks
     int32_t* tile_count;   // [n_tiles] (zero between suns)
     int32_t* tile_start;   // [n_tiles + 1]
     int32_t* tile_cursor;  // [n_tiles]
     int32_t* bins;         // [bin_cap]
+    int4* modbox;          // [n_mod] tile range (x0, x1, y0, y1) of each module's samples; x0 > x1: none
     int32_t bin_cap;
     int32_t tile;          // tile edge in texels
     int32_t ntx;           // tiles per row
+    int32_t n_tiles;
     int32_t large_tiles;   // triangles touching more tiles than this go to the large list
+};
+
+// What the tile kernel writes for one sun.
+struct TileOut {
+    uint32_t* map;         // depth picture to export, or nullptr
+    uint32_t* counts;      // [n_cells] shaded samples (accumulated; zero beforehand)
+    uint32_t* bits;        // [n_cells][words] shaded flags (accumulated), or nullptr
+    int32_t test;          // 1: depth-check the samples inside the tile
+    int32_t sparse;        // 1: evaluate the picture only at sample texels (no export)
+};
+
+// Tile grid of one evaluation: tile edge, tiles per row, tile count, and the
+// 32-bit words of a per-sun mask with one bit per tile.
+struct TileGrid {
+    int32_t tile, ntx, n_tiles, words;
 };
 
 // Generator as the kernels see it.
@@ -94,14 +113,19 @@ hipError_t launch_sample_tables(double* fu, double* fv, int32_t k, int32_t n_cu,
                                 hipStream_t st);
 hipError_t launch_setup(const double* sun, int64_t n_sun, const double* dni, const GenDev& g,
                         const double* sphere, int32_t n, View* views, double* beam, int32_t* bias,
-                        hipStream_t st);
+                        const TileGrid& tg, uint32_t* tmask, hipStream_t st);
 hipError_t launch_tri_setup(int64_t s, const View* views, const SceneDev& sc, const GenDev& g,
-                            int32_t n, const BinBuffers& bb, SunCounters* ctr, hipStream_t st);
+                            const int32_t* bias, int32_t n, const BinBuffers& bb, SunCounters* ctr,
+                            const uint32_t* tmask, hipStream_t st);
 hipError_t launch_bin_scan(int32_t n_tiles, const BinBuffers& bb, hipStream_t st);
-hipError_t launch_bin_scatter(int64_t s, const BinBuffers& bb, int32_t n_tiles,
-                              SunCounters* ctr, hipStream_t st);
+hipError_t launch_bin_scatter(int64_t s, const BinBuffers& bb, int32_t n_mod, SunCounters* ctr,
+                              int32_t grid, const uint32_t* tmask, hipStream_t st);
 hipError_t launch_raster(int64_t s, const View* views, const BinBuffers& bb, const SunCounters* ctr,
-                         int32_t n, uint32_t* map, hipStream_t st);
+                         int32_t n, const GenDev& g, const int32_t* bias, const double* fu,
+                         const double* fv, int32_t k, const TileOut& out, const uint32_t* tmask,
+                         hipStream_t st);
+size_t bin_lds_bytes(int32_t n_tiles);
+hipError_t configure_kernels(size_t max_lds);
 hipError_t launch_sample_test(int64_t s, const View* views, const GenDev& g, const double* beam,
                               const int32_t* bias, const double* fu, const double* fv, int32_t k,
                               const uint32_t* map, int32_t n, uint32_t* counts, uint32_t* bits,

@@ -3,19 +3,27 @@
 //
 // Per sun position:
 //   setup       one workgroup per sun: image basis, window over the module
-//               corners, depth range, per-module beam and depth bias
-//   tri_setup   one thread per triangle: FP64 light-space transform, culling,
-//               guard-band clip, 1/256-texel snap, fixed-point edge and depth
-//               planes, tile counts
+//               corners, depth range, per-module beam and depth bias, and the
+//               mask of tiles that hold samples
+//   tri_setup   one thread per triangle (and per module): FP64 light-space
+//               transform, culling, guard-band clip, 1/256-texel snap,
+//               fixed-point edge and depth planes; per-tile counts in LDS
 //   bin_scan    exclusive scan of the tile counts (one workgroup)
-//   bin_scatter one thread per set-up triangle: triangle ids into tile bins
-//   raster      one workgroup per tile: depth tile in LDS, nearest depth by
-//               ds_min_u32, 8x8-pixel stamps per wave, coalesced tile store
-//   sample_test one wave per cell: FP64 affine map of the k x k sub-cell
-//               samples, depth check against the picture, ballot + popcount
+//   bin_scatter triangle ids and modules into tile bins: per-workgroup LDS
+//               ranks, one global atomic per (workgroup, tile)
+//   tile        one workgroup per tile. Full route: 8x8-pixel stamps per
+//               wave with whole-stamp reject / accept and ds_min_u32 into an
+//               LDS depth tile, optional coalesced store. Sparse route: only
+//               texels that hold a sample are evaluated. Either way the
+//               samples whose texel lies in the tile are depth-checked there.
+//   sample_test the same depth check from a materialised picture (one wave
+//               per cell), kept as an independent second route
 //   loss        one workgroup per sun: substring capacities, ideal bypass
 //               string power, strings summed in order
 //   energy      sum of power * dt in sun order
+// (Triangle, tile) pairs are spread over the lanes of a wave, and tiles
+// read triangle records in batches, so neither binning nor raster waits on
+// one memory round trip per pair.
 //
 // Arithmetic: binary64 with contraction disabled (-ffp-contract=off), every
 // dot product as (ax*bx + ay*by) + az*bz, so the FP64 steps give the same
@@ -38,7 +46,6 @@ __device__ __forceinline__ d3 cross(d3 a, d3 b) {
 __device__ __forceinline__ d3 add(d3 a, d3 b) { return d3{a.x + b.x, a.y + b.y, a.z + b.z}; }
 
 __device__ __forceinline__ int64_t floor_shift(int64_t a, int s) { return a >> s; }  // arithmetic
-
 // ---------------------------------------------------------------------------
 // generator preparation
 // ---------------------------------------------------------------------------
@@ -114,19 +121,55 @@ __global__ void k_sample_tables(double* fu, double* fv, int32_t k, int32_t n_cu,
 }
 
 // ---------------------------------------------------------------------------
-// per-sun view and module terms
+// per-sun view, module terms and the tiles that hold samples
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ d3 to_light(const View& V, d3 p) {
+    return d3{(dot(p, ld3(V.e1)) - V.ox) * V.itx, (dot(p, ld3(V.e2)) - V.oy) * V.ity,
+              (dot(p, ld3(V.d)) - V.znear) * V.izd};
+}
+
+// A rectangle of tiles; empty when x0 > x1.
+struct TileBox {
+    int32_t x0, x1, y0, y1;
+    __device__ int32_t count() const { return x0 > x1 ? 0 : (x1 - x0 + 1) * (y1 - y0 + 1); }
+};
+
+__device__ __forceinline__ TileBox rec_box(int32_t ilo, int32_t ihi, int32_t jlo, int32_t jhi, int32_t T) {
+    return TileBox{ilo / T, ihi / T, jlo / T, jhi / T};
+}
+
+// Tile range of the texels a module's samples can fall in: the texel box of
+// its corners widened by one texel, clamped to the map like the samples.
+__device__ TileBox module_box(const View& V, const Module& M, int32_t n, int32_t T) {
+    double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+    for (int q = 0; q < 4; q++) {
+        d3 p;
+        module_corner(M, q, p);
+        d3 l = to_light(V, p);
+        xmin = fmin(xmin, l.x); xmax = fmax(xmax, l.x);
+        ymin = fmin(ymin, l.y); ymax = fmax(ymax, l.y);
+    }
+    const double hi = (double)(n - 1);
+    int32_t i0 = (int32_t)fmin(fmax(floor(xmin) - 1.0, 0.0), hi), i1 = (int32_t)fmin(fmax(floor(xmax) + 1.0, 0.0), hi);
+    int32_t j0 = (int32_t)fmin(fmax(floor(ymin) - 1.0, 0.0), hi), j1 = (int32_t)fmin(fmax(floor(ymax) + 1.0, 0.0), hi);
+    return TileBox{i0 / T, i1 / T, j0 / T, j1 / T};
+}
+
+constexpr int kMaxMaskWords = 512;   // up to 16384 tiles per sun
+
 __global__ __launch_bounds__(256) void k_setup(const double* sun, const double* dni, GenDev g,
                                                const double* sphere, int32_t n, View* views,
-                                               double* beam, int32_t* bias) {
+                                               double* beam, int32_t* bias, TileGrid tg, uint32_t* tmask) {
     __shared__ double red[5][256];
     __shared__ int any_front;
     __shared__ View sv;
+    __shared__ uint32_t mask[kMaxMaskWords];
     const int64_t s = blockIdx.x;
     const int tid = threadIdx.x;
     const d3 sn = ld3(sun + 3 * s);
     const bool up = sn.z > 0.0;
     if (tid == 0) any_front = 0;
+    for (int q = tid; q < tg.words; q += 256) mask[q] = 0;
     __syncthreads();
     if (up)
         for (int m = tid; m < g.n_mod; m += 256)
@@ -203,20 +246,104 @@ __global__ __launch_bounds__(256) void k_setup(const double* sun, const double* 
         }
         beam[s * g.n_mod + m] = bm;
         bias[s * g.n_mod + m] = bi;
+        if (tmask && bi >= 0) {
+            const TileBox b = module_box(sv, g.mods[m], n, tg.tile);
+            for (int32_t ty = b.y0; ty <= b.y1; ty++)
+                for (int32_t tx = b.x0; tx <= b.x1; tx++) {
+                    const int32_t q = ty * tg.ntx + tx;
+                    atomicOr(&mask[q >> 5], 1u << (q & 31));
+                }
+        }
+    }
+    if (tmask) {
+        __syncthreads();
+        for (int q = tid; q < tg.words; q += 256) tmask[s * tg.words + q] = mask[q];
     }
 }
 
 // ---------------------------------------------------------------------------
 // triangle set-up and binning
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ d3 to_light(const View& V, d3 p) {
-    return d3{(dot(p, ld3(V.e1)) - V.ox) * V.itx, (dot(p, ld3(V.e2)) - V.oy) * V.ity,
-              (dot(p, ld3(V.d)) - V.znear) * V.izd};
+__device__ __forceinline__ bool mask_has(const uint32_t* m, int32_t q) {
+    return m == nullptr || ((m[q >> 5] >> (q & 31)) & 1u);
 }
 
-// Snap, orient and set up one light-space triangle; append it to the records
-// and count it into the tiles it touches.
-__device__ void emit_triangle(const d3 t[3], int32_t n, const BinBuffers& bb, SunCounters* ctr) {
+// Edges of a set-up triangle as the binning test needs them.
+struct Edges {
+    int64_t e0[3];
+    int32_t a[3], b[3];
+    int32_t ilo, ihi, jlo, jhi;
+};
+
+// False when one edge excludes every pixel centre of the triangle's box
+// clipped to tile (tx, ty): that tile cannot hold a covered pixel.
+__device__ __forceinline__ bool tile_overlap(const Edges& E, int32_t tx, int32_t ty, int32_t T) {
+    const int32_t i0 = max(E.ilo, tx * T), i1 = min(E.ihi, tx * T + T - 1);
+    const int32_t j0 = max(E.jlo, ty * T), j1 = min(E.jhi, ty * T + T - 1);
+    for (int e = 0; e < 3; e++) {
+        const int64_t A = (int64_t)E.a[e] * 256, B = (int64_t)E.b[e] * 256;
+        if (E.e0[e] + A * (A > 0 ? i1 : i0) + B * (B > 0 ? j1 : j0) < 0) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ void edges_of(const TriRec& r, Edges& E) {
+    for (int e = 0; e < 3; e++) { E.e0[e] = r.e0[e]; E.a[e] = r.a[e]; E.b[e] = r.b[e]; }
+    E.ilo = r.ilo; E.ihi = r.ihi; E.jlo = r.jlo; E.jhi = r.jhi;
+}
+
+// Every (lane, tile) pair of a wave, 64 at a time: lane L owns the tiles of
+// box[L] (kind 0: none, 1: a triangle whose tiles pass the overlap test,
+// 2: a module, every tile of its box). f(q, payload of the owner) runs for
+// each kept tile q on the lane that takes the pair. All lanes of the wave
+// must call this (the shuffles need every lane active).
+template <typename F>
+__device__ __forceinline__ void wave_pairs(const TileBox& box, int32_t kind, const Edges& E, int32_t payload, int lane,
+                                           int32_t T, int32_t ntx, const uint32_t* mask, F&& f) {
+    const int32_t cnt = kind ? box.count() : 0;
+    int32_t incl = cnt;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    const int32_t total = __shfl(incl, 63, 64);
+    const int32_t excl = incl - cnt;
+    for (int32_t base = 0; base < total; base += 64) {
+        const bool live = base + lane < total;
+        const int32_t p = min(base + lane, total - 1);
+        int32_t lo = 0, hi = 63;                       // owner: last lane whose first pair is <= p
+        for (int it = 0; it < 6; it++) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            const bool le = __shfl(excl, mid, 64) <= p;
+            lo = le ? mid : lo;
+            hi = le ? hi : mid - 1;
+        }
+        const int32_t o = lo;
+        const int32_t okind = __shfl(kind, o, 64);
+        const int32_t ox0 = __shfl(box.x0, o, 64), ox1 = __shfl(box.x1, o, 64), oy0 = __shfl(box.y0, o, 64);
+        const int32_t q = p - __shfl(excl, o, 64);
+        const int32_t bw = ox1 - ox0 + 1;
+        const int32_t ty = oy0 + q / bw, tx = ox0 + q % bw;
+        Edges oe;
+        for (int e = 0; e < 3; e++) {
+            oe.e0[e] = __shfl(E.e0[e], o, 64);
+            oe.a[e] = __shfl(E.a[e], o, 64);
+            oe.b[e] = __shfl(E.b[e], o, 64);
+        }
+        oe.ilo = __shfl(E.ilo, o, 64); oe.ihi = __shfl(E.ihi, o, 64);
+        oe.jlo = __shfl(E.jlo, o, 64); oe.jhi = __shfl(E.jhi, o, 64);
+        const int32_t opay = __shfl(payload, o, 64);
+        const int32_t tq = ty * ntx + tx;
+        bool keep = live && mask_has(mask, tq);
+        if (keep && okind == 1) keep = tile_overlap(oe, tx, ty, T);
+        if (keep) f(tq, opay);
+    }
+}
+
+// Snap, orient and set up one light-space triangle and append its record;
+// returns the record id, or -1 when it covers no pixel centre.
+__device__ int32_t emit_triangle(const d3 t[3], int32_t n, const BinBuffers& bb, SunCounters* ctr, Edges& E,
+                                 bool& large) {
     int64_t X[3], Y[3];
     double Z[3];
     const double tv[3][3] = {{t[0].x, t[0].y, t[0].z}, {t[1].x, t[1].y, t[1].z}, {t[2].x, t[2].y, t[2].z}};
@@ -226,7 +353,7 @@ __device__ void emit_triangle(const d3 t[3], int32_t n, const BinBuffers& bb, Su
         Z[q] = tv[q][2];
     }
     int64_t A = (X[1] - X[0]) * (Y[2] - Y[0]) - (X[2] - X[0]) * (Y[1] - Y[0]);
-    if (A == 0) return;
+    if (A == 0) return -1;
     if (A < 0) {
         int64_t tx = X[1]; X[1] = X[2]; X[2] = tx;
         int64_t ty = Y[1]; Y[1] = Y[2]; Y[2] = ty;
@@ -240,7 +367,7 @@ __device__ void emit_triangle(const d3 t[3], int32_t n, const BinBuffers& bb, Su
     int64_t jlo = -floor_shift(-(ymin - 128), kSubBits), jhi = floor_shift(ymax - 128, kSubBits);
     ilo = max(ilo, (int64_t)0); jlo = max(jlo, (int64_t)0);
     ihi = min(ihi, (int64_t)n - 1); jhi = min(jhi, (int64_t)n - 1);
-    if (ilo > ihi || jlo > jhi) return;
+    if (ilo > ihi || jlo > jhi) return -1;
 
     TriRec r;
     const int ea[3] = {1, 2, 0}, eb[3] = {2, 0, 1};
@@ -281,19 +408,16 @@ __device__ void emit_triangle(const d3 t[3], int32_t n, const BinBuffers& bb, Su
     int32_t idx = atomicAdd(&ctr->n_rec, 1);
     if (idx >= bb.rec_cap) {
         atomicOr(&ctr->overflow, 1);
-        return;
+        return -1;
     }
     bb.rec[idx] = r;
-    const int32_t T = bb.tile;
-    int32_t tx0 = (int32_t)ilo / T, tx1 = (int32_t)ihi / T, ty0 = (int32_t)jlo / T, ty1 = (int32_t)jhi / T;
-    int32_t nt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-    if (nt > bb.large_tiles) {
+    edges_of(r, E);
+    large = rec_box((int32_t)ilo, (int32_t)ihi, (int32_t)jlo, (int32_t)jhi, bb.tile).count() > bb.large_tiles;
+    if (large) {
         int32_t li = atomicAdd(&ctr->n_large, 1);
         bb.large[li] = idx;
-    } else {
-        for (int32_t ty = ty0; ty <= ty1; ty++)
-            for (int32_t tx = tx0; tx <= tx1; tx++) atomicAdd(&bb.tile_count[ty * bb.ntx + tx], 1);
     }
+    return idx;
 }
 
 // Sutherland-Hodgman against one side of the guard square.
@@ -316,9 +440,12 @@ __device__ int clip_side(const d3* in, int nin, d3* out, int axis, double c, boo
     return m;
 }
 
-__device__ __noinline__ void clip_and_emit(const d3 t[3], int32_t n, const BinBuffers& bb, SunCounters* ctr) {
+// A triangle reaching beyond the guard square: clip, fan, set up each piece
+// and count it (one lane; such triangles are rare).
+__device__ __noinline__ void clip_and_emit(d3 t0, d3 t1, d3 t2, int32_t n, BinBuffers bb, SunCounters* ctr,
+                                           uint32_t* cnt, const uint32_t* mask) {
     d3 a[8], b[8];
-    a[0] = t[0]; a[1] = t[1]; a[2] = t[2];
+    a[0] = t0; a[1] = t1; a[2] = t2;
     int m = clip_side(a, 3, b, 0, -kGuard, true);
     if (m < 3) return;
     m = clip_side(b, m, a, 0, kGuard, false);
@@ -329,39 +456,81 @@ __device__ __noinline__ void clip_and_emit(const d3 t[3], int32_t n, const BinBu
     if (m < 3) return;
     for (int q = 1; q + 1 < m; q++) {
         d3 f[3] = {a[0], a[q], a[q + 1]};
-        emit_triangle(f, n, bb, ctr);
+        Edges E;
+        bool large = false;
+        if (emit_triangle(f, n, bb, ctr, E, large) < 0 || large) continue;
+        const TileBox box = rec_box(E.ilo, E.ihi, E.jlo, E.jhi, bb.tile);
+        for (int32_t ty = box.y0; ty <= box.y1; ty++)
+            for (int32_t tx = box.x0; tx <= box.x1; tx++) {
+                const int32_t tq = ty * bb.ntx + tx;
+                if (mask_has(mask, tq) && tile_overlap(E, tx, ty, bb.tile)) atomicAdd(&cnt[tq], 1u);
+            }
     }
 }
 
+// One thread per scene triangle, module triangle and module: set-up, then
+// per-tile counts accumulated in LDS and added to the global counts once.
 __global__ __launch_bounds__(256) void k_tri_setup(int64_t s, const View* views, SceneDev sc, GenDev g,
-                                                   int32_t n, BinBuffers bb, SunCounters* ctr) {
+                                                   const int32_t* bias, int32_t n, BinBuffers bb,
+                                                   SunCounters* ctr, const uint32_t* tmask) {
+    extern __shared__ uint32_t cnt[];
     const View& V = views[s];
-    if (!V.valid) return;
-    const int64_t total = sc.n_tri + (g.occluders ? 2 * (int64_t)g.n_mod : 0);
+    const int64_t n_tri_all = sc.n_tri + (g.occluders ? 2 * (int64_t)g.n_mod : 0);
     const int64_t t = blockIdx.x * 256ll + threadIdx.x;
-    if (t >= total) return;
-    d3 c[3];
-    if (t < sc.n_tri) {
-        for (int q = 0; q < 3; q++) c[q] = ld3(sc.xyz + 3 * (int64_t)sc.tri[3 * t + q]);
-    } else {
-        int64_t mt = t - sc.n_tri;
-        const Module& M = g.mods[mt / 2];
-        module_corner(M, 0, c[0]);
-        if ((mt & 1) == 0) { module_corner(M, 1, c[1]); module_corner(M, 2, c[2]); }
-        else { module_corner(M, 2, c[1]); module_corner(M, 3, c[2]); }
+    const int lane = threadIdx.x & 63;
+    if (!V.valid) {                                   // nothing is drawn or tested for this sun
+        if (t >= n_tri_all && t < n_tri_all + g.n_mod) bb.modbox[t - n_tri_all] = make_int4(1, 0, 1, 0);
+        return;
     }
-    d3 l[3];
-    for (int q = 0; q < 3; q++) l[q] = to_light(V, c[q]);
-    double zmin = fmin(l[0].z, fmin(l[1].z, l[2].z));
-    if (zmin > (double)kDepthMax) return;
-    double xmin = fmin(l[0].x, fmin(l[1].x, l[2].x)), xmax = fmax(l[0].x, fmax(l[1].x, l[2].x));
-    double ymin = fmin(l[0].y, fmin(l[1].y, l[2].y)), ymax = fmax(l[0].y, fmax(l[1].y, l[2].y));
-    if (xmax < 0.0 || xmin >= (double)n || ymax < 0.0 || ymin >= (double)n) return;
-    bool big = false;
-    for (int q = 0; q < 3; q++)
-        if (fabs(l[q].x) >= kGuard || fabs(l[q].y) >= kGuard) big = true;
-    if (big) clip_and_emit(l, n, bb, ctr);
-    else emit_triangle(l, n, bb, ctr);
+    for (int32_t q = threadIdx.x; q < bb.n_tiles; q += 256) cnt[q] = 0;
+    __syncthreads();
+    TileBox box{1, 0, 1, 0};
+    int32_t kind = 0;
+    Edges E;
+    for (int e = 0; e < 3; e++) { E.e0[e] = 0; E.a[e] = 0; E.b[e] = 0; }
+    E.ilo = E.ihi = E.jlo = E.jhi = 0;
+    if (t < n_tri_all) {
+        d3 c[3];
+        if (t < sc.n_tri) {
+            for (int q = 0; q < 3; q++) c[q] = ld3(sc.xyz + 3 * (int64_t)sc.tri[3 * t + q]);
+        } else {
+            int64_t mt = t - sc.n_tri;
+            const Module& M = g.mods[mt / 2];
+            module_corner(M, 0, c[0]);
+            if ((mt & 1) == 0) { module_corner(M, 1, c[1]); module_corner(M, 2, c[2]); }
+            else { module_corner(M, 2, c[1]); module_corner(M, 3, c[2]); }
+        }
+        d3 l[3];
+        for (int q = 0; q < 3; q++) l[q] = to_light(V, c[q]);
+        double zmin = fmin(l[0].z, fmin(l[1].z, l[2].z));
+        double xmin = fmin(l[0].x, fmin(l[1].x, l[2].x)), xmax = fmax(l[0].x, fmax(l[1].x, l[2].x));
+        double ymin = fmin(l[0].y, fmin(l[1].y, l[2].y)), ymax = fmax(l[0].y, fmax(l[1].y, l[2].y));
+        bool keep = !(zmin > (double)kDepthMax) && !(xmax < 0.0 || xmin >= (double)n || ymax < 0.0 || ymin >= (double)n);
+        if (keep) {
+            bool big = false;
+            for (int q = 0; q < 3; q++)
+                if (fabs(l[q].x) >= kGuard || fabs(l[q].y) >= kGuard) big = true;
+            if (big) {
+                clip_and_emit(l[0], l[1], l[2], n, bb, ctr, cnt, tmask);
+            } else {
+                bool large = false;
+                if (emit_triangle(l, n, bb, ctr, E, large) >= 0 && !large) {
+                    box = rec_box(E.ilo, E.ihi, E.jlo, E.jhi, bb.tile);
+                    kind = 1;
+                }
+            }
+        }
+    } else if (t < n_tri_all + g.n_mod) {
+        const int32_t m = (int32_t)(t - n_tri_all);
+        TileBox b{1, 0, 1, 0};
+        if (bias[s * g.n_mod + m] >= 0) b = module_box(V, g.mods[m], n, bb.tile);
+        bb.modbox[m] = make_int4(b.x0, b.x1, b.y0, b.y1);
+        if (b.count() > 0) { box = b; kind = 2; }
+    }
+    wave_pairs(box, kind, E, 0, lane, bb.tile, bb.ntx, tmask, [&](int32_t tq, int32_t) { atomicAdd(&cnt[tq], 1u); });
+    __syncthreads();
+    for (int32_t q = threadIdx.x; q < bb.n_tiles; q += 256)
+        if (cnt[q]) atomicAdd(&bb.tile_count[q], (int32_t)cnt[q]);
 }
 
 __global__ __launch_bounds__(1024) void k_bin_scan(int32_t n_tiles, BinBuffers bb) {
@@ -390,89 +559,533 @@ __global__ __launch_bounds__(1024) void k_bin_scan(int32_t n_tiles, BinBuffers b
     if (tid == 1023) bb.tile_start[n_tiles] = part[1023];
 }
 
-__global__ __launch_bounds__(256) void k_bin_scatter(int64_t s, BinBuffers bb, SunCounters* ctr) {
+// Item of the scatter: a binned triangle record (kind 1) or a module (kind 2).
+__device__ __forceinline__ void scatter_item(int32_t item, int32_t n_rec, int32_t n_items, const BinBuffers& bb,
+                                             TileBox& box, int32_t& kind, Edges& E, int32_t& id) {
+    box = TileBox{1, 0, 1, 0};
+    kind = 0;
+    id = 0;
+    for (int e = 0; e < 3; e++) { E.e0[e] = 0; E.a[e] = 0; E.b[e] = 0; }
+    E.ilo = E.ihi = E.jlo = E.jhi = 0;
+    if (item >= n_items) return;
+    if (item < n_rec) {
+        const TriRec& r = bb.rec[item];
+        edges_of(r, E);
+        const TileBox b = rec_box(r.ilo, r.ihi, r.jlo, r.jhi, bb.tile);
+        id = item;
+        if (b.count() <= bb.large_tiles) { box = b; kind = 1; }
+        return;
+    }
+    const int32_t m = item - n_rec;
+    const int4 v = bb.modbox[m];
+    id = -(m + 1);
+    box = TileBox{v.x, v.y, v.z, v.w};
+    if (box.count() > 0) kind = 2;
+}
+
+// A contiguous range of items per workgroup: count per tile in LDS, take one
+// block of bin slots per (workgroup, tile) with a single global atomic, then
+// place every (item, tile) pair at its LDS-assigned rank inside that block.
+// The pair filter is the one k_tri_setup counted with.
+__global__ __launch_bounds__(256) void k_bin_scatter(int64_t s, BinBuffers bb, int32_t n_mod, SunCounters* ctr,
+                                                     const uint32_t* tmask) {
+    extern __shared__ uint32_t lds[];
+    uint32_t* cnt = lds;                 // per-tile count, then running rank
+    uint32_t* base = lds + bb.n_tiles;   // per-tile first bin slot of this workgroup
+    const int lane = threadIdx.x & 63;
     const int32_t n_rec = min(ctr[s].n_rec, bb.rec_cap);
-    const int32_t idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= n_rec) return;
-    const TriRec& r = bb.rec[idx];
-    const int32_t T = bb.tile;
-    int32_t tx0 = r.ilo / T, tx1 = r.ihi / T, ty0 = r.jlo / T, ty1 = r.jhi / T;
-    if ((tx1 - tx0 + 1) * (ty1 - ty0 + 1) > bb.large_tiles) return;
-    for (int32_t ty = ty0; ty <= ty1; ty++)
-        for (int32_t tx = tx0; tx <= tx1; tx++) {
-            int32_t pos = atomicAdd(&bb.tile_cursor[ty * bb.ntx + tx], 1);
-            if (pos < bb.bin_cap) bb.bins[pos] = idx;
+    const int32_t total = n_rec + n_mod;
+    const int32_t per = (total + (int32_t)gridDim.x - 1) / (int32_t)gridDim.x;
+    const int32_t i0 = blockIdx.x * per, i1 = min(i0 + per, total);
+    if (i0 >= i1) return;
+    for (int32_t q = threadIdx.x; q < bb.n_tiles; q += 256) cnt[q] = 0;
+    __syncthreads();
+    for (int32_t it0 = i0; it0 < i1; it0 += 256) {
+        TileBox box;
+        int32_t kind, id;
+        Edges E;
+        scatter_item(it0 + (int32_t)threadIdx.x, n_rec, i1, bb, box, kind, E, id);
+        wave_pairs(box, kind, E, id, lane, bb.tile, bb.ntx, tmask, [&](int32_t tq, int32_t) { atomicAdd(&cnt[tq], 1u); });
+    }
+    __syncthreads();
+    for (int32_t q = threadIdx.x; q < bb.n_tiles; q += 256) {
+        const uint32_t c = cnt[q];
+        if (c) base[q] = (uint32_t)atomicAdd(&bb.tile_cursor[q], (int32_t)c);
+        cnt[q] = 0;
+    }
+    __syncthreads();
+    for (int32_t it0 = i0; it0 < i1; it0 += 256) {
+        TileBox box;
+        int32_t kind, id;
+        Edges E;
+        scatter_item(it0 + (int32_t)threadIdx.x, n_rec, i1, bb, box, kind, E, id);
+        wave_pairs(box, kind, E, id, lane, bb.tile, bb.ntx, tmask, [&](int32_t tq, int32_t oid) {
+            const uint32_t pos = base[tq] + atomicAdd(&cnt[tq], 1u);
+            if (pos < (uint32_t)bb.bin_cap) bb.bins[pos] = oid;
             else atomicOr(&ctr[s].overflow, 1);
-        }
+        });
+    }
 }
 
 // ---------------------------------------------------------------------------
-// raster: one workgroup per tile, nearest depth wins (Fig. 3)
+// tile kernel. Every tile gathers the modules whose samples may fall in it.
+// Full route: raster every triangle into an LDS depth tile (the nearest depth
+// wins, Fig. 3), optionally store the tile, then depth-check the samples
+// whose texel lies in the tile (Fig. 4). Sparse route: the depth picture only
+// matters at texels that hold a sample, so the tile lists those samples
+// (sorted by texel row) and every triangle is tested at their texel centres
+// only; a sample's shaded flag is the same as with the full picture.
 // ---------------------------------------------------------------------------
-template <int TS>
-__global__ __launch_bounds__(256) void k_raster(int64_t s, const View* views, BinBuffers bb,
-                                                const SunCounters* ctr, int32_t n, uint32_t* map) {
-    constexpr int PITCH = TS + 8;                 // 8x8 stamp rows land in distinct banks
-    __shared__ uint32_t zt[TS * PITCH];
-    __shared__ int32_t next;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int32_t tile = blockIdx.x;
-    const int32_t x0 = (tile % bb.ntx) * TS, y0 = (tile / bb.ntx) * TS;
-    for (int q = tid; q < TS * PITCH; q += 256) zt[q] = kDepthMax;
-    if (tid == 0) next = 0;
-    __syncthreads();
-    if (views[s].valid) {
-        const int32_t n_large = ctr[s].n_large;
-        const int32_t bs = min(bb.tile_start[tile], bb.bin_cap);
-        const int32_t be = min(bb.tile_start[tile + 1], bb.bin_cap);
-        const int32_t total = n_large + (be - bs);
-        const int lx = lane & 7, ly = lane >> 3;
-        for (;;) {
-            int32_t got = 0;
-            if (lane == 0) got = atomicAdd(&next, 1);
-            const int32_t item = __builtin_amdgcn_readfirstlane(got);
-            if (item >= total) break;
-            const int32_t rid = __builtin_amdgcn_readfirstlane(item < n_large ? bb.large[item]
-                                                                             : bb.bins[bs + item - n_large]);
-            const TriRec& R = bb.rec[rid];
-            const int32_t ilo = max((int32_t)R.ilo, x0), ihi = min((int32_t)R.ihi, x0 + TS - 1);
-            const int32_t jlo = max((int32_t)R.jlo, y0), jhi = min((int32_t)R.jhi, y0 + TS - 1);
-            if (ilo > ihi || jlo > jhi) continue;
-            for (int32_t sy = (jlo - y0) & ~7; sy <= jhi - y0; sy += 8)
-                for (int32_t sx = (ilo - x0) & ~7; sx <= ihi - x0; sx += 8) {
-                    const int32_t px = x0 + sx + lx, py = y0 + sy + ly;
-                    const int64_t E0 = R.e0[0] + ((int64_t)R.a[0] * px + (int64_t)R.b[0] * py) * 256;
-                    const int64_t E1 = R.e0[1] + ((int64_t)R.a[1] * px + (int64_t)R.b[1] * py) * 256;
-                    const int64_t E2 = R.e0[2] + ((int64_t)R.a[2] * px + (int64_t)R.b[2] * py) * 256;
-                    if ((E0 | E1 | E2) >= 0) {
-                        const int64_t z = R.z0 + (int64_t)px * R.gx + (int64_t)py * R.gy;
-                        const int64_t zq = z >> 16;
-                        const uint32_t D = zq < 0 ? 0u : (zq > (int64_t)kDepthMax ? kDepthMax : (uint32_t)zq);
-                        atomicMin(&zt[(sy + ly) * PITCH + sx + lx], D);
-                    }
-                }
+constexpr int kMaxTileMods = 256;       // module entries kept in LDS per tile
+constexpr int kMaxCellCounters = 256;   // per-wave cell counters of the full route
+constexpr int kMaxTileCells = 2048;     // (module slot, cell) counters of the sparse route
+
+struct TileCtx {
+    int64_t s;
+    int32_t x0, y0, n, bs, be, n_large;
+};
+
+// Waves take triangles in chunks; the lanes of the wave load the chunk's
+// records at once, then the wave walks them one by one from registers.
+constexpr int kChunk = 16;
+
+struct RecLane {
+    uint32_t w[20];
+};
+
+__device__ __forceinline__ int32_t next_chunk(int32_t* next, int lane) {
+    int32_t got = 0;
+    if (lane == 0) got = atomicAdd(next, kChunk);
+    return __builtin_amdgcn_readfirstlane(got);
+}
+
+__device__ __forceinline__ int32_t load_chunk(const BinBuffers& bb, int32_t base, int32_t cnt, int32_t n_large,
+                                              int32_t bs, int lane, RecLane& L) {
+    for (int q = 0; q < 20; q++) L.w[q] = 0;
+    int32_t rid = -1;
+    if (lane < cnt) {
+        const int32_t item = base + lane;
+        rid = item < n_large ? bb.large[item] : bb.bins[bs + item - n_large];
+        if (rid >= 0) {
+            const uint4* p = reinterpret_cast<const uint4*>(bb.rec + rid);
+            for (int q = 0; q < 5; q++) {
+                const uint4 v = p[q];
+                L.w[4 * q] = v.x; L.w[4 * q + 1] = v.y; L.w[4 * q + 2] = v.z; L.w[4 * q + 3] = v.w;
+            }
         }
     }
-    __syncthreads();
-    // coalesced tile store
+    return rid;
+}
+
+__device__ __forceinline__ TriRec rec_of_lane(const RecLane& L, int i) {
+    uint32_t w[20];
+    for (int q = 0; q < 20; q++) w[q] = __builtin_amdgcn_readlane(L.w[q], i);
+    TriRec r;
+    __builtin_memcpy(&r, w, sizeof(TriRec));
+    return r;
+}
+
+// Per-module light-space affine map of the samples and the range of sample
+// indices (qa along edge_u, qb along edge_v) whose texel can lie in the tile.
+struct ModMap {
+    d3 p0, du, dv;
+    int32_t qa0, qa1, qb0, qb1;
+};
+
+template <int TS>
+__device__ __forceinline__ bool module_map(const View& V, const Module& M, int32_t knu, int32_t knv, const TileCtx& c,
+                                           ModMap& mm) {
+    const d3 e1 = ld3(V.e1), e2 = ld3(V.e2), dd = ld3(V.d);
+    mm.p0 = to_light(V, ld3(M.o));
+    const d3 U = ld3(M.u), W = ld3(M.v);
+    mm.du = d3{dot(U, e1) * V.itx, dot(U, e2) * V.ity, dot(U, dd) * V.izd};
+    mm.dv = d3{dot(W, e1) * V.itx, dot(W, e2) * V.ity, dot(W, dd) * V.izd};
+    mm.qa0 = 0; mm.qa1 = knu - 1; mm.qb0 = 0; mm.qb1 = knv - 1;
+    const d3 du = mm.du, dv = mm.dv, p0 = mm.p0;
+    const double det = du.x * dv.y - du.y * dv.x;
+    if (fabs(det) > 1e-9 * (fabs(du.x * dv.y) + fabs(du.y * dv.x)) && det != 0.0) {
+        // invert the map at the tile's corners (open-ended at map borders, where samples would clamp)
+        const double BIG = 1e15;
+        const double cx[2] = {c.x0 == 0 ? -BIG : (double)c.x0, c.x0 + TS >= c.n ? BIG : (double)(c.x0 + TS)};
+        const double cy[2] = {c.y0 == 0 ? -BIG : (double)c.y0, c.y0 + TS >= c.n ? BIG : (double)(c.y0 + TS)};
+        double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+        for (int qx = 0; qx < 2; qx++)
+            for (int qy = 0; qy < 2; qy++) {
+                const double ddx = cx[qx] - p0.x, ddy = cy[qy] - p0.y;
+                const double fu = (ddx * dv.y - ddy * dv.x) / det;
+                const double fv = (du.x * ddy - du.y * ddx) / det;
+                umin = fmin(umin, fu); umax = fmax(umax, fu);
+                vmin = fmin(vmin, fv); vmax = fmax(vmax, fv);
+            }
+        const double a0 = floor(umin * knu - 0.5) - 1.0, a1 = ceil(umax * knu - 0.5) + 1.0;
+        const double b0 = floor(vmin * knv - 0.5) - 1.0, b1 = ceil(vmax * knv - 0.5) + 1.0;
+        mm.qa0 = (int32_t)fmax(a0, 0.0); mm.qa1 = (int32_t)fmin(a1, (double)(knu - 1));
+        mm.qb0 = (int32_t)fmax(b0, 0.0); mm.qb1 = (int32_t)fmin(b1, (double)(knv - 1));
+    }
+    return mm.qa0 <= mm.qa1 && mm.qb0 <= mm.qb1;
+}
+
+// Light-space texel and depth of sample (qa, qb); false when its texel is not in the tile.
+template <int TS>
+__device__ __forceinline__ bool sample_in_tile(const ModMap& mm, const double* fu_tab, const double* fv_tab, int32_t qa,
+                                               int32_t qb, const TileCtx& c, int32_t* li, int32_t* lj, int64_t* zs) {
+    const double fu = fu_tab[qa], fv = fv_tab[qb];
+    const double x = (mm.p0.x + fu * mm.du.x) + fv * mm.dv.x;
+    const double y = (mm.p0.y + fu * mm.du.y) + fv * mm.dv.y;
+    const double z = (mm.p0.z + fu * mm.du.z) + fv * mm.dv.z;
+    int64_t i = (int64_t)floor(x), j = (int64_t)floor(y);
+    i = min(max(i, (int64_t)0), (int64_t)c.n - 1);
+    j = min(max(j, (int64_t)0), (int64_t)c.n - 1);
+    if (i < c.x0 || i >= c.x0 + TS || j < c.y0 || j >= c.y0 + TS) return false;
+    *li = (int32_t)(i - c.x0);
+    *lj = (int32_t)(j - c.y0);
+    *zs = (int64_t)floor(z);
+    return true;
+}
+
+// Record of a triangle touching the tile, with its box clipped to the tile;
+// false when the box or an edge excludes the whole clipped box.
+struct TriClip {
+    int32_t ilo, ihi, jlo, jhi;
+    int64_t EA[3], EB[3];
+};
+
+__device__ __forceinline__ bool clip_to_tile(const TriRec& R, int32_t x0, int32_t y0, int32_t TS, TriClip& t) {
+    t.ilo = max((int32_t)R.ilo, x0); t.ihi = min((int32_t)R.ihi, x0 + TS - 1);
+    t.jlo = max((int32_t)R.jlo, y0); t.jhi = min((int32_t)R.jhi, y0 + TS - 1);
+    if (t.ilo > t.ihi || t.jlo > t.jhi) return false;
+    bool outside = false;
+    for (int e = 0; e < 3; e++) {
+        t.EA[e] = (int64_t)R.a[e] * 256;
+        t.EB[e] = (int64_t)R.b[e] * 256;
+        const int64_t bmax = R.e0[e] + t.EA[e] * (t.EA[e] > 0 ? t.ihi : t.ilo) + t.EB[e] * (t.EB[e] > 0 ? t.jhi : t.jlo);
+        outside |= bmax < 0;
+    }
+    return !outside;
+}
+
+__device__ __forceinline__ uint32_t depth_q(int64_t z) {
+    const int64_t zq = z >> 16;
+    return zq < 0 ? 0u : (zq > (int64_t)kDepthMax ? kDepthMax : (uint32_t)zq);
+}
+
+// Full raster of the tile's triangles into zt (all waves; `next` starts at 0).
+template <int TS>
+__device__ void raster_full(uint32_t* zt, int32_t* next, const BinBuffers& bb, const TileCtx& c, int lane) {
+    constexpr int PITCH = TS + 8;
+    const int32_t total = c.n_large + (c.be - c.bs);
+    const int lx = lane & 7, ly = lane >> 3;
+    for (;;) {
+        const int32_t base = next_chunk(next, lane);
+        if (base >= total) break;
+        const int32_t cnt = min(kChunk, total - base);
+        RecLane L;
+        const int32_t rid = load_chunk(bb, base, cnt, c.n_large, c.bs, lane, L);
+        for (int ci = 0; ci < cnt; ci++) {
+        if (__builtin_amdgcn_readlane(rid, ci) < 0) continue;   // a module entry
+        const TriRec R = rec_of_lane(L, ci);
+        TriClip t;
+        if (!clip_to_tile(R, c.x0, c.y0, TS, t)) continue;
+        int64_t er[3], emaxo[3], emino[3], el[3];
+        for (int e = 0; e < 3; e++) {
+            emaxo[e] = (t.EA[e] > 0 ? 7 * t.EA[e] : 0) + (t.EB[e] > 0 ? 7 * t.EB[e] : 0);
+            emino[e] = (t.EA[e] < 0 ? 7 * t.EA[e] : 0) + (t.EB[e] < 0 ? 7 * t.EB[e] : 0);
+        }
+        const int32_t sx0 = c.x0 + ((t.ilo - c.x0) & ~7), sy0 = c.y0 + ((t.jlo - c.y0) & ~7);
+        for (int e = 0; e < 3; e++) {
+            el[e] = t.EA[e] * lx + t.EB[e] * ly;
+            er[e] = R.e0[e] + t.EA[e] * sx0 + t.EB[e] * sy0;
+        }
+        const int64_t gx = R.gx, gy = R.gy;
+        const int64_t zl = gx * lx + gy * ly;
+        int64_t zr = R.z0 + gx * sx0 + gy * sy0;
+        for (int32_t sy = sy0; sy <= t.jhi; sy += 8) {
+            int64_t es0 = er[0], es1 = er[1], es2 = er[2], zs = zr;
+            const int32_t row = (sy - c.y0 + ly) * PITCH + lx;
+            for (int32_t sx = sx0; sx <= t.ihi; sx += 8) {
+                const bool skip = (es0 + emaxo[0] < 0) | (es1 + emaxo[1] < 0) | (es2 + emaxo[2] < 0);
+                if (!skip) {
+                    const bool full = (es0 + emino[0] >= 0) & (es1 + emino[1] >= 0) & (es2 + emino[2] >= 0);
+                    const uint32_t D = depth_q(zs + zl);
+                    bool cov = full;
+                    if (!full) cov = ((es0 + el[0]) | (es1 + el[1]) | (es2 + el[2])) >= 0;
+                    if (cov) atomicMin(&zt[row + (sx - c.x0)], D);
+                }
+                es0 += 8 * t.EA[0]; es1 += 8 * t.EA[1]; es2 += 8 * t.EA[2];
+                zs += 8 * gx;
+            }
+            er[0] += 8 * t.EB[0]; er[1] += 8 * t.EB[1]; er[2] += 8 * t.EB[2];
+            zr += 8 * gy;
+        }
+        }
+    }
+}
+
+template <int TS>
+__device__ void store_tile(const uint32_t* zt, uint32_t* map, const TileCtx& c, int tid) {
+    constexpr int PITCH = TS + 8;
+    const int32_t n = c.n;
     if ((n & 3) == 0) {
         for (int q = tid; q < TS * TS / 4; q += 256) {
-            const int r = q / (TS / 4), c = (q % (TS / 4)) * 4;
-            const int32_t py = y0 + r, px = x0 + c;
+            const int r = q / (TS / 4), cc = (q % (TS / 4)) * 4;
+            const int32_t py = c.y0 + r, px = c.x0 + cc;
             if (py < n && px < n) {
                 uint4 v;
-                v.x = zt[r * PITCH + c]; v.y = zt[r * PITCH + c + 1];
-                v.z = zt[r * PITCH + c + 2]; v.w = zt[r * PITCH + c + 3];
+                v.x = zt[r * PITCH + cc]; v.y = zt[r * PITCH + cc + 1];
+                v.z = zt[r * PITCH + cc + 2]; v.w = zt[r * PITCH + cc + 3];
                 *reinterpret_cast<uint4*>(map + (int64_t)py * n + px) = v;
             }
         }
     } else {
         for (int q = tid; q < TS * TS; q += 256) {
-            const int r = q / TS, c = q % TS;
-            const int32_t py = y0 + r, px = x0 + c;
-            if (py < n && px < n) map[(int64_t)py * n + px] = zt[r * PITCH + c];
+            const int r = q / TS, cc = q % TS;
+            const int32_t py = c.y0 + r, px = c.x0 + cc;
+            if (py < n && px < n) map[(int64_t)py * n + px] = zt[r * PITCH + cc];
         }
     }
+}
+
+// Depth check of the tile's samples against the full LDS tile (waves over modules).
+template <int TS>
+__device__ void samples_full(const uint32_t* zt, const int32_t* mods, int32_t nm, bool mods_in_lds, uint32_t* cc,
+                             const View& V, const BinBuffers& bb, const GenDev& g, const int32_t* bias,
+                             const double* fu_tab, const double* fv_tab, int32_t k, const TileOut& out,
+                             const TileCtx& c, int lane, int wv) {
+    constexpr int PITCH = TS + 8;
+    const int32_t cpm = g.n_cu * g.n_cv;
+    const int32_t knu = k * g.n_cu, knv = k * g.n_cv;
+    const int32_t kk = k * k, words = (kk + 31) / 32;
+    const bool lds_cells = cpm <= kMaxCellCounters;
+    for (int32_t mi = wv; mi < nm; mi += 4) {
+        int32_t m;
+        if (!mods_in_lds) {
+            const int32_t id = bb.bins[c.bs + mi];
+            if (id >= 0) continue;
+            m = -id - 1;
+        } else {
+            m = mods[mi];
+        }
+        const int32_t bm = bias[c.s * g.n_mod + m];
+        if (bm < 0) continue;
+        ModMap mm;
+        if (!module_map<TS>(V, g.mods[m], knu, knv, c, mm)) continue;
+        const int32_t na = mm.qa1 - mm.qa0 + 1, ncand = na * (mm.qb1 - mm.qb0 + 1);
+        if (lds_cells)
+            for (int32_t q = lane; q < cpm; q += 64) cc[q] = 0;
+        __builtin_amdgcn_wave_barrier();
+        for (int32_t t = lane; t < ncand; t += 64) {
+            const int32_t ob = t / na;
+            const int32_t qa = mm.qa0 + (t - ob * na), qb = mm.qb0 + ob;
+            int32_t li, lj;
+            int64_t zs;
+            if (!sample_in_tile<TS>(mm, fu_tab, fv_tab, qa, qb, c, &li, &lj, &zs)) continue;
+            if (zs > (int64_t)zt[lj * PITCH + li] + (int64_t)bm) {
+                const int32_t cu = qa / k, cv = qb / k;
+                const int32_t cell = cv * g.n_cu + cu;
+                if (lds_cells) atomicAdd(&cc[cell], 1u);
+                else atomicAdd(&out.counts[(int64_t)m * cpm + cell], 1u);
+                if (out.bits) {
+                    const int32_t si = (qb - cv * k) * k + (qa - cu * k);
+                    atomicOr(&out.bits[((int64_t)m * cpm + cell) * words + si / 32], 1u << (si % 32));
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (lds_cells)
+            for (int32_t q = lane; q < cpm; q += 64) {
+                const uint32_t v = cc[q];
+                if (v) atomicAdd(&out.counts[(int64_t)m * cpm + q], v);
+            }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Sparse-route sample entry: texel (li, lj) in the tile, shading threshold
+// (shaded iff threshold > nearest depth at the texel), and the sample's
+// identity (tile module slot, qa, qb).
+struct SparseLds {
+    uint16_t* texel;     // lj * TS + li
+    int32_t* thr;        // zs - bias
+    uint32_t* code;      // slot << 24 | qb << 12 | qa
+    uint32_t* dmin;      // nearest depth at the texel centre
+    uint16_t* order;     // entries sorted by texel row
+};
+
+template <int TS, int CAP>
+__global__ __launch_bounds__(256) void k_tile(int64_t s, const View* views, BinBuffers bb, const SunCounters* ctr,
+                                              int32_t n, GenDev g, const int32_t* bias, const double* fu_tab,
+                                              const double* fv_tab, int32_t k, TileOut out, int32_t sparse,
+                                              const uint32_t* tmask) {
+    constexpr int PITCH = TS + 8;
+    constexpr int ZT_BYTES = TS * PITCH * 4;
+    constexpr int SP_BYTES = CAP * (2 + 4 + 4 + 4 + 2);
+    constexpr int POOL = ZT_BYTES > SP_BYTES ? ZT_BYTES : SP_BYTES;
+    __shared__ __attribute__((aligned(16))) unsigned char pool[POOL];
+    __shared__ int32_t mods[kMaxTileMods];
+    __shared__ uint32_t cells[kMaxTileCells > 4 * kMaxCellCounters ? kMaxTileCells : 4 * kMaxCellCounters];
+    __shared__ int32_t rowstart[TS + 1];
+    __shared__ int32_t next, n_mods, mods_overflow, n_ent, ent_overflow, max_thr;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int32_t tile = blockIdx.x;
+    TileCtx c;
+    c.s = s;
+    c.n = n;
+    c.x0 = (tile % bb.ntx) * TS;
+    c.y0 = (tile / bb.ntx) * TS;
+    const View& V = views[s];
+    uint32_t* zt = reinterpret_cast<uint32_t*>(pool);
+    if (V.valid && !out.map && !mask_has(tmask, tile)) return;   // no sample can fall in this tile
+    if (!V.valid) {
+        if (out.map) {                            // nothing drawn: the exported picture stays at the far depth
+            for (int q = tid; q < TS * TS; q += 256) {
+                const int32_t py = c.y0 + q / TS, px = c.x0 + q % TS;
+                if (py < n && px < n) out.map[(int64_t)py * n + px] = kDepthMax;
+            }
+        }
+        return;
+    }
+    c.bs = min(bb.tile_start[tile], bb.bin_cap);
+    c.be = min(bb.tile_start[tile + 1], bb.bin_cap);
+    c.n_large = ctr[s].n_large;
+    if (tid == 0) { next = 0; n_mods = 0; mods_overflow = 0; n_ent = 0; ent_overflow = 0; max_thr = INT32_MIN; }
+    __syncthreads();
+    for (int32_t q = c.bs + tid; q < c.be; q += 256) {   // module entries of this tile
+        const int32_t id = bb.bins[q];
+        if (id < 0) {
+            const int32_t slot = atomicAdd(&n_mods, 1);
+            if (slot < kMaxTileMods) mods[slot] = -id - 1;
+            else mods_overflow = 1;
+        }
+    }
+    __syncthreads();
+    const bool test = out.test && n_mods > 0;
+    if (!test && !out.map) return;                        // no sample falls here and nothing to export
+    const int32_t cpm = g.n_cu * g.n_cv;
+    const int32_t knu = k * g.n_cu, knv = k * g.n_cv;
+    bool go_sparse = sparse && !out.map && test && !mods_overflow;
+
+    if (go_sparse) {
+        SparseLds sp;
+        sp.texel = reinterpret_cast<uint16_t*>(pool);
+        sp.thr = reinterpret_cast<int32_t*>(pool + 2 * CAP);
+        sp.code = reinterpret_cast<uint32_t*>(pool + 6 * CAP);
+        sp.dmin = reinterpret_cast<uint32_t*>(pool + 10 * CAP);
+        sp.order = reinterpret_cast<uint16_t*>(pool + 14 * CAP);
+        // 1. list the samples whose texel lies in this tile
+        for (int32_t mi = wv; mi < n_mods; mi += 4) {
+            const int32_t m = mods[mi];
+            const int32_t bm = bias[s * g.n_mod + m];
+            if (bm < 0) continue;
+            ModMap mm;
+            if (!module_map<TS>(V, g.mods[m], knu, knv, c, mm)) continue;
+            const int32_t na = mm.qa1 - mm.qa0 + 1, ncand = na * (mm.qb1 - mm.qb0 + 1);
+            for (int32_t t = lane; t < ncand; t += 64) {
+                const int32_t ob = t / na;
+                const int32_t qa = mm.qa0 + (t - ob * na), qb = mm.qb0 + ob;
+                int32_t li, lj;
+                int64_t zs;
+                if (!sample_in_tile<TS>(mm, fu_tab, fv_tab, qa, qb, c, &li, &lj, &zs)) continue;
+                const int32_t e = atomicAdd(&n_ent, 1);
+                if (e >= CAP) { ent_overflow = 1; continue; }
+                const int32_t th = (int32_t)(zs - (int64_t)bm);
+                sp.texel[e] = (uint16_t)(lj * TS + li);
+                sp.thr[e] = th;
+                sp.code[e] = ((uint32_t)mi << 24) | ((uint32_t)qb << 12) | (uint32_t)qa;
+                sp.dmin[e] = kDepthMax;
+                atomicMax(&max_thr, th);
+            }
+        }
+        for (int q = tid; q <= TS; q += 256) rowstart[q] = 0;
+        __syncthreads();
+        if (!ent_overflow) {
+            const int32_t ne = n_ent;
+            // 2. counting sort of the entries by texel row
+            for (int32_t e = tid; e < ne; e += 256) atomicAdd(&rowstart[sp.texel[e] / TS + 1], 1);
+            __syncthreads();
+            if (tid == 0)
+                for (int r = 1; r <= TS; r++) rowstart[r] += rowstart[r - 1];
+            __syncthreads();
+            uint32_t* cur = cells;                    // row cursors (the counters are not in use yet)
+            for (int r = tid; r < TS; r += 256) cur[r] = (uint32_t)rowstart[r];
+            __syncthreads();
+            for (int32_t e = tid; e < ne; e += 256) sp.order[atomicAdd(&cur[sp.texel[e] / TS], 1u)] = (uint16_t)e;
+            __syncthreads();
+            // 3. every triangle against the sample texels of the rows it spans
+            const int32_t mthr = max_thr;
+            const int32_t total = c.n_large + (c.be - c.bs);
+            for (;;) {
+                const int32_t base = next_chunk(&next, lane);
+                if (base >= total) break;
+                const int32_t cnt = min(kChunk, total - base);
+                RecLane L;
+                const int32_t rid = load_chunk(bb, base, cnt, c.n_large, c.bs, lane, L);
+                for (int ci = 0; ci < cnt; ci++) {
+                if (__builtin_amdgcn_readlane(rid, ci) < 0) continue;
+                const TriRec R = rec_of_lane(L, ci);
+                TriClip t;
+                if (!clip_to_tile(R, c.x0, c.y0, TS, t)) continue;
+                // nearest depth of the plane over the clipped box: when it is not in front of any
+                // sample's threshold the triangle cannot shade a sample of this tile
+                const int64_t zmin = R.z0 + R.gx * (R.gx > 0 ? t.ilo : t.ihi) + R.gy * (R.gy > 0 ? t.jlo : t.jhi);
+                if ((int64_t)depth_q(zmin) >= (int64_t)mthr) continue;
+                const int32_t p0 = rowstart[t.jlo - c.y0], p1 = rowstart[t.jhi - c.y0 + 1];
+                for (int32_t p = p0 + lane; p < p1; p += 64) {
+                    const int32_t e = sp.order[p];
+                    const int32_t tx = sp.texel[e];
+                    const int32_t i = c.x0 + tx % TS, j = c.y0 + tx / TS;
+                    if (i < t.ilo || i > t.ihi) continue;
+                    const int64_t E0 = R.e0[0] + t.EA[0] * i + t.EB[0] * j;
+                    const int64_t E1 = R.e0[1] + t.EA[1] * i + t.EB[1] * j;
+                    const int64_t E2 = R.e0[2] + t.EA[2] * i + t.EB[2] * j;
+                    if ((E0 | E1 | E2) >= 0) atomicMin(&sp.dmin[e], depth_q(R.z0 + R.gx * i + R.gy * j));
+                }
+                }
+            }
+            __syncthreads();
+            // 4. shaded flags, per-cell counts
+            const int32_t mods_n = n_mods;
+            const bool lds_cells = mods_n * cpm <= kMaxTileCells;
+            if (lds_cells)
+                for (int32_t q = tid; q < mods_n * cpm; q += 256) cells[q] = 0;
+            __syncthreads();
+            const int32_t words = (k * k + 31) / 32;
+            for (int32_t e = tid; e < ne; e += 256) {
+                if (!(sp.thr[e] > (int32_t)sp.dmin[e])) continue;
+                const uint32_t code = sp.code[e];
+                const int32_t slot = (int32_t)(code >> 24), qb = (int32_t)((code >> 12) & 0xFFF), qa = (int32_t)(code & 0xFFF);
+                const int32_t cu = qa / k, cv = qb / k, cell = cv * g.n_cu + cu;
+                const int32_t m = mods[slot];
+                if (lds_cells) atomicAdd(&cells[slot * cpm + cell], 1u);
+                else atomicAdd(&out.counts[(int64_t)m * cpm + cell], 1u);
+                if (out.bits) {
+                    const int32_t si = (qb - cv * k) * k + (qa - cu * k);
+                    atomicOr(&out.bits[((int64_t)m * cpm + cell) * words + si / 32], 1u << (si % 32));
+                }
+            }
+            __syncthreads();
+            if (lds_cells)
+                for (int32_t q = tid; q < mods_n * cpm; q += 256) {
+                    const uint32_t v = cells[q];
+                    if (v) atomicAdd(&out.counts[(int64_t)mods[q / cpm] * cpm + q % cpm], v);
+                }
+            return;
+        }
+        // too many samples for the LDS list: fall through to the full route
+        if (tid == 0) next = 0;
+        __syncthreads();
+    }
+
+    // full route
+    for (int q = tid; q < TS * PITCH; q += 256) zt[q] = kDepthMax;
+    __syncthreads();
+    raster_full<TS>(zt, &next, bb, c, lane);
+    __syncthreads();
+    if (out.map) store_tile<TS>(zt, out.map, c, tid);
+    if (!test) return;
+    const int32_t nm = mods_overflow ? (c.be - c.bs) : n_mods;
+    samples_full<TS>(zt, mods, nm, !mods_overflow, cells + wv * kMaxCellCounters, V, bb, g, bias, fu_tab, fv_tab, k,
+                     out, c, lane, wv);
 }
 
 // ---------------------------------------------------------------------------
@@ -643,19 +1256,28 @@ hipError_t launch_sample_tables(double* fu, double* fv, int32_t k, int32_t n_cu,
 
 hipError_t launch_setup(const double* sun, int64_t n_sun, const double* dni, const GenDev& g,
                         const double* sphere, int32_t n, View* views, double* beam, int32_t* bias,
-                        hipStream_t st) {
+                        const TileGrid& tg, uint32_t* tmask, hipStream_t st) {
     if (n_sun <= 0) return hipSuccess;
+    if (tmask && tg.words > kMaxMaskWords) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_setup, dim3((unsigned)n_sun), dim3(256), 0, st, sun, dni, g, sphere, n, views,
-                       beam, bias);
+                       beam, bias, tg, tmask);
     return hipGetLastError();
 }
 
-hipError_t launch_tri_setup(int64_t s, const View* views, const SceneDev& sc, const GenDev& g, int32_t n,
-                            const BinBuffers& bb, SunCounters* ctr, hipStream_t st) {
-    int64_t total = sc.n_tri + (g.occluders ? 2 * (int64_t)g.n_mod : 0);
+size_t bin_lds_bytes(int32_t n_tiles) { return 8 * (size_t)n_tiles; }
+
+hipError_t configure_kernels(size_t max_lds) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_tri_setup, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_bin_scatter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
+}
+
+hipError_t launch_tri_setup(int64_t s, const View* views, const SceneDev& sc, const GenDev& g, const int32_t* bias,
+                            int32_t n, const BinBuffers& bb, SunCounters* ctr, const uint32_t* tmask, hipStream_t st) {
+    int64_t total = sc.n_tri + (g.occluders ? 2 * (int64_t)g.n_mod : 0) + g.n_mod;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tri_setup, dim3(grid_for(total, 256)), dim3(256), 0, st, s, views, sc, g, n, bb,
-                       ctr + s);
+    hipLaunchKernelGGL(k_tri_setup, dim3(grid_for(total, 256)), dim3(256), 4 * (size_t)bb.n_tiles, st, s, views, sc,
+                       g, bias, n, bb, ctr + s, tmask);
     return hipGetLastError();
 }
 
@@ -664,21 +1286,22 @@ hipError_t launch_bin_scan(int32_t n_tiles, const BinBuffers& bb, hipStream_t st
     return hipGetLastError();
 }
 
-hipError_t launch_bin_scatter(int64_t s, const BinBuffers& bb, int32_t n_tiles, SunCounters* ctr,
-                              hipStream_t st) {
-    (void)n_tiles;
-    hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(bb.rec_cap, 256)), dim3(256), 0, st, s, bb, ctr);
+hipError_t launch_bin_scatter(int64_t s, const BinBuffers& bb, int32_t n_mod, SunCounters* ctr, int32_t grid,
+                              const uint32_t* tmask, hipStream_t st) {
+    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)grid), dim3(256), bin_lds_bytes(bb.n_tiles), st, s, bb, n_mod,
+                       ctr, tmask);
     return hipGetLastError();
 }
 
-hipError_t launch_raster(int64_t s, const View* views, const BinBuffers& bb, const SunCounters* ctr,
-                         int32_t n, uint32_t* map, hipStream_t st) {
-    int32_t nt = (n + bb.tile - 1) / bb.tile;
-    dim3 grid((unsigned)(nt * nt));
+hipError_t launch_raster(int64_t s, const View* views, const BinBuffers& bb, const SunCounters* ctr, int32_t n,
+                         const GenDev& g, const int32_t* bias, const double* fu, const double* fv, int32_t k,
+                         const TileOut& out, const uint32_t* tmask, hipStream_t st) {
+    dim3 grid((unsigned)bb.n_tiles);
+    const int32_t sparse = out.sparse;
     switch (bb.tile) {
-        case 32: hipLaunchKernelGGL(k_raster<32>, grid, dim3(256), 0, st, s, views, bb, ctr, n, map); break;
-        case 64: hipLaunchKernelGGL(k_raster<64>, grid, dim3(256), 0, st, s, views, bb, ctr, n, map); break;
-        case 128: hipLaunchKernelGGL(k_raster<128>, grid, dim3(256), 0, st, s, views, bb, ctr, n, map); break;
+        case 32: hipLaunchKernelGGL((k_tile<32, 1024>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out, sparse, tmask); break;
+        case 64: hipLaunchKernelGGL((k_tile<64, 2048>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out, sparse, tmask); break;
+        case 128: hipLaunchKernelGGL((k_tile<128, 4096>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out, sparse, tmask); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

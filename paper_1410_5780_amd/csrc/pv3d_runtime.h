@@ -48,17 +48,17 @@ struct Gen {
 };
 
 struct PathSizes {
-    int32_t tile, ntx, n_tiles, large_tiles, words;
+    int32_t tile, ntx, n_tiles, large_tiles, words, mask_words;
     int64_t tri_total, rec_cap, bin_cap, cells, n_sun;
 };
 
 struct Work {
     Buf rec, large, bins, tile_count, tile_start, tile_cursor, map;
-    Buf views, ctr, beam, bias, sweep, sphere, partial, fu, fv;
+    Buf views, ctr, beam, bias, sweep, sphere, partial, fu, fv, modbox, tmask;
     Buf counts, outd, maps, bits;
     void release_all(Ctx* c) {
         Buf* all[] = {&rec, &large, &bins, &tile_count, &tile_start, &tile_cursor, &map, &views, &ctr, &beam,
-                      &bias, &sweep, &sphere, &partial, &fu, &fv, &counts, &outd, &maps, &bits};
+                      &bias, &sweep, &sphere, &partial, &fu, &fv, &modbox, &tmask, &counts, &outd, &maps, &bits};
         for (Buf* b : all) b->release(c);
     }
 };
@@ -66,7 +66,23 @@ struct Work {
 struct BatchState;
 struct Server;
 
+// Event pairs around launches of selected stages (profiling aid).
+struct Profiler {
+    uint32_t mask = 0;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, size_t>> pending;   // (stage, index of the start event in pool)
+    size_t used = 0;
+    double total_ms[PV3D_N_STAGES] = {};
+    int64_t launches[PV3D_N_STAGES] = {};
+    bool on(int stage) const { return (mask >> stage) & 1u; }
+    hipError_t begin(int stage, hipStream_t st, size_t* slot);
+    hipError_t end(size_t slot, hipStream_t st);
+    hipError_t collect();
+    void reset();
+};
+
 PathSizes path_sizes(const Scene& sc, const Gen& g, const pv3d_params& p, int64_t n_sun);
+int32_t choose_tile(const pv3d_params& p);
 SceneDev scene_dev(const Scene& sc);
 GenDev gen_dev(const Gen& g);
 
@@ -76,6 +92,7 @@ struct Ctx {
     hipStream_t stream_in_use = nullptr;
     uint64_t budget = 0;
     uint64_t used = 0;
+    size_t max_lds = 65536;
     std::map<void*, size_t> sizes;
     std::map<uint64_t, Scene> scenes;
     std::map<uint64_t, Gen> gens;
@@ -89,6 +106,7 @@ struct Ctx {
     hipEvent_t staging_done = nullptr;
     BatchState* batch = nullptr;
     Server* server = nullptr;
+    Profiler prof;
 
     pv3d_status dalloc(void** p, size_t bytes, const char* what);
     void dfree(void* p);
@@ -96,6 +114,9 @@ struct Ctx {
     pv3d_status stage_reserve(size_t bytes);
     pv3d_status stage_done(hipStream_t st);
     pv3d_status ensure_path(const PathSizes& z, const Gen& g, int32_t map_n, bool own_map);
+    pv3d_status run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, const GenDev& gd, const pv3d_params& p,
+                        const View* views, SunCounters* ctr, const int32_t* bias, const double* beam, uint32_t* map,
+                        uint32_t* counts_s, uint32_t* bits_s, const uint32_t* tmask_s, hipStream_t st);
     pv3d_status ensure_tables(const Gen& g, int32_t k);
     BinBuffers bin_buffers(const PathSizes& z);
     pv3d_status run_path(const Scene& sc, const Gen& g, const pv3d_params& p, const double* sun_host, int64_t n_sun,

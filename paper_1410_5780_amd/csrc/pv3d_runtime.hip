@@ -150,6 +150,68 @@ pv3d_status Ctx::stage_done(hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// stage timing
+// ---------------------------------------------------------------------------
+hipError_t Profiler::begin(int stage, hipStream_t st, size_t* slot) {
+    if (used + 2 > pool.size()) {
+        size_t grow = std::max<size_t>(1024, pool.size());
+        for (size_t i = 0; i < grow; i++) {
+            hipEvent_t ev;
+            hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) return e;
+            pool.push_back(ev);
+        }
+    }
+    *slot = used;
+    used += 2;
+    pending.emplace_back(stage, *slot);
+    return hipEventRecord(pool[*slot], st);
+}
+
+hipError_t Profiler::end(size_t slot, hipStream_t st) { return hipEventRecord(pool[slot + 1], st); }
+
+hipError_t Profiler::collect() {
+    for (auto& pr : pending) {
+        hipError_t e = hipEventSynchronize(pool[pr.second + 1]);
+        if (e != hipSuccess) return e;
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, pool[pr.second], pool[pr.second + 1]);
+        if (e != hipSuccess) return e;
+        total_ms[pr.first] += (double)ms;
+        launches[pr.first] += 1;
+    }
+    pending.clear();
+    used = 0;
+    return hipSuccess;
+}
+
+void Profiler::reset() {
+    pending.clear();
+    used = 0;
+    for (int i = 0; i < PV3D_N_STAGES; i++) {
+        total_ms[i] = 0.0;
+        launches[i] = 0;
+    }
+}
+
+// Launch `call` for `stage`, bracketed by timing events when that stage is profiled.
+template <typename F>
+static hipError_t timed(Profiler& pf, int stage, hipStream_t st, F&& call) {
+    if (!pf.on(stage)) return call();
+    size_t slot = 0;
+    hipError_t e = pf.begin(stage, st, &slot);
+    if (e != hipSuccess) return e;
+    e = call();
+    if (e != hipSuccess) return e;
+    if (pf.used >= 1u << 16) {                     // bound the event pool: fold what is done
+        e = pf.end(slot, st);
+        if (e != hipSuccess) return e;
+        return pf.collect();
+    }
+    return pf.end(slot, st);
+}
+
+// ---------------------------------------------------------------------------
 // validation helpers
 // ---------------------------------------------------------------------------
 static bool finite3(const double* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
@@ -174,7 +236,8 @@ pv3d_status check_params(const pv3d_params* p) {
     if (!p) return fail(PV3D_EINVAL, "params is NULL");
     if (p->map_n < 16 || p->map_n > 16384) return fail(PV3D_EINVAL, "map_n %d outside [16, 16384]", p->map_n);
     if (p->k < 1 || p->k > 255) return fail(PV3D_EINVAL, "k %d outside [1, 255]", p->k);
-    if (p->flags & ~(PV3D_EXPORT_DEPTH | PV3D_EXPORT_BITS)) return fail(PV3D_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->flags & ~(PV3D_EXPORT_DEPTH | PV3D_EXPORT_BITS | PV3D_SEPARATE_TEST | PV3D_FULL_RASTER))
+        return fail(PV3D_EINVAL, "unknown flags 0x%x", p->flags);
     if (p->tile != 0 && p->tile != 32 && p->tile != 64 && p->tile != 128)
         return fail(PV3D_EINVAL, "tile %d not in {0, 32, 64, 128}", p->tile);
     return PV3D_OK;
@@ -183,20 +246,22 @@ pv3d_status check_params(const pv3d_params* p) {
 // ---------------------------------------------------------------------------
 // per-sun path
 // ---------------------------------------------------------------------------
-int32_t choose_tile(const pv3d_params& p) { return p.tile ? p.tile : 64; }
+int32_t choose_tile(const pv3d_params& p) { return p.tile ? p.tile : (p.map_n <= 4096 ? 64 : 128); }
 
 PathSizes path_sizes(const Scene& sc, const Gen& g, const pv3d_params& p, int64_t n_sun) {
     PathSizes z;
     z.tile = choose_tile(p);
     z.ntx = (p.map_n + z.tile - 1) / z.tile;
     z.n_tiles = z.ntx * z.ntx;
-    z.large_tiles = 16;
+    z.large_tiles = 256;
     z.tri_total = sc.n_tri + (g.occluders ? 2 * g.n_mod : 0);
     // a clipped triangle becomes at most 5 (a triangle cut by four half-planes
-    // is a polygon of at most 7 corners); a binned one touches <= large_tiles tiles
+    // is a polygon of at most 7 corners); a binned one touches <= large_tiles
+    // tiles, a module's samples at most every tile
     z.rec_cap = 5 * z.tri_total + 64;
-    z.bin_cap = (int64_t)z.large_tiles * z.rec_cap;
+    z.bin_cap = (int64_t)z.large_tiles * z.rec_cap + (int64_t)g.n_mod * z.n_tiles;
     z.cells = (int64_t)g.n_mod * g.n_cu * g.n_cv;
+    z.mask_words = (z.n_tiles + 31) / 32;
     z.words = (p.k * p.k + 31) / 32;
     z.n_sun = n_sun;
     return z;
@@ -206,6 +271,8 @@ pv3d_status Ctx::ensure_path(const PathSizes& z, const Gen& g, int32_t map_n, bo
     pv3d_status st;
     if (z.rec_cap > INT32_MAX || z.bin_cap > INT32_MAX)
         return fail(PV3D_ERANGE, "scene too large for 32-bit bin indices");
+    if (bin_lds_bytes(z.n_tiles) > max_lds)
+        return fail(PV3D_ERANGE, "%d tiles need more LDS than a workgroup has; use a larger tile", z.n_tiles);
     if ((st = w.rec.ensure(this, sizeof(TriRec) * (size_t)z.rec_cap, "triangle records"))) return st;
     if ((st = w.large.ensure(this, 4 * (size_t)z.rec_cap, "large-triangle list"))) return st;
     if ((st = w.bins.ensure(this, 4 * (size_t)z.bin_cap, "tile bins"))) return st;
@@ -219,6 +286,9 @@ pv3d_status Ctx::ensure_path(const PathSizes& z, const Gen& g, int32_t map_n, bo
     if ((st = w.bias.ensure(this, 4 * (size_t)std::max<int64_t>(z.n_sun * g.n_mod, 1), "module bias"))) return st;
     if ((st = w.sweep.ensure(this, 8 * 6 * (size_t)std::max<int64_t>(z.n_sun, 1), "sweep"))) return st;
     if ((st = w.sphere.ensure(this, 64, "bounding sphere"))) return st;
+    if ((st = w.modbox.ensure(this, 16 * (size_t)g.n_mod, "module tile boxes"))) return st;
+    if ((st = w.tmask.ensure(this, 4 * (size_t)z.mask_words * (size_t)std::max<int64_t>(z.n_sun, 1), "tile masks")))
+        return st;
     if ((st = w.partial.ensure(this, 8 * 6 * 1024, "bounds partials"))) return st;
     return PV3D_OK;
 }
@@ -232,9 +302,11 @@ BinBuffers Ctx::bin_buffers(const PathSizes& z) {
     bb.tile_start = static_cast<int32_t*>(w.tile_start.ptr);
     bb.tile_cursor = static_cast<int32_t*>(w.tile_cursor.ptr);
     bb.bins = static_cast<int32_t*>(w.bins.ptr);
+    bb.modbox = static_cast<int4*>(w.modbox.ptr);
     bb.bin_cap = (int32_t)z.bin_cap;
     bb.tile = z.tile;
     bb.ntx = z.ntx;
+    bb.n_tiles = z.n_tiles;
     bb.large_tiles = z.large_tiles;
     return bb;
 }
@@ -269,7 +341,7 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
                           const double* d_dt, uint32_t* counts, double* power, double* power_ref,
                           double* energy, uint32_t* maps, uint32_t* bits, hipStream_t st) {
     PathSizes z = path_sizes(sc, g, p, n_sun);
-    pv3d_status rs = ensure_path(z, g, p.map_n, maps == nullptr);
+    pv3d_status rs = ensure_path(z, g, p.map_n, maps == nullptr && (p.flags & PV3D_SEPARATE_TEST));
     if (rs) return rs;
     hipError_t e;
     if ((rs = ensure_tables(g, p.k))) return rs;
@@ -293,25 +365,58 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
     int32_t n_part = bounds_partials(sc.n_vert + 4 * g.n_mod);
     if ((e = launch_bounds(sd, gd, static_cast<double*>(w.partial.ptr), n_part, sphere, st)))
         return hip_fail(e, "bounds");
-    if ((e = launch_setup(d_sun, n_sun, d_dni, gd, sphere, p.map_n, views, beam, bias, st)))
+    // the sparse route bins triangles only into tiles that hold samples
+    const bool sparse = maps == nullptr && !(p.flags & (PV3D_SEPARATE_TEST | PV3D_FULL_RASTER));
+    uint32_t* tmask = sparse ? static_cast<uint32_t*>(w.tmask.ptr) : nullptr;
+    TileGrid tg{z.tile, z.ntx, z.n_tiles, z.mask_words};
+    if (z.mask_words > 512) tmask = nullptr;
+    if ((e = timed(prof, PV3D_STAGE_SETUP, st, [&] { return launch_setup(d_sun, n_sun, d_dni, gd, sphere, p.map_n, views, beam, bias, tg, tmask, st); })))
         return hip_fail(e, "setup");
-    BinBuffers bb = bin_buffers(z);
-    uint32_t* scratch_counts = counts;
     for (int64_t s = 0; s < n_sun; s++) {
         if (!(sun_host[3 * s + 2] > 0.0)) continue;        // below the horizon: outputs stay zero
-        uint32_t* map = maps ? maps + s * N2 : static_cast<uint32_t*>(w.map.ptr);
-        if ((e = launch_tri_setup(s, views, sd, gd, p.map_n, bb, ctr, st))) return hip_fail(e, "tri_setup");
-        if ((e = launch_bin_scan(z.n_tiles, bb, st))) return hip_fail(e, "bin_scan");
-        if ((e = launch_bin_scatter(s, bb, z.n_tiles, ctr, st))) return hip_fail(e, "bin_scatter");
-        if ((e = launch_raster(s, views, bb, ctr, p.map_n, map, st))) return hip_fail(e, "raster");
-        if ((e = launch_sample_test(s, views, gd, beam, bias, static_cast<double*>(w.fu.ptr),
-                                    static_cast<double*>(w.fv.ptr), p.k, map, p.map_n,
-                                    scratch_counts + s * z.cells, bits ? bits + s * z.cells * z.words : nullptr, st)))
-            return hip_fail(e, "sample_test");
+        uint32_t* map = maps ? maps + s * N2 : nullptr;
+        if ((rs = run_sun(s, z, sd, gd, p, views, ctr, bias, beam, map, counts + s * z.cells,
+                          bits ? bits + s * z.cells * z.words : nullptr, tmask ? tmask + s * z.mask_words : nullptr, st)))
+            return rs;
     }
-    if ((e = launch_loss(n_sun, d_sun, beam, counts, d_dpoa, gd, p.k, power, power_ref, st)))
+    if ((e = timed(prof, PV3D_STAGE_LOSS, st, [&] { return launch_loss(n_sun, d_sun, beam, counts, d_dpoa, gd, p.k, power, power_ref, st); })))
         return hip_fail(e, "loss");
     if ((e = launch_energy(n_sun, power, power_ref, d_dt, energy, st))) return hip_fail(e, "energy");
+    return PV3D_OK;
+}
+
+// The launch sequence of one sun.
+pv3d_status Ctx::run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, const GenDev& gd, const pv3d_params& p,
+                         const View* views, SunCounters* ctr, const int32_t* bias, const double* beam, uint32_t* map,
+                         uint32_t* counts_s, uint32_t* bits_s, const uint32_t* tmask_s, hipStream_t st) {
+    hipError_t e;
+    BinBuffers bb = bin_buffers(z);
+    const bool separate = (p.flags & PV3D_SEPARATE_TEST) != 0;
+    if (separate && !map) map = static_cast<uint32_t*>(w.map.ptr);
+    const int32_t scatter_grid = 1024;
+    if ((e = timed(prof, PV3D_STAGE_TRI_SETUP, st, [&] { return launch_tri_setup(s, views, sd, gd, bias, p.map_n, bb, ctr, tmask_s, st); })))
+        return hip_fail(e, "tri_setup");
+    if ((e = timed(prof, PV3D_STAGE_BIN_SCAN, st, [&] { return launch_bin_scan(z.n_tiles, bb, st); })))
+        return hip_fail(e, "bin_scan");
+    if ((e = timed(prof, PV3D_STAGE_BIN_SCATTER, st, [&] { return launch_bin_scatter(s, bb, gd.n_mod, ctr, scatter_grid, tmask_s, st); })))
+        return hip_fail(e, "bin_scatter");
+    TileOut to;
+    to.map = map;
+    to.counts = counts_s;
+    to.bits = bits_s;
+    to.test = separate ? 0 : 1;
+    to.sparse = (map == nullptr && !separate && !(p.flags & PV3D_FULL_RASTER)) ? 1 : 0;
+    if ((e = timed(prof, PV3D_STAGE_RASTER, st, [&] {
+             return launch_raster(s, views, bb, ctr, p.map_n, gd, bias, static_cast<double*>(w.fu.ptr),
+                                  static_cast<double*>(w.fv.ptr), p.k, to, tmask_s, st);
+         })))
+        return hip_fail(e, "raster");
+    if (separate &&
+        (e = timed(prof, PV3D_STAGE_SAMPLE_TEST, st, [&] {
+             return launch_sample_test(s, views, gd, beam, bias, static_cast<double*>(w.fu.ptr),
+                                       static_cast<double*>(w.fv.ptr), p.k, map, p.map_n, counts_s, bits_s, st);
+         })))
+        return hip_fail(e, "sample_test");
     return PV3D_OK;
 }
 
@@ -363,6 +468,12 @@ pv3d_status pv3d_create(int32_t device, uint64_t hbm_budget_bytes, pv3d_ctx** ou
     if ((e = hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming)) != hipSuccess)
         return hip_fail(e, "hipEventCreate");
     c->stream_in_use = c->stream;
+    {
+        hipDeviceProp_t prop;
+        if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        c->max_lds = prop.sharedMemPerBlock;
+        if ((e = configure_kernels(c->max_lds)) != hipSuccess) return hip_fail(e, "configure kernels");
+    }
     *out = c.release();
     return PV3D_OK;
 }
@@ -385,6 +496,7 @@ void pv3d_destroy(pv3d_ctx* ctx) {
     ctx->w.release_all(ctx);
     ctx->release_batched();
     if (ctx->staging) (void)hipHostFree(ctx->staging);
+    for (hipEvent_t ev : ctx->prof.pool) (void)hipEventDestroy(ev);
     (void)hipEventDestroy(ctx->staging_done);
     (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -574,6 +686,8 @@ pv3d_status pv3d_evaluate(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const dou
     const Scene& sc = si->second;
     const Gen& g = gi->second;
     const pv3d_params& p = *params;
+    if ((int64_t)p.k * g.n_cu > 4095 || (int64_t)p.k * g.n_cv > 4095)
+        return fail(PV3D_ERANGE, "k * cells per module side exceeds 4095 samples");
     const int64_t cells = g.n_mod * g.n_cu * g.n_cv;
     const int64_t words = (p.k * p.k + 31) / 32;
     const bool want_maps = (p.flags & PV3D_EXPORT_DEPTH) != 0, want_bits = (p.flags & PV3D_EXPORT_BITS) != 0;
@@ -608,7 +722,7 @@ pv3d_status pv3d_evaluate(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const dou
         }
     }
     PathSizes z = path_sizes(sc, g, p, n_sun);
-    if ((st = ctx->ensure_path(z, g, p.map_n, !want_maps))) return st;
+    if ((st = ctx->ensure_path(z, g, p.map_n, !want_maps && (p.flags & PV3D_SEPARATE_TEST)))) return st;
     double* d_sweep = static_cast<double*>(ctx->w.sweep.ptr);
     double *d_sun = d_sweep, *d_dni = d_sweep + 3 * n_sun, *d_dpoa = d_dni + n_sun, *d_dt = d_dpoa + n_sun;
     if (n_sun > 0) {
@@ -643,6 +757,30 @@ pv3d_status pv3d_evaluate(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const dou
     } else {
         if ((e = hipGetLastError())) return hip_fail(e, "launch");
     }
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_profile_enable(pv3d_ctx* ctx, uint32_t stage_mask) {
+    if (!ctx) return fail(PV3D_EINVAL, "null context");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (stage_mask >> PV3D_N_STAGES) return fail(PV3D_EINVAL, "unknown stage bits 0x%x", stage_mask);
+    (void)hipSetDevice(ctx->device);
+    hipError_t e = ctx->prof.collect();
+    if (e != hipSuccess) return hip_fail(e, "collect timings");
+    if (stage_mask == 0) ctx->prof.reset();
+    ctx->prof.mask = stage_mask;
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_profile_read(pv3d_ctx* ctx, int32_t stage, double* total_ms, int64_t* launches) {
+    if (!ctx || !total_ms || !launches) return fail(PV3D_EINVAL, "null argument");
+    if (stage < 0 || stage >= PV3D_N_STAGES) return fail(PV3D_EINVAL, "stage %d", stage);
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    hipError_t e = ctx->prof.collect();
+    if (e != hipSuccess) return hip_fail(e, "collect timings");
+    *total_ms = ctx->prof.total_ms[stage];
+    *launches = ctx->prof.launches[stage];
     return PV3D_OK;
 }
 

@@ -17,7 +17,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpv3d.so")
 
 OK, EINVAL, ENOMEM, ENOENT, EDEVICE, ERANGE, EBUSY, ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7
-EXPORT_DEPTH, EXPORT_BITS = 1, 2
+EXPORT_DEPTH, EXPORT_BITS, SEPARATE_TEST, FULL_RASTER = 1, 2, 4, 8
+STAGES = ("tri_setup", "bin_scan", "bin_scatter", "raster", "sample_test", "setup", "loss")
+STAGE = {n: i for i, n in enumerate(STAGES)}
+N_STAGES = len(STAGES)
 DEPTH_MAX = (1 << 24) - 1
 
 _P = ctypes.c_void_p
@@ -76,7 +79,9 @@ def lib():
         L.pv3d_poll.argtypes = [_P, _u64, ctypes.POINTER(_i32)]
         L.pv3d_wait.argtypes = [_P, _u64]
         L.pv3d_cancel.argtypes = [_P, _u64]
-        for f in ("pv3d_create", "pv3d_scene_load", "pv3d_scene_release", "pv3d_generator_define",
+        L.pv3d_profile_enable.argtypes = [_P, _u32]
+        L.pv3d_profile_read.argtypes = [_P, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
+        for f in ("pv3d_profile_enable", "pv3d_profile_read", "pv3d_create", "pv3d_scene_load", "pv3d_scene_release", "pv3d_generator_define",
                   "pv3d_generator_release", "pv3d_sun_cooper", "pv3d_evaluate", "pv3d_evaluate_batched",
                   "pv3d_submit", "pv3d_poll", "pv3d_wait", "pv3d_cancel"):
             getattr(L, f).restype = _i32
@@ -156,6 +161,15 @@ class Context:
         except Exception:
             pass
 
+    def profile_enable(self, stage_mask: int):
+        _check(lib().pv3d_profile_enable(self.h, stage_mask), self.h)
+
+    def profile_read(self, stage: int):
+        """(summed milliseconds, launches) of one stage since profiling was enabled."""
+        ms, n = _f64(), _i64()
+        _check(lib().pv3d_profile_read(self.h, stage, ctypes.byref(ms), ctypes.byref(n)), self.h)
+        return ms.value, n.value
+
     def load_scene(self, scene) -> int:
         xyz = _c(scene.xyz, np.float64).reshape(-1, 3)
         tri = _c(scene.tri, np.int32).reshape(-1, 3)
@@ -179,11 +193,13 @@ class Context:
         _check(lib().pv3d_generator_release(self.h, h), self.h)
 
     @staticmethod
-    def params(map_n: int, k: int, export_depth=False, export_bits=False, tile: int = 0) -> Params:
-        return Params(map_n, k, (EXPORT_DEPTH if export_depth else 0) | (EXPORT_BITS if export_bits else 0), tile)
+    def params(map_n: int, k: int, export_depth=False, export_bits=False, tile: int = 0,
+               separate_test=False, full_raster=False) -> Params:
+        return Params(map_n, k, (EXPORT_DEPTH if export_depth else 0) | (EXPORT_BITS if export_bits else 0)
+                      | (SEPARATE_TEST if separate_test else 0) | (FULL_RASTER if full_raster else 0), tile)
 
     def evaluate(self, scene_h: int, gen_h: int, gen, sweep, map_n: int, k: int, export_depth=False,
-                 export_bits=False, tile: int = 0) -> Result:
+                 export_bits=False, tile: int = 0, separate_test=False, full_raster=False) -> Result:
         """Host outputs (synchronous)."""
         s = _c(sweep.sun_xyz, np.float64)
         dni, dp, dt = (_c(a, np.float64) for a in (sweep.dni, sweep.d_poa, sweep.dt_h))
@@ -195,13 +211,13 @@ class Context:
         maps = np.zeros((n, map_n, map_n), np.uint32) if export_depth else None
         bits = np.zeros((n, cells, words), np.uint32) if export_bits else None
         out = Outputs(_ptr(counts), _ptr(pw), _ptr(pr), _ptr(en), _ptr(maps), _ptr(bits), 0)
-        p = self.params(map_n, k, export_depth, export_bits, tile)
+        p = self.params(map_n, k, export_depth, export_bits, tile, separate_test, full_raster)
         _check(lib().pv3d_evaluate(self.h, scene_h, gen_h, _ptr(s), _ptr(dni), _ptr(dp), _ptr(dt), n,
                                    ctypes.byref(p), ctypes.byref(out), None), self.h)
         return Result(counts, pw, pr, en, maps, bits)
 
     def evaluate_device(self, scene_h: int, gen_h: int, gen, sweep, map_n: int, k: int, stream=None,
-                        counts=None, tile: int = 0) -> Result:
+                        counts=None, tile: int = 0, separate_test=False, full_raster=False) -> Result:
         """Device outputs as torch tensors, asynchronous on `stream` (default: torch's current stream)."""
         import torch
         s = _c(sweep.sun_xyz, np.float64)
@@ -212,7 +228,7 @@ class Context:
         pr = torch.empty(n, dtype=torch.float64, device=dev)
         en = torch.empty(2, dtype=torch.float64, device=dev)
         out = Outputs(_ptr(counts), _ptr(pw), _ptr(pr), _ptr(en), None, None, 1)
-        p = self.params(map_n, k, tile=tile)
+        p = self.params(map_n, k, tile=tile, separate_test=separate_test, full_raster=full_raster)
         st = stream if stream is not None else torch.cuda.current_stream()
         _check(lib().pv3d_evaluate(self.h, scene_h, gen_h, _ptr(s), _ptr(dni), _ptr(dp), _ptr(dt), n,
                                    ctypes.byref(p), ctypes.byref(out), ctypes.c_void_p(st.cuda_stream)), self.h)

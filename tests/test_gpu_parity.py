@@ -43,8 +43,19 @@ def compare(ctx, oracle_lib, w, maps=True, bits=True, tile=0, threads=0):
     finally:
         ctx.release_scene(sh)
         ctx.release_generator(gh)
+    sh = ctx.load_scene(w.scene)
+    gh = ctx.define_generator(w.gen)
+    try:                      # the production route: picture only at sample texels, nothing exported
+        lean = ctx.evaluate(sh, gh, w.gen, w.sweep, w.map_n, w.k, tile=tile, export_bits=bits)
+    finally:
+        ctx.release_scene(sh)
+        ctx.release_generator(gh)
     ref = oracle_lib.evaluate(w.scene, w.gen, w.sweep, w.map_n, w.k, export_maps=maps, export_bits=bits,
                               threads=threads)
+    assert np.array_equal(lean.counts, ref.counts)
+    if bits:
+        assert np.array_equal(lean.bits, ref.bits)
+    np.testing.assert_allclose(lean.power, ref.power, rtol=REL, atol=0)
     assert ref.outside == 0
     if maps:
         bad = np.nonzero((got.maps != ref.maps).reshape(w.sweep.n, -1).any(axis=1))[0]
@@ -83,6 +94,22 @@ def test_tile_sizes_give_identical_results(ctx):
     for o in outs[1:]:
         assert np.array_equal(o.maps, outs[0].maps) and np.array_equal(o.bits, outs[0].bits)
         assert np.array_equal(o.power, outs[0].power)
+
+
+@pytest.mark.parametrize("seed,n,k", [(42, 256, 4), (43, 190, 3)])
+def test_separate_test_route_matches_fused_route(ctx, seed, n, k):
+    """Depth check in a second kernel reading the materialised picture == check inside the tile."""
+    w = W.random_tiny(seed, n_boxes=10, n_loose=50, n_mod_side=3, map_n=n, k=k, n_sun=6)
+    sh, gh = ctx.load_scene(w.scene), ctx.define_generator(w.gen)
+    a = ctx.evaluate(sh, gh, w.gen, w.sweep, w.map_n, w.k, export_depth=True, export_bits=True)
+    b = ctx.evaluate(sh, gh, w.gen, w.sweep, w.map_n, w.k, export_depth=True, export_bits=True, separate_test=True)
+    c = ctx.evaluate(sh, gh, w.gen, w.sweep, w.map_n, w.k, separate_test=True)
+    d = ctx.evaluate(sh, gh, w.gen, w.sweep, w.map_n, w.k, export_bits=True)                    # sparse
+    e = ctx.evaluate(sh, gh, w.gen, w.sweep, w.map_n, w.k, export_bits=True, full_raster=True)  # full, no export
+    assert np.array_equal(a.maps, b.maps) and np.array_equal(a.bits, b.bits)
+    assert np.array_equal(a.bits, d.bits) and np.array_equal(a.bits, e.bits)
+    for o in (b, c, d, e):
+        assert np.array_equal(a.counts, o.counts) and np.array_equal(a.power, o.power)
 
 
 def test_empty_scene_and_backlit_and_below_horizon(ctx, oracle_lib):
