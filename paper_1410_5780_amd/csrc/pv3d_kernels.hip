@@ -638,7 +638,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(int64_t s, BinBuffers bb, i
 // ---------------------------------------------------------------------------
 constexpr int kMaxTileMods = 256;       // module entries kept in LDS per tile
 constexpr int kMaxCellCounters = 256;   // per-wave cell counters of the full route
-constexpr int kMaxTileCells = 2048;     // (module slot, cell) counters of the sparse route
+constexpr int kMaxTileCells = 1024;     // (module slot, cell) counters of the sparse route
 
 struct TileCtx {
     int64_t s;
@@ -685,61 +685,97 @@ __device__ __forceinline__ TriRec rec_of_lane(const RecLane& L, int i) {
     return r;
 }
 
-// Per-module light-space affine map of the samples and the range of sample
-// indices (qa along edge_u, qb along edge_v) whose texel can lie in the tile.
-struct ModMap {
-    d3 p0, du, dv;
-    int32_t qa0, qa1, qb0, qb1;
+// A square of texels [x, x + size) x [y, y + size) inside a tile.
+struct Rect {
+    int32_t x, y, size;
 };
 
-template <int TS>
-__device__ __forceinline__ bool module_map(const View& V, const Module& M, int32_t knu, int32_t knv, const TileCtx& c,
-                                           ModMap& mm) {
+// Per-module light-space affine map of the samples.
+struct ModMap {
+    d3 p0, du, dv;
+};
+
+__device__ __forceinline__ void module_map(const View& V, const Module& M, ModMap& mm) {
     const d3 e1 = ld3(V.e1), e2 = ld3(V.e2), dd = ld3(V.d);
     mm.p0 = to_light(V, ld3(M.o));
     const d3 U = ld3(M.u), W = ld3(M.v);
     mm.du = d3{dot(U, e1) * V.itx, dot(U, e2) * V.ity, dot(U, dd) * V.izd};
     mm.dv = d3{dot(W, e1) * V.itx, dot(W, e2) * V.ity, dot(W, dd) * V.izd};
-    mm.qa0 = 0; mm.qa1 = knu - 1; mm.qb0 = 0; mm.qb1 = knv - 1;
-    const d3 du = mm.du, dv = mm.dv, p0 = mm.p0;
-    const double det = du.x * dv.y - du.y * dv.x;
-    if (fabs(det) > 1e-9 * (fabs(du.x * dv.y) + fabs(du.y * dv.x)) && det != 0.0) {
-        // invert the map at the tile's corners (open-ended at map borders, where samples would clamp)
-        const double BIG = 1e15;
-        const double cx[2] = {c.x0 == 0 ? -BIG : (double)c.x0, c.x0 + TS >= c.n ? BIG : (double)(c.x0 + TS)};
-        const double cy[2] = {c.y0 == 0 ? -BIG : (double)c.y0, c.y0 + TS >= c.n ? BIG : (double)(c.y0 + TS)};
-        double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
-        for (int qx = 0; qx < 2; qx++)
-            for (int qy = 0; qy < 2; qy++) {
-                const double ddx = cx[qx] - p0.x, ddy = cy[qy] - p0.y;
-                const double fu = (ddx * dv.y - ddy * dv.x) / det;
-                const double fv = (du.x * ddy - du.y * ddx) / det;
-                umin = fmin(umin, fu); umax = fmax(umax, fu);
-                vmin = fmin(vmin, fv); vmax = fmax(vmax, fv);
-            }
-        const double a0 = floor(umin * knu - 0.5) - 1.0, a1 = ceil(umax * knu - 0.5) + 1.0;
-        const double b0 = floor(vmin * knv - 0.5) - 1.0, b1 = ceil(vmax * knv - 0.5) + 1.0;
-        mm.qa0 = (int32_t)fmax(a0, 0.0); mm.qa1 = (int32_t)fmin(a1, (double)(knu - 1));
-        mm.qb0 = (int32_t)fmax(b0, 0.0); mm.qb1 = (int32_t)fmin(b1, (double)(knv - 1));
-    }
-    return mm.qa0 <= mm.qa1 && mm.qb0 <= mm.qb1;
 }
 
-// Light-space texel and depth of sample (qa, qb); false when its texel is not in the tile.
-template <int TS>
-__device__ __forceinline__ bool sample_in_tile(const ModMap& mm, const double* fu_tab, const double* fv_tab, int32_t qa,
-                                               int32_t qb, const TileCtx& c, int32_t* li, int32_t* lj, int64_t* zs) {
-    const double fu = fu_tab[qa], fv = fv_tab[qb];
+// Light-space extent of a rect for sample selection: texels clamp to the map,
+// so at a map border the rect reaches to infinity.
+__device__ __forceinline__ void rect_bounds(const Rect& r, int32_t n, double& xl, double& xh, double& yl, double& yh) {
+    xl = r.x == 0 ? -INFINITY : (double)r.x;
+    xh = r.x + r.size >= n ? INFINITY : (double)(r.x + r.size);
+    yl = r.y == 0 ? -INFINITY : (double)r.y;
+    yh = r.y + r.size >= n ? INFINITY : (double)(r.y + r.size);
+}
+
+// Conservative range of sample rows qb whose texels can fall in the rect:
+// the rect's corners mapped back to module coordinates (all rows when the
+// map is nearly singular or the rect is open-ended).
+__device__ __forceinline__ void row_range(const ModMap& mm, int32_t knv, double xl, double xh, double yl, double yh,
+                                          int32_t& qb0, int32_t& qb1) {
+    qb0 = 0;
+    qb1 = knv - 1;
+    const d3 du = mm.du, dv = mm.dv;
+    const double det = du.x * dv.y - du.y * dv.x;
+    if (!(fabs(det) > 1e-9 * (fabs(du.x * dv.y) + fabs(du.y * dv.x)) && det != 0.0)) return;
+    if (!(isfinite(xl) && isfinite(xh) && isfinite(yl) && isfinite(yh))) return;
+    double vmin = INFINITY, vmax = -INFINITY;
+    const double cx[2] = {xl, xh}, cy[2] = {yl, yh};
+    for (int qx = 0; qx < 2; qx++)
+        for (int qy = 0; qy < 2; qy++) {
+            const double fv = (du.x * (cy[qy] - mm.p0.y) - du.y * (cx[qx] - mm.p0.x)) / det;
+            vmin = fmin(vmin, fv);
+            vmax = fmax(vmax, fv);
+        }
+    const double b0 = floor(vmin * knv - 0.5) - 1.0, b1 = ceil(vmax * knv - 0.5) + 1.0;
+    qb0 = (int32_t)fmax(b0, 0.0);
+    qb1 = (int32_t)fmin(b1, (double)(knv - 1));
+}
+
+// Conservative column range [qa0, qa1] of one sample row whose texels can
+// fall in the rect: the row is a line in light space; intersect it with the
+// rect's slab in x and in y (widened by one sample for rounding).
+__device__ __forceinline__ void col_range(const ModMap& mm, double fv, int32_t knu, double xl, double xh, double yl,
+                                          double yh, int32_t& qa0, int32_t& qa1) {
+    double lo = 0.0, hi = 1.0;
+    const double bx = mm.p0.x + fv * mm.dv.x, by = mm.p0.y + fv * mm.dv.y;
+    const double cs[2] = {mm.du.x, mm.du.y}, bs[2] = {bx, by}, ls[2] = {xl, yl}, hs[2] = {xh, yh};
+    for (int q = 0; q < 2; q++) {
+        const double c = cs[q], b = bs[q];
+        if (fabs(c) > 1e-300) {
+            double f0 = (ls[q] - 1.0 - b) / c, f1 = (hs[q] + 1.0 - b) / c;   // one texel of margin
+            if (f0 > f1) { const double t = f0; f0 = f1; f1 = t; }
+            lo = fmax(lo, f0);
+            hi = fmin(hi, f1);
+        } else if (!(b >= ls[q] - 1.0 && b <= hs[q] + 1.0)) {
+            lo = 1.0; hi = 0.0;
+        }
+    }
+    if (!(lo <= hi)) { qa0 = 1; qa1 = 0; return; }
+    const double a0 = floor(lo * knu - 0.5) - 1.0, a1 = ceil(hi * knu - 0.5) + 1.0;
+    qa0 = (int32_t)fmax(a0, 0.0);
+    qa1 = (int32_t)fmin(a1, (double)(knu - 1));
+}
+
+// Texel and depth of sample (qa, qb), exactly as the definition computes
+// them; false when its texel is not in the rect. zs is the sample depth
+// clamped to int32 (the shaded test compares it with values below 2^25).
+__device__ __forceinline__ bool sample_in_rect(const ModMap& mm, double fu, double fv, const Rect& r, int32_t n,
+                                               int32_t* li, int32_t* lj, int32_t* zs) {
     const double x = (mm.p0.x + fu * mm.du.x) + fv * mm.dv.x;
     const double y = (mm.p0.y + fu * mm.du.y) + fv * mm.dv.y;
     const double z = (mm.p0.z + fu * mm.du.z) + fv * mm.dv.z;
-    int64_t i = (int64_t)floor(x), j = (int64_t)floor(y);
-    i = min(max(i, (int64_t)0), (int64_t)c.n - 1);
-    j = min(max(j, (int64_t)0), (int64_t)c.n - 1);
-    if (i < c.x0 || i >= c.x0 + TS || j < c.y0 || j >= c.y0 + TS) return false;
-    *li = (int32_t)(i - c.x0);
-    *lj = (int32_t)(j - c.y0);
-    *zs = (int64_t)floor(z);
+    const double hi = (double)(n - 1);
+    const int32_t i = (int32_t)fmin(fmax(floor(x), 0.0), hi);
+    const int32_t j = (int32_t)fmin(fmax(floor(y), 0.0), hi);
+    if (i < r.x || i >= r.x + r.size || j < r.y || j >= r.y + r.size) return false;
+    *li = i - r.x;
+    *lj = j - r.y;
+    *zs = (int32_t)fmin(fmax(floor(z), -2147483648.0), 2147483647.0);
     return true;
 }
 
@@ -753,6 +789,20 @@ struct TriClip {
 __device__ __forceinline__ bool clip_to_tile(const TriRec& R, int32_t x0, int32_t y0, int32_t TS, TriClip& t) {
     t.ilo = max((int32_t)R.ilo, x0); t.ihi = min((int32_t)R.ihi, x0 + TS - 1);
     t.jlo = max((int32_t)R.jlo, y0); t.jhi = min((int32_t)R.jhi, y0 + TS - 1);
+    if (t.ilo > t.ihi || t.jlo > t.jhi) return false;
+    bool outside = false;
+    for (int e = 0; e < 3; e++) {
+        t.EA[e] = (int64_t)R.a[e] * 256;
+        t.EB[e] = (int64_t)R.b[e] * 256;
+        const int64_t bmax = R.e0[e] + t.EA[e] * (t.EA[e] > 0 ? t.ihi : t.ilo) + t.EB[e] * (t.EB[e] > 0 ? t.jhi : t.jlo);
+        outside |= bmax < 0;
+    }
+    return !outside;
+}
+
+__device__ __forceinline__ bool clip_to_rect(const TriRec& R, const Rect& r, TriClip& t) {
+    t.ilo = max((int32_t)R.ilo, r.x); t.ihi = min((int32_t)R.ihi, r.x + r.size - 1);
+    t.jlo = max((int32_t)R.jlo, r.y); t.jhi = min((int32_t)R.jhi, r.y + r.size - 1);
     if (t.ilo > t.ihi || t.jlo > t.jhi) return false;
     bool outside = false;
     for (int e = 0; e < 3; e++) {
@@ -845,17 +895,20 @@ __device__ void store_tile(const uint32_t* zt, uint32_t* map, const TileCtx& c, 
     }
 }
 
-// Depth check of the tile's samples against the full LDS tile (waves over modules).
+// Depth check of the samples whose texel lies in rect r against the full LDS
+// tile (waves over modules; each sample row gets its exact column range).
 template <int TS>
 __device__ void samples_full(const uint32_t* zt, const int32_t* mods, int32_t nm, bool mods_in_lds, uint32_t* cc,
                              const View& V, const BinBuffers& bb, const GenDev& g, const int32_t* bias,
                              const double* fu_tab, const double* fv_tab, int32_t k, const TileOut& out,
-                             const TileCtx& c, int lane, int wv) {
+                             const TileCtx& c, const Rect& r, int lane, int wv) {
     constexpr int PITCH = TS + 8;
     const int32_t cpm = g.n_cu * g.n_cv;
     const int32_t knu = k * g.n_cu, knv = k * g.n_cv;
     const int32_t kk = k * k, words = (kk + 31) / 32;
     const bool lds_cells = cpm <= kMaxCellCounters;
+    double xl, xh, yl, yh;
+    rect_bounds(r, c.n, xl, xh, yl, yh);
     for (int32_t mi = wv; mi < nm; mi += 4) {
         int32_t m;
         if (!mods_in_lds) {
@@ -868,25 +921,29 @@ __device__ void samples_full(const uint32_t* zt, const int32_t* mods, int32_t nm
         const int32_t bm = bias[c.s * g.n_mod + m];
         if (bm < 0) continue;
         ModMap mm;
-        if (!module_map<TS>(V, g.mods[m], knu, knv, c, mm)) continue;
-        const int32_t na = mm.qa1 - mm.qa0 + 1, ncand = na * (mm.qb1 - mm.qb0 + 1);
+        module_map(V, g.mods[m], mm);
+        int32_t qb0, qb1;
+        row_range(mm, knv, xl, xh, yl, yh, qb0, qb1);
         if (lds_cells)
             for (int32_t q = lane; q < cpm; q += 64) cc[q] = 0;
         __builtin_amdgcn_wave_barrier();
-        for (int32_t t = lane; t < ncand; t += 64) {
-            const int32_t ob = t / na;
-            const int32_t qa = mm.qa0 + (t - ob * na), qb = mm.qb0 + ob;
-            int32_t li, lj;
-            int64_t zs;
-            if (!sample_in_tile<TS>(mm, fu_tab, fv_tab, qa, qb, c, &li, &lj, &zs)) continue;
-            if (zs > (int64_t)zt[lj * PITCH + li] + (int64_t)bm) {
-                const int32_t cu = qa / k, cv = qb / k;
-                const int32_t cell = cv * g.n_cu + cu;
-                if (lds_cells) atomicAdd(&cc[cell], 1u);
-                else atomicAdd(&out.counts[(int64_t)m * cpm + cell], 1u);
-                if (out.bits) {
-                    const int32_t si = (qb - cv * k) * k + (qa - cu * k);
-                    atomicOr(&out.bits[((int64_t)m * cpm + cell) * words + si / 32], 1u << (si % 32));
+        for (int32_t qb = qb0; qb <= qb1; qb++) {
+            const double fv = fv_tab[qb];
+            int32_t qa0, qa1;
+            col_range(mm, fv, knu, xl, xh, yl, yh, qa0, qa1);
+            for (int32_t qa = qa0 + lane; qa <= qa1; qa += 64) {
+                int32_t li, lj, zs;
+                if (!sample_in_rect(mm, fu_tab[qa], fv, r, c.n, &li, &lj, &zs)) continue;
+                const int32_t lx = li + r.x - c.x0, ly = lj + r.y - c.y0;
+                if ((int64_t)zs > (int64_t)zt[ly * PITCH + lx] + (int64_t)bm) {
+                    const int32_t cu = qa / k, cv = qb / k;
+                    const int32_t cell = cv * g.n_cu + cu;
+                    if (lds_cells) atomicAdd(&cc[cell], 1u);
+                    else atomicAdd(&out.counts[(int64_t)m * cpm + cell], 1u);
+                    if (out.bits) {
+                        const int32_t si = (qb - cv * k) * k + (qa - cu * k);
+                        atomicOr(&out.bits[((int64_t)m * cpm + cell) * words + si / 32], 1u << (si % 32));
+                    }
                 }
             }
         }
@@ -901,7 +958,7 @@ __device__ void samples_full(const uint32_t* zt, const int32_t* mods, int32_t nm
     }
 }
 
-// Sparse-route sample entry: texel (li, lj) in the tile, shading threshold
+// Sparse-route sample entry: texel (li, lj) in the rect, shading threshold
 // (shaded iff threshold > nearest depth at the texel), and the sample's
 // identity (tile module slot, qa, qb).
 struct SparseLds {
@@ -911,6 +968,225 @@ struct SparseLds {
     uint32_t* dmin;      // nearest depth at the texel centre
     uint16_t* order;     // entries sorted by texel row
 };
+
+struct SparseShared {
+    int32_t n_ent, ent_overflow, max_thr, next, n_slots;
+};
+
+// A triangle of the current chunk, relative to the rect origin: edge k at
+// texel (li, lj) of the rect is ex[k] + A[k] li + B[k] lj, depth
+// (zx + gx li + gy lj) >> 16; box = clipped texel box (4 x 8 bits).
+struct TriSlot {
+    int64_t ex[3], A[3], B[3];
+    int64_t zx, gx, gy;
+    uint32_t box, pad;
+};
+
+constexpr int kTriChunk = 64;     // triangles staged in LDS at a time
+constexpr int kStampList = 48;    // triangle slots listed per 8x8 stamp
+
+struct TriBins {
+    TriSlot* slot;      // [kTriChunk]
+    int32_t* cnt;       // [64] triangles per stamp
+    uint8_t* list;      // [64][kStampList]
+};
+
+// Sparse route over one rect of the tile: list the samples whose texel lies
+// in the rect, test every binned triangle at their texel centres, count the
+// shaded ones. Returns false (nothing written) when the rect holds more
+// samples than the LDS list; the caller then splits it.
+template <int TS, int CAP>
+__device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriBins& tb, int32_t* rowstart, uint32_t* cells,
+                            const int32_t* mods, int32_t n_mods, const View& V, const BinBuffers& bb, const GenDev& g,
+                            const int32_t* bias, const double* fu_tab, const double* fv_tab, int32_t k,
+                            const TileOut& out, const TileCtx& c, int tid, int lane, int wv) {
+    const int32_t cpm = g.n_cu * g.n_cv;
+    const int32_t knu = k * g.n_cu, knv = k * g.n_cv;
+    double xl, xh, yl, yh;
+    rect_bounds(r, c.n, xl, xh, yl, yh);
+    if (tid == 0) { sh.n_ent = 0; sh.ent_overflow = 0; sh.max_thr = INT32_MIN; sh.next = 0; }
+    for (int q = tid; q <= r.size; q += 256) rowstart[q] = 0;
+    __syncthreads();
+    // 1. the samples whose texel lies in the rect: waves over modules; a wave
+    //    walks 8 x 8 blocks of (row, column) sample indices covering the rows'
+    //    exact column ranges, lane (r, c) = (lane / 8, lane % 8)
+    const double dknu = (double)knu, dknv = (double)knv;
+    int32_t my_max = INT32_MIN;
+    for (int32_t mi = wv; mi < n_mods; mi += 4) {
+        const int32_t m = mods[mi];
+        const int32_t bm = bias[c.s * g.n_mod + m];
+        if (bm < 0) continue;
+        ModMap mm;
+        module_map(V, g.mods[m], mm);
+        int32_t qb0, qb1;
+        row_range(mm, knv, xl, xh, yl, yh, qb0, qb1);
+        for (int32_t rb = qb0; rb <= qb1; rb += 8) {
+            const int32_t qb = rb + (lane >> 3);
+            double fv = 0.0;
+            int32_t qa0 = 1, qa1 = 0;
+            if (qb <= qb1) {
+                fv = ((double)qb + 0.5) / dknv;         // the sample's fraction along edge_v
+                col_range(mm, fv, knu, xl, xh, yl, yh, qa0, qa1);
+            }
+            int32_t blo = qa0 <= qa1 ? qa0 : INT32_MAX, bhi = qa0 <= qa1 ? qa1 : -1;
+            for (int off = 8; off < 64; off <<= 1) {    // union of the 8 rows' ranges
+                blo = min(blo, __shfl_xor(blo, off, 64));
+                bhi = max(bhi, __shfl_xor(bhi, off, 64));
+            }
+            for (int32_t cb = blo; cb <= bhi; cb += 8) {
+                const int32_t qa = cb + (lane & 7);
+                if (qa < qa0 || qa > qa1) continue;
+                const double fu = ((double)qa + 0.5) / dknu;   // the sample's fraction along edge_u
+                int32_t li, lj, zs;
+                if (!sample_in_rect(mm, fu, fv, r, c.n, &li, &lj, &zs)) continue;
+                const int32_t e = atomicAdd(&sh.n_ent, 1);
+                if (e >= CAP) { sh.ent_overflow = 1; continue; }
+                const int64_t th64 = (int64_t)zs - (int64_t)bm;
+                const int32_t th = th64 < (int64_t)INT32_MIN ? INT32_MIN : (int32_t)th64;
+                sp.texel[e] = (uint16_t)(lj * TS + li);
+                sp.thr[e] = th;
+                sp.code[e] = ((uint32_t)mi << 24) | ((uint32_t)qb << 12) | (uint32_t)qa;
+                sp.dmin[e] = kDepthMax;
+                my_max = max(my_max, th);
+            }
+        }
+    }
+    for (int off = 1; off < 64; off <<= 1) my_max = max(my_max, __shfl_xor(my_max, off, 64));
+    if (lane == 0 && my_max != INT32_MIN) atomicMax(&sh.max_thr, my_max);
+    __syncthreads();
+    if (sh.ent_overflow) return false;
+    const int32_t ne = sh.n_ent;
+    if (ne == 0) return true;
+    // 2. counting sort of the entries by 8x8 stamp of the rect
+    const int32_t spr = (r.size + 7) / 8, n_st = spr * spr;
+    for (int32_t e = tid; e < ne; e += 256) {
+        const int32_t tx = sp.texel[e];
+        atomicAdd(&rowstart[(tx / TS / 8) * spr + (tx % TS) / 8 + 1], 1);
+    }
+    __syncthreads();
+    if (tid == 0)
+        for (int q = 1; q <= n_st; q++) rowstart[q] += rowstart[q - 1];
+    __syncthreads();
+    for (int q = tid; q < n_st; q += 256) cells[q] = (uint32_t)rowstart[q];
+    __syncthreads();
+    for (int32_t e = tid; e < ne; e += 256) {
+        const int32_t tx = sp.texel[e];
+        sp.order[atomicAdd(&cells[(tx / TS / 8) * spr + (tx % TS) / 8], 1u)] = (uint16_t)e;
+    }
+    // 3. triangles in chunks: each chunk's records go to LDS (relative to the
+    //    rect origin), are binned into the rect's stamps one lane per stamp,
+    //    and every sample then tests only the triangles of its own stamp
+    const int32_t mthr = sh.max_thr;
+    const int32_t total = c.n_large + (c.be - c.bs);
+    for (int32_t base = 0; base < total; base += kTriChunk) {
+        if (tid == 0) sh.n_slots = 0;
+        for (int q = tid; q < n_st; q += 256) { tb.cnt[q] = 0; }
+        __syncthreads();
+        if (tid < kTriChunk && base + tid < total) {
+            const int32_t item = base + tid;
+            const int32_t rid = item < c.n_large ? bb.large[item] : bb.bins[c.bs + item - c.n_large];
+            if (rid >= 0) {
+                const TriRec R = bb.rec[rid];
+                TriClip t;
+                if (clip_to_rect(R, r, t)) {
+                    const int64_t zmin = R.z0 + R.gx * (R.gx > 0 ? t.ilo : t.ihi) + R.gy * (R.gy > 0 ? t.jlo : t.jhi);
+                    if ((int64_t)depth_q(zmin) < (int64_t)mthr) {
+                        const int32_t q = atomicAdd(&sh.n_slots, 1);
+                        TriSlot& T = tb.slot[q];
+                        for (int e = 0; e < 3; e++) {
+                            T.ex[e] = R.e0[e] + t.EA[e] * r.x + t.EB[e] * r.y;
+                            T.A[e] = t.EA[e];
+                            T.B[e] = t.EB[e];
+                        }
+                        T.zx = R.z0 + R.gx * r.x + R.gy * r.y;
+                        T.gx = R.gx;
+                        T.gy = R.gy;
+                        T.box = (uint32_t)(t.ilo - r.x) | ((uint32_t)(t.ihi - r.x) << 8) | ((uint32_t)(t.jlo - r.y) << 16) |
+                                ((uint32_t)(t.jhi - r.y) << 24);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        const int32_t ns = sh.n_slots;
+        if (ns == 0) continue;
+        // stamp binning: wave per triangle slot, lane per stamp
+        for (int32_t q = wv; q < ns; q += 4) {
+            const TriSlot& T = tb.slot[q];
+            const int32_t bi0 = (int32_t)(T.box & 255), bi1 = (int32_t)((T.box >> 8) & 255);
+            const int32_t bj0 = (int32_t)((T.box >> 16) & 255), bj1 = (int32_t)(T.box >> 24);
+            if (lane < n_st) {
+                const int32_t sx = (lane % spr) * 8, sy = (lane / spr) * 8;
+                const int32_t i0 = max(sx, bi0), i1 = min(sx + 7, bi1), j0 = max(sy, bj0), j1 = min(sy + 7, bj1);
+                bool hit = i0 <= i1 && j0 <= j1;
+                for (int e = 0; e < 3 && hit; e++) {
+                    const int64_t emax = T.ex[e] + T.A[e] * (T.A[e] > 0 ? i1 : i0) + T.B[e] * (T.B[e] > 0 ? j1 : j0);
+                    hit = emax >= 0;
+                }
+                if (hit) {
+                    const int32_t pos = atomicAdd(&tb.cnt[lane], 1);
+                    if (pos < kStampList) tb.list[lane * kStampList + pos] = (uint8_t)q;
+                }
+            }
+        }
+        __syncthreads();
+        // samples against the triangles of their stamp (all triangles of the chunk when the list overflowed)
+        for (int32_t p = tid; p < ne; p += 256) {
+            const int32_t e = sp.order[p];
+            const int32_t tx = sp.texel[e];
+            const int32_t li = tx % TS, lj = tx / TS;
+            const int32_t st = (lj / 8) * spr + li / 8;
+            const int32_t nl = tb.cnt[st];
+            const bool all = nl > kStampList;
+            const int32_t nt = all ? ns : nl;
+            uint32_t dm = sp.dmin[e];
+            for (int32_t u = 0; u < nt; u++) {
+                const int32_t q = all ? u : (int32_t)tb.list[st * kStampList + u];
+                const TriSlot& T = tb.slot[q];
+                const int64_t E0 = T.ex[0] + T.A[0] * li + T.B[0] * lj;
+                const int64_t E1 = T.ex[1] + T.A[1] * li + T.B[1] * lj;
+                const int64_t E2 = T.ex[2] + T.A[2] * li + T.B[2] * lj;
+                if ((E0 | E1 | E2) >= 0) {
+                    const uint32_t D = depth_q(T.zx + T.gx * li + T.gy * lj);
+                    dm = D < dm ? D : dm;
+                }
+            }
+            sp.dmin[e] = dm;
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    // 4. shaded flags, per-cell counts
+    const bool lds_cells = n_mods * cpm <= kMaxTileCells;
+    if (lds_cells)
+        for (int32_t q = tid; q < n_mods * cpm; q += 256) cells[q] = 0;
+    __syncthreads();
+    const int32_t words = (k * k + 31) / 32;
+    for (int32_t e = tid; e < ne; e += 256) {
+        if (!(sp.thr[e] > (int32_t)sp.dmin[e])) continue;
+        const uint32_t code = sp.code[e];
+        const int32_t slot = (int32_t)(code >> 24), qb = (int32_t)((code >> 12) & 0xFFF), qa = (int32_t)(code & 0xFFF);
+        const int32_t cu = qa / k, cv = qb / k, cell = cv * g.n_cu + cu;
+        const int32_t m = mods[slot];
+        if (lds_cells) atomicAdd(&cells[slot * cpm + cell], 1u);
+        else atomicAdd(&out.counts[(int64_t)m * cpm + cell], 1u);
+        if (out.bits) {
+            const int32_t si = (qb - cv * k) * k + (qa - cu * k);
+            atomicOr(&out.bits[((int64_t)m * cpm + cell) * words + si / 32], 1u << (si % 32));
+        }
+    }
+    __syncthreads();
+    if (lds_cells)
+        for (int32_t q = tid; q < n_mods * cpm; q += 256) {
+            const uint32_t v = cells[q];
+            if (v) atomicAdd(&out.counts[(int64_t)mods[q / cpm] * cpm + q % cpm], v);
+        }
+    __syncthreads();
+    return true;
+}
+
+constexpr int kMinRect = 16;
+constexpr int kMaxRects = 64;
 
 template <int TS, int CAP>
 __global__ __launch_bounds__(256) void k_tile(int64_t s, const View* views, BinBuffers bb, const SunCounters* ctr,
@@ -925,7 +1201,12 @@ __global__ __launch_bounds__(256) void k_tile(int64_t s, const View* views, BinB
     __shared__ int32_t mods[kMaxTileMods];
     __shared__ uint32_t cells[kMaxTileCells > 4 * kMaxCellCounters ? kMaxTileCells : 4 * kMaxCellCounters];
     __shared__ int32_t rowstart[TS + 1];
-    __shared__ int32_t next, n_mods, mods_overflow, n_ent, ent_overflow, max_thr;
+    __shared__ Rect todo[kMaxRects], failed[kMaxRects];
+    __shared__ TriSlot tslots[kTriChunk];
+    __shared__ int32_t tcnt[64];
+    __shared__ uint8_t tlist[64 * kStampList];
+    __shared__ int32_t next, n_mods, mods_overflow, n_todo, n_failed;
+    __shared__ SparseShared sh;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int32_t tile = blockIdx.x;
     TileCtx c;
@@ -948,7 +1229,7 @@ __global__ __launch_bounds__(256) void k_tile(int64_t s, const View* views, BinB
     c.bs = min(bb.tile_start[tile], bb.bin_cap);
     c.be = min(bb.tile_start[tile + 1], bb.bin_cap);
     c.n_large = ctr[s].n_large;
-    if (tid == 0) { next = 0; n_mods = 0; mods_overflow = 0; n_ent = 0; ent_overflow = 0; max_thr = INT32_MIN; }
+    if (tid == 0) { next = 0; n_mods = 0; mods_overflow = 0; n_todo = 0; n_failed = 0; }
     __syncthreads();
     for (int32_t q = c.bs + tid; q < c.be; q += 256) {   // module entries of this tile
         const int32_t id = bb.bins[q];
@@ -961,118 +1242,50 @@ __global__ __launch_bounds__(256) void k_tile(int64_t s, const View* views, BinB
     __syncthreads();
     const bool test = out.test && n_mods > 0;
     if (!test && !out.map) return;                        // no sample falls here and nothing to export
-    const int32_t cpm = g.n_cu * g.n_cv;
-    const int32_t knu = k * g.n_cu, knv = k * g.n_cv;
-    bool go_sparse = sparse && !out.map && test && !mods_overflow;
+    const Rect whole{c.x0, c.y0, TS};
 
-    if (go_sparse) {
+    if (sparse && !out.map && test && !mods_overflow) {
         SparseLds sp;
         sp.texel = reinterpret_cast<uint16_t*>(pool);
         sp.thr = reinterpret_cast<int32_t*>(pool + 2 * CAP);
         sp.code = reinterpret_cast<uint32_t*>(pool + 6 * CAP);
         sp.dmin = reinterpret_cast<uint32_t*>(pool + 10 * CAP);
         sp.order = reinterpret_cast<uint16_t*>(pool + 14 * CAP);
-        // 1. list the samples whose texel lies in this tile
-        for (int32_t mi = wv; mi < n_mods; mi += 4) {
-            const int32_t m = mods[mi];
-            const int32_t bm = bias[s * g.n_mod + m];
-            if (bm < 0) continue;
-            ModMap mm;
-            if (!module_map<TS>(V, g.mods[m], knu, knv, c, mm)) continue;
-            const int32_t na = mm.qa1 - mm.qa0 + 1, ncand = na * (mm.qb1 - mm.qb0 + 1);
-            for (int32_t t = lane; t < ncand; t += 64) {
-                const int32_t ob = t / na;
-                const int32_t qa = mm.qa0 + (t - ob * na), qb = mm.qb0 + ob;
-                int32_t li, lj;
-                int64_t zs;
-                if (!sample_in_tile<TS>(mm, fu_tab, fv_tab, qa, qb, c, &li, &lj, &zs)) continue;
-                const int32_t e = atomicAdd(&n_ent, 1);
-                if (e >= CAP) { ent_overflow = 1; continue; }
-                const int32_t th = (int32_t)(zs - (int64_t)bm);
-                sp.texel[e] = (uint16_t)(lj * TS + li);
-                sp.thr[e] = th;
-                sp.code[e] = ((uint32_t)mi << 24) | ((uint32_t)qb << 12) | (uint32_t)qa;
-                sp.dmin[e] = kDepthMax;
-                atomicMax(&max_thr, th);
-            }
+        TriBins tb;
+        tb.slot = tslots;
+        tb.cnt = tcnt;
+        tb.list = tlist;
+        if (tid == 0) {                               // rects of at most 64 x 64 texels (one lane per 8x8 stamp)
+            const int32_t rs = TS < 64 ? TS : 64;
+            n_todo = 0;
+            for (int32_t y = 0; y < TS; y += rs)
+                for (int32_t x = 0; x < TS; x += rs) todo[n_todo++] = Rect{c.x0 + x, c.y0 + y, rs};
         }
-        for (int q = tid; q <= TS; q += 256) rowstart[q] = 0;
         __syncthreads();
-        if (!ent_overflow) {
-            const int32_t ne = n_ent;
-            // 2. counting sort of the entries by texel row
-            for (int32_t e = tid; e < ne; e += 256) atomicAdd(&rowstart[sp.texel[e] / TS + 1], 1);
+        while (n_todo > 0) {                              // a rect with too many samples is split in four
+            const Rect r = todo[n_todo - 1];
             __syncthreads();
-            if (tid == 0)
-                for (int r = 1; r <= TS; r++) rowstart[r] += rowstart[r - 1];
-            __syncthreads();
-            uint32_t* cur = cells;                    // row cursors (the counters are not in use yet)
-            for (int r = tid; r < TS; r += 256) cur[r] = (uint32_t)rowstart[r];
-            __syncthreads();
-            for (int32_t e = tid; e < ne; e += 256) sp.order[atomicAdd(&cur[sp.texel[e] / TS], 1u)] = (uint16_t)e;
-            __syncthreads();
-            // 3. every triangle against the sample texels of the rows it spans
-            const int32_t mthr = max_thr;
-            const int32_t total = c.n_large + (c.be - c.bs);
-            for (;;) {
-                const int32_t base = next_chunk(&next, lane);
-                if (base >= total) break;
-                const int32_t cnt = min(kChunk, total - base);
-                RecLane L;
-                const int32_t rid = load_chunk(bb, base, cnt, c.n_large, c.bs, lane, L);
-                for (int ci = 0; ci < cnt; ci++) {
-                if (__builtin_amdgcn_readlane(rid, ci) < 0) continue;
-                const TriRec R = rec_of_lane(L, ci);
-                TriClip t;
-                if (!clip_to_tile(R, c.x0, c.y0, TS, t)) continue;
-                // nearest depth of the plane over the clipped box: when it is not in front of any
-                // sample's threshold the triangle cannot shade a sample of this tile
-                const int64_t zmin = R.z0 + R.gx * (R.gx > 0 ? t.ilo : t.ihi) + R.gy * (R.gy > 0 ? t.jlo : t.jhi);
-                if ((int64_t)depth_q(zmin) >= (int64_t)mthr) continue;
-                const int32_t p0 = rowstart[t.jlo - c.y0], p1 = rowstart[t.jhi - c.y0 + 1];
-                for (int32_t p = p0 + lane; p < p1; p += 64) {
-                    const int32_t e = sp.order[p];
-                    const int32_t tx = sp.texel[e];
-                    const int32_t i = c.x0 + tx % TS, j = c.y0 + tx / TS;
-                    if (i < t.ilo || i > t.ihi) continue;
-                    const int64_t E0 = R.e0[0] + t.EA[0] * i + t.EB[0] * j;
-                    const int64_t E1 = R.e0[1] + t.EA[1] * i + t.EB[1] * j;
-                    const int64_t E2 = R.e0[2] + t.EA[2] * i + t.EB[2] * j;
-                    if ((E0 | E1 | E2) >= 0) atomicMin(&sp.dmin[e], depth_q(R.z0 + R.gx * i + R.gy * j));
-                }
+            if (tid == 0) n_todo--;
+            const bool ok = sparse_rect<TS, CAP>(r, sp, sh, tb, rowstart, cells, mods, n_mods, V, bb, g, bias, fu_tab,
+                                                 fv_tab, k, out, c, tid, lane, wv);
+            if (tid == 0 && !ok) {
+                if (r.size > kMinRect && n_todo + 4 <= kMaxRects) {
+                    const int32_t h = r.size / 2;
+                    todo[n_todo++] = Rect{r.x, r.y, h};
+                    todo[n_todo++] = Rect{r.x + h, r.y, h};
+                    todo[n_todo++] = Rect{r.x, r.y + h, h};
+                    todo[n_todo++] = Rect{r.x + h, r.y + h, h};
+                } else if (n_failed < kMaxRects) {
+                    failed[n_failed++] = r;
                 }
             }
             __syncthreads();
-            // 4. shaded flags, per-cell counts
-            const int32_t mods_n = n_mods;
-            const bool lds_cells = mods_n * cpm <= kMaxTileCells;
-            if (lds_cells)
-                for (int32_t q = tid; q < mods_n * cpm; q += 256) cells[q] = 0;
-            __syncthreads();
-            const int32_t words = (k * k + 31) / 32;
-            for (int32_t e = tid; e < ne; e += 256) {
-                if (!(sp.thr[e] > (int32_t)sp.dmin[e])) continue;
-                const uint32_t code = sp.code[e];
-                const int32_t slot = (int32_t)(code >> 24), qb = (int32_t)((code >> 12) & 0xFFF), qa = (int32_t)(code & 0xFFF);
-                const int32_t cu = qa / k, cv = qb / k, cell = cv * g.n_cu + cu;
-                const int32_t m = mods[slot];
-                if (lds_cells) atomicAdd(&cells[slot * cpm + cell], 1u);
-                else atomicAdd(&out.counts[(int64_t)m * cpm + cell], 1u);
-                if (out.bits) {
-                    const int32_t si = (qb - cv * k) * k + (qa - cu * k);
-                    atomicOr(&out.bits[((int64_t)m * cpm + cell) * words + si / 32], 1u << (si % 32));
-                }
-            }
-            __syncthreads();
-            if (lds_cells)
-                for (int32_t q = tid; q < mods_n * cpm; q += 256) {
-                    const uint32_t v = cells[q];
-                    if (v) atomicAdd(&out.counts[(int64_t)mods[q / cpm] * cpm + q % cpm], v);
-                }
-            return;
         }
-        // too many samples for the LDS list: fall through to the full route
-        if (tid == 0) next = 0;
+        if (n_failed == 0) return;
+        if (tid == 0) next = 0;                           // full route for the rects that stayed too dense
+        __syncthreads();
+    } else {
+        if (tid == 0) { failed[0] = whole; n_failed = 1; }
         __syncthreads();
     }
 
@@ -1084,8 +1297,9 @@ __global__ __launch_bounds__(256) void k_tile(int64_t s, const View* views, BinB
     if (out.map) store_tile<TS>(zt, out.map, c, tid);
     if (!test) return;
     const int32_t nm = mods_overflow ? (c.be - c.bs) : n_mods;
-    samples_full<TS>(zt, mods, nm, !mods_overflow, cells + wv * kMaxCellCounters, V, bb, g, bias, fu_tab, fv_tab, k,
-                     out, c, lane, wv);
+    for (int32_t f = 0; f < n_failed; f++)
+        samples_full<TS>(zt, mods, nm, !mods_overflow, cells + wv * kMaxCellCounters, V, bb, g, bias, fu_tab, fv_tab,
+                         k, out, c, failed[f], lane, wv);
 }
 
 // ---------------------------------------------------------------------------
