@@ -42,6 +42,11 @@ def parse():
     ap.add_argument("--cpu-every", type=int, default=20, help="oracle leg: every n-th sun of the year")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
+    ap.add_argument("--route", default="sparse", choices=["sparse", "materialised"],
+                    help="sparse: picture evaluated at sample texels only (default); materialised: every "
+                         "sun's full picture written to HBM and read back by a separate depth-check kernel")
+    ap.add_argument("--no-materialised", action="store_true",
+                    help="skip the extra one-step run of the materialised route")
     return ap.parse_args()
 
 
@@ -65,16 +70,47 @@ def algorithmic_bytes(w):
     return 24 * V + 12 * T + 4 * w.map_n * w.map_n + 4 * w.gen.n_cells
 
 
-def stage_unit_bytes(stage, w):
-    """Algorithmic HBM bytes of one launch of a stage (one sun)."""
+# Peaks of one MI355X: HBM3E 8 TB/s; VALU lane operations (int32 / fp32 / fp64
+# non-packed: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Lane operations the depth check of one sample needs at least: the FP64 affine
+# map to light space (3 x 4), three floors and clamps (12), and at its texel
+# the edge functions and depth plane of the two surfaces every sample sees
+# (its own module and what lies behind it): 2 x (3 edges + 1 plane) x 2 int64
+# multiply-adds x 4 int32 operations = 64; 88 in all.
+SAMPLE_LANE_OPS = 88
+
+
+def stage_roofline(stage, w, route):
+    """(bound, algorithmic units per launch, unit, peak) of one launch of a stage (one sun)."""
     V = w.scene.n_vert + 4 * w.gen.n_mod
+    if stage == "raster" and route == "materialised":
+        return "hbm", 4 * w.map_n * w.map_n, "GB/s", HBM_PEAK_GBS        # the picture, written once
     if stage == "raster":
-        return 4 * w.map_n * w.map_n                 # the depth picture, written once
+        return "alu", SAMPLE_LANE_OPS * w.n_samples, "TOP/s", VALU_PEAK_TOPS
     if stage == "sample_test":
-        return 4 * w.n_samples + 4 * w.gen.n_cells    # one texel read per sample, one count per cell
+        return "hbm", 4 * w.n_samples + 4 * w.gen.n_cells, "GB/s", HBM_PEAK_GBS
     if stage == "tri_setup":
-        return 24 * V + 12 * w.n_tri_submitted
-    return 0
+        return "hbm", 24 * V + 12 * w.n_tri_submitted, "GB/s", HBM_PEAK_GBS
+    return "hbm", 0, "GB/s", HBM_PEAK_GBS
+
+
+def measured_traffic(kernel, route):
+    """HBM bytes per launch of the tile kernel from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    if kernel != "raster" or route != "sparse":
+        return None
+    prof = os.path.join(ROOT, "profiles", "tile_c2_row_plant.md")
+    src = os.path.join(ROOT, "paper_1410_5780_amd", "csrc", "pv3d_kernels.hip")
+    try:
+        kv = dict(line.split(" = ", 1) for line in open(prof).read().splitlines() if " = " in line)
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if kv.get("kernel_source_sha256_16", "").strip() != sha:
+        return None
+    return int(kv["tile_traffic_bytes_per_launch"])
 
 
 def cpu_baseline(w_full, every):
@@ -115,8 +151,9 @@ def main():
     counts = torch.empty((n_sun, w.gen.n_cells), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
 
-    def step():
-        return ctx.evaluate_device(sh, gh, w.gen, w.sweep, w.map_n, w.k, stream=stream, counts=counts, tile=a.tile)
+    def step(route=a.route):
+        return ctx.evaluate_device(sh, gh, w.gen, w.sweep, w.map_n, w.k, stream=stream, counts=counts, tile=a.tile,
+                                   separate_test=(route == "materialised"))
 
     # warmup; the first warmup pass also times every stage to find the dominant kernel
     stage_ms = {}
@@ -159,9 +196,31 @@ def main():
     tests = w.n_samples * n_sun
     tris = w.n_tri_submitted * n_sun
     avg_s = k_ms * 1e-3 / max(k_n, 1)
-    unit_bytes = stage_unit_bytes(dominant, w)
-    achieved = unit_bytes / avg_s / 1e9 if unit_bytes else None
+    bound, units, unit, peak = stage_roofline(dominant, w, a.route)
+    achieved = units / avg_s / (1e9 if unit == "GB/s" else 1e12) if units else None
     loss = res.loss
+
+    mat = None
+    if not a.no_materialised and a.route != "materialised":
+        # the same year with the picture materialised in HBM: raster writes it, a second kernel reads it
+        ctx.profile_enable((1 << pv3d.STAGE["raster"]) | (1 << pv3d.STAGE["sample_test"]))
+        torch.cuda.synchronize()
+        m0 = time.perf_counter()
+        mres = step("materialised")
+        torch.cuda.synchronize()
+        m1 = time.perf_counter()
+        r_ms, r_n = ctx.profile_read(pv3d.STAGE["raster"])
+        t_ms, t_n = ctx.profile_read(pv3d.STAGE["sample_test"])
+        ctx.profile_enable(0)
+        r_avg = r_ms * 1e-3 / max(r_n, 1)
+        mb = 4 * w.map_n * w.map_n
+        mat = {"year_seconds": (m1 - m0) * (4379.0 / n_sun), "identical_energy": bool(
+                   np.array_equal(mres.energy.cpu().numpy(), res.energy.cpu().numpy())),
+               "raster_avg_us": r_avg * 1e6, "sample_test_avg_us": t_ms * 1e3 / max(t_n, 1),
+               "raster_roofline": {"bound": "hbm", "achieved": mb / r_avg / 1e9, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": mb / r_avg / 1e9 / HBM_PEAK_GBS,
+                                   "bytes_per_launch": mb}}
+        print(f"[bench] materialised route: {m1 - m0:.3f} s", file=sys.stderr, flush=True)
     path_bytes = algorithmic_bytes(w) * n_sun
     line = {
         "metric": "sample x sun shadow tests/s (+ triangles rasterized/s)",
@@ -177,6 +236,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.note}; {n_sun} suns per step, plain per-sun launch loop",
+                   "route": a.route,
                    "triangles": w.n_tri_submitted, "cells": w.gen.n_cells, "samples_per_sun": w.n_samples,
                    "suns": n_sun, "map_n": w.map_n, "k": w.k},
         "triangles_per_s": tris / sec_per_step,
@@ -184,10 +244,14 @@ def main():
         "path_hbm_roofline": {"algorithmic_bytes_per_sun": algorithmic_bytes(w),
                               "achieved_GBs": path_bytes / sec_per_step / 1e9,
                               "frac": path_bytes / sec_per_step / 1e9 / HBM_PEAK_GBS},
-        "roofline": {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": None, "avg_launch_us": avg_s * 1e6, "launches": k_n,
-                     "bytes_per_launch": unit_bytes},
+        "roofline": {"kernel": dominant, "bound": bound, "achieved": achieved, "peak": peak,
+                     "unit": unit, "frac": (achieved / peak) if achieved else None,
+                     "traffic": measured_traffic(dominant, a.route), "avg_launch_us": avg_s * 1e6, "launches": k_n,
+                     "units_per_launch": units,
+                     "model": ("88 lane-ops per sample (FP64 light-space map, floors, two covering surfaces' "
+                               "edge and depth evaluations)" if bound == "alu" else "algorithmic bytes")},
+        "route": a.route,
+        "materialised_route": mat,
         "stage_avg_us": {k: round(v["avg_us"], 3) for k, v in stage_ms.items()},
         "energy_loss": loss,
     }
