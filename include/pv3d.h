@@ -122,7 +122,11 @@ typedef struct {
     int32_t k;         /* k x k sample points per cell (Sec. 2 Step 3 uses 3 x 3) */
     uint32_t flags;    /* PV3D_EXPORT_* */
     int32_t tile;      /* raster tile edge in texels: 0 = library's choice (64 up to map_n
-                          4096, else 128), else 32/64/128 */
+                          4096, else 128; 64 in the batched form), else 32/64/128
+                          (batched form: 32/64) */
+    int32_t bin_limit; /* a triangle overlapping more tiles than this is not binned; every
+                          tile checks it instead. 0 = library's choice (256), else 1..256 */
+    int32_t reserved;  /* must be 0 */
 } pv3d_params;
 
 /* Outputs (all optional except power, power_ref, energy):
@@ -176,12 +180,51 @@ typedef struct {
     pv3d_outputs out;
 } pv3d_job;
 
-/* All suns of all jobs in one persistent launch: workgroups pull (job, sun)
- * items from a device queue, so uneven scenes balance across the GPU. Results
- * are identical to pv3d_evaluate on each job. EXPORT flags are not accepted
- * here (EINVAL). */
+/* All suns above the horizon of all jobs in one persistent launch (per job,
+ * two small preparation launches come first: the scene's bounding sphere and
+ * the sample tables). Workgroups take units of work (a sun's set-up, a range
+ * of triangles, the bin scan, a range of bin entries, a tile, the sun's
+ * losses) from per-slot queues in device memory; a slot holds one (job, sun)
+ * item at a time and takes the next item when its sun is done, so uneven
+ * scenes share the GPU without a return to the host. Per job, results
+ * (counts, powers, energy) are identical to pv3d_evaluate with the same
+ * params. flags may be 0 or PV3D_FULL_RASTER (EINVAL otherwise); tile is 0,
+ * 32 or 64. A sun whose set-up records or bin entries exceed the slot's
+ * capacity is evaluated again with the per-sun path after the launch, so the
+ * result does not depend on the capacity. Returns when every job's outputs
+ * are in place (the call synchronizes hip_stream). ENOMEM when the slots do
+ * not fit the budget. */
 pv3d_status pv3d_evaluate_batched(pv3d_ctx* ctx, const pv3d_job* jobs, int64_t n_jobs,
                                   void* hip_stream);
+
+/* Autotuner of the batched form: times every candidate (tile edge 32 or 64 x
+ * bin_limit 16, 64 or 256) on up to n_probe of the job's suns above the
+ * horizon (evenly spaced), through the persistent launch, and writes the
+ * fastest into job->params.tile and job->params.bin_limit. Every candidate
+ * gives identical results; only time differs. best_ms_out (may be NULL)
+ * receives the winner's time for the probe suns. The job's outputs are
+ * not written. */
+pv3d_status pv3d_autotune(pv3d_ctx* ctx, pv3d_job* job, int32_t n_probe, double* best_ms_out);
+
+/* Memory and placement of the batched form: at most max_slots (item) slots
+ * in flight, each with room for slot_records triangle set-up records (and 8
+ * bin entries per record); 0 = library's choice (128 slots, 2^20 records). A
+ * smaller budget per slot only sends more suns to the per-sun path. By
+ * default each slot is served by the workgroups of one XCD (slot i by XCD
+ * i % 8, when the device shows 8 XCD ids), so the slot's buffers stay in that
+ * XCD's L2; PV3D_BATCH_ANY_XCD lets every XCD serve every slot. Results are
+ * the same either way. EINVAL: negative values, max_slots above 4096, unknown
+ * flags. */
+#define PV3D_BATCH_ANY_XCD 1u
+pv3d_status pv3d_batch_limits(pv3d_ctx* ctx, int32_t max_slots, int64_t slot_records, uint32_t flags);
+
+/* Statistics of the last pv3d_evaluate_batched or pv3d_autotune launch:
+ * out[0] items (suns) run, out[1] work units run, out[2] items evaluated
+ * again with the per-sun path (capacity exceeded), out[3] workgroups of the
+ * persistent launch, out[4] slots, out[5] elapsed microseconds of the
+ * persistent launch (HIP events), out[6] XCD groups (8: slots served per
+ * XCD, 1: by every XCD). */
+pv3d_status pv3d_batch_stats(pv3d_ctx* ctx, int64_t out[7]);
 
 /* Serving: submit a job to the context's running service loop. It is
  * admitted when its working set fits the HBM budget, then its suns join the

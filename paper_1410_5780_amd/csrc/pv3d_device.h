@@ -104,6 +104,100 @@ struct SceneDev {
     int64_t n_vert, n_tri;
 };
 
+// ---- persistent launch: every (job, sun) item of a batch in one launch ----
+// Phases of one item, in order; a phase is split into units that any
+// workgroup may take.
+enum : int32_t {
+    kPhIdle = 0,      // slot holds no item
+    kPhSetup = 1,     // 1 unit: view, module terms, tile mask
+    kPhTri = 2,       // a unit per kTriPerUnit triangles (and modules): set-up and tile counts
+    kPhScan = 3,      // 1 unit: scan of the tile counts, list of non-empty tiles, capacity check
+    kPhScatter = 4,   // a unit per kScatterPerUnit records: bins
+    kPhTile = 5,      // a unit per listed tile: raster and sample depth check
+    kPhLoss = 6,      // 1 unit: string powers of the sun
+};
+constexpr int32_t kTriPerUnit = 1024;
+constexpr int32_t kScatterPerUnit = 2048;
+
+// One job as the persistent kernel sees it (device pointers).
+struct PJob {
+    SceneDev sc;
+    GenDev g;
+    const double* sun;       // [n_sun][3]
+    const double* dni;       // [n_sun]
+    const double* dpoa;      // [n_sun]
+    uint32_t* counts;        // [n_sun][cells], zero beforehand
+    double* power;           // [n_sun], zero beforehand (suns below the horizon stay zero)
+    double* power_ref;       // [n_sun]
+    double* energy;          // [2]
+    const double* dt;        // [n_sun]
+    const double* sphere;    // scene bounding sphere (centre, radius)
+    const double* fu;        // sample tables
+    const double* fv;
+    int64_t n_sun, cells;
+    int32_t n, k, tile, sparse, use_mask, large_tiles, ntx, n_tiles, words, n_items;
+};
+
+// (job, sun) of one item; the items of a job are consecutive.
+struct PItem {
+    int32_t job, sun;
+};
+
+// Work buffers of one slot (the item it holds).
+struct PSlotBufs {
+    TriRec* rec;
+    int32_t* large;
+    int32_t* bins;
+    int32_t* tile_count;     // zero between items
+    int32_t* tile_start;
+    int32_t* tile_cursor;
+    int32_t* tile_list;      // non-empty tiles of the item
+    int4* modbox;
+    View* view;
+    double* beam;
+    int32_t* bias;
+    uint32_t* tmask;
+    SunCounters* ctr;
+};
+
+// Queue state of one slot, alone in a 128-byte line. word packs the phase
+// (bits 56-63), its unit count (bits 32-55) and the next unit to hand out
+// (bits 0-31): a workgroup takes a unit with one atomic add and knows from
+// the value it got which phase the unit belongs to.
+struct alignas(128) PSlotState {
+    unsigned long long word;
+    uint32_t done;           // units of the current phase completed
+    int32_t item;            // item held
+    int32_t n_list;          // tiles listed by the scan
+    int32_t overflow;        // 1: a capacity was exceeded, the host evaluates the sun again
+    int32_t pad[26];
+};
+static_assert(sizeof(PSlotState) == 128, "PSlotState layout");
+
+struct PSched {
+    uint32_t next_item;          // next item to admit
+    uint32_t items_done;
+    uint32_t n_items;
+    uint32_t abort;              // 1: the watchdog saw no progress; every workgroup leaves
+    unsigned long long units;    // units completed (statistics, watchdog progress)
+    uint32_t n_overflow;         // items listed in overflow_items
+    uint32_t pad;
+};
+
+struct PLaunch {
+    const PJob* jobs;
+    const PItem* items;
+    const PSlotBufs* slots;
+    PSlotState* state;
+    PSched* sched;
+    uint32_t* job_done;          // [n_jobs] items finished
+    int32_t* job_overflow;       // [n_jobs] 1: an item was left to the host
+    int32_t* overflow_items;     // [n_items]
+    int32_t n_slots, rec_cap, bin_cap;
+    int32_t groups;              // 8: slot i is served by the XCD whose id is i % 8; 1: by every XCD
+    long long stall_ticks;       // wall-clock ticks without progress before the watchdog fires
+};
+
 // ---- launch wrappers (pv3d_kernels.hip) -----------------------------------
 hipError_t launch_module_normals(Module* mods, int32_t n_mod, hipStream_t st);
 hipError_t launch_bounds(const SceneDev& sc, const GenDev& g, double* partial, int32_t n_part,
@@ -136,5 +230,8 @@ hipError_t launch_loss(int64_t n_sun, const double* sun, const double* beam, con
 hipError_t launch_energy(int64_t n_sun, const double* power, const double* power_ref,
                          const double* dt, double* energy, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+hipError_t persist_blocks_per_cu(int32_t* blocks);
+hipError_t launch_xcc_probe(uint32_t* mask, int32_t grid, hipStream_t st);
+hipError_t launch_persist(const PLaunch& P, int32_t grid, hipStream_t st);
 
 }  // namespace pv3d

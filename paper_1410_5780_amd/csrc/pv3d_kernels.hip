@@ -46,6 +46,13 @@ __device__ __forceinline__ d3 cross(d3 a, d3 b) {
 __device__ __forceinline__ d3 add(d3 a, d3 b) { return d3{a.x + b.x, a.y + b.y, a.z + b.z}; }
 
 __device__ __forceinline__ int64_t floor_shift(int64_t a, int s) { return a >> s; }  // arithmetic
+
+// Load of a word that other workgroups of the same launch update with
+// atomics: read at the device's coherence point, not from a cached copy.
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T* p) {
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 // ---------------------------------------------------------------------------
 // generator preparation
 // ---------------------------------------------------------------------------
@@ -157,16 +164,24 @@ __device__ TileBox module_box(const View& V, const Module& M, int32_t n, int32_t
 
 constexpr int kMaxMaskWords = 512;   // up to 16384 tiles per sun
 
-__global__ __launch_bounds__(256) void k_setup(const double* sun, const double* dni, GenDev g,
-                                               const double* sphere, int32_t n, View* views,
-                                               double* beam, int32_t* bias, TileGrid tg, uint32_t* tmask) {
-    __shared__ double red[5][256];
-    __shared__ int any_front;
-    __shared__ View sv;
-    __shared__ uint32_t mask[kMaxMaskWords];
-    const int64_t s = blockIdx.x;
+struct SetupLds {
+    double red[5][256];
+    View sv;
+    uint32_t mask[kMaxMaskWords];
+    int any_front;
+};
+
+// One sun: sun3 is its unit vector, dn its DNI; view, beam_s, bias_s and
+// tmask_s receive this sun's view, per-module beam and bias, and tile mask.
+__device__ void setup_body(SetupLds& L, const double* sun3, double dn, const GenDev& g, const double* sphere,
+                           int32_t n, View* view, double* beam_s, int32_t* bias_s, const TileGrid& tg,
+                           uint32_t* tmask_s) {
+    auto& red = L.red;
+    auto& any_front = L.any_front;
+    auto& sv = L.sv;
+    auto& mask = L.mask;
     const int tid = threadIdx.x;
-    const d3 sn = ld3(sun + 3 * s);
+    const d3 sn = ld3(sun3);
     const bool up = sn.z > 0.0;
     if (tid == 0) any_front = 0;
     for (int q = tid; q < tg.words; q += 256) mask[q] = 0;
@@ -224,10 +239,9 @@ __global__ __launch_bounds__(256) void k_setup(const double* sun, const double* 
             }
         }
         sv = V;
-        views[s] = V;
+        *view = V;
     }
     __syncthreads();
-    const double dn = dni[s];
     for (int m = tid; m < g.n_mod; m += 256) {
         d3 nh = ld3(g.mods[m].n);
         double cm = dot(nh, sn);
@@ -244,9 +258,9 @@ __global__ __launch_bounds__(256) void k_setup(const double* sun, const double* 
                 bi = (int32_t)b;
             }
         }
-        beam[s * g.n_mod + m] = bm;
-        bias[s * g.n_mod + m] = bi;
-        if (tmask && bi >= 0) {
+        beam_s[m] = bm;
+        bias_s[m] = bi;
+        if (tmask_s && bi >= 0) {
             const TileBox b = module_box(sv, g.mods[m], n, tg.tile);
             for (int32_t ty = b.y0; ty <= b.y1; ty++)
                 for (int32_t tx = b.x0; tx <= b.x1; tx++) {
@@ -255,10 +269,19 @@ __global__ __launch_bounds__(256) void k_setup(const double* sun, const double* 
                 }
         }
     }
-    if (tmask) {
+    if (tmask_s) {
         __syncthreads();
-        for (int q = tid; q < tg.words; q += 256) tmask[s * tg.words + q] = mask[q];
+        for (int q = tid; q < tg.words; q += 256) tmask_s[q] = mask[q];
     }
+}
+
+__global__ __launch_bounds__(256) void k_setup(const double* sun, const double* dni, GenDev g,
+                                               const double* sphere, int32_t n, View* views,
+                                               double* beam, int32_t* bias, TileGrid tg, uint32_t* tmask) {
+    __shared__ SetupLds L;
+    const int64_t s = blockIdx.x;
+    setup_body(L, sun + 3 * s, dni[s], g, sphere, n, views + s, beam + s * g.n_mod, bias + s * g.n_mod, tg,
+               tmask ? tmask + s * tg.words : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -468,95 +491,133 @@ __device__ __noinline__ void clip_and_emit(d3 t0, d3 t1, d3 t2, int32_t n, BinBu
     }
 }
 
-// One thread per scene triangle, module triangle and module: set-up, then
-// per-tile counts accumulated in LDS and added to the global counts once.
+// One thread per scene triangle, module triangle and module of [t0, t1)
+// (t0 a multiple of 256; 256 at a time): set-up, then per-tile counts
+// accumulated in LDS (cnt, n_tiles words) and added to the global counts
+// once; with cnt == nullptr every pair goes straight to the global counts.
+__device__ void tri_setup_body(uint32_t* cnt, int64_t t0, int64_t t1, const View& V, const SceneDev& sc,
+                               const GenDev& g, const int32_t* bias_s, int32_t n, const BinBuffers& bb,
+                               SunCounters* ctr_s, const uint32_t* tmask_s) {
+    const int64_t n_tri_all = sc.n_tri + (g.occluders ? 2 * (int64_t)g.n_mod : 0);
+    const int lane = threadIdx.x & 63;
+    if (!V.valid) {                                   // nothing is drawn or tested for this sun
+        for (int64_t t = t0 + threadIdx.x; t < t1; t += 256)
+            if (t >= n_tri_all && t < n_tri_all + g.n_mod) bb.modbox[t - n_tri_all] = make_int4(1, 0, 1, 0);
+        return;
+    }
+    uint32_t* gcnt = reinterpret_cast<uint32_t*>(bb.tile_count);
+    if (cnt) {
+        for (int32_t q = threadIdx.x; q < bb.n_tiles; q += 256) cnt[q] = 0;
+        __syncthreads();
+    }
+    uint32_t* sink = cnt ? cnt : gcnt;
+    for (int64_t tb = t0; tb < t1; tb += 256) {
+        const int64_t t = tb + threadIdx.x;
+        TileBox box{1, 0, 1, 0};
+        int32_t kind = 0;
+        Edges E;
+        for (int e = 0; e < 3; e++) { E.e0[e] = 0; E.a[e] = 0; E.b[e] = 0; }
+        E.ilo = E.ihi = E.jlo = E.jhi = 0;
+        if (t < t1 && t < n_tri_all) {
+            d3 c[3];
+            if (t < sc.n_tri) {
+                for (int q = 0; q < 3; q++) c[q] = ld3(sc.xyz + 3 * (int64_t)sc.tri[3 * t + q]);
+            } else {
+                int64_t mt = t - sc.n_tri;
+                const Module& M = g.mods[mt / 2];
+                module_corner(M, 0, c[0]);
+                if ((mt & 1) == 0) { module_corner(M, 1, c[1]); module_corner(M, 2, c[2]); }
+                else { module_corner(M, 2, c[1]); module_corner(M, 3, c[2]); }
+            }
+            d3 l[3];
+            for (int q = 0; q < 3; q++) l[q] = to_light(V, c[q]);
+            double zmin = fmin(l[0].z, fmin(l[1].z, l[2].z));
+            double xmin = fmin(l[0].x, fmin(l[1].x, l[2].x)), xmax = fmax(l[0].x, fmax(l[1].x, l[2].x));
+            double ymin = fmin(l[0].y, fmin(l[1].y, l[2].y)), ymax = fmax(l[0].y, fmax(l[1].y, l[2].y));
+            bool keep = !(zmin > (double)kDepthMax) && !(xmax < 0.0 || xmin >= (double)n || ymax < 0.0 || ymin >= (double)n);
+            if (keep) {
+                bool big = false;
+                for (int q = 0; q < 3; q++)
+                    if (fabs(l[q].x) >= kGuard || fabs(l[q].y) >= kGuard) big = true;
+                if (big) {
+                    clip_and_emit(l[0], l[1], l[2], n, bb, ctr_s, sink, tmask_s);
+                } else {
+                    bool large = false;
+                    if (emit_triangle(l, n, bb, ctr_s, E, large) >= 0 && !large) {
+                        box = rec_box(E.ilo, E.ihi, E.jlo, E.jhi, bb.tile);
+                        kind = 1;
+                    }
+                }
+            }
+        } else if (t < t1 && t < n_tri_all + g.n_mod) {
+            const int32_t m = (int32_t)(t - n_tri_all);
+            TileBox b{1, 0, 1, 0};
+            if (bias_s[m] >= 0) b = module_box(V, g.mods[m], n, bb.tile);
+            bb.modbox[m] = make_int4(b.x0, b.x1, b.y0, b.y1);
+            if (b.count() > 0) { box = b; kind = 2; }
+        }
+        wave_pairs(box, kind, E, 0, lane, bb.tile, bb.ntx, tmask_s, [&](int32_t tq, int32_t) { atomicAdd(&sink[tq], 1u); });
+    }
+    if (cnt) {
+        __syncthreads();
+        for (int32_t q = threadIdx.x; q < bb.n_tiles; q += 256)
+            if (cnt[q]) atomicAdd(&gcnt[q], cnt[q]);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_tri_setup(int64_t s, const View* views, SceneDev sc, GenDev g,
                                                    const int32_t* bias, int32_t n, BinBuffers bb,
                                                    SunCounters* ctr, const uint32_t* tmask) {
     extern __shared__ uint32_t cnt[];
-    const View& V = views[s];
-    const int64_t n_tri_all = sc.n_tri + (g.occluders ? 2 * (int64_t)g.n_mod : 0);
-    const int64_t t = blockIdx.x * 256ll + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    if (!V.valid) {                                   // nothing is drawn or tested for this sun
-        if (t >= n_tri_all && t < n_tri_all + g.n_mod) bb.modbox[t - n_tri_all] = make_int4(1, 0, 1, 0);
-        return;
-    }
-    for (int32_t q = threadIdx.x; q < bb.n_tiles; q += 256) cnt[q] = 0;
-    __syncthreads();
-    TileBox box{1, 0, 1, 0};
-    int32_t kind = 0;
-    Edges E;
-    for (int e = 0; e < 3; e++) { E.e0[e] = 0; E.a[e] = 0; E.b[e] = 0; }
-    E.ilo = E.ihi = E.jlo = E.jhi = 0;
-    if (t < n_tri_all) {
-        d3 c[3];
-        if (t < sc.n_tri) {
-            for (int q = 0; q < 3; q++) c[q] = ld3(sc.xyz + 3 * (int64_t)sc.tri[3 * t + q]);
-        } else {
-            int64_t mt = t - sc.n_tri;
-            const Module& M = g.mods[mt / 2];
-            module_corner(M, 0, c[0]);
-            if ((mt & 1) == 0) { module_corner(M, 1, c[1]); module_corner(M, 2, c[2]); }
-            else { module_corner(M, 2, c[1]); module_corner(M, 3, c[2]); }
-        }
-        d3 l[3];
-        for (int q = 0; q < 3; q++) l[q] = to_light(V, c[q]);
-        double zmin = fmin(l[0].z, fmin(l[1].z, l[2].z));
-        double xmin = fmin(l[0].x, fmin(l[1].x, l[2].x)), xmax = fmax(l[0].x, fmax(l[1].x, l[2].x));
-        double ymin = fmin(l[0].y, fmin(l[1].y, l[2].y)), ymax = fmax(l[0].y, fmax(l[1].y, l[2].y));
-        bool keep = !(zmin > (double)kDepthMax) && !(xmax < 0.0 || xmin >= (double)n || ymax < 0.0 || ymin >= (double)n);
-        if (keep) {
-            bool big = false;
-            for (int q = 0; q < 3; q++)
-                if (fabs(l[q].x) >= kGuard || fabs(l[q].y) >= kGuard) big = true;
-            if (big) {
-                clip_and_emit(l[0], l[1], l[2], n, bb, ctr, cnt, tmask);
-            } else {
-                bool large = false;
-                if (emit_triangle(l, n, bb, ctr, E, large) >= 0 && !large) {
-                    box = rec_box(E.ilo, E.ihi, E.jlo, E.jhi, bb.tile);
-                    kind = 1;
-                }
-            }
-        }
-    } else if (t < n_tri_all + g.n_mod) {
-        const int32_t m = (int32_t)(t - n_tri_all);
-        TileBox b{1, 0, 1, 0};
-        if (bias[s * g.n_mod + m] >= 0) b = module_box(V, g.mods[m], n, bb.tile);
-        bb.modbox[m] = make_int4(b.x0, b.x1, b.y0, b.y1);
-        if (b.count() > 0) { box = b; kind = 2; }
-    }
-    wave_pairs(box, kind, E, 0, lane, bb.tile, bb.ntx, tmask, [&](int32_t tq, int32_t) { atomicAdd(&cnt[tq], 1u); });
-    __syncthreads();
-    for (int32_t q = threadIdx.x; q < bb.n_tiles; q += 256)
-        if (cnt[q]) atomicAdd(&bb.tile_count[q], (int32_t)cnt[q]);
+    const int64_t total = sc.n_tri + (g.occluders ? 2 * (int64_t)g.n_mod : 0) + g.n_mod;
+    const int64_t t0 = blockIdx.x * 256ll;
+    tri_setup_body(cnt, t0, min(t0 + 256, total), views[s], sc, g, bias + s * g.n_mod, n, bb, ctr, tmask);
 }
 
-__global__ __launch_bounds__(1024) void k_bin_scan(int32_t n_tiles, BinBuffers bb) {
-    __shared__ int32_t part[1024];
+// Exclusive scan of the tile counts by NT threads; every count is left at
+// zero for the next sun. With list != nullptr the tiles holding at least
+// one entry are also listed in tile order and their number returned
+// (thread 0 only).
+template <int NT, bool COHERENT>
+__device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& bb, int32_t* list) {
     const int tid = threadIdx.x;
-    const int32_t per = (n_tiles + 1023) / 1024;
+    const int32_t per = (n_tiles + NT - 1) / NT;
     const int32_t b0 = min(tid * per, n_tiles), b1 = min(b0 + per, n_tiles);
-    int32_t sum = 0;
-    for (int32_t i = b0; i < b1; i++) sum += bb.tile_count[i];
+    int32_t sum = 0, nz = 0;
+    for (int32_t i = b0; i < b1; i++) {
+        const int32_t c = COHERENT ? ld_dev(bb.tile_count + i) : bb.tile_count[i];
+        sum += c;
+        nz += c > 0 ? 1 : 0;
+    }
     part[tid] = sum;
+    part[NT + tid] = nz;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {     // inclusive Hillis-Steele scan
-        int32_t v = tid >= off ? part[tid - off] : 0;
+    for (int off = 1; off < NT; off <<= 1) {       // inclusive Hillis-Steele scans
+        const int32_t v = tid >= off ? part[tid - off] : 0;
+        const int32_t w = tid >= off ? part[NT + tid - off] : 0;
         __syncthreads();
         part[tid] += v;
+        part[NT + tid] += w;
         __syncthreads();
     }
-    int32_t run = part[tid] - sum;
+    int32_t run = part[tid] - sum, lpos = part[NT + tid] - nz;
     for (int32_t i = b0; i < b1; i++) {
-        int32_t c = bb.tile_count[i];
+        const int32_t c = COHERENT ? ld_dev(bb.tile_count + i) : bb.tile_count[i];
         bb.tile_start[i] = run;
         bb.tile_cursor[i] = run;
         bb.tile_count[i] = 0;
+        if (list && c > 0) list[lpos++] = i;
         run += c;
     }
-    if (tid == 1023) bb.tile_start[n_tiles] = part[1023];
+    if (tid == NT - 1) bb.tile_start[n_tiles] = part[NT - 1];
+    const int32_t n_list = part[2 * NT - 1];
+    __syncthreads();
+    return n_list;
+}
+
+__global__ __launch_bounds__(1024) void k_bin_scan(int32_t n_tiles, BinBuffers bb) {
+    __shared__ int32_t part[2 * 1024];
+    scan_body<1024, false>(part, n_tiles, bb, nullptr);
 }
 
 // Item of the scatter: a binned triangle record (kind 1) or a module (kind 2).
@@ -583,21 +644,35 @@ __device__ __forceinline__ void scatter_item(int32_t item, int32_t n_rec, int32_
     if (box.count() > 0) kind = 2;
 }
 
-// A contiguous range of items per workgroup: count per tile in LDS, take one
-// block of bin slots per (workgroup, tile) with a single global atomic, then
-// place every (item, tile) pair at its LDS-assigned rank inside that block.
-// The pair filter is the one k_tri_setup counted with.
-__global__ __launch_bounds__(256) void k_bin_scatter(int64_t s, BinBuffers bb, int32_t n_mod, SunCounters* ctr,
-                                                     const uint32_t* tmask) {
-    extern __shared__ uint32_t lds[];
-    uint32_t* cnt = lds;                 // per-tile count, then running rank
-    uint32_t* base = lds + bb.n_tiles;   // per-tile first bin slot of this workgroup
+// A contiguous range of items per unit (unit u of n_units): count per tile
+// in LDS, take one block of bin slots per (unit, tile) with a single global
+// atomic, then place every (item, tile) pair at its LDS-assigned rank inside
+// that block. The pair filter is the one the triangle set-up counted with.
+// With lds == nullptr every pair takes its slot with its own global atomic.
+__device__ void scatter_body(uint32_t* lds, int32_t unit, int32_t n_units, const BinBuffers& bb, int32_t n_mod,
+                             int32_t n_rec_all, SunCounters* ctr_s, const uint32_t* tmask_s) {
     const int lane = threadIdx.x & 63;
-    const int32_t n_rec = min(ctr[s].n_rec, bb.rec_cap);
+    const int32_t n_rec = min(n_rec_all, bb.rec_cap);
     const int32_t total = n_rec + n_mod;
-    const int32_t per = (total + (int32_t)gridDim.x - 1) / (int32_t)gridDim.x;
-    const int32_t i0 = blockIdx.x * per, i1 = min(i0 + per, total);
+    const int32_t per = (total + n_units - 1) / n_units;
+    const int32_t i0 = unit * per, i1 = min(i0 + per, total);
     if (i0 >= i1) return;
+    if (!lds) {
+        for (int32_t it0 = i0; it0 < i1; it0 += 256) {
+            TileBox box;
+            int32_t kind, id;
+            Edges E;
+            scatter_item(it0 + (int32_t)threadIdx.x, n_rec, i1, bb, box, kind, E, id);
+            wave_pairs(box, kind, E, id, lane, bb.tile, bb.ntx, tmask_s, [&](int32_t tq, int32_t oid) {
+                const uint32_t pos = (uint32_t)atomicAdd(&bb.tile_cursor[tq], 1);
+                if (pos < (uint32_t)bb.bin_cap) bb.bins[pos] = oid;
+                else atomicOr(&ctr_s->overflow, 1);
+            });
+        }
+        return;
+    }
+    uint32_t* cnt = lds;                 // per-tile count, then running rank
+    uint32_t* base = lds + bb.n_tiles;   // per-tile first bin slot of this unit
     for (int32_t q = threadIdx.x; q < bb.n_tiles; q += 256) cnt[q] = 0;
     __syncthreads();
     for (int32_t it0 = i0; it0 < i1; it0 += 256) {
@@ -605,7 +680,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(int64_t s, BinBuffers bb, i
         int32_t kind, id;
         Edges E;
         scatter_item(it0 + (int32_t)threadIdx.x, n_rec, i1, bb, box, kind, E, id);
-        wave_pairs(box, kind, E, id, lane, bb.tile, bb.ntx, tmask, [&](int32_t tq, int32_t) { atomicAdd(&cnt[tq], 1u); });
+        wave_pairs(box, kind, E, id, lane, bb.tile, bb.ntx, tmask_s, [&](int32_t tq, int32_t) { atomicAdd(&cnt[tq], 1u); });
     }
     __syncthreads();
     for (int32_t q = threadIdx.x; q < bb.n_tiles; q += 256) {
@@ -619,12 +694,18 @@ __global__ __launch_bounds__(256) void k_bin_scatter(int64_t s, BinBuffers bb, i
         int32_t kind, id;
         Edges E;
         scatter_item(it0 + (int32_t)threadIdx.x, n_rec, i1, bb, box, kind, E, id);
-        wave_pairs(box, kind, E, id, lane, bb.tile, bb.ntx, tmask, [&](int32_t tq, int32_t oid) {
+        wave_pairs(box, kind, E, id, lane, bb.tile, bb.ntx, tmask_s, [&](int32_t tq, int32_t oid) {
             const uint32_t pos = base[tq] + atomicAdd(&cnt[tq], 1u);
             if (pos < (uint32_t)bb.bin_cap) bb.bins[pos] = oid;
-            else atomicOr(&ctr[s].overflow, 1);
+            else atomicOr(&ctr_s->overflow, 1);
         });
     }
+}
+
+__global__ __launch_bounds__(256) void k_bin_scatter(int64_t s, BinBuffers bb, int32_t n_mod, SunCounters* ctr,
+                                                     const uint32_t* tmask) {
+    extern __shared__ uint32_t lds[];
+    scatter_body(lds, blockIdx.x, gridDim.x, bb, n_mod, ctr[s].n_rec, ctr + s, tmask);
 }
 
 // ---------------------------------------------------------------------------
@@ -641,7 +722,6 @@ constexpr int kMaxCellCounters = 256;   // per-wave cell counters of the full ro
 constexpr int kMaxTileCells = 1024;     // (module slot, cell) counters of the sparse route
 
 struct TileCtx {
-    int64_t s;
     int32_t x0, y0, n, bs, be, n_large;
 };
 
@@ -918,7 +998,7 @@ __device__ void samples_full(const uint32_t* zt, const int32_t* mods, int32_t nm
         } else {
             m = mods[mi];
         }
-        const int32_t bm = bias[c.s * g.n_mod + m];
+        const int32_t bm = bias[m];
         if (bm < 0) continue;
         ModMap mm;
         module_map(V, g.mods[m], mm);
@@ -1014,7 +1094,7 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
     int32_t my_max = INT32_MIN;
     for (int32_t mi = wv; mi < n_mods; mi += 4) {
         const int32_t m = mods[mi];
-        const int32_t bm = bias[c.s * g.n_mod + m];
+        const int32_t bm = bias[m];
         if (bm < 0) continue;
         ModMap mm;
         module_map(V, g.mods[m], mm);
@@ -1189,32 +1269,51 @@ constexpr int kMinRect = 16;
 constexpr int kMaxRects = 64;
 
 template <int TS, int CAP>
-__global__ __launch_bounds__(256) void k_tile(int64_t s, const View* views, BinBuffers bb, const SunCounters* ctr,
-                                              int32_t n, GenDev g, const int32_t* bias, const double* fu_tab,
-                                              const double* fv_tab, int32_t k, TileOut out, int32_t sparse,
-                                              const uint32_t* tmask) {
+struct TileLds {
+    static constexpr int PITCH = TS + 8;
+    static constexpr int ZT_BYTES = TS * PITCH * 4;
+    static constexpr int SP_BYTES = CAP * (2 + 4 + 4 + 4 + 2);
+    static constexpr int POOL = ZT_BYTES > SP_BYTES ? ZT_BYTES : SP_BYTES;
+    __attribute__((aligned(16))) unsigned char pool[POOL];
+    int32_t mods[kMaxTileMods];
+    uint32_t cells[kMaxTileCells > 4 * kMaxCellCounters ? kMaxTileCells : 4 * kMaxCellCounters];
+    int32_t rowstart[TS + 1];
+    Rect todo[kMaxRects], failed[kMaxRects];
+    TriSlot tslots[kTriChunk];
+    int32_t tcnt[64];
+    uint8_t tlist[64 * kStampList];
+    int32_t next, n_mods, mods_overflow, n_todo, n_failed;
+    SparseShared sh;
+};
+
+// One tile of one sun. V, bias_s and n_large are this sun's view, module
+// biases and count of unbinned triangles.
+template <int TS, int CAP>
+__device__ void tile_body(TileLds<TS, CAP>& L, int32_t tile, const View& V, const BinBuffers& bb, int32_t n_large,
+                          int32_t n, const GenDev& g, const int32_t* bias, const double* fu_tab,
+                          const double* fv_tab, int32_t k, const TileOut& out, int32_t sparse,
+                          const uint32_t* tmask) {
     constexpr int PITCH = TS + 8;
-    constexpr int ZT_BYTES = TS * PITCH * 4;
-    constexpr int SP_BYTES = CAP * (2 + 4 + 4 + 4 + 2);
-    constexpr int POOL = ZT_BYTES > SP_BYTES ? ZT_BYTES : SP_BYTES;
-    __shared__ __attribute__((aligned(16))) unsigned char pool[POOL];
-    __shared__ int32_t mods[kMaxTileMods];
-    __shared__ uint32_t cells[kMaxTileCells > 4 * kMaxCellCounters ? kMaxTileCells : 4 * kMaxCellCounters];
-    __shared__ int32_t rowstart[TS + 1];
-    __shared__ Rect todo[kMaxRects], failed[kMaxRects];
-    __shared__ TriSlot tslots[kTriChunk];
-    __shared__ int32_t tcnt[64];
-    __shared__ uint8_t tlist[64 * kStampList];
-    __shared__ int32_t next, n_mods, mods_overflow, n_todo, n_failed;
-    __shared__ SparseShared sh;
+    auto& pool = L.pool;
+    auto& mods = L.mods;
+    auto& cells = L.cells;
+    auto& rowstart = L.rowstart;
+    auto& todo = L.todo;
+    auto& failed = L.failed;
+    auto& tslots = L.tslots;
+    auto& tcnt = L.tcnt;
+    auto& tlist = L.tlist;
+    auto& next = L.next;
+    auto& n_mods = L.n_mods;
+    auto& mods_overflow = L.mods_overflow;
+    auto& n_todo = L.n_todo;
+    auto& n_failed = L.n_failed;
+    auto& sh = L.sh;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int32_t tile = blockIdx.x;
     TileCtx c;
-    c.s = s;
     c.n = n;
     c.x0 = (tile % bb.ntx) * TS;
     c.y0 = (tile / bb.ntx) * TS;
-    const View& V = views[s];
     uint32_t* zt = reinterpret_cast<uint32_t*>(pool);
     if (V.valid && !out.map && !mask_has(tmask, tile)) return;   // no sample can fall in this tile
     if (!V.valid) {
@@ -1228,7 +1327,7 @@ __global__ __launch_bounds__(256) void k_tile(int64_t s, const View* views, BinB
     }
     c.bs = min(bb.tile_start[tile], bb.bin_cap);
     c.be = min(bb.tile_start[tile + 1], bb.bin_cap);
-    c.n_large = ctr[s].n_large;
+    c.n_large = n_large;
     if (tid == 0) { next = 0; n_mods = 0; mods_overflow = 0; n_todo = 0; n_failed = 0; }
     __syncthreads();
     for (int32_t q = c.bs + tid; q < c.be; q += 256) {   // module entries of this tile
@@ -1302,6 +1401,16 @@ __global__ __launch_bounds__(256) void k_tile(int64_t s, const View* views, BinB
                          k, out, c, failed[f], lane, wv);
 }
 
+template <int TS, int CAP>
+__global__ __launch_bounds__(256) void k_tile(int64_t s, const View* views, BinBuffers bb, const SunCounters* ctr,
+                                              int32_t n, GenDev g, const int32_t* bias, const double* fu_tab,
+                                              const double* fv_tab, int32_t k, TileOut out, int32_t sparse,
+                                              const uint32_t* tmask) {
+    __shared__ TileLds<TS, CAP> L;
+    tile_body<TS, CAP>(L, blockIdx.x, views[s], bb, ctr[s].n_large, n, g, bias + s * g.n_mod, fu_tab, fv_tab, k,
+                       out, sparse, tmask);
+}
+
 // ---------------------------------------------------------------------------
 // depth check of the sub-cell samples (Fig. 4), one wave per cell
 // ---------------------------------------------------------------------------
@@ -1365,60 +1474,91 @@ __global__ __launch_bounds__(256) void k_sample_test(int64_t s, const View* view
 // ---------------------------------------------------------------------------
 constexpr int kMaxSubPerString = 4096;
 
-__global__ __launch_bounds__(256) void k_loss(const double* sun, const double* beam, const uint32_t* counts,
-                                              const double* d_poa, GenDev g, int32_t k, double* power,
-                                              double* power_ref) {
-    __shared__ double cap[kMaxSubPerString];
-    __shared__ double red[256];
-    const int64_t s = blockIdx.x;
-    const int tid = threadIdx.x;
-    if (!(sun[3 * s + 2] > 0.0)) {
-        if (tid == 0) { power[s] = 0.0; power_ref[s] = 0.0; }
+constexpr int kLossStrings = 1024;   // strings per chunk of the loss
+
+struct LossLds {
+    double cap[kMaxSubPerString];        // substring capacities of a chunk of whole strings
+    double best[kLossStrings];           // best operating point of each string of the chunk
+    int32_t chunk[2];                    // [first string, end string) of the chunk
+};
+
+// One sun: sun3 its unit vector, beam_s its per-module beam, counts_s its
+// per-cell shaded counts, dp its diffuse irradiance. Strings go in chunks
+// (consecutive whole strings, at most kMaxSubPerString substrings): every
+// substring capacity of the chunk at once, then one wave per string for its
+// best current, then the string powers added in string order.
+template <bool COHERENT>
+__device__ void loss_body(LossLds& L, const double* sun3, const double* beam_s, const uint32_t* counts_s, double dp,
+                          const GenDev& g, int32_t k, double* power_s, double* power_ref_s) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (!(sun3[2] > 0.0)) {
+        if (tid == 0) { *power_s = 0.0; *power_ref_s = 0.0; }
         return;
     }
     const int32_t cpm = g.n_cu * g.n_cv;
-    const int64_t n_cells = (int64_t)g.n_mod * cpm;
     const double kk = (double)(k * k);
-    const double dp = d_poa[s];
     double tot[2] = {0.0, 0.0};
-    for (int32_t st = 0; st < g.n_str; st++) {
-        const int32_t m0 = g.str_start[st], m1 = g.str_start[st + 1];
-        const int32_t nsub = (m1 - m0) * g.n_sub;
+    for (int32_t st0 = 0; st0 < g.n_str;) {
+        if (tid == 0) {
+            int32_t st1 = st0;
+            while (st1 < g.n_str && st1 - st0 < kLossStrings &&
+                   (g.str_start[st1 + 1] - g.str_start[st0]) * g.n_sub <= kMaxSubPerString)
+                st1++;
+            L.chunk[0] = st0;
+            L.chunk[1] = st1;
+        }
+        __syncthreads();
+        const int32_t st1 = L.chunk[1];
+        const int32_t p0 = g.str_start[st0];
+        const int32_t nq = (g.str_start[st1] - p0) * g.n_sub;
         for (int pass = 0; pass < 2; pass++) {
-            for (int32_t q = tid; q < nsub; q += 256) {
-                const int32_t m = g.str_mods[m0 + q / g.n_sub], sq = q % g.n_sub;
-                const double bm = beam[s * g.n_mod + m];
+            for (int32_t q = tid; q < nq; q += 256) {
+                const int32_t m = g.str_mods[p0 + q / g.n_sub], sq = q % g.n_sub;
+                const double bm = beam_s[m];
                 double cmin = INFINITY;
                 for (int32_t c = 0; c < cpm; c++) {
                     if (g.cell_sub[c] != sq) continue;
-                    const uint32_t sh = pass == 0 ? counts[s * n_cells + (int64_t)m * cpm + c] : 0u;
+                    const uint32_t sh = pass == 0 ? (COHERENT ? ld_dev(counts_s + (int64_t)m * cpm + c)
+                                                              : counts_s[(int64_t)m * cpm + c])
+                                                  : 0u;
                     const double f = (double)sh / kk;
                     cmin = fmin(cmin, bm * (1.0 - f) + dp);
                 }
-                cap[q] = cmin;
+                L.cap[q] = cmin;
             }
             __syncthreads();
-            double best = 0.0;
-            for (int32_t q = tid; q < nsub; q += 256) {
-                const double v = cap[q];
-                int32_t cnt = 0;
-                for (int32_t r = 0; r < nsub; r++) cnt += cap[r] >= v ? 1 : 0;
-                best = fmax(best, (double)cnt * v);
+            for (int32_t st = st0 + wv; st < st1; st += 4) {
+                const int32_t a = (g.str_start[st] - p0) * g.n_sub, b = (g.str_start[st + 1] - p0) * g.n_sub;
+                double best = 0.0;
+                for (int32_t q = a + lane; q < b; q += 64) {
+                    const double v = L.cap[q];
+                    int32_t cnt = 0;
+                    for (int32_t r = a; r < b; r++) cnt += L.cap[r] >= v ? 1 : 0;
+                    best = fmax(best, (double)cnt * v);
+                }
+                for (int off = 32; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off, 64));
+                if (lane == 0) L.best[st - st0] = best;
             }
-            red[tid] = best;
             __syncthreads();
-            for (int w = 128; w > 0; w >>= 1) {
-                if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
-                __syncthreads();
-            }
-            if (tid == 0) tot[pass] += red[0];
+            if (tid == 0)
+                for (int32_t st = st0; st < st1; st++) tot[pass] += L.best[st - st0];
             __syncthreads();
         }
+        st0 = st1;
     }
     if (tid == 0) {
-        power[s] = tot[0];
-        power_ref[s] = tot[1];
+        *power_s = tot[0];
+        *power_ref_s = tot[1];
     }
+}
+
+__global__ __launch_bounds__(256) void k_loss(const double* sun, const double* beam, const uint32_t* counts,
+                                              const double* d_poa, GenDev g, int32_t k, double* power,
+                                              double* power_ref) {
+    __shared__ LossLds L;
+    const int64_t s = blockIdx.x;
+    const int64_t n_cells = (int64_t)g.n_mod * g.n_cu * g.n_cv;
+    loss_body<false>(L, sun + 3 * s, beam + s * g.n_mod, counts + s * n_cells, d_poa[s], g, k, power + s, power_ref + s);
 }
 
 __global__ void k_energy(int64_t n_sun, const double* power, const double* power_ref, const double* dt,
@@ -1435,6 +1575,374 @@ __global__ void k_energy(int64_t n_sun, const double* power, const double* power
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
     for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// persistent launch: workgroups take units of (job, sun) items from per-slot
+// queues until every item is done. The units run the same bodies as the
+// per-sun kernels above, so results are the same.
+// ---------------------------------------------------------------------------
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+constexpr size_t kPLdsBytes = cmax(cmax(sizeof(TileLds<64, 2048>), sizeof(TileLds<32, 1024>)),
+                                   cmax(cmax(sizeof(SetupLds), sizeof(LossLds)), 2 * 256 * 4 + 1024 * 8));
+
+__device__ __forceinline__ unsigned long long pword(int32_t phase, int32_t n_units) {
+    return ((unsigned long long)(uint32_t)phase << 56) | ((unsigned long long)(uint32_t)n_units << 32);
+}
+__device__ __forceinline__ int32_t w_phase(unsigned long long w) { return (int32_t)(w >> 56); }
+__device__ __forceinline__ uint32_t w_units(unsigned long long w) { return (uint32_t)(w >> 32) & 0xFFFFFFu; }
+__device__ __forceinline__ uint32_t w_next(unsigned long long w) { return (uint32_t)w; }
+__device__ __forceinline__ bool w_open(unsigned long long w) { return w_phase(w) != kPhIdle && w_next(w) < w_units(w); }
+
+__device__ __forceinline__ BinBuffers slot_bins(const PLaunch& P, const PJob& J, const PSlotBufs& B) {
+    BinBuffers bb;
+    bb.rec = B.rec;
+    bb.rec_cap = P.rec_cap;
+    bb.large = B.large;
+    bb.tile_count = B.tile_count;
+    bb.tile_start = B.tile_start;
+    bb.tile_cursor = B.tile_cursor;
+    bb.bins = B.bins;
+    bb.modbox = B.modbox;
+    bb.bin_cap = P.bin_cap;
+    bb.tile = J.tile;
+    bb.ntx = J.ntx;
+    bb.n_tiles = J.n_tiles;
+    bb.large_tiles = J.large_tiles;
+    return bb;
+}
+
+// Each phase as a function of its own, so the persistent kernel needs the
+// registers of its largest phase, not of all phases inlined together.
+__device__ __noinline__ void unit_setup(unsigned char* raw, const PJob& J, const PItem it, const PSlotBufs& B) {
+    if (threadIdx.x == 0) {                // counters other units update with atomics
+        __hip_atomic_store(&B.ctr->n_rec, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&B.ctr->n_large, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&B.ctr->overflow, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const TileGrid tg{J.tile, J.ntx, J.n_tiles, J.words};
+    setup_body(*reinterpret_cast<SetupLds*>(raw), J.sun + 3 * it.sun, J.dni[it.sun], J.g, J.sphere, J.n, B.view,
+               B.beam, B.bias, tg, J.use_mask ? B.tmask : nullptr);
+}
+
+__device__ __noinline__ void unit_tri(unsigned char* raw, const PJob& J, const PSlotBufs& B, const BinBuffers& bb,
+                                      int32_t unit) {
+    const int64_t total = J.sc.n_tri + (J.g.occluders ? 2 * (int64_t)J.g.n_mod : 0) + J.g.n_mod;
+    const int64_t t0 = (int64_t)unit * kTriPerUnit;
+    uint32_t* cnt = 4 * (size_t)J.n_tiles <= kPLdsBytes ? reinterpret_cast<uint32_t*>(raw) : nullptr;
+    tri_setup_body(cnt, t0, min(t0 + kTriPerUnit, total), *B.view, J.sc, J.g, B.bias, J.n, bb, B.ctr,
+                   J.use_mask ? B.tmask : nullptr);
+}
+
+__device__ __noinline__ void unit_scan(unsigned char* raw, const PLaunch& P, const PJob& J, const PSlotBufs& B,
+                                       const BinBuffers& bb, PSlotState& st) {
+    int32_t* part = reinterpret_cast<int32_t*>(raw);
+    const int32_t n_list = scan_body<256, true>(part, J.n_tiles, bb, B.tile_list);
+    if (threadIdx.x == 0) {
+        const int32_t total = part[255];
+        st.n_list = n_list;
+        st.overflow = (ld_dev(&B.ctr->overflow) || ld_dev(&B.ctr->n_rec) > P.rec_cap || total > P.bin_cap) ? 1 : 0;
+    }
+}
+
+__device__ __noinline__ void unit_scatter(unsigned char* raw, const PJob& J, const PSlotBufs& B, const BinBuffers& bb,
+                                          int32_t unit, int32_t units) {
+    uint32_t* lds = 8 * (size_t)J.n_tiles <= kPLdsBytes ? reinterpret_cast<uint32_t*>(raw) : nullptr;
+    scatter_body(lds, unit, units, bb, J.g.n_mod, ld_dev(&B.ctr->n_rec), B.ctr, J.use_mask ? B.tmask : nullptr);
+}
+
+__device__ __noinline__ void unit_tile(unsigned char* raw, const PJob& J, const PItem it, const PSlotBufs& B,
+                                       const BinBuffers& bb, int32_t unit) {
+    const int32_t tile = B.tile_list[unit];
+    TileOut out;
+    out.map = nullptr;
+    out.counts = J.counts + (int64_t)it.sun * J.cells;
+    out.bits = nullptr;
+    out.test = 1;
+    out.sparse = J.sparse;
+    const uint32_t* tmask = J.use_mask ? B.tmask : nullptr;
+    if (J.tile == 64)
+        tile_body<64, 2048>(*reinterpret_cast<TileLds<64, 2048>*>(raw), tile, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, J.g,
+                            B.bias, J.fu, J.fv, J.k, out, J.sparse, tmask);
+    else
+        tile_body<32, 1024>(*reinterpret_cast<TileLds<32, 1024>*>(raw), tile, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, J.g,
+                            B.bias, J.fu, J.fv, J.k, out, J.sparse, tmask);
+}
+
+__device__ __noinline__ void unit_loss(unsigned char* raw, const PJob& J, const PItem it, const PSlotBufs& B) {
+    loss_body<true>(*reinterpret_cast<LossLds*>(raw), J.sun + 3 * it.sun, B.beam, J.counts + (int64_t)it.sun * J.cells,
+              J.dpoa[it.sun], J.g, J.k, J.power + it.sun, J.power_ref + it.sun);
+}
+
+// Coherence of the persistent launch. Every unit ends with a device-scope
+// release (dirty L2 lines written back, nothing invalidated). With XCD
+// groups, the units of a slot run on one XCD, whose L2 every producer and
+// consumer of the slot's buffers share, so taking a unit only has to drop
+// this CU's L1; words that other units update with atomics are read with
+// ld_dev. Without groups, taking a unit invalidates L1 and L2.
+__device__ __forceinline__ void acquire_unit(int32_t groups) {
+    if (groups > 1)
+        asm volatile("buffer_inv sc0" ::: "memory");
+    else
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15): every vector memory access of the wave done
+constexpr int kWaitVmem = 0x0F70;
+
+__device__ __forceinline__ int32_t xcc_id() { return (int32_t)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20); }
+
+struct PCtl {
+    int32_t slot, unit, phase, units;
+    int32_t stop, finish, job_last, job;
+};
+
+__device__ __forceinline__ void publish(PSlotState& st, int32_t phase, int32_t n_units) {
+    st.done = 0;
+    __hip_atomic_store(&st.word, pword(phase, n_units), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The last unit of a phase moves its item on (thread 0 decides; the whole
+// workgroup runs the energy sum of a finished job).
+__device__ void advance(const PLaunch& P, PCtl& ctl, double* stage, int32_t slot, int32_t phase) {
+    const int tid = threadIdx.x;
+    PSlotState& st = P.state[slot];
+    const int32_t item = st.item;
+    const PItem it = P.items[item];
+    const PJob& J = P.jobs[it.job];
+    const PSlotBufs& B = P.slots[slot];
+    if (tid == 0) {
+        bool item_done = false;
+        ctl.job_last = 0;
+        switch (phase) {
+            case kPhSetup:
+                if (B.view->valid) {
+                    const int64_t total = J.sc.n_tri + (J.g.occluders ? 2 * (int64_t)J.g.n_mod : 0) + J.g.n_mod;
+                    publish(st, kPhTri, (int32_t)((total + kTriPerUnit - 1) / kTriPerUnit));
+                } else {
+                    publish(st, kPhLoss, 1);
+                }
+                break;
+            case kPhTri: publish(st, kPhScan, 1); break;
+            case kPhScan:
+                if (st.overflow) {
+                    item_done = true;
+                } else {
+                    const int32_t items = min(ld_dev(&B.ctr->n_rec), P.rec_cap) + J.g.n_mod;
+                    publish(st, kPhScatter, max(1, (items + kScatterPerUnit - 1) / kScatterPerUnit));
+                }
+                break;
+            case kPhScatter:
+                if (ld_dev(&B.ctr->overflow)) {
+                    st.overflow = 1;
+                    item_done = true;
+                } else if (st.n_list > 0) {
+                    publish(st, kPhTile, st.n_list);
+                } else {
+                    publish(st, kPhLoss, 1);
+                }
+                break;
+            case kPhTile: publish(st, kPhLoss, 1); break;
+            default: item_done = true; break;
+        }
+        if (item_done) {
+            if (st.overflow) {
+                const uint32_t q = atomicAdd(&P.sched->n_overflow, 1u);
+                P.overflow_items[q] = item;
+                __hip_atomic_store(&P.job_overflow[it.job], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            const uint32_t jd =
+                __hip_atomic_fetch_add(&P.job_done[it.job], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1;
+            if (jd == (uint32_t)J.n_items &&
+                __hip_atomic_load(&P.job_overflow[it.job], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                ctl.job_last = 1;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the job's powers come from every XCD
+            } else {
+                ctl.job_last = 0;
+            }
+            ctl.job = it.job;
+            // the slot takes the next item
+            const uint32_t ni = atomicAdd(&P.sched->next_item, 1u);
+            st.overflow = 0;
+            st.n_list = 0;
+            if (ni < P.sched->n_items) {
+                st.item = (int32_t)ni;
+                publish(st, kPhSetup, 1);
+            } else {
+                publish(st, kPhIdle, 0);
+            }
+            if (!ctl.job_last) __hip_atomic_fetch_add(&P.sched->items_done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    __syncthreads();
+    if (ctl.job_last) {
+        // energy of the finished job: sum of power * dt in sun order, as the per-sun path sums it
+        const PJob& JJ = P.jobs[ctl.job];
+        double e = 0.0, er = 0.0;
+        for (int64_t t0 = 0; t0 < JJ.n_sun; t0 += 256) {
+            const int64_t t = t0 + tid;
+            if (t < JJ.n_sun) {
+                stage[tid] = JJ.power[t];
+                stage[256 + tid] = JJ.power_ref[t];
+                stage[512 + tid] = JJ.dt[t];
+            }
+            __syncthreads();
+            if (tid == 0) {
+                const int64_t m = min((int64_t)256, JJ.n_sun - t0);
+                for (int64_t q = 0; q < m; q++) {
+                    e += stage[q] * stage[512 + q];
+                    er += stage[256 + q] * stage[512 + q];
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            JJ.energy[0] = e;
+            JJ.energy[1] = er;
+            __hip_atomic_fetch_add(&P.sched->items_done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
+    __shared__ __attribute__((aligned(16))) unsigned char raw[kPLdsBytes];
+    __shared__ PCtl ctl;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // the slots this workgroup serves: my, my + G, my + 2G, ...
+    const int32_t G = P.groups > 1 ? P.groups : 1;
+    const int32_t my = G > 1 ? xcc_id() % G : 0;
+    const int32_t n_mine = my < P.n_slots ? (P.n_slots - my + G - 1) / G : 0;
+    int32_t home = n_mine > 0 ? (int32_t)((blockIdx.x / (unsigned)G) % (unsigned)n_mine) : 0;
+    unsigned long long seen_units = ~0ull;
+    long long seen_at = 0;
+    int32_t backoff = 1;
+    for (;;) {
+        if (tid < 64) {                                   // wave 0 looks for a unit
+            int32_t got = -1, gj = 0, unit = 0, phase = 0, units = 0;
+            const bool aborted = __hip_atomic_load(&P.sched->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            for (int32_t base = 0; base < n_mine && got < 0 && !aborted; base += 64) {
+                const int32_t kk = base + lane;
+                int32_t j = home + kk;
+                if (j >= n_mine) j -= n_mine;
+                const int32_t i = my + j * G;
+                // the oldest item with an open unit first: few items per XCD at a time keep
+                // their buffers in its L2, while phases of younger items fill the gaps
+                int32_t key = INT32_MAX;
+                if (kk < n_mine &&
+                    w_open(__hip_atomic_load(&P.state[i].word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+                    key = __hip_atomic_load(&P.state[i].item, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int attempt = 0; attempt < 64 && got < 0; attempt++) {
+                    int32_t kmin = key, l = lane;
+                    for (int off = 32; off > 0; off >>= 1) {
+                        const int32_t k2 = __shfl_xor(kmin, off, 64), l2 = __shfl_xor(l, off, 64);
+                        if (k2 < kmin || (k2 == kmin && l2 < l)) {
+                            kmin = k2;
+                            l = l2;
+                        }
+                    }
+                    if (kmin == INT32_MAX) break;
+                    int32_t ok = 0, u = 0, ph = 0, nu = 0;
+                    if (lane == l) {
+                        key = INT32_MAX;
+                        const unsigned long long o =
+                            __hip_atomic_fetch_add(&P.state[i].word, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (w_open(o)) {
+                            ok = 1;
+                            u = (int32_t)w_next(o);
+                            ph = w_phase(o);
+                            nu = (int32_t)w_units(o);
+                        }
+                    }
+                    ok = __shfl(ok, l, 64);
+                    if (ok) {
+                        got = __shfl(i, l, 64);
+                        gj = __shfl(j, l, 64);
+                        unit = __shfl(u, l, 64);
+                        phase = __shfl(ph, l, 64);
+                        units = __shfl(nu, l, 64);
+                    }
+                }
+            }
+            if (got >= 0) {
+                home = gj;
+                backoff = 1;
+            }
+            if (lane == 0) {
+                ctl.slot = got;
+                ctl.unit = unit;
+                ctl.phase = phase;
+                ctl.units = units;
+                ctl.stop = 0;
+                if (got >= 0) {
+                    acquire_unit(G);                           // see what the unit's inputs' writers released
+                } else {
+                    const uint32_t done = __hip_atomic_load(&P.sched->items_done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    if (done >= P.sched->n_items || aborted) {
+                        ctl.stop = 1;
+                    } else {
+                        const unsigned long long u =
+                            __hip_atomic_load(&P.sched->units, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const long long now = (long long)wall_clock64();
+                        if (u != seen_units) {
+                            seen_units = u;
+                            seen_at = now;
+                        } else if (now - seen_at > P.stall_ticks) {
+                            __hip_atomic_store(&P.sched->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            ctl.stop = 1;
+                        }
+                        for (int32_t q = 0; q < backoff; q++) __builtin_amdgcn_s_sleep(8);
+                    }
+                }
+            }
+            if (got < 0 && backoff < 32) backoff *= 2;
+        }
+        __syncthreads();
+        const int32_t slot = ctl.slot, unit = ctl.unit, phase = ctl.phase;
+        if (slot < 0) {
+            const int32_t stop = ctl.stop;
+            __syncthreads();
+            if (stop) break;
+            continue;
+        }
+        {
+            PSlotState& st = P.state[slot];
+            const PItem it = P.items[st.item];
+            const PJob& J = P.jobs[it.job];
+            const PSlotBufs& B = P.slots[slot];
+            const BinBuffers bb = slot_bins(P, J, B);
+            switch (phase) {
+                case kPhSetup: unit_setup(raw, J, it, B); break;
+                case kPhTri: unit_tri(raw, J, B, bb, unit); break;
+                case kPhScan: unit_scan(raw, P, J, B, bb, st); break;
+                case kPhScatter: unit_scatter(raw, J, B, bb, unit, ctl.units); break;
+                case kPhTile: unit_tile(raw, J, it, B, bb, unit); break;
+                default: unit_loss(raw, J, it, B); break;
+            }
+        }
+        // this unit's writes, before it counts as done: complete in the XCD's L2 when the
+        // slot's readers share it, else (and for the powers the energy sum reads from
+        // every XCD) written back to memory
+        if (G > 1 && phase != kPhLoss)
+            __builtin_amdgcn_s_waitcnt(kWaitVmem);
+        else
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0) {
+            __hip_atomic_fetch_add(&P.sched->units, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t d =
+                __hip_atomic_fetch_add(&P.state[slot].done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+            ctl.finish = d == (uint32_t)ctl.units ? 1 : 0;
+            if (ctl.finish) acquire_unit(G);                   // the other units of the phase
+        }
+        __syncthreads();
+        if (ctl.finish) advance(P, ctl, reinterpret_cast<double*>(raw), slot, phase);
+        __syncthreads();
+    }
+}
+
+// Which XCD ids the workgroups of a launch run on (bit x of mask: XCD x).
+__global__ void k_xcc_probe(uint32_t* mask) {
+    if (threadIdx.x == 0) atomicOr(mask, 1u << (xcc_id() & 31));
 }
 
 inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -1550,6 +2058,24 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     int64_t b = grid_for(n, 256);
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)(b > 4096 ? 4096 : b)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_xcc_probe(uint32_t* mask, int32_t grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_xcc_probe, dim3((unsigned)grid), dim3(64), 0, st, mask);
+    return hipGetLastError();
+}
+
+hipError_t persist_blocks_per_cu(int32_t* blocks) {
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist, 256, 0);
+    *blocks = nb;
+    return e;
+}
+
+hipError_t launch_persist(const PLaunch& P, int32_t grid, hipStream_t st) {
+    if (grid <= 0 || P.n_slots <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_persist, dim3((unsigned)grid), dim3(256), 0, st, P);
     return hipGetLastError();
 }
 

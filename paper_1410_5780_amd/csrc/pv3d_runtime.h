@@ -19,6 +19,8 @@ namespace pv3d {
 
 struct Ctx;
 
+constexpr int32_t kMaxBinLimit = 256;   // default and largest bin_limit
+
 pv3d_status fail(pv3d_status code, const char* fmt, ...);
 pv3d_status hip_fail(hipError_t e, const char* what);
 pv3d_status check_params(const pv3d_params* p);

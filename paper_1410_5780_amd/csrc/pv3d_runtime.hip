@@ -240,6 +240,9 @@ pv3d_status check_params(const pv3d_params* p) {
         return fail(PV3D_EINVAL, "unknown flags 0x%x", p->flags);
     if (p->tile != 0 && p->tile != 32 && p->tile != 64 && p->tile != 128)
         return fail(PV3D_EINVAL, "tile %d not in {0, 32, 64, 128}", p->tile);
+    if (p->bin_limit < 0 || p->bin_limit > kMaxBinLimit)
+        return fail(PV3D_EINVAL, "bin_limit %d outside [0, %d]", p->bin_limit, kMaxBinLimit);
+    if (p->reserved != 0) return fail(PV3D_EINVAL, "reserved field must be 0");
     return PV3D_OK;
 }
 
@@ -253,7 +256,7 @@ PathSizes path_sizes(const Scene& sc, const Gen& g, const pv3d_params& p, int64_
     z.tile = choose_tile(p);
     z.ntx = (p.map_n + z.tile - 1) / z.tile;
     z.n_tiles = z.ntx * z.ntx;
-    z.large_tiles = 256;
+    z.large_tiles = p.bin_limit ? p.bin_limit : kMaxBinLimit;
     z.tri_total = sc.n_tri + (g.occluders ? 2 * g.n_mod : 0);
     // a clipped triangle becomes at most 5 (a triangle cut by four half-planes
     // is a polygon of at most 7 corners); a binned one touches <= large_tiles

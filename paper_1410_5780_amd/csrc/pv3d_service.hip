@@ -1,22 +1,541 @@
-// Batched and serving entry points of libpv3d (placeholders until the
-// persistent kernel lands; they report that the form is unavailable).
+// Batched form of libpv3d: every (job, sun) item of a set of jobs in one
+// persistent launch (k_persist), and the autotuner that picks its tile and
+// bin sizes.
+//
+// Host side of a batch:
+//   1. validate the jobs, copy their sweeps to the device in one staging pass;
+//   2. per job: bounding sphere and sample tables (two small launches), and
+//      zeroed outputs (suns below the horizon keep zero power);
+//   3. size the slots (work buffers of one item each) from the largest job
+//      and the HBM budget, zero their tile counters, seed the first items;
+//   4. one persistent launch over the list of suns above the horizon;
+//   5. suns that exceeded a slot's capacity are evaluated again with the
+//      per-sun path, and their jobs' energies summed again;
+//   6. copy host outputs back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/pv3d.h"
+#include "pv3d_device.h"
 #include "pv3d_runtime.h"
 
 using namespace pv3d;
 
 namespace pv3d {
+
+constexpr int32_t kMaxSlots = 128;          // items in flight
+constexpr int64_t kSlotRecCap = 1 << 20;    // set-up records per slot (more: the sun goes to the per-sun path)
+constexpr double kStallSeconds = 5.0;       // watchdog of the persistent launch
+
+struct BatchState {
+    Buf slotmem, slots, state, sched, jobs, items, jobdone, overflow, jobmem, partial, energy_tmp;
+    int32_t max_slots = kMaxSlots;
+    int64_t slot_records = kSlotRecCap;
+    int32_t xcd_groups = 1;       // 8 when every slot can be served by one XCD
+    bool any_xcd = false;         // PV3D_BATCH_ANY_XCD
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int32_t blocks_per_cu = 0, n_cu = 0;
+    long long stall_ticks = 0;
+    int64_t stats[7] = {};
+};
+
+void Ctx::release_batched() {
+    if (!batch) return;
+    BatchState& b = *batch;
+    Buf* all[] = {&b.slotmem, &b.slots, &b.state, &b.sched, &b.jobs, &b.items,
+                  &b.jobdone, &b.overflow, &b.jobmem, &b.partial, &b.energy_tmp};
+    for (Buf* x : all) x->release(this);
+    if (b.ev0) (void)hipEventDestroy(b.ev0);
+    if (b.ev1) (void)hipEventDestroy(b.ev1);
+    delete batch;
+    batch = nullptr;
+}
+
 bool Ctx::scene_in_use(uint64_t) { return false; }
 bool Ctx::gen_in_use(uint64_t) { return false; }
-void Ctx::release_batched() {}
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Host view of one job of a batch.
+struct HostJob {
+    const Scene* sc;
+    const Gen* g;
+    pv3d_job job;
+    int32_t tile, ntx, n_tiles, words, large_tiles, sparse, use_mask;
+    int64_t cells, tri_all, n_items;
+    // device regions
+    double *d_sun, *d_dni, *d_dpoa, *d_dt, *d_sphere, *d_fu, *d_fv;
+    uint32_t* d_counts;
+    double *d_power, *d_pref, *d_energy;
+};
+
+static pv3d_status batch_state(Ctx* c, BatchState** out) {
+    if (!c->batch) {
+        std::unique_ptr<BatchState> b(new BatchState());
+        hipError_t e;
+        if ((e = hipEventCreate(&b->ev0)) || (e = hipEventCreate(&b->ev1))) return hip_fail(e, "hipEventCreate");
+        int32_t bpc = 0;
+        if ((e = persist_blocks_per_cu(&bpc))) return hip_fail(e, "occupancy of the persistent kernel");
+        hipDeviceProp_t prop;
+        if ((e = hipGetDeviceProperties(&prop, c->device))) return hip_fail(e, "hipGetDeviceProperties");
+        int rate_khz = 0;
+        if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess || rate_khz <= 0)
+            rate_khz = 100000;
+        b->blocks_per_cu = std::max(1, bpc);
+        b->n_cu = std::max(1, prop.multiProcessorCount);
+        b->stall_ticks = (long long)(kStallSeconds * 1000.0 * (double)rate_khz);
+        {   // XCD ids the workgroups of a full-device launch run on
+            uint32_t* d_mask = nullptr;
+            if ((e = hipMalloc(&d_mask, 256))) return hip_fail(e, "hipMalloc");
+            uint32_t mask = 0;
+            e = hipMemsetAsync(d_mask, 0, 4, c->stream);
+            if (!e) e = launch_xcc_probe(d_mask, 8 * b->n_cu, c->stream);
+            if (!e) e = hipMemcpyAsync(&mask, d_mask, 4, hipMemcpyDeviceToHost, c->stream);
+            if (!e) e = hipStreamSynchronize(c->stream);
+            (void)hipFree(d_mask);
+            if (e) return hip_fail(e, "XCD probe");
+            b->xcd_groups = mask == 0xFFu ? 8 : 1;
+        }
+        c->batch = b.release();
+    }
+    *out = c->batch;
+    return PV3D_OK;
+}
+
+// Validate one job and fill its host view (no device work).
+static pv3d_status check_job(Ctx* c, const pv3d_job& j, int64_t idx, HostJob& h) {
+    pv3d_status st;
+    if ((st = check_params(&j.params))) return fail(st, "job %lld: %s", (long long)idx, pv3d_last_error(nullptr));
+    if (j.params.flags & ~PV3D_FULL_RASTER)
+        return fail(PV3D_EINVAL, "job %lld: the batched form takes flags 0 or FULL_RASTER", (long long)idx);
+    if (j.params.tile != 0 && j.params.tile != 32 && j.params.tile != 64)
+        return fail(PV3D_EINVAL, "job %lld: the batched form takes tile 0, 32 or 64", (long long)idx);
+    if ((st = check_sweep(j.sun_xyz, j.dni, j.d_poa, j.dt_h, j.n_sun)))
+        return fail(st, "job %lld: %s", (long long)idx, pv3d_last_error(nullptr));
+    if (!j.out.power || !j.out.power_ref || !j.out.energy)
+        return fail(PV3D_EINVAL, "job %lld: power, power_ref and energy are required", (long long)idx);
+    auto si = c->scenes.find(j.scene);
+    if (si == c->scenes.end()) return fail(PV3D_ENOENT, "job %lld: unknown scene %llu", (long long)idx, (unsigned long long)j.scene);
+    auto gi = c->gens.find(j.gen);
+    if (gi == c->gens.end()) return fail(PV3D_ENOENT, "job %lld: unknown generator %llu", (long long)idx, (unsigned long long)j.gen);
+    const Gen& g = gi->second;
+    if ((int64_t)j.params.k * g.n_cu > 4095 || (int64_t)j.params.k * g.n_cv > 4095)
+        return fail(PV3D_ERANGE, "job %lld: k * cells per module side exceeds 4095 samples", (long long)idx);
+    memset(&h, 0, sizeof(h));
+    h.sc = &si->second;
+    h.g = &g;
+    h.job = j;
+    h.tile = j.params.tile ? j.params.tile : 64;
+    h.ntx = (j.params.map_n + h.tile - 1) / h.tile;
+    h.n_tiles = h.ntx * h.ntx;
+    h.words = (h.n_tiles + 31) / 32;
+    h.large_tiles = j.params.bin_limit ? j.params.bin_limit : kMaxBinLimit;
+    h.sparse = (j.params.flags & PV3D_FULL_RASTER) ? 0 : 1;
+    h.use_mask = h.sparse && h.words <= 512;
+    h.cells = g.n_mod * g.n_cu * g.n_cv;
+    h.tri_all = h.sc->n_tri + (g.occluders ? 2 * g.n_mod : 0);
+    h.n_items = 0;
+    for (int64_t t = 0; t < j.n_sun; t++)
+        if (j.sun_xyz[3 * t + 2] > 0.0) h.n_items++;
+    return PV3D_OK;
+}
+
+// One batch: every job's suns above the horizon through the persistent kernel.
+static pv3d_status run_batch(Ctx* c, const pv3d_job* jobs, int64_t n_jobs, hipStream_t s) {
+    BatchState* B = nullptr;
+    pv3d_status st;
+    if ((st = batch_state(c, &B))) return st;
+    for (int i = 0; i < 7; i++) B->stats[i] = 0;
+    std::vector<HostJob> H((size_t)n_jobs);
+    int64_t n_items = 0, sweep_total = 0;
+    for (int64_t i = 0; i < n_jobs; i++) {
+        if ((st = check_job(c, jobs[i], i, H[(size_t)i]))) return st;
+        n_items += H[(size_t)i].n_items;
+        sweep_total += jobs[i].n_sun;
+    }
+    if (n_items >= INT32_MAX) return fail(PV3D_ERANGE, "more than 2^31 suns in one batch");
+    hipError_t e;
+
+    // --- per-job device memory: sweep, sphere, sample tables, internal outputs
+    size_t jm = 0;
+    std::vector<size_t> off((size_t)n_jobs);
+    for (int64_t i = 0; i < n_jobs; i++) {
+        const HostJob& h = H[(size_t)i];
+        const int64_t ns = h.job.n_sun;
+        off[(size_t)i] = jm;
+        jm += al256(48 * (size_t)ns) + 256;                                          // sweep + sphere
+        jm += 2 * al256(8 * (size_t)h.job.params.k * std::max(h.g->n_cu, h.g->n_cv));   // fu, fv
+        if (!h.job.out.on_device || !h.job.out.cell_counts) jm += al256(4 * (size_t)(ns * h.cells));
+        if (!h.job.out.on_device) jm += al256(16 * (size_t)ns) + 256;
+    }
+    if ((st = B->jobmem.ensure(c, std::max<size_t>(jm, 256), "batched job data"))) return st;
+    if ((st = B->partial.ensure(c, 8 * 6 * 1024, "bounds partials"))) return st;
+    if ((st = B->energy_tmp.ensure(c, 256, "energy scratch"))) return st;
+    if ((st = c->stage_reserve(48 * (size_t)sweep_total + 256 * 4 * (size_t)n_jobs))) return st;
+    char* base = static_cast<char*>(B->jobmem.ptr);
+    for (int64_t i = 0; i < n_jobs; i++) {
+        HostJob& h = H[(size_t)i];
+        const int64_t ns = h.job.n_sun;
+        char* p = base + off[(size_t)i];
+        h.d_sun = reinterpret_cast<double*>(p);
+        h.d_dni = h.d_sun + 3 * ns;
+        h.d_dpoa = h.d_dni + ns;
+        h.d_dt = h.d_dpoa + ns;
+        p += al256(48 * (size_t)ns);
+        h.d_sphere = reinterpret_cast<double*>(p);
+        p += 256;
+        const size_t tb = al256(8 * (size_t)h.job.params.k * std::max(h.g->n_cu, h.g->n_cv));
+        h.d_fu = reinterpret_cast<double*>(p);
+        p += tb;
+        h.d_fv = reinterpret_cast<double*>(p);
+        p += tb;
+        if (h.job.out.on_device && h.job.out.cell_counts) {
+            h.d_counts = h.job.out.cell_counts;
+        } else {
+            h.d_counts = reinterpret_cast<uint32_t*>(p);
+            p += al256(4 * (size_t)(ns * h.cells));
+        }
+        if (h.job.out.on_device) {
+            h.d_power = h.job.out.power;
+            h.d_pref = h.job.out.power_ref;
+            h.d_energy = h.job.out.energy;
+        } else {
+            h.d_power = reinterpret_cast<double*>(p);
+            h.d_pref = h.d_power + ns;
+            p += al256(16 * (size_t)ns);
+            h.d_energy = reinterpret_cast<double*>(p);
+        }
+        if (ns > 0) {
+            if ((st = c->stage(h.job.sun_xyz, 24 * (size_t)ns, h.d_sun, s))) return st;
+            if ((st = c->stage(h.job.dni, 8 * (size_t)ns, h.d_dni, s))) return st;
+            if ((st = c->stage(h.job.d_poa, 8 * (size_t)ns, h.d_dpoa, s))) return st;
+            if ((st = c->stage(h.job.dt_h, 8 * (size_t)ns, h.d_dt, s))) return st;
+        }
+    }
+    if ((st = c->stage_done(s))) return st;
+    for (int64_t i = 0; i < n_jobs; i++) {
+        HostJob& h = H[(size_t)i];
+        const int64_t ns = h.job.n_sun;
+        const SceneDev sd = scene_dev(*h.sc);
+        const GenDev gd = gen_dev(*h.g);
+        if ((e = launch_bounds(sd, gd, static_cast<double*>(B->partial.ptr), bounds_partials(h.sc->n_vert + 4 * h.g->n_mod),
+                               h.d_sphere, s)))
+            return hip_fail(e, "bounds");
+        if ((e = launch_sample_tables(h.d_fu, h.d_fv, h.job.params.k, h.g->n_cu, h.g->n_cv, s)))
+            return hip_fail(e, "sample tables");
+        if (ns > 0) {
+            if ((e = hipMemsetAsync(h.d_counts, 0, 4 * (size_t)(ns * h.cells), s))) return hip_fail(e, "clear counts");
+            if ((e = hipMemsetAsync(h.d_power, 0, 8 * (size_t)ns, s))) return hip_fail(e, "clear power");
+            if ((e = hipMemsetAsync(h.d_pref, 0, 8 * (size_t)ns, s))) return hip_fail(e, "clear power_ref");
+        }
+        if ((e = hipMemsetAsync(h.d_energy, 0, 16, s))) return hip_fail(e, "clear energy");
+    }
+
+    if (n_items > 0) {
+        // --- slots
+        int64_t worst_rec = 64, max_tiles = 1, max_mod = 1;
+        int64_t worst_bins = 0;
+        for (const HostJob& h : H) {
+            if (h.n_items == 0) continue;
+            const int64_t rec = 5 * h.tri_all + 64;
+            worst_rec = std::max(worst_rec, rec);
+            worst_bins = std::max(worst_bins, (int64_t)h.large_tiles * rec + h.g->n_mod * (int64_t)h.n_tiles);
+            max_tiles = std::max<int64_t>(max_tiles, h.n_tiles);
+            max_mod = std::max<int64_t>(max_mod, h.g->n_mod);
+        }
+        const int64_t rec_cap = std::min(worst_rec, B->slot_records);
+        const int64_t bin_cap = std::min(worst_bins, 8 * rec_cap + 64 * max_mod + 65536);
+        const size_t per_rec = al256(80 * (size_t)rec_cap), per_large = al256(4 * (size_t)rec_cap);
+        const size_t per_bins = al256(4 * (size_t)bin_cap), per_t = al256(4 * (size_t)(max_tiles + 1));
+        const size_t per_mod = al256(16 * (size_t)max_mod) + al256(8 * (size_t)max_mod) + al256(4 * (size_t)max_mod);
+        const size_t per_misc = 256 /*view*/ + al256(4 * 512) /*mask*/ + 256 /*counters*/;
+        const size_t slot_bytes = per_rec + per_large + per_bins + 4 * per_t + per_mod + per_misc;
+        const uint64_t room = c->budget > c->used + B->slotmem.cap ? c->budget - c->used + B->slotmem.cap : 0;
+        int64_t n_slots = std::min<int64_t>(std::min<int64_t>(n_items, B->max_slots), (int64_t)(room / 2 / slot_bytes));
+        if (n_slots < 1) return fail(PV3D_ENOMEM, "one batch slot (%zu bytes) does not fit the HBM budget", slot_bytes);
+        const size_t ns = (size_t)n_slots;
+        if ((st = B->slotmem.ensure(c, slot_bytes * ns, "batch slots"))) return st;
+        char* q = static_cast<char*>(B->slotmem.ptr);
+        // one region per array kind, so the tile counters of every slot clear in one call
+        char* r_rec = q; q += per_rec * ns;
+        char* r_large = q; q += per_large * ns;
+        char* r_bins = q; q += per_bins * ns;
+        char* r_tc = q; q += per_t * ns;
+        char* r_ts = q; q += per_t * ns;
+        char* r_tcur = q; q += per_t * ns;
+        char* r_tl = q; q += per_t * ns;
+        char* r_mod = q; q += per_mod * ns;
+        char* r_misc = q;
+        std::vector<PSlotBufs> slots(ns);
+        for (size_t i = 0; i < ns; i++) {
+            PSlotBufs& b = slots[i];
+            b.rec = reinterpret_cast<TriRec*>(r_rec + per_rec * i);
+            b.large = reinterpret_cast<int32_t*>(r_large + per_large * i);
+            b.bins = reinterpret_cast<int32_t*>(r_bins + per_bins * i);
+            b.tile_count = reinterpret_cast<int32_t*>(r_tc + per_t * i);
+            b.tile_start = reinterpret_cast<int32_t*>(r_ts + per_t * i);
+            b.tile_cursor = reinterpret_cast<int32_t*>(r_tcur + per_t * i);
+            b.tile_list = reinterpret_cast<int32_t*>(r_tl + per_t * i);
+            char* m = r_mod + per_mod * i;
+            b.modbox = reinterpret_cast<int4*>(m);
+            b.beam = reinterpret_cast<double*>(m + al256(16 * (size_t)max_mod));
+            b.bias = reinterpret_cast<int32_t*>(m + al256(16 * (size_t)max_mod) + al256(8 * (size_t)max_mod));
+            char* x = r_misc + per_misc * i;
+            b.view = reinterpret_cast<View*>(x);
+            b.tmask = reinterpret_cast<uint32_t*>(x + 256);
+            b.ctr = reinterpret_cast<SunCounters*>(x + 256 + al256(4 * 512));
+        }
+        if ((e = hipMemsetAsync(r_tc, 0, per_t * ns, s))) return hip_fail(e, "clear slot tile counts");
+
+        // --- tables
+        std::vector<PJob> pj((size_t)n_jobs);
+        std::vector<PItem> items((size_t)n_items);
+        int64_t k = 0;
+        for (int64_t i = 0; i < n_jobs; i++) {
+            const HostJob& h = H[(size_t)i];
+            PJob& J = pj[(size_t)i];
+            memset(&J, 0, sizeof(J));
+            J.sc = scene_dev(*h.sc);
+            J.g = gen_dev(*h.g);
+            J.sun = h.d_sun;
+            J.dni = h.d_dni;
+            J.dpoa = h.d_dpoa;
+            J.counts = h.d_counts;
+            J.power = h.d_power;
+            J.power_ref = h.d_pref;
+            J.energy = h.d_energy;
+            J.dt = h.d_dt;
+            J.sphere = h.d_sphere;
+            J.fu = h.d_fu;
+            J.fv = h.d_fv;
+            J.n_sun = h.job.n_sun;
+            J.cells = h.cells;
+            J.n = h.job.params.map_n;
+            J.k = h.job.params.k;
+            J.tile = h.tile;
+            J.sparse = h.sparse;
+            J.use_mask = h.use_mask;
+            J.large_tiles = h.large_tiles;
+            J.ntx = h.ntx;
+            J.n_tiles = h.n_tiles;
+            J.words = h.words;
+            J.n_items = (int32_t)h.n_items;
+            for (int64_t t = 0; t < h.job.n_sun; t++)
+                if (h.job.sun_xyz[3 * t + 2] > 0.0) items[(size_t)k++] = PItem{(int32_t)i, (int32_t)t};
+        }
+        std::vector<PSlotState> state(ns);
+        memset(state.data(), 0, sizeof(PSlotState) * ns);
+        for (size_t i = 0; i < ns; i++) {
+            state[i].item = (int32_t)i;
+            state[i].word = ((unsigned long long)kPhSetup << 56) | (1ull << 32);
+        }
+        PSched sched;
+        memset(&sched, 0, sizeof(sched));
+        sched.next_item = (uint32_t)ns;
+        sched.n_items = (uint32_t)n_items;
+        if ((st = B->slots.ensure(c, sizeof(PSlotBufs) * ns, "slot table"))) return st;
+        if ((st = B->state.ensure(c, sizeof(PSlotState) * ns, "slot states"))) return st;
+        if ((st = B->sched.ensure(c, sizeof(PSched), "scheduler"))) return st;
+        if ((st = B->jobs.ensure(c, sizeof(PJob) * (size_t)n_jobs, "job table"))) return st;
+        if ((st = B->items.ensure(c, sizeof(PItem) * (size_t)n_items, "item list"))) return st;
+        if ((st = B->jobdone.ensure(c, 8 * (size_t)n_jobs, "job counters"))) return st;
+        if ((st = B->overflow.ensure(c, 4 * (size_t)n_items, "overflow list"))) return st;
+        const size_t tbytes = al256(sizeof(PSlotBufs) * ns) + al256(sizeof(PSlotState) * ns) + al256(sizeof(PSched)) +
+                              al256(sizeof(PJob) * (size_t)n_jobs) + al256(sizeof(PItem) * (size_t)n_items) + 4096;
+        if ((st = c->stage_reserve(tbytes))) return st;
+        if ((st = c->stage(slots.data(), sizeof(PSlotBufs) * ns, B->slots.ptr, s))) return st;
+        if ((st = c->stage(state.data(), sizeof(PSlotState) * ns, B->state.ptr, s))) return st;
+        if ((st = c->stage(&sched, sizeof(PSched), B->sched.ptr, s))) return st;
+        if ((st = c->stage(pj.data(), sizeof(PJob) * (size_t)n_jobs, B->jobs.ptr, s))) return st;
+        if ((st = c->stage(items.data(), sizeof(PItem) * (size_t)n_items, B->items.ptr, s))) return st;
+        if ((st = c->stage_done(s))) return st;
+        if ((e = hipMemsetAsync(B->jobdone.ptr, 0, 8 * (size_t)n_jobs, s))) return hip_fail(e, "clear job counters");
+
+        PLaunch P;
+        memset(&P, 0, sizeof(P));
+        P.jobs = static_cast<const PJob*>(B->jobs.ptr);
+        P.items = static_cast<const PItem*>(B->items.ptr);
+        P.slots = static_cast<const PSlotBufs*>(B->slots.ptr);
+        P.state = static_cast<PSlotState*>(B->state.ptr);
+        P.sched = static_cast<PSched*>(B->sched.ptr);
+        P.job_done = static_cast<uint32_t*>(B->jobdone.ptr);
+        P.job_overflow = reinterpret_cast<int32_t*>(static_cast<uint32_t*>(B->jobdone.ptr) + n_jobs);
+        P.overflow_items = static_cast<int32_t*>(B->overflow.ptr);
+        P.n_slots = (int32_t)n_slots;
+        P.rec_cap = (int32_t)rec_cap;
+        P.bin_cap = (int32_t)bin_cap;
+        P.stall_ticks = B->stall_ticks;
+        P.groups = B->any_xcd ? 1 : B->xcd_groups;
+        const int32_t grid = B->blocks_per_cu * B->n_cu;
+        if ((e = hipEventRecord(B->ev0, s))) return hip_fail(e, "event");
+        if ((e = launch_persist(P, grid, s))) return hip_fail(e, "persistent launch");
+        if ((e = hipEventRecord(B->ev1, s))) return hip_fail(e, "event");
+        PSched got;
+        if ((e = hipMemcpyAsync(&got, B->sched.ptr, sizeof(PSched), hipMemcpyDeviceToHost, s))) return hip_fail(e, "read scheduler");
+        if ((e = hipStreamSynchronize(s))) return hip_fail(e, "persistent launch");
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, B->ev0, B->ev1);
+        if (got.abort) return fail(PV3D_EDEVICE, "persistent launch made no progress for %.0f s", kStallSeconds);
+        if (got.items_done != (uint32_t)n_items)
+            return fail(PV3D_EDEVICE, "persistent launch ended with %u of %lld items done", got.items_done, (long long)n_items);
+        B->stats[0] = n_items;
+        B->stats[1] = (int64_t)got.units;
+        B->stats[2] = got.n_overflow;
+        B->stats[3] = grid;
+        B->stats[4] = n_slots;
+        B->stats[5] = (int64_t)llround((double)ms * 1000.0);
+        B->stats[6] = P.groups;
+
+        // --- suns beyond a slot's capacity: the per-sun path, then the job's energy again
+        if (got.n_overflow > 0) {
+            std::vector<int32_t> ov(got.n_overflow);
+            if ((e = hipMemcpy(ov.data(), B->overflow.ptr, 4 * ov.size(), hipMemcpyDeviceToHost))) return hip_fail(e, "read overflow list");
+            std::vector<char> redo((size_t)n_jobs, 0);
+            for (int32_t it : ov) {
+                const PItem pi = items[(size_t)it];
+                HostJob& h = H[(size_t)pi.job];
+                const int64_t t = pi.sun;
+                pv3d_params p1 = h.job.params;
+                p1.tile = h.tile;
+                if ((st = c->run_path(*h.sc, *h.g, p1, h.job.sun_xyz + 3 * t, 1, h.d_sun + 3 * t, h.d_dni + t, h.d_dpoa + t,
+                                      h.d_dt + t, h.d_counts + t * h.cells, h.d_power + t, h.d_pref + t,
+                                      static_cast<double*>(B->energy_tmp.ptr), nullptr, nullptr, s)))
+                    return st;
+                redo[(size_t)pi.job] = 1;
+            }
+            for (int64_t i = 0; i < n_jobs; i++)
+                if (redo[(size_t)i]) {
+                    const HostJob& h = H[(size_t)i];
+                    if ((e = launch_energy(h.job.n_sun, h.d_power, h.d_pref, h.d_dt, h.d_energy, s))) return hip_fail(e, "energy");
+                }
+        }
+    }
+
+    // --- host outputs
+    for (int64_t i = 0; i < n_jobs; i++) {
+        const HostJob& h = H[(size_t)i];
+        if (h.job.out.on_device) continue;
+        const int64_t ns = h.job.n_sun;
+        if (h.job.out.cell_counts && ns &&
+            (e = hipMemcpyAsync(h.job.out.cell_counts, h.d_counts, 4 * (size_t)(ns * h.cells), hipMemcpyDeviceToHost, s)))
+            return hip_fail(e, "copy counts");
+        if (ns && (e = hipMemcpyAsync(h.job.out.power, h.d_power, 8 * (size_t)ns, hipMemcpyDeviceToHost, s))) return hip_fail(e, "copy power");
+        if (ns && (e = hipMemcpyAsync(h.job.out.power_ref, h.d_pref, 8 * (size_t)ns, hipMemcpyDeviceToHost, s)))
+            return hip_fail(e, "copy power_ref");
+        if ((e = hipMemcpyAsync(h.job.out.energy, h.d_energy, 16, hipMemcpyDeviceToHost, s))) return hip_fail(e, "copy energy");
+    }
+    if ((e = hipStreamSynchronize(s))) return hip_fail(e, "synchronize");
+    return PV3D_OK;
+}
+
 }  // namespace pv3d
 
 void pv3d_server_stop(pv3d_ctx*) {}
 
 extern "C" {
+
 pv3d_status pv3d_evaluate_batched(pv3d_ctx* ctx, const pv3d_job* jobs, int64_t n_jobs, void* hip_stream) {
-    (void)ctx; (void)jobs; (void)n_jobs; (void)hip_stream;
-    return fail(PV3D_ERANGE, "batched evaluation is not available in this build");
+    if (!ctx) return fail(PV3D_EINVAL, "null context");
+    if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(PV3D_EINVAL, "bad job list");
+    if (n_jobs >= INT32_MAX) return fail(PV3D_ERANGE, "too many jobs");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->stream;
+    ctx->stream_in_use = s;
+    return run_batch(ctx, jobs, n_jobs, s);
 }
+
+pv3d_status pv3d_autotune(pv3d_ctx* ctx, pv3d_job* job, int32_t n_probe, double* best_ms_out) {
+    if (!ctx || !job) return fail(PV3D_EINVAL, "null argument");
+    if (n_probe < 1) return fail(PV3D_EINVAL, "n_probe %d < 1", n_probe);
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    HostJob h;
+    ctx->stream_in_use = ctx->stream;
+    pv3d_status st;
+    if ((st = check_job(ctx, *job, 0, h))) return st;
+    // probe suns: evenly spaced among those above the horizon
+    std::vector<int64_t> up;
+    for (int64_t t = 0; t < job->n_sun; t++)
+        if (job->sun_xyz[3 * t + 2] > 0.0) up.push_back(t);
+    const int64_t np = std::min<int64_t>(n_probe, (int64_t)up.size());
+    if (np == 0) {
+        if (best_ms_out) *best_ms_out = 0.0;
+        return PV3D_OK;                              // nothing to time: keep the job's params
+    }
+    std::vector<double> sun(3 * (size_t)np), dni((size_t)np), dp((size_t)np), dt((size_t)np);
+    for (int64_t q = 0; q < np; q++) {
+        const int64_t t = up[(size_t)((q * (int64_t)up.size()) / np)];
+        for (int c = 0; c < 3; c++) sun[(size_t)(3 * q + c)] = job->sun_xyz[3 * t + c];
+        dni[(size_t)q] = job->dni[t];
+        dp[(size_t)q] = job->d_poa[t];
+        dt[(size_t)q] = job->dt_h[t];
+    }
+    std::vector<uint32_t> counts((size_t)(np * h.cells));
+    std::vector<double> pw((size_t)np), pr((size_t)np), en(2);
+    pv3d_job probe = *job;
+    probe.sun_xyz = sun.data();
+    probe.dni = dni.data();
+    probe.d_poa = dp.data();
+    probe.dt_h = dt.data();
+    probe.n_sun = np;
+    probe.out.cell_counts = nullptr;
+    probe.out.power = pw.data();
+    probe.out.power_ref = pr.data();
+    probe.out.energy = en.data();
+    probe.out.depth_maps = nullptr;
+    probe.out.shaded_bits = nullptr;
+    probe.out.on_device = 0;
+    const int32_t tiles[2] = {32, 64};
+    const int32_t limits[3] = {16, 64, 256};
+    double best = INFINITY;
+    int32_t bt = 64, bl = kMaxBinLimit;
+    for (int32_t tile : tiles)
+        for (int32_t lim : limits) {
+            probe.params.tile = tile;
+            probe.params.bin_limit = lim;
+            if ((st = run_batch(ctx, &probe, 1, ctx->stream))) return st;     // warm
+            if ((st = run_batch(ctx, &probe, 1, ctx->stream))) return st;
+            const double ms = (double)ctx->batch->stats[5] / 1000.0;
+            if (ms < best) {
+                best = ms;
+                bt = tile;
+                bl = lim;
+            }
+        }
+    job->params.tile = bt;
+    job->params.bin_limit = bl;
+    if (best_ms_out) *best_ms_out = best;
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_batch_limits(pv3d_ctx* ctx, int32_t max_slots, int64_t slot_records, uint32_t flags) {
+    if (!ctx) return fail(PV3D_EINVAL, "null context");
+    if (max_slots < 0 || max_slots > 4096 || slot_records < 0 || slot_records > INT32_MAX / 8)
+        return fail(PV3D_EINVAL, "batch limits out of range");
+    if (flags & ~PV3D_BATCH_ANY_XCD) return fail(PV3D_EINVAL, "unknown batch flags 0x%x", flags);
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    BatchState* B = nullptr;
+    pv3d_status st;
+    if ((st = batch_state(ctx, &B))) return st;
+    B->max_slots = max_slots ? max_slots : kMaxSlots;
+    B->slot_records = slot_records ? slot_records : kSlotRecCap;
+    B->any_xcd = (flags & PV3D_BATCH_ANY_XCD) != 0;
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_batch_stats(pv3d_ctx* ctx, int64_t out[7]) {
+    if (!ctx || !out) return fail(PV3D_EINVAL, "null argument");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    for (int i = 0; i < 7; i++) out[i] = ctx->batch ? ctx->batch->stats[i] : 0;
+    return PV3D_OK;
+}
+
 pv3d_status pv3d_submit(pv3d_ctx* ctx, const pv3d_job* job, uint64_t* ticket) {
     (void)ctx; (void)job; (void)ticket;
     return fail(PV3D_ERANGE, "serving is not available in this build");
@@ -33,4 +552,5 @@ pv3d_status pv3d_cancel(pv3d_ctx* ctx, uint64_t ticket) {
     (void)ctx; (void)ticket;
     return fail(PV3D_ENOENT, "unknown ticket");
 }
-}
+
+}  // extern "C"

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libpv3d.so")
 
 OK, EINVAL, ENOMEM, ENOENT, EDEVICE, ERANGE, EBUSY, ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7
 EXPORT_DEPTH, EXPORT_BITS, SEPARATE_TEST, FULL_RASTER = 1, 2, 4, 8
+BATCH_ANY_XCD = 1
 STAGES = ("tri_setup", "bin_scan", "bin_scatter", "raster", "sample_test", "setup", "loss")
 STAGE = {n: i for i, n in enumerate(STAGES)}
 N_STAGES = len(STAGES)
@@ -32,7 +33,8 @@ class Module(ctypes.Structure):
 
 
 class Params(ctypes.Structure):
-    _fields_ = [("map_n", _i32), ("k", _i32), ("flags", _u32), ("tile", _i32)]
+    _fields_ = [("map_n", _i32), ("k", _i32), ("flags", _u32), ("tile", _i32), ("bin_limit", _i32),
+                ("reserved", _i32)]
 
 
 class Outputs(ctypes.Structure):
@@ -75,6 +77,9 @@ def lib():
         L.pv3d_evaluate.argtypes = [_P, _u64, _u64, _P, _P, _P, _P, _i64, ctypes.POINTER(Params),
                                     ctypes.POINTER(Outputs), _P]
         L.pv3d_evaluate_batched.argtypes = [_P, ctypes.POINTER(Job), _i64, _P]
+        L.pv3d_autotune.argtypes = [_P, ctypes.POINTER(Job), _i32, ctypes.POINTER(_f64)]
+        L.pv3d_batch_stats.argtypes = [_P, ctypes.POINTER(_i64 * 7)]
+        L.pv3d_batch_limits.argtypes = [_P, _i32, _i64, _u32]
         L.pv3d_submit.argtypes = [_P, ctypes.POINTER(Job), ctypes.POINTER(_u64)]
         L.pv3d_poll.argtypes = [_P, _u64, ctypes.POINTER(_i32)]
         L.pv3d_wait.argtypes = [_P, _u64]
@@ -83,6 +88,7 @@ def lib():
         L.pv3d_profile_read.argtypes = [_P, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
         for f in ("pv3d_profile_enable", "pv3d_profile_read", "pv3d_create", "pv3d_scene_load", "pv3d_scene_release", "pv3d_generator_define",
                   "pv3d_generator_release", "pv3d_sun_cooper", "pv3d_evaluate", "pv3d_evaluate_batched",
+                  "pv3d_autotune", "pv3d_batch_stats", "pv3d_batch_limits",
                   "pv3d_submit", "pv3d_poll", "pv3d_wait", "pv3d_cancel"):
             getattr(L, f).restype = _i32
         _lib = L
@@ -194,12 +200,14 @@ class Context:
 
     @staticmethod
     def params(map_n: int, k: int, export_depth=False, export_bits=False, tile: int = 0,
-               separate_test=False, full_raster=False) -> Params:
+               separate_test=False, full_raster=False, bin_limit: int = 0) -> Params:
         return Params(map_n, k, (EXPORT_DEPTH if export_depth else 0) | (EXPORT_BITS if export_bits else 0)
-                      | (SEPARATE_TEST if separate_test else 0) | (FULL_RASTER if full_raster else 0), tile)
+                      | (SEPARATE_TEST if separate_test else 0) | (FULL_RASTER if full_raster else 0), tile,
+                      bin_limit, 0)
 
     def evaluate(self, scene_h: int, gen_h: int, gen, sweep, map_n: int, k: int, export_depth=False,
-                 export_bits=False, tile: int = 0, separate_test=False, full_raster=False) -> Result:
+                 export_bits=False, tile: int = 0, separate_test=False, full_raster=False,
+                 bin_limit: int = 0) -> Result:
         """Host outputs (synchronous)."""
         s = _c(sweep.sun_xyz, np.float64)
         dni, dp, dt = (_c(a, np.float64) for a in (sweep.dni, sweep.d_poa, sweep.dt_h))
@@ -211,7 +219,7 @@ class Context:
         maps = np.zeros((n, map_n, map_n), np.uint32) if export_depth else None
         bits = np.zeros((n, cells, words), np.uint32) if export_bits else None
         out = Outputs(_ptr(counts), _ptr(pw), _ptr(pr), _ptr(en), _ptr(maps), _ptr(bits), 0)
-        p = self.params(map_n, k, export_depth, export_bits, tile, separate_test, full_raster)
+        p = self.params(map_n, k, export_depth, export_bits, tile, separate_test, full_raster, bin_limit)
         _check(lib().pv3d_evaluate(self.h, scene_h, gen_h, _ptr(s), _ptr(dni), _ptr(dp), _ptr(dt), n,
                                    ctypes.byref(p), ctypes.byref(out), None), self.h)
         return Result(counts, pw, pr, en, maps, bits)
@@ -233,3 +241,59 @@ class Context:
         _check(lib().pv3d_evaluate(self.h, scene_h, gen_h, _ptr(s), _ptr(dni), _ptr(dp), _ptr(dt), n,
                                    ctypes.byref(p), ctypes.byref(out), ctypes.c_void_p(st.cuda_stream)), self.h)
         return Result(counts, pw, pr, en)
+
+    # ------------------------------------------------------------------
+    # batched form
+    # ------------------------------------------------------------------
+    def _job(self, spec, device: bool, keep: list) -> Job:
+        """spec: dict with scene, gen (handles), generator, sweep, map_n, k and optional tile,
+        bin_limit, full_raster. Host outputs are numpy arrays; device outputs torch tensors."""
+        sw, g = spec["sweep"], spec["generator"]
+        arrs = [_c(sw.sun_xyz, np.float64), _c(sw.dni, np.float64), _c(sw.d_poa, np.float64),
+                _c(sw.dt_h, np.float64)]
+        keep.append(arrs)
+        n = arrs[0].shape[0]
+        if device:
+            import torch
+            dev = torch.device("cuda", torch.cuda.current_device())
+            counts = torch.zeros((n, g.n_cells), dtype=torch.int32, device=dev) if spec.get("counts", True) else None
+            pw = torch.zeros(n, dtype=torch.float64, device=dev)
+            pr = torch.zeros(n, dtype=torch.float64, device=dev)
+            en = torch.zeros(2, dtype=torch.float64, device=dev)
+        else:
+            counts = np.zeros((n, g.n_cells), np.uint32) if spec.get("counts", True) else None
+            pw, pr, en = np.zeros(n), np.zeros(n), np.zeros(2)
+        res = Result(counts, pw, pr, en)
+        keep.append(res)
+        p = self.params(spec["map_n"], spec["k"], tile=spec.get("tile", 0), full_raster=spec.get("full_raster", False),
+                        bin_limit=spec.get("bin_limit", 0))
+        out = Outputs(_ptr(counts), _ptr(pw), _ptr(pr), _ptr(en), None, None, 1 if device else 0)
+        return Job(spec["scene"], spec["gen"], _ptr(arrs[0]), _ptr(arrs[1]), _ptr(arrs[2]), _ptr(arrs[3]), n, p, out)
+
+    def evaluate_batched(self, specs, device: bool = False, stream=None):
+        """Every job of `specs` (see _job) in one persistent launch; one Result per job."""
+        keep: list = []
+        jobs = (Job * len(specs))(*[self._job(sp, device, keep) for sp in specs])
+        results = [r for r in keep if isinstance(r, Result)]
+        st = None
+        if device:
+            import torch
+            st = ctypes.c_void_p((stream if stream is not None else torch.cuda.current_stream()).cuda_stream)
+        _check(lib().pv3d_evaluate_batched(self.h, jobs, len(specs), st), self.h)
+        return results
+
+    def autotune(self, spec, n_probe: int = 8):
+        """(tile, bin_limit, best probe milliseconds) the autotuner picks for one job."""
+        keep: list = []
+        job = self._job(dict(spec, counts=False), False, keep)
+        ms = _f64()
+        _check(lib().pv3d_autotune(self.h, ctypes.byref(job), n_probe, ctypes.byref(ms)), self.h)
+        return job.params.tile, job.params.bin_limit, ms.value
+
+    def batch_limits(self, max_slots: int = 0, slot_records: int = 0, any_xcd: bool = False):
+        _check(lib().pv3d_batch_limits(self.h, max_slots, slot_records, BATCH_ANY_XCD if any_xcd else 0), self.h)
+
+    def batch_stats(self) -> dict:
+        a = (_i64 * 7)()
+        _check(lib().pv3d_batch_stats(self.h, ctypes.byref(a)), self.h)
+        return dict(zip(("items", "units", "redone", "workgroups", "slots", "launch_us", "xcd_groups"), list(a)))

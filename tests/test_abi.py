@@ -30,7 +30,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for want in ("pv3d_create", "pv3d_destroy", "pv3d_last_error", "pv3d_scene_load", "pv3d_scene_release",
                  "pv3d_generator_define", "pv3d_generator_release", "pv3d_sun_cooper", "pv3d_evaluate",
-                 "pv3d_evaluate_batched", "pv3d_submit", "pv3d_poll", "pv3d_wait", "pv3d_cancel"):
+                 "pv3d_evaluate_batched", "pv3d_autotune", "pv3d_batch_stats", "pv3d_submit", "pv3d_poll",
+                 "pv3d_wait", "pv3d_cancel"):
         assert want in names
 
 
@@ -42,9 +43,9 @@ def test_library_exports_every_declared_symbol(lib):
 def test_struct_layouts_match_header():
     from paper_1410_5780_amd import pv3d
     assert ctypes.sizeof(pv3d.Module) == 80
-    assert ctypes.sizeof(pv3d.Params) == 16
+    assert ctypes.sizeof(pv3d.Params) == 24
     assert ctypes.sizeof(pv3d.Outputs) == 56
-    assert ctypes.sizeof(pv3d.Job) == 128
+    assert ctypes.sizeof(pv3d.Job) == 136
 
 
 def test_sun_helper_matches_input_generator(lib):
