@@ -180,9 +180,9 @@ typedef struct {
     pv3d_outputs out;
 } pv3d_job;
 
-/* All suns above the horizon of all jobs in one persistent launch (per job,
- * two small preparation launches come first: the scene's bounding sphere and
- * the sample tables). Workgroups take units of work (a sun's set-up, a range
+/* All suns above the horizon of all jobs in one persistent launch (the
+ * per-job constants, the scene's bounding sphere and the sample tables, are
+ * computed on the host and copied in). Workgroups take units of work (a sun's set-up, a range
  * of triangles, the bin scan, a range of bin entries, a tile, the sun's
  * losses) from per-slot queues in device memory; a slot holds one (job, sun)
  * item at a time and takes the next item when its sun is done, so uneven
@@ -226,18 +226,36 @@ pv3d_status pv3d_batch_limits(pv3d_ctx* ctx, int32_t max_slots, int64_t slot_rec
  * XCD, 1: by every XCD). */
 pv3d_status pv3d_batch_stats(pv3d_ctx* ctx, int64_t out[7]);
 
-/* Serving: submit a job to the context's running service loop. It is
- * admitted when its working set fits the HBM budget, then its suns join the
- * device queue that is already being drained; results are identical to
- * pv3d_evaluate. EBUSY when the pending queue is full; ENOMEM when the job
- * can never fit. ticket identifies the job. */
+/* Serving: submit a job to the context's serving loop (started by the first
+ * submit, with a service thread of its own). At its start the loop takes, of
+ * the context's unused HBM budget, its slots and then half of what is left
+ * as the arena for job data (sweep, constants, and internal outputs). Jobs
+ * are admitted in submission order as soon as their data fits the arena;
+ * every sun of an admitted job becomes an item of the live persistent launch
+ * that the loop keeps running while work is in flight, so jobs that arrive
+ * while others run share the GPU with them (continuous batching). Per job,
+ * results are identical to pv3d_evaluate with the same params (same rules
+ * as pv3d_evaluate_batched: flags 0 or FULL_RASTER, tile 0/32/64). The job's
+ * input arrays are copied before the call returns. Host outputs are written
+ * when the job completes; device outputs are written by the device while the
+ * job runs. The job's scene and generator cannot be released until it ends
+ * (EBUSY). Limits: at most 4096 modules and 65536 raster tiles per job.
+ * EBUSY: 65536 jobs wait already; ENOMEM: the job's data can never fit the
+ * arena. ticket identifies the job. */
 pv3d_status pv3d_submit(pv3d_ctx* ctx, const pv3d_job* job, uint64_t* ticket);
-/* done = 1 once the job's outputs are in place, 0 while it runs. */
+/* done = 1 once the job has ended (outputs in place, cancelled or failed). */
 pv3d_status pv3d_poll(pv3d_ctx* ctx, uint64_t ticket, int32_t* done);
-/* Block until the job is done; ECANCELED if it was cancelled. Forgets the ticket. */
+/* Block until the job has ended; ECANCELED if it was cancelled, the failure's
+ * code if it failed. Forgets the ticket. */
 pv3d_status pv3d_wait(pv3d_ctx* ctx, uint64_t ticket);
-/* Cancel a job that has not completed; its outputs are left undefined. */
+/* Cancel a job. A job not yet admitted never runs; an admitted one runs to
+ * its end but its host outputs are not written (device outputs may be, until
+ * pv3d_wait returns). Outputs are undefined either way. */
 pv3d_status pv3d_cancel(pv3d_ctx* ctx, uint64_t ticket);
+/* Serving statistics: out[0] jobs ended, out[1] persistent launches started
+ * by the loop, out[2] items (suns) published, out[3] jobs waiting for
+ * admission. */
+pv3d_status pv3d_serve_stats(pv3d_ctx* ctx, int64_t out[4]);
 
 /* Kernel timing, a profiling aid. With bit i of stage_mask set, the per-sun
  * path records a pair of HIP events on its stream around every launch of

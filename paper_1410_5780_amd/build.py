@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpv3d.so")
-SOURCES = ["pv3d_kernels.hip", "pv3d_runtime.hip", "pv3d_service.hip"]
+SOURCES = ["pv3d_kernels.hip", "pv3d_runtime.hip", "pv3d_service.hip", "pv3d_serve.hip"]
 ARCH = os.environ.get("PV3D_ARCH", "gfx950")
 
 

@@ -115,6 +115,7 @@ enum : int32_t {
     kPhScatter = 4,   // a unit per kScatterPerUnit records: bins
     kPhTile = 5,      // a unit per listed tile: raster and sample depth check
     kPhLoss = 6,      // 1 unit: string powers of the sun
+    kPhAdmit = 7,     // serving: a workgroup is putting a newly published item into the slot
 };
 constexpr int32_t kTriPerUnit = 1024;
 constexpr int32_t kScatterPerUnit = 2048;
@@ -136,6 +137,10 @@ struct PJob {
     const double* fv;
     int64_t n_sun, cells;
     int32_t n, k, tile, sparse, use_mask, large_tiles, ntx, n_tiles, words, n_items;
+    uint32_t done_target;    // job_done value once every item of the job is done
+    uint32_t ovf_base;       // job_overflow value when the job started (more: a sun overflowed)
+    uint32_t seq;            // serving: completion tag written to the report word
+    int32_t pad2;
 };
 
 // (job, sun) of one item; the items of a job are consecutive.
@@ -167,10 +172,11 @@ struct PSlotBufs {
 struct alignas(128) PSlotState {
     unsigned long long word;
     uint32_t done;           // units of the current phase completed
-    int32_t item;            // item held
+    int32_t item;            // item held (its position in the launch's item order)
     int32_t n_list;          // tiles listed by the scan
     int32_t overflow;        // 1: a capacity was exceeded, the host evaluates the sun again
-    int32_t pad[26];
+    int32_t job, sun;        // what the item is
+    int32_t pad[24];
 };
 static_assert(sizeof(PSlotState) == 128, "PSlotState layout");
 
@@ -196,10 +202,17 @@ struct PLaunch {
     int32_t n_slots, rec_cap, bin_cap;
     int32_t groups;              // 8: slot i is served by the XCD whose id is i % 8; 1: by every XCD
     long long stall_ticks;       // wall-clock ticks without progress before the watchdog fires
+    // serving: items arrive while the launch runs
+    int32_t serve;               // 1: take items from feed instead of items
+    uint32_t feed_cap;           // entries of the feed ring
+    const unsigned long long* feed;   // host memory: ring of items, (job slot << 32) | sun
+    const uint32_t* feed_pub;    // host memory: items published so far
+    const uint32_t* stop_flag;   // host memory: nonzero asks the launch to end once idle
+    uint32_t* report;            // host memory: [job slots] completion tag of the last job done
+    long long idle_ticks;        // wall-clock ticks of idleness before the launch ends by itself
 };
 
 // ---- launch wrappers (pv3d_kernels.hip) -----------------------------------
-hipError_t launch_module_normals(Module* mods, int32_t n_mod, hipStream_t st);
 hipError_t launch_bounds(const SceneDev& sc, const GenDev& g, double* partial, int32_t n_part,
                          double* sphere, hipStream_t st);
 int32_t bounds_partials(int64_t n_points);

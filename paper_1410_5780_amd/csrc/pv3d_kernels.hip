@@ -56,16 +56,6 @@ __device__ __forceinline__ T ld_dev(const T* p) {
 // ---------------------------------------------------------------------------
 // generator preparation
 // ---------------------------------------------------------------------------
-__global__ void k_module_normals(Module* mods, int32_t n_mod) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_mod) return;
-    d3 c = cross(ld3(mods[i].u), ld3(mods[i].v));
-    double l = sqrt(dot(c, c));
-    mods[i].n[0] = c.x / l;
-    mods[i].n[1] = c.y / l;
-    mods[i].n[2] = c.z / l;
-}
-
 __device__ __forceinline__ void module_corner(const Module& m, int q, d3& p) {
     d3 o = ld3(m.o), u = ld3(m.u), v = ld3(m.v);
     if (q == 0) p = o;
@@ -604,8 +594,13 @@ __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& b
     for (int32_t i = b0; i < b1; i++) {
         const int32_t c = COHERENT ? ld_dev(bb.tile_count + i) : bb.tile_count[i];
         bb.tile_start[i] = run;
-        bb.tile_cursor[i] = run;
-        bb.tile_count[i] = 0;
+        if (COHERENT) {       // words other units update with atomics are written with atomics only
+            __hip_atomic_store(bb.tile_cursor + i, run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(bb.tile_count + i, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            bb.tile_cursor[i] = run;
+            bb.tile_count[i] = 0;
+        }
         if (list && c > 0) list[lpos++] = i;
         run += c;
     }
@@ -1620,6 +1615,9 @@ __device__ __noinline__ void unit_setup(unsigned char* raw, const PJob& J, const
         __hip_atomic_store(&B.ctr->n_large, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&B.ctr->overflow, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    uint32_t* row = J.counts + (int64_t)it.sun * J.cells;     // tile units add to it with atomics
+    for (int64_t c = threadIdx.x; c < J.cells; c += 256)
+        __hip_atomic_store(row + c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const TileGrid tg{J.tile, J.ntx, J.n_tiles, J.words};
     setup_body(*reinterpret_cast<SetupLds*>(raw), J.sun + 3 * it.sun, J.dni[it.sun], J.g, J.sphere, J.n, B.view,
                B.beam, B.bias, tg, J.use_mask ? B.tmask : nullptr);
@@ -1640,8 +1638,9 @@ __device__ __noinline__ void unit_scan(unsigned char* raw, const PLaunch& P, con
     const int32_t n_list = scan_body<256, true>(part, J.n_tiles, bb, B.tile_list);
     if (threadIdx.x == 0) {
         const int32_t total = part[255];
-        st.n_list = n_list;
-        st.overflow = (ld_dev(&B.ctr->overflow) || ld_dev(&B.ctr->n_rec) > P.rec_cap || total > P.bin_cap) ? 1 : 0;
+        const int32_t ovf = (ld_dev(&B.ctr->overflow) || ld_dev(&B.ctr->n_rec) > P.rec_cap || total > P.bin_cap) ? 1 : 0;
+        __hip_atomic_store(&st.n_list, n_list, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&st.overflow, ovf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -1674,18 +1673,15 @@ __device__ __noinline__ void unit_loss(unsigned char* raw, const PJob& J, const 
               J.dpoa[it.sun], J.g, J.k, J.power + it.sun, J.power_ref + it.sun);
 }
 
-// Coherence of the persistent launch. Every unit ends with a device-scope
-// release (dirty L2 lines written back, nothing invalidated). With XCD
+// Coherence of the persistent launch. Taking a unit is a device-scope
+// acquire (this CU's L1 and the L2's non-coherent lines dropped, dirty lines
+// kept), so a unit never reads a line cached before its inputs were written,
+// even when a slot's buffers held another item a moment ago. With XCD
 // groups, the units of a slot run on one XCD, whose L2 every producer and
-// consumer of the slot's buffers share, so taking a unit only has to drop
-// this CU's L1; words that other units update with atomics are read with
-// ld_dev. Without groups, taking a unit invalidates L1 and L2.
-__device__ __forceinline__ void acquire_unit(int32_t groups) {
-    if (groups > 1)
-        asm volatile("buffer_inv sc0" ::: "memory");
-    else
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
+// consumer of the slot's buffers share, so a unit's release only has to wait
+// for its own stores; without groups it writes the L2 back to memory. Words
+// that other units update with atomics are read with ld_dev.
+__device__ __forceinline__ void acquire_unit(int32_t) { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 // s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15): every vector memory access of the wave done
 constexpr int kWaitVmem = 0x0F70;
@@ -1698,8 +1694,50 @@ struct PCtl {
 };
 
 __device__ __forceinline__ void publish(PSlotState& st, int32_t phase, int32_t n_units) {
-    st.done = 0;
+    __hip_atomic_store(&st.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&st.word, pword(phase, n_units), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_dev(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Put the next item into slot st (one lane). Batch: the next entry of the
+// item list. Serving: the next published entry of the feed, if any.
+__device__ bool admit(const PLaunch& P, PSlotState& st) {
+    int32_t item, job, sun;
+    if (!P.serve) {
+        const uint32_t ni = atomicAdd(&P.sched->next_item, 1u);
+        if (ni >= P.sched->n_items) return false;
+        const PItem it = P.items[ni];
+        item = (int32_t)ni;
+        job = it.job;
+        sun = it.sun;
+    } else {
+        for (;;) {
+            uint32_t cur = ld_dev(&P.sched->next_item);
+            const uint32_t pub = __hip_atomic_load(P.feed_pub, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+            if ((int32_t)(pub - cur) <= 0) return false;
+            if (__hip_atomic_compare_exchange_strong(&P.sched->next_item, &cur, cur + 1, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                const unsigned long long e = __hip_atomic_load(P.feed + (cur % P.feed_cap), __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_SYSTEM);
+                item = (int32_t)(cur & 0x7FFFFFFFu);
+                job = (int32_t)(e >> 32);
+                sun = (int32_t)(e & 0xFFFFFFFFu);
+                // the job's table entry and inputs were copied in by the host before it published
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                break;
+            }
+        }
+    }
+    st_dev(&st.item, item);
+    st_dev(&st.job, job);
+    st_dev(&st.sun, sun);
+    st_dev(&st.overflow, 0);
+    st_dev(&st.n_list, 0);
+    return true;
 }
 
 // The last unit of a phase moves its item on (thread 0 decides; the whole
@@ -1707,9 +1745,9 @@ __device__ __forceinline__ void publish(PSlotState& st, int32_t phase, int32_t n
 __device__ void advance(const PLaunch& P, PCtl& ctl, double* stage, int32_t slot, int32_t phase) {
     const int tid = threadIdx.x;
     PSlotState& st = P.state[slot];
-    const int32_t item = st.item;
-    const PItem it = P.items[item];
-    const PJob& J = P.jobs[it.job];
+    const int32_t item = ld_dev(&st.item);
+    const int32_t job = ld_dev(&st.job);
+    const PJob& J = P.jobs[job];
     const PSlotBufs& B = P.slots[slot];
     if (tid == 0) {
         bool item_done = false;
@@ -1725,7 +1763,7 @@ __device__ void advance(const PLaunch& P, PCtl& ctl, double* stage, int32_t slot
                 break;
             case kPhTri: publish(st, kPhScan, 1); break;
             case kPhScan:
-                if (st.overflow) {
+                if (ld_dev(&st.overflow)) {
                     item_done = true;
                 } else {
                     const int32_t items = min(ld_dev(&B.ctr->n_rec), P.rec_cap) + J.g.n_mod;
@@ -1734,72 +1772,74 @@ __device__ void advance(const PLaunch& P, PCtl& ctl, double* stage, int32_t slot
                 break;
             case kPhScatter:
                 if (ld_dev(&B.ctr->overflow)) {
-                    st.overflow = 1;
+                    st_dev(&st.overflow, 1);
                     item_done = true;
-                } else if (st.n_list > 0) {
-                    publish(st, kPhTile, st.n_list);
                 } else {
-                    publish(st, kPhLoss, 1);
+                    const int32_t nl = ld_dev(&st.n_list);
+                    if (nl > 0) publish(st, kPhTile, nl);
+                    else publish(st, kPhLoss, 1);
                 }
                 break;
             case kPhTile: publish(st, kPhLoss, 1); break;
             default: item_done = true; break;
         }
         if (item_done) {
-            if (st.overflow) {
-                const uint32_t q = atomicAdd(&P.sched->n_overflow, 1u);
-                P.overflow_items[q] = item;
-                __hip_atomic_store(&P.job_overflow[it.job], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (ld_dev(&st.overflow)) {
+                if (!P.serve) {
+                    const uint32_t q = atomicAdd(&P.sched->n_overflow, 1u);
+                    P.overflow_items[q] = item;
+                }
+                atomicAdd(reinterpret_cast<uint32_t*>(&P.job_overflow[job]), 1u);
             }
             const uint32_t jd =
-                __hip_atomic_fetch_add(&P.job_done[it.job], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1;
-            if (jd == (uint32_t)J.n_items &&
-                __hip_atomic_load(&P.job_overflow[it.job], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-                ctl.job_last = 1;
+                __hip_atomic_fetch_add(&P.job_done[job], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) + 1;
+            if (jd == J.done_target) {
+                const bool clean = (uint32_t)ld_dev(&P.job_overflow[job]) == J.ovf_base;
+                ctl.job_last = clean ? 1 : 2;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the job's powers come from every XCD
-            } else {
-                ctl.job_last = 0;
             }
-            ctl.job = it.job;
+            ctl.job = job;
             // the slot takes the next item
-            const uint32_t ni = atomicAdd(&P.sched->next_item, 1u);
-            st.overflow = 0;
-            st.n_list = 0;
-            if (ni < P.sched->n_items) {
-                st.item = (int32_t)ni;
-                publish(st, kPhSetup, 1);
-            } else {
-                publish(st, kPhIdle, 0);
-            }
-            if (!ctl.job_last) __hip_atomic_fetch_add(&P.sched->items_done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (admit(P, st)) publish(st, kPhSetup, 1);
+            else publish(st, kPhIdle, 0);
+            if (!ctl.job_last && !P.serve)
+                __hip_atomic_fetch_add(&P.sched->items_done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     __syncthreads();
     if (ctl.job_last) {
-        // energy of the finished job: sum of power * dt in sun order, as the per-sun path sums it
         const PJob& JJ = P.jobs[ctl.job];
-        double e = 0.0, er = 0.0;
-        for (int64_t t0 = 0; t0 < JJ.n_sun; t0 += 256) {
-            const int64_t t = t0 + tid;
-            if (t < JJ.n_sun) {
-                stage[tid] = JJ.power[t];
-                stage[256 + tid] = JJ.power_ref[t];
-                stage[512 + tid] = JJ.dt[t];
-            }
-            __syncthreads();
-            if (tid == 0) {
-                const int64_t m = min((int64_t)256, JJ.n_sun - t0);
-                for (int64_t q = 0; q < m; q++) {
-                    e += stage[q] * stage[512 + q];
-                    er += stage[256 + q] * stage[512 + q];
+        if (ctl.job_last == 1) {
+            // energy of the finished job: sum of power * dt in sun order, as the per-sun path sums it
+            double e = 0.0, er = 0.0;
+            for (int64_t t0 = 0; t0 < JJ.n_sun; t0 += 256) {
+                const int64_t t = t0 + tid;
+                if (t < JJ.n_sun) {
+                    stage[tid] = JJ.power[t];
+                    stage[256 + tid] = JJ.power_ref[t];
+                    stage[512 + tid] = JJ.dt[t];
                 }
+                __syncthreads();
+                if (tid == 0) {
+                    const int64_t m = min((int64_t)256, JJ.n_sun - t0);
+                    for (int64_t q = 0; q < m; q++) {
+                        e += stage[q] * stage[512 + q];
+                        er += stage[256 + q] * stage[512 + q];
+                    }
+                }
+                __syncthreads();
             }
-            __syncthreads();
+            if (tid == 0) {
+                JJ.energy[0] = e;
+                JJ.energy[1] = er;
+            }
         }
         if (tid == 0) {
-            JJ.energy[0] = e;
-            JJ.energy[1] = er;
-            __hip_atomic_fetch_add(&P.sched->items_done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (P.serve)      // outputs written back, then the tag the host waits for
+                __hip_atomic_store(P.report + ctl.job, JJ.seq | (ctl.job_last == 2 ? 0x80000000u : 0u),
+                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            else
+                __hip_atomic_fetch_add(&P.sched->items_done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -1814,7 +1854,7 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
     const int32_t n_mine = my < P.n_slots ? (P.n_slots - my + G - 1) / G : 0;
     int32_t home = n_mine > 0 ? (int32_t)((blockIdx.x / (unsigned)G) % (unsigned)n_mine) : 0;
     unsigned long long seen_units = ~0ull;
-    long long seen_at = 0;
+    long long seen_at = 0, quiet_since = -1;
     int32_t backoff = 1;
     for (;;) {
         if (tid < 64) {                                   // wave 0 looks for a unit
@@ -1830,7 +1870,7 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
                 int32_t key = INT32_MAX;
                 if (kk < n_mine &&
                     w_open(__hip_atomic_load(&P.state[i].word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
-                    key = __hip_atomic_load(&P.state[i].item, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    key = ld_dev(&P.state[i].item);
                 for (int attempt = 0; attempt < 64 && got < 0; attempt++) {
                     int32_t kmin = key, l = lane;
                     for (int off = 32; off > 0; off >>= 1) {
@@ -1863,6 +1903,37 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
                     }
                 }
             }
+            bool refilled = false;
+            if (got < 0 && !aborted && P.serve && n_mine > 0) {
+                // serving: an idle slot of this XCD takes a newly published item
+                const uint32_t pub = __hip_atomic_load(P.feed_pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                if ((int32_t)(pub - ld_dev(&P.sched->next_item)) > 0) {
+                    for (int32_t base = 0; base < n_mine && !refilled; base += 64) {
+                        const int32_t kk = base + lane;
+                        const int32_t i = my + kk * G;
+                        unsigned long long w = 0;
+                        bool idle = false;
+                        if (kk < n_mine) {
+                            w = __hip_atomic_load(&P.state[i].word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            idle = w_phase(w) == kPhIdle;
+                        }
+                        const unsigned long long m = __ballot(idle);
+                        if (m != 0ull) {
+                            const int l = __ffsll((long long)m) - 1;
+                            if (lane == l) {
+                                unsigned long long exp = w;
+                                if (__hip_atomic_compare_exchange_strong(&P.state[i].word, &exp, pword(kPhAdmit, 0),
+                                                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                                         __HIP_MEMORY_SCOPE_AGENT)) {
+                                    if (admit(P, P.state[i])) publish(P.state[i], kPhSetup, 1);
+                                    else publish(P.state[i], kPhIdle, 0);
+                                }
+                            }
+                            refilled = true;
+                        }
+                    }
+                }
+            }
             if (got >= 0) {
                 home = gj;
                 backoff = 1;
@@ -1873,28 +1944,51 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
                 ctl.phase = phase;
                 ctl.units = units;
                 ctl.stop = 0;
-                if (got >= 0) {
-                    acquire_unit(G);                           // see what the unit's inputs' writers released
-                } else {
-                    const uint32_t done = __hip_atomic_load(&P.sched->items_done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                    if (done >= P.sched->n_items || aborted) {
-                        ctl.stop = 1;
-                    } else {
+            }
+            if (got >= 0) {
+                if (lane == 0) acquire_unit(G);                // see what the unit's inputs' writers released
+            } else if (!refilled) {
+                bool stop = aborted, quiet = false;
+                if (!stop && !P.serve) {
+                    stop = __hip_atomic_load(&P.sched->items_done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >=
+                           P.sched->n_items;
+                } else if (!stop) {
+                    // serving: quiet when every slot is idle and nothing waits in the feed
+                    bool busy = false;
+                    for (int32_t base = 0; base < P.n_slots; base += 64)
+                        if (base + lane < P.n_slots &&
+                            w_phase(__hip_atomic_load(&P.state[base + lane].word, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT)) != kPhIdle)
+                            busy = true;
+                    busy = __ballot(busy) != 0ull;
+                    const uint32_t pub = __hip_atomic_load(P.feed_pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    quiet = !busy && (int32_t)(pub - ld_dev(&P.sched->next_item)) <= 0;
+                }
+                if (lane == 0) {
+                    const long long now = (long long)wall_clock64();
+                    if (!stop && quiet) {
+                        if (quiet_since < 0) quiet_since = now;
+                        if (__hip_atomic_load(P.stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u ||
+                            now - quiet_since > P.idle_ticks)
+                            stop = true;
+                    } else if (!stop) {
+                        quiet_since = -1;
                         const unsigned long long u =
                             __hip_atomic_load(&P.sched->units, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        const long long now = (long long)wall_clock64();
                         if (u != seen_units) {
                             seen_units = u;
                             seen_at = now;
                         } else if (now - seen_at > P.stall_ticks) {
                             __hip_atomic_store(&P.sched->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            ctl.stop = 1;
+                            stop = true;
                         }
-                        for (int32_t q = 0; q < backoff; q++) __builtin_amdgcn_s_sleep(8);
                     }
+                    if (!stop)
+                        for (int32_t q = 0; q < backoff; q++) __builtin_amdgcn_s_sleep(8);
+                    ctl.stop = stop ? 1 : 0;
                 }
+                if (backoff < 32) backoff *= 2;
             }
-            if (got < 0 && backoff < 32) backoff *= 2;
         }
         __syncthreads();
         const int32_t slot = ctl.slot, unit = ctl.unit, phase = ctl.phase;
@@ -1906,7 +2000,7 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
         }
         {
             PSlotState& st = P.state[slot];
-            const PItem it = P.items[st.item];
+            const PItem it{ld_dev(&st.job), ld_dev(&st.sun)};
             const PJob& J = P.jobs[it.job];
             const PSlotBufs& B = P.slots[slot];
             const BinBuffers bb = slot_bins(P, J, B);
@@ -1921,8 +2015,12 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
         }
         // this unit's writes, before it counts as done: complete in the XCD's L2 when the
         // slot's readers share it, else (and for the powers the energy sum reads from
-        // every XCD) written back to memory
-        if (G > 1 && phase != kPhLoss)
+        // every XCD) written back to memory; while serving, the host's copy engine reads
+        // a job's counts and powers as soon as its tag is set, so the last unit of every
+        // item writes its XCD's dirty lines back for the host too
+        if (P.serve && phase == kPhLoss)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        else if (G > 1 && phase != kPhLoss)
             __builtin_amdgcn_s_waitcnt(kWaitVmem);
         else
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -1952,11 +2050,6 @@ inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) /
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
-hipError_t launch_module_normals(Module* mods, int32_t n_mod, hipStream_t st) {
-    hipLaunchKernelGGL(k_module_normals, dim3(grid_for(n_mod, 256)), dim3(256), 0, st, mods, n_mod);
-    return hipGetLastError();
-}
-
 int32_t bounds_partials(int64_t n_points) {
     int64_t b = (n_points + 255) / 256;
     return (int32_t)(b < 1 ? 1 : (b > 1024 ? 1024 : b));

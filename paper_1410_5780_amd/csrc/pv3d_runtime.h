@@ -38,9 +38,13 @@ struct Scene {
     double* xyz = nullptr;
     int32_t* tri = nullptr;
     int64_t n_vert = 0, n_tri = 0;
+    double lo[3], hi[3];          // axis-aligned box of the vertices (+inf / -inf when empty)
+    int32_t users = 0;            // jobs of the serving loop that read it
 };
 
 struct Gen {
+    double lo[3], hi[3];          // axis-aligned box of the module corners
+    int32_t users = 0;            // jobs of the serving loop that read it
     Module* mods = nullptr;
     int32_t* cell_sub = nullptr;
     int32_t* str_start = nullptr;
@@ -68,6 +72,14 @@ struct Work {
 struct BatchState;
 struct Server;
 
+// What the persistent kernel needs to know about the device, probed once.
+struct DevInfo {
+    int32_t blocks_per_cu = 0, n_cu = 0;
+    int32_t xcd_groups = 1;       // 8 when the workgroups of a full launch show XCD ids 0..7
+    long long stall_ticks = 0;
+    int rate_khz = 100000;        // wall clock of the device
+};
+
 // Event pairs around launches of selected stages (profiling aid).
 struct Profiler {
     uint32_t mask = 0;
@@ -84,6 +96,8 @@ struct Profiler {
 };
 
 PathSizes path_sizes(const Scene& sc, const Gen& g, const pv3d_params& p, int64_t n_sun);
+void host_sphere(const Scene& sc, const Gen& g, double sphere[4]);
+void host_sample_tables(int32_t k, int32_t n_cu, int32_t n_cv, double* fu, double* fv);
 int32_t choose_tile(const pv3d_params& p);
 SceneDev scene_dev(const Scene& sc);
 GenDev gen_dev(const Gen& g);
@@ -108,6 +122,11 @@ struct Ctx {
     hipEvent_t staging_done = nullptr;
     BatchState* batch = nullptr;
     Server* server = nullptr;
+    DevInfo dev_info;
+    // pv3d_batch_limits: slots of the batched form and the serving loop
+    int32_t batch_max_slots = 128;
+    int64_t batch_slot_records = 1 << 20;
+    bool batch_any_xcd = false;
     Profiler prof;
 
     pv3d_status dalloc(void** p, size_t bytes, const char* what);

@@ -314,6 +314,28 @@ BinBuffers Ctx::bin_buffers(const PathSizes& z) {
     return bb;
 }
 
+// Bounding sphere of the scene vertices and module corners: centre and half
+// diagonal of their axis-aligned box (the kernels' bounds reduction computes
+// the same values from the same IEEE operations).
+void host_sphere(const Scene& sc, const Gen& g, double sphere[4]) {
+    double lo[3], hi[3];
+    for (int c = 0; c < 3; c++) {
+        lo[c] = std::fmin(sc.lo[c], g.lo[c]);
+        hi[c] = std::fmax(sc.hi[c], g.hi[c]);
+    }
+    const double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+    sphere[0] = (lo[0] + hi[0]) * 0.5;
+    sphere[1] = (lo[1] + hi[1]) * 0.5;
+    sphere[2] = (lo[2] + hi[2]) * 0.5;
+    sphere[3] = 0.5 * std::sqrt((dx * dx + dy * dy) + dz * dz);
+}
+
+// Fractional sample positions along a module edge, (q + 1/2) / (k n).
+void host_sample_tables(int32_t k, int32_t n_cu, int32_t n_cv, double* fu, double* fv) {
+    for (int32_t i = 0; i < k * n_cu; i++) fu[i] = ((double)i + 0.5) / (double)(k * n_cu);
+    for (int32_t i = 0; i < k * n_cv; i++) fv[i] = ((double)i + 0.5) / (double)(k * n_cv);
+}
+
 SceneDev scene_dev(const Scene& sc) {
     SceneDev d;
     d.xyz = sc.xyz;
@@ -529,6 +551,15 @@ pv3d_status pv3d_scene_load(pv3d_ctx* ctx, const double* xyz, int64_t n_vert, co
     Scene s;
     s.n_vert = n_vert;
     s.n_tri = n_tri;
+    for (int c = 0; c < 3; c++) {
+        s.lo[c] = INFINITY;
+        s.hi[c] = -INFINITY;
+    }
+    for (int64_t i = 0; i < n_vert; i++)
+        for (int c = 0; c < 3; c++) {
+            s.lo[c] = std::fmin(s.lo[c], xyz[3 * i + c]);
+            s.hi[c] = std::fmax(s.hi[c], xyz[3 * i + c]);
+        }
     pv3d_status st;
     if ((st = ctx->dalloc((void**)&s.xyz, 24 * (size_t)n_vert, "scene vertices"))) return st;
     if ((st = ctx->dalloc((void**)&s.tri, 12 * (size_t)n_tri, "scene triangles"))) {
@@ -586,6 +617,11 @@ pv3d_status pv3d_generator_define(pv3d_ctx* ctx, const pv3d_module* mods, int64_
             D.u[c] = M.edge_u[c];
             D.v[c] = M.edge_v[c];
         }
+        // unit front normal u x v / |u x v|, the same IEEE operations the kernels use
+        const double l = std::sqrt((cx * cx + cy * cy) + cz * cz);
+        D.n[0] = cx / l;
+        D.n[1] = cy / l;
+        D.n[2] = cz / l;
     }
     std::vector<int32_t> seen((size_t)n_sub, 0);
     for (int32_t c = 0; c < n_cu * n_cv; c++) {
@@ -614,6 +650,20 @@ pv3d_status pv3d_generator_define(pv3d_ctx* ctx, const pv3d_module* mods, int64_
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     (void)hipSetDevice(ctx->device);
     Gen g;
+    for (int c = 0; c < 3; c++) {
+        g.lo[c] = INFINITY;
+        g.hi[c] = -INFINITY;
+    }
+    for (int64_t m = 0; m < n_mod; m++) {
+        const Module& D = hm[(size_t)m];
+        for (int q = 0; q < 4; q++) {                 // corners o, o+u, (o+u)+v, o+v
+            for (int c = 0; c < 3; c++) {
+                const double p = q == 0 ? D.o[c] : q == 1 ? D.o[c] + D.u[c] : q == 2 ? (D.o[c] + D.u[c]) + D.v[c] : D.o[c] + D.v[c];
+                g.lo[c] = std::fmin(g.lo[c], p);
+                g.hi[c] = std::fmax(g.hi[c], p);
+            }
+        }
+    }
     g.n_mod = n_mod;
     g.n_cu = n_cu;
     g.n_cv = n_cv;
@@ -630,8 +680,6 @@ pv3d_status pv3d_generator_define(pv3d_ctx* ctx, const pv3d_module* mods, int64_
     if ((e = hipMemcpy(g.cell_sub, cell_substring, 4 * (size_t)(n_cu * n_cv), hipMemcpyHostToDevice))) return hip_fail(e, "copy cell map");
     if ((e = hipMemcpy(g.str_start, start.data(), 4 * (size_t)(n_str + 1), hipMemcpyHostToDevice))) return hip_fail(e, "copy strings");
     if ((e = hipMemcpy(g.str_mods, order.data(), 4 * (size_t)n_mod, hipMemcpyHostToDevice))) return hip_fail(e, "copy strings");
-    if ((e = launch_module_normals(g.mods, (int32_t)n_mod, ctx->stream))) return hip_fail(e, "module normals");
-    if ((e = hipStreamSynchronize(ctx->stream))) return hip_fail(e, "module normals");
     uint64_t h = ++ctx->next_handle;
     ctx->gens[h] = g;
     *gen_out = h;

@@ -3,23 +3,25 @@
 // bin sizes.
 //
 // Host side of a batch:
-//   1. validate the jobs, copy their sweeps to the device in one staging pass;
-//   2. per job: bounding sphere and sample tables (two small launches), and
-//      zeroed outputs (suns below the horizon keep zero power);
-//   3. size the slots (work buffers of one item each) from the largest job
+//   1. validate the jobs, copy their sweeps and constants (bounding sphere,
+//      sample tables, computed on the host) to the device in one staging pass,
+//      and zero their outputs (suns below the horizon keep zero power);
+//   2. size the slots (work buffers of one item each) from the largest job
 //      and the HBM budget, zero their tile counters, seed the first items;
-//   4. one persistent launch over the list of suns above the horizon;
-//   5. suns that exceeded a slot's capacity are evaluated again with the
+//   3. one persistent launch over the list of suns above the horizon;
+//   4. suns that exceeded a slot's capacity are evaluated again with the
 //      per-sun path, and their jobs' energies summed again;
-//   6. copy host outputs back.
+//   5. copy host outputs back.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include "../../include/pv3d.h"
+#include "pv3d_batch.h"
 #include "pv3d_device.h"
 #include "pv3d_runtime.h"
 
@@ -27,27 +29,16 @@ using namespace pv3d;
 
 namespace pv3d {
 
-constexpr int32_t kMaxSlots = 128;          // items in flight
-constexpr int64_t kSlotRecCap = 1 << 20;    // set-up records per slot (more: the sun goes to the per-sun path)
-constexpr double kStallSeconds = 5.0;       // watchdog of the persistent launch
-
 struct BatchState {
-    Buf slotmem, slots, state, sched, jobs, items, jobdone, overflow, jobmem, partial, energy_tmp;
-    int32_t max_slots = kMaxSlots;
-    int64_t slot_records = kSlotRecCap;
-    int32_t xcd_groups = 1;       // 8 when every slot can be served by one XCD
-    bool any_xcd = false;         // PV3D_BATCH_ANY_XCD
+    Buf slotmem, slots, state, sched, jobs, items, jobdone, overflow, jobmem, energy_tmp;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    int32_t blocks_per_cu = 0, n_cu = 0;
-    long long stall_ticks = 0;
     int64_t stats[7] = {};
 };
 
 void Ctx::release_batched() {
     if (!batch) return;
     BatchState& b = *batch;
-    Buf* all[] = {&b.slotmem, &b.slots, &b.state, &b.sched, &b.jobs, &b.items,
-                  &b.jobdone, &b.overflow, &b.jobmem, &b.partial, &b.energy_tmp};
+    Buf* all[] = {&b.slotmem, &b.slots, &b.state, &b.sched, &b.jobs, &b.items, &b.jobdone, &b.overflow, &b.jobmem, &b.energy_tmp};
     for (Buf* x : all) x->release(this);
     if (b.ev0) (void)hipEventDestroy(b.ev0);
     if (b.ev1) (void)hipEventDestroy(b.ev1);
@@ -55,29 +46,10 @@ void Ctx::release_batched() {
     batch = nullptr;
 }
 
-bool Ctx::scene_in_use(uint64_t) { return false; }
-bool Ctx::gen_in_use(uint64_t) { return false; }
-
-static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// Host view of one job of a batch.
-struct HostJob {
-    const Scene* sc;
-    const Gen* g;
-    pv3d_job job;
-    int32_t tile, ntx, n_tiles, words, large_tiles, sparse, use_mask;
-    int64_t cells, tri_all, n_items;
-    // device regions
-    double *d_sun, *d_dni, *d_dpoa, *d_dt, *d_sphere, *d_fu, *d_fv;
-    uint32_t* d_counts;
-    double *d_power, *d_pref, *d_energy;
-};
-
-static pv3d_status batch_state(Ctx* c, BatchState** out) {
-    if (!c->batch) {
-        std::unique_ptr<BatchState> b(new BatchState());
+pv3d_status device_info(Ctx* c, DevInfo* out) {
+    if (c->dev_info.n_cu == 0) {
+        DevInfo d;
         hipError_t e;
-        if ((e = hipEventCreate(&b->ev0)) || (e = hipEventCreate(&b->ev1))) return hip_fail(e, "hipEventCreate");
         int32_t bpc = 0;
         if ((e = persist_blocks_per_cu(&bpc))) return hip_fail(e, "occupancy of the persistent kernel");
         hipDeviceProp_t prop;
@@ -85,29 +57,39 @@ static pv3d_status batch_state(Ctx* c, BatchState** out) {
         int rate_khz = 0;
         if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess || rate_khz <= 0)
             rate_khz = 100000;
-        b->blocks_per_cu = std::max(1, bpc);
-        b->n_cu = std::max(1, prop.multiProcessorCount);
-        b->stall_ticks = (long long)(kStallSeconds * 1000.0 * (double)rate_khz);
-        {   // XCD ids the workgroups of a full-device launch run on
-            uint32_t* d_mask = nullptr;
-            if ((e = hipMalloc(&d_mask, 256))) return hip_fail(e, "hipMalloc");
-            uint32_t mask = 0;
-            e = hipMemsetAsync(d_mask, 0, 4, c->stream);
-            if (!e) e = launch_xcc_probe(d_mask, 8 * b->n_cu, c->stream);
-            if (!e) e = hipMemcpyAsync(&mask, d_mask, 4, hipMemcpyDeviceToHost, c->stream);
-            if (!e) e = hipStreamSynchronize(c->stream);
-            (void)hipFree(d_mask);
-            if (e) return hip_fail(e, "XCD probe");
-            b->xcd_groups = mask == 0xFFu ? 8 : 1;
-        }
+        d.blocks_per_cu = std::max(1, bpc);
+        d.n_cu = std::max(1, prop.multiProcessorCount);
+        d.rate_khz = rate_khz;
+        d.stall_ticks = (long long)(kStallSeconds * 1000.0 * (double)rate_khz);
+        // XCD ids the workgroups of a full-device launch run on
+        uint32_t* d_mask = nullptr;
+        if ((e = hipMalloc(&d_mask, 256))) return hip_fail(e, "hipMalloc");
+        uint32_t mask = 0;
+        e = hipMemsetAsync(d_mask, 0, 4, c->stream);
+        if (!e) e = launch_xcc_probe(d_mask, 8 * d.n_cu, c->stream);
+        if (!e) e = hipMemcpyAsync(&mask, d_mask, 4, hipMemcpyDeviceToHost, c->stream);
+        if (!e) e = hipStreamSynchronize(c->stream);
+        (void)hipFree(d_mask);
+        if (e) return hip_fail(e, "XCD probe");
+        d.xcd_groups = mask == 0xFFu ? 8 : 1;
+        c->dev_info = d;
+    }
+    *out = c->dev_info;
+    return PV3D_OK;
+}
+
+static pv3d_status batch_state(Ctx* c, BatchState** out) {
+    if (!c->batch) {
+        std::unique_ptr<BatchState> b(new BatchState());
+        hipError_t e;
+        if ((e = hipEventCreate(&b->ev0)) || (e = hipEventCreate(&b->ev1))) return hip_fail(e, "hipEventCreate");
         c->batch = b.release();
     }
     *out = c->batch;
     return PV3D_OK;
 }
 
-// Validate one job and fill its host view (no device work).
-static pv3d_status check_job(Ctx* c, const pv3d_job& j, int64_t idx, HostJob& h) {
+pv3d_status check_job(Ctx* c, const pv3d_job& j, int64_t idx, HostJob& h) {
     pv3d_status st;
     if ((st = check_params(&j.params))) return fail(st, "job %lld: %s", (long long)idx, pv3d_last_error(nullptr));
     if (j.params.flags & ~PV3D_FULL_RASTER)
@@ -144,11 +126,139 @@ static pv3d_status check_job(Ctx* c, const pv3d_job& j, int64_t idx, HostJob& h)
     return PV3D_OK;
 }
 
+static size_t table_bytes(const HostJob& h) {
+    return al256(8 * (size_t)h.job.params.k * std::max(h.g->n_cu, h.g->n_cv));
+}
+
+size_t job_bytes(const HostJob& h, bool with_counts, bool with_powers) {
+    const size_t ns = (size_t)h.job.n_sun;
+    size_t b = al256(48 * ns) + 256 + 2 * table_bytes(h);
+    if (with_counts) b += al256(4 * ns * (size_t)h.cells);
+    if (with_powers) b += al256(16 * ns) + 256;
+    return b;
+}
+
+void carve_job(HostJob& h, char* p, bool with_counts, bool with_powers) {
+    const int64_t ns = h.job.n_sun;
+    h.d_sun = reinterpret_cast<double*>(p);
+    h.d_dni = h.d_sun + 3 * ns;
+    h.d_dpoa = h.d_dni + ns;
+    h.d_dt = h.d_dpoa + ns;
+    p += al256(48 * (size_t)ns);
+    h.d_sphere = reinterpret_cast<double*>(p);
+    p += 256;
+    const size_t tb = table_bytes(h);
+    h.d_fu = reinterpret_cast<double*>(p);
+    p += tb;
+    h.d_fv = reinterpret_cast<double*>(p);
+    p += tb;
+    if (with_counts) {
+        h.d_counts = reinterpret_cast<uint32_t*>(p);
+        p += al256(4 * (size_t)(ns * h.cells));
+    }
+    if (with_powers) {
+        h.d_power = reinterpret_cast<double*>(p);
+        h.d_pref = h.d_power + ns;
+        p += al256(16 * (size_t)ns);
+        h.d_energy = reinterpret_cast<double*>(p);
+    }
+}
+
+void job_constants(const HostJob& h, std::vector<double>& tab) {
+    const int32_t kk = h.job.params.k;
+    tab.assign(4 + (size_t)kk * (h.g->n_cu + h.g->n_cv), 0.0);
+    host_sphere(*h.sc, *h.g, tab.data());
+    host_sample_tables(kk, h.g->n_cu, h.g->n_cv, tab.data() + 4, tab.data() + 4 + (size_t)kk * h.g->n_cu);
+}
+
+PJob make_pjob(const HostJob& h) {
+    PJob J;
+    memset(&J, 0, sizeof(J));
+    J.sc = scene_dev(*h.sc);
+    J.g = gen_dev(*h.g);
+    J.sun = h.d_sun;
+    J.dni = h.d_dni;
+    J.dpoa = h.d_dpoa;
+    J.counts = h.d_counts;
+    J.power = h.d_power;
+    J.power_ref = h.d_pref;
+    J.energy = h.d_energy;
+    J.dt = h.d_dt;
+    J.sphere = h.d_sphere;
+    J.fu = h.d_fu;
+    J.fv = h.d_fv;
+    J.n_sun = h.job.n_sun;
+    J.cells = h.cells;
+    J.n = h.job.params.map_n;
+    J.k = h.job.params.k;
+    J.tile = h.tile;
+    J.sparse = h.sparse;
+    J.use_mask = h.use_mask;
+    J.large_tiles = h.large_tiles;
+    J.ntx = h.ntx;
+    J.n_tiles = h.n_tiles;
+    J.words = h.words;
+    J.n_items = (int32_t)h.n_items;
+    J.done_target = (uint32_t)h.n_items;
+    return J;
+}
+
+SlotGeom slot_geom(int64_t rec_cap, int64_t bin_cap, int64_t max_tiles, int64_t max_mod) {
+    SlotGeom g;
+    g.rec_cap = rec_cap;
+    g.bin_cap = bin_cap;
+    g.max_tiles = max_tiles;
+    g.max_mod = max_mod;
+    g.per_rec = al256(80 * (size_t)rec_cap);
+    g.per_large = al256(4 * (size_t)rec_cap);
+    g.per_bins = al256(4 * (size_t)bin_cap);
+    g.per_t = al256(4 * (size_t)(max_tiles + 1));
+    g.per_mod = al256(16 * (size_t)max_mod) + al256(8 * (size_t)max_mod) + al256(4 * (size_t)max_mod);
+    g.per_misc = 256 /*view*/ + al256(4 * 512) /*mask*/ + 256 /*counters*/;
+    g.slot_bytes = g.per_rec + g.per_large + g.per_bins + 4 * g.per_t + g.per_mod + g.per_misc;
+    return g;
+}
+
+char* carve_slots(char* q, const SlotGeom& g, int64_t n_slots, std::vector<PSlotBufs>& out) {
+    const size_t ns = (size_t)n_slots;
+    char* r_rec = q; q += g.per_rec * ns;
+    char* r_large = q; q += g.per_large * ns;
+    char* r_bins = q; q += g.per_bins * ns;
+    char* r_tc = q; q += g.per_t * ns;
+    char* r_ts = q; q += g.per_t * ns;
+    char* r_tcur = q; q += g.per_t * ns;
+    char* r_tl = q; q += g.per_t * ns;
+    char* r_mod = q; q += g.per_mod * ns;
+    char* r_misc = q;
+    out.resize(ns);
+    for (size_t i = 0; i < ns; i++) {
+        PSlotBufs& b = out[i];
+        b.rec = reinterpret_cast<TriRec*>(r_rec + g.per_rec * i);
+        b.large = reinterpret_cast<int32_t*>(r_large + g.per_large * i);
+        b.bins = reinterpret_cast<int32_t*>(r_bins + g.per_bins * i);
+        b.tile_count = reinterpret_cast<int32_t*>(r_tc + g.per_t * i);
+        b.tile_start = reinterpret_cast<int32_t*>(r_ts + g.per_t * i);
+        b.tile_cursor = reinterpret_cast<int32_t*>(r_tcur + g.per_t * i);
+        b.tile_list = reinterpret_cast<int32_t*>(r_tl + g.per_t * i);
+        char* m = r_mod + g.per_mod * i;
+        b.modbox = reinterpret_cast<int4*>(m);
+        b.beam = reinterpret_cast<double*>(m + al256(16 * (size_t)g.max_mod));
+        b.bias = reinterpret_cast<int32_t*>(m + al256(16 * (size_t)g.max_mod) + al256(8 * (size_t)g.max_mod));
+        char* x = r_misc + g.per_misc * i;
+        b.view = reinterpret_cast<View*>(x);
+        b.tmask = reinterpret_cast<uint32_t*>(x + 256);
+        b.ctr = reinterpret_cast<SunCounters*>(x + 256 + al256(4 * 512));
+    }
+    return r_tc;
+}
+
 // One batch: every job's suns above the horizon through the persistent kernel.
-static pv3d_status run_batch(Ctx* c, const pv3d_job* jobs, int64_t n_jobs, hipStream_t s) {
+pv3d_status run_batch(Ctx* c, const pv3d_job* jobs, int64_t n_jobs, hipStream_t s) {
     BatchState* B = nullptr;
     pv3d_status st;
     if ((st = batch_state(c, &B))) return st;
+    DevInfo D;
+    if ((st = device_info(c, &D))) return st;
     for (int i = 0; i < 7; i++) B->stats[i] = 0;
     std::vector<HostJob> H((size_t)n_jobs);
     int64_t n_items = 0, sweep_total = 0;
@@ -165,49 +275,26 @@ static pv3d_status run_batch(Ctx* c, const pv3d_job* jobs, int64_t n_jobs, hipSt
     std::vector<size_t> off((size_t)n_jobs);
     for (int64_t i = 0; i < n_jobs; i++) {
         const HostJob& h = H[(size_t)i];
-        const int64_t ns = h.job.n_sun;
         off[(size_t)i] = jm;
-        jm += al256(48 * (size_t)ns) + 256;                                          // sweep + sphere
-        jm += 2 * al256(8 * (size_t)h.job.params.k * std::max(h.g->n_cu, h.g->n_cv));   // fu, fv
-        if (!h.job.out.on_device || !h.job.out.cell_counts) jm += al256(4 * (size_t)(ns * h.cells));
-        if (!h.job.out.on_device) jm += al256(16 * (size_t)ns) + 256;
+        jm += job_bytes(h, !h.job.out.on_device || !h.job.out.cell_counts, !h.job.out.on_device);
     }
     if ((st = B->jobmem.ensure(c, std::max<size_t>(jm, 256), "batched job data"))) return st;
-    if ((st = B->partial.ensure(c, 8 * 6 * 1024, "bounds partials"))) return st;
     if ((st = B->energy_tmp.ensure(c, 256, "energy scratch"))) return st;
-    if ((st = c->stage_reserve(48 * (size_t)sweep_total + 256 * 4 * (size_t)n_jobs))) return st;
+    size_t tab_total = 0;
+    for (const HostJob& h : H) tab_total += 2 * al256(8 * (size_t)h.job.params.k * std::max(h.g->n_cu, h.g->n_cv)) + 256;
+    if ((st = c->stage_reserve(48 * (size_t)sweep_total + 256 * 4 * (size_t)n_jobs + tab_total))) return st;
+    std::vector<double> tab;
     char* base = static_cast<char*>(B->jobmem.ptr);
     for (int64_t i = 0; i < n_jobs; i++) {
         HostJob& h = H[(size_t)i];
         const int64_t ns = h.job.n_sun;
-        char* p = base + off[(size_t)i];
-        h.d_sun = reinterpret_cast<double*>(p);
-        h.d_dni = h.d_sun + 3 * ns;
-        h.d_dpoa = h.d_dni + ns;
-        h.d_dt = h.d_dpoa + ns;
-        p += al256(48 * (size_t)ns);
-        h.d_sphere = reinterpret_cast<double*>(p);
-        p += 256;
-        const size_t tb = al256(8 * (size_t)h.job.params.k * std::max(h.g->n_cu, h.g->n_cv));
-        h.d_fu = reinterpret_cast<double*>(p);
-        p += tb;
-        h.d_fv = reinterpret_cast<double*>(p);
-        p += tb;
-        if (h.job.out.on_device && h.job.out.cell_counts) {
-            h.d_counts = h.job.out.cell_counts;
-        } else {
-            h.d_counts = reinterpret_cast<uint32_t*>(p);
-            p += al256(4 * (size_t)(ns * h.cells));
-        }
+        const bool own_counts = !h.job.out.on_device || !h.job.out.cell_counts;
+        carve_job(h, base + off[(size_t)i], own_counts, !h.job.out.on_device);
+        if (!own_counts) h.d_counts = h.job.out.cell_counts;
         if (h.job.out.on_device) {
             h.d_power = h.job.out.power;
             h.d_pref = h.job.out.power_ref;
             h.d_energy = h.job.out.energy;
-        } else {
-            h.d_power = reinterpret_cast<double*>(p);
-            h.d_pref = h.d_power + ns;
-            p += al256(16 * (size_t)ns);
-            h.d_energy = reinterpret_cast<double*>(p);
         }
         if (ns > 0) {
             if ((st = c->stage(h.job.sun_xyz, 24 * (size_t)ns, h.d_sun, s))) return st;
@@ -215,18 +302,17 @@ static pv3d_status run_batch(Ctx* c, const pv3d_job* jobs, int64_t n_jobs, hipSt
             if ((st = c->stage(h.job.d_poa, 8 * (size_t)ns, h.d_dpoa, s))) return st;
             if ((st = c->stage(h.job.dt_h, 8 * (size_t)ns, h.d_dt, s))) return st;
         }
+        // bounding sphere and sample tables, computed on the host (no launch per job)
+        const int32_t kk = h.job.params.k;
+        job_constants(h, tab);
+        if ((st = c->stage(tab.data(), 32, h.d_sphere, s))) return st;
+        if ((st = c->stage(tab.data() + 4, 8 * (size_t)kk * h.g->n_cu, h.d_fu, s))) return st;
+        if ((st = c->stage(tab.data() + 4 + (size_t)kk * h.g->n_cu, 8 * (size_t)kk * h.g->n_cv, h.d_fv, s))) return st;
     }
     if ((st = c->stage_done(s))) return st;
     for (int64_t i = 0; i < n_jobs; i++) {
         HostJob& h = H[(size_t)i];
         const int64_t ns = h.job.n_sun;
-        const SceneDev sd = scene_dev(*h.sc);
-        const GenDev gd = gen_dev(*h.g);
-        if ((e = launch_bounds(sd, gd, static_cast<double*>(B->partial.ptr), bounds_partials(h.sc->n_vert + 4 * h.g->n_mod),
-                               h.d_sphere, s)))
-            return hip_fail(e, "bounds");
-        if ((e = launch_sample_tables(h.d_fu, h.d_fv, h.job.params.k, h.g->n_cu, h.g->n_cv, s)))
-            return hip_fail(e, "sample tables");
         if (ns > 0) {
             if ((e = hipMemsetAsync(h.d_counts, 0, 4 * (size_t)(ns * h.cells), s))) return hip_fail(e, "clear counts");
             if ((e = hipMemsetAsync(h.d_power, 0, 8 * (size_t)ns, s))) return hip_fail(e, "clear power");
@@ -247,49 +333,17 @@ static pv3d_status run_batch(Ctx* c, const pv3d_job* jobs, int64_t n_jobs, hipSt
             max_tiles = std::max<int64_t>(max_tiles, h.n_tiles);
             max_mod = std::max<int64_t>(max_mod, h.g->n_mod);
         }
-        const int64_t rec_cap = std::min(worst_rec, B->slot_records);
+        const int64_t rec_cap = std::min(worst_rec, c->batch_slot_records);
         const int64_t bin_cap = std::min(worst_bins, 8 * rec_cap + 64 * max_mod + 65536);
-        const size_t per_rec = al256(80 * (size_t)rec_cap), per_large = al256(4 * (size_t)rec_cap);
-        const size_t per_bins = al256(4 * (size_t)bin_cap), per_t = al256(4 * (size_t)(max_tiles + 1));
-        const size_t per_mod = al256(16 * (size_t)max_mod) + al256(8 * (size_t)max_mod) + al256(4 * (size_t)max_mod);
-        const size_t per_misc = 256 /*view*/ + al256(4 * 512) /*mask*/ + 256 /*counters*/;
-        const size_t slot_bytes = per_rec + per_large + per_bins + 4 * per_t + per_mod + per_misc;
+        const SlotGeom geo = slot_geom(rec_cap, bin_cap, max_tiles, max_mod);
         const uint64_t room = c->budget > c->used + B->slotmem.cap ? c->budget - c->used + B->slotmem.cap : 0;
-        int64_t n_slots = std::min<int64_t>(std::min<int64_t>(n_items, B->max_slots), (int64_t)(room / 2 / slot_bytes));
-        if (n_slots < 1) return fail(PV3D_ENOMEM, "one batch slot (%zu bytes) does not fit the HBM budget", slot_bytes);
+        int64_t n_slots = std::min<int64_t>(std::min<int64_t>(n_items, c->batch_max_slots), (int64_t)(room / 2 / geo.slot_bytes));
+        if (n_slots < 1) return fail(PV3D_ENOMEM, "one batch slot (%zu bytes) does not fit the HBM budget", geo.slot_bytes);
         const size_t ns = (size_t)n_slots;
-        if ((st = B->slotmem.ensure(c, slot_bytes * ns, "batch slots"))) return st;
-        char* q = static_cast<char*>(B->slotmem.ptr);
-        // one region per array kind, so the tile counters of every slot clear in one call
-        char* r_rec = q; q += per_rec * ns;
-        char* r_large = q; q += per_large * ns;
-        char* r_bins = q; q += per_bins * ns;
-        char* r_tc = q; q += per_t * ns;
-        char* r_ts = q; q += per_t * ns;
-        char* r_tcur = q; q += per_t * ns;
-        char* r_tl = q; q += per_t * ns;
-        char* r_mod = q; q += per_mod * ns;
-        char* r_misc = q;
-        std::vector<PSlotBufs> slots(ns);
-        for (size_t i = 0; i < ns; i++) {
-            PSlotBufs& b = slots[i];
-            b.rec = reinterpret_cast<TriRec*>(r_rec + per_rec * i);
-            b.large = reinterpret_cast<int32_t*>(r_large + per_large * i);
-            b.bins = reinterpret_cast<int32_t*>(r_bins + per_bins * i);
-            b.tile_count = reinterpret_cast<int32_t*>(r_tc + per_t * i);
-            b.tile_start = reinterpret_cast<int32_t*>(r_ts + per_t * i);
-            b.tile_cursor = reinterpret_cast<int32_t*>(r_tcur + per_t * i);
-            b.tile_list = reinterpret_cast<int32_t*>(r_tl + per_t * i);
-            char* m = r_mod + per_mod * i;
-            b.modbox = reinterpret_cast<int4*>(m);
-            b.beam = reinterpret_cast<double*>(m + al256(16 * (size_t)max_mod));
-            b.bias = reinterpret_cast<int32_t*>(m + al256(16 * (size_t)max_mod) + al256(8 * (size_t)max_mod));
-            char* x = r_misc + per_misc * i;
-            b.view = reinterpret_cast<View*>(x);
-            b.tmask = reinterpret_cast<uint32_t*>(x + 256);
-            b.ctr = reinterpret_cast<SunCounters*>(x + 256 + al256(4 * 512));
-        }
-        if ((e = hipMemsetAsync(r_tc, 0, per_t * ns, s))) return hip_fail(e, "clear slot tile counts");
+        if ((st = B->slotmem.ensure(c, geo.slot_bytes * ns, "batch slots"))) return st;
+        std::vector<PSlotBufs> slots;
+        char* r_tc = carve_slots(static_cast<char*>(B->slotmem.ptr), geo, n_slots, slots);
+        if ((e = hipMemsetAsync(r_tc, 0, geo.per_t * ns, s))) return hip_fail(e, "clear slot tile counts");
 
         // --- tables
         std::vector<PJob> pj((size_t)n_jobs);
@@ -297,33 +351,7 @@ static pv3d_status run_batch(Ctx* c, const pv3d_job* jobs, int64_t n_jobs, hipSt
         int64_t k = 0;
         for (int64_t i = 0; i < n_jobs; i++) {
             const HostJob& h = H[(size_t)i];
-            PJob& J = pj[(size_t)i];
-            memset(&J, 0, sizeof(J));
-            J.sc = scene_dev(*h.sc);
-            J.g = gen_dev(*h.g);
-            J.sun = h.d_sun;
-            J.dni = h.d_dni;
-            J.dpoa = h.d_dpoa;
-            J.counts = h.d_counts;
-            J.power = h.d_power;
-            J.power_ref = h.d_pref;
-            J.energy = h.d_energy;
-            J.dt = h.d_dt;
-            J.sphere = h.d_sphere;
-            J.fu = h.d_fu;
-            J.fv = h.d_fv;
-            J.n_sun = h.job.n_sun;
-            J.cells = h.cells;
-            J.n = h.job.params.map_n;
-            J.k = h.job.params.k;
-            J.tile = h.tile;
-            J.sparse = h.sparse;
-            J.use_mask = h.use_mask;
-            J.large_tiles = h.large_tiles;
-            J.ntx = h.ntx;
-            J.n_tiles = h.n_tiles;
-            J.words = h.words;
-            J.n_items = (int32_t)h.n_items;
+            pj[(size_t)i] = make_pjob(h);
             for (int64_t t = 0; t < h.job.n_sun; t++)
                 if (h.job.sun_xyz[3 * t + 2] > 0.0) items[(size_t)k++] = PItem{(int32_t)i, (int32_t)t};
         }
@@ -331,6 +359,8 @@ static pv3d_status run_batch(Ctx* c, const pv3d_job* jobs, int64_t n_jobs, hipSt
         memset(state.data(), 0, sizeof(PSlotState) * ns);
         for (size_t i = 0; i < ns; i++) {
             state[i].item = (int32_t)i;
+            state[i].job = items[i].job;
+            state[i].sun = items[i].sun;
             state[i].word = ((unsigned long long)kPhSetup << 56) | (1ull << 32);
         }
         PSched sched;
@@ -368,9 +398,9 @@ static pv3d_status run_batch(Ctx* c, const pv3d_job* jobs, int64_t n_jobs, hipSt
         P.n_slots = (int32_t)n_slots;
         P.rec_cap = (int32_t)rec_cap;
         P.bin_cap = (int32_t)bin_cap;
-        P.stall_ticks = B->stall_ticks;
-        P.groups = B->any_xcd ? 1 : B->xcd_groups;
-        const int32_t grid = B->blocks_per_cu * B->n_cu;
+        P.stall_ticks = D.stall_ticks;
+        P.groups = c->batch_any_xcd ? 1 : D.xcd_groups;
+        const int32_t grid = D.blocks_per_cu * D.n_cu;
         if ((e = hipEventRecord(B->ev0, s))) return hip_fail(e, "event");
         if ((e = launch_persist(P, grid, s))) return hip_fail(e, "persistent launch");
         if ((e = hipEventRecord(B->ev1, s))) return hip_fail(e, "event");
@@ -433,8 +463,6 @@ static pv3d_status run_batch(Ctx* c, const pv3d_job* jobs, int64_t n_jobs, hipSt
 }
 
 }  // namespace pv3d
-
-void pv3d_server_stop(pv3d_ctx*) {}
 
 extern "C" {
 
@@ -519,13 +547,9 @@ pv3d_status pv3d_batch_limits(pv3d_ctx* ctx, int32_t max_slots, int64_t slot_rec
         return fail(PV3D_EINVAL, "batch limits out of range");
     if (flags & ~PV3D_BATCH_ANY_XCD) return fail(PV3D_EINVAL, "unknown batch flags 0x%x", flags);
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    (void)hipSetDevice(ctx->device);
-    BatchState* B = nullptr;
-    pv3d_status st;
-    if ((st = batch_state(ctx, &B))) return st;
-    B->max_slots = max_slots ? max_slots : kMaxSlots;
-    B->slot_records = slot_records ? slot_records : kSlotRecCap;
-    B->any_xcd = (flags & PV3D_BATCH_ANY_XCD) != 0;
+    ctx->batch_max_slots = max_slots ? max_slots : kMaxSlots;
+    ctx->batch_slot_records = slot_records ? slot_records : kSlotRecCap;
+    ctx->batch_any_xcd = (flags & PV3D_BATCH_ANY_XCD) != 0;
     return PV3D_OK;
 }
 
@@ -534,23 +558,6 @@ pv3d_status pv3d_batch_stats(pv3d_ctx* ctx, int64_t out[7]) {
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     for (int i = 0; i < 7; i++) out[i] = ctx->batch ? ctx->batch->stats[i] : 0;
     return PV3D_OK;
-}
-
-pv3d_status pv3d_submit(pv3d_ctx* ctx, const pv3d_job* job, uint64_t* ticket) {
-    (void)ctx; (void)job; (void)ticket;
-    return fail(PV3D_ERANGE, "serving is not available in this build");
-}
-pv3d_status pv3d_poll(pv3d_ctx* ctx, uint64_t ticket, int32_t* done) {
-    (void)ctx; (void)ticket; (void)done;
-    return fail(PV3D_ENOENT, "unknown ticket");
-}
-pv3d_status pv3d_wait(pv3d_ctx* ctx, uint64_t ticket) {
-    (void)ctx; (void)ticket;
-    return fail(PV3D_ENOENT, "unknown ticket");
-}
-pv3d_status pv3d_cancel(pv3d_ctx* ctx, uint64_t ticket) {
-    (void)ctx; (void)ticket;
-    return fail(PV3D_ENOENT, "unknown ticket");
 }
 
 }  // extern "C"

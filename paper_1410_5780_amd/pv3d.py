@@ -80,6 +80,7 @@ def lib():
         L.pv3d_autotune.argtypes = [_P, ctypes.POINTER(Job), _i32, ctypes.POINTER(_f64)]
         L.pv3d_batch_stats.argtypes = [_P, ctypes.POINTER(_i64 * 7)]
         L.pv3d_batch_limits.argtypes = [_P, _i32, _i64, _u32]
+        L.pv3d_serve_stats.argtypes = [_P, ctypes.POINTER(_i64 * 4)]
         L.pv3d_submit.argtypes = [_P, ctypes.POINTER(Job), ctypes.POINTER(_u64)]
         L.pv3d_poll.argtypes = [_P, _u64, ctypes.POINTER(_i32)]
         L.pv3d_wait.argtypes = [_P, _u64]
@@ -88,7 +89,7 @@ def lib():
         L.pv3d_profile_read.argtypes = [_P, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
         for f in ("pv3d_profile_enable", "pv3d_profile_read", "pv3d_create", "pv3d_scene_load", "pv3d_scene_release", "pv3d_generator_define",
                   "pv3d_generator_release", "pv3d_sun_cooper", "pv3d_evaluate", "pv3d_evaluate_batched",
-                  "pv3d_autotune", "pv3d_batch_stats", "pv3d_batch_limits",
+                  "pv3d_autotune", "pv3d_batch_stats", "pv3d_batch_limits", "pv3d_serve_stats",
                   "pv3d_submit", "pv3d_poll", "pv3d_wait", "pv3d_cancel"):
             getattr(L, f).restype = _i32
         _lib = L
@@ -297,3 +298,37 @@ class Context:
         a = (_i64 * 7)()
         _check(lib().pv3d_batch_stats(self.h, ctypes.byref(a)), self.h)
         return dict(zip(("items", "units", "redone", "workgroups", "slots", "launch_us", "xcd_groups"), list(a)))
+
+    # ------------------------------------------------------------------
+    # serving loop
+    # ------------------------------------------------------------------
+    def submit(self, spec, device: bool = False) -> int:
+        """Submit one job (see _job) to the serving loop; returns its ticket. The Result
+        (host arrays, filled when the job ends) is kept until wait()."""
+        keep: list = []
+        job = self._job(spec, device, keep)
+        t = _u64()
+        _check(lib().pv3d_submit(self.h, ctypes.byref(job), ctypes.byref(t)), self.h)
+        if not hasattr(self, "_tickets"):
+            self._tickets = {}
+        self._tickets[t.value] = [r for r in keep if isinstance(r, Result)][0]
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = _i32()
+        _check(lib().pv3d_poll(self.h, ticket, ctypes.byref(d)), self.h)
+        return bool(d.value)
+
+    def wait(self, ticket: int) -> Result:
+        """Block until the job ends; its Result (raises Pv3dError if cancelled or failed)."""
+        res = self._tickets.pop(ticket, None)
+        _check(lib().pv3d_wait(self.h, ticket), self.h)
+        return res
+
+    def cancel(self, ticket: int):
+        _check(lib().pv3d_cancel(self.h, ticket), self.h)
+
+    def serve_stats(self) -> dict:
+        a = (_i64 * 4)()
+        _check(lib().pv3d_serve_stats(self.h, ctypes.byref(a)), self.h)
+        return dict(zip(("jobs_done", "launches", "items", "pending"), list(a)))
