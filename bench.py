@@ -47,6 +47,12 @@ def parse():
                          "sun's full picture written to HBM and read back by a separate depth-check kernel")
     ap.add_argument("--no-materialised", action="store_true",
                     help="skip the extra one-step run of the materialised route")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched, C4 and serving legs")
+    ap.add_argument("--c4-every", type=int, default=50, help="C4 leg: every n-th sun of the year")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="serving leg: arrivals per second")
+    ap.add_argument("--serve-seconds", type=float, default=0.1, help="serving leg: seconds of arrivals")
+    ap.add_argument("--light-rate", type=float, default=4.0, help="serving leg: light-load arrivals per second")
+    ap.add_argument("--light-seconds", type=float, default=3.0, help="serving leg: light-load seconds of arrivals")
     return ap.parse_args()
 
 
@@ -111,6 +117,92 @@ def measured_traffic(kernel, route):
     if kv.get("kernel_source_sha256_16", "").strip() != sha:
         return None
     return int(kv["tile_traffic_bytes_per_launch"])
+
+
+def batched_leg(ctx, w, sh, gh, plain_energy, plain_power, plain_year_s, log):
+    """The same year in one persistent launch (pv3d_evaluate_batched), results checked against the loop."""
+    import torch
+    spec = dict(scene=sh, gen=gh, generator=w.gen, sweep=w.sweep, map_n=w.map_n, k=w.k, counts=False)
+    best = None
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.evaluate_batched([spec], device=True)[0]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    st = ctx.batch_stats()
+    same = bool(np.array_equal(r.energy.cpu().numpy(), plain_energy) and np.array_equal(r.power.cpu().numpy(), plain_power))
+    log(f"[bench] batched year: {best:.3f} s, identical {same}")
+    return {"value": w.n_samples * w.sweep.n / best, "unit": "sample-sun tests/s", "year_seconds": best,
+            "speedup_vs_plain_loop": plain_year_s / best, "identical_to_plain_loop": same,
+            "launch_us": st["launch_us"], "units": st["units"], "slots": st["slots"],
+            "workgroups": st["workgroups"], "xcd_groups": st["xcd_groups"]}
+
+
+def c4_leg(ctx, every, log):
+    """64 uneven sites: the plain per-sun loop against one persistent launch (autotuned per size class)."""
+    import torch
+    from paper_1410_5780_amd import workloads as W
+    yr = W.year_sweep()
+    sub = yr.subset(np.arange(0, yr.n, every))
+    ws = W.c4_batched(sweep=sub)
+    specs = [dict(scene=ctx.load_scene(x.scene), gen=ctx.define_generator(x.gen), generator=x.gen, sweep=x.sweep,
+                  map_n=x.map_n, k=x.k, counts=False) for x in ws]
+    t0 = time.perf_counter()
+    tuned = {}
+    for sp, x in zip(specs, ws):
+        key = (x.map_n, int(np.log10(max(x.scene.n_tri, 1))))
+        if key not in tuned:
+            tuned[key] = ctx.autotune(sp, n_probe=4)[:2]
+        sp["tile"], sp["bin_limit"] = tuned[key]
+    tune_s = time.perf_counter() - t0
+    log(f"[bench] c4: {len(ws)} sites x {sub.n} suns, autotuned {len(tuned)} classes in {tune_s:.2f} s")
+    best_p = best_b = None
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain = [ctx.evaluate_device(sp["scene"], sp["gen"], sp["generator"], sp["sweep"], sp["map_n"], sp["k"])
+                 for sp in specs]
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        bat = ctx.evaluate_batched(specs, device=True)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        best_p = tp if best_p is None else min(best_p, tp)
+        best_b = tb if best_b is None else min(best_b, tb)
+    st = ctx.batch_stats()
+    same = all(np.array_equal(a.energy.cpu().numpy(), b.energy.cpu().numpy()) and
+               np.array_equal(a.power.cpu().numpy(), b.power.cpu().numpy()) for a, b in zip(plain, bat))
+    samples = sum(x.n_samples * x.sweep.n for x in ws)
+    tris = sum(x.n_tri_submitted * x.sweep.n for x in ws)
+    for sp in specs:
+        ctx.release_scene(sp["scene"])
+        ctx.release_generator(sp["gen"])
+    log(f"[bench] c4: plain {best_p:.3f} s, batched {best_b:.3f} s, identical {same}")
+    return {"workload": f"64 sites (1k-2M triangles, 60-24,000 cells, N 2048-8192), every {every}th sun of the "
+                        f"year ({sub.n} suns each, {st['items']} items)",
+            "plain_loop_s": best_p, "batched_s": best_b, "speedup": best_p / best_b, "identical": same,
+            "batched_tests_per_s": samples / best_b, "batched_triangles_per_s": tris / best_b,
+            "autotune_s": tune_s, "autotuned": {f"N{k[0]}_1e{k[1]}tri": list(v) for k, v in tuned.items()},
+            "units": st["units"], "slots": st["slots"], "redone_per_sun": st["redone"]}
+
+
+def serving_leg(ctx, log, rate_hz, duration_s, light_rate, light_s):
+    """Poisson request streams through the serving loop: latency from arrival to completion."""
+    from paper_1410_5780_amd import serve, workloads as W
+    out = {}
+    for name, rate, dur, seed in (("configured_rate", rate_hz, duration_s, 5), ("light_load", light_rate, light_s, 6)):
+        reqs = W.serving_stream(seed=seed, rate_hz=rate, duration_s=dur)
+        if not reqs:
+            continue
+        log(f"[bench] serving {name}: {len(reqs)} requests at {rate} /s")
+        r = serve.run_stream(ctx, reqs, seed=seed, log=log)
+        r.update({"rate_hz": rate, "duration_s": dur})
+        log(f"[bench] serving {name}: {r['requests']} requests, p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms")
+        out[name] = r
+    return out
 
 
 def cpu_baseline(w_full, every):
@@ -255,6 +347,13 @@ def main():
         "stage_avg_us": {k: round(v["avg_us"], 3) for k, v in stage_ms.items()},
         "energy_loss": loss,
     }
+    if not a.no_extra and a.route == "sparse" and a.suns <= 1 and a.workload == "c2":
+        def log(msg):
+            print(msg, file=sys.stderr, flush=True)
+        line["batched"] = batched_leg(ctx, w, sh, gh, res.energy.cpu().numpy(), res.power.cpu().numpy(),
+                                      line["year_seconds"], log)
+        line["c4_batched"] = c4_leg(ctx, a.c4_every, log)
+        line["serving"] = serving_leg(ctx, log, a.serve_rate, a.serve_seconds, a.light_rate, a.light_seconds)
     if not a.no_cpu:
         print("[bench] cpu oracle leg ...", file=sys.stderr, flush=True)
         full = w if a.suns <= 1 else workload(a.workload, 1)

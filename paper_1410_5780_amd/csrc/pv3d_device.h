@@ -187,7 +187,10 @@ struct PSched {
     uint32_t abort;              // 1: the watchdog saw no progress; every workgroup leaves
     unsigned long long units;    // units completed (statistics, watchdog progress)
     uint32_t n_overflow;         // items listed in overflow_items
-    uint32_t pad;
+    // serving: device copies of the host's words, refreshed by a few polling workgroups
+    uint32_t pub_dev;            // items published
+    uint32_t stop_dev;           // stop asked
+    int32_t busy;                // slots holding an item
 };
 
 struct PLaunch {

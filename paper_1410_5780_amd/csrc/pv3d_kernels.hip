@@ -1685,6 +1685,9 @@ __device__ __forceinline__ void acquire_unit(int32_t) { __builtin_amdgcn_fence(_
 
 // s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15): every vector memory access of the wave done
 constexpr int kWaitVmem = 0x0F70;
+// Serving: workgroups that read the host's words, and how often (wall-clock ticks, 100 MHz).
+constexpr int32_t kPollers = 8;
+constexpr long long kPollTicks = 200;
 
 __device__ __forceinline__ int32_t xcc_id() { return (int32_t)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20); }
 
@@ -1717,11 +1720,11 @@ __device__ bool admit(const PLaunch& P, PSlotState& st) {
     } else {
         for (;;) {
             uint32_t cur = ld_dev(&P.sched->next_item);
-            const uint32_t pub = __hip_atomic_load(P.feed_pub, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+            const uint32_t pub = ld_dev(&P.sched->pub_dev);
             if ((int32_t)(pub - cur) <= 0) return false;
             if (__hip_atomic_compare_exchange_strong(&P.sched->next_item, &cur, cur + 1, __ATOMIC_RELAXED,
                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                const unsigned long long e = __hip_atomic_load(P.feed + (cur % P.feed_cap), __ATOMIC_RELAXED,
+                const unsigned long long e = __hip_atomic_load(P.feed + (cur % P.feed_cap), __ATOMIC_ACQUIRE,
                                                                __HIP_MEMORY_SCOPE_SYSTEM);
                 item = (int32_t)(cur & 0x7FFFFFFFu);
                 job = (int32_t)(e >> 32);
@@ -1800,8 +1803,12 @@ __device__ void advance(const PLaunch& P, PCtl& ctl, double* stage, int32_t slot
             }
             ctl.job = job;
             // the slot takes the next item
-            if (admit(P, st)) publish(st, kPhSetup, 1);
-            else publish(st, kPhIdle, 0);
+            if (admit(P, st)) {
+                publish(st, kPhSetup, 1);
+            } else {
+                if (P.serve) atomicSub(reinterpret_cast<uint32_t*>(&P.sched->busy), 1u);
+                publish(st, kPhIdle, 0);
+            }
             if (!ctl.job_last && !P.serve)
                 __hip_atomic_fetch_add(&P.sched->items_done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -1854,9 +1861,21 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
     const int32_t n_mine = my < P.n_slots ? (P.n_slots - my + G - 1) / G : 0;
     int32_t home = n_mine > 0 ? (int32_t)((blockIdx.x / (unsigned)G) % (unsigned)n_mine) : 0;
     unsigned long long seen_units = ~0ull;
-    long long seen_at = 0, quiet_since = -1;
+    long long seen_at = 0, quiet_since = -1, polled_at = -(1ll << 40);
     int32_t backoff = 1;
     for (;;) {
+        if (P.serve && tid == 0 && (int32_t)blockIdx.x < kPollers) {
+            // serving: a few workgroups copy the host's published count and stop flag into
+            // device memory, at most every kPollTicks; every other workgroup reads the copies
+            const long long now = (long long)wall_clock64();
+            if (now - polled_at >= kPollTicks) {
+                polled_at = now;
+                const uint32_t pub = __hip_atomic_load(P.feed_pub, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                if ((int32_t)(pub - ld_dev(&P.sched->pub_dev)) > 0) atomicMax(&P.sched->pub_dev, pub);
+                if (__hip_atomic_load(P.stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u)
+                    st_dev(&P.sched->stop_dev, 1u);
+            }
+        }
         if (tid < 64) {                                   // wave 0 looks for a unit
             int32_t got = -1, gj = 0, unit = 0, phase = 0, units = 0;
             const bool aborted = __hip_atomic_load(&P.sched->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
@@ -1906,7 +1925,7 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
             bool refilled = false;
             if (got < 0 && !aborted && P.serve && n_mine > 0) {
                 // serving: an idle slot of this XCD takes a newly published item
-                const uint32_t pub = __hip_atomic_load(P.feed_pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                const uint32_t pub = ld_dev(&P.sched->pub_dev);
                 if ((int32_t)(pub - ld_dev(&P.sched->next_item)) > 0) {
                     for (int32_t base = 0; base < n_mine && !refilled; base += 64) {
                         const int32_t kk = base + lane;
@@ -1925,8 +1944,12 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
                                 if (__hip_atomic_compare_exchange_strong(&P.state[i].word, &exp, pword(kPhAdmit, 0),
                                                                          __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                                          __HIP_MEMORY_SCOPE_AGENT)) {
-                                    if (admit(P, P.state[i])) publish(P.state[i], kPhSetup, 1);
-                                    else publish(P.state[i], kPhIdle, 0);
+                                    if (admit(P, P.state[i])) {
+                                        atomicAdd(reinterpret_cast<uint32_t*>(&P.sched->busy), 1u);
+                                        publish(P.state[i], kPhSetup, 1);
+                                    } else {
+                                        publish(P.state[i], kPhIdle, 0);
+                                    }
                                 }
                             }
                             refilled = true;
@@ -1953,24 +1976,15 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
                     stop = __hip_atomic_load(&P.sched->items_done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >=
                            P.sched->n_items;
                 } else if (!stop) {
-                    // serving: quiet when every slot is idle and nothing waits in the feed
-                    bool busy = false;
-                    for (int32_t base = 0; base < P.n_slots; base += 64)
-                        if (base + lane < P.n_slots &&
-                            w_phase(__hip_atomic_load(&P.state[base + lane].word, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT)) != kPhIdle)
-                            busy = true;
-                    busy = __ballot(busy) != 0ull;
-                    const uint32_t pub = __hip_atomic_load(P.feed_pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-                    quiet = !busy && (int32_t)(pub - ld_dev(&P.sched->next_item)) <= 0;
+                    // serving: quiet when no slot holds an item and nothing waits in the feed
+                    quiet = ld_dev(&P.sched->busy) <= 0 &&
+                            (int32_t)(ld_dev(&P.sched->pub_dev) - ld_dev(&P.sched->next_item)) <= 0;
                 }
                 if (lane == 0) {
                     const long long now = (long long)wall_clock64();
                     if (!stop && quiet) {
                         if (quiet_since < 0) quiet_since = now;
-                        if (__hip_atomic_load(P.stop_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u ||
-                            now - quiet_since > P.idle_ticks)
-                            stop = true;
+                        if (ld_dev(&P.sched->stop_dev) != 0u || now - quiet_since > P.idle_ticks) stop = true;
                     } else if (!stop) {
                         quiet_since = -1;
                         const unsigned long long u =

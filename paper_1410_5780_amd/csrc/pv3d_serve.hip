@@ -127,7 +127,8 @@ struct Server {
     uint32_t* stop = nullptr;
     uint32_t* report = nullptr;
     void* host_mem = nullptr;
-    void* staging = nullptr;
+    void* staging = nullptr;           // pinned: job uploads and output bounce
+    void* staging_dev = nullptr;       // its device address
     size_t staging_cap = 0;
     uint32_t published = 0;
     int64_t inflight_items = 0;
@@ -242,6 +243,28 @@ static void* dev_ptr(void* host) {
     return d;
 }
 
+// Copies of the loop go through the copy engines (no compute unit): the live
+// launch holds every CU, and a copy done by a kernel would wait for it to end.
+// Host memory takes part through the device address of pinned staging.
+static hipError_t copy_nocu(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDeviceNoCU, st);
+}
+
+static pv3d_status ensure_staging(Server* S, size_t need) {
+    if (need <= S->staging_cap) return PV3D_OK;
+    if (S->staging) (void)hipHostFree(S->staging);
+    S->staging = nullptr;
+    S->staging_dev = nullptr;
+    S->staging_cap = 0;
+    const size_t cap = std::max(need + need / 2, (size_t)64 << 20);   // rarely regrown: a free may wait for the device
+    hipError_t e = hipHostMalloc(&S->staging, cap, hipHostMallocDefault);
+    if (e) return hip_fail(e, "hipHostMalloc staging");
+    S->staging_dev = dev_ptr(S->staging);
+    S->staging_cap = cap;
+    return PV3D_OK;
+}
+
 // Upload a job and publish its items (server lock held). False: it has to wait.
 static bool try_admit(Server* S, SJob* J, pv3d_status* err) {
     HostJob& h = J->h;
@@ -273,17 +296,9 @@ static bool try_admit(Server* S, SJob* J, pv3d_status* err) {
     const int32_t kk = h.job.params.k;
     const size_t need = 48 * (size_t)ns + 8 * tab.size() + sizeof(PJob) + 1024;
     hipError_t e = hipSuccess;
-    if (need > S->staging_cap) {
-        if (S->staging) (void)hipHostFree(S->staging);
-        S->staging = nullptr;
-        S->staging_cap = 0;
-        if ((e = hipHostMalloc(&S->staging, need * 2, hipHostMallocDefault))) {
-            *err = hip_fail(e, "hipHostMalloc staging");
-            return false;
-        }
-        S->staging_cap = need * 2;
-    }
+    if ((*err = ensure_staging(S, need))) return false;
     char* sp = static_cast<char*>(S->staging);
+    char* sd = static_cast<char*>(S->staging_dev);
     memcpy(sp, J->in.data(), 48 * (size_t)ns);          // sun (3 ns), dni, d_poa, dt: the device layout
     char* tp = sp + al256(48 * (size_t)ns);
     memcpy(tp, tab.data(), 8 * tab.size());
@@ -294,12 +309,12 @@ static bool try_admit(Server* S, SJob* J, pv3d_status* err) {
     pj.seq = J->seq;
     char* jp = tp + al256(8 * tab.size());
     memcpy(jp, &pj, sizeof(PJob));
-    if (ns > 0) e = hipMemcpyAsync(h.d_sun, sp, 48 * (size_t)ns, hipMemcpyHostToDevice, S->cstream);
-    if (!e) e = hipMemcpyAsync(h.d_sphere, tp, 32, hipMemcpyHostToDevice, S->cstream);
-    if (!e) e = hipMemcpyAsync(h.d_fu, tp + 32, 8 * (size_t)kk * h.g->n_cu, hipMemcpyHostToDevice, S->cstream);
-    if (!e) e = hipMemcpyAsync(h.d_fv, tp + 32 + 8 * (size_t)kk * h.g->n_cu, 8 * (size_t)kk * h.g->n_cv,
-                               hipMemcpyHostToDevice, S->cstream);
-    if (!e) e = hipMemcpyAsync(static_cast<PJob*>(S->jobtab.ptr) + j, jp, sizeof(PJob), hipMemcpyHostToDevice, S->cstream);
+    const size_t to = (size_t)(tp - sp), jo = (size_t)(jp - sp);
+    if (ns > 0) e = copy_nocu(h.d_sun, sd, 48 * (size_t)ns, S->cstream);
+    if (!e) e = copy_nocu(h.d_sphere, sd + to, 32, S->cstream);
+    if (!e) e = copy_nocu(h.d_fu, sd + to + 32, 8 * (size_t)kk * h.g->n_cu, S->cstream);
+    if (!e) e = copy_nocu(h.d_fv, sd + to + 32 + 8 * (size_t)kk * h.g->n_cu, 8 * (size_t)kk * h.g->n_cv, S->cstream);
+    if (!e) e = copy_nocu(static_cast<PJob*>(S->jobtab.ptr) + j, sd + jo, sizeof(PJob), S->cstream);
     if (!e) e = hipStreamSynchronize(S->cstream);
     if (e) {
         *err = hip_fail(e, "upload of a serving job");
@@ -331,9 +346,15 @@ static void finish(Server* S, std::unique_lock<std::mutex>& lk, SJob* J, bool ov
     hipError_t e = hipSuccess;
     if (ns == 0) {
         static const double zero[2] = {0.0, 0.0};
-        if (h.job.out.on_device) e = hipMemcpyAsync(h.job.out.energy, zero, 16, hipMemcpyHostToDevice, S->cstream);
-        else memcpy(h.job.out.energy, zero, 16);
-        if (!e) e = hipStreamSynchronize(S->cstream);
+        if (h.job.out.on_device) {
+            if ((st = ensure_staging(S, 16)) == PV3D_OK) {
+                memcpy(S->staging, zero, 16);
+                e = copy_nocu(h.job.out.energy, S->staging_dev, 16, S->cstream);
+                if (!e) e = hipStreamSynchronize(S->cstream);
+            }
+        } else {
+            memcpy(h.job.out.energy, zero, 16);
+        }
     } else if (overflow) {
         // a sun exceeded a slot's capacity: the per-sun path evaluates the job again
         lk.unlock();
@@ -346,18 +367,33 @@ static void finish(Server* S, std::unique_lock<std::mutex>& lk, SJob* J, bool ov
                                 h.d_power, h.d_pref, h.d_energy, nullptr, nullptr, S->cstream);
             if (!st) e = hipStreamSynchronize(S->cstream);
             uint32_t ov = 0;
-            if (!st && !e) e = hipMemcpy(&ov, static_cast<uint32_t*>(S->counters.ptr) + kServeJobs + j, 4, hipMemcpyDeviceToHost);
+            if (!st && !e && (st = ensure_staging(S, 4)) == PV3D_OK) {
+                e = copy_nocu(S->staging_dev, static_cast<uint32_t*>(S->counters.ptr) + kServeJobs + j, 4, S->cstream);
+                if (!e) e = hipStreamSynchronize(S->cstream);
+                if (!e) memcpy(&ov, S->staging, 4);
+            }
             if (!st && !e) S->ovf_base[(size_t)j] = ov;
         }
         lk.lock();
     }
     if (!st && !e && !h.job.out.on_device && ns > 0 && !J->cancel) {
-        if (h.job.out.cell_counts)
-            e = hipMemcpyAsync(h.job.out.cell_counts, h.d_counts, 4 * (size_t)(ns * h.cells), hipMemcpyDeviceToHost, S->cstream);
-        if (!e) e = hipMemcpyAsync(h.job.out.power, h.d_power, 8 * (size_t)ns, hipMemcpyDeviceToHost, S->cstream);
-        if (!e) e = hipMemcpyAsync(h.job.out.power_ref, h.d_pref, 8 * (size_t)ns, hipMemcpyDeviceToHost, S->cstream);
-        if (!e) e = hipMemcpyAsync(h.job.out.energy, h.d_energy, 16, hipMemcpyDeviceToHost, S->cstream);
-        if (!e) e = hipStreamSynchronize(S->cstream);
+        // one copy of the job's output region (counts, powers, energy lie in this order) into
+        // pinned staging, then into the caller's arrays
+        const char* first = h.job.out.cell_counts ? reinterpret_cast<const char*>(h.d_counts)
+                                                  : reinterpret_cast<const char*>(h.d_power);
+        const size_t span = (size_t)(reinterpret_cast<const char*>(h.d_energy) + 16 - first);
+        if ((st = ensure_staging(S, span)) == PV3D_OK) {
+            e = copy_nocu(S->staging_dev, first, span, S->cstream);
+            if (!e) e = hipStreamSynchronize(S->cstream);
+            if (!e) {
+                const char* b = static_cast<const char*>(S->staging);
+                auto at = [&](const void* dev) { return b + (reinterpret_cast<const char*>(dev) - first); };
+                if (h.job.out.cell_counts) memcpy(h.job.out.cell_counts, at(h.d_counts), 4 * (size_t)(ns * h.cells));
+                memcpy(h.job.out.power, at(h.d_power), 8 * (size_t)ns);
+                memcpy(h.job.out.power_ref, at(h.d_pref), 8 * (size_t)ns);
+                memcpy(h.job.out.energy, at(h.d_energy), 16);
+            }
+        }
     }
     if (e) st = hip_fail(e, "serving outputs");
     S->arena.release(J->off, J->bytes);
@@ -414,8 +450,12 @@ static void service(Server* S) {
         if (S->live && q != hipErrorNotReady) {
             S->live = false;
             PSched got;
-            if (q != hipSuccess || hipMemcpy(&got, S->sched.ptr, sizeof(PSched), hipMemcpyDeviceToHost) != hipSuccess ||
-                got.abort) {
+            memset(&got, 0, sizeof(got));
+            bool ok = q == hipSuccess && ensure_staging(S, sizeof(PSched)) == PV3D_OK &&
+                      copy_nocu(S->staging_dev, S->sched.ptr, sizeof(PSched), S->cstream) == hipSuccess &&
+                      hipStreamSynchronize(S->cstream) == hipSuccess;
+            if (ok) memcpy(&got, S->staging, sizeof(PSched));
+            if (!ok || got.abort) {
                 S->fatal = fail(PV3D_EDEVICE, "the serving launch stopped making progress");
                 fail_live(S, S->fatal);
             }

@@ -142,10 +142,26 @@ def modules_of(gen) -> ctypes.Array:
     return arr
 
 
+def _torch_first():
+    """Device arrays cross the ABI as torch tensors. torch carries a HIP runtime of its own, and
+    when the library's runtime starts first torch no longer finds the GPU, so start torch's first
+    whenever torch is importable."""
+    try:
+        import torch
+    except ImportError:
+        return
+    try:
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except Exception:
+        pass
+
+
 class Context:
     """One library context on one device (owns a HIP stream and an HBM budget)."""
 
     def __init__(self, device: int = 0, budget_bytes: int = 0):
+        _torch_first()
         h = _P()
         _check(lib().pv3d_create(device, budget_bytes, ctypes.byref(h)))
         self.h = h
