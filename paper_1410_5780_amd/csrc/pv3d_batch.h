@@ -56,7 +56,7 @@ PJob make_pjob(const HostJob& h);
 // clear in one call.
 struct SlotGeom {
     int64_t rec_cap, bin_cap, max_tiles, max_mod;
-    size_t per_rec, per_large, per_bins, per_t, per_mod, per_misc, slot_bytes;
+    size_t per_rec, per_large, per_bins, per_t, per_list, per_mod, per_misc, slot_bytes;
 };
 SlotGeom slot_geom(int64_t rec_cap, int64_t bin_cap, int64_t max_tiles, int64_t max_mod);
 // Fills out[0..n_slots) and returns the tile-counter region (per_t * n_slots bytes).

@@ -66,12 +66,20 @@ struct BinBuffers {
     int32_t* tile_cursor;  // [n_tiles]
     int32_t* bins;         // [bin_cap]
     int4* modbox;          // [n_mod] tile range (x0, x1, y0, y1) of each module's samples; x0 > x1: none
+    int32_t* tile_list;    // [4 n_tiles] work items of the tile pass, heaviest first (nullptr: one per tile)
+    int32_t* list_ctr;     // [2] items listed, next item to take (the scan sets both)
+    int32_t split_at;      // list order: < 0 tile order; else heaviest first, tiles with more
+                           // entries than split_at > 0 as four quadrant items
     int32_t bin_cap;
     int32_t tile;          // tile edge in texels
     int32_t ntx;           // tiles per row
     int32_t n_tiles;
     int32_t large_tiles;   // triangles touching more tiles than this go to the large list
 };
+
+// A work item of the tile pass: tile << 3 | part, part 0..3 a 32 x 32 quadrant
+// (of a 64-texel tile) and kWholeTile the whole tile.
+constexpr int32_t kWholeTile = 4;
 
 // What the tile kernel writes for one sun.
 struct TileOut {
@@ -233,7 +241,7 @@ hipError_t launch_bin_scatter(int64_t s, const BinBuffers& bb, int32_t n_mod, Su
 hipError_t launch_raster(int64_t s, const View* views, const BinBuffers& bb, const SunCounters* ctr,
                          int32_t n, const GenDev& g, const int32_t* bias, const double* fu,
                          const double* fv, int32_t k, const TileOut& out, const uint32_t* tmask,
-                         hipStream_t st);
+                         int32_t n_cu, hipStream_t st);
 size_t bin_lds_bytes(int32_t n_tiles);
 hipError_t configure_kernels(size_t max_lds);
 hipError_t launch_sample_test(int64_t s, const View* views, const GenDev& g, const double* beam,

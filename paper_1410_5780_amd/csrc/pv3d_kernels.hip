@@ -565,11 +565,15 @@ __global__ __launch_bounds__(256) void k_tri_setup(int64_t s, const View* views,
 }
 
 // Exclusive scan of the tile counts by NT threads; every count is left at
-// zero for the next sun. With list != nullptr the tiles holding at least
-// one entry are also listed in tile order and their number returned
-// (thread 0 only).
+// zero for the next sun. With list != nullptr the tiles holding at least one
+// entry are also listed as work items and their number returned (every
+// thread): in tile order when split_at < 0, otherwise the most entries first
+// (entries bucketed by eight), a tile with more than split_at > 0 entries as
+// its four quadrants. part holds 2 NT + 2 kScanBuckets ints.
+constexpr int kScanBuckets = 256;
+
 template <int NT, bool COHERENT>
-__device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& bb, int32_t* list) {
+__device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& bb, int32_t* list, int32_t split_at) {
     const int tid = threadIdx.x;
     const int32_t per = (n_tiles + NT - 1) / NT;
     const int32_t b0 = min(tid * per, n_tiles), b1 = min(b0 + per, n_tiles);
@@ -590,6 +594,7 @@ __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& b
         part[NT + tid] += w;
         __syncthreads();
     }
+    const bool in_order = list && split_at < 0;
     int32_t run = part[tid] - sum, lpos = part[NT + tid] - nz;
     for (int32_t i = b0; i < b1; i++) {
         const int32_t c = COHERENT ? ld_dev(bb.tile_count + i) : bb.tile_count[i];
@@ -601,18 +606,57 @@ __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& b
             bb.tile_cursor[i] = run;
             bb.tile_count[i] = 0;
         }
-        if (list && c > 0) list[lpos++] = i;
+        if (in_order && c > 0) list[lpos++] = (i << 3) | kWholeTile;
         run += c;
     }
     if (tid == NT - 1) bb.tile_start[n_tiles] = part[NT - 1];
-    const int32_t n_list = part[2 * NT - 1];
+    const int32_t n_nonempty = part[2 * NT - 1];
     __syncthreads();
-    return n_list;
+    if (!list || in_order) return n_nonempty;
+    // heaviest first: counting sort of the non-empty tiles by entry bucket
+    int32_t* hist = part + 2 * NT;
+    int32_t* cur = hist + kScanBuckets;
+    for (int q = tid; q < kScanBuckets; q += NT) hist[q] = 0;
+    __syncthreads();
+    for (int32_t i = b0; i < b1; i++) {
+        const int32_t c = bb.tile_start[i + 1] - bb.tile_start[i];
+        if (c <= 0) continue;
+        const int32_t bk = kScanBuckets - 1 - min(c >> 3, kScanBuckets - 1);
+        atomicAdd(&hist[bk], (split_at > 0 && c > split_at) ? 4 : 1);
+    }
+    __syncthreads();
+    const int32_t own = tid < kScanBuckets ? hist[tid] : 0;
+    for (int off = 1; off < kScanBuckets; off <<= 1) {     // inclusive scan of the buckets
+        const int32_t v = (tid < kScanBuckets && tid >= off) ? hist[tid - off] : 0;
+        __syncthreads();
+        if (tid < kScanBuckets) hist[tid] += v;
+        __syncthreads();
+    }
+    if (tid < kScanBuckets) cur[tid] = hist[tid] - own;
+    const int32_t n_items = hist[kScanBuckets - 1];
+    __syncthreads();
+    for (int32_t i = b0; i < b1; i++) {
+        const int32_t c = bb.tile_start[i + 1] - bb.tile_start[i];
+        if (c <= 0) continue;
+        const int32_t bk = kScanBuckets - 1 - min(c >> 3, kScanBuckets - 1);
+        const bool split = split_at > 0 && c > split_at;
+        const int32_t pos = atomicAdd(&cur[bk], split ? 4 : 1);
+        if (split)
+            for (int32_t q = 0; q < 4; q++) list[pos + q] = (i << 3) | q;
+        else
+            list[pos] = (i << 3) | kWholeTile;
+    }
+    __syncthreads();
+    return n_items;
 }
 
 __global__ __launch_bounds__(1024) void k_bin_scan(int32_t n_tiles, BinBuffers bb) {
-    __shared__ int32_t part[2 * 1024];
-    scan_body<1024, false>(part, n_tiles, bb, nullptr);
+    __shared__ int32_t part[2 * 1024 + 2 * kScanBuckets];
+    const int32_t n_items = scan_body<1024, false>(part, n_tiles, bb, bb.tile_list, bb.split_at);
+    if (bb.tile_list && threadIdx.x == 0) {
+        bb.list_ctr[0] = n_items;
+        bb.list_ctr[1] = 0;
+    }
 }
 
 // Item of the scatter: a binned triangle record (kind 1) or a module (kind 2).
@@ -1281,10 +1325,11 @@ struct TileLds {
     SparseShared sh;
 };
 
-// One tile of one sun. V, bias_s and n_large are this sun's view, module
-// biases and count of unbinned triangles.
+// One work item of one sun: a tile, or a quadrant of it (the tile's samples
+// in that quadrant, against every triangle binned to the tile). V, bias_s and
+// n_large are this sun's view, module biases and count of unbinned triangles.
 template <int TS, int CAP>
-__device__ void tile_body(TileLds<TS, CAP>& L, int32_t tile, const View& V, const BinBuffers& bb, int32_t n_large,
+__device__ void tile_body(TileLds<TS, CAP>& L, int32_t item, const View& V, const BinBuffers& bb, int32_t n_large,
                           int32_t n, const GenDev& g, const int32_t* bias, const double* fu_tab,
                           const double* fv_tab, int32_t k, const TileOut& out, int32_t sparse,
                           const uint32_t* tmask) {
@@ -1305,6 +1350,7 @@ __device__ void tile_body(TileLds<TS, CAP>& L, int32_t tile, const View& V, cons
     auto& n_failed = L.n_failed;
     auto& sh = L.sh;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int32_t tile = item >> 3, part = item & 7;
     TileCtx c;
     c.n = n;
     c.x0 = (tile % bb.ntx) * TS;
@@ -1350,10 +1396,15 @@ __device__ void tile_body(TileLds<TS, CAP>& L, int32_t tile, const View& V, cons
         tb.cnt = tcnt;
         tb.list = tlist;
         if (tid == 0) {                               // rects of at most 64 x 64 texels (one lane per 8x8 stamp)
-            const int32_t rs = TS < 64 ? TS : 64;
             n_todo = 0;
-            for (int32_t y = 0; y < TS; y += rs)
-                for (int32_t x = 0; x < TS; x += rs) todo[n_todo++] = Rect{c.x0 + x, c.y0 + y, rs};
+            if (part != kWholeTile) {
+                const int32_t h = TS / 2;
+                todo[n_todo++] = Rect{c.x0 + (part & 1) * h, c.y0 + (part >> 1) * h, h};
+            } else {
+                const int32_t rs = TS < 64 ? TS : 64;
+                for (int32_t y = 0; y < TS; y += rs)
+                    for (int32_t x = 0; x < TS; x += rs) todo[n_todo++] = Rect{c.x0 + x, c.y0 + y, rs};
+            }
         }
         __syncthreads();
         while (n_todo > 0) {                              // a rect with too many samples is split in four
@@ -1379,7 +1430,11 @@ __device__ void tile_body(TileLds<TS, CAP>& L, int32_t tile, const View& V, cons
         if (tid == 0) next = 0;                           // full route for the rects that stayed too dense
         __syncthreads();
     } else {
-        if (tid == 0) { failed[0] = whole; n_failed = 1; }
+        if (tid == 0) {
+            const int32_t h = TS / 2;
+            failed[0] = part == kWholeTile ? whole : Rect{c.x0 + (part & 1) * h, c.y0 + (part >> 1) * h, h};
+            n_failed = 1;
+        }
         __syncthreads();
     }
 
@@ -1402,8 +1457,24 @@ __global__ __launch_bounds__(256) void k_tile(int64_t s, const View* views, BinB
                                               const double* fv_tab, int32_t k, TileOut out, int32_t sparse,
                                               const uint32_t* tmask) {
     __shared__ TileLds<TS, CAP> L;
-    tile_body<TS, CAP>(L, blockIdx.x, views[s], bb, ctr[s].n_large, n, g, bias + s * g.n_mod, fu_tab, fv_tab, k,
-                       out, sparse, tmask);
+    __shared__ int32_t take;
+    if (!bb.tile_list) {                      // one workgroup per tile
+        tile_body<TS, CAP>(L, ((int32_t)blockIdx.x << 3) | kWholeTile, views[s], bb, ctr[s].n_large, n, g,
+                           bias + s * g.n_mod, fu_tab, fv_tab, k, out, sparse, tmask);
+        return;
+    }
+    // the scan's work list, heaviest items first, taken one at a time
+    const int32_t n_items = bb.list_ctr[0];
+    for (;;) {
+        if (threadIdx.x == 0) take = atomicAdd(&bb.list_ctr[1], 1);
+        __syncthreads();
+        const int32_t it = take;
+        __syncthreads();
+        if (it >= n_items) break;
+        tile_body<TS, CAP>(L, bb.tile_list[it], views[s], bb, ctr[s].n_large, n, g, bias + s * g.n_mod, fu_tab, fv_tab,
+                           k, out, sparse, tmask);
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1579,7 +1650,7 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
 // ---------------------------------------------------------------------------
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 constexpr size_t kPLdsBytes = cmax(cmax(sizeof(TileLds<64, 2048>), sizeof(TileLds<32, 1024>)),
-                                   cmax(cmax(sizeof(SetupLds), sizeof(LossLds)), 2 * 256 * 4 + 1024 * 8));
+                                   cmax(cmax(sizeof(SetupLds), sizeof(LossLds)), (2 * 256 + 2 * kScanBuckets) * 4 + 1024 * 8));
 
 __device__ __forceinline__ unsigned long long pword(int32_t phase, int32_t n_units) {
     return ((unsigned long long)(uint32_t)phase << 56) | ((unsigned long long)(uint32_t)n_units << 32);
@@ -1599,6 +1670,9 @@ __device__ __forceinline__ BinBuffers slot_bins(const PLaunch& P, const PJob& J,
     bb.tile_cursor = B.tile_cursor;
     bb.bins = B.bins;
     bb.modbox = B.modbox;
+    bb.tile_list = nullptr;           // the scan and tile units use the slot's list directly
+    bb.list_ctr = nullptr;
+    bb.split_at = 0;
     bb.bin_cap = P.bin_cap;
     bb.tile = J.tile;
     bb.ntx = J.ntx;
@@ -1635,7 +1709,9 @@ __device__ __noinline__ void unit_tri(unsigned char* raw, const PJob& J, const P
 __device__ __noinline__ void unit_scan(unsigned char* raw, const PLaunch& P, const PJob& J, const PSlotBufs& B,
                                        const BinBuffers& bb, PSlotState& st) {
     int32_t* part = reinterpret_cast<int32_t*>(raw);
-    const int32_t n_list = scan_body<256, true>(part, J.n_tiles, bb, B.tile_list);
+    // tile order: a slot's workgroups sit on one XCD, and neighbouring tiles
+    // share triangle records in its L2; the slots balance the load
+    const int32_t n_list = scan_body<256, true>(part, J.n_tiles, bb, B.tile_list, -1);
     if (threadIdx.x == 0) {
         const int32_t total = part[255];
         const int32_t ovf = (ld_dev(&B.ctr->overflow) || ld_dev(&B.ctr->n_rec) > P.rec_cap || total > P.bin_cap) ? 1 : 0;
@@ -1652,7 +1728,7 @@ __device__ __noinline__ void unit_scatter(unsigned char* raw, const PJob& J, con
 
 __device__ __noinline__ void unit_tile(unsigned char* raw, const PJob& J, const PItem it, const PSlotBufs& B,
                                        const BinBuffers& bb, int32_t unit) {
-    const int32_t tile = B.tile_list[unit];
+    const int32_t item = B.tile_list[unit];
     TileOut out;
     out.map = nullptr;
     out.counts = J.counts + (int64_t)it.sun * J.cells;
@@ -1661,10 +1737,10 @@ __device__ __noinline__ void unit_tile(unsigned char* raw, const PJob& J, const 
     out.sparse = J.sparse;
     const uint32_t* tmask = J.use_mask ? B.tmask : nullptr;
     if (J.tile == 64)
-        tile_body<64, 2048>(*reinterpret_cast<TileLds<64, 2048>*>(raw), tile, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, J.g,
+        tile_body<64, 2048>(*reinterpret_cast<TileLds<64, 2048>*>(raw), item, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, J.g,
                             B.bias, J.fu, J.fv, J.k, out, J.sparse, tmask);
     else
-        tile_body<32, 1024>(*reinterpret_cast<TileLds<32, 1024>*>(raw), tile, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, J.g,
+        tile_body<32, 1024>(*reinterpret_cast<TileLds<32, 1024>*>(raw), item, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, J.g,
                             B.bias, J.fu, J.fv, J.k, out, J.sparse, tmask);
 }
 
@@ -2122,15 +2198,44 @@ hipError_t launch_bin_scatter(int64_t s, const BinBuffers& bb, int32_t n_mod, Su
     return hipGetLastError();
 }
 
+// Workgroups of the tile kernel: one per tile, or, with the work list, as
+// many as stay resident (at most one per possible item), each taking items
+// until the list is empty.
+template <int TS, int CAP>
+static hipError_t tile_launch(dim3 (&grid), const BinBuffers& bb, int32_t n_cu) {
+    grid = dim3((unsigned)bb.n_tiles);
+    if (!bb.tile_list) return hipSuccess;
+    static int per_cu = 0;                     // the same code object on every device of one architecture
+    if (per_cu == 0) {
+        int nb = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tile<TS, CAP>, 256, 0);
+        if (e != hipSuccess) return e;
+        per_cu = nb > 0 ? nb : 1;
+    }
+    const int64_t most = 4 * (int64_t)bb.n_tiles;
+    grid = dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(most, (int64_t)n_cu * per_cu)));
+    return hipSuccess;
+}
+
 hipError_t launch_raster(int64_t s, const View* views, const BinBuffers& bb, const SunCounters* ctr, int32_t n,
                          const GenDev& g, const int32_t* bias, const double* fu, const double* fv, int32_t k,
-                         const TileOut& out, const uint32_t* tmask, hipStream_t st) {
-    dim3 grid((unsigned)bb.n_tiles);
+                         const TileOut& out, const uint32_t* tmask, int32_t n_cu, hipStream_t st) {
+    dim3 grid;
+    hipError_t e;
     const int32_t sparse = out.sparse;
     switch (bb.tile) {
-        case 32: hipLaunchKernelGGL((k_tile<32, 1024>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out, sparse, tmask); break;
-        case 64: hipLaunchKernelGGL((k_tile<64, 2048>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out, sparse, tmask); break;
-        case 128: hipLaunchKernelGGL((k_tile<128, 4096>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out, sparse, tmask); break;
+        case 32:
+            if ((e = tile_launch<32, 1024>(grid, bb, n_cu))) return e;
+            hipLaunchKernelGGL((k_tile<32, 1024>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out, sparse, tmask);
+            break;
+        case 64:
+            if ((e = tile_launch<64, 2048>(grid, bb, n_cu))) return e;
+            hipLaunchKernelGGL((k_tile<64, 2048>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out, sparse, tmask);
+            break;
+        case 128:
+            if ((e = tile_launch<128, 4096>(grid, bb, n_cu))) return e;
+            hipLaunchKernelGGL((k_tile<128, 4096>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out, sparse, tmask);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -59,12 +59,12 @@ struct PathSizes {
 };
 
 struct Work {
-    Buf rec, large, bins, tile_count, tile_start, tile_cursor, map;
+    Buf rec, large, bins, tile_count, tile_start, tile_cursor, tile_list, map;
     Buf views, ctr, beam, bias, sweep, sphere, partial, fu, fv, modbox, tmask;
     Buf counts, outd, maps, bits;
     void release_all(Ctx* c) {
-        Buf* all[] = {&rec, &large, &bins, &tile_count, &tile_start, &tile_cursor, &map, &views, &ctr, &beam,
-                      &bias, &sweep, &sphere, &partial, &fu, &fv, &modbox, &tmask, &counts, &outd, &maps, &bits};
+        Buf* all[] = {&rec, &large, &bins, &tile_count, &tile_start, &tile_cursor, &tile_list, &map, &views, &ctr,
+                      &beam, &bias, &sweep, &sphere, &partial, &fu, &fv, &modbox, &tmask, &counts, &outd, &maps, &bits};
         for (Buf* b : all) b->release(c);
     }
 };
@@ -109,6 +109,7 @@ struct Ctx {
     uint64_t budget = 0;
     uint64_t used = 0;
     size_t max_lds = 65536;
+    int32_t n_cu = 256;
     std::map<void*, size_t> sizes;
     std::map<uint64_t, Scene> scenes;
     std::map<uint64_t, Gen> gens;

@@ -282,6 +282,7 @@ pv3d_status Ctx::ensure_path(const PathSizes& z, const Gen& g, int32_t map_n, bo
     if ((st = w.tile_count.ensure(this, 4 * (size_t)z.n_tiles, "tile counts"))) return st;
     if ((st = w.tile_start.ensure(this, 4 * (size_t)(z.n_tiles + 1), "tile starts"))) return st;
     if ((st = w.tile_cursor.ensure(this, 4 * (size_t)z.n_tiles, "tile cursors"))) return st;
+    if ((st = w.tile_list.ensure(this, 4 * (4 * (size_t)z.n_tiles + 2), "tile work list"))) return st;
     if (own_map && (st = w.map.ensure(this, 4 * (size_t)map_n * map_n, "depth picture"))) return st;
     if ((st = w.views.ensure(this, sizeof(View) * (size_t)std::max<int64_t>(z.n_sun, 1), "views"))) return st;
     if ((st = w.ctr.ensure(this, sizeof(SunCounters) * (size_t)std::max<int64_t>(z.n_sun, 1), "counters"))) return st;
@@ -306,6 +307,9 @@ BinBuffers Ctx::bin_buffers(const PathSizes& z) {
     bb.tile_cursor = static_cast<int32_t*>(w.tile_cursor.ptr);
     bb.bins = static_cast<int32_t*>(w.bins.ptr);
     bb.modbox = static_cast<int4*>(w.modbox.ptr);
+    bb.tile_list = nullptr;                // one workgroup per tile unless the sun takes the work list
+    bb.list_ctr = nullptr;
+    bb.split_at = 0;
     bb.bin_cap = (int32_t)z.bin_cap;
     bb.tile = z.tile;
     bb.ntx = z.ntx;
@@ -410,6 +414,11 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
     return PV3D_OK;
 }
 
+// 64-texel tiles with more bin entries than this go to four workgroups, one per
+// quadrant (each still walks all of the tile's triangles): the heaviest tiles,
+// under tall occluders, otherwise finish long after the rest of the launch.
+constexpr int32_t kSplitEntries = 64;
+
 // The launch sequence of one sun.
 pv3d_status Ctx::run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, const GenDev& gd, const pv3d_params& p,
                          const View* views, SunCounters* ctr, const int32_t* bias, const double* beam, uint32_t* map,
@@ -419,21 +428,27 @@ pv3d_status Ctx::run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, cons
     const bool separate = (p.flags & PV3D_SEPARATE_TEST) != 0;
     if (separate && !map) map = static_cast<uint32_t*>(w.map.ptr);
     const int32_t scatter_grid = 1024;
-    if ((e = timed(prof, PV3D_STAGE_TRI_SETUP, st, [&] { return launch_tri_setup(s, views, sd, gd, bias, p.map_n, bb, ctr, tmask_s, st); })))
-        return hip_fail(e, "tri_setup");
-    if ((e = timed(prof, PV3D_STAGE_BIN_SCAN, st, [&] { return launch_bin_scan(z.n_tiles, bb, st); })))
-        return hip_fail(e, "bin_scan");
-    if ((e = timed(prof, PV3D_STAGE_BIN_SCATTER, st, [&] { return launch_bin_scatter(s, bb, gd.n_mod, ctr, scatter_grid, tmask_s, st); })))
-        return hip_fail(e, "bin_scatter");
     TileOut to;
     to.map = map;
     to.counts = counts_s;
     to.bits = bits_s;
     to.test = separate ? 0 : 1;
     to.sparse = (map == nullptr && !separate && !(p.flags & PV3D_FULL_RASTER)) ? 1 : 0;
+    if (to.sparse) {       // the scan lists the tiles with work, heaviest first; 64-texel ones split in quadrants
+        int32_t* tl = static_cast<int32_t*>(w.tile_list.ptr);
+        bb.list_ctr = tl;
+        bb.tile_list = tl + 2;
+        bb.split_at = z.tile == 64 ? kSplitEntries : 0;
+    }
+    if ((e = timed(prof, PV3D_STAGE_TRI_SETUP, st, [&] { return launch_tri_setup(s, views, sd, gd, bias, p.map_n, bb, ctr, tmask_s, st); })))
+        return hip_fail(e, "tri_setup");
+    if ((e = timed(prof, PV3D_STAGE_BIN_SCAN, st, [&] { return launch_bin_scan(z.n_tiles, bb, st); })))
+        return hip_fail(e, "bin_scan");
+    if ((e = timed(prof, PV3D_STAGE_BIN_SCATTER, st, [&] { return launch_bin_scatter(s, bb, gd.n_mod, ctr, scatter_grid, tmask_s, st); })))
+        return hip_fail(e, "bin_scatter");
     if ((e = timed(prof, PV3D_STAGE_RASTER, st, [&] {
              return launch_raster(s, views, bb, ctr, p.map_n, gd, bias, static_cast<double*>(w.fu.ptr),
-                                  static_cast<double*>(w.fv.ptr), p.k, to, tmask_s, st);
+                                  static_cast<double*>(w.fv.ptr), p.k, to, tmask_s, n_cu, st);
          })))
         return hip_fail(e, "raster");
     if (separate &&
@@ -497,6 +512,7 @@ pv3d_status pv3d_create(int32_t device, uint64_t hbm_budget_bytes, pv3d_ctx** ou
         hipDeviceProp_t prop;
         if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
         c->max_lds = prop.sharedMemPerBlock;
+        c->n_cu = prop.multiProcessorCount;
         if ((e = configure_kernels(c->max_lds)) != hipSuccess) return hip_fail(e, "configure kernels");
     }
     *out = c.release();

@@ -213,9 +213,10 @@ SlotGeom slot_geom(int64_t rec_cap, int64_t bin_cap, int64_t max_tiles, int64_t 
     g.per_large = al256(4 * (size_t)rec_cap);
     g.per_bins = al256(4 * (size_t)bin_cap);
     g.per_t = al256(4 * (size_t)(max_tiles + 1));
+    g.per_list = al256(4 * (size_t)max_tiles);           // one item per tile, in tile order
     g.per_mod = al256(16 * (size_t)max_mod) + al256(8 * (size_t)max_mod) + al256(4 * (size_t)max_mod);
     g.per_misc = 256 /*view*/ + al256(4 * 512) /*mask*/ + 256 /*counters*/;
-    g.slot_bytes = g.per_rec + g.per_large + g.per_bins + 4 * g.per_t + g.per_mod + g.per_misc;
+    g.slot_bytes = g.per_rec + g.per_large + g.per_bins + 3 * g.per_t + g.per_list + g.per_mod + g.per_misc;
     return g;
 }
 
@@ -227,7 +228,7 @@ char* carve_slots(char* q, const SlotGeom& g, int64_t n_slots, std::vector<PSlot
     char* r_tc = q; q += g.per_t * ns;
     char* r_ts = q; q += g.per_t * ns;
     char* r_tcur = q; q += g.per_t * ns;
-    char* r_tl = q; q += g.per_t * ns;
+    char* r_tl = q; q += g.per_list * ns;
     char* r_mod = q; q += g.per_mod * ns;
     char* r_misc = q;
     out.resize(ns);
@@ -239,7 +240,7 @@ char* carve_slots(char* q, const SlotGeom& g, int64_t n_slots, std::vector<PSlot
         b.tile_count = reinterpret_cast<int32_t*>(r_tc + g.per_t * i);
         b.tile_start = reinterpret_cast<int32_t*>(r_ts + g.per_t * i);
         b.tile_cursor = reinterpret_cast<int32_t*>(r_tcur + g.per_t * i);
-        b.tile_list = reinterpret_cast<int32_t*>(r_tl + g.per_t * i);
+        b.tile_list = reinterpret_cast<int32_t*>(r_tl + g.per_list * i);
         char* m = r_mod + g.per_mod * i;
         b.modbox = reinterpret_cast<int4*>(m);
         b.beam = reinterpret_cast<double*>(m + al256(16 * (size_t)g.max_mod));

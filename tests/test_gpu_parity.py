@@ -86,6 +86,15 @@ def test_random_tiny_ragged(ctx, oracle_lib, seed, n, k, tile):
     compare(ctx, oracle_lib, w, tile=tile)
 
 
+@pytest.mark.parametrize("seed,n", [(61, 256), (62, 200)])
+def test_dense_tiles_split_in_quadrants(ctx, oracle_lib, seed, n):
+    """Thousands of loose triangles over the generator: every 64-texel tile holds
+    far more than 64 bin entries, so the tile pass takes each as four quadrant
+    items (a ragged map at n = 200)."""
+    w = W.random_tiny(seed, n_boxes=4, n_loose=2500, n_mod_side=3, map_n=n, k=4, n_sun=5)
+    compare(ctx, oracle_lib, w, tile=64)
+
+
 def test_tile_sizes_give_identical_results(ctx):
     w = W.random_tiny(41, n_boxes=12, n_loose=60, n_mod_side=3, map_n=300, k=4, n_sun=5)
     sh, gh = ctx.load_scene(w.scene), ctx.define_generator(w.gen)
