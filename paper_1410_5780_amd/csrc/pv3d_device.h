@@ -109,8 +109,10 @@ struct GenDev {
 struct SceneDev {
     const double* xyz;
     const int32_t* tri;
+    const double* cbox;     // [ceil(n_tri / 256)][6] vertex box (lo xyz, hi xyz) of each block of 256 triangles
     int64_t n_vert, n_tri;
 };
+constexpr int kTriBlock = 256;
 
 // ---- persistent launch: every (job, sun) item of a batch in one launch ----
 // Phases of one item, in order; a phase is split into units that any

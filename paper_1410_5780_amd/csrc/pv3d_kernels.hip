@@ -485,6 +485,28 @@ __device__ __noinline__ void clip_and_emit(d3 t0, d3 t1, d3 t2, int32_t n, BinBu
 // (t0 a multiple of 256; 256 at a time): set-up, then per-tile counts
 // accumulated in LDS (cnt, n_tiles words) and added to the global counts
 // once; with cnt == nullptr every pair goes straight to the global counts.
+// True when every triangle of scene block blk would be culled for this view:
+// the block's vertex box, mapped to light space corner by corner, lies beyond
+// the far depth or wholly outside the window by more than a texel. The
+// per-triangle test sees each vertex's own mapping, which differs from the
+// corners' convex combination by rounding many orders of magnitude below the
+// margin, so the skip never drops a triangle the test would keep.
+__device__ __forceinline__ bool block_culled(const View& V, const double* cbox, int64_t blk, int32_t n) {
+    const double* b = cbox + 6 * blk;
+    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY, z0 = INFINITY;
+    for (int q = 0; q < 8; q++) {
+        const d3 l = to_light(V, d3{b[(q & 1) ? 3 : 0], b[(q & 2) ? 4 : 1], b[(q & 4) ? 5 : 2]});
+        x0 = fmin(x0, l.x); x1 = fmax(x1, l.x);
+        y0 = fmin(y0, l.y); y1 = fmax(y1, l.y);
+        z0 = fmin(z0, l.z);
+    }
+    auto mg = [](double v) { return 1.0 + 1e-9 * fabs(v); };
+    return z0 > (double)kDepthMax + mg(z0) || x1 < -mg(x1) || x0 >= (double)n + mg(x0) || y1 < -mg(y1) ||
+           y0 >= (double)n + mg(y0);
+}
+
+// Triangles [t0, t1) of the set-up index space (scene triangles, module
+// triangles, modules); t0 is a multiple of kTriBlock.
 __device__ void tri_setup_body(uint32_t* cnt, int64_t t0, int64_t t1, const View& V, const SceneDev& sc,
                                const GenDev& g, const int32_t* bias_s, int32_t n, const BinBuffers& bb,
                                SunCounters* ctr_s, const uint32_t* tmask_s) {
@@ -495,47 +517,56 @@ __device__ void tri_setup_body(uint32_t* cnt, int64_t t0, int64_t t1, const View
             if (t >= n_tri_all && t < n_tri_all + g.n_mod) bb.modbox[t - n_tri_all] = make_int4(1, 0, 1, 0);
         return;
     }
+    if (sc.cbox && t1 <= sc.n_tri) {                   // scene triangles only: leave if every block is culled
+        bool all = true;
+        for (int64_t tb = t0; tb < t1 && all; tb += kTriBlock) all = block_culled(V, sc.cbox, tb / kTriBlock, n);
+        if (all) return;
+    }
     uint32_t* gcnt = reinterpret_cast<uint32_t*>(bb.tile_count);
     if (cnt) {
         for (int32_t q = threadIdx.x; q < bb.n_tiles; q += 256) cnt[q] = 0;
         __syncthreads();
     }
     uint32_t* sink = cnt ? cnt : gcnt;
+    static_assert(kTriBlock == 256, "one thread per triangle of a block");
     for (int64_t tb = t0; tb < t1; tb += 256) {
         const int64_t t = tb + threadIdx.x;
+        const bool skip = sc.cbox && tb < sc.n_tri && block_culled(V, sc.cbox, tb / kTriBlock, n);
         TileBox box{1, 0, 1, 0};
         int32_t kind = 0;
         Edges E;
         for (int e = 0; e < 3; e++) { E.e0[e] = 0; E.a[e] = 0; E.b[e] = 0; }
         E.ilo = E.ihi = E.jlo = E.jhi = 0;
         if (t < t1 && t < n_tri_all) {
-            d3 c[3];
-            if (t < sc.n_tri) {
-                for (int q = 0; q < 3; q++) c[q] = ld3(sc.xyz + 3 * (int64_t)sc.tri[3 * t + q]);
-            } else {
-                int64_t mt = t - sc.n_tri;
-                const Module& M = g.mods[mt / 2];
-                module_corner(M, 0, c[0]);
-                if ((mt & 1) == 0) { module_corner(M, 1, c[1]); module_corner(M, 2, c[2]); }
-                else { module_corner(M, 2, c[1]); module_corner(M, 3, c[2]); }
-            }
-            d3 l[3];
-            for (int q = 0; q < 3; q++) l[q] = to_light(V, c[q]);
-            double zmin = fmin(l[0].z, fmin(l[1].z, l[2].z));
-            double xmin = fmin(l[0].x, fmin(l[1].x, l[2].x)), xmax = fmax(l[0].x, fmax(l[1].x, l[2].x));
-            double ymin = fmin(l[0].y, fmin(l[1].y, l[2].y)), ymax = fmax(l[0].y, fmax(l[1].y, l[2].y));
-            bool keep = !(zmin > (double)kDepthMax) && !(xmax < 0.0 || xmin >= (double)n || ymax < 0.0 || ymin >= (double)n);
-            if (keep) {
-                bool big = false;
-                for (int q = 0; q < 3; q++)
-                    if (fabs(l[q].x) >= kGuard || fabs(l[q].y) >= kGuard) big = true;
-                if (big) {
-                    clip_and_emit(l[0], l[1], l[2], n, bb, ctr_s, sink, tmask_s);
+            if (!(skip && t < sc.n_tri)) {
+                d3 c[3];
+                if (t < sc.n_tri) {
+                    for (int q = 0; q < 3; q++) c[q] = ld3(sc.xyz + 3 * (int64_t)sc.tri[3 * t + q]);
                 } else {
-                    bool large = false;
-                    if (emit_triangle(l, n, bb, ctr_s, E, large) >= 0 && !large) {
-                        box = rec_box(E.ilo, E.ihi, E.jlo, E.jhi, bb.tile);
-                        kind = 1;
+                    int64_t mt = t - sc.n_tri;
+                    const Module& M = g.mods[mt / 2];
+                    module_corner(M, 0, c[0]);
+                    if ((mt & 1) == 0) { module_corner(M, 1, c[1]); module_corner(M, 2, c[2]); }
+                    else { module_corner(M, 2, c[1]); module_corner(M, 3, c[2]); }
+                }
+                d3 l[3];
+                for (int q = 0; q < 3; q++) l[q] = to_light(V, c[q]);
+                double zmin = fmin(l[0].z, fmin(l[1].z, l[2].z));
+                double xmin = fmin(l[0].x, fmin(l[1].x, l[2].x)), xmax = fmax(l[0].x, fmax(l[1].x, l[2].x));
+                double ymin = fmin(l[0].y, fmin(l[1].y, l[2].y)), ymax = fmax(l[0].y, fmax(l[1].y, l[2].y));
+                bool keep = !(zmin > (double)kDepthMax) && !(xmax < 0.0 || xmin >= (double)n || ymax < 0.0 || ymin >= (double)n);
+                if (keep) {
+                    bool big = false;
+                    for (int q = 0; q < 3; q++)
+                        if (fabs(l[q].x) >= kGuard || fabs(l[q].y) >= kGuard) big = true;
+                    if (big) {
+                        clip_and_emit(l[0], l[1], l[2], n, bb, ctr_s, sink, tmask_s);
+                    } else {
+                        bool large = false;
+                        if (emit_triangle(l, n, bb, ctr_s, E, large) >= 0 && !large) {
+                            box = rec_box(E.ilo, E.ihi, E.jlo, E.jhi, bb.tile);
+                            kind = 1;
+                        }
                     }
                 }
             }
@@ -1090,7 +1121,51 @@ struct SparseLds {
 
 struct SparseShared {
     int32_t n_ent, ent_overflow, max_thr, next, n_slots;
+    int32_t wsum[4];
 };
+
+// Exclusive prefix sum of v over the 256 threads of a workgroup; total gets
+// the sum. Every thread calls it (it holds two barriers).
+__device__ __forceinline__ int32_t block_scan_excl(int32_t v, int32_t* wsum, int32_t& total, int lane, int wv) {
+    int32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int32_t base = 0;
+    total = 0;
+    for (int w = 0; w < 4; w++) {
+        const int32_t t = wsum[w];
+        base += w < wv ? t : 0;
+        total += t;
+    }
+    __syncthreads();
+    return base + x - v;
+}
+
+// Lanes of the wave below this one whose bit is set.
+__device__ __forceinline__ int32_t lanes_below(unsigned long long bal) {
+    return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+}
+
+// Last index i in [0, n) with key(a[i]) <= x, for keys that do not decrease
+// and key(a[0]) <= x.
+template <int SHIFT>
+__device__ __forceinline__ int32_t last_at_most(const uint32_t* a, int32_t n, uint32_t x) {
+    int32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if ((a[mid] >> SHIFT) <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Light-space maps of the first kMapCache module slots of a tile are kept in
+// LDS while its samples are listed.
+constexpr int kMapCache = 64;
 
 // A triangle of the current chunk, relative to the rect origin: edge k at
 // texel (li, lj) of the rect is ex[k] + A[k] li + B[k] lj, depth
@@ -1126,49 +1201,109 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
     if (tid == 0) { sh.n_ent = 0; sh.ent_overflow = 0; sh.max_thr = INT32_MIN; sh.next = 0; }
     for (int q = tid; q <= r.size; q += 256) rowstart[q] = 0;
     __syncthreads();
-    // 1. the samples whose texel lies in the rect: waves over modules; a wave
-    //    walks 8 x 8 blocks of (row, column) sample indices covering the rows'
-    //    exact column ranges, lane (r, c) = (lane / 8, lane % 8)
+    // 1. the samples whose texel lies in the rect, in three steps: a thread per
+    //    module finds its light-space map and conservative row range; a thread
+    //    per row finds the row's column range; the (row, column) candidates are
+    //    then spread evenly over all threads, each finding its row by binary
+    //    search, and the entries are allocated once per wave.
+    //    Meanwhile `cells` holds the row tables, the triangle slots the map
+    //    cache and the (not yet used) entry order the module biases.
+    uint32_t* const mstart = cells;            // [256] (first row << 12) | first row index qb0, per module slot
+    uint32_t* const rmq = cells + 256;         // [256] (module slot << 12) | qb, per row of a pass
+    uint32_t* const ra0 = cells + 512;         // [256] first column of the row's range
+    uint32_t* const rst = cells + 768;         // [256] first candidate of the row
+    ModMap* const mcache = reinterpret_cast<ModMap*>(tb.slot);
+    int32_t* const mbias = reinterpret_cast<int32_t*>(sp.order);
+    static_assert(sizeof(ModMap) * kMapCache <= sizeof(TriSlot) * kTriChunk, "map cache exceeds the slot area");
+    static_assert(kMaxTileMods <= 256 && 4 * kMaxTileMods <= 2 * CAP, "one thread per module slot, biases in the order area");
     const double dknu = (double)knu, dknv = (double)knv;
     int32_t my_max = INT32_MIN;
-    for (int32_t mi = wv; mi < n_mods; mi += 4) {
-        const int32_t m = mods[mi];
-        const int32_t bm = bias[m];
-        if (bm < 0) continue;
-        ModMap mm;
-        module_map(V, g.mods[m], mm);
-        int32_t qb0, qb1;
-        row_range(mm, knv, xl, xh, yl, yh, qb0, qb1);
-        for (int32_t rb = qb0; rb <= qb1; rb += 8) {
-            const int32_t qb = rb + (lane >> 3);
-            double fv = 0.0;
-            int32_t qa0 = 1, qa1 = 0;
-            if (qb <= qb1) {
-                fv = ((double)qb + 0.5) / dknv;         // the sample's fraction along edge_v
-                col_range(mm, fv, knu, xl, xh, yl, yh, qa0, qa1);
-            }
-            int32_t blo = qa0 <= qa1 ? qa0 : INT32_MAX, bhi = qa0 <= qa1 ? qa1 : -1;
-            for (int off = 8; off < 64; off <<= 1) {    // union of the 8 rows' ranges
-                blo = min(blo, __shfl_xor(blo, off, 64));
-                bhi = max(bhi, __shfl_xor(bhi, off, 64));
-            }
-            for (int32_t cb = blo; cb <= bhi; cb += 8) {
-                const int32_t qa = cb + (lane & 7);
-                if (qa < qa0 || qa > qa1) continue;
-                const double fu = ((double)qa + 0.5) / dknu;   // the sample's fraction along edge_u
-                int32_t li, lj, zs;
-                if (!sample_in_rect(mm, fu, fv, r, c.n, &li, &lj, &zs)) continue;
-                const int32_t e = atomicAdd(&sh.n_ent, 1);
-                if (e >= CAP) { sh.ent_overflow = 1; continue; }
-                const int64_t th64 = (int64_t)zs - (int64_t)bm;
-                const int32_t th = th64 < (int64_t)INT32_MIN ? INT32_MIN : (int32_t)th64;
-                sp.texel[e] = (uint16_t)(lj * TS + li);
-                sp.thr[e] = th;
-                sp.code[e] = ((uint32_t)mi << 24) | ((uint32_t)qb << 12) | (uint32_t)qa;
-                sp.dmin[e] = kDepthMax;
-                my_max = max(my_max, th);
+    int32_t n_rows;
+    {
+        int32_t rows = 0, qb0 = 0;
+        if (tid < n_mods) {
+            const int32_t m = mods[tid];
+            const int32_t bm = bias[m];
+            mbias[tid] = bm;
+            if (bm >= 0) {                              // back-lit modules have no samples to test
+                ModMap mm;
+                module_map(V, g.mods[m], mm);
+                if (tid < kMapCache) mcache[tid] = mm;
+                int32_t qb1;
+                row_range(mm, knv, xl, xh, yl, yh, qb0, qb1);
+                rows = qb0 <= qb1 ? qb1 - qb0 + 1 : 0;
             }
         }
+        const int32_t first = block_scan_excl(rows, sh.wsum, n_rows, lane, wv);
+        if (tid < n_mods) mstart[tid] = ((uint32_t)first << 12) | (uint32_t)qb0;
+        __syncthreads();
+    }
+    for (int32_t p0 = 0; p0 < n_rows; p0 += 256) {
+        const int32_t rho = p0 + tid;
+        int32_t cnt = 0;
+        uint32_t rq = 0, a0 = 0;
+        if (rho < n_rows) {
+            const int32_t mi = last_at_most<12>(mstart, n_mods, (uint32_t)rho);
+            const int32_t qb = (int32_t)(mstart[mi] & 0xFFFu) + rho - (int32_t)(mstart[mi] >> 12);
+            ModMap mm;
+            if (mi < kMapCache) mm = mcache[mi];
+            else module_map(V, g.mods[mods[mi]], mm);
+            const double fv = ((double)qb + 0.5) / dknv;     // the sample's fraction along edge_v
+            int32_t qa0, qa1;
+            col_range(mm, fv, knu, xl, xh, yl, yh, qa0, qa1);
+            cnt = qa0 <= qa1 ? qa1 - qa0 + 1 : 0;
+            rq = ((uint32_t)mi << 12) | (uint32_t)qb;
+            a0 = (uint32_t)qa0;
+        }
+        int32_t n_cand;
+        const int32_t first = block_scan_excl(cnt, sh.wsum, n_cand, lane, wv);
+        rmq[tid] = rq;
+        ra0[tid] = a0;
+        rst[tid] = (uint32_t)first;
+        __syncthreads();
+        const int32_t nr = min(256, n_rows - p0);
+        for (int32_t c0 = 0; c0 < n_cand; c0 += 256) {
+            const int32_t cand = c0 + tid;
+            bool ok = false;
+            int32_t li = 0, lj = 0, th = 0;
+            uint32_t code = 0;
+            if (cand < n_cand) {
+                const int32_t row = last_at_most<0>(rst, nr, (uint32_t)cand);
+                const uint32_t q = rmq[row];
+                const int32_t mi = (int32_t)(q >> 12), qb = (int32_t)(q & 0xFFFu);
+                const int32_t qa = (int32_t)ra0[row] + cand - (int32_t)rst[row];
+                ModMap mm;
+                const int32_t bm = mbias[mi];
+                if (mi < kMapCache) mm = mcache[mi];
+                else module_map(V, g.mods[mods[mi]], mm);
+                const double fv = ((double)qb + 0.5) / dknv;
+                const double fu = ((double)qa + 0.5) / dknu;     // the sample's fraction along edge_u
+                int32_t zs;
+                ok = sample_in_rect(mm, fu, fv, r, c.n, &li, &lj, &zs);
+                if (ok) {
+                    const int64_t th64 = (int64_t)zs - (int64_t)bm;
+                    th = th64 < (int64_t)INT32_MIN ? INT32_MIN : (int32_t)th64;
+                    code = ((uint32_t)mi << 24) | ((uint32_t)qb << 12) | (uint32_t)qa;
+                    my_max = max(my_max, th);
+                }
+            }
+            const unsigned long long bal = __ballot(ok);
+            int32_t wbase = 0;
+            if (lane == 0 && bal) wbase = atomicAdd(&sh.n_ent, __popcll(bal));
+            wbase = __builtin_amdgcn_readfirstlane(wbase);
+            if (ok) {
+                const int32_t e = wbase + lanes_below(bal);
+                if (e >= CAP) {
+                    sh.ent_overflow = 1;
+                } else {
+                    sp.texel[e] = (uint16_t)(lj * TS + li);
+                    sp.thr[e] = th;
+                    sp.code[e] = code;
+                    sp.dmin[e] = kDepthMax;
+                }
+            }
+        }
+        __syncthreads();                                   // the row tables are rewritten by the next pass
     }
     for (int off = 1; off < 64; off <<= 1) my_max = max(my_max, __shfl_xor(my_max, off, 64));
     if (lane == 0 && my_max != INT32_MIN) atomicMax(&sh.max_thr, my_max);
@@ -1183,8 +1318,14 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
         atomicAdd(&rowstart[(tx / TS / 8) * spr + (tx % TS) / 8 + 1], 1);
     }
     __syncthreads();
-    if (tid == 0)
-        for (int q = 1; q <= n_st; q++) rowstart[q] += rowstart[q - 1];
+    if (wv == 0) {                                  // inclusive scan of the <= 64 stamp counts
+        int32_t x = lane < n_st ? rowstart[lane + 1] : 0;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane < n_st) rowstart[lane + 1] = x;
+    }
     __syncthreads();
     for (int q = tid; q < n_st; q += 256) cells[q] = (uint32_t)rowstart[q];
     __syncthreads();
@@ -1770,7 +1911,24 @@ __device__ __forceinline__ int32_t xcc_id() { return (int32_t)__builtin_amdgcn_s
 struct PCtl {
     int32_t slot, unit, phase, units;
     int32_t stop, finish, job_last, job;
+    int32_t count;          // units claimed at once: unit, unit + 1, ...
 };
+
+// Units of the many-unit phases (triangles, scatter, tiles) are claimed a
+// quarter of the remaining ones at a time, at most kMaxClaim, and run one
+// after the other: every claim is an atomic on the slot word that all of
+// the XCD's workgroups contend for. One unit per claim spent about a third
+// of the launch in claiming; the guided claim also keeps the last units of
+// a phase small, so the item's next phase is not held up.
+constexpr int32_t kMaxClaim = 32;
+constexpr int32_t kClaimDiv = 4;
+
+__device__ __forceinline__ int32_t claim_size(unsigned long long w) {
+    const int32_t ph = w_phase(w);
+    if (ph != kPhTri && ph != kPhScatter && ph != kPhTile) return 1;
+    const uint32_t left = w_units(w) - min(w_units(w), w_next(w));
+    return max(1, min(kMaxClaim, (int32_t)(left / kClaimDiv)));
+}
 
 __device__ __forceinline__ void publish(PSlotState& st, int32_t phase, int32_t n_units) {
     __hip_atomic_store(&st.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1953,7 +2111,7 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
             }
         }
         if (tid < 64) {                                   // wave 0 looks for a unit
-            int32_t got = -1, gj = 0, unit = 0, phase = 0, units = 0;
+            int32_t got = -1, gj = 0, unit = 0, phase = 0, units = 0, count = 0;
             const bool aborted = __hip_atomic_load(&P.sched->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
             for (int32_t base = 0; base < n_mine && got < 0 && !aborted; base += 64) {
                 const int32_t kk = base + lane;
@@ -1963,9 +2121,16 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
                 // the oldest item with an open unit first: few items per XCD at a time keep
                 // their buffers in its L2, while phases of younger items fill the gaps
                 int32_t key = INT32_MAX;
-                if (kk < n_mine &&
-                    w_open(__hip_atomic_load(&P.state[i].word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
-                    key = ld_dev(&P.state[i].item);
+                int32_t want = 1;
+                if (kk < n_mine) {                      // word and item loaded together: one trip to L2
+                    const unsigned long long w =
+                        __hip_atomic_load(&P.state[i].word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const int32_t itm = ld_dev(&P.state[i].item);
+                    if (w_open(w)) key = itm;
+                    // while serving, the feed pollers take one unit at a time: a poller held
+                    // in a long claim leaves new items unseen and slots empty
+                    want = (P.serve && (int32_t)blockIdx.x < kPollers) ? 1 : claim_size(w);
+                }
                 for (int attempt = 0; attempt < 64 && got < 0; attempt++) {
                     int32_t kmin = key, l = lane;
                     for (int off = 32; off > 0; off >>= 1) {
@@ -1976,16 +2141,19 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
                         }
                     }
                     if (kmin == INT32_MAX) break;
-                    int32_t ok = 0, u = 0, ph = 0, nu = 0;
+                    int32_t ok = 0, u = 0, ph = 0, nu = 0, cn = 0;
                     if (lane == l) {
                         key = INT32_MAX;
-                        const unsigned long long o =
-                            __hip_atomic_fetch_add(&P.state[i].word, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        // the phase may have moved on since the word was read: the claim
+                        // covers whatever units of the current phase the add returns
+                        const unsigned long long o = __hip_atomic_fetch_add(
+                            &P.state[i].word, (unsigned long long)want, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         if (w_open(o)) {
                             ok = 1;
                             u = (int32_t)w_next(o);
                             ph = w_phase(o);
                             nu = (int32_t)w_units(o);
+                            cn = min(want, nu - u);
                         }
                     }
                     ok = __shfl(ok, l, 64);
@@ -1995,6 +2163,7 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
                         unit = __shfl(u, l, 64);
                         phase = __shfl(ph, l, 64);
                         units = __shfl(nu, l, 64);
+                        count = __shfl(cn, l, 64);
                     }
                 }
             }
@@ -2042,6 +2211,7 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
                 ctl.unit = unit;
                 ctl.phase = phase;
                 ctl.units = units;
+                ctl.count = count;
                 ctl.stop = 0;
             }
             if (got >= 0) {
@@ -2081,7 +2251,7 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
             }
         }
         __syncthreads();
-        const int32_t slot = ctl.slot, unit = ctl.unit, phase = ctl.phase;
+        const int32_t slot = ctl.slot, unit = ctl.unit, phase = ctl.phase, count = ctl.count;
         if (slot < 0) {
             const int32_t stop = ctl.stop;
             __syncthreads();
@@ -2096,10 +2266,25 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
             const BinBuffers bb = slot_bins(P, J, B);
             switch (phase) {
                 case kPhSetup: unit_setup(raw, J, it, B); break;
-                case kPhTri: unit_tri(raw, J, B, bb, unit); break;
+                case kPhTri:
+                    for (int32_t q = 0; q < count; q++) {
+                        if (q) __syncthreads();
+                        unit_tri(raw, J, B, bb, unit + q);
+                    }
+                    break;
                 case kPhScan: unit_scan(raw, P, J, B, bb, st); break;
-                case kPhScatter: unit_scatter(raw, J, B, bb, unit, ctl.units); break;
-                case kPhTile: unit_tile(raw, J, it, B, bb, unit); break;
+                case kPhScatter:
+                    for (int32_t q = 0; q < count; q++) {
+                        if (q) __syncthreads();
+                        unit_scatter(raw, J, B, bb, unit + q, ctl.units);
+                    }
+                    break;
+                case kPhTile:
+                    for (int32_t q = 0; q < count; q++) {
+                        if (q) __syncthreads();
+                        unit_tile(raw, J, it, B, bb, unit + q);
+                    }
+                    break;
                 default: unit_loss(raw, J, it, B); break;
             }
         }
@@ -2116,9 +2301,9 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         if (tid == 0) {
-            __hip_atomic_fetch_add(&P.sched->units, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t d =
-                __hip_atomic_fetch_add(&P.state[slot].done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+            __hip_atomic_fetch_add(&P.sched->units, (unsigned long long)count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t d = __hip_atomic_fetch_add(&P.state[slot].done, (uint32_t)count, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT) + (uint32_t)count;
             ctl.finish = d == (uint32_t)ctl.units ? 1 : 0;
             if (ctl.finish) acquire_unit(G);                   // the other units of the phase
         }

@@ -37,6 +37,7 @@ struct Buf {
 struct Scene {
     double* xyz = nullptr;
     int32_t* tri = nullptr;
+    double* cbox = nullptr;       // per block of 256 triangles: box of its vertices
     int64_t n_vert = 0, n_tri = 0;
     double lo[3], hi[3];          // axis-aligned box of the vertices (+inf / -inf when empty)
     int32_t users = 0;            // jobs of the serving loop that read it

@@ -344,6 +344,7 @@ SceneDev scene_dev(const Scene& sc) {
     SceneDev d;
     d.xyz = sc.xyz;
     d.tri = sc.tri;
+    d.cbox = sc.cbox;
     d.n_vert = sc.n_vert;
     d.n_tri = sc.n_tri;
     return d;
@@ -582,9 +583,34 @@ pv3d_status pv3d_scene_load(pv3d_ctx* ctx, const double* xyz, int64_t n_vert, co
         ctx->dfree(s.xyz);
         return st;
     }
+    // vertex box of every block of kTriBlock triangles: the triangle set-up
+    // skips a block whose box lies wholly outside a sun's window
+    const int64_t n_blk = (n_tri + kTriBlock - 1) / kTriBlock;
+    std::vector<double> cbox(6 * (size_t)n_blk);
+    for (int64_t b = 0; b < n_blk; b++) {
+        double* q = cbox.data() + 6 * b;
+        for (int c = 0; c < 3; c++) {
+            q[c] = INFINITY;
+            q[3 + c] = -INFINITY;
+        }
+        for (int64_t t = b * kTriBlock; t < std::min<int64_t>(n_tri, (b + 1) * kTriBlock); t++)
+            for (int v = 0; v < 3; v++)
+                for (int c = 0; c < 3; c++) {
+                    const double x = xyz[3 * (int64_t)tri[3 * t + v] + c];
+                    q[c] = std::fmin(q[c], x);
+                    q[3 + c] = std::fmax(q[3 + c], x);
+                }
+    }
+    if (n_blk && (st = ctx->dalloc((void**)&s.cbox, 48 * (size_t)n_blk, "triangle block boxes"))) {
+        ctx->dfree(s.xyz);
+        ctx->dfree(s.tri);
+        return st;
+    }
     hipError_t e;
     if (n_vert && (e = hipMemcpy(s.xyz, xyz, 24 * (size_t)n_vert, hipMemcpyHostToDevice))) return hip_fail(e, "copy vertices");
     if (n_tri && (e = hipMemcpy(s.tri, tri, 12 * (size_t)n_tri, hipMemcpyHostToDevice))) return hip_fail(e, "copy triangles");
+    if (n_blk && (e = hipMemcpy(s.cbox, cbox.data(), 48 * (size_t)n_blk, hipMemcpyHostToDevice)))
+        return hip_fail(e, "copy block boxes");
     uint64_t h = ++ctx->next_handle;
     ctx->scenes[h] = s;
     *scene_out = h;
@@ -601,6 +627,7 @@ pv3d_status pv3d_scene_release(pv3d_ctx* ctx, uint64_t scene) {
     (void)hipDeviceSynchronize();
     ctx->dfree(it->second.xyz);
     ctx->dfree(it->second.tri);
+    if (it->second.cbox) ctx->dfree(it->second.cbox);
     ctx->scenes.erase(it);
     return PV3D_OK;
 }
