@@ -259,8 +259,8 @@ pv3d_status pv3d_serve_stats(pv3d_ctx* ctx, int64_t out[4]);
 
 /* Kernel timing, a profiling aid. With bit i of stage_mask set, the per-sun
  * path records a pair of HIP events on its stream around every launch of
- * stage i (0 tri_setup, 1 bin_scan, 2 bin_scatter, 3 raster, 4 sample_test,
- * 5 setup, 6 loss); mask 0 turns recording off and clears the sums.
+ * stage i (0 tri_setup, 1 bin_scan: the tile counts and their scan,
+ * 2 bin_scatter, 3 raster, 4 sample_test, 5 setup, 6 loss); mask 0 turns recording off and clears the sums.
  * pv3d_profile_read waits for the recorded work and returns, for one stage,
  * the summed event-measured duration in milliseconds and the launch count. */
 #define PV3D_STAGE_TRI_SETUP 0

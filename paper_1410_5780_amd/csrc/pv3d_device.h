@@ -52,7 +52,17 @@ struct SunCounters {
     int32_t n_large;    // triangles handled by every tile instead of binned
     int32_t overflow;   // 1 if a buffer was too small for this sun
     int32_t pad;
+    unsigned long long pairs;   // pair mode: items << 32 | (item, tile) pairs taken
 };
+
+// An item of the per-sun path's pair mode: a binned record (id >= 0) or a
+// module's sample box (id = -(m + 1)), owning pairs [start, start + box
+// size) of the sun's (item, tile-in-box) pair space.
+struct PairItem {
+    int32_t id, start;
+    uint32_t xr, yr;    // tile box: x0 | x1 << 16, y0 | y1 << 16
+};
+constexpr int kPairChunk = 256;     // pairs per chunk of the counting and scatter passes
 
 // Where one sun's triangle set-up and binning write. A bin entry is a
 // triangle record id (>= 0) or a module -(m + 1) whose samples may fall in
@@ -70,6 +80,12 @@ struct BinBuffers {
     int32_t* list_ctr;     // [2] items listed, next item to take (the scan sets both)
     int32_t split_at;      // list order: < 0 tile order; else heaviest first, tiles with more
                            // entries than split_at > 0 as four quadrant items
+    // pair mode (pitems != nullptr): the triangle set-up only lays out items
+    // in pair space; counting and scatter then take the pairs in chunks
+    PairItem* pitems;      // [item_cap]
+    int32_t* pchunk;       // [bin_cap / kPairChunk + 1] item holding the first pair of each chunk
+    unsigned long long* pctr;   // this sun's SunCounters::pairs
+    int32_t item_cap;
     int32_t bin_cap;
     int32_t tile;          // tile edge in texels
     int32_t ntx;           // tiles per row
@@ -238,6 +254,8 @@ hipError_t launch_tri_setup(int64_t s, const View* views, const SceneDev& sc, co
                             const int32_t* bias, int32_t n, const BinBuffers& bb, SunCounters* ctr,
                             const uint32_t* tmask, hipStream_t st);
 hipError_t launch_bin_scan(int32_t n_tiles, const BinBuffers& bb, hipStream_t st);
+hipError_t launch_pair_count(const BinBuffers& bb, const uint32_t* tmask, int32_t grid, hipStream_t st);
+hipError_t launch_pair_scatter(const BinBuffers& bb, const uint32_t* tmask, int32_t grid, hipStream_t st);
 hipError_t launch_bin_scatter(int64_t s, const BinBuffers& bb, int32_t n_mod, SunCounters* ctr,
                               int32_t grid, const uint32_t* tmask, hipStream_t st);
 hipError_t launch_raster(int64_t s, const View* views, const BinBuffers& bb, const SunCounters* ctr,

@@ -353,6 +353,45 @@ __device__ __forceinline__ void wave_pairs(const TileBox& box, int32_t kind, con
     }
 }
 
+// Exclusive prefix sum of v over the 256 threads of a workgroup; total gets
+// the sum. Every thread calls it (it holds two barriers).
+__device__ __forceinline__ int32_t block_scan_excl(int32_t v, int32_t* wsum, int32_t& total, int lane, int wv) {
+    int32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    int32_t base = 0;
+    total = 0;
+    for (int w = 0; w < 4; w++) {
+        const int32_t t = wsum[w];
+        base += w < wv ? t : 0;
+        total += t;
+    }
+    __syncthreads();
+    return base + x - v;
+}
+
+// Lanes of the wave below this one whose bit is set.
+__device__ __forceinline__ int32_t lanes_below(unsigned long long bal) {
+    return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+}
+
+// Last index i in [0, n) with key(a[i]) <= x, for keys that do not decrease
+// and key(a[0]) <= x.
+template <int SHIFT>
+__device__ __forceinline__ int32_t last_at_most(const uint32_t* a, int32_t n, uint32_t x) {
+    int32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if ((a[mid] >> SHIFT) <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Snap, orient and set up one light-space triangle and append its record;
 // returns the record id, or -1 when it covers no pixel centre.
 __device__ int32_t emit_triangle(const d3 t[3], int32_t n, const BinBuffers& bb, SunCounters* ctr, Edges& E,
@@ -455,6 +494,47 @@ __device__ int clip_side(const d3* in, int nin, d3* out, int axis, double c, boo
 
 // A triangle reaching beyond the guard square: clip, fan, set up each piece
 // and count it (one lane; such triangles are rare).
+// Pair mode: write item k (first pair s, c pairs) and mark the chunks whose
+// first pair it holds.
+__device__ __forceinline__ void put_pair_item(const BinBuffers& bb, SunCounters* ctr, unsigned long long at,
+                                              int32_t c, int32_t id, const TileBox& box) {
+    const int64_t k = (int64_t)(at >> 32), s = (int64_t)(at & 0xFFFFFFFFull);
+    // the capacities bound every sun (an item per record and module, at most
+    // as many pairs as bin entries); were one exceeded, every item below
+    // item_cap is still written and the pair passes read no pair past bin_cap
+    if (k >= bb.item_cap || s + c > bb.bin_cap) atomicOr(&ctr->overflow, 1);
+    if (k >= bb.item_cap) return;
+    bb.pitems[k] = PairItem{id, (int32_t)min(s, (int64_t)bb.bin_cap), (uint32_t)box.x0 | ((uint32_t)box.x1 << 16),
+                            (uint32_t)box.y0 | ((uint32_t)box.y1 << 16)};
+    const int64_t e = min(s + c, (int64_t)bb.bin_cap);
+    for (int64_t q = (s + kPairChunk - 1) / kPairChunk; q * kPairChunk < e; q++) bb.pchunk[q] = (int32_t)k;
+}
+
+// Pair mode, every thread of the workgroup: the threads with c > 0 pairs
+// take consecutive items and pair ranges, with one 64-bit atomic (items in
+// the high word, pairs in the low) per workgroup, so that item starts grow
+// with the item index. lds holds 5 words.
+__device__ void reserve_pair_items(unsigned long long* lds, const BinBuffers& bb, SunCounters* ctr, int32_t c,
+                                   int32_t id, const TileBox& box, int lane, int wv) {
+    const unsigned long long v = c > 0 ? ((1ull << 32) | (unsigned long long)c) : 0ull;
+    unsigned long long x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) lds[wv] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long tot = lds[0] + lds[1] + lds[2] + lds[3];
+        lds[4] = tot ? atomicAdd(bb.pctr, tot) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long at = lds[4] + x - v;
+    for (int w = 0; w < wv; w++) at += lds[w];
+    __syncthreads();
+    if (c > 0) put_pair_item(bb, ctr, at, c, id, box);
+}
+
 __device__ __noinline__ void clip_and_emit(d3 t0, d3 t1, d3 t2, int32_t n, BinBuffers bb, SunCounters* ctr,
                                            uint32_t* cnt, const uint32_t* mask) {
     d3 a[8], b[8];
@@ -471,8 +551,14 @@ __device__ __noinline__ void clip_and_emit(d3 t0, d3 t1, d3 t2, int32_t n, BinBu
         d3 f[3] = {a[0], a[q], a[q + 1]};
         Edges E;
         bool large = false;
-        if (emit_triangle(f, n, bb, ctr, E, large) < 0 || large) continue;
+        const int32_t rid = emit_triangle(f, n, bb, ctr, E, large);
+        if (rid < 0 || large) continue;
         const TileBox box = rec_box(E.ilo, E.ihi, E.jlo, E.jhi, bb.tile);
+        if (bb.pitems) {                                   // pair mode: an item of its own
+            const int32_t c = box.count();
+            if (c > 0) put_pair_item(bb, ctr, atomicAdd(bb.pctr, (1ull << 32) | (unsigned long long)c), c, rid, box);
+            continue;
+        }
         for (int32_t ty = box.y0; ty <= box.y1; ty++)
             for (int32_t tx = box.x0; tx <= box.x1; tx++) {
                 const int32_t tq = ty * bb.ntx + tx;
@@ -481,10 +567,6 @@ __device__ __noinline__ void clip_and_emit(d3 t0, d3 t1, d3 t2, int32_t n, BinBu
     }
 }
 
-// One thread per scene triangle, module triangle and module of [t0, t1)
-// (t0 a multiple of 256; 256 at a time): set-up, then per-tile counts
-// accumulated in LDS (cnt, n_tiles words) and added to the global counts
-// once; with cnt == nullptr every pair goes straight to the global counts.
 // True when every triangle of scene block blk would be culled for this view:
 // the block's vertex box, mapped to light space corner by corner, lies beyond
 // the far depth or wholly outside the window by more than a texel. The
@@ -506,7 +588,12 @@ __device__ __forceinline__ bool block_culled(const View& V, const double* cbox, 
 }
 
 // Triangles [t0, t1) of the set-up index space (scene triangles, module
-// triangles, modules); t0 is a multiple of kTriBlock.
+// triangles, modules); t0 is a multiple of kTriBlock. In pair mode
+// (bb.pitems set) the binned records and module boxes only take their items
+// in pair space, and cnt holds the 5 words of the reservation. Otherwise,
+// 256 at a time, the per-tile counts of the pairs are accumulated in LDS
+// (cnt, n_tiles words) and added to the global counts once; with cnt ==
+// nullptr every pair goes straight to the global counts.
 __device__ void tri_setup_body(uint32_t* cnt, int64_t t0, int64_t t1, const View& V, const SceneDev& sc,
                                const GenDev& g, const int32_t* bias_s, int32_t n, const BinBuffers& bb,
                                SunCounters* ctr_s, const uint32_t* tmask_s) {
@@ -522,8 +609,9 @@ __device__ void tri_setup_body(uint32_t* cnt, int64_t t0, int64_t t1, const View
         for (int64_t tb = t0; tb < t1 && all; tb += kTriBlock) all = block_culled(V, sc.cbox, tb / kTriBlock, n);
         if (all) return;
     }
+    const bool pairs = bb.pitems != nullptr;
     uint32_t* gcnt = reinterpret_cast<uint32_t*>(bb.tile_count);
-    if (cnt) {
+    if (cnt && !pairs) {
         for (int32_t q = threadIdx.x; q < bb.n_tiles; q += 256) cnt[q] = 0;
         __syncthreads();
     }
@@ -533,7 +621,7 @@ __device__ void tri_setup_body(uint32_t* cnt, int64_t t0, int64_t t1, const View
         const int64_t t = tb + threadIdx.x;
         const bool skip = sc.cbox && tb < sc.n_tri && block_culled(V, sc.cbox, tb / kTriBlock, n);
         TileBox box{1, 0, 1, 0};
-        int32_t kind = 0;
+        int32_t kind = 0, pid = 0;
         Edges E;
         for (int e = 0; e < 3; e++) { E.e0[e] = 0; E.a[e] = 0; E.b[e] = 0; }
         E.ilo = E.ihi = E.jlo = E.jhi = 0;
@@ -563,9 +651,11 @@ __device__ void tri_setup_body(uint32_t* cnt, int64_t t0, int64_t t1, const View
                         clip_and_emit(l[0], l[1], l[2], n, bb, ctr_s, sink, tmask_s);
                     } else {
                         bool large = false;
-                        if (emit_triangle(l, n, bb, ctr_s, E, large) >= 0 && !large) {
+                        const int32_t rid = emit_triangle(l, n, bb, ctr_s, E, large);
+                        if (rid >= 0 && !large) {
                             box = rec_box(E.ilo, E.ihi, E.jlo, E.jhi, bb.tile);
                             kind = 1;
+                            pid = rid;
                         }
                     }
                 }
@@ -575,11 +665,16 @@ __device__ void tri_setup_body(uint32_t* cnt, int64_t t0, int64_t t1, const View
             TileBox b{1, 0, 1, 0};
             if (bias_s[m] >= 0) b = module_box(V, g.mods[m], n, bb.tile);
             bb.modbox[m] = make_int4(b.x0, b.x1, b.y0, b.y1);
-            if (b.count() > 0) { box = b; kind = 2; }
+            if (b.count() > 0) { box = b; kind = 2; pid = -(m + 1); }
         }
-        wave_pairs(box, kind, E, 0, lane, bb.tile, bb.ntx, tmask_s, [&](int32_t tq, int32_t) { atomicAdd(&sink[tq], 1u); });
+        if (pairs)
+            reserve_pair_items(reinterpret_cast<unsigned long long*>(cnt), bb, ctr_s, kind ? box.count() : 0, pid, box,
+                               lane, threadIdx.x >> 6);
+        else
+            wave_pairs(box, kind, E, 0, lane, bb.tile, bb.ntx, tmask_s,
+                       [&](int32_t tq, int32_t) { atomicAdd(&sink[tq], 1u); });
     }
-    if (cnt) {
+    if (cnt && !pairs) {
         __syncthreads();
         for (int32_t q = threadIdx.x; q < bb.n_tiles; q += 256)
             if (cnt[q]) atomicAdd(&gcnt[q], cnt[q]);
@@ -595,17 +690,45 @@ __global__ __launch_bounds__(256) void k_tri_setup(int64_t s, const View* views,
     tri_setup_body(cnt, t0, min(t0 + 256, total), views[s], sc, g, bias + s * g.n_mod, n, bb, ctr, tmask);
 }
 
+// Exclusive prefix sum over the NT threads of a workgroup (wave shuffles,
+// then the wave totals); total gets the sum. Every thread calls it; wsum
+// holds NT / 64 words.
+template <int NT>
+__device__ __forceinline__ unsigned long long scan_excl64(unsigned long long v, unsigned long long* wsum,
+                                                          unsigned long long& total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    unsigned long long x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    unsigned long long base = 0;
+    total = 0;
+    for (int w = 0; w < NT / 64; w++) {
+        const unsigned long long t = wsum[w];
+        base += w < wv ? t : 0ull;
+        total += t;
+    }
+    __syncthreads();
+    return base + x - v;
+}
+
 // Exclusive scan of the tile counts by NT threads; every count is left at
 // zero for the next sun. With list != nullptr the tiles holding at least one
 // entry are also listed as work items and their number returned (every
 // thread): in tile order when split_at < 0, otherwise the most entries first
 // (entries bucketed by eight), a tile with more than split_at > 0 entries as
-// its four quadrants. part holds 2 NT + 2 kScanBuckets ints.
+// its four quadrants. part holds 2 NT + 2 kScanBuckets ints; the count total
+// is left in part[0].
 constexpr int kScanBuckets = 256;
 
 template <int NT, bool COHERENT>
 __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& bb, int32_t* list, int32_t split_at) {
+    static_assert(NT >= kScanBuckets && NT % 64 == 0, "a thread per bucket");
     const int tid = threadIdx.x;
+    unsigned long long* wsum = reinterpret_cast<unsigned long long*>(part + 2);
     const int32_t per = (n_tiles + NT - 1) / NT;
     const int32_t b0 = min(tid * per, n_tiles), b1 = min(b0 + per, n_tiles);
     int32_t sum = 0, nz = 0;
@@ -614,19 +737,12 @@ __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& b
         sum += c;
         nz += c > 0 ? 1 : 0;
     }
-    part[tid] = sum;
-    part[NT + tid] = nz;
-    __syncthreads();
-    for (int off = 1; off < NT; off <<= 1) {       // inclusive Hillis-Steele scans
-        const int32_t v = tid >= off ? part[tid - off] : 0;
-        const int32_t w = tid >= off ? part[NT + tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        part[NT + tid] += w;
-        __syncthreads();
-    }
+    // entries and non-empty tiles, scanned together
+    unsigned long long tot;
+    const unsigned long long ex =
+        scan_excl64<NT>(((unsigned long long)nz << 32) | (unsigned long long)(uint32_t)sum, wsum, tot);
     const bool in_order = list && split_at < 0;
-    int32_t run = part[tid] - sum, lpos = part[NT + tid] - nz;
+    int32_t run = (int32_t)(uint32_t)ex, lpos = (int32_t)(ex >> 32);
     for (int32_t i = b0; i < b1; i++) {
         const int32_t c = COHERENT ? ld_dev(bb.tile_count + i) : bb.tile_count[i];
         bb.tile_start[i] = run;
@@ -640,8 +756,9 @@ __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& b
         if (in_order && c > 0) list[lpos++] = (i << 3) | kWholeTile;
         run += c;
     }
-    if (tid == NT - 1) bb.tile_start[n_tiles] = part[NT - 1];
-    const int32_t n_nonempty = part[2 * NT - 1];
+    const int32_t n_entries = (int32_t)(uint32_t)tot, n_nonempty = (int32_t)(tot >> 32);
+    if (tid == NT - 1) bb.tile_start[n_tiles] = n_entries;
+    if (tid == 0) part[0] = n_entries;
     __syncthreads();
     if (!list || in_order) return n_nonempty;
     // heaviest first: counting sort of the non-empty tiles by entry bucket
@@ -656,15 +773,11 @@ __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& b
         atomicAdd(&hist[bk], (split_at > 0 && c > split_at) ? 4 : 1);
     }
     __syncthreads();
-    const int32_t own = tid < kScanBuckets ? hist[tid] : 0;
-    for (int off = 1; off < kScanBuckets; off <<= 1) {     // inclusive scan of the buckets
-        const int32_t v = (tid < kScanBuckets && tid >= off) ? hist[tid - off] : 0;
-        __syncthreads();
-        if (tid < kScanBuckets) hist[tid] += v;
-        __syncthreads();
-    }
-    if (tid < kScanBuckets) cur[tid] = hist[tid] - own;
-    const int32_t n_items = hist[kScanBuckets - 1];
+    const unsigned long long own = tid < kScanBuckets ? (unsigned long long)hist[tid] : 0ull;
+    unsigned long long n_items64;
+    const unsigned long long first = scan_excl64<NT>(own, wsum, n_items64);
+    if (tid < kScanBuckets) cur[tid] = (int32_t)first;
+    const int32_t n_items = (int32_t)n_items64;
     __syncthreads();
     for (int32_t i = b0; i < b1; i++) {
         const int32_t c = bb.tile_start[i + 1] - bb.tile_start[i];
@@ -682,7 +795,7 @@ __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& b
 }
 
 __global__ __launch_bounds__(1024) void k_bin_scan(int32_t n_tiles, BinBuffers bb) {
-    __shared__ int32_t part[2 * 1024 + 2 * kScanBuckets];
+    __shared__ __attribute__((aligned(16))) int32_t part[2 * 1024 + 2 * kScanBuckets];
     const int32_t n_items = scan_body<1024, false>(part, n_tiles, bb, bb.tile_list, bb.split_at);
     if (bb.tile_list && threadIdx.x == 0) {
         bb.list_ctr[0] = n_items;
@@ -776,6 +889,61 @@ __global__ __launch_bounds__(256) void k_bin_scatter(int64_t s, BinBuffers bb, i
                                                      const uint32_t* tmask) {
     extern __shared__ uint32_t lds[];
     scatter_body(lds, blockIdx.x, gridDim.x, bb, n_mod, ctr[s].n_rec, ctr + s, tmask);
+}
+
+// Pair mode: every pair of the sun's pair space, in chunks of kPairChunk over
+// the grid. A thread finds its item among the (at most kPairChunk) items the
+// chunk touches by binary search over their starts in LDS, then its tile;
+// f(tile, id) runs for the pairs the binning keeps: tiles with samples, and
+// for a record only the tiles its edges reach (the filter of wave_pairs).
+template <typename F>
+__device__ void pair_chunks(const BinBuffers& bb, const uint32_t* tmask, uint32_t* st, F&& f) {
+    const unsigned long long pc = *bb.pctr;
+    // a sun whose items overflowed the buffers is reported by the host and
+    // evaluated no further; its reads stay inside the buffers all the same
+    const int64_t n_items = min((int64_t)(pc >> 32), (int64_t)bb.item_cap);
+    const int64_t n_pairs = min((int64_t)(pc & 0xFFFFFFFFull), (int64_t)bb.bin_cap);
+    const int64_t n_chunks = (n_pairs + kPairChunk - 1) / kPairChunk;
+    const int32_t nty = bb.n_tiles / bb.ntx;
+    static_assert(kPairChunk == 256, "one thread per pair of a chunk");
+    for (int64_t q = blockIdx.x; q < n_chunks; q += gridDim.x) {
+        const int32_t k0 = bb.pchunk[q];
+        const bool k0_ok = k0 >= 0 && k0 < n_items;
+        const int64_t k = k0 + (int64_t)threadIdx.x;
+        st[threadIdx.x] = (k0_ok && k < n_items) ? (uint32_t)bb.pitems[k].start : 0xFFFFFFFFu;
+        __syncthreads();
+        const int64_t p = q * kPairChunk + threadIdx.x;
+        if (k0_ok && p < n_pairs && st[0] <= (uint32_t)p) {
+            const PairItem it = bb.pitems[k0 + last_at_most<0>(st, kPairChunk, (uint32_t)p)];
+            const int32_t x0 = (int32_t)(it.xr & 0xFFFFu), x1 = (int32_t)(it.xr >> 16);
+            const int32_t y0 = (int32_t)(it.yr & 0xFFFFu);
+            const int32_t r = (int32_t)(p - it.start), bw = x1 - x0 + 1;
+            const int32_t tx = x0 + (bw > 0 ? r % bw : 0), ty = y0 + (bw > 0 ? r / bw : 0);
+            const int32_t tq = ty * bb.ntx + tx;
+            bool keep = bw > 0 && tx < bb.ntx && ty < nty && it.id < bb.rec_cap;
+            keep = keep && mask_has(tmask, tq);
+            if (keep && it.id >= 0) {
+                Edges E;
+                edges_of(bb.rec[it.id], E);
+                keep = tile_overlap(E, tx, ty, bb.tile);
+            }
+            if (keep) f(tq, it.id);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pair_count(BinBuffers bb, const uint32_t* tmask) {
+    __shared__ uint32_t st[kPairChunk];
+    pair_chunks(bb, tmask, st, [&](int32_t tq, int32_t) { atomicAdd(&bb.tile_count[tq], 1); });
+}
+
+__global__ __launch_bounds__(256) void k_pair_scatter(BinBuffers bb, const uint32_t* tmask) {
+    __shared__ uint32_t st[kPairChunk];
+    pair_chunks(bb, tmask, st, [&](int32_t tq, int32_t id) {
+        const int32_t at = atomicAdd(&bb.tile_cursor[tq], 1);
+        if (at < bb.bin_cap) bb.bins[at] = id;
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -1124,45 +1292,6 @@ struct SparseShared {
     int32_t wsum[4];
 };
 
-// Exclusive prefix sum of v over the 256 threads of a workgroup; total gets
-// the sum. Every thread calls it (it holds two barriers).
-__device__ __forceinline__ int32_t block_scan_excl(int32_t v, int32_t* wsum, int32_t& total, int lane, int wv) {
-    int32_t x = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        const int32_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) wsum[wv] = x;
-    __syncthreads();
-    int32_t base = 0;
-    total = 0;
-    for (int w = 0; w < 4; w++) {
-        const int32_t t = wsum[w];
-        base += w < wv ? t : 0;
-        total += t;
-    }
-    __syncthreads();
-    return base + x - v;
-}
-
-// Lanes of the wave below this one whose bit is set.
-__device__ __forceinline__ int32_t lanes_below(unsigned long long bal) {
-    return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-}
-
-// Last index i in [0, n) with key(a[i]) <= x, for keys that do not decrease
-// and key(a[0]) <= x.
-template <int SHIFT>
-__device__ __forceinline__ int32_t last_at_most(const uint32_t* a, int32_t n, uint32_t x) {
-    int32_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if ((a[mid] >> SHIFT) <= x) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 // Light-space maps of the first kMapCache module slots of a tile are kept in
 // LDS while its samples are listed.
 constexpr int kMapCache = 64;
@@ -1399,7 +1528,11 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
             const int32_t nl = tb.cnt[st];
             const bool all = nl > kStampList;
             const int32_t nt = all ? ns : nl;
+            // only whether the sample is shaded is kept, and a covering depth
+            // below its threshold settles that: the search stops there
+            const int32_t thr = sp.thr[e];
             uint32_t dm = sp.dmin[e];
+            if (thr > (int32_t)dm) continue;
             for (int32_t u = 0; u < nt; u++) {
                 const int32_t q = all ? u : (int32_t)tb.list[st * kStampList + u];
                 const TriSlot& T = tb.slot[q];
@@ -1409,6 +1542,7 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
                 if ((E0 | E1 | E2) >= 0) {
                     const uint32_t D = depth_q(T.zx + T.gx * li + T.gy * lj);
                     dm = D < dm ? D : dm;
+                    if (thr > (int32_t)dm) break;
                 }
             }
             sp.dmin[e] = dm;
@@ -1814,6 +1948,10 @@ __device__ __forceinline__ BinBuffers slot_bins(const PLaunch& P, const PJob& J,
     bb.tile_list = nullptr;           // the scan and tile units use the slot's list directly
     bb.list_ctr = nullptr;
     bb.split_at = 0;
+    bb.pitems = nullptr;              // units count their pairs as they set up
+    bb.pchunk = nullptr;
+    bb.pctr = nullptr;
+    bb.item_cap = 0;
     bb.bin_cap = P.bin_cap;
     bb.tile = J.tile;
     bb.ntx = J.ntx;
@@ -1854,7 +1992,7 @@ __device__ __noinline__ void unit_scan(unsigned char* raw, const PLaunch& P, con
     // share triangle records in its L2; the slots balance the load
     const int32_t n_list = scan_body<256, true>(part, J.n_tiles, bb, B.tile_list, -1);
     if (threadIdx.x == 0) {
-        const int32_t total = part[255];
+        const int32_t total = part[0];
         const int32_t ovf = (ld_dev(&B.ctr->overflow) || ld_dev(&B.ctr->n_rec) > P.rec_cap || total > P.bin_cap) ? 1 : 0;
         __hip_atomic_store(&st.n_list, n_list, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&st.overflow, ovf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2366,8 +2504,19 @@ hipError_t launch_tri_setup(int64_t s, const View* views, const SceneDev& sc, co
                             int32_t n, const BinBuffers& bb, SunCounters* ctr, const uint32_t* tmask, hipStream_t st) {
     int64_t total = sc.n_tri + (g.occluders ? 2 * (int64_t)g.n_mod : 0) + g.n_mod;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tri_setup, dim3(grid_for(total, 256)), dim3(256), 4 * (size_t)bb.n_tiles, st, s, views, sc,
-                       g, bias, n, bb, ctr + s, tmask);
+    const size_t lds = bb.pitems ? 5 * sizeof(unsigned long long) : 4 * (size_t)bb.n_tiles;
+    hipLaunchKernelGGL(k_tri_setup, dim3(grid_for(total, 256)), dim3(256), lds, st, s, views, sc, g, bias, n, bb,
+                       ctr + s, tmask);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_count(const BinBuffers& bb, const uint32_t* tmask, int32_t grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_pair_count, dim3((unsigned)grid), dim3(256), 0, st, bb, tmask);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_scatter(const BinBuffers& bb, const uint32_t* tmask, int32_t grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)grid), dim3(256), 0, st, bb, tmask);
     return hipGetLastError();
 }
 

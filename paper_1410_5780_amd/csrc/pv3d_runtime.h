@@ -57,14 +57,16 @@ struct Gen {
 struct PathSizes {
     int32_t tile, ntx, n_tiles, large_tiles, words, mask_words;
     int64_t tri_total, rec_cap, bin_cap, cells, n_sun;
+    int64_t item_cap, chunk_cap;      // pair mode: binned items, chunks of pair space
 };
 
 struct Work {
-    Buf rec, large, bins, tile_count, tile_start, tile_cursor, tile_list, map;
+    Buf rec, large, bins, tile_count, tile_start, tile_cursor, tile_list, pitems, pchunk, map;
     Buf views, ctr, beam, bias, sweep, sphere, partial, fu, fv, modbox, tmask;
     Buf counts, outd, maps, bits;
     void release_all(Ctx* c) {
-        Buf* all[] = {&rec, &large, &bins, &tile_count, &tile_start, &tile_cursor, &tile_list, &map, &views, &ctr,
+        Buf* all[] = {&rec, &large, &bins, &tile_count, &tile_start, &tile_cursor, &tile_list, &pitems, &pchunk, &map,
+                      &views, &ctr,
                       &beam, &bias, &sweep, &sphere, &partial, &fu, &fv, &modbox, &tmask, &counts, &outd, &maps, &bits};
         for (Buf* b : all) b->release(c);
     }

@@ -263,6 +263,9 @@ PathSizes path_sizes(const Scene& sc, const Gen& g, const pv3d_params& p, int64_
     // tiles, a module's samples at most every tile
     z.rec_cap = 5 * z.tri_total + 64;
     z.bin_cap = (int64_t)z.large_tiles * z.rec_cap + (int64_t)g.n_mod * z.n_tiles;
+    // pair mode: an item per binned record and module, and the same bound on pairs as on bin entries
+    z.item_cap = z.rec_cap + g.n_mod;
+    z.chunk_cap = z.bin_cap / kPairChunk + 1;
     z.cells = (int64_t)g.n_mod * g.n_cu * g.n_cv;
     z.mask_words = (z.n_tiles + 31) / 32;
     z.words = (p.k * p.k + 31) / 32;
@@ -283,6 +286,8 @@ pv3d_status Ctx::ensure_path(const PathSizes& z, const Gen& g, int32_t map_n, bo
     if ((st = w.tile_start.ensure(this, 4 * (size_t)(z.n_tiles + 1), "tile starts"))) return st;
     if ((st = w.tile_cursor.ensure(this, 4 * (size_t)z.n_tiles, "tile cursors"))) return st;
     if ((st = w.tile_list.ensure(this, 4 * (4 * (size_t)z.n_tiles + 2), "tile work list"))) return st;
+    if ((st = w.pitems.ensure(this, sizeof(PairItem) * (size_t)z.item_cap, "pair items"))) return st;
+    if ((st = w.pchunk.ensure(this, 4 * (size_t)z.chunk_cap, "pair chunks"))) return st;
     if (own_map && (st = w.map.ensure(this, 4 * (size_t)map_n * map_n, "depth picture"))) return st;
     if ((st = w.views.ensure(this, sizeof(View) * (size_t)std::max<int64_t>(z.n_sun, 1), "views"))) return st;
     if ((st = w.ctr.ensure(this, sizeof(SunCounters) * (size_t)std::max<int64_t>(z.n_sun, 1), "counters"))) return st;
@@ -310,6 +315,10 @@ BinBuffers Ctx::bin_buffers(const PathSizes& z) {
     bb.tile_list = nullptr;                // one workgroup per tile unless the sun takes the work list
     bb.list_ctr = nullptr;
     bb.split_at = 0;
+    bb.pitems = static_cast<PairItem*>(w.pitems.ptr);
+    bb.pchunk = static_cast<int32_t*>(w.pchunk.ptr);
+    bb.pctr = nullptr;                     // per sun
+    bb.item_cap = (int32_t)z.item_cap;
     bb.bin_cap = (int32_t)z.bin_cap;
     bb.tile = z.tile;
     bb.ntx = z.ntx;
@@ -428,7 +437,6 @@ pv3d_status Ctx::run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, cons
     BinBuffers bb = bin_buffers(z);
     const bool separate = (p.flags & PV3D_SEPARATE_TEST) != 0;
     if (separate && !map) map = static_cast<uint32_t*>(w.map.ptr);
-    const int32_t scatter_grid = 1024;
     TileOut to;
     to.map = map;
     to.counts = counts_s;
@@ -441,11 +449,18 @@ pv3d_status Ctx::run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, cons
         bb.tile_list = tl + 2;
         bb.split_at = z.tile == 64 ? kSplitEntries : 0;
     }
+    // pair mode: set-up lays the binned records and module boxes out in pair
+    // space; counting and scatter then share the pairs evenly over the grid
+    bb.pctr = &ctr[s].pairs;
+    const int32_t pair_grid = 4 * n_cu;
     if ((e = timed(prof, PV3D_STAGE_TRI_SETUP, st, [&] { return launch_tri_setup(s, views, sd, gd, bias, p.map_n, bb, ctr, tmask_s, st); })))
         return hip_fail(e, "tri_setup");
-    if ((e = timed(prof, PV3D_STAGE_BIN_SCAN, st, [&] { return launch_bin_scan(z.n_tiles, bb, st); })))
+    if ((e = timed(prof, PV3D_STAGE_BIN_SCAN, st, [&] {
+             hipError_t r = launch_pair_count(bb, tmask_s, pair_grid, st);
+             return r ? r : launch_bin_scan(z.n_tiles, bb, st);
+         })))
         return hip_fail(e, "bin_scan");
-    if ((e = timed(prof, PV3D_STAGE_BIN_SCATTER, st, [&] { return launch_bin_scatter(s, bb, gd.n_mod, ctr, scatter_grid, tmask_s, st); })))
+    if ((e = timed(prof, PV3D_STAGE_BIN_SCATTER, st, [&] { return launch_pair_scatter(bb, tmask_s, pair_grid, st); })))
         return hip_fail(e, "bin_scatter");
     if ((e = timed(prof, PV3D_STAGE_RASTER, st, [&] {
              return launch_raster(s, views, bb, ctr, p.map_n, gd, bias, static_cast<double*>(w.fu.ptr),
