@@ -1118,15 +1118,23 @@ __device__ __forceinline__ bool clip_to_tile(const TriRec& R, int32_t x0, int32_
     return !outside;
 }
 
+// e0 + a x + b y for x = 256 i, y = 256 j (i, j texel offsets, so x and y fit
+// 32 bits): each product is one 32 x 32 -> 64-bit multiply-add, and the sum
+// is the exact value the 64-bit per-texel steps a 256, b 256 give.
+__device__ __forceinline__ int64_t edge_at(int64_t e0, int32_t a, int32_t b, int32_t x, int32_t y) {
+    return e0 + (int64_t)a * x + (int64_t)b * y;
+}
+
+// The record's box clipped to the rect; false when the box or an edge
+// excludes the whole clipped box (the edge steps of t are not filled).
 __device__ __forceinline__ bool clip_to_rect(const TriRec& R, const Rect& r, TriClip& t) {
     t.ilo = max((int32_t)R.ilo, r.x); t.ihi = min((int32_t)R.ihi, r.x + r.size - 1);
     t.jlo = max((int32_t)R.jlo, r.y); t.jhi = min((int32_t)R.jhi, r.y + r.size - 1);
     if (t.ilo > t.ihi || t.jlo > t.jhi) return false;
     bool outside = false;
     for (int e = 0; e < 3; e++) {
-        t.EA[e] = (int64_t)R.a[e] * 256;
-        t.EB[e] = (int64_t)R.b[e] * 256;
-        const int64_t bmax = R.e0[e] + t.EA[e] * (t.EA[e] > 0 ? t.ihi : t.ilo) + t.EB[e] * (t.EB[e] > 0 ? t.jhi : t.jlo);
+        const int64_t bmax = edge_at(R.e0[e], R.a[e], R.b[e], 256 * (R.a[e] > 0 ? t.ihi : t.ilo),
+                                     256 * (R.b[e] > 0 ? t.jhi : t.jlo));
         outside |= bmax < 0;
     }
     return !outside;
@@ -1280,12 +1288,16 @@ __device__ void samples_full(const uint32_t* zt, const int32_t* mods, int32_t nm
 // (shaded iff threshold > nearest depth at the texel), and the sample's
 // identity (tile module slot, qa, qb).
 struct SparseLds {
-    uint16_t* texel;     // lj * TS + li
+    uint16_t* texel;     // lj * TS + li, and kShadedBit once a covering depth below thr is found
     int32_t* thr;        // zs - bias
     uint32_t* code;      // slot << 24 | qb << 12 | qa
-    uint32_t* dmin;      // nearest depth at the texel centre
-    uint16_t* order;     // entries sorted by texel row
+    uint16_t* order;     // entries sorted by 8 x 8 stamp
 };
+// A sample is shaded when some covering depth lies below its threshold; only
+// that flag is kept, in the top bit of its texel (texels of a tile of at most
+// 128 x 128 need 14 bits).
+constexpr uint16_t kShadedBit = 0x8000;
+constexpr uint16_t kTexelMask = 0x3FFF;
 
 struct SparseShared {
     int32_t n_ent, ent_overflow, max_thr, next, n_slots;
@@ -1300,7 +1312,8 @@ constexpr int kMapCache = 64;
 // texel (li, lj) of the rect is ex[k] + A[k] li + B[k] lj, depth
 // (zx + gx li + gy lj) >> 16; box = clipped texel box (4 x 8 bits).
 struct TriSlot {
-    int64_t ex[3], A[3], B[3];
+    int64_t ex[3];          // edge values at the rect origin
+    int32_t A[3], B[3];     // edge coefficients; a texel step adds 256 A (256 B)
     int64_t zx, gx, gy;
     uint32_t box, pad;
 };
@@ -1428,7 +1441,6 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
                     sp.texel[e] = (uint16_t)(lj * TS + li);
                     sp.thr[e] = th;
                     sp.code[e] = code;
-                    sp.dmin[e] = kDepthMax;
                 }
             }
         }
@@ -1443,7 +1455,7 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
     // 2. counting sort of the entries by 8x8 stamp of the rect
     const int32_t spr = (r.size + 7) / 8, n_st = spr * spr;
     for (int32_t e = tid; e < ne; e += 256) {
-        const int32_t tx = sp.texel[e];
+        const int32_t tx = sp.texel[e] & kTexelMask;
         atomicAdd(&rowstart[(tx / TS / 8) * spr + (tx % TS) / 8 + 1], 1);
     }
     __syncthreads();
@@ -1459,7 +1471,7 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
     for (int q = tid; q < n_st; q += 256) cells[q] = (uint32_t)rowstart[q];
     __syncthreads();
     for (int32_t e = tid; e < ne; e += 256) {
-        const int32_t tx = sp.texel[e];
+        const int32_t tx = sp.texel[e] & kTexelMask;
         sp.order[atomicAdd(&cells[(tx / TS / 8) * spr + (tx % TS) / 8], 1u)] = (uint16_t)e;
     }
     // 3. triangles in chunks: each chunk's records go to LDS (relative to the
@@ -1483,9 +1495,9 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
                         const int32_t q = atomicAdd(&sh.n_slots, 1);
                         TriSlot& T = tb.slot[q];
                         for (int e = 0; e < 3; e++) {
-                            T.ex[e] = R.e0[e] + t.EA[e] * r.x + t.EB[e] * r.y;
-                            T.A[e] = t.EA[e];
-                            T.B[e] = t.EB[e];
+                            T.ex[e] = edge_at(R.e0[e], R.a[e], R.b[e], 256 * r.x, 256 * r.y);
+                            T.A[e] = R.a[e];
+                            T.B[e] = R.b[e];
                         }
                         T.zx = R.z0 + R.gx * r.x + R.gy * r.y;
                         T.gx = R.gx;
@@ -1509,7 +1521,8 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
                 const int32_t i0 = max(sx, bi0), i1 = min(sx + 7, bi1), j0 = max(sy, bj0), j1 = min(sy + 7, bj1);
                 bool hit = i0 <= i1 && j0 <= j1;
                 for (int e = 0; e < 3 && hit; e++) {
-                    const int64_t emax = T.ex[e] + T.A[e] * (T.A[e] > 0 ? i1 : i0) + T.B[e] * (T.B[e] > 0 ? j1 : j0);
+                    const int64_t emax = edge_at(T.ex[e], T.A[e], T.B[e], 256 * (T.A[e] > 0 ? i1 : i0),
+                                                 256 * (T.B[e] > 0 ? j1 : j0));
                     hit = emax >= 0;
                 }
                 if (hit) {
@@ -1522,8 +1535,11 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
         // samples against the triangles of their stamp (all triangles of the chunk when the list overflowed)
         for (int32_t p = tid; p < ne; p += 256) {
             const int32_t e = sp.order[p];
-            const int32_t tx = sp.texel[e];
+            const uint16_t tw = sp.texel[e];
+            if (tw & kShadedBit) continue;                  // settled by an earlier chunk
+            const int32_t tx = tw & kTexelMask;
             const int32_t li = tx % TS, lj = tx / TS;
+            const int32_t li256 = li * 256, lj256 = lj * 256;
             const int32_t st = (lj / 8) * spr + li / 8;
             const int32_t nl = tb.cnt[st];
             const bool all = nl > kStampList;
@@ -1531,21 +1547,19 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
             // only whether the sample is shaded is kept, and a covering depth
             // below its threshold settles that: the search stops there
             const int32_t thr = sp.thr[e];
-            uint32_t dm = sp.dmin[e];
-            if (thr > (int32_t)dm) continue;
+            bool shaded = false;
             for (int32_t u = 0; u < nt; u++) {
                 const int32_t q = all ? u : (int32_t)tb.list[st * kStampList + u];
                 const TriSlot& T = tb.slot[q];
-                const int64_t E0 = T.ex[0] + T.A[0] * li + T.B[0] * lj;
-                const int64_t E1 = T.ex[1] + T.A[1] * li + T.B[1] * lj;
-                const int64_t E2 = T.ex[2] + T.A[2] * li + T.B[2] * lj;
-                if ((E0 | E1 | E2) >= 0) {
-                    const uint32_t D = depth_q(T.zx + T.gx * li + T.gy * lj);
-                    dm = D < dm ? D : dm;
-                    if (thr > (int32_t)dm) break;
+                const int64_t E0 = edge_at(T.ex[0], T.A[0], T.B[0], li256, lj256);
+                const int64_t E1 = edge_at(T.ex[1], T.A[1], T.B[1], li256, lj256);
+                const int64_t E2 = edge_at(T.ex[2], T.A[2], T.B[2], li256, lj256);
+                if ((E0 | E1 | E2) >= 0 && thr > (int32_t)depth_q(T.zx + T.gx * li + T.gy * lj)) {
+                    shaded = true;
+                    break;
                 }
             }
-            sp.dmin[e] = dm;
+            if (shaded) sp.texel[e] = tw | kShadedBit;
         }
         __syncthreads();
     }
@@ -1557,7 +1571,7 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
     __syncthreads();
     const int32_t words = (k * k + 31) / 32;
     for (int32_t e = tid; e < ne; e += 256) {
-        if (!(sp.thr[e] > (int32_t)sp.dmin[e])) continue;
+        if (!(sp.texel[e] & kShadedBit)) continue;
         const uint32_t code = sp.code[e];
         const int32_t slot = (int32_t)(code >> 24), qb = (int32_t)((code >> 12) & 0xFFF), qa = (int32_t)(code & 0xFFF);
         const int32_t cu = qa / k, cv = qb / k, cell = cv * g.n_cu + cu;
@@ -1582,11 +1596,17 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
 constexpr int kMinRect = 16;
 constexpr int kMaxRects = 64;
 
+// Sample entries a rect of the sparse route may hold (a denser rect is split
+// in four): 12 bytes each, sized so that 64-texel tiles of the row-plant
+// workload (up to about 2,450 samples) never split.
+constexpr int kCap32 = 1364, kCap64 = 2730, kCap128 = 5460;
+
 template <int TS, int CAP>
 struct TileLds {
     static constexpr int PITCH = TS + 8;
     static constexpr int ZT_BYTES = TS * PITCH * 4;
-    static constexpr int SP_BYTES = CAP * (2 + 4 + 4 + 4 + 2);
+    static constexpr int SP_BYTES = CAP * (2 + 4 + 4 + 2);
+    static_assert(CAP % 2 == 0 && TS <= 128, "aligned entry arrays; texels below kShadedBit");
     static constexpr int POOL = ZT_BYTES > SP_BYTES ? ZT_BYTES : SP_BYTES;
     __attribute__((aligned(16))) unsigned char pool[POOL];
     int32_t mods[kMaxTileMods];
@@ -1664,8 +1684,7 @@ __device__ void tile_body(TileLds<TS, CAP>& L, int32_t item, const View& V, cons
         sp.texel = reinterpret_cast<uint16_t*>(pool);
         sp.thr = reinterpret_cast<int32_t*>(pool + 2 * CAP);
         sp.code = reinterpret_cast<uint32_t*>(pool + 6 * CAP);
-        sp.dmin = reinterpret_cast<uint32_t*>(pool + 10 * CAP);
-        sp.order = reinterpret_cast<uint16_t*>(pool + 14 * CAP);
+        sp.order = reinterpret_cast<uint16_t*>(pool + 10 * CAP);
         TriBins tb;
         tb.slot = tslots;
         tb.cnt = tcnt;
@@ -1727,7 +1746,7 @@ __device__ void tile_body(TileLds<TS, CAP>& L, int32_t item, const View& V, cons
 }
 
 template <int TS, int CAP>
-__global__ __launch_bounds__(256) void k_tile(int64_t s, const View* views, BinBuffers bb, const SunCounters* ctr,
+__global__ __launch_bounds__(256, 3) void k_tile(int64_t s, const View* views, BinBuffers bb, const SunCounters* ctr,
                                               int32_t n, GenDev g, const int32_t* bias, const double* fu_tab,
                                               const double* fv_tab, int32_t k, TileOut out, int32_t sparse,
                                               const uint32_t* tmask) {
@@ -1924,7 +1943,7 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
 // per-sun kernels above, so results are the same.
 // ---------------------------------------------------------------------------
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
-constexpr size_t kPLdsBytes = cmax(cmax(sizeof(TileLds<64, 2048>), sizeof(TileLds<32, 1024>)),
+constexpr size_t kPLdsBytes = cmax(cmax(sizeof(TileLds<64, kCap64>), sizeof(TileLds<32, kCap32>)),
                                    cmax(cmax(sizeof(SetupLds), sizeof(LossLds)), (2 * 256 + 2 * kScanBuckets) * 4 + 1024 * 8));
 
 __device__ __forceinline__ unsigned long long pword(int32_t phase, int32_t n_units) {
@@ -2016,10 +2035,10 @@ __device__ __noinline__ void unit_tile(unsigned char* raw, const PJob& J, const 
     out.sparse = J.sparse;
     const uint32_t* tmask = J.use_mask ? B.tmask : nullptr;
     if (J.tile == 64)
-        tile_body<64, 2048>(*reinterpret_cast<TileLds<64, 2048>*>(raw), item, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, J.g,
+        tile_body<64, kCap64>(*reinterpret_cast<TileLds<64, kCap64>*>(raw), item, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, J.g,
                             B.bias, J.fu, J.fv, J.k, out, J.sparse, tmask);
     else
-        tile_body<32, 1024>(*reinterpret_cast<TileLds<32, 1024>*>(raw), item, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, J.g,
+        tile_body<32, kCap32>(*reinterpret_cast<TileLds<32, kCap32>*>(raw), item, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, J.g,
                             B.bias, J.fu, J.fv, J.k, out, J.sparse, tmask);
 }
 
@@ -2559,16 +2578,16 @@ hipError_t launch_raster(int64_t s, const View* views, const BinBuffers& bb, con
     const int32_t sparse = out.sparse;
     switch (bb.tile) {
         case 32:
-            if ((e = tile_launch<32, 1024>(grid, bb, n_cu))) return e;
-            hipLaunchKernelGGL((k_tile<32, 1024>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out, sparse, tmask);
+            if ((e = tile_launch<32, kCap32>(grid, bb, n_cu))) return e;
+            hipLaunchKernelGGL((k_tile<32, kCap32>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out, sparse, tmask);
             break;
         case 64:
-            if ((e = tile_launch<64, 2048>(grid, bb, n_cu))) return e;
-            hipLaunchKernelGGL((k_tile<64, 2048>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out, sparse, tmask);
+            if ((e = tile_launch<64, kCap64>(grid, bb, n_cu))) return e;
+            hipLaunchKernelGGL((k_tile<64, kCap64>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out, sparse, tmask);
             break;
         case 128:
-            if ((e = tile_launch<128, 4096>(grid, bb, n_cu))) return e;
-            hipLaunchKernelGGL((k_tile<128, 4096>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out, sparse, tmask);
+            if ((e = tile_launch<128, kCap128>(grid, bb, n_cu))) return e;
+            hipLaunchKernelGGL((k_tile<128, kCap128>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out, sparse, tmask);
             break;
         default: return hipErrorInvalidValue;
     }
