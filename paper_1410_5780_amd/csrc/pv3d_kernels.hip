@@ -1300,7 +1300,7 @@ constexpr uint16_t kShadedBit = 0x8000;
 constexpr uint16_t kTexelMask = 0x3FFF;
 
 struct SparseShared {
-    int32_t n_ent, ent_overflow, max_thr, next, n_slots;
+    int32_t n_ent, ent_overflow, max_thr, next, n_slots, cut;
     int32_t wsum[4];
 };
 
@@ -1474,43 +1474,63 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
         const int32_t tx = sp.texel[e] & kTexelMask;
         sp.order[atomicAdd(&cells[(tx / TS / 8) * spr + (tx % TS) / 8], 1u)] = (uint16_t)e;
     }
-    // 3. triangles in chunks: each chunk's records go to LDS (relative to the
-    //    rect origin), are binned into the rect's stamps one lane per stamp,
-    //    and every sample then tests only the triangles of its own stamp
+    // 3. triangles in chunks of up to kTriChunk: the records that reach the
+    //    rect go to LDS (relative to the rect origin), are binned into the
+    //    rect's stamps one lane per stamp, and every sample then tests only
+    //    the triangles of its own stamp. A chunk is filled 256 candidates at
+    //    a time: every thread tests one, the survivors take the free slots in
+    //    candidate order, and the walk goes on after the last one placed, so
+    //    a rect that few of its tile's triangles reach (a quadrant item) takes
+    //    few chunks.
     const int32_t mthr = sh.max_thr;
     const int32_t total = c.n_large + (c.be - c.bs);
-    for (int32_t base = 0; base < total; base += kTriChunk) {
-        if (tid == 0) sh.n_slots = 0;
-        for (int q = tid; q < n_st; q += 256) { tb.cnt[q] = 0; }
-        __syncthreads();
-        if (tid < kTriChunk && base + tid < total) {
+    int32_t base = 0;
+    while (base < total) {
+        for (int q = tid; q < n_st; q += 256) tb.cnt[q] = 0;
+        int32_t ns = 0;
+        while (ns < kTriChunk && base < total) {      // uniform: base and ns follow block totals
             const int32_t item = base + tid;
-            const int32_t rid = item < c.n_large ? bb.large[item] : bb.bins[c.bs + item - c.n_large];
-            if (rid >= 0) {
-                const TriRec R = bb.rec[rid];
-                TriClip t;
-                if (clip_to_rect(R, r, t)) {
-                    const int64_t zmin = R.z0 + R.gx * (R.gx > 0 ? t.ilo : t.ihi) + R.gy * (R.gy > 0 ? t.jlo : t.jhi);
-                    if ((int64_t)depth_q(zmin) < (int64_t)mthr) {
-                        const int32_t q = atomicAdd(&sh.n_slots, 1);
-                        TriSlot& T = tb.slot[q];
-                        for (int e = 0; e < 3; e++) {
-                            T.ex[e] = edge_at(R.e0[e], R.a[e], R.b[e], 256 * r.x, 256 * r.y);
-                            T.A[e] = R.a[e];
-                            T.B[e] = R.b[e];
-                        }
-                        T.zx = R.z0 + R.gx * r.x + R.gy * r.y;
-                        T.gx = R.gx;
-                        T.gy = R.gy;
-                        T.box = (uint32_t)(t.ilo - r.x) | ((uint32_t)(t.ihi - r.x) << 8) | ((uint32_t)(t.jlo - r.y) << 16) |
-                                ((uint32_t)(t.jhi - r.y) << 24);
+            bool keep = false;
+            TriRec R;
+            TriClip t;
+            if (item < total) {
+                const int32_t rid = item < c.n_large ? bb.large[item] : bb.bins[c.bs + item - c.n_large];
+                if (rid >= 0) {
+                    R = bb.rec[rid];
+                    if (clip_to_rect(R, r, t)) {
+                        const int64_t zmin = R.z0 + R.gx * (R.gx > 0 ? t.ilo : t.ihi) + R.gy * (R.gy > 0 ? t.jlo : t.jhi);
+                        keep = (int64_t)depth_q(zmin) < (int64_t)mthr;
                     }
                 }
             }
+            int32_t n_keep;
+            const int32_t rank = block_scan_excl(keep ? 1 : 0, sh.wsum, n_keep, lane, wv);
+            const int32_t room = kTriChunk - ns;
+            if (keep && rank < room) {
+                TriSlot& T = tb.slot[ns + rank];
+                for (int e = 0; e < 3; e++) {
+                    T.ex[e] = edge_at(R.e0[e], R.a[e], R.b[e], 256 * r.x, 256 * r.y);
+                    T.A[e] = R.a[e];
+                    T.B[e] = R.b[e];
+                }
+                T.zx = R.z0 + R.gx * r.x + R.gy * r.y;
+                T.gx = R.gx;
+                T.gy = R.gy;
+                T.box = (uint32_t)(t.ilo - r.x) | ((uint32_t)(t.ihi - r.x) << 8) | ((uint32_t)(t.jlo - r.y) << 16) |
+                        ((uint32_t)(t.jhi - r.y) << 24);
+            }
+            if (keep && rank == room) sh.cut = tid;        // the first survivor left for the next chunk
+            if (n_keep > room) {
+                __syncthreads();
+                base += sh.cut;
+                ns = kTriChunk;
+            } else {
+                base += 256;
+                ns += n_keep;
+            }
         }
         __syncthreads();
-        const int32_t ns = sh.n_slots;
-        if (ns == 0) continue;
+        if (ns == 0) break;
         // stamp binning: wave per triangle slot, lane per stamp
         for (int32_t q = wv; q < ns; q += 4) {
             const TriSlot& T = tb.slot[q];

@@ -60,14 +60,26 @@ struct PathSizes {
     int64_t item_cap, chunk_cap;      // pair mode: binned items, chunks of pair space
 };
 
+// The buffers one stream of the per-sun path works in; consecutive suns
+// alternate between two lanes on two streams.
+struct Lane {
+    Buf rec, large, bins, tile_count, tile_start, tile_cursor, tile_list, pitems, pchunk, modbox, map;
+    void release_all(Ctx* c) {
+        Buf* all[] = {&rec, &large, &bins, &tile_count, &tile_start, &tile_cursor, &tile_list, &pitems, &pchunk,
+                      &modbox, &map};
+        for (Buf* b : all) b->release(c);
+    }
+};
+
 struct Work {
-    Buf rec, large, bins, tile_count, tile_start, tile_cursor, tile_list, pitems, pchunk, map;
-    Buf views, ctr, beam, bias, sweep, sphere, partial, fu, fv, modbox, tmask;
+    Lane lane[2];
+    Buf views, ctr, beam, bias, sweep, sphere, partial, fu, fv, tmask;
     Buf counts, outd, maps, bits;
     void release_all(Ctx* c) {
-        Buf* all[] = {&rec, &large, &bins, &tile_count, &tile_start, &tile_cursor, &tile_list, &pitems, &pchunk, &map,
-                      &views, &ctr,
-                      &beam, &bias, &sweep, &sphere, &partial, &fu, &fv, &modbox, &tmask, &counts, &outd, &maps, &bits};
+        lane[0].release_all(c);
+        lane[1].release_all(c);
+        Buf* all[] = {&views, &ctr, &beam, &bias, &sweep, &sphere, &partial, &fu, &fv, &tmask, &counts, &outd, &maps,
+                      &bits};
         for (Buf* b : all) b->release(c);
     }
 };
@@ -109,6 +121,8 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t stream_in_use = nullptr;
+    hipStream_t stream2 = nullptr;          // the per-sun path's second lane
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     uint64_t budget = 0;
     uint64_t used = 0;
     size_t max_lds = 65536;
@@ -139,11 +153,12 @@ struct Ctx {
     pv3d_status stage_reserve(size_t bytes);
     pv3d_status stage_done(hipStream_t st);
     pv3d_status ensure_path(const PathSizes& z, const Gen& g, int32_t map_n, bool own_map);
+    pv3d_status ensure_lane(Lane& L, const PathSizes& z, const Gen& g, int32_t map_n, bool own_map);
     pv3d_status run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, const GenDev& gd, const pv3d_params& p,
                         const View* views, SunCounters* ctr, const int32_t* bias, const double* beam, uint32_t* map,
-                        uint32_t* counts_s, uint32_t* bits_s, const uint32_t* tmask_s, hipStream_t st);
+                        uint32_t* counts_s, uint32_t* bits_s, const uint32_t* tmask_s, int lane, hipStream_t st);
     pv3d_status ensure_tables(const Gen& g, int32_t k);
-    BinBuffers bin_buffers(const PathSizes& z);
+    BinBuffers bin_buffers(const PathSizes& z, int lane);
     pv3d_status run_path(const Scene& sc, const Gen& g, const pv3d_params& p, const double* sun_host, int64_t n_sun,
                          const double* d_sun, const double* d_dni, const double* d_dpoa, const double* d_dt,
                          uint32_t* counts, double* power, double* power_ref, double* energy, uint32_t* maps,

@@ -279,44 +279,51 @@ pv3d_status Ctx::ensure_path(const PathSizes& z, const Gen& g, int32_t map_n, bo
         return fail(PV3D_ERANGE, "scene too large for 32-bit bin indices");
     if (bin_lds_bytes(z.n_tiles) > max_lds)
         return fail(PV3D_ERANGE, "%d tiles need more LDS than a workgroup has; use a larger tile", z.n_tiles);
-    if ((st = w.rec.ensure(this, sizeof(TriRec) * (size_t)z.rec_cap, "triangle records"))) return st;
-    if ((st = w.large.ensure(this, 4 * (size_t)z.rec_cap, "large-triangle list"))) return st;
-    if ((st = w.bins.ensure(this, 4 * (size_t)z.bin_cap, "tile bins"))) return st;
-    if ((st = w.tile_count.ensure(this, 4 * (size_t)z.n_tiles, "tile counts"))) return st;
-    if ((st = w.tile_start.ensure(this, 4 * (size_t)(z.n_tiles + 1), "tile starts"))) return st;
-    if ((st = w.tile_cursor.ensure(this, 4 * (size_t)z.n_tiles, "tile cursors"))) return st;
-    if ((st = w.tile_list.ensure(this, 4 * (4 * (size_t)z.n_tiles + 2), "tile work list"))) return st;
-    if ((st = w.pitems.ensure(this, sizeof(PairItem) * (size_t)z.item_cap, "pair items"))) return st;
-    if ((st = w.pchunk.ensure(this, 4 * (size_t)z.chunk_cap, "pair chunks"))) return st;
-    if (own_map && (st = w.map.ensure(this, 4 * (size_t)map_n * map_n, "depth picture"))) return st;
+    if ((st = ensure_lane(w.lane[0], z, g, map_n, own_map))) return st;
     if ((st = w.views.ensure(this, sizeof(View) * (size_t)std::max<int64_t>(z.n_sun, 1), "views"))) return st;
     if ((st = w.ctr.ensure(this, sizeof(SunCounters) * (size_t)std::max<int64_t>(z.n_sun, 1), "counters"))) return st;
     if ((st = w.beam.ensure(this, 8 * (size_t)std::max<int64_t>(z.n_sun * g.n_mod, 1), "module beam"))) return st;
     if ((st = w.bias.ensure(this, 4 * (size_t)std::max<int64_t>(z.n_sun * g.n_mod, 1), "module bias"))) return st;
     if ((st = w.sweep.ensure(this, 8 * 6 * (size_t)std::max<int64_t>(z.n_sun, 1), "sweep"))) return st;
     if ((st = w.sphere.ensure(this, 64, "bounding sphere"))) return st;
-    if ((st = w.modbox.ensure(this, 16 * (size_t)g.n_mod, "module tile boxes"))) return st;
     if ((st = w.tmask.ensure(this, 4 * (size_t)z.mask_words * (size_t)std::max<int64_t>(z.n_sun, 1), "tile masks")))
         return st;
     if ((st = w.partial.ensure(this, 8 * 6 * 1024, "bounds partials"))) return st;
     return PV3D_OK;
 }
 
-BinBuffers Ctx::bin_buffers(const PathSizes& z) {
+pv3d_status Ctx::ensure_lane(Lane& L, const PathSizes& z, const Gen& g, int32_t map_n, bool own_map) {
+    pv3d_status st;
+    if ((st = L.rec.ensure(this, sizeof(TriRec) * (size_t)z.rec_cap, "triangle records"))) return st;
+    if ((st = L.large.ensure(this, 4 * (size_t)z.rec_cap, "large-triangle list"))) return st;
+    if ((st = L.bins.ensure(this, 4 * (size_t)z.bin_cap, "tile bins"))) return st;
+    if ((st = L.tile_count.ensure(this, 4 * (size_t)z.n_tiles, "tile counts"))) return st;
+    if ((st = L.tile_start.ensure(this, 4 * (size_t)(z.n_tiles + 1), "tile starts"))) return st;
+    if ((st = L.tile_cursor.ensure(this, 4 * (size_t)z.n_tiles, "tile cursors"))) return st;
+    if ((st = L.tile_list.ensure(this, 4 * (4 * (size_t)z.n_tiles + 2), "tile work list"))) return st;
+    if ((st = L.pitems.ensure(this, sizeof(PairItem) * (size_t)z.item_cap, "pair items"))) return st;
+    if ((st = L.pchunk.ensure(this, 4 * (size_t)z.chunk_cap, "pair chunks"))) return st;
+    if ((st = L.modbox.ensure(this, 16 * (size_t)g.n_mod, "module tile boxes"))) return st;
+    if (own_map && (st = L.map.ensure(this, 4 * (size_t)map_n * map_n, "depth picture"))) return st;
+    return PV3D_OK;
+}
+
+BinBuffers Ctx::bin_buffers(const PathSizes& z, int lane) {
+    Lane& L = w.lane[lane];
     BinBuffers bb;
-    bb.rec = static_cast<TriRec*>(w.rec.ptr);
+    bb.rec = static_cast<TriRec*>(L.rec.ptr);
     bb.rec_cap = (int32_t)z.rec_cap;
-    bb.large = static_cast<int32_t*>(w.large.ptr);
-    bb.tile_count = static_cast<int32_t*>(w.tile_count.ptr);
-    bb.tile_start = static_cast<int32_t*>(w.tile_start.ptr);
-    bb.tile_cursor = static_cast<int32_t*>(w.tile_cursor.ptr);
-    bb.bins = static_cast<int32_t*>(w.bins.ptr);
-    bb.modbox = static_cast<int4*>(w.modbox.ptr);
+    bb.large = static_cast<int32_t*>(L.large.ptr);
+    bb.tile_count = static_cast<int32_t*>(L.tile_count.ptr);
+    bb.tile_start = static_cast<int32_t*>(L.tile_start.ptr);
+    bb.tile_cursor = static_cast<int32_t*>(L.tile_cursor.ptr);
+    bb.bins = static_cast<int32_t*>(L.bins.ptr);
+    bb.modbox = static_cast<int4*>(L.modbox.ptr);
     bb.tile_list = nullptr;                // one workgroup per tile unless the sun takes the work list
     bb.list_ctr = nullptr;
     bb.split_at = 0;
-    bb.pitems = static_cast<PairItem*>(w.pitems.ptr);
-    bb.pchunk = static_cast<int32_t*>(w.pchunk.ptr);
+    bb.pitems = static_cast<PairItem*>(L.pitems.ptr);
+    bb.pchunk = static_cast<int32_t*>(L.pchunk.ptr);
     bb.pctr = nullptr;                     // per sun
     bb.item_cap = (int32_t)z.item_cap;
     bb.bin_cap = (int32_t)z.bin_cap;
@@ -395,8 +402,20 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
 
     if ((e = hipMemsetAsync(ctr, 0, sizeof(SunCounters) * (size_t)std::max<int64_t>(n_sun, 1), st)))
         return hip_fail(e, "clear counters");
+    // a second lane when its buffers fit the budget: consecutive suns then
+    // alternate between two streams, so that one sun's set-up and binning
+    // kernels, which leave most of the GPU idle, run beside the other's tile
+    // pass and the drain at its end
+    const bool own_map = maps == nullptr && (p.flags & PV3D_SEPARATE_TEST);
+    int n_lanes = 1;
+    if (stream2 && n_sun > 1) {
+        if (ensure_lane(w.lane[1], z, g, p.map_n, own_map) == PV3D_OK) n_lanes = 2;
+        else w.lane[1].release_all(this);
+    }
     // tile counts start at zero; the scan of every sun leaves them at zero again
-    if ((e = hipMemsetAsync(w.tile_count.ptr, 0, 4 * (size_t)z.n_tiles, st))) return hip_fail(e, "clear tile counts");
+    for (int l = 0; l < n_lanes; l++)
+        if ((e = hipMemsetAsync(w.lane[l].tile_count.ptr, 0, 4 * (size_t)z.n_tiles, st)))
+            return hip_fail(e, "clear tile counts");
     if (counts && (e = hipMemsetAsync(counts, 0, 4 * (size_t)(n_sun * z.cells), st))) return hip_fail(e, "clear counts");
     if (bits && (e = hipMemsetAsync(bits, 0, 4 * (size_t)(n_sun * z.cells * z.words), st))) return hip_fail(e, "clear bits");
     if (maps && (e = launch_fill_u32(maps, kDepthMax, n_sun * N2, st))) return hip_fail(e, "fill depth maps");
@@ -411,12 +430,23 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
     if (z.mask_words > 512) tmask = nullptr;
     if ((e = timed(prof, PV3D_STAGE_SETUP, st, [&] { return launch_setup(d_sun, n_sun, d_dni, gd, sphere, p.map_n, views, beam, bias, tg, tmask, st); })))
         return hip_fail(e, "setup");
+    if (n_lanes == 2) {
+        if ((e = hipEventRecord(fork_ev, st)) || (e = hipStreamWaitEvent(stream2, fork_ev, 0)))
+            return hip_fail(e, "fork the second lane");
+    }
+    int64_t done = 0;
     for (int64_t s = 0; s < n_sun; s++) {
         if (!(sun_host[3 * s + 2] > 0.0)) continue;        // below the horizon: outputs stay zero
         uint32_t* map = maps ? maps + s * N2 : nullptr;
+        const int lane = (int)(done++ % n_lanes);
         if ((rs = run_sun(s, z, sd, gd, p, views, ctr, bias, beam, map, counts + s * z.cells,
-                          bits ? bits + s * z.cells * z.words : nullptr, tmask ? tmask + s * z.mask_words : nullptr, st)))
+                          bits ? bits + s * z.cells * z.words : nullptr, tmask ? tmask + s * z.mask_words : nullptr,
+                          lane, lane ? stream2 : st)))
             return rs;
+    }
+    if (n_lanes == 2) {
+        if ((e = hipEventRecord(join_ev, stream2)) || (e = hipStreamWaitEvent(st, join_ev, 0)))
+            return hip_fail(e, "join the second lane");
     }
     if ((e = timed(prof, PV3D_STAGE_LOSS, st, [&] { return launch_loss(n_sun, d_sun, beam, counts, d_dpoa, gd, p.k, power, power_ref, st); })))
         return hip_fail(e, "loss");
@@ -432,11 +462,11 @@ constexpr int32_t kSplitEntries = 64;
 // The launch sequence of one sun.
 pv3d_status Ctx::run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, const GenDev& gd, const pv3d_params& p,
                          const View* views, SunCounters* ctr, const int32_t* bias, const double* beam, uint32_t* map,
-                         uint32_t* counts_s, uint32_t* bits_s, const uint32_t* tmask_s, hipStream_t st) {
+                         uint32_t* counts_s, uint32_t* bits_s, const uint32_t* tmask_s, int lane, hipStream_t st) {
     hipError_t e;
-    BinBuffers bb = bin_buffers(z);
+    BinBuffers bb = bin_buffers(z, lane);
     const bool separate = (p.flags & PV3D_SEPARATE_TEST) != 0;
-    if (separate && !map) map = static_cast<uint32_t*>(w.map.ptr);
+    if (separate && !map) map = static_cast<uint32_t*>(w.lane[lane].map.ptr);
     TileOut to;
     to.map = map;
     to.counts = counts_s;
@@ -444,7 +474,7 @@ pv3d_status Ctx::run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, cons
     to.test = separate ? 0 : 1;
     to.sparse = (map == nullptr && !separate && !(p.flags & PV3D_FULL_RASTER)) ? 1 : 0;
     if (to.sparse) {       // the scan lists the tiles with work, heaviest first; 64-texel ones split in quadrants
-        int32_t* tl = static_cast<int32_t*>(w.tile_list.ptr);
+        int32_t* tl = static_cast<int32_t*>(w.lane[lane].tile_list.ptr);
         bb.list_ctr = tl;
         bb.tile_list = tl + 2;
         bb.split_at = z.tile == 64 ? kSplitEntries : 0;
@@ -524,6 +554,11 @@ pv3d_status pv3d_create(int32_t device, uint64_t hbm_budget_bytes, pv3d_ctx** ou
     if ((e = hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming)) != hipSuccess)
         return hip_fail(e, "hipEventCreate");
     c->stream_in_use = c->stream;
+    if ((e = hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "hipStreamCreate");
+    if ((e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "hipEventCreate");
     {
         hipDeviceProp_t prop;
         if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
@@ -556,6 +591,9 @@ void pv3d_destroy(pv3d_ctx* ctx) {
     for (hipEvent_t ev : ctx->prof.pool) (void)hipEventDestroy(ev);
     (void)hipEventDestroy(ctx->staging_done);
     (void)hipStreamDestroy(ctx->stream);
+    if (ctx->stream2) (void)hipStreamDestroy(ctx->stream2);
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
     delete ctx;
 }
 
