@@ -47,6 +47,11 @@ def _bind(path: str):
     L.oracle_raster.argtypes = [P, i64, i32, P, P]
     L.oracle_string_power.restype = f64
     L.oracle_string_power.argtypes = [P, i64]
+    L.oracle_evaluate_tracked.restype = i64
+    L.oracle_evaluate_tracked.argtypes = [P, i64, P, i64, P, P, P, i64, i32, i32, P, i32, P, i32, P, i32, P,
+                                          P, P, P, P, i64, i32, i32, P, P, P, P, P, P, i32]
+    L.oracle_pose.restype = None
+    L.oracle_pose.argtypes = [P, i32, P, P, P, P, i64, P, P, P, P]
     return L
 
 
@@ -131,10 +136,19 @@ def evaluate(scene, gen, sweep, map_n: int, k: int, export_maps: bool = False,
     maps = np.zeros((ns, map_n, map_n), np.uint32) if export_maps else None
     words = (k * k + 31) // 32
     bits = np.zeros((ns, cells, words), np.uint32) if export_bits else None
-    out = L.oracle_evaluate(_p(xyz), xyz.shape[0], _p(tri), tri.shape[0], _p(org), _p(eu), _p(ev),
-                            gen.n_mod, gen.n_cu, gen.n_cv, _p(cs), gen.n_sub, _p(ms),
-                            1 if gen.add_as_occluders else 0, _p(s), _p(dni), _p(dp), _p(dt), ns,
-                            map_n, k, _p(counts), _p(pw), _p(pr), _p(en), _p(maps), _p(bits), threads)
+    if getattr(gen, "trackers", None) is not None:
+        trk = _c(gen.trackers, np.float64).reshape(-1, 7)
+        mt = _c(gen.module_tracker, np.int32)
+        out = L.oracle_evaluate_tracked(_p(xyz), xyz.shape[0], _p(tri), tri.shape[0], _p(org), _p(eu), _p(ev),
+                                        gen.n_mod, gen.n_cu, gen.n_cv, _p(cs), gen.n_sub, _p(ms),
+                                        1 if gen.add_as_occluders else 0, _p(trk), trk.shape[0], _p(mt),
+                                        _p(s), _p(dni), _p(dp), _p(dt), ns, map_n, k, _p(counts), _p(pw), _p(pr),
+                                        _p(en), _p(maps), _p(bits), threads)
+    else:
+        out = L.oracle_evaluate(_p(xyz), xyz.shape[0], _p(tri), tri.shape[0], _p(org), _p(eu), _p(ev),
+                                gen.n_mod, gen.n_cu, gen.n_cv, _p(cs), gen.n_sub, _p(ms),
+                                1 if gen.add_as_occluders else 0, _p(s), _p(dni), _p(dp), _p(dt), ns,
+                                map_n, k, _p(counts), _p(pw), _p(pr), _p(en), _p(maps), _p(bits), threads)
     if out < 0:
         raise ValueError("oracle rejected its arguments")
     return OracleResult(counts, pw, pr, en, maps, bits, int(out))
@@ -153,6 +167,18 @@ def view(scene, gen, sun, map_n: int, dni: float = 1000.0):
                   _p(w), _p(beam), _p(bias))
     return dict(e1=w[0:3], e2=w[3:6], d=w[6:9], ox=w[9], oy=w[10], itx=w[11], ity=w[12],
                 znear=w[13], izd=w[14], valid=bool(w[15]), n=int(w[16]), beam=beam, bias=bias)
+
+
+def pose(gen, sun):
+    """The generator's modules posed for one sun: (origin, edge_u, edge_v), each [M, 3]."""
+    L = lib()
+    org, eu, ev = (_c(a, np.float64) for a in (gen.origin, gen.edge_u, gen.edge_v))
+    trk = _c(gen.trackers, np.float64).reshape(-1, 7)
+    mt = _c(gen.module_tracker, np.int32)
+    s = _c(sun, np.float64)
+    o2, u2, v2 = (np.zeros_like(org) for _ in range(3))
+    L.oracle_pose(_p(trk), trk.shape[0], _p(mt), _p(org), _p(eu), _p(ev), gen.n_mod, _p(s), _p(o2), _p(u2), _p(v2))
+    return o2, u2, v2
 
 
 def raster(tris_light: np.ndarray, map_n: int, with_cover: bool = True):

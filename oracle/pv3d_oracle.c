@@ -28,6 +28,10 @@
  * evaluated in IEEE binary64 with no contraction (build with
  * -ffp-contract=off), every dot product as (ax*bx + ay*by) + az*bz.
  *
+ * Trackers (Sec. 3.4): generators whose modules turn about a pivot to follow
+ * the sun are evaluated with the modules posed anew for every sun (see the
+ * tracker section below for the reading of the tracking law).
+ *
  * Parallelism: sun positions are independent, so the driver runs one sun per
  * OpenMP thread; the work inside one sun is plain sequential loops.
  */
@@ -474,6 +478,116 @@ static void eval_sun(const or_problem* P, v3 centre, double radius, const double
 }
 
 /* ------------------------------------------------------------------------ */
+/* trackers                                                                 */
+/* ------------------------------------------------------------------------ */
+/* Sec. 3.4 evaluates a plant of two-axis trackers; the paper states no
+ * tracking law. Reading taken: ideal tracking with no angle limits and no
+ * backtracking. A tracker turns the modules assigned to it about its pivot P.
+ * At rest its frame is u0 = a x z, v0 = a, n0 = z, a being its horizontal
+ * axis; a module given at rest keeps its coordinates in that frame, which for
+ * a sun s (unit, above the horizon) becomes
+ *   kind 1, one horizontal axis a:  v' = a, n' = unit(s - (s.a) a), u' = v' x n'
+ *   kind 2, two axes:               n' = s, u' = unit(z x s), v' = n' x u'
+ * (u' = u0 when the sun is at the zenith, n' = z if s is along a). */
+typedef struct { int32_t kind; v3 p, a; } or_tracker;
+
+static v3 unit3(v3 v) {
+    double l = sqrt(dot3(v, v));
+    return mk(v.x / l, v.y / l, v.z / l);
+}
+
+static void tracker_frame(const or_tracker* T, v3 s, v3* u, v3* v, v3* n) {
+    const v3 z = mk(0.0, 0.0, 1.0);
+    if (T->kind == 1) {
+        double sa = dot3(s, T->a);
+        v3 q = mk(s.x - sa * T->a.x, s.y - sa * T->a.y, s.z - sa * T->a.z);
+        *v = T->a;
+        *n = dot3(q, q) > 1e-30 ? unit3(q) : z;
+        *u = cross3(*v, *n);
+    } else {
+        v3 h = cross3(z, s);
+        *n = s;
+        *u = dot3(h, h) > 1e-30 ? unit3(h) : cross3(T->a, z);
+        *v = cross3(*n, *u);
+    }
+}
+
+/* coordinates (c0, c1, c2) in the frame (u, v, n): (c0 u + c1 v) + c2 n */
+static v3 in_frame(double c0, double c1, double c2, v3 u, v3 v, v3 n) {
+    return mk((c0 * u.x + c1 * v.x) + c2 * n.x, (c0 * u.y + c1 * v.y) + c2 * n.y,
+              (c0 * u.z + c1 * v.z) + c2 * n.z);
+}
+
+/* Module m of the rest pose (org, eu, ev) posed for sun s: untouched when it
+ * belongs to no tracker (mod_trk[m] < 0). */
+static void pose_module(const or_tracker* trk, const int32_t* mod_trk, const double* org, const double* eu,
+                        const double* ev, int64_t m, v3 s, double* o_out, double* u_out, double* v_out) {
+    v3 o = ld3(org + 3 * m), U = ld3(eu + 3 * m), W = ld3(ev + 3 * m);
+    if (mod_trk[m] >= 0) {
+        const or_tracker* T = trk + mod_trk[m];
+        const v3 z = mk(0.0, 0.0, 1.0);
+        v3 u0 = cross3(T->a, z), v0 = T->a, n0 = z, u, v, n;
+        tracker_frame(T, s, &u, &v, &n);
+        v3 r = sub3(o, T->p);
+        o = add3(T->p, in_frame(dot3(r, u0), dot3(r, v0), dot3(r, n0), u, v, n));
+        U = in_frame(dot3(U, u0), dot3(U, v0), dot3(U, n0), u, v, n);
+        W = in_frame(dot3(W, u0), dot3(W, v0), dot3(W, n0), u, v, n);
+    }
+    o_out[0] = o.x; o_out[1] = o.y; o_out[2] = o.z;
+    u_out[0] = U.x; u_out[1] = U.y; u_out[2] = U.z;
+    v_out[0] = W.x; v_out[1] = W.y; v_out[2] = W.z;
+}
+
+/* Bounding sphere when modules move: the box of the scene vertices, the
+ * corners of the modules that stay put, and for every tracker the cube
+ * P +- r, r the distance from P of its farthest module corner at rest (a
+ * rotation about P keeps every corner within it). */
+static void tracked_sphere(const or_problem* P, const or_tracker* trk, int32_t n_trk, const int32_t* mod_trk,
+                           v3* centre, double* radius) {
+    v3 lo = mk(INFINITY, INFINITY, INFINITY), hi = mk(-INFINITY, -INFINITY, -INFINITY);
+#define OR_GROW(q) do { v3 q_ = (q); \
+        lo.x = q_.x < lo.x ? q_.x : lo.x; hi.x = q_.x > hi.x ? q_.x : hi.x; \
+        lo.y = q_.y < lo.y ? q_.y : lo.y; hi.y = q_.y > hi.y ? q_.y : hi.y; \
+        lo.z = q_.z < lo.z ? q_.z : lo.z; hi.z = q_.z > hi.z ? q_.z : hi.z; } while (0)
+    for (int64_t i = 0; i < P->n_vert; i++) OR_GROW(ld3(P->xyz + 3 * i));
+    for (int32_t t = 0; t < n_trk; t++) {
+        double r = 0.0;
+        for (int64_t m = 0; m < P->n_mod; m++) {
+            if (mod_trk[m] != t) continue;
+            v3 c[4];
+            module_corners(P, m, c);
+            for (int q = 0; q < 4; q++) {
+                v3 d = sub3(c[q], trk[t].p);
+                double l = sqrt(dot3(d, d));
+                r = l > r ? l : r;
+            }
+        }
+        if (r > 0.0) {
+            OR_GROW(mk(trk[t].p.x - r, trk[t].p.y - r, trk[t].p.z - r));
+            OR_GROW(mk(trk[t].p.x + r, trk[t].p.y + r, trk[t].p.z + r));
+        }
+    }
+    for (int64_t m = 0; m < P->n_mod; m++) {
+        if (mod_trk[m] >= 0) continue;
+        v3 c[4];
+        module_corners(P, m, c);
+        for (int q = 0; q < 4; q++) OR_GROW(c[q]);
+    }
+#undef OR_GROW
+    *centre = mk((lo.x + hi.x) * 0.5, (lo.y + hi.y) * 0.5, (lo.z + hi.z) * 0.5);
+    v3 dg = sub3(hi, lo);
+    *radius = 0.5 * sqrt(dot3(dg, dg));
+}
+
+static void read_trackers(const double* trk_in, int32_t n_trk, or_tracker* trk) {
+    for (int32_t t = 0; t < n_trk; t++) {
+        trk[t].kind = (int32_t)trk_in[7 * t];
+        trk[t].p = ld3(trk_in + 7 * t + 1);
+        trk[t].a = ld3(trk_in + 7 * t + 4);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* exported entry points (called through ctypes by the tests)               */
 /* ------------------------------------------------------------------------ */
 static void fill_problem(or_problem* P, const double* xyz, int64_t n_vert, const int32_t* tri,
@@ -604,4 +718,88 @@ double oracle_string_power(const double* caps, int64_t n) {
     double p = string_power(c, n);
     free(c);
     return p;
+}
+
+/* Rest-pose modules (org, eu, ev) posed for one sun: trk [n_trk][7] = kind,
+ * pivot xyz, axis xyz; mod_trk [n_mod] the tracker of each module (-1 none). */
+void oracle_pose(const double* trk_in, int32_t n_trk, const int32_t* mod_trk, const double* org,
+                 const double* eu, const double* ev, int64_t n_mod, const double* sun,
+                 double* org_out, double* eu_out, double* ev_out) {
+    or_tracker* trk = (or_tracker*)malloc(sizeof(or_tracker) * (size_t)(n_trk > 0 ? n_trk : 1));
+    read_trackers(trk_in, n_trk, trk);
+    v3 s = ld3(sun);
+    for (int64_t m = 0; m < n_mod; m++)
+        pose_module(trk, mod_trk, org, eu, ev, m, s, org_out + 3 * m, eu_out + 3 * m, ev_out + 3 * m);
+    free(trk);
+}
+
+/* oracle_evaluate for a generator whose modules follow the sun: every sun is
+ * evaluated with the modules posed for it (bounding sphere as above). */
+int64_t oracle_evaluate_tracked(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t n_tri,
+                                const double* org, const double* eu, const double* ev, int64_t n_mod,
+                                int32_t n_cu, int32_t n_cv, const int32_t* cell_sub, int32_t n_sub,
+                                const int32_t* mod_string, int32_t occluders,
+                                const double* trk_in, int32_t n_trk, const int32_t* mod_trk,
+                                const double* sun_xyz, const double* dni, const double* d_poa,
+                                const double* dt_h, int64_t n_sun, int32_t n, int32_t k,
+                                uint32_t* counts, double* power, double* power_ref, double* energy,
+                                uint32_t* depth_maps, uint32_t* bits, int32_t threads) {
+    if (n < 16 || k < 1 || n_mod < 1 || n_trk < 0) return -1;
+    for (int64_t m = 0; m < n_mod; m++)
+        if (mod_trk[m] >= n_trk) return -1;
+    or_problem P;
+    fill_problem(&P, xyz, n_vert, tri, n_tri, org, eu, ev, n_mod, n_cu, n_cv, cell_sub, n_sub,
+                 mod_string, occluders);
+    or_tracker* trk = (or_tracker*)malloc(sizeof(or_tracker) * (size_t)(n_trk > 0 ? n_trk : 1));
+    read_trackers(trk_in, n_trk, trk);
+    v3 centre;
+    double radius;
+    tracked_sphere(&P, trk, n_trk, mod_trk, &centre, &radius);
+    int64_t cells = n_mod * (int64_t)n_cu * n_cv;
+    int32_t words = (k * k + 31) / 32;
+    int64_t outside = 0;
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+#pragma omp parallel reduction(+ : outside)
+    {
+        double* beam = (double*)malloc(sizeof(double) * (size_t)n_mod);
+        int32_t* bias = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_mod);
+        double* caps = (double*)malloc(sizeof(double) * (size_t)(n_mod * n_sub));
+        double* pose = (double*)malloc(sizeof(double) * (size_t)(9 * n_mod));
+        uint32_t* own_map = depth_maps ? NULL : (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n * n);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t t = 0; t < n_sun; t++) {
+            v3 s = ld3(sun_xyz + 3 * t);
+            or_problem Ps = P;
+            if (s.z > 0.0) {
+                for (int64_t m = 0; m < n_mod; m++)
+                    pose_module(trk, mod_trk, org, eu, ev, m, s, pose + 3 * m, pose + 3 * (n_mod + m),
+                                pose + 3 * (2 * n_mod + m));
+                Ps.org = pose;
+                Ps.eu = pose + 3 * n_mod;
+                Ps.ev = pose + 6 * n_mod;
+            }
+            or_sun_out o;
+            o.counts = counts + t * cells;
+            o.bits = bits ? bits + t * cells * words : NULL;
+            o.map = depth_maps ? depth_maps + t * (int64_t)n * n : own_map;
+            eval_sun(&Ps, centre, radius, sun_xyz + 3 * t, dni[t], d_poa[t], n, k, &o, beam, bias, caps);
+            power[t] = o.power;
+            power_ref[t] = o.power_ref;
+            outside += o.outside;
+        }
+        free(beam); free(bias); free(caps); free(pose); free(own_map);
+    }
+    free(trk);
+    double e = 0.0, er = 0.0;
+    for (int64_t t = 0; t < n_sun; t++) {
+        e += power[t] * dt_h[t];
+        er += power_ref[t] * dt_h[t];
+    }
+    energy[0] = e;
+    energy[1] = er;
+    return outside;
 }

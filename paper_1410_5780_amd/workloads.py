@@ -66,6 +66,12 @@ class Generator:
     n_sub: int
     module_string: np.ndarray  # int32 [M]
     add_as_occluders: bool = True
+    # trackers: modules given at rest, turned about a pivot as the sun moves
+    # (None: the modules stay put). trackers [T, 7] = kind (1 one horizontal
+    # axis, 2 two axes), pivot xyz, horizontal unit axis xyz; module_tracker
+    # [M] the tracker of each module, -1 for none.
+    trackers: Optional[np.ndarray] = None
+    module_tracker: Optional[np.ndarray] = None
 
     @property
     def n_mod(self) -> int:
@@ -401,6 +407,118 @@ def gen_bbox(gen: Generator):
     c = np.concatenate([gen.origin, gen.origin + gen.edge_u, gen.origin + gen.edge_u + gen.edge_v,
                         gen.origin + gen.edge_v])
     return c.min(0), c.max(0)
+
+
+# --------------------------------------------------------------------------
+# trackers
+# --------------------------------------------------------------------------
+def tracker_generator(pivots, kind: int, axis=(0.0, 1.0, 0.0), n_u: int = 7, n_v: int = 4,
+                      gap: float = 0.02, modules_per_string: int = 14, lift: float = 0.15) -> Generator:
+    """Trackers of n_u x n_v portrait modules each, flat and facing up at rest,
+    centred over their pivots and `lift` metres above them: the 6-cell side
+    runs along u0 = axis x z (n_u modules), the 10-cell side along v0 = axis
+    (n_v modules). kind 1 turns about the horizontal axis, kind 2 about two axes."""
+    pv = np.atleast_2d(np.asarray(pivots, dtype=np.float64))
+    a = np.asarray(axis, dtype=np.float64)
+    assert a[2] == 0.0 and abs(np.dot(a, a) - 1.0) < 1e-12, "the axis is a horizontal unit vector"
+    u0 = np.array([a[1], -a[0], 0.0])            # a x z
+    v0 = a
+    w = n_u * MOD_W + (n_u - 1) * gap
+    h = n_v * MOD_L + (n_v - 1) * gap
+    nt, per = pv.shape[0], n_u * n_v
+    m = np.arange(nt * per)
+    t, i, j = m // per, (m % per) % n_u, (m % per) // n_u
+    au = -w / 2 + i * (MOD_W + gap)
+    bv = -h / 2 + j * (MOD_L + gap)
+    O = pv[t] + au[:, None] * u0[None] + bv[:, None] * v0[None] + np.array([0.0, 0.0, lift])
+    trk = np.concatenate([np.full((nt, 1), float(kind)), pv, np.tile(a, (nt, 1))], 1)
+    return Generator(np.ascontiguousarray(O), np.tile(MOD_W * u0, (nt * per, 1)), np.tile(MOD_L * v0, (nt * per, 1)),
+                     N_CU, N_CV, portrait_substrings(), 3, (m // modules_per_string).astype(np.int32),
+                     trackers=np.ascontiguousarray(trk), module_tracker=t.astype(np.int32))
+
+
+def terrain(x0, y0, x1, y1, n: int, rng, hills: int = 6, height: float = 3.0, spread: float = 40.0):
+    """Uneven ground: an n x n grid of quads over [x0, x1] x [y0, y1], heights a sum of Gaussian hills."""
+    cx = rng.uniform(x0, x1, hills)
+    cy = rng.uniform(y0, y1, hills)
+    amp = rng.uniform(-height, height, hills)
+    xs, ys = np.linspace(x0, x1, n + 1), np.linspace(y0, y1, n + 1)
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+
+    def z_at(x, y):
+        x, y = np.asarray(x, float), np.asarray(y, float)
+        return sum(a * np.exp(-((x - u) ** 2 + (y - v) ** 2) / (2 * spread ** 2)) for a, u, v in zip(amp, cx, cy))
+
+    v = np.stack([X.ravel(), Y.ravel(), z_at(X.ravel(), Y.ravel())], 1)
+    q = np.arange(n * n)
+    r, c = q // n, q % n
+    a0 = r * (n + 1) + c
+    t = np.concatenate([np.stack([a0, a0 + 1, a0 + n + 2], 1), np.stack([a0, a0 + n + 2, a0 + n + 1], 1)])
+    return v, t, z_at
+
+
+def tracker_pair(gap_m: float = 4.0, kind: int = 2, map_n: int = 512, k: int = 4,
+                 sweep: Optional[Sweep] = None) -> Workload:
+    """Two trackers of 3 x 2 modules and nothing else. Two-axis trackers stand in a
+    north-south line (the southern one shades the other when the sun is low in the south),
+    one-axis trackers (north-south axes) in an east-west line (they shade each other in the
+    morning and evening)."""
+    second = [0.0, gap_m, 2.5] if kind == 2 else [gap_m, 0.0, 2.5]
+    gen = tracker_generator([[0.0, 0.0, 2.5], second], kind, n_u=3, n_v=2, modules_per_string=6)
+    sw = sweep if sweep is not None else make_sweep(LAT_DEG, [20, 80, 172, 355], np.arange(5, 20), up_only=True)
+    return Workload(f"tracker_pair_k{kind}", Scene(np.zeros((0, 3)), np.zeros((0, 3), np.int32)), gen, sw,
+                    map_n, k, f"2 trackers (kind {kind}), {gap_m} m apart")
+
+
+def c6_tracker_plant(seed: int = 6, sweep: Optional[Sweep] = None, map_n: int = 4096, k: int = 8,
+                     n_x: int = 6, n_y: int = 3) -> Workload:
+    """Two-axis tracker plant on uneven ground (the paper's Sec. 3.4 case): 18 trackers of
+    7 x 4 modules (504 modules, 30,240 cells) on rolling terrain, one lattice pylon in the field."""
+    rng = np.random.default_rng(seed)
+    sx, sy = 22.0, 28.0
+    xs = (np.arange(n_x) - (n_x - 1) / 2) * sx
+    ys = (np.arange(n_y) - (n_y - 1) / 2) * sy
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    x, y = X.ravel(), Y.ravel()
+    half = max(abs(xs).max(), abs(ys).max()) + 120.0
+    tv, tt, z_at = terrain(-half, -half, half, half, 64, rng)
+    piv = np.stack([x, y, z_at(x, y) + 3.5], 1)
+    gen = tracker_generator(piv, 2)
+    m = _Mesh()
+    m.add(tv, tt)
+    px, py = xs[2] + sx / 2, ys[1] + sy / 2            # between trackers
+    pv, pt = pylons(px, py, rng.uniform(0, 2 * np.pi, 1))
+    pv = pv.copy()
+    pv[..., 2] += float(z_at(px, py))
+    m.add(pv, pt)
+    sw = sweep if sweep is not None else year_sweep()
+    return Workload("c6_tracker_plant", m.scene(), gen, sw, map_n, k,
+                    f"{n_x * n_y} two-axis trackers of 7x4 modules on terrain, 1 pylon, N={map_n}, k={k}")
+
+
+def c2_tracker_rows(seed: int = 2, n_pylons: int = 50, sweep: Optional[Sweep] = None, rows: int = 20,
+                    map_n: int = 4096, k: int = 8) -> Workload:
+    """The row plant on one-axis trackers: 20 north-south rows of 2 x 10 modules (400 modules,
+    24,000 cells) turning about their axes, 4.5 m apart, ground plane, 50 lattice pylons."""
+    rng = np.random.default_rng(seed)
+    xs = (np.arange(rows) - (rows - 1) / 2) * 4.5
+    piv = np.stack([xs, np.zeros(rows), np.full(rows, 2.0)], 1)
+    gen = tracker_generator(piv, 1, n_u=2, n_v=10, modules_per_string=20)
+    lo = np.array([xs.min() - 3.0, -10.0, 0.0])
+    hi = np.array([xs.max() + 3.0, 10.0, 4.0])
+    m = _Mesh()
+    m.add(*ground_plane(lo[0] - 200, lo[1] - 200, hi[0] + 200, hi[1] + 200, 0.0))
+    px, py = [], []
+    while len(px) < n_pylons:
+        x = rng.uniform(lo[0] - 60, hi[0] + 60)
+        y = rng.uniform(lo[1] - 60, hi[1] + 60)
+        if lo[0] - 5 <= x <= hi[0] + 5 and lo[1] - 5 <= y <= hi[1] + 5:
+            continue
+        px.append(x); py.append(y)
+    m.add(*pylons(np.array(px), np.array(py), rng.uniform(0, 2 * np.pi, n_pylons)))
+    sw = sweep if sweep is not None else year_sweep()
+    return Workload("c2_tracker_rows", m.scene(), gen, sw, map_n, k,
+                    f"{rows} one-axis tracker rows of 2x10 modules, {n_pylons} pylons, ground, N={map_n}, k={k}")
 
 
 # --------------------------------------------------------------------------

@@ -7,6 +7,7 @@ import pytest
 
 from oracle import oracle as O
 from tests import test_oracle_pins as pins
+from tests import test_oracle_trackers as tpins
 
 SRC = open(O.SRC).read()
 
@@ -28,6 +29,13 @@ MUTANTS = {
     "back_lit_tested": ("if (!(cm > 0.0) || !V.valid) continue;\n        double nx = dot3(nh, V.e1), ny = dot3(nh, V.e2), nz = dot3(nh, V.d);\n        double gxs",
                         "if (!V.valid) continue;\n        double nx = dot3(nh, V.e1), ny = dot3(nh, V.e2), nz = dot3(nh, V.d);\n        double gxs"),
     "far_cull_inverted": ("if (zmin > (double)OR_DMAX) return;", "if (zmin < (double)OR_DMAX) return;"),
+    "tracker_frame_mirrored": ("*v = cross3(*n, *u);", "*v = cross3(*u, *n);"),
+    "one_axis_normal_not_projected": ("v3 q = mk(s.x - sa * T->a.x, s.y - sa * T->a.y, s.z - sa * T->a.z);",
+                                      "v3 q = s;"),
+    "pose_drops_height_over_pivot": ("o = add3(T->p, in_frame(dot3(r, u0), dot3(r, v0), dot3(r, n0), u, v, n));",
+                                     "o = add3(T->p, in_frame(dot3(r, u0), dot3(r, v0), 0.0, u, v, n));"),
+    "pose_edges_left_at_rest": ("U = in_frame(dot3(U, u0), dot3(U, v0), dot3(U, n0), u, v, n);", ""),
+    "tracked_sphere_ignores_reach": ("OR_GROW(mk(trk[t].p.x + r, trk[t].p.y + r, trk[t].p.z + r));", ""),
 }
 
 PINS = [
@@ -43,6 +51,12 @@ PINS = [
     (pins.test_back_lit_module_is_not_tested, {}),
     (pins.test_pole_shadow_length_on_flat_receiver, {"day": 355}),
     (pins.test_agrees_with_ray_casting_outside_band, {"seed": 21}),
+    (tpins.test_pose_is_a_rigid_turn_about_the_pivot, {"kind": 2}),
+    (tpins.test_pose_is_a_rigid_turn_about_the_pivot, {"kind": 1}),
+    (tpins.test_two_axis_tracker_faces_the_sun, {}),
+    (tpins.test_one_axis_tracker_faces_the_sun_as_its_axis_allows, {"axis": (0.6, -0.8, 0.0)}),
+    (tpins.test_lone_tracker_is_never_shaded, {"kind": 2}),
+    (tpins.test_tracker_shadow_agrees_with_ray_casting_outside_band, {"kind": 2}),
 ]
 
 
