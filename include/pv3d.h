@@ -100,6 +100,35 @@ pv3d_status pv3d_generator_define(pv3d_ctx* ctx, const pv3d_module* mods, int64_
                                   uint64_t* gen_out);
 pv3d_status pv3d_generator_release(pv3d_ctx* ctx, uint64_t gen);
 
+/* Trackers (Sec. 3.4 evaluates a plant of two-axis trackers; the paper gives
+ * no tracking law, so ideal tracking is taken: no angle limits, no
+ * backtracking). A tracker turns the modules assigned to it about its pivot
+ * as the sun moves. Its rest frame is u0 = axis x z, v0 = axis, n0 = z (axis:
+ * horizontal unit vector, axis[2] == 0); the modules are given at rest in
+ * world coordinates and keep their coordinates in the tracker's frame,
+ * which for a sun s becomes
+ *   kind 1 (one horizontal axis): v' = axis, n' = unit(s - (s.axis) axis), u' = v' x n'
+ *   kind 2 (two axes):            n' = s, u' = unit(z x s) (u0 at the zenith), v' = n' x u'.
+ * Modules with module_tracker[m] = -1 stay put. The rest of the definition is
+ * pv3d_generator_define's.
+ * Evaluation: pv3d_evaluate poses every module for every sun on the device
+ * (n_sun x n_mod x 128 bytes, counted against the HBM budget); the batched
+ * form and the serving loop reject tracked generators (EINVAL).
+ * EINVAL: kind not 1 or 2, axis not horizontal unit length within 1e-9,
+ * pivot not finite, module_tracker out of [-1, n_tracker). */
+typedef struct {
+    int32_t kind;       /* 1 or 2 */
+    int32_t reserved;   /* 0 */
+    double pivot[3];
+    double axis[3];
+} pv3d_tracker;
+
+pv3d_status pv3d_generator_define_tracked(pv3d_ctx* ctx, const pv3d_module* mods, int64_t n_mod,
+                                          const int32_t* cell_substring, int32_t n_sub_per_module,
+                                          const int32_t* module_string, int32_t add_as_occluders,
+                                          const pv3d_tracker* trackers, int32_t n_tracker,
+                                          const int32_t* module_tracker, uint64_t* gen_out);
+
 /* Helper (host): sun unit vectors for day-of-year and local solar hour at a
  * latitude, with Cooper's declination and 15 degrees of hour angle per hour
  * (the paper only states that the solar position is defined, Sec. 2 Step 3).

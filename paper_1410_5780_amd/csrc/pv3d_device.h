@@ -113,8 +113,16 @@ struct TileGrid {
 };
 
 // Generator as the kernels see it.
+// A tracker (Sec. 3.4; ideal tracking): pivot, horizontal unit axis, kind
+// 1 (one axis) or 2 (two axes).
+struct TrackerDev {
+    double p[3], a[3];
+    int32_t kind, pad;
+};
+
 struct GenDev {
     const Module* mods;
+    const Module* mods_sun;     // trackers: [n_sun][n_mod] modules posed per sun (nullptr: fixed modules)
     int32_t n_mod, n_cu, n_cv, n_sub, n_str;
     int32_t occluders;
     const int32_t* cell_sub;    // [n_cu*n_cv]
@@ -254,6 +262,9 @@ hipError_t launch_tri_setup(int64_t s, const View* views, const SceneDev& sc, co
                             const int32_t* bias, int32_t n, const BinBuffers& bb, SunCounters* ctr,
                             const uint32_t* tmask, hipStream_t st);
 hipError_t launch_bin_scan(int32_t n_tiles, const BinBuffers& bb, hipStream_t st);
+hipError_t launch_pose(const double* sun, int64_t n_sun, const Module* rest, int32_t n_mod, const TrackerDev* trk,
+                       const int32_t* mod_trk, Module* posed, hipStream_t st);
+hipError_t launch_box_sphere(const double lo[3], const double hi[3], double* sphere, hipStream_t st);
 hipError_t launch_pair_count(const BinBuffers& bb, const uint32_t* tmask, int32_t grid, hipStream_t st);
 hipError_t launch_pair_scatter(const BinBuffers& bb, const uint32_t* tmask, int32_t grid, hipStream_t st);
 hipError_t launch_bin_scatter(int64_t s, const BinBuffers& bb, int32_t n_mod, SunCounters* ctr,

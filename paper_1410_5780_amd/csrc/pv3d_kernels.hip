@@ -270,8 +270,80 @@ __global__ __launch_bounds__(256) void k_setup(const double* sun, const double* 
                                                double* beam, int32_t* bias, TileGrid tg, uint32_t* tmask) {
     __shared__ SetupLds L;
     const int64_t s = blockIdx.x;
-    setup_body(L, sun + 3 * s, dni[s], g, sphere, n, views + s, beam + s * g.n_mod, bias + s * g.n_mod, tg,
+    GenDev gs = g;                                    // trackers: this sun's posed modules
+    if (g.mods_sun) gs.mods = g.mods_sun + s * g.n_mod;
+    setup_body(L, sun + 3 * s, dni[s], gs, sphere, n, views + s, beam + s * g.n_mod, bias + s * g.n_mod, tg,
                tmask ? tmask + s * tg.words : nullptr);
+}
+
+// Trackers (Sec. 3.4; the reading taken is ideal tracking, no angle limits,
+// no backtracking): every module of a tracker keeps its coordinates in the
+// tracker's frame, which turns with the sun. Rest frame u0 = a x z, v0 = a,
+// n0 = z (a: horizontal unit axis); for sun s
+//   kind 1: v' = a, n' = unit(s - (s.a) a), u' = v' x n'
+//   kind 2: n' = s, u' = unit(z x s) (u0 at the zenith), v' = n' x u'.
+// One thread per (sun, module); suns below the horizon and modules of no
+// tracker keep the rest pose. The front normal is recomputed from the posed
+// edges with the operations the generator definition uses.
+__device__ __forceinline__ d3 unit3(d3 v) {
+    const double l = sqrt(dot(v, v));
+    return d3{v.x / l, v.y / l, v.z / l};
+}
+
+__device__ __forceinline__ d3 in_frame(double c0, double c1, double c2, d3 u, d3 v, d3 n) {
+    return d3{(c0 * u.x + c1 * v.x) + c2 * n.x, (c0 * u.y + c1 * v.y) + c2 * n.y, (c0 * u.z + c1 * v.z) + c2 * n.z};
+}
+
+__global__ __launch_bounds__(256) void k_pose(const double* sun, int64_t n_sun, const Module* rest, int32_t n_mod,
+                                              const TrackerDev* trk, const int32_t* mod_trk, Module* posed) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n_sun * n_mod) return;
+    const int64_t s = i / n_mod;
+    const int32_t m = (int32_t)(i % n_mod);
+    Module M = rest[m];
+    const int32_t t = mod_trk[m];
+    const d3 sv = ld3(sun + 3 * s);
+    if (t >= 0 && sv.z > 0.0) {
+        const TrackerDev& T = trk[t];
+        const d3 z{0.0, 0.0, 1.0}, a = ld3(T.a), P = ld3(T.p);
+        d3 u, v, n;
+        if (T.kind == 1) {
+            const double sa = dot(sv, a);
+            const d3 q{sv.x - sa * a.x, sv.y - sa * a.y, sv.z - sa * a.z};
+            v = a;
+            n = dot(q, q) > 1e-30 ? unit3(q) : z;
+            u = cross(v, n);
+        } else {
+            const d3 h = cross(z, sv);
+            n = sv;
+            u = dot(h, h) > 1e-30 ? unit3(h) : cross(a, z);
+            v = cross(n, u);
+        }
+        const d3 u0 = cross(a, z), v0 = a, n0 = z;
+        const d3 r{M.o[0] - P.x, M.o[1] - P.y, M.o[2] - P.z};
+        const d3 o = add(P, in_frame(dot(r, u0), dot(r, v0), dot(r, n0), u, v, n));
+        const d3 U0 = ld3(M.u), W0 = ld3(M.v);
+        const d3 U = in_frame(dot(U0, u0), dot(U0, v0), dot(U0, n0), u, v, n);
+        const d3 W = in_frame(dot(W0, u0), dot(W0, v0), dot(W0, n0), u, v, n);
+        const double cx = U.y * W.z - U.z * W.y, cy = U.z * W.x - U.x * W.z, cz = U.x * W.y - U.y * W.x;
+        const double l = sqrt((cx * cx + cy * cy) + cz * cz);
+        M.o[0] = o.x; M.o[1] = o.y; M.o[2] = o.z;
+        M.u[0] = U.x; M.u[1] = U.y; M.u[2] = U.z;
+        M.v[0] = W.x; M.v[1] = W.y; M.v[2] = W.z;
+        M.n[0] = cx / l; M.n[1] = cy / l; M.n[2] = cz / l;
+    }
+    posed[i] = M;
+}
+
+// Bounding sphere from a box given by value (centre, half diagonal), in
+// stream order with the kernels that read it.
+__global__ void k_box_sphere(double lx, double ly, double lz, double hx, double hy, double hz, double* out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double dx = hx - lx, dy = hy - ly, dz = hz - lz;
+    out[0] = (lx + hx) * 0.5;
+    out[1] = (ly + hy) * 0.5;
+    out[2] = (lz + hz) * 0.5;
+    out[3] = 0.5 * sqrt((dx * dx + dy * dy) + dz * dz);
 }
 
 // ---------------------------------------------------------------------------
@@ -2556,6 +2628,20 @@ hipError_t launch_pair_count(const BinBuffers& bb, const uint32_t* tmask, int32_
 
 hipError_t launch_pair_scatter(const BinBuffers& bb, const uint32_t* tmask, int32_t grid, hipStream_t st) {
     hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)grid), dim3(256), 0, st, bb, tmask);
+    return hipGetLastError();
+}
+
+hipError_t launch_pose(const double* sun, int64_t n_sun, const Module* rest, int32_t n_mod, const TrackerDev* trk,
+                       const int32_t* mod_trk, Module* posed, hipStream_t st) {
+    const int64_t total = n_sun * n_mod;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pose, dim3(grid_for(total, 256)), dim3(256), 0, st, sun, n_sun, rest, n_mod, trk, mod_trk,
+                       posed);
+    return hipGetLastError();
+}
+
+hipError_t launch_box_sphere(const double lo[3], const double hi[3], double* sphere, hipStream_t st) {
+    hipLaunchKernelGGL(k_box_sphere, dim3(1), dim3(64), 0, st, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], sphere);
     return hipGetLastError();
 }
 

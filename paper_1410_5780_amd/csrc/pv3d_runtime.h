@@ -44,7 +44,7 @@ struct Scene {
 };
 
 struct Gen {
-    double lo[3], hi[3];          // axis-aligned box of the module corners
+    double lo[3], hi[3];          // axis-aligned box of the module corners (with trackers: of their reach)
     int32_t users = 0;            // jobs of the serving loop that read it
     Module* mods = nullptr;
     int32_t* cell_sub = nullptr;
@@ -52,6 +52,9 @@ struct Gen {
     int32_t* str_mods = nullptr;
     int64_t n_mod = 0;
     int32_t n_cu = 0, n_cv = 0, n_sub = 0, n_str = 0, occluders = 0;
+    TrackerDev* trk = nullptr;    // [n_trk] (trackers: modules turn with the sun)
+    int32_t* mod_trk = nullptr;   // [n_mod] tracker of each module, -1 none
+    int32_t n_trk = 0;
 };
 
 struct PathSizes {
@@ -73,13 +76,13 @@ struct Lane {
 
 struct Work {
     Lane lane[2];
-    Buf views, ctr, beam, bias, sweep, sphere, partial, fu, fv, tmask;
+    Buf views, ctr, beam, bias, sweep, sphere, partial, fu, fv, tmask, posed;
     Buf counts, outd, maps, bits;
     void release_all(Ctx* c) {
         lane[0].release_all(c);
         lane[1].release_all(c);
-        Buf* all[] = {&views, &ctr, &beam, &bias, &sweep, &sphere, &partial, &fu, &fv, &tmask, &counts, &outd, &maps,
-                      &bits};
+        Buf* all[] = {&views, &ctr, &beam, &bias, &sweep, &sphere, &partial, &fu, &fv, &tmask, &posed, &counts, &outd,
+                      &maps, &bits};
         for (Buf* b : all) b->release(c);
     }
 };

@@ -369,6 +369,7 @@ SceneDev scene_dev(const Scene& sc) {
 GenDev gen_dev(const Gen& g) {
     GenDev d;
     d.mods = g.mods;
+    d.mods_sun = nullptr;
     d.n_mod = (int32_t)g.n_mod;
     d.n_cu = g.n_cu;
     d.n_cv = g.n_cv;
@@ -420,9 +421,26 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
     if (bits && (e = hipMemsetAsync(bits, 0, 4 * (size_t)(n_sun * z.cells * z.words), st))) return hip_fail(e, "clear bits");
     if (maps && (e = launch_fill_u32(maps, kDepthMax, n_sun * N2, st))) return hip_fail(e, "fill depth maps");
 
-    int32_t n_part = bounds_partials(sc.n_vert + 4 * g.n_mod);
-    if ((e = launch_bounds(sd, gd, static_cast<double*>(w.partial.ptr), n_part, sphere, st)))
-        return hip_fail(e, "bounds");
+    if (g.n_trk > 0) {
+        // trackers: every module posed for every sun, and a sphere over the scene and the
+        // trackers' reach (boxes known on the host since load and definition)
+        if ((rs = w.posed.ensure(this, sizeof(Module) * (size_t)std::max<int64_t>(n_sun * g.n_mod, 1), "posed modules")))
+            return rs;
+        Module* posed = static_cast<Module*>(w.posed.ptr);
+        if ((e = launch_pose(d_sun, n_sun, g.mods, (int32_t)g.n_mod, g.trk, g.mod_trk, posed, st)))
+            return hip_fail(e, "pose modules");
+        gd.mods_sun = posed;
+        double lo[3], hi[3];
+        for (int c = 0; c < 3; c++) {
+            lo[c] = std::fmin(sc.lo[c], g.lo[c]);
+            hi[c] = std::fmax(sc.hi[c], g.hi[c]);
+        }
+        if ((e = launch_box_sphere(lo, hi, sphere, st))) return hip_fail(e, "bounding sphere");
+    } else {
+        int32_t n_part = bounds_partials(sc.n_vert + 4 * g.n_mod);
+        if ((e = launch_bounds(sd, gd, static_cast<double*>(w.partial.ptr), n_part, sphere, st)))
+            return hip_fail(e, "bounds");
+    }
     // the sparse route bins triangles only into tiles that hold samples
     const bool sparse = maps == nullptr && !(p.flags & (PV3D_SEPARATE_TEST | PV3D_FULL_RASTER));
     uint32_t* tmask = sparse ? static_cast<uint32_t*>(w.tmask.ptr) : nullptr;
@@ -460,10 +478,12 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
 constexpr int32_t kSplitEntries = 64;
 
 // The launch sequence of one sun.
-pv3d_status Ctx::run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, const GenDev& gd, const pv3d_params& p,
+pv3d_status Ctx::run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, const GenDev& g_all, const pv3d_params& p,
                          const View* views, SunCounters* ctr, const int32_t* bias, const double* beam, uint32_t* map,
                          uint32_t* counts_s, uint32_t* bits_s, const uint32_t* tmask_s, int lane, hipStream_t st) {
     hipError_t e;
+    GenDev gd = g_all;                                   // trackers: this sun's posed modules
+    if (g_all.mods_sun) gd.mods = g_all.mods_sun + s * g_all.n_mod;
     BinBuffers bb = bin_buffers(z, lane);
     const bool separate = (p.flags & PV3D_SEPARATE_TEST) != 0;
     if (separate && !map) map = static_cast<uint32_t*>(w.lane[lane].map.ptr);
@@ -578,12 +598,15 @@ void pv3d_destroy(pv3d_ctx* ctx) {
     for (auto& kv : ctx->scenes) {
         ctx->dfree(kv.second.xyz);
         ctx->dfree(kv.second.tri);
+        if (kv.second.cbox) ctx->dfree(kv.second.cbox);
     }
     for (auto& kv : ctx->gens) {
         ctx->dfree(kv.second.mods);
         ctx->dfree(kv.second.cell_sub);
         ctx->dfree(kv.second.str_start);
         ctx->dfree(kv.second.str_mods);
+        if (kv.second.trk) ctx->dfree(kv.second.trk);
+        if (kv.second.mod_trk) ctx->dfree(kv.second.mod_trk);
     }
     ctx->w.release_all(ctx);
     ctx->release_batched();
@@ -685,10 +708,27 @@ pv3d_status pv3d_scene_release(pv3d_ctx* ctx, uint64_t scene) {
     return PV3D_OK;
 }
 
-pv3d_status pv3d_generator_define(pv3d_ctx* ctx, const pv3d_module* mods, int64_t n_mod, const int32_t* cell_substring,
-                                  int32_t n_sub, const int32_t* module_string, int32_t add_as_occluders,
-                                  uint64_t* gen_out) {
+static pv3d_status define_generator(pv3d_ctx* ctx, const pv3d_module* mods, int64_t n_mod,
+                                   const int32_t* cell_substring, int32_t n_sub, const int32_t* module_string,
+                                   int32_t add_as_occluders, const pv3d_tracker* trackers, int32_t n_trk,
+                                   const int32_t* module_tracker, uint64_t* gen_out) {
     if (!ctx || !mods || !cell_substring || !module_string || !gen_out) return fail(PV3D_EINVAL, "null argument");
+    if (n_trk < 0 || (n_trk > 0 && (!trackers || !module_tracker))) return fail(PV3D_EINVAL, "trackers");
+    for (int32_t t = 0; t < n_trk; t++) {
+        const pv3d_tracker& T = trackers[t];
+        if (T.kind != 1 && T.kind != 2) return fail(PV3D_EINVAL, "tracker %d: kind %d", t, T.kind);
+        if (T.reserved != 0) return fail(PV3D_EINVAL, "tracker %d: reserved field not 0", t);
+        if (!finite3(T.pivot) || !finite3(T.axis)) return fail(PV3D_EINVAL, "tracker %d is not finite", t);
+        const double aa = (T.axis[0] * T.axis[0] + T.axis[1] * T.axis[1]) + T.axis[2] * T.axis[2];
+        if (T.axis[2] != 0.0 || !(std::fabs(aa - 1.0) <= 1e-9))
+            return fail(PV3D_EINVAL, "tracker %d: the axis must be a horizontal unit vector", t);
+        for (int c = 0; c < 3; c++)
+            if (std::fabs(T.pivot[c]) > kMaxCoord) return fail(PV3D_ERANGE, "tracker %d beyond %.0e m", t, kMaxCoord);
+    }
+    if (n_trk > 0)
+        for (int64_t m = 0; m < n_mod; m++)
+            if (module_tracker[m] < -1 || module_tracker[m] >= n_trk)
+                return fail(PV3D_EINVAL, "module %lld: tracker %d out of range", (long long)m, module_tracker[m]);
     if (n_mod < 1 || n_mod >= INT32_MAX / 8) return fail(PV3D_EINVAL, "n_mod %lld", (long long)n_mod);
     const int32_t n_cu = mods[0].n_cu, n_cv = mods[0].n_cv;
     if (n_cu < 1 || n_cv < 1 || n_cu > 4096 || n_cv > 4096) return fail(PV3D_EINVAL, "cells per module %d x %d", n_cu, n_cv);
@@ -750,15 +790,36 @@ pv3d_status pv3d_generator_define(pv3d_ctx* ctx, const pv3d_module* mods, int64_
         g.lo[c] = INFINITY;
         g.hi[c] = -INFINITY;
     }
-    for (int64_t m = 0; m < n_mod; m++) {
+    // corners o, o+u, (o+u)+v, o+v of module m
+    auto corner = [&](int64_t m, int q, int c) {
         const Module& D = hm[(size_t)m];
-        for (int q = 0; q < 4; q++) {                 // corners o, o+u, (o+u)+v, o+v
+        return q == 0 ? D.o[c] : q == 1 ? D.o[c] + D.u[c] : q == 2 ? (D.o[c] + D.u[c]) + D.v[c] : D.o[c] + D.v[c];
+    };
+    for (int64_t m = 0; m < n_mod; m++) {
+        if (n_trk > 0 && module_tracker[m] >= 0) continue;      // a tracker's reach counts instead
+        for (int q = 0; q < 4; q++)
             for (int c = 0; c < 3; c++) {
-                const double p = q == 0 ? D.o[c] : q == 1 ? D.o[c] + D.u[c] : q == 2 ? (D.o[c] + D.u[c]) + D.v[c] : D.o[c] + D.v[c];
-                g.lo[c] = std::fmin(g.lo[c], p);
-                g.hi[c] = std::fmax(g.hi[c], p);
+                g.lo[c] = std::fmin(g.lo[c], corner(m, q, c));
+                g.hi[c] = std::fmax(g.hi[c], corner(m, q, c));
+            }
+    }
+    // a turn about the pivot keeps every corner within r of it: the cube P +- r
+    for (int32_t t = 0; t < n_trk; t++) {
+        double r = 0.0;
+        for (int64_t m = 0; m < n_mod; m++) {
+            if (module_tracker[m] != t) continue;
+            for (int q = 0; q < 4; q++) {
+                const double dx = corner(m, q, 0) - trackers[t].pivot[0], dy = corner(m, q, 1) - trackers[t].pivot[1],
+                             dz = corner(m, q, 2) - trackers[t].pivot[2];
+                const double l = std::sqrt((dx * dx + dy * dy) + dz * dz);
+                r = l > r ? l : r;
             }
         }
+        if (r > 0.0)
+            for (int c = 0; c < 3; c++) {
+                g.lo[c] = std::fmin(g.lo[c], trackers[t].pivot[c] - r);
+                g.hi[c] = std::fmax(g.hi[c], trackers[t].pivot[c] + r);
+            }
     }
     g.n_mod = n_mod;
     g.n_cu = n_cu;
@@ -776,10 +837,44 @@ pv3d_status pv3d_generator_define(pv3d_ctx* ctx, const pv3d_module* mods, int64_
     if ((e = hipMemcpy(g.cell_sub, cell_substring, 4 * (size_t)(n_cu * n_cv), hipMemcpyHostToDevice))) return hip_fail(e, "copy cell map");
     if ((e = hipMemcpy(g.str_start, start.data(), 4 * (size_t)(n_str + 1), hipMemcpyHostToDevice))) return hip_fail(e, "copy strings");
     if ((e = hipMemcpy(g.str_mods, order.data(), 4 * (size_t)n_mod, hipMemcpyHostToDevice))) return hip_fail(e, "copy strings");
+    if (n_trk > 0) {
+        std::vector<TrackerDev> td((size_t)n_trk);
+        for (int32_t t = 0; t < n_trk; t++) {
+            memset(&td[(size_t)t], 0, sizeof(TrackerDev));
+            for (int c = 0; c < 3; c++) {
+                td[(size_t)t].p[c] = trackers[t].pivot[c];
+                td[(size_t)t].a[c] = trackers[t].axis[c];
+            }
+            td[(size_t)t].kind = trackers[t].kind;
+        }
+        if ((st = ctx->dalloc((void**)&g.trk, sizeof(TrackerDev) * (size_t)n_trk, "trackers"))) return st;
+        if ((st = ctx->dalloc((void**)&g.mod_trk, 4 * (size_t)n_mod, "module trackers"))) return st;
+        if ((e = hipMemcpy(g.trk, td.data(), sizeof(TrackerDev) * (size_t)n_trk, hipMemcpyHostToDevice)))
+            return hip_fail(e, "copy trackers");
+        if ((e = hipMemcpy(g.mod_trk, module_tracker, 4 * (size_t)n_mod, hipMemcpyHostToDevice)))
+            return hip_fail(e, "copy module trackers");
+        g.n_trk = n_trk;
+    }
     uint64_t h = ++ctx->next_handle;
     ctx->gens[h] = g;
     *gen_out = h;
     return PV3D_OK;
+}
+
+pv3d_status pv3d_generator_define(pv3d_ctx* ctx, const pv3d_module* mods, int64_t n_mod, const int32_t* cell_substring,
+                                  int32_t n_sub, const int32_t* module_string, int32_t add_as_occluders,
+                                  uint64_t* gen_out) {
+    return define_generator(ctx, mods, n_mod, cell_substring, n_sub, module_string, add_as_occluders, nullptr, 0,
+                            nullptr, gen_out);
+}
+
+pv3d_status pv3d_generator_define_tracked(pv3d_ctx* ctx, const pv3d_module* mods, int64_t n_mod,
+                                          const int32_t* cell_substring, int32_t n_sub, const int32_t* module_string,
+                                          int32_t add_as_occluders, const pv3d_tracker* trackers, int32_t n_tracker,
+                                          const int32_t* module_tracker, uint64_t* gen_out) {
+    if (n_tracker < 1) return fail(PV3D_EINVAL, "a tracked generator needs at least one tracker");
+    return define_generator(ctx, mods, n_mod, cell_substring, n_sub, module_string, add_as_occluders, trackers,
+                            n_tracker, module_tracker, gen_out);
 }
 
 pv3d_status pv3d_generator_release(pv3d_ctx* ctx, uint64_t gen) {
@@ -794,6 +889,8 @@ pv3d_status pv3d_generator_release(pv3d_ctx* ctx, uint64_t gen) {
     ctx->dfree(it->second.cell_sub);
     ctx->dfree(it->second.str_start);
     ctx->dfree(it->second.str_mods);
+    if (it->second.trk) ctx->dfree(it->second.trk);
+    if (it->second.mod_trk) ctx->dfree(it->second.mod_trk);
     ctx->gens.erase(it);
     return PV3D_OK;
 }

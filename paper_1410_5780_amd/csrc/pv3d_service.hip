@@ -105,6 +105,9 @@ pv3d_status check_job(Ctx* c, const pv3d_job& j, int64_t idx, HostJob& h) {
     auto gi = c->gens.find(j.gen);
     if (gi == c->gens.end()) return fail(PV3D_ENOENT, "job %lld: unknown generator %llu", (long long)idx, (unsigned long long)j.gen);
     const Gen& g = gi->second;
+    if (g.n_trk > 0)
+        return fail(PV3D_EINVAL, "job %lld: tracked generators are evaluated by pv3d_evaluate (per-sun path)",
+                    (long long)idx);
     if ((int64_t)j.params.k * g.n_cu > 4095 || (int64_t)j.params.k * g.n_cv > 4095)
         return fail(PV3D_ERANGE, "job %lld: k * cells per module side exceeds 4095 samples", (long long)idx);
     memset(&h, 0, sizeof(h));

@@ -32,6 +32,10 @@ class Module(ctypes.Structure):
     _fields_ = [("origin", _f64 * 3), ("edge_u", _f64 * 3), ("edge_v", _f64 * 3), ("n_cu", _i32), ("n_cv", _i32)]
 
 
+class Tracker(ctypes.Structure):
+    _fields_ = [("kind", _i32), ("reserved", _i32), ("pivot", _f64 * 3), ("axis", _f64 * 3)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("map_n", _i32), ("k", _i32), ("flags", _u32), ("tile", _i32), ("bin_limit", _i32),
                 ("reserved", _i32)]
@@ -72,6 +76,8 @@ def lib():
         L.pv3d_scene_load.argtypes = [_P, _P, _i64, _P, _i64, ctypes.POINTER(_u64)]
         L.pv3d_scene_release.argtypes = [_P, _u64]
         L.pv3d_generator_define.argtypes = [_P, _P, _i64, _P, _i32, _P, _i32, ctypes.POINTER(_u64)]
+        L.pv3d_generator_define_tracked.argtypes = [_P, _P, _i64, _P, _i32, _P, _i32, _P, _i32, _P,
+                                                    ctypes.POINTER(_u64)]
         L.pv3d_generator_release.argtypes = [_P, _u64]
         L.pv3d_sun_cooper.argtypes = [_f64, _P, _P, _i64, _P]
         L.pv3d_evaluate.argtypes = [_P, _u64, _u64, _P, _P, _P, _P, _i64, ctypes.POINTER(Params),
@@ -88,7 +94,7 @@ def lib():
         L.pv3d_profile_enable.argtypes = [_P, _u32]
         L.pv3d_profile_read.argtypes = [_P, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
         for f in ("pv3d_profile_enable", "pv3d_profile_read", "pv3d_create", "pv3d_scene_load", "pv3d_scene_release", "pv3d_generator_define",
-                  "pv3d_generator_release", "pv3d_sun_cooper", "pv3d_evaluate", "pv3d_evaluate_batched",
+                  "pv3d_generator_define_tracked", "pv3d_generator_release", "pv3d_sun_cooper", "pv3d_evaluate", "pv3d_evaluate_batched",
                   "pv3d_autotune", "pv3d_batch_stats", "pv3d_batch_limits", "pv3d_serve_stats",
                   "pv3d_submit", "pv3d_poll", "pv3d_wait", "pv3d_cancel"):
             getattr(L, f).restype = _i32
@@ -208,8 +214,23 @@ class Context:
         cs = _c(gen.cell_substring, np.int32)
         ms = _c(gen.module_string, np.int32)
         h = _u64()
-        _check(lib().pv3d_generator_define(self.h, ctypes.addressof(mods), gen.n_mod, _ptr(cs), int(gen.n_sub),
-                                           _ptr(ms), 1 if gen.add_as_occluders else 0, ctypes.byref(h)), self.h)
+        occ = 1 if gen.add_as_occluders else 0
+        trk = getattr(gen, "trackers", None)
+        if trk is None:
+            _check(lib().pv3d_generator_define(self.h, ctypes.addressof(mods), gen.n_mod, _ptr(cs), int(gen.n_sub),
+                                               _ptr(ms), occ, ctypes.byref(h)), self.h)
+            return h.value
+        t = np.asarray(trk, np.float64).reshape(-1, 7)
+        arr = (Tracker * t.shape[0])()
+        for i, row in enumerate(t):
+            arr[i].kind = int(row[0])
+            arr[i].reserved = 0
+            arr[i].pivot[:] = [float(x) for x in row[1:4]]
+            arr[i].axis[:] = [float(x) for x in row[4:7]]
+        mt = _c(gen.module_tracker, np.int32)
+        _check(lib().pv3d_generator_define_tracked(self.h, ctypes.addressof(mods), gen.n_mod, _ptr(cs),
+                                                   int(gen.n_sub), _ptr(ms), occ, ctypes.addressof(arr), t.shape[0],
+                                                   _ptr(mt), ctypes.byref(h)), self.h)
         return h.value
 
     def release_generator(self, h: int):
