@@ -189,6 +189,43 @@ def c4_leg(ctx, every, log):
             "units": st["units"], "slots": st["slots"], "redone_per_sun": st["redone"]}
 
 
+def tracker_leg(ctx, log):
+    """The two-axis tracker plant on terrain (Sec. 3.4's case): a year on the per-sun loop,
+    modules posed for every sun on the device."""
+    import torch
+    from paper_1410_5780_amd import workloads as W
+    w = W.c6_tracker_plant()
+    sh, gh = ctx.load_scene(w.scene), ctx.define_generator(w.gen)
+    best = None
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.evaluate_device(sh, gh, w.gen, w.sweep, w.map_n, w.k)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    loss = r.loss
+    spec = dict(scene=sh, gen=gh, generator=w.gen, sweep=w.sweep, map_n=w.map_n, k=w.k, counts=False)
+    bbest = None
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b = ctx.evaluate_batched([spec], device=True)[0]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        bbest = dt if bbest is None else min(bbest, dt)
+    same = bool(np.array_equal(b.energy.cpu().numpy(), r.energy.cpu().numpy())
+                and np.array_equal(b.power.cpu().numpy(), r.power.cpu().numpy()))
+    ctx.release_scene(sh)
+    ctx.release_generator(gh)
+    log(f"[bench] trackers: {w.gen.trackers.shape[0]} two-axis trackers, {w.gen.n_cells} cells, year {best:.3f} s, "
+        f"batched {bbest:.3f} s, identical {same}")
+    return {"workload": f"{w.name}: {w.note}", "suns": w.sweep.n, "year_seconds": best,
+            "value": w.n_samples * w.sweep.n / best, "unit": "sample-sun tests/s",
+            "triangles_per_s": w.n_tri_submitted * w.sweep.n / best, "energy_loss": loss,
+            "batched_year_seconds": bbest, "batched_identical": same}
+
+
 def serving_leg(ctx, log, rate_hz, duration_s, light_rate, light_s):
     """Poisson request streams through the serving loop: latency from arrival to completion."""
     from paper_1410_5780_amd import serve, workloads as W
@@ -354,6 +391,7 @@ def main():
                                       line["year_seconds"], log)
         line["c4_batched"] = c4_leg(ctx, a.c4_every, log)
         line["serving"] = serving_leg(ctx, log, a.serve_rate, a.serve_seconds, a.light_rate, a.light_seconds)
+        line["trackers"] = tracker_leg(ctx, log)
     if not a.no_cpu:
         print("[bench] cpu oracle leg ...", file=sys.stderr, flush=True)
         full = w if a.suns <= 1 else workload(a.workload, 1)

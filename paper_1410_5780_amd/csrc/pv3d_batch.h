@@ -32,15 +32,17 @@ struct HostJob {
     int32_t tile, ntx, n_tiles, words, large_tiles, sparse, use_mask;
     int64_t cells, tri_all, n_items;
     double *d_sun, *d_dni, *d_dpoa, *d_dt, *d_sphere, *d_fu, *d_fv;
+    Module* d_posed;          // trackers: [n_sun][n_mod] modules posed per sun
     uint32_t* d_counts;
     double *d_power, *d_pref, *d_energy;
 };
 
 // Validate one job (params, sweep, handles, outputs) and fill its sizes.
-pv3d_status check_job(Ctx* c, const pv3d_job& j, int64_t idx, HostJob& h);
+// Tracked generators are taken only when allow_tracked (the batched form).
+pv3d_status check_job(Ctx* c, const pv3d_job& j, int64_t idx, HostJob& h, bool allow_tracked = false);
 
-// Bytes of a job's device data: sweep, sphere, sample tables, and (when
-// with_outputs) counts, powers and energy.
+// Bytes of a job's device data: sweep, sphere, sample tables, posed modules
+// (trackers), and (when with_outputs) counts, powers and energy.
 size_t job_bytes(const HostJob& h, bool with_counts, bool with_powers);
 
 // Lay out the job's device data from p on (the regions listed in job_bytes).

@@ -2071,6 +2071,13 @@ __device__ __forceinline__ BinBuffers slot_bins(const PLaunch& P, const PJob& J,
     return bb;
 }
 
+// The job's generator as one sun sees it: trackers' modules posed for that sun.
+__device__ __forceinline__ GenDev sun_gen(const PJob& J, const PItem it) {
+    GenDev g = J.g;
+    if (g.mods_sun) g.mods = g.mods_sun + (int64_t)it.sun * g.n_mod;
+    return g;
+}
+
 // Each phase as a function of its own, so the persistent kernel needs the
 // registers of its largest phase, not of all phases inlined together.
 __device__ __noinline__ void unit_setup(unsigned char* raw, const PJob& J, const PItem it, const PSlotBufs& B) {
@@ -2083,16 +2090,16 @@ __device__ __noinline__ void unit_setup(unsigned char* raw, const PJob& J, const
     for (int64_t c = threadIdx.x; c < J.cells; c += 256)
         __hip_atomic_store(row + c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const TileGrid tg{J.tile, J.ntx, J.n_tiles, J.words};
-    setup_body(*reinterpret_cast<SetupLds*>(raw), J.sun + 3 * it.sun, J.dni[it.sun], J.g, J.sphere, J.n, B.view,
-               B.beam, B.bias, tg, J.use_mask ? B.tmask : nullptr);
+    setup_body(*reinterpret_cast<SetupLds*>(raw), J.sun + 3 * it.sun, J.dni[it.sun], sun_gen(J, it), J.sphere, J.n,
+               B.view, B.beam, B.bias, tg, J.use_mask ? B.tmask : nullptr);
 }
 
-__device__ __noinline__ void unit_tri(unsigned char* raw, const PJob& J, const PSlotBufs& B, const BinBuffers& bb,
-                                      int32_t unit) {
+__device__ __noinline__ void unit_tri(unsigned char* raw, const PJob& J, const PItem it, const PSlotBufs& B,
+                                      const BinBuffers& bb, int32_t unit) {
     const int64_t total = J.sc.n_tri + (J.g.occluders ? 2 * (int64_t)J.g.n_mod : 0) + J.g.n_mod;
     const int64_t t0 = (int64_t)unit * kTriPerUnit;
     uint32_t* cnt = 4 * (size_t)J.n_tiles <= kPLdsBytes ? reinterpret_cast<uint32_t*>(raw) : nullptr;
-    tri_setup_body(cnt, t0, min(t0 + kTriPerUnit, total), *B.view, J.sc, J.g, B.bias, J.n, bb, B.ctr,
+    tri_setup_body(cnt, t0, min(t0 + kTriPerUnit, total), *B.view, J.sc, sun_gen(J, it), B.bias, J.n, bb, B.ctr,
                    J.use_mask ? B.tmask : nullptr);
 }
 
@@ -2119,6 +2126,7 @@ __device__ __noinline__ void unit_scatter(unsigned char* raw, const PJob& J, con
 __device__ __noinline__ void unit_tile(unsigned char* raw, const PJob& J, const PItem it, const PSlotBufs& B,
                                        const BinBuffers& bb, int32_t unit) {
     const int32_t item = B.tile_list[unit];
+    const GenDev gs = sun_gen(J, it);
     TileOut out;
     out.map = nullptr;
     out.counts = J.counts + (int64_t)it.sun * J.cells;
@@ -2127,10 +2135,10 @@ __device__ __noinline__ void unit_tile(unsigned char* raw, const PJob& J, const 
     out.sparse = J.sparse;
     const uint32_t* tmask = J.use_mask ? B.tmask : nullptr;
     if (J.tile == 64)
-        tile_body<64, kCap64>(*reinterpret_cast<TileLds<64, kCap64>*>(raw), item, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, J.g,
+        tile_body<64, kCap64>(*reinterpret_cast<TileLds<64, kCap64>*>(raw), item, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, gs,
                             B.bias, J.fu, J.fv, J.k, out, J.sparse, tmask);
     else
-        tile_body<32, kCap32>(*reinterpret_cast<TileLds<32, kCap32>*>(raw), item, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, J.g,
+        tile_body<32, kCap32>(*reinterpret_cast<TileLds<32, kCap32>*>(raw), item, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, gs,
                             B.bias, J.fu, J.fv, J.k, out, J.sparse, tmask);
 }
 
@@ -2518,7 +2526,7 @@ __global__ __launch_bounds__(256, 3) void k_persist(PLaunch P) {
                 case kPhTri:
                     for (int32_t q = 0; q < count; q++) {
                         if (q) __syncthreads();
-                        unit_tri(raw, J, B, bb, unit + q);
+                        unit_tri(raw, J, it, B, bb, unit + q);
                     }
                     break;
                 case kPhScan: unit_scan(raw, P, J, B, bb, st); break;

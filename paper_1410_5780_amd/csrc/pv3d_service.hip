@@ -89,7 +89,7 @@ static pv3d_status batch_state(Ctx* c, BatchState** out) {
     return PV3D_OK;
 }
 
-pv3d_status check_job(Ctx* c, const pv3d_job& j, int64_t idx, HostJob& h) {
+pv3d_status check_job(Ctx* c, const pv3d_job& j, int64_t idx, HostJob& h, bool allow_tracked) {
     pv3d_status st;
     if ((st = check_params(&j.params))) return fail(st, "job %lld: %s", (long long)idx, pv3d_last_error(nullptr));
     if (j.params.flags & ~PV3D_FULL_RASTER)
@@ -105,9 +105,8 @@ pv3d_status check_job(Ctx* c, const pv3d_job& j, int64_t idx, HostJob& h) {
     auto gi = c->gens.find(j.gen);
     if (gi == c->gens.end()) return fail(PV3D_ENOENT, "job %lld: unknown generator %llu", (long long)idx, (unsigned long long)j.gen);
     const Gen& g = gi->second;
-    if (g.n_trk > 0)
-        return fail(PV3D_EINVAL, "job %lld: tracked generators are evaluated by pv3d_evaluate (per-sun path)",
-                    (long long)idx);
+    if (g.n_trk > 0 && !allow_tracked)
+        return fail(PV3D_EINVAL, "job %lld: the serving loop does not take tracked generators", (long long)idx);
     if ((int64_t)j.params.k * g.n_cu > 4095 || (int64_t)j.params.k * g.n_cv > 4095)
         return fail(PV3D_ERANGE, "job %lld: k * cells per module side exceeds 4095 samples", (long long)idx);
     memset(&h, 0, sizeof(h));
@@ -136,6 +135,7 @@ static size_t table_bytes(const HostJob& h) {
 size_t job_bytes(const HostJob& h, bool with_counts, bool with_powers) {
     const size_t ns = (size_t)h.job.n_sun;
     size_t b = al256(48 * ns) + 256 + 2 * table_bytes(h);
+    if (h.g->n_trk > 0) b += al256(sizeof(Module) * ns * (size_t)h.g->n_mod);
     if (with_counts) b += al256(4 * ns * (size_t)h.cells);
     if (with_powers) b += al256(16 * ns) + 256;
     return b;
@@ -155,6 +155,11 @@ void carve_job(HostJob& h, char* p, bool with_counts, bool with_powers) {
     p += tb;
     h.d_fv = reinterpret_cast<double*>(p);
     p += tb;
+    h.d_posed = nullptr;
+    if (h.g->n_trk > 0) {
+        h.d_posed = reinterpret_cast<Module*>(p);
+        p += al256(sizeof(Module) * (size_t)ns * (size_t)h.g->n_mod);
+    }
     if (with_counts) {
         h.d_counts = reinterpret_cast<uint32_t*>(p);
         p += al256(4 * (size_t)(ns * h.cells));
@@ -179,6 +184,7 @@ PJob make_pjob(const HostJob& h) {
     memset(&J, 0, sizeof(J));
     J.sc = scene_dev(*h.sc);
     J.g = gen_dev(*h.g);
+    J.g.mods_sun = h.d_posed;
     J.sun = h.d_sun;
     J.dni = h.d_dni;
     J.dpoa = h.d_dpoa;
@@ -267,7 +273,7 @@ pv3d_status run_batch(Ctx* c, const pv3d_job* jobs, int64_t n_jobs, hipStream_t 
     std::vector<HostJob> H((size_t)n_jobs);
     int64_t n_items = 0, sweep_total = 0;
     for (int64_t i = 0; i < n_jobs; i++) {
-        if ((st = check_job(c, jobs[i], i, H[(size_t)i]))) return st;
+        if ((st = check_job(c, jobs[i], i, H[(size_t)i], true))) return st;
         n_items += H[(size_t)i].n_items;
         sweep_total += jobs[i].n_sun;
     }
@@ -323,6 +329,10 @@ pv3d_status run_batch(Ctx* c, const pv3d_job* jobs, int64_t n_jobs, hipStream_t 
             if ((e = hipMemsetAsync(h.d_pref, 0, 8 * (size_t)ns, s))) return hip_fail(e, "clear power_ref");
         }
         if ((e = hipMemsetAsync(h.d_energy, 0, 16, s))) return hip_fail(e, "clear energy");
+        // trackers: every module posed for every sun before the launch reads them
+        if (h.d_posed && ns > 0 &&
+            (e = launch_pose(h.d_sun, ns, h.g->mods, (int32_t)h.g->n_mod, h.g->trk, h.g->mod_trk, h.d_posed, s)))
+            return hip_fail(e, "pose modules");
     }
 
     if (n_items > 0) {
@@ -489,7 +499,7 @@ pv3d_status pv3d_autotune(pv3d_ctx* ctx, pv3d_job* job, int32_t n_probe, double*
     HostJob h;
     ctx->stream_in_use = ctx->stream;
     pv3d_status st;
-    if ((st = check_job(ctx, *job, 0, h))) return st;
+    if ((st = check_job(ctx, *job, 0, h, true))) return st;
     // probe suns: evenly spaced among those above the horizon
     std::vector<int64_t> up;
     for (int64_t t = 0; t < job->n_sun; t++)
