@@ -47,8 +47,9 @@ def parse():
                          "sun's full picture written to HBM and read back by a separate depth-check kernel")
     ap.add_argument("--no-materialised", action="store_true",
                     help="skip the extra one-step run of the materialised route")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched, C4 and serving legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched, C4, serving, tracker and stadium legs")
     ap.add_argument("--c4-every", type=int, default=50, help="C4 leg: every n-th sun of the year")
+    ap.add_argument("--stadium-every", type=int, default=4, help="stadium leg: every n-th sun of the year")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="serving leg: arrivals per second")
     ap.add_argument("--serve-seconds", type=float, default=0.1, help="serving leg: seconds of arrivals")
     ap.add_argument("--light-rate", type=float, default=4.0, help="serving leg: light-load arrivals per second")
@@ -226,6 +227,52 @@ def tracker_leg(ctx, log):
             "batched_year_seconds": bbest, "batched_identical": same}
 
 
+def stadium_leg(ctx, log, every):
+    """Sec. 3.3's case: 88 generators of 14 x 4 modules in one stadium scene, each with its own
+    window and picture. The scene is loaded once; the per-generator loop (one per-sun-path call
+    per generator) against one persistent launch over all 88 generators' suns."""
+    import torch
+    from paper_1410_5780_amd import workloads as W
+    yr = W.year_sweep()
+    ws = W.c7_stadium(sweep=yr.subset(np.arange(0, yr.n, every)))
+    sh = ctx.load_scene(ws[0].scene)
+    ghs = [ctx.define_generator(w.gen) for w in ws]
+    best = None
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = [ctx.evaluate_device(sh, gh, w.gen, w.sweep, w.map_n, w.k) for gh, w in zip(ghs, ws)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    specs = [dict(scene=sh, gen=gh, generator=w.gen, sweep=w.sweep, map_n=w.map_n, k=w.k, counts=False)
+             for gh, w in zip(ghs, ws)]
+    bbest = None
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bs = ctx.evaluate_batched(specs, device=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        bbest = dt if bbest is None else min(bbest, dt)
+    same = all(np.array_equal(a.power.cpu().numpy(), b.power.cpu().numpy())
+               and np.array_equal(a.energy.cpu().numpy(), b.energy.cpu().numpy()) for a, b in zip(rs, bs))
+    loss = np.array([r.loss for r in rs])
+    for gh in ghs:
+        ctx.release_generator(gh)
+    ctx.release_scene(sh)
+    n_sun = ws[0].sweep.n
+    tests = sum(w.n_samples for w in ws) * n_sun
+    log(f"[bench] stadium: {len(ws)} generators x {n_sun} suns, loop {best:.3f} s, batched {bbest:.3f} s, "
+        f"identical {same}, loss {loss.min():.4f}..{loss.max():.4f}")
+    return {"workload": f"c7_stadium: {len(ws)} generators of 14x4 modules, {ws[0].scene.n_tri} scene triangles, "
+                        f"N={ws[0].map_n}, k={ws[0].k}, every {every}th sun of the year",
+            "generators": len(ws), "suns": n_sun, "loop_seconds": best, "batched_seconds": bbest,
+            "value": tests / bbest, "unit": "sample-sun tests/s", "loop_value": tests / best,
+            "batched_identical": same, "energy_loss_min": float(loss.min()), "energy_loss_mean": float(loss.mean()),
+            "energy_loss_max": float(loss.max())}
+
+
 def serving_leg(ctx, log, rate_hz, duration_s, light_rate, light_s):
     """Poisson request streams through the serving loop: latency from arrival to completion."""
     from paper_1410_5780_amd import serve, workloads as W
@@ -392,6 +439,7 @@ def main():
         line["c4_batched"] = c4_leg(ctx, a.c4_every, log)
         line["serving"] = serving_leg(ctx, log, a.serve_rate, a.serve_seconds, a.light_rate, a.light_seconds)
         line["trackers"] = tracker_leg(ctx, log)
+        line["stadium"] = stadium_leg(ctx, log, a.stadium_every)
     if not a.no_cpu:
         print("[bench] cpu oracle leg ...", file=sys.stderr, flush=True)
         full = w if a.suns <= 1 else workload(a.workload, 1)

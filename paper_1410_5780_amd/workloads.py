@@ -522,6 +522,71 @@ def c2_tracker_rows(seed: int = 2, n_pylons: int = 50, sweep: Optional[Sweep] = 
 
 
 # --------------------------------------------------------------------------
+# many generators in one scene
+# --------------------------------------------------------------------------
+def c7_stadium(seed: int = 7, sweep: Optional[Sweep] = None, n_gen: int = 88, n_u: int = 4, n_v: int = 14,
+               map_n: int = 4096, k: int = 8, ring=(110.0, 90.0), slope_deg: float = 12.0) -> List[Workload]:
+    """A stadium roof with many generators (the paper's Sec. 3.3 case: 88 generators of 14 x 4
+    panels, each with its own orientation), here 4 panels along the ring and 14 down the roof.
+    The generators sit around an elliptical ring on a roof that slopes toward the pitch; an
+    outer wall ends just below them and four light towers stand inside the ring. Every
+    generator's modules are part of the shared scene, so each generator is shaded by the
+    others; each is evaluated with its own window and picture (one job per generator, all
+    sharing the scene) and does not add itself again as occluders."""
+    rng = np.random.default_rng(seed)
+    a_r, b_r = ring
+    beta = math.radians(slope_deg)
+    w = n_u * MOD_W + (n_u - 1) * 0.02
+    gens = []
+    m = _Mesh()
+    for i in range(n_gen):
+        phi = 2.0 * math.pi * (i + 0.5) / n_gen
+        c = np.array([a_r * math.cos(phi), b_r * math.sin(phi), 30.0])
+        er = np.array([math.cos(phi) / a_r, math.sin(phi) / b_r, 0.0])      # outward normal of the ellipse
+        er /= np.linalg.norm(er)
+        et = np.array([-er[1], er[0], 0.0])                                # tangential, er x et = z
+        up = math.cos(beta) * er + math.sin(beta) * np.array([0.0, 0.0, 1.0])   # rises outward
+        U, V = MOD_W * et, MOD_L * up
+        if np.cross(U, V)[2] < 0.0:
+            U = -U
+        uh, vh = U / MOD_W, V / MOD_L
+        q = np.arange(n_u * n_v)
+        iu, jv = q % n_u, q // n_u
+        O = (c - 0.5 * w * uh)[None] + (iu * (MOD_W + 0.02))[:, None] * uh[None] + (jv * (MOD_L + 0.02))[:, None] * vh[None]
+        g = Generator(np.ascontiguousarray(O), np.tile(U, (O.shape[0], 1)), np.tile(V, (O.shape[0], 1)), N_CU, N_CV,
+                      portrait_substrings(), 3, (q // 14).astype(np.int32), add_as_occluders=False)
+        gens.append(g)
+        c0, c1, c2 = O, O + U, (O + U) + V
+        m.add(np.stack([c0, c1, c2], 1), np.array([[0, 1, 2]]))
+        m.add(np.stack([c0, c2, O + V], 1), np.array([[0, 1, 2]]))
+    # outer wall: 176 segments ending just below the panels; four light towers
+    n_w = 2 * n_gen
+    ph = 2.0 * math.pi * (np.arange(n_w) + 0.5) / n_w
+    grow = 1.0 + (n_v * MOD_L * math.cos(beta) + 1.0) / min(a_r, b_r)
+    wx, wy = a_r * grow * np.cos(ph), b_r * grow * np.sin(ph)
+    seg = 2.0 * math.pi * max(a_r, b_r) * grow / n_w * 1.05
+    yaw = np.arctan2(b_r * np.cos(ph), -a_r * np.sin(ph))
+    top = 29.5
+    m.add(*boxes(wx, wy, seg, 1.0, 0.0, top, yaw, floor=False))
+    tw = rng.uniform(0.0, 2.0 * math.pi) + np.arange(4) * math.pi / 2
+    m.add(*boxes(0.7 * a_r * np.cos(tw), 0.7 * b_r * np.sin(tw), 2.0, 2.0, 0.0, 55.0, 0.0, floor=False))
+    scene = m.scene()
+    sw = sweep if sweep is not None else year_sweep()
+    return [Workload(f"c7_stadium_g{i}", scene, g, sw, map_n, k,
+                     f"generator {i} of {n_gen} ({n_u}x{n_v} modules) on a stadium ring, N={map_n}, k={k}")
+            for i, g in enumerate(gens)]
+
+
+def c7_stadium_small(sweep: Optional[Sweep] = None) -> List[Workload]:
+    """Ten generators of 2 x 4 modules on a 30 m x 24 m ring, N = 256, k = 2, every 37th sun of
+    the year: a stadium small enough for the oracle in seconds that still shades itself."""
+    if sweep is None:
+        yr = year_sweep()
+        sweep = yr.subset(np.arange(0, yr.n, 37))
+    return c7_stadium(sweep=sweep, n_gen=10, n_u=2, n_v=4, map_n=256, k=2, ring=(30.0, 24.0))
+
+
+# --------------------------------------------------------------------------
 # the configurations
 # --------------------------------------------------------------------------
 def c1_tiny(d_poa: float = 0.0) -> Workload:
