@@ -113,7 +113,8 @@ pv3d_status pv3d_generator_release(pv3d_ctx* ctx, uint64_t gen);
  * pv3d_generator_define's.
  * Evaluation: pv3d_evaluate poses every module for every sun on the device
  * (n_sun x n_mod x 128 bytes, counted against the HBM budget); the batched
- * form and the serving loop reject tracked generators (EINVAL).
+ * form poses each tracked job's modules in its job memory before its launch;
+ * the serving loop rejects tracked generators (EINVAL).
  * EINVAL: kind not 1 or 2, axis not horizontal unit length within 1e-9,
  * pivot not finite, module_tracker out of [-1, n_tracker). */
 typedef struct {
@@ -128,6 +129,37 @@ pv3d_status pv3d_generator_define_tracked(pv3d_ctx* ctx, const pv3d_module* mods
                                           const int32_t* module_string, int32_t add_as_occluders,
                                           const pv3d_tracker* trackers, int32_t n_tracker,
                                           const int32_t* module_tracker, uint64_t* gen_out);
+
+/* Electrical model (Sec. 2 Step 4 turns the geometric shading into power with
+ * a diode model of the cells and a system model, neither given in the paper).
+ * By default a generator uses ideal bypass-diode strings: a substring carries
+ * at most the irradiance of its weakest cell, at unit voltage, or is bypassed;
+ * each string works at its best current. pv3d_generator_set_diode switches a
+ * generator to the single-diode cell model instead: every cell follows
+ *   I = Iph - I0 (exp((V + I Rs) / a) - 1) - (V + I Rs) / Rsh,
+ *   Iph = isc_ref * G / g_ref  (G: the cell's irradiance, beam on the module
+ *   times its unshaded fraction, plus the diffuse),
+ * at a fixed temperature (a = n k T / q is given); each substring's bypass
+ * diode holds the substring's voltage at no less than -v_bypass; substrings
+ * are in series; each string works at its maximum power point, found by a
+ * search over 65 evenly spaced currents in [0, largest cell photocurrent]
+ * refined by 40 golden-section steps around every sampled maximum. power and
+ * power_ref are then in W. The setting applies to evaluations started after
+ * the call (per-sun, batched and serving). d = NULL returns to ideal strings.
+ * EINVAL: non-finite parameters, isc_ref, g_ref, i0, a or rsh not > 0, rs or
+ * v_bypass negative; ENOENT: unknown generator; EBUSY: a running serving job
+ * reads the generator. */
+typedef struct {
+    double isc_ref;    /* cell photocurrent at g_ref, A */
+    double g_ref;      /* irradiance of isc_ref, W/m^2 */
+    double i0;         /* diode saturation current, A */
+    double a;          /* modified ideality factor n k T / q, V */
+    double rs;         /* series resistance, ohm */
+    double rsh;        /* shunt resistance, ohm */
+    double v_bypass;   /* bypass diode forward voltage, V */
+} pv3d_diode;
+
+pv3d_status pv3d_generator_set_diode(pv3d_ctx* ctx, uint64_t gen, const pv3d_diode* d);
 
 /* Helper (host): sun unit vectors for day-of-year and local solar hour at a
  * latitude, with Cooper's declination and 15 degrees of hour angle per hour
@@ -162,7 +194,8 @@ typedef struct {
  * cell_counts: [n_sun][n_cells] shaded samples per cell (cells in module,
  *   then cell-index order); a cell's shaded fraction is count / k^2.
  * power, power_ref: [n_sun] generator power with and without shading
- *   (W, with current proportional to irradiance and unit substring voltage).
+ *   (ideal strings: W per unit substring voltage, current proportional to
+ *   irradiance; single-diode model: W).
  * energy: [2] sum over suns of power * dt_h and power_ref * dt_h, in sun
  *   order; the shading loss is 1 - energy[0] / energy[1].
  * depth_maps: [n_sun][map_n][map_n] 24-bit depths in uint32 (row j = image

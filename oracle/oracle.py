@@ -40,7 +40,7 @@ def _bind(path: str):
     i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     L.oracle_evaluate.restype = i64
     L.oracle_evaluate.argtypes = [P, i64, P, i64, P, P, P, i64, i32, i32, P, i32, P, i32,
-                                  P, P, P, P, i64, i32, i32, P, P, P, P, P, P, i32]
+                                  P, P, P, P, i64, i32, i32, P, P, P, P, P, P, i32, P]
     L.oracle_view.restype = None
     L.oracle_view.argtypes = [P, i64, P, P, P, i64, P, f64, i32, P, P, P]
     L.oracle_raster.restype = None
@@ -49,9 +49,15 @@ def _bind(path: str):
     L.oracle_string_power.argtypes = [P, i64]
     L.oracle_evaluate_tracked.restype = i64
     L.oracle_evaluate_tracked.argtypes = [P, i64, P, i64, P, P, P, i64, i32, i32, P, i32, P, i32, P, i32, P,
-                                          P, P, P, P, i64, i32, i32, P, P, P, P, P, P, i32]
+                                          P, P, P, P, i64, i32, i32, P, P, P, P, P, P, i32, P]
     L.oracle_pose.restype = None
     L.oracle_pose.argtypes = [P, i32, P, P, P, P, i64, P, P, P, P]
+    L.oracle_cell_voltage.restype = f64
+    L.oracle_cell_voltage.argtypes = [P, f64, f64]
+    L.oracle_string_voltage.restype = f64
+    L.oracle_string_voltage.argtypes = [P, P, P, i64, f64]
+    L.oracle_string_mpp.restype = f64
+    L.oracle_string_mpp.argtypes = [P, P, P, i64]
     return L
 
 
@@ -136,6 +142,7 @@ def evaluate(scene, gen, sweep, map_n: int, k: int, export_maps: bool = False,
     maps = np.zeros((ns, map_n, map_n), np.uint32) if export_maps else None
     words = (k * k + 31) // 32
     bits = np.zeros((ns, cells, words), np.uint32) if export_bits else None
+    dio = _diode(getattr(gen, "diode", None))
     if getattr(gen, "trackers", None) is not None:
         trk = _c(gen.trackers, np.float64).reshape(-1, 7)
         mt = _c(gen.module_tracker, np.int32)
@@ -143,15 +150,46 @@ def evaluate(scene, gen, sweep, map_n: int, k: int, export_maps: bool = False,
                                         gen.n_mod, gen.n_cu, gen.n_cv, _p(cs), gen.n_sub, _p(ms),
                                         1 if gen.add_as_occluders else 0, _p(trk), trk.shape[0], _p(mt),
                                         _p(s), _p(dni), _p(dp), _p(dt), ns, map_n, k, _p(counts), _p(pw), _p(pr),
-                                        _p(en), _p(maps), _p(bits), threads)
+                                        _p(en), _p(maps), _p(bits), threads, _p(dio))
     else:
         out = L.oracle_evaluate(_p(xyz), xyz.shape[0], _p(tri), tri.shape[0], _p(org), _p(eu), _p(ev),
                                 gen.n_mod, gen.n_cu, gen.n_cv, _p(cs), gen.n_sub, _p(ms),
                                 1 if gen.add_as_occluders else 0, _p(s), _p(dni), _p(dp), _p(dt), ns,
-                                map_n, k, _p(counts), _p(pw), _p(pr), _p(en), _p(maps), _p(bits), threads)
+                                map_n, k, _p(counts), _p(pw), _p(pr), _p(en), _p(maps), _p(bits), threads,
+                                _p(dio))
     if out < 0:
         raise ValueError("oracle rejected its arguments")
     return OracleResult(counts, pw, pr, en, maps, bits, int(out))
+
+
+def _diode(d) -> Optional[np.ndarray]:
+    """Single-diode parameters as the C side takes them: Isc_ref, G_ref, I0, a, Rs, Rsh, Vb."""
+    if d is None:
+        return None
+    a = _c(d, np.float64).reshape(-1)
+    if a.shape[0] != 7:
+        raise ValueError("diode parameters: Isc_ref, G_ref, I0, a, Rs, Rsh, Vb")
+    return a
+
+
+def cell_voltage(d, G: float, I: float) -> float:
+    """Voltage of one cell of the single-diode model at irradiance G and current I."""
+    dd = _diode(d)
+    return float(lib().oracle_cell_voltage(_p(dd), float(G), float(I)))
+
+
+def string_voltage(d, g, sub_len, I: float) -> float:
+    """Voltage of a string (cell irradiances g, substring after substring, sub_len cells each)."""
+    dd, gg, sl = _diode(d), _c(g, np.float64), _c(sub_len, np.int32)
+    assert int(sl.sum()) == gg.shape[0]
+    return float(lib().oracle_string_voltage(_p(dd), _p(gg), _p(sl), sl.shape[0], float(I)))
+
+
+def string_mpp(d, g, sub_len) -> float:
+    """Maximum power of such a string under the single-diode model."""
+    dd, gg, sl = _diode(d), _c(g, np.float64), _c(sub_len, np.int32)
+    assert int(sl.sum()) == gg.shape[0]
+    return float(lib().oracle_string_mpp(_p(dd), _p(gg), _p(sl), sl.shape[0]))
 
 
 def view(scene, gen, sun, map_n: int, dni: float = 1000.0):

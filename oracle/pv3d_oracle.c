@@ -76,6 +76,7 @@ typedef struct {
     const int32_t* cell_sub; int32_t n_sub;
     const int32_t* mod_string; int32_t n_string;
     int32_t occluders;            /* 1: each module is also drawn as two triangles */
+    const double* diode;          /* single-diode cell parameters, or NULL: ideal strings */
 } or_problem;
 
 typedef struct {
@@ -327,7 +328,8 @@ static void raster_light_triangle(const double t[3][3], int32_t n, uint32_t* map
 /* ------------------------------------------------------------------------ */
 /* one sun position                                                         */
 /* ------------------------------------------------------------------------ */
-typedef struct { double* cap; int32_t* order; } or_scratch;
+/* per-thread scratch: cap [n_mod * n_cu * n_cv] doubles, sub_len [n_mod * n_sub] */
+typedef struct { double* cap; int32_t* sub_len; } or_scratch;
 
 static int cmp_desc(const void* a, const void* b) {
     double x = *(const double*)a, y = *(const double*)b;
@@ -376,6 +378,145 @@ static double generator_power(const or_problem* P, const double* beam, const uin
     return total;
 }
 
+/* ------------------------------------------------------------------------ */
+/* single-diode electrical model                                            */
+/* ------------------------------------------------------------------------ */
+/* Step 4 turns the geometric shading into power with a diode model of the
+ * cells and a model of the system, neither given in the paper. Reading taken
+ * for this model: every cell follows the five-parameter single-diode equation
+ *   I = Iph - I0 (exp((V + I Rs) / a) - 1) - (V + I Rs) / Rsh,
+ * with the photocurrent proportional to the cell's irradiance,
+ * Iph = Isc_ref G / G_ref, at a fixed cell temperature (a = n k T / q given).
+ * The cells of a substring are in series and its bypass diode holds the
+ * substring's voltage at no less than -Vb; substrings are in series in a
+ * string, and each string works at its own maximum power point.
+ * Parameters: d[0] Isc_ref (A), d[1] G_ref (W/m^2), d[2] I0 (A), d[3] a (V),
+ * d[4] Rs (ohm), d[5] Rsh (ohm), d[6] Vb (V). */
+#define OR_MPP_GRID 64       /* current grid of the maximum power search */
+#define OR_MPP_REFINE 40     /* golden-section steps around each grid maximum */
+
+/* Voltage of one cell carrying current I at irradiance G. With x = V + I Rs
+ * the equation reads f(x) = c - I0 exp(x / a) - x / Rsh = 0, c = Iph + I0 - I;
+ * f falls and is concave, so Newton's method started at a point where f <= 0
+ * goes down to the root without passing it. Such a start: x = Rsh c (there
+ * f = -I0 exp(x/a) < 0), and when c >= I0 also x = a ln(c / I0) (there
+ * f = -x / Rsh <= 0); the smaller of the two is taken. The iteration stops
+ * when a step no longer lowers x. */
+static double cell_voltage(const double* d, double G, double I) {
+    double iph = d[0] * G / d[1];
+    double c = iph + d[2] - I;
+    double x = d[5] * c;
+    if (c >= d[2]) {
+        double xl = d[3] * log(c / d[2]);
+        if (xl < x) x = xl;
+    }
+    for (int it = 0; it < 64; it++) {
+        double e = exp(x / d[3]);
+        double f = (c - d[2] * e) - x / d[5];
+        double fp = -(d[2] / d[3]) * e - 1.0 / d[5];
+        double xn = x - f / fp;
+        if (!(xn < x)) break;
+        x = xn;
+    }
+    return x - I * d[4];
+}
+
+/* String voltage at current I: g holds the irradiance of every cell of the
+ * string, substring after substring; sub_len the number of cells of each of
+ * its n_q substrings. */
+static double string_voltage(const double* d, const double* g, const int32_t* sub_len, int64_t n_q, double I) {
+    double v = 0.0;
+    int64_t c = 0;
+    for (int64_t q = 0; q < n_q; q++) {
+        double vs = 0.0;
+        for (int32_t i = 0; i < sub_len[q]; i++) vs += cell_voltage(d, g[c + i], I);
+        c += sub_len[q];
+        if (vs < -d[6]) vs = -d[6];
+        v += vs;
+    }
+    return v;
+}
+
+static double string_p(const double* d, const double* g, const int32_t* sub_len, int64_t n_q, double I) {
+    return I * string_voltage(d, g, sub_len, n_q, I);
+}
+
+/* Maximum power of one string over its currents [0, Imax], Imax the largest
+ * photocurrent of its cells (above it every cell is reverse-biased). The
+ * power is sampled at OR_MPP_GRID + 1 evenly spaced currents; around every
+ * sample that is not below its neighbours, a golden-section search over the
+ * two grid steps beside it refines the maximum. The largest value seen (and
+ * at least 0) is the string's power. */
+static double string_mpp(const double* d, const double* g, const int32_t* sub_len, int64_t n_q) {
+    int64_t n_c = 0;
+    for (int64_t q = 0; q < n_q; q++) n_c += sub_len[q];
+    double imax = 0.0;
+    for (int64_t c = 0; c < n_c; c++) {
+        double iph = d[0] * g[c] / d[1];
+        if (iph > imax) imax = iph;
+    }
+    if (!(imax > 0.0)) return 0.0;
+    double p[OR_MPP_GRID + 1];
+    for (int q = 0; q <= OR_MPP_GRID; q++)
+        p[q] = string_p(d, g, sub_len, n_q, imax * (double)q / (double)OR_MPP_GRID);
+    const double r = 0.6180339887498949;       /* (sqrt(5) - 1) / 2 */
+    double best = 0.0;
+    for (int q = 1; q <= OR_MPP_GRID; q++) {
+        if (!(p[q] >= p[q - 1]) || (q < OR_MPP_GRID && !(p[q] >= p[q + 1]))) continue;
+        if (p[q] > best) best = p[q];
+        double lo = imax * (double)(q - 1) / (double)OR_MPP_GRID;
+        double hi = imax * (double)(q < OR_MPP_GRID ? q + 1 : q) / (double)OR_MPP_GRID;
+        double xc = hi - r * (hi - lo), xd = lo + r * (hi - lo);
+        double fc = string_p(d, g, sub_len, n_q, xc), fd = string_p(d, g, sub_len, n_q, xd);
+        if (fc > best) best = fc;
+        if (fd > best) best = fd;
+        for (int it = 0; it < OR_MPP_REFINE; it++) {
+            if (fc >= fd) {
+                hi = xd; xd = xc; fd = fc;
+                xc = hi - r * (hi - lo);
+                fc = string_p(d, g, sub_len, n_q, xc);
+                if (fc > best) best = fc;
+            } else {
+                lo = xc; xc = xd; fc = fd;
+                xd = lo + r * (hi - lo);
+                fd = string_p(d, g, sub_len, n_q, xd);
+                if (fd > best) best = fd;
+            }
+        }
+    }
+    return best;
+}
+
+/* Generator power for one sun with the single-diode model: per string, the
+ * irradiance of each cell (beam on the module minus its shaded share, plus
+ * the diffuse), substring by substring in module order, then the string's
+ * maximum power; strings add up. g and sub_len are scratch of n_cells and
+ * n_mod * n_sub entries. */
+static double generator_power_diode(const or_problem* P, const double* beam, const uint32_t* counts,
+                                    int32_t k, double d_poa, double* g, int32_t* sub_len) {
+    int64_t cpm = (int64_t)P->n_cu * P->n_cv;
+    double total = 0.0;
+    for (int32_t st = 0; st < P->n_string; st++) {
+        int64_t nq = 0, nc = 0;
+        for (int64_t m = 0; m < P->n_mod; m++) {
+            if (P->mod_string[m] != st) continue;
+            for (int32_t q = 0; q < P->n_sub; q++) {
+                int32_t len = 0;
+                for (int64_t c = 0; c < cpm; c++) {
+                    if (P->cell_sub[c] != q) continue;
+                    uint32_t sh = counts ? counts[m * cpm + c] : 0u;
+                    double f = (double)sh / (double)(k * k);
+                    g[nc++] = beam[m] * (1.0 - f) + d_poa;
+                    len++;
+                }
+                sub_len[nq++] = len;
+            }
+        }
+        total += string_mpp(P->diode, g, sub_len, nq);
+    }
+    return total;
+}
+
 typedef struct {
     uint32_t* counts;      /* [n_cells] */
     uint32_t* bits;        /* [n_cells][words] or NULL */
@@ -386,7 +527,7 @@ typedef struct {
 
 static void eval_sun(const or_problem* P, v3 centre, double radius, const double* s_in, double dni,
                      double d_poa, int32_t n, int32_t k, or_sun_out* o, double* beam, int32_t* bias,
-                     double* caps) {
+                     or_scratch* sc) {
     int64_t cpm = (int64_t)P->n_cu * P->n_cv;
     int64_t nn = (int64_t)n * n;
     int32_t words = (k * k + 31) / 32;
@@ -473,8 +614,13 @@ static void eval_sun(const or_problem* P, v3 centre, double radius, const double
                 }
         }
     }
-    o->power = generator_power(P, beam, o->counts, k, d_poa, caps);
-    o->power_ref = generator_power(P, beam, NULL, k, d_poa, caps);
+    if (P->diode) {
+        o->power = generator_power_diode(P, beam, o->counts, k, d_poa, sc->cap, sc->sub_len);
+        o->power_ref = generator_power_diode(P, beam, NULL, k, d_poa, sc->cap, sc->sub_len);
+    } else {
+        o->power = generator_power(P, beam, o->counts, k, d_poa, sc->cap);
+        o->power_ref = generator_power(P, beam, NULL, k, d_poa, sc->cap);
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -598,6 +744,7 @@ static void fill_problem(or_problem* P, const double* xyz, int64_t n_vert, const
     P->org = org; P->eu = eu; P->ev = ev; P->n_mod = n_mod;
     P->n_cu = n_cu; P->n_cv = n_cv; P->cell_sub = cell_sub; P->n_sub = n_sub;
     P->mod_string = mod_string; P->occluders = occluders;
+    P->diode = NULL;
     int32_t ns = 0;
     for (int64_t m = 0; m < n_mod; m++)
         if (mod_string[m] + 1 > ns) ns = mod_string[m] + 1;
@@ -615,11 +762,12 @@ int64_t oracle_evaluate(const double* xyz, int64_t n_vert, const int32_t* tri, i
                         const double* sun_xyz, const double* dni, const double* d_poa,
                         const double* dt_h, int64_t n_sun, int32_t n, int32_t k,
                         uint32_t* counts, double* power, double* power_ref, double* energy,
-                        uint32_t* depth_maps, uint32_t* bits, int32_t threads) {
+                        uint32_t* depth_maps, uint32_t* bits, int32_t threads, const double* diode) {
     if (n < 16 || k < 1 || n_mod < 1) return -1;
     or_problem P;
     fill_problem(&P, xyz, n_vert, tri, n_tri, org, eu, ev, n_mod, n_cu, n_cv, cell_sub, n_sub,
                  mod_string, occluders);
+    P.diode = diode;
     v3 centre;
     double radius;
     scene_sphere(&P, &centre, &radius);
@@ -635,7 +783,9 @@ int64_t oracle_evaluate(const double* xyz, int64_t n_vert, const int32_t* tri, i
     {
         double* beam = (double*)malloc(sizeof(double) * (size_t)n_mod);
         int32_t* bias = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_mod);
-        double* caps = (double*)malloc(sizeof(double) * (size_t)(n_mod * n_sub));
+        or_scratch sc;
+        sc.cap = (double*)malloc(sizeof(double) * (size_t)cells);
+        sc.sub_len = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_mod * n_sub));
         uint32_t* own_map = depth_maps ? NULL : (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n * n);
 #pragma omp for schedule(dynamic, 1)
         for (int64_t t = 0; t < n_sun; t++) {
@@ -643,12 +793,12 @@ int64_t oracle_evaluate(const double* xyz, int64_t n_vert, const int32_t* tri, i
             o.counts = counts + t * cells;
             o.bits = bits ? bits + t * cells * words : NULL;
             o.map = depth_maps ? depth_maps + t * (int64_t)n * n : own_map;
-            eval_sun(&P, centre, radius, sun_xyz + 3 * t, dni[t], d_poa[t], n, k, &o, beam, bias, caps);
+            eval_sun(&P, centre, radius, sun_xyz + 3 * t, dni[t], d_poa[t], n, k, &o, beam, bias, &sc);
             power[t] = o.power;
             power_ref[t] = o.power_ref;
             outside += o.outside;
         }
-        free(beam); free(bias); free(caps); free(own_map);
+        free(beam); free(bias); free(sc.cap); free(sc.sub_len); free(own_map);
     }
     double e = 0.0, er = 0.0;
     for (int64_t t = 0; t < n_sun; t++) {
@@ -720,6 +870,19 @@ double oracle_string_power(const double* caps, int64_t n) {
     return p;
 }
 
+/* Single-diode model pieces (for pins): the voltage of one cell, and the
+ * maximum power of one string whose cells' irradiances g are given substring
+ * after substring (sub_len cells each, n_q substrings). d as above. */
+double oracle_cell_voltage(const double* d, double G, double I) { return cell_voltage(d, G, I); }
+
+double oracle_string_voltage(const double* d, const double* g, const int32_t* sub_len, int64_t n_q, double I) {
+    return string_voltage(d, g, sub_len, n_q, I);
+}
+
+double oracle_string_mpp(const double* d, const double* g, const int32_t* sub_len, int64_t n_q) {
+    return string_mpp(d, g, sub_len, n_q);
+}
+
 /* Rest-pose modules (org, eu, ev) posed for one sun: trk [n_trk][7] = kind,
  * pivot xyz, axis xyz; mod_trk [n_mod] the tracker of each module (-1 none). */
 void oracle_pose(const double* trk_in, int32_t n_trk, const int32_t* mod_trk, const double* org,
@@ -743,13 +906,14 @@ int64_t oracle_evaluate_tracked(const double* xyz, int64_t n_vert, const int32_t
                                 const double* sun_xyz, const double* dni, const double* d_poa,
                                 const double* dt_h, int64_t n_sun, int32_t n, int32_t k,
                                 uint32_t* counts, double* power, double* power_ref, double* energy,
-                                uint32_t* depth_maps, uint32_t* bits, int32_t threads) {
+                                uint32_t* depth_maps, uint32_t* bits, int32_t threads, const double* diode) {
     if (n < 16 || k < 1 || n_mod < 1 || n_trk < 0) return -1;
     for (int64_t m = 0; m < n_mod; m++)
         if (mod_trk[m] >= n_trk) return -1;
     or_problem P;
     fill_problem(&P, xyz, n_vert, tri, n_tri, org, eu, ev, n_mod, n_cu, n_cv, cell_sub, n_sub,
                  mod_string, occluders);
+    P.diode = diode;
     or_tracker* trk = (or_tracker*)malloc(sizeof(or_tracker) * (size_t)(n_trk > 0 ? n_trk : 1));
     read_trackers(trk_in, n_trk, trk);
     v3 centre;
@@ -767,7 +931,9 @@ int64_t oracle_evaluate_tracked(const double* xyz, int64_t n_vert, const int32_t
     {
         double* beam = (double*)malloc(sizeof(double) * (size_t)n_mod);
         int32_t* bias = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_mod);
-        double* caps = (double*)malloc(sizeof(double) * (size_t)(n_mod * n_sub));
+        or_scratch sc;
+        sc.cap = (double*)malloc(sizeof(double) * (size_t)cells);
+        sc.sub_len = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_mod * n_sub));
         double* pose = (double*)malloc(sizeof(double) * (size_t)(9 * n_mod));
         uint32_t* own_map = depth_maps ? NULL : (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n * n);
 #pragma omp for schedule(dynamic, 1)
@@ -786,12 +952,12 @@ int64_t oracle_evaluate_tracked(const double* xyz, int64_t n_vert, const int32_t
             o.counts = counts + t * cells;
             o.bits = bits ? bits + t * cells * words : NULL;
             o.map = depth_maps ? depth_maps + t * (int64_t)n * n : own_map;
-            eval_sun(&Ps, centre, radius, sun_xyz + 3 * t, dni[t], d_poa[t], n, k, &o, beam, bias, caps);
+            eval_sun(&Ps, centre, radius, sun_xyz + 3 * t, dni[t], d_poa[t], n, k, &o, beam, bias, &sc);
             power[t] = o.power;
             power_ref[t] = o.power_ref;
             outside += o.outside;
         }
-        free(beam); free(bias); free(caps); free(pose); free(own_map);
+        free(beam); free(bias); free(sc.cap); free(sc.sub_len); free(pose); free(own_map);
     }
     free(trk);
     double e = 0.0, er = 0.0;

@@ -120,6 +120,15 @@ struct TrackerDev {
     int32_t kind, pad;
 };
 
+// Single-diode cell model (Step 4's diode model, parameters given): the
+// photocurrent at irradiance G is isc * G / gref; a = n k T / q; rs, rsh the
+// series and shunt resistances; vb the bypass diode's forward voltage.
+// on = 0: ideal bypass-diode strings instead.
+struct DiodeDev {
+    double isc, gref, i0, a, rs, rsh, vb;
+    int32_t on, pad;
+};
+
 struct GenDev {
     const Module* mods;
     const Module* mods_sun;     // trackers: [n_sun][n_mod] modules posed per sun (nullptr: fixed modules)
@@ -128,6 +137,9 @@ struct GenDev {
     const int32_t* cell_sub;    // [n_cu*n_cv]
     const int32_t* str_start;   // [n_str + 1] CSR of modules per string
     const int32_t* str_mods;    // [n_mod]
+    const int32_t* sub_start;   // [n_sub + 1] CSR of the cells of each substring of a module
+    const int32_t* sub_cell;    // [n_cu*n_cv] cell indices, ascending within each substring
+    DiodeDev diode;
 };
 
 struct SceneDev {

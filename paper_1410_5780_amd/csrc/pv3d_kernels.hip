@@ -1934,6 +1934,208 @@ struct LossLds {
     int32_t chunk[2];                    // [first string, end string) of the chunk
 };
 
+// ---------------------------------------------------------------------------
+// Step 4 with the single-diode cell model: every cell follows
+//   I = Iph - I0 (exp((V + I Rs) / a) - 1) - (V + I Rs) / Rsh,  Iph = isc G / gref,
+// a substring's bypass diode keeps its voltage at -vb or above, substrings are
+// in series, and each string works at its maximum power point. One wave per
+// string; lanes take the string's substrings.
+// ---------------------------------------------------------------------------
+constexpr int kDiodeCells = 4096;     // shaded counts of one string staged per wave
+constexpr int kMppGrid = 64;          // current grid of the maximum power search
+constexpr int kMppRefine = 40;        // golden-section steps around each grid maximum
+
+struct DiodeLds {
+    uint16_t cnt[4][kDiodeCells];     // per wave: its string's counts, module by module, substring-major
+    double spow[kLossStrings];        // string powers of a chunk of strings
+};
+
+// Cell voltage at current I and irradiance G. In the diode voltage x = V + I Rs
+// the equation is f(x) = c - I0 exp(x / a) - x / Rsh = 0 with c = Iph + I0 - I;
+// f falls and is concave, so Newton's method from a point where f <= 0 moves
+// down to the root without passing it. Start: the smaller of Rsh c (where
+// f = -I0 exp(x / a)) and, when c >= I0, a ln(c / I0) (where f = -x / Rsh). The
+// iteration ends when a step no longer lowers x.
+__device__ double cell_voltage(const DiodeDev& d, double G, double I) {
+    const double iph = d.isc * G / d.gref;
+    const double c = iph + d.i0 - I;
+    double x = d.rsh * c;
+    if (c >= d.i0) {
+        const double xl = d.a * log(c / d.i0);
+        if (xl < x) x = xl;
+    }
+    for (int it = 0; it < 64; it++) {
+        const double e = exp(x / d.a);
+        const double f = (c - d.i0 * e) - x / d.rsh;
+        const double fp = -(d.i0 / d.a) * e - 1.0 / d.rsh;
+        const double xn = x - f / fp;
+        if (!(xn < x)) break;
+        x = xn;
+    }
+    return x - I * d.rs;
+}
+
+// Sum over the wave, the same value in every lane (pairs add commutatively).
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// One string of one sun, as one wave sees it.
+struct DiodeString {
+    const GenDev* g;
+    const double* beam_s;         // per-module beam of the sun
+    const uint32_t* counts_s;     // per-cell shaded counts (nullptr: none shaded)
+    const uint16_t* staged;       // the string's counts staged in LDS, or nullptr
+    double dp, kk;                // diffuse irradiance, samples per cell
+    int32_t p0, nq, cpm;          // first module of the string in str_mods, substrings, cells per module
+};
+
+// Shaded count of the i-th cell (in substring order) of the string's mi-th module.
+template <bool COHERENT>
+__device__ __forceinline__ int32_t diode_count(const DiodeString& S, int32_t mi, int32_t m, int32_t i) {
+    if (S.staged) return S.staged[mi * S.cpm + i];
+    if (!S.counts_s) return 0;
+    const uint32_t* p = S.counts_s + (int64_t)m * S.cpm + S.g->sub_cell[i];
+    return (int32_t)(COHERENT ? ld_dev(p) : *p);
+}
+
+// Voltage of substring q of the string at current I: its cells in order, one
+// solve per run of equal counts, clamped by the bypass diode.
+template <bool COHERENT>
+__device__ double sub_voltage(const DiodeString& S, int32_t q, double I) {
+    const GenDev& g = *S.g;
+    const int32_t mi = q / g.n_sub, sq = q % g.n_sub;
+    const int32_t m = g.str_mods[S.p0 + mi];
+    const double bm = S.beam_s[m];
+    double vs = 0.0, vc = 0.0;
+    int32_t prev = -1;
+    for (int32_t i = g.sub_start[sq]; i < g.sub_start[sq + 1]; i++) {
+        const int32_t cn = diode_count<COHERENT>(S, mi, m, i);
+        if (cn != prev) {
+            const double G = bm * (1.0 - (double)cn / S.kk) + S.dp;
+            vc = cell_voltage(g.diode, G, I);
+            prev = cn;
+        }
+        vs += vc;
+    }
+    return vs < -g.diode.vb ? -g.diode.vb : vs;
+}
+
+template <bool COHERENT>
+__device__ double string_power_at(const DiodeString& S, int lane, double I) {
+    double v = 0.0;
+    for (int32_t q = lane; q < S.nq; q += 64) v += sub_voltage<COHERENT>(S, q, I);
+    return I * wave_sum(v);
+}
+
+// Maximum power of the string over currents [0, Imax], Imax its largest cell
+// photocurrent: the power at kMppGrid + 1 evenly spaced currents, then a
+// golden-section search over the two grid steps around every sample that is
+// not below its neighbours; the largest value seen, at least 0. Every lane
+// holds the same powers, so the search's branches are uniform.
+template <bool COHERENT>
+__device__ double string_mpp_wave(const DiodeString& S, int lane) {
+    const GenDev& g = *S.g;
+    const DiodeDev& d = g.diode;
+    double imax = 0.0;
+    for (int32_t q = lane; q < S.nq; q += 64) {
+        const int32_t mi = q / g.n_sub, sq = q % g.n_sub;
+        const int32_t m = g.str_mods[S.p0 + mi];
+        const double bm = S.beam_s[m];
+        for (int32_t i = g.sub_start[sq]; i < g.sub_start[sq + 1]; i++) {
+            const int32_t cn = diode_count<COHERENT>(S, mi, m, i);
+            const double iph = d.isc * (bm * (1.0 - (double)cn / S.kk) + S.dp) / d.gref;
+            imax = fmax(imax, iph);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) imax = fmax(imax, __shfl_xor(imax, off, 64));
+    if (!(imax > 0.0)) return 0.0;
+    const double r = 0.6180339887498949;       // (sqrt(5) - 1) / 2
+    double best = 0.0;
+    double pm = string_power_at<COHERENT>(S, lane, imax * 0.0 / (double)kMppGrid);
+    double pc = string_power_at<COHERENT>(S, lane, imax * 1.0 / (double)kMppGrid);
+    for (int q = 1; q <= kMppGrid; q++) {
+        const double pn = q < kMppGrid ? string_power_at<COHERENT>(S, lane, imax * (double)(q + 1) / (double)kMppGrid)
+                                       : 0.0;
+        if (pc >= pm && (q == kMppGrid || pc >= pn)) {
+            if (pc > best) best = pc;
+            double lo = imax * (double)(q - 1) / (double)kMppGrid;
+            double hi = imax * (double)(q < kMppGrid ? q + 1 : q) / (double)kMppGrid;
+            double xc = hi - r * (hi - lo), xd = lo + r * (hi - lo);
+            double fc = string_power_at<COHERENT>(S, lane, xc), fd = string_power_at<COHERENT>(S, lane, xd);
+            if (fc > best) best = fc;
+            if (fd > best) best = fd;
+            for (int it = 0; it < kMppRefine; it++) {
+                if (fc >= fd) {
+                    hi = xd; xd = xc; fd = fc;
+                    xc = hi - r * (hi - lo);
+                    fc = string_power_at<COHERENT>(S, lane, xc);
+                    if (fc > best) best = fc;
+                } else {
+                    lo = xc; xc = xd; fc = fd;
+                    xd = lo + r * (hi - lo);
+                    fd = string_power_at<COHERENT>(S, lane, xd);
+                    if (fd > best) best = fd;
+                }
+            }
+        }
+        pm = pc;
+        pc = pn;
+    }
+    return best;
+}
+
+// One sun with the single-diode model: the shaded powers, then the unshaded
+// reference; per pass, strings in chunks of kLossStrings, a wave per string,
+// the string powers added in string order.
+template <bool COHERENT>
+__device__ void diode_loss_body(DiodeLds& L, const double* beam_s, const uint32_t* counts_s, double dp,
+                                const GenDev& g, int32_t k, double* power_s, double* power_ref_s) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int32_t cpm = g.n_cu * g.n_cv;
+    double tot[2] = {0.0, 0.0};
+    for (int pass = 0; pass < 2; pass++) {
+        for (int32_t st0 = 0; st0 < g.n_str; st0 += kLossStrings) {
+            const int32_t st1 = min(g.n_str, st0 + kLossStrings);
+            for (int32_t st = st0 + wv; st < st1; st += 4) {
+                DiodeString S;
+                S.g = &g;
+                S.beam_s = beam_s;
+                S.counts_s = pass == 0 ? counts_s : nullptr;
+                S.staged = nullptr;
+                S.dp = dp;
+                S.kk = (double)(k * k);
+                S.p0 = g.str_start[st];
+                S.cpm = cpm;
+                const int32_t nm = g.str_start[st + 1] - S.p0;
+                S.nq = nm * g.n_sub;
+                if (pass == 0 && nm * cpm <= kDiodeCells) {
+                    // each lane stages the cells of its own substrings, and reads only those
+                    uint16_t* dst = L.cnt[wv];
+                    for (int32_t q = lane; q < S.nq; q += 64) {
+                        const int32_t mi = q / g.n_sub, sq = q % g.n_sub;
+                        const int32_t m = g.str_mods[S.p0 + mi];
+                        for (int32_t i = g.sub_start[sq]; i < g.sub_start[sq + 1]; i++)
+                            dst[mi * cpm + i] = (uint16_t)diode_count<COHERENT>(S, mi, m, i);
+                    }
+                    S.staged = dst;
+                }
+                const double p = string_mpp_wave<COHERENT>(S, lane);
+                if (lane == 0) L.spow[st - st0] = p;
+            }
+            __syncthreads();
+            if (tid == 0)
+                for (int32_t st = st0; st < st1; st++) tot[pass] += L.spow[st - st0];
+            __syncthreads();
+        }
+    }
+    if (tid == 0) {
+        *power_s = tot[0];
+        *power_ref_s = tot[1];
+    }
+}
+
 // One sun: sun3 its unit vector, beam_s its per-module beam, counts_s its
 // per-cell shaded counts, dp its diffuse irradiance. Strings go in chunks
 // (consecutive whole strings, at most kMaxSubPerString substrings): every
@@ -1945,6 +2147,11 @@ __device__ void loss_body(LossLds& L, const double* sun3, const double* beam_s, 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (!(sun3[2] > 0.0)) {
         if (tid == 0) { *power_s = 0.0; *power_ref_s = 0.0; }
+        return;
+    }
+    if (g.diode.on) {
+        static_assert(sizeof(DiodeLds) <= sizeof(LossLds), "the diode model works in the loss stage's LDS");
+        diode_loss_body<COHERENT>(*reinterpret_cast<DiodeLds*>(&L), beam_s, counts_s, dp, g, k, power_s, power_ref_s);
         return;
     }
     const int32_t cpm = g.n_cu * g.n_cv;

@@ -55,7 +55,13 @@ struct Gen {
     TrackerDev* trk = nullptr;    // [n_trk] (trackers: modules turn with the sun)
     int32_t* mod_trk = nullptr;   // [n_mod] tracker of each module, -1 none
     int32_t n_trk = 0;
+    int32_t* sub_start = nullptr; // [n_sub + 1] CSR of the cells of each substring
+    int32_t* sub_cell = nullptr;  // [n_cu * n_cv]
+    DiodeDev diode{};             // electrical model (diode.on = 0: ideal strings)
 };
+
+// Frees the device arrays of a generator.
+void free_gen(Ctx* c, Gen& g);
 
 struct PathSizes {
     int32_t tile, ntx, n_tiles, large_tiles, words, mask_words;

@@ -366,6 +366,15 @@ SceneDev scene_dev(const Scene& sc) {
     return d;
 }
 
+void free_gen(Ctx* c, Gen& g) {
+    void** all[] = {(void**)&g.mods, (void**)&g.cell_sub, (void**)&g.str_start, (void**)&g.str_mods,
+                    (void**)&g.trk, (void**)&g.mod_trk, (void**)&g.sub_start, (void**)&g.sub_cell};
+    for (void** p : all) {
+        c->dfree(*p);
+        *p = nullptr;
+    }
+}
+
 GenDev gen_dev(const Gen& g) {
     GenDev d;
     d.mods = g.mods;
@@ -379,6 +388,9 @@ GenDev gen_dev(const Gen& g) {
     d.cell_sub = g.cell_sub;
     d.str_start = g.str_start;
     d.str_mods = g.str_mods;
+    d.sub_start = g.sub_start;
+    d.sub_cell = g.sub_cell;
+    d.diode = g.diode;
     return d;
 }
 
@@ -600,14 +612,7 @@ void pv3d_destroy(pv3d_ctx* ctx) {
         ctx->dfree(kv.second.tri);
         if (kv.second.cbox) ctx->dfree(kv.second.cbox);
     }
-    for (auto& kv : ctx->gens) {
-        ctx->dfree(kv.second.mods);
-        ctx->dfree(kv.second.cell_sub);
-        ctx->dfree(kv.second.str_start);
-        ctx->dfree(kv.second.str_mods);
-        if (kv.second.trk) ctx->dfree(kv.second.trk);
-        if (kv.second.mod_trk) ctx->dfree(kv.second.mod_trk);
-    }
+    for (auto& kv : ctx->gens) free_gen(ctx, kv.second);
     ctx->w.release_all(ctx);
     ctx->release_batched();
     if (ctx->staging) (void)hipHostFree(ctx->staging);
@@ -707,6 +712,11 @@ pv3d_status pv3d_scene_release(pv3d_ctx* ctx, uint64_t scene) {
     ctx->scenes.erase(it);
     return PV3D_OK;
 }
+
+static pv3d_status define_upload(pv3d_ctx* ctx, Gen& g, const std::vector<Module>& hm, const int32_t* cell_substring,
+                                 const std::vector<int32_t>& start, const std::vector<int32_t>& order,
+                                 const std::vector<int32_t>& sub_start, const std::vector<int32_t>& sub_cell,
+                                 const pv3d_tracker* trackers, int32_t n_trk, const int32_t* module_tracker);
 
 static pv3d_status define_generator(pv3d_ctx* ctx, const pv3d_module* mods, int64_t n_mod,
                                    const int32_t* cell_substring, int32_t n_sub, const int32_t* module_string,
@@ -827,16 +837,50 @@ static pv3d_status define_generator(pv3d_ctx* ctx, const pv3d_module* mods, int6
     g.n_sub = n_sub;
     g.n_str = n_str;
     g.occluders = add_as_occluders ? 1 : 0;
+    // cells of each substring, ascending (the order the string model adds them in)
+    const int32_t cpm = n_cu * n_cv;
+    std::vector<int32_t> sub_start((size_t)n_sub + 1, 0), sub_cell((size_t)cpm);
+    for (int32_t c = 0; c < cpm; c++) sub_start[(size_t)cell_substring[c] + 1]++;
+    for (int32_t q = 0; q < n_sub; q++) sub_start[(size_t)q + 1] += sub_start[(size_t)q];
+    {
+        std::vector<int32_t> cur(sub_start.begin(), sub_start.end() - 1);
+        for (int32_t c = 0; c < cpm; c++) sub_cell[(size_t)cur[(size_t)cell_substring[c]]++] = c;
+    }
+    pv3d_status st = define_upload(ctx, g, hm, cell_substring, start, order, sub_start, sub_cell, trackers, n_trk,
+                                   module_tracker);
+    if (st) {
+        free_gen(ctx, g);
+        return st;
+    }
+    uint64_t h = ++ctx->next_handle;
+    ctx->gens[h] = g;
+    *gen_out = h;
+    return PV3D_OK;
+}
+
+// Device arrays of a generator being defined (freed by the caller on failure).
+static pv3d_status define_upload(pv3d_ctx* ctx, Gen& g, const std::vector<Module>& hm, const int32_t* cell_substring,
+                                 const std::vector<int32_t>& start, const std::vector<int32_t>& order,
+                                 const std::vector<int32_t>& sub_start, const std::vector<int32_t>& sub_cell,
+                                 const pv3d_tracker* trackers, int32_t n_trk, const int32_t* module_tracker) {
+    const int64_t n_mod = g.n_mod;
+    const int32_t n_cu = g.n_cu, n_cv = g.n_cv, n_str = g.n_str, n_sub = g.n_sub;
     pv3d_status st;
     if ((st = ctx->dalloc((void**)&g.mods, sizeof(Module) * (size_t)n_mod, "modules"))) return st;
     if ((st = ctx->dalloc((void**)&g.cell_sub, 4 * (size_t)(n_cu * n_cv), "cell map"))) return st;
     if ((st = ctx->dalloc((void**)&g.str_start, 4 * (size_t)(n_str + 1), "string starts"))) return st;
     if ((st = ctx->dalloc((void**)&g.str_mods, 4 * (size_t)n_mod, "string modules"))) return st;
+    if ((st = ctx->dalloc((void**)&g.sub_start, 4 * (size_t)(n_sub + 1), "substring starts"))) return st;
+    if ((st = ctx->dalloc((void**)&g.sub_cell, 4 * (size_t)(n_cu * n_cv), "substring cells"))) return st;
     hipError_t e;
     if ((e = hipMemcpy(g.mods, hm.data(), sizeof(Module) * (size_t)n_mod, hipMemcpyHostToDevice))) return hip_fail(e, "copy modules");
     if ((e = hipMemcpy(g.cell_sub, cell_substring, 4 * (size_t)(n_cu * n_cv), hipMemcpyHostToDevice))) return hip_fail(e, "copy cell map");
     if ((e = hipMemcpy(g.str_start, start.data(), 4 * (size_t)(n_str + 1), hipMemcpyHostToDevice))) return hip_fail(e, "copy strings");
     if ((e = hipMemcpy(g.str_mods, order.data(), 4 * (size_t)n_mod, hipMemcpyHostToDevice))) return hip_fail(e, "copy strings");
+    if ((e = hipMemcpy(g.sub_start, sub_start.data(), 4 * (size_t)(n_sub + 1), hipMemcpyHostToDevice)))
+        return hip_fail(e, "copy substrings");
+    if ((e = hipMemcpy(g.sub_cell, sub_cell.data(), 4 * (size_t)(n_cu * n_cv), hipMemcpyHostToDevice)))
+        return hip_fail(e, "copy substrings");
     if (n_trk > 0) {
         std::vector<TrackerDev> td((size_t)n_trk);
         for (int32_t t = 0; t < n_trk; t++) {
@@ -855,9 +899,6 @@ static pv3d_status define_generator(pv3d_ctx* ctx, const pv3d_module* mods, int6
             return hip_fail(e, "copy module trackers");
         g.n_trk = n_trk;
     }
-    uint64_t h = ++ctx->next_handle;
-    ctx->gens[h] = g;
-    *gen_out = h;
     return PV3D_OK;
 }
 
@@ -877,6 +918,33 @@ pv3d_status pv3d_generator_define_tracked(pv3d_ctx* ctx, const pv3d_module* mods
                             n_tracker, module_tracker, gen_out);
 }
 
+pv3d_status pv3d_generator_set_diode(pv3d_ctx* ctx, uint64_t gen, const pv3d_diode* d) {
+    if (!ctx) return fail(PV3D_EINVAL, "null context");
+    DiodeDev dd{};
+    if (d) {
+        const double v[7] = {d->isc_ref, d->g_ref, d->i0, d->a, d->rs, d->rsh, d->v_bypass};
+        for (double x : v)
+            if (!std::isfinite(x)) return fail(PV3D_EINVAL, "diode parameters must be finite");
+        if (!(d->isc_ref > 0.0) || !(d->g_ref > 0.0) || !(d->i0 > 0.0) || !(d->a > 0.0) || !(d->rs >= 0.0) ||
+            !(d->rsh > 0.0) || !(d->v_bypass >= 0.0))
+            return fail(PV3D_EINVAL, "diode parameters out of range (isc_ref, g_ref, i0, a, rsh > 0; rs, v_bypass >= 0)");
+        dd.isc = d->isc_ref;
+        dd.gref = d->g_ref;
+        dd.i0 = d->i0;
+        dd.a = d->a;
+        dd.rs = d->rs;
+        dd.rsh = d->rsh;
+        dd.vb = d->v_bypass;
+        dd.on = 1;
+    }
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->gens.find(gen);
+    if (it == ctx->gens.end()) return fail(PV3D_ENOENT, "unknown generator %llu", (unsigned long long)gen);
+    if (ctx->gen_in_use(gen)) return fail(PV3D_EBUSY, "generator %llu is used by a running job", (unsigned long long)gen);
+    it->second.diode = dd;
+    return PV3D_OK;
+}
+
 pv3d_status pv3d_generator_release(pv3d_ctx* ctx, uint64_t gen) {
     if (!ctx) return fail(PV3D_EINVAL, "null context");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
@@ -885,12 +953,7 @@ pv3d_status pv3d_generator_release(pv3d_ctx* ctx, uint64_t gen) {
     if (ctx->gen_in_use(gen)) return fail(PV3D_EBUSY, "generator %llu is used by a running job", (unsigned long long)gen);
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    ctx->dfree(it->second.mods);
-    ctx->dfree(it->second.cell_sub);
-    ctx->dfree(it->second.str_start);
-    ctx->dfree(it->second.str_mods);
-    if (it->second.trk) ctx->dfree(it->second.trk);
-    if (it->second.mod_trk) ctx->dfree(it->second.mod_trk);
+    free_gen(ctx, it->second);
     ctx->gens.erase(it);
     return PV3D_OK;
 }

@@ -36,6 +36,11 @@ class Tracker(ctypes.Structure):
     _fields_ = [("kind", _i32), ("reserved", _i32), ("pivot", _f64 * 3), ("axis", _f64 * 3)]
 
 
+class Diode(ctypes.Structure):
+    _fields_ = [("isc_ref", _f64), ("g_ref", _f64), ("i0", _f64), ("a", _f64), ("rs", _f64), ("rsh", _f64),
+                ("v_bypass", _f64)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("map_n", _i32), ("k", _i32), ("flags", _u32), ("tile", _i32), ("bin_limit", _i32),
                 ("reserved", _i32)]
@@ -79,6 +84,7 @@ def lib():
         L.pv3d_generator_define_tracked.argtypes = [_P, _P, _i64, _P, _i32, _P, _i32, _P, _i32, _P,
                                                     ctypes.POINTER(_u64)]
         L.pv3d_generator_release.argtypes = [_P, _u64]
+        L.pv3d_generator_set_diode.argtypes = [_P, _u64, ctypes.POINTER(Diode)]
         L.pv3d_sun_cooper.argtypes = [_f64, _P, _P, _i64, _P]
         L.pv3d_evaluate.argtypes = [_P, _u64, _u64, _P, _P, _P, _P, _i64, ctypes.POINTER(Params),
                                     ctypes.POINTER(Outputs), _P]
@@ -94,7 +100,7 @@ def lib():
         L.pv3d_profile_enable.argtypes = [_P, _u32]
         L.pv3d_profile_read.argtypes = [_P, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
         for f in ("pv3d_profile_enable", "pv3d_profile_read", "pv3d_create", "pv3d_scene_load", "pv3d_scene_release", "pv3d_generator_define",
-                  "pv3d_generator_define_tracked", "pv3d_generator_release", "pv3d_sun_cooper", "pv3d_evaluate", "pv3d_evaluate_batched",
+                  "pv3d_generator_define_tracked", "pv3d_generator_release", "pv3d_generator_set_diode", "pv3d_sun_cooper", "pv3d_evaluate", "pv3d_evaluate_batched",
                   "pv3d_autotune", "pv3d_batch_stats", "pv3d_batch_limits", "pv3d_serve_stats",
                   "pv3d_submit", "pv3d_poll", "pv3d_wait", "pv3d_cancel"):
             getattr(L, f).restype = _i32
@@ -219,7 +225,7 @@ class Context:
         if trk is None:
             _check(lib().pv3d_generator_define(self.h, ctypes.addressof(mods), gen.n_mod, _ptr(cs), int(gen.n_sub),
                                                _ptr(ms), occ, ctypes.byref(h)), self.h)
-            return h.value
+            return self._with_diode(h.value, gen)
         t = np.asarray(trk, np.float64).reshape(-1, 7)
         arr = (Tracker * t.shape[0])()
         for i, row in enumerate(t):
@@ -231,7 +237,29 @@ class Context:
         _check(lib().pv3d_generator_define_tracked(self.h, ctypes.addressof(mods), gen.n_mod, _ptr(cs),
                                                    int(gen.n_sub), _ptr(ms), occ, ctypes.addressof(arr), t.shape[0],
                                                    _ptr(mt), ctypes.byref(h)), self.h)
-        return h.value
+        return self._with_diode(h.value, gen)
+
+    def _with_diode(self, h: int, gen) -> int:
+        d = getattr(gen, "diode", None)
+        if d is not None:
+            try:
+                self.set_diode(h, d)
+            except Pv3dError:
+                self.release_generator(h)
+                raise
+        return h
+
+    def set_diode(self, gen_h: int, d):
+        """Single-diode cell model for the generator: d = (Isc_ref, G_ref, I0, a, Rs, Rsh, Vb), or None
+        for ideal bypass-diode strings."""
+        if d is None:
+            _check(lib().pv3d_generator_set_diode(self.h, gen_h, None), self.h)
+            return
+        v = [float(x) for x in np.asarray(d, np.float64).reshape(-1)]
+        if len(v) != 7:
+            raise ValueError("diode parameters: Isc_ref, G_ref, I0, a, Rs, Rsh, Vb")
+        dd = Diode(*v)
+        _check(lib().pv3d_generator_set_diode(self.h, gen_h, ctypes.byref(dd)), self.h)
 
     def release_generator(self, h: int):
         _check(lib().pv3d_generator_release(self.h, h), self.h)

@@ -29,6 +29,11 @@ MOD_W = N_CU * CELL     # 0.936 m
 MOD_L = N_CV * CELL     # 1.56 m
 LAT_DEG = 40.4
 
+# A 156 mm monocrystalline cell at 25 C for the single-diode model: Isc 9.0 A at
+# 1000 W/m^2, open-circuit voltage about 0.63 V (ideality 1.2, kT/q 25.693 mV),
+# Rs 4 mOhm, Rsh 15 Ohm; Schottky bypass diodes at 0.4 V.
+DIODE_CELL = np.array([9.0, 1000.0, 1.2e-8, 1.2 * 0.025693, 0.004, 15.0, 0.4])
+
 
 # --------------------------------------------------------------------------
 # containers
@@ -72,6 +77,10 @@ class Generator:
     # [M] the tracker of each module, -1 for none.
     trackers: Optional[np.ndarray] = None
     module_tracker: Optional[np.ndarray] = None
+    # electrical model: None for ideal bypass-diode strings, else the single-diode
+    # cell parameters [7] = Isc_ref (A), G_ref (W/m^2), I0 (A), a = n k T / q (V),
+    # Rs (ohm), Rsh (ohm) and the bypass diode's forward voltage Vb (V)
+    diode: Optional[np.ndarray] = None
 
     @property
     def n_mod(self) -> int:

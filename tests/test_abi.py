@@ -31,7 +31,7 @@ def test_header_declares_the_boundary():
     for want in ("pv3d_create", "pv3d_destroy", "pv3d_last_error", "pv3d_scene_load", "pv3d_scene_release",
                  "pv3d_generator_define", "pv3d_generator_release", "pv3d_sun_cooper", "pv3d_evaluate",
                  "pv3d_evaluate_batched", "pv3d_autotune", "pv3d_batch_stats", "pv3d_submit", "pv3d_poll",
-                 "pv3d_wait", "pv3d_cancel", "pv3d_generator_define_tracked"):
+                 "pv3d_wait", "pv3d_cancel", "pv3d_generator_define_tracked", "pv3d_generator_set_diode"):
         assert want in names
 
 
@@ -47,6 +47,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(pv3d.Outputs) == 56
     assert ctypes.sizeof(pv3d.Job) == 136
     assert ctypes.sizeof(pv3d.Tracker) == 56
+    assert ctypes.sizeof(pv3d.Diode) == 56
 
 
 def test_sun_helper_matches_input_generator(lib):

@@ -7,6 +7,7 @@ import pytest
 
 from oracle import oracle as O
 from tests import test_oracle_pins as pins
+from tests import test_oracle_diode as dpins
 from tests import test_oracle_trackers as tpins
 
 SRC = open(O.SRC).read()
@@ -36,6 +37,14 @@ MUTANTS = {
                                      "o = add3(T->p, in_frame(dot3(r, u0), dot3(r, v0), 0.0, u, v, n));"),
     "pose_edges_left_at_rest": ("U = in_frame(dot3(U, u0), dot3(U, v0), dot3(U, n0), u, v, n);", ""),
     "tracked_sphere_ignores_reach": ("OR_GROW(mk(trk[t].p.x + r, trk[t].p.y + r, trk[t].p.z + r));", ""),
+    "diode_series_resistance_sign": ("return x - I * d[4];", "return x + I * d[4];"),
+    "diode_shunt_dropped": ("double f = (c - d[2] * e) - x / d[5];", "double f = c - d[2] * e;"),
+    "diode_photocurrent_unscaled": ("double iph = d[0] * G / d[1];", "double iph = d[0];"),
+    "bypass_diode_missing": ("if (vs < -d[6]) vs = -d[6];", ""),
+    "mpp_not_refined": ("for (int it = 0; it < OR_MPP_REFINE; it++) {", "for (int it = 0; it < 0; it++) {"),
+    "mpp_first_maximum_only": ("        if (!(p[q] >= p[q - 1]) || (q < OR_MPP_GRID && !(p[q] >= p[q + 1]))) continue;",
+                               "        if (best > 0.0) break;\n"
+                               "        if (!(p[q] >= p[q - 1]) || (q < OR_MPP_GRID && !(p[q] >= p[q + 1]))) continue;"),
 }
 
 PINS = [
@@ -57,6 +66,10 @@ PINS = [
     (tpins.test_one_axis_tracker_faces_the_sun_as_its_axis_allows, {"axis": (0.6, -0.8, 0.0)}),
     (tpins.test_lone_tracker_is_never_shaded, {"kind": 2}),
     (tpins.test_tracker_shadow_agrees_with_ray_casting_outside_band, {"kind": 2}),
+    (dpins.test_cell_voltage_matches_lambert_w, {"G": 700.0}),
+    (dpins.test_uniform_string_is_cells_times_cell_maximum, {"G": 800.0}),
+    (dpins.test_partial_shading_matches_brute_force, {"case": "one_shaded_substring"}),
+    (dpins.test_partial_shading_matches_brute_force, {"case": "two_maxima_later_higher"}),
 ]
 
 
