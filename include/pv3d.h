@@ -227,6 +227,30 @@ pv3d_status pv3d_evaluate(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const dou
                           int64_t n_sun, const pv3d_params* params, pv3d_outputs* out,
                           void* hip_stream);
 
+/* Diffuse shading (Sec. 4: obstacles also hide part of the diffuse sky, which
+ * the paper's evaluation leaves out). An isotropic sky is seen through n_dir
+ * fixed directions above the horizon, each standing for an equal share of it
+ * (dirs: [n_dir][3] unit vectors with z > 0, host memory). Every direction is
+ * evaluated as a sun of unit beam with params (the same picture and depth
+ * test; export flags are ignored), and a cell's sky view factor is
+ *   svf = sum_j w_j (1 - shaded_j / k^2) / sum_j w_j,  w_j = max(0, n . s_j),
+ * summed in direction order, n the module's front normal; 1 when no
+ * direction faces the module. svf_out: [n_cells] host memory. The call is
+ * synchronous and works on the context stream. EINVAL: a direction not above
+ * the horizon or not of unit length, bad params, a tracked generator (its
+ * view of the sky changes with its pose); ENOENT: bad handle; ENOMEM. */
+pv3d_status pv3d_sky_view(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const double* dirs, int64_t n_dir,
+                          const pv3d_params* params, double* svf_out);
+
+/* Attach per-cell sky view factors (svf: [n_cells] host memory, each in
+ * [0, 1], copied) to a generator: from then on a cell's diffuse irradiance in
+ * the shaded power is d_poa * svf[cell]; the reference power keeps the whole
+ * sky. svf = NULL detaches them. Applies to evaluations started after the
+ * call (per-sun, batched and serving). EINVAL: a value outside [0, 1], a
+ * tracked generator; ENOENT: unknown generator; EBUSY: a running serving job
+ * reads the generator. */
+pv3d_status pv3d_generator_set_sky(pv3d_ctx* ctx, uint64_t gen, const double* svf);
+
 /* One job = one (scene, generator, sweep) evaluation. Its input arrays must
  * stay valid until the call that takes the job returns; its outputs until the
  * job completes. */

@@ -40,7 +40,9 @@ def _bind(path: str):
     i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     L.oracle_evaluate.restype = i64
     L.oracle_evaluate.argtypes = [P, i64, P, i64, P, P, P, i64, i32, i32, P, i32, P, i32,
-                                  P, P, P, P, i64, i32, i32, P, P, P, P, P, P, i32, P]
+                                  P, P, P, P, i64, i32, i32, P, P, P, P, P, P, i32, P, P]
+    L.oracle_sky_view.restype = i64
+    L.oracle_sky_view.argtypes = [P, i64, P, i64, P, P, P, i64, i32, i32, P, i32, P, i32, P, i64, i32, i32, P, i32]
     L.oracle_view.restype = None
     L.oracle_view.argtypes = [P, i64, P, P, P, i64, P, f64, i32, P, P, P]
     L.oracle_raster.restype = None
@@ -49,7 +51,7 @@ def _bind(path: str):
     L.oracle_string_power.argtypes = [P, i64]
     L.oracle_evaluate_tracked.restype = i64
     L.oracle_evaluate_tracked.argtypes = [P, i64, P, i64, P, P, P, i64, i32, i32, P, i32, P, i32, P, i32, P,
-                                          P, P, P, P, i64, i32, i32, P, P, P, P, P, P, i32, P]
+                                          P, P, P, P, i64, i32, i32, P, P, P, P, P, P, i32, P, P]
     L.oracle_pose.restype = None
     L.oracle_pose.argtypes = [P, i32, P, P, P, P, i64, P, P, P, P]
     L.oracle_cell_voltage.restype = f64
@@ -143,6 +145,10 @@ def evaluate(scene, gen, sweep, map_n: int, k: int, export_maps: bool = False,
     words = (k * k + 31) // 32
     bits = np.zeros((ns, cells, words), np.uint32) if export_bits else None
     dio = _diode(getattr(gen, "diode", None))
+    svf = getattr(gen, "sky_view", None)
+    if svf is not None:
+        svf = _c(svf, np.float64).reshape(-1)
+        assert svf.shape[0] == gen.n_cells
     if getattr(gen, "trackers", None) is not None:
         trk = _c(gen.trackers, np.float64).reshape(-1, 7)
         mt = _c(gen.module_tracker, np.int32)
@@ -150,16 +156,34 @@ def evaluate(scene, gen, sweep, map_n: int, k: int, export_maps: bool = False,
                                         gen.n_mod, gen.n_cu, gen.n_cv, _p(cs), gen.n_sub, _p(ms),
                                         1 if gen.add_as_occluders else 0, _p(trk), trk.shape[0], _p(mt),
                                         _p(s), _p(dni), _p(dp), _p(dt), ns, map_n, k, _p(counts), _p(pw), _p(pr),
-                                        _p(en), _p(maps), _p(bits), threads, _p(dio))
+                                        _p(en), _p(maps), _p(bits), threads, _p(dio), _p(svf))
     else:
         out = L.oracle_evaluate(_p(xyz), xyz.shape[0], _p(tri), tri.shape[0], _p(org), _p(eu), _p(ev),
                                 gen.n_mod, gen.n_cu, gen.n_cv, _p(cs), gen.n_sub, _p(ms),
                                 1 if gen.add_as_occluders else 0, _p(s), _p(dni), _p(dp), _p(dt), ns,
                                 map_n, k, _p(counts), _p(pw), _p(pr), _p(en), _p(maps), _p(bits), threads,
-                                _p(dio))
+                                _p(dio), _p(svf))
     if out < 0:
         raise ValueError("oracle rejected its arguments")
     return OracleResult(counts, pw, pr, en, maps, bits, int(out))
+
+
+def sky_view(scene, gen, dirs, map_n: int, k: int, threads: int = 0) -> np.ndarray:
+    """Per-cell sky view factors [n_cells] of a fixed generator over sky directions dirs [n, 3]."""
+    L = lib()
+    xyz = _c(scene.xyz, np.float64).reshape(-1, 3)
+    tri = _c(scene.tri, np.int32).reshape(-1, 3)
+    org, eu, ev = (_c(a, np.float64) for a in (gen.origin, gen.edge_u, gen.edge_v))
+    cs = _c(gen.cell_substring, np.int32)
+    ms = _c(gen.module_string, np.int32)
+    d = _c(dirs, np.float64).reshape(-1, 3)
+    out = np.zeros(gen.n_cells)
+    r = L.oracle_sky_view(_p(xyz), xyz.shape[0], _p(tri), tri.shape[0], _p(org), _p(eu), _p(ev), gen.n_mod,
+                          gen.n_cu, gen.n_cv, _p(cs), gen.n_sub, _p(ms), 1 if gen.add_as_occluders else 0, _p(d),
+                          d.shape[0], map_n, k, _p(out), threads)
+    if r != 0:
+        raise ValueError(f"oracle sky view: {r}")
+    return out
 
 
 def _diode(d) -> Optional[np.ndarray]:

@@ -32,6 +32,12 @@
  * the sun are evaluated with the modules posed anew for every sun (see the
  * tracker section below for the reading of the tracking law).
  *
+ * Electrical model (Step 4): ideal bypass-diode strings by default, or the
+ * single-diode cell model with bypass diodes and a maximum power point per
+ * string (see its section below). Diffuse shading (Sec. 4): per-cell sky view
+ * factors from fixed sky directions, each evaluated as a sun, scale each
+ * cell's diffuse (see the sky view section below).
+ *
  * Parallelism: sun positions are independent, so the driver runs one sun per
  * OpenMP thread; the work inside one sun is plain sequential loops.
  */
@@ -77,6 +83,7 @@ typedef struct {
     const int32_t* mod_string; int32_t n_string;
     int32_t occluders;            /* 1: each module is also drawn as two triangles */
     const double* diode;          /* single-diode cell parameters, or NULL: ideal strings */
+    const double* svf;            /* [n_mod * n_cu * n_cv] share of the diffuse each cell gets, or NULL: all */
 } or_problem;
 
 typedef struct {
@@ -367,7 +374,8 @@ static double generator_power(const or_problem* P, const double* beam, const uin
                     if (P->cell_sub[c] != q) continue;
                     uint32_t sh = counts ? counts[m * cpm + c] : 0u;
                     double f = (double)sh / (double)(k * k);
-                    double g = beam[m] * (1.0 - f) + d_poa;
+                    double sky = counts && P->svf ? P->svf[m * cpm + c] : 1.0;   /* reference: whole sky */
+                    double g = beam[m] * (1.0 - f) + d_poa * sky;
                     if (g < cmin) cmin = g;
                 }
                 caps[nc++] = cmin;
@@ -506,7 +514,8 @@ static double generator_power_diode(const or_problem* P, const double* beam, con
                     if (P->cell_sub[c] != q) continue;
                     uint32_t sh = counts ? counts[m * cpm + c] : 0u;
                     double f = (double)sh / (double)(k * k);
-                    g[nc++] = beam[m] * (1.0 - f) + d_poa;
+                    double sky = counts && P->svf ? P->svf[m * cpm + c] : 1.0;   /* reference: whole sky */
+                    g[nc++] = beam[m] * (1.0 - f) + d_poa * sky;
                     len++;
                 }
                 sub_len[nq++] = len;
@@ -745,6 +754,7 @@ static void fill_problem(or_problem* P, const double* xyz, int64_t n_vert, const
     P->n_cu = n_cu; P->n_cv = n_cv; P->cell_sub = cell_sub; P->n_sub = n_sub;
     P->mod_string = mod_string; P->occluders = occluders;
     P->diode = NULL;
+    P->svf = NULL;
     int32_t ns = 0;
     for (int64_t m = 0; m < n_mod; m++)
         if (mod_string[m] + 1 > ns) ns = mod_string[m] + 1;
@@ -753,8 +763,10 @@ static void fill_problem(or_problem* P, const double* xyz, int64_t n_vert, const
 
 /* Whole sweep. counts [n_sun][n_cells]; power, power_ref [n_sun]; energy[2] =
  * (sum P dt, sum P_ref dt) in sun order. depth_maps ([n_sun][n][n]) and bits
- * ([n_sun][n_cells][ceil(k*k/32)]) may be NULL. Returns the number of samples
- * that fell outside the map (0 when the window is right), or -1 on bad args. */
+ * ([n_sun][n_cells][ceil(k*k/32)]) may be NULL. diode: single-diode cell
+ * parameters (NULL: ideal strings); svf: [n_cells] sky view factors scaling
+ * each cell's diffuse (NULL: 1). Returns the number of samples that fell
+ * outside the map (0 when the window is right), or -1 on bad args. */
 int64_t oracle_evaluate(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t n_tri,
                         const double* org, const double* eu, const double* ev, int64_t n_mod,
                         int32_t n_cu, int32_t n_cv, const int32_t* cell_sub, int32_t n_sub,
@@ -762,12 +774,14 @@ int64_t oracle_evaluate(const double* xyz, int64_t n_vert, const int32_t* tri, i
                         const double* sun_xyz, const double* dni, const double* d_poa,
                         const double* dt_h, int64_t n_sun, int32_t n, int32_t k,
                         uint32_t* counts, double* power, double* power_ref, double* energy,
-                        uint32_t* depth_maps, uint32_t* bits, int32_t threads, const double* diode) {
+                        uint32_t* depth_maps, uint32_t* bits, int32_t threads, const double* diode,
+                        const double* svf) {
     if (n < 16 || k < 1 || n_mod < 1) return -1;
     or_problem P;
     fill_problem(&P, xyz, n_vert, tri, n_tri, org, eu, ev, n_mod, n_cu, n_cv, cell_sub, n_sub,
                  mod_string, occluders);
     P.diode = diode;
+    P.svf = svf;
     v3 centre;
     double radius;
     scene_sphere(&P, &centre, &radius);
@@ -808,6 +822,61 @@ int64_t oracle_evaluate(const double* xyz, int64_t n_vert, const int32_t* tri, i
     energy[0] = e;
     energy[1] = er;
     return outside;
+}
+
+/* ------------------------------------------------------------------------ */
+/* diffuse shading: sky view factors                                        */
+/* ------------------------------------------------------------------------ */
+/* The paper's evaluation removes only the beam from shaded areas and notes
+ * that obstacles also hide part of the diffuse sky (Sec. 4). Reading taken:
+ * an isotropic sky seen through a fixed set of directions s_j above the
+ * horizon, each standing for an equal share of it. A sample sees direction j
+ * when the depth test from s_j finds it lit. A cell's sky view factor is
+ *   svf = sum_j w_j (1 - shaded_j / k^2) / sum_j w_j,  w_j = max(0, n . s_j),
+ * n the module's front normal, summed in direction order; 1 when no direction
+ * lies in front of the module. The diffuse a cell receives is then
+ * d_poa * svf. Every direction is evaluated as a sun of unit beam: the same
+ * view, depth picture and test. dirs: [n_dir][3] unit vectors with z > 0.
+ * svf_out: [n_cells]. Returns the samples that fell outside a map, or -1. */
+int64_t oracle_sky_view(const double* xyz, int64_t n_vert, const int32_t* tri, int64_t n_tri,
+                        const double* org, const double* eu, const double* ev, int64_t n_mod,
+                        int32_t n_cu, int32_t n_cv, const int32_t* cell_sub, int32_t n_sub,
+                        const int32_t* mod_string, int32_t occluders, const double* dirs, int64_t n_dir,
+                        int32_t n, int32_t k, double* svf_out, int32_t threads) {
+    if (n < 16 || k < 1 || n_mod < 1 || n_dir < 1) return -1;
+    for (int64_t j = 0; j < n_dir; j++)
+        if (!(dirs[3 * j + 2] > 0.0)) return -1;
+    int64_t cells = n_mod * (int64_t)n_cu * n_cv;
+    uint32_t* counts = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(cells * n_dir));
+    double* in = (double*)malloc(sizeof(double) * (size_t)n_dir * 3);   /* beam 1, no diffuse, no weight */
+    for (int64_t j = 0; j < n_dir; j++) { in[j] = 1.0; in[n_dir + j] = 0.0; in[2 * n_dir + j] = 0.0; }
+    double* pw = (double*)malloc(sizeof(double) * (size_t)n_dir * 2);
+    double en[2];
+    int64_t out = oracle_evaluate(xyz, n_vert, tri, n_tri, org, eu, ev, n_mod, n_cu, n_cv, cell_sub, n_sub,
+                                  mod_string, occluders, dirs, in, in + n_dir, in + 2 * n_dir, n_dir, n, k,
+                                  counts, pw, pw + n_dir, en, NULL, NULL, threads, NULL, NULL);
+    if (out >= 0) {
+        or_problem P;
+        fill_problem(&P, xyz, n_vert, tri, n_tri, org, eu, ev, n_mod, n_cu, n_cv, cell_sub, n_sub,
+                     mod_string, occluders);
+        int64_t cpm = (int64_t)n_cu * n_cv;
+        for (int64_t m = 0; m < n_mod; m++) {
+            v3 nh = unit_normal(&P, m);
+            for (int64_t c = 0; c < cpm; c++) {
+                double num = 0.0, den = 0.0;
+                for (int64_t j = 0; j < n_dir; j++) {
+                    double w = dot3(nh, ld3(dirs + 3 * j));
+                    if (!(w > 0.0)) continue;
+                    double f = (double)counts[j * cells + m * cpm + c] / (double)(k * k);
+                    num += w * (1.0 - f);
+                    den += w;
+                }
+                svf_out[m * cpm + c] = den > 0.0 ? num / den : 1.0;
+            }
+        }
+    }
+    free(counts); free(in); free(pw);
+    return out;
 }
 
 /* View and module terms of one sun, for the tests' brute-force comparison.
@@ -906,7 +975,8 @@ int64_t oracle_evaluate_tracked(const double* xyz, int64_t n_vert, const int32_t
                                 const double* sun_xyz, const double* dni, const double* d_poa,
                                 const double* dt_h, int64_t n_sun, int32_t n, int32_t k,
                                 uint32_t* counts, double* power, double* power_ref, double* energy,
-                                uint32_t* depth_maps, uint32_t* bits, int32_t threads, const double* diode) {
+                                uint32_t* depth_maps, uint32_t* bits, int32_t threads, const double* diode,
+                        const double* svf) {
     if (n < 16 || k < 1 || n_mod < 1 || n_trk < 0) return -1;
     for (int64_t m = 0; m < n_mod; m++)
         if (mod_trk[m] >= n_trk) return -1;
@@ -914,6 +984,7 @@ int64_t oracle_evaluate_tracked(const double* xyz, int64_t n_vert, const int32_t
     fill_problem(&P, xyz, n_vert, tri, n_tri, org, eu, ev, n_mod, n_cu, n_cv, cell_sub, n_sub,
                  mod_string, occluders);
     P.diode = diode;
+    P.svf = svf;
     or_tracker* trk = (or_tracker*)malloc(sizeof(or_tracker) * (size_t)(n_trk > 0 ? n_trk : 1));
     read_trackers(trk_in, n_trk, trk);
     v3 centre;

@@ -139,6 +139,7 @@ struct GenDev {
     const int32_t* str_mods;    // [n_mod]
     const int32_t* sub_start;   // [n_sub + 1] CSR of the cells of each substring of a module
     const int32_t* sub_cell;    // [n_cu*n_cv] cell indices, ascending within each substring
+    const double* svf;          // [n_cells] share of the diffuse sky each cell sees (nullptr: all of it)
     DiodeDev diode;
 };
 
@@ -296,6 +297,8 @@ hipError_t launch_loss(int64_t n_sun, const double* sun, const double* beam, con
                        double* power_ref, hipStream_t st);
 hipError_t launch_energy(int64_t n_sun, const double* power, const double* power_ref,
                          const double* dt, double* energy, hipStream_t st);
+hipError_t launch_svf(const Module* mods, int32_t cpm, int64_t n_cells, const double* dirs, int64_t n_dir,
+                      const uint32_t* counts, int32_t k, double* svf, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t persist_blocks_per_cu(int32_t* blocks);
 hipError_t launch_xcc_probe(uint32_t* mask, int32_t grid, hipStream_t st);

@@ -1987,6 +1987,7 @@ struct DiodeString {
     const double* beam_s;         // per-module beam of the sun
     const uint32_t* counts_s;     // per-cell shaded counts (nullptr: none shaded)
     const uint16_t* staged;       // the string's counts staged in LDS, or nullptr
+    const double* svf;            // per-cell sky view factors, or nullptr (whole sky)
     double dp, kk;                // diffuse irradiance, samples per cell
     int32_t p0, nq, cpm;          // first module of the string in str_mods, substrings, cells per module
 };
@@ -2000,22 +2001,29 @@ __device__ __forceinline__ int32_t diode_count(const DiodeString& S, int32_t mi,
     return (int32_t)(COHERENT ? ld_dev(p) : *p);
 }
 
+// Irradiance of that cell: the beam on its module minus the shaded share, plus
+// the diffuse times the share of the sky the cell sees (whole sky: reference).
+template <bool COHERENT>
+__device__ __forceinline__ double diode_irradiance(const DiodeString& S, int32_t mi, int32_t m, int32_t i, double bm) {
+    const int32_t cn = diode_count<COHERENT>(S, mi, m, i);
+    const double sky = S.svf ? S.svf[(int64_t)m * S.cpm + S.g->sub_cell[i]] : 1.0;
+    return bm * (1.0 - (double)cn / S.kk) + S.dp * sky;
+}
+
 // Voltage of substring q of the string at current I: its cells in order, one
-// solve per run of equal counts, clamped by the bypass diode.
+// solve per run of equal irradiances, clamped by the bypass diode.
 template <bool COHERENT>
 __device__ double sub_voltage(const DiodeString& S, int32_t q, double I) {
     const GenDev& g = *S.g;
     const int32_t mi = q / g.n_sub, sq = q % g.n_sub;
     const int32_t m = g.str_mods[S.p0 + mi];
     const double bm = S.beam_s[m];
-    double vs = 0.0, vc = 0.0;
-    int32_t prev = -1;
+    double vs = 0.0, vc = 0.0, prev = -1.0;
     for (int32_t i = g.sub_start[sq]; i < g.sub_start[sq + 1]; i++) {
-        const int32_t cn = diode_count<COHERENT>(S, mi, m, i);
-        if (cn != prev) {
-            const double G = bm * (1.0 - (double)cn / S.kk) + S.dp;
+        const double G = diode_irradiance<COHERENT>(S, mi, m, i, bm);
+        if (G != prev) {
             vc = cell_voltage(g.diode, G, I);
-            prev = cn;
+            prev = G;
         }
         vs += vc;
     }
@@ -2044,8 +2052,7 @@ __device__ double string_mpp_wave(const DiodeString& S, int lane) {
         const int32_t m = g.str_mods[S.p0 + mi];
         const double bm = S.beam_s[m];
         for (int32_t i = g.sub_start[sq]; i < g.sub_start[sq + 1]; i++) {
-            const int32_t cn = diode_count<COHERENT>(S, mi, m, i);
-            const double iph = d.isc * (bm * (1.0 - (double)cn / S.kk) + S.dp) / d.gref;
+            const double iph = d.isc * diode_irradiance<COHERENT>(S, mi, m, i, bm) / d.gref;
             imax = fmax(imax, iph);
         }
     }
@@ -2104,6 +2111,7 @@ __device__ void diode_loss_body(DiodeLds& L, const double* beam_s, const uint32_
                 S.beam_s = beam_s;
                 S.counts_s = pass == 0 ? counts_s : nullptr;
                 S.staged = nullptr;
+                S.svf = pass == 0 ? g.svf : nullptr;
                 S.dp = dp;
                 S.kk = (double)(k * k);
                 S.p0 = g.str_start[st];
@@ -2181,7 +2189,8 @@ __device__ void loss_body(LossLds& L, const double* sun3, const double* beam_s, 
                                                               : counts_s[(int64_t)m * cpm + c])
                                                   : 0u;
                     const double f = (double)sh / kk;
-                    cmin = fmin(cmin, bm * (1.0 - f) + dp);
+                    const double sky = pass == 0 && g.svf ? g.svf[(int64_t)m * cpm + c] : 1.0;
+                    cmin = fmin(cmin, bm * (1.0 - f) + dp * sky);
                 }
                 L.cap[q] = cmin;
             }
@@ -2230,6 +2239,27 @@ __global__ void k_energy(int64_t n_sun, const double* power, const double* power
     }
     energy[0] = e;
     energy[1] = er;
+}
+
+// Diffuse shading: sky view factor of every cell from the shaded counts of
+// n_dir sky directions (each evaluated as a sun): the front-facing directions'
+// weights w = n . s, in direction order, times the cell's lit share, over the
+// sum of the weights; 1 when no direction faces the module.
+__global__ __launch_bounds__(256) void k_svf(const Module* mods, int32_t cpm, int64_t n_cells, const double* dirs,
+                                             int64_t n_dir, const uint32_t* counts, int32_t k, double* svf) {
+    const int64_t c = blockIdx.x * 256ll + threadIdx.x;
+    if (c >= n_cells) return;
+    const Module& M = mods[c / cpm];
+    const double kk = (double)(k * k);
+    double num = 0.0, den = 0.0;
+    for (int64_t j = 0; j < n_dir; j++) {
+        const double w = (M.n[0] * dirs[3 * j] + M.n[1] * dirs[3 * j + 1]) + M.n[2] * dirs[3 * j + 2];
+        if (!(w > 0.0)) continue;
+        const double f = (double)counts[j * n_cells + c] / kk;
+        num += w * (1.0 - f);
+        den += w;
+    }
+    svf[c] = den > 0.0 ? num / den : 1.0;
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
@@ -2931,6 +2961,14 @@ hipError_t launch_loss(int64_t n_sun, const double* sun, const double* beam, con
     if (n_sun <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_loss, dim3((unsigned)n_sun), dim3(256), 0, st, sun, beam, counts, d_poa, g, k, power,
                        power_ref);
+    return hipGetLastError();
+}
+
+hipError_t launch_svf(const Module* mods, int32_t cpm, int64_t n_cells, const double* dirs, int64_t n_dir,
+                      const uint32_t* counts, int32_t k, double* svf, hipStream_t st) {
+    if (n_cells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_svf, dim3((unsigned)((n_cells + 255) / 256)), dim3(256), 0, st, mods, cpm, n_cells, dirs,
+                       n_dir, counts, k, svf);
     return hipGetLastError();
 }
 

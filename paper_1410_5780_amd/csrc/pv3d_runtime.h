@@ -57,6 +57,7 @@ struct Gen {
     int32_t n_trk = 0;
     int32_t* sub_start = nullptr; // [n_sub + 1] CSR of the cells of each substring
     int32_t* sub_cell = nullptr;  // [n_cu * n_cv]
+    double* svf = nullptr;        // [n_cells] sky view factors (nullptr: every cell sees the whole sky)
     DiodeDev diode{};             // electrical model (diode.on = 0: ideal strings)
 };
 
@@ -83,12 +84,12 @@ struct Lane {
 struct Work {
     Lane lane[2];
     Buf views, ctr, beam, bias, sweep, sphere, partial, fu, fv, tmask, posed;
-    Buf counts, outd, maps, bits;
+    Buf counts, outd, maps, bits, sky;
     void release_all(Ctx* c) {
         lane[0].release_all(c);
         lane[1].release_all(c);
         Buf* all[] = {&views, &ctr, &beam, &bias, &sweep, &sphere, &partial, &fu, &fv, &tmask, &posed, &counts, &outd,
-                      &maps, &bits};
+                      &maps, &bits, &sky};
         for (Buf* b : all) b->release(c);
     }
 };

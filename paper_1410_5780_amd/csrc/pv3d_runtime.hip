@@ -368,7 +368,7 @@ SceneDev scene_dev(const Scene& sc) {
 
 void free_gen(Ctx* c, Gen& g) {
     void** all[] = {(void**)&g.mods, (void**)&g.cell_sub, (void**)&g.str_start, (void**)&g.str_mods,
-                    (void**)&g.trk, (void**)&g.mod_trk, (void**)&g.sub_start, (void**)&g.sub_cell};
+                    (void**)&g.trk, (void**)&g.mod_trk, (void**)&g.sub_start, (void**)&g.sub_cell, (void**)&g.svf};
     for (void** p : all) {
         c->dfree(*p);
         *p = nullptr;
@@ -390,6 +390,7 @@ GenDev gen_dev(const Gen& g) {
     d.str_mods = g.str_mods;
     d.sub_start = g.sub_start;
     d.sub_cell = g.sub_cell;
+    d.svf = g.svf;
     d.diode = g.diode;
     return d;
 }
@@ -942,6 +943,79 @@ pv3d_status pv3d_generator_set_diode(pv3d_ctx* ctx, uint64_t gen, const pv3d_dio
     if (it == ctx->gens.end()) return fail(PV3D_ENOENT, "unknown generator %llu", (unsigned long long)gen);
     if (ctx->gen_in_use(gen)) return fail(PV3D_EBUSY, "generator %llu is used by a running job", (unsigned long long)gen);
     it->second.diode = dd;
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_generator_set_sky(pv3d_ctx* ctx, uint64_t gen, const double* svf) {
+    if (!ctx) return fail(PV3D_EINVAL, "null context");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->gens.find(gen);
+    if (it == ctx->gens.end()) return fail(PV3D_ENOENT, "unknown generator %llu", (unsigned long long)gen);
+    Gen& g = it->second;
+    if (g.n_trk > 0) return fail(PV3D_EINVAL, "sky view factors of a tracked generator change with its pose");
+    if (ctx->gen_in_use(gen)) return fail(PV3D_EBUSY, "generator %llu is used by a running job", (unsigned long long)gen);
+    const int64_t cells = g.n_mod * g.n_cu * g.n_cv;
+    if (svf)
+        for (int64_t c = 0; c < cells; c++)
+            if (!(svf[c] >= 0.0 && svf[c] <= 1.0)) return fail(PV3D_EINVAL, "cell %lld: sky view factor not in [0, 1]", (long long)c);
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->dfree(g.svf);
+    g.svf = nullptr;
+    if (!svf) return PV3D_OK;
+    pv3d_status st;
+    if ((st = ctx->dalloc((void**)&g.svf, 8 * (size_t)cells, "sky view factors"))) return st;
+    hipError_t e = hipMemcpy(g.svf, svf, 8 * (size_t)cells, hipMemcpyHostToDevice);
+    if (e) {
+        ctx->dfree(g.svf);
+        g.svf = nullptr;
+        return hip_fail(e, "copy sky view factors");
+    }
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_sky_view(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const double* dirs, int64_t n_dir,
+                          const pv3d_params* params, double* svf_out) {
+    if (!ctx || !dirs || !svf_out || !params) return fail(PV3D_EINVAL, "null argument");
+    if (n_dir < 1) return fail(PV3D_EINVAL, "n_dir %lld", (long long)n_dir);
+    for (int64_t j = 0; j < n_dir; j++)
+        if (!(dirs[3 * j + 2] > 0.0)) return fail(PV3D_EINVAL, "direction %lld is not above the horizon", (long long)j);
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto gi = ctx->gens.find(gen);
+    if (gi == ctx->gens.end()) return fail(PV3D_ENOENT, "unknown generator %llu", (unsigned long long)gen);
+    const Gen& g = gi->second;
+    if (g.n_trk > 0) return fail(PV3D_EINVAL, "sky view factors of a tracked generator change with its pose");
+    const int64_t cells = g.n_mod * g.n_cu * g.n_cv;
+    // every direction is a sun of unit beam and no diffuse
+    std::vector<double> in((size_t)(2 * n_dir), 0.0);
+    for (int64_t j = 0; j < n_dir; j++) in[(size_t)j] = 1.0;
+    pv3d_params p = *params;
+    p.flags &= ~(PV3D_EXPORT_DEPTH | PV3D_EXPORT_BITS);
+    pv3d_status st;
+    if ((st = ctx->w.sky.ensure(ctx, 8 * (size_t)(2 * n_dir + 2 + 3 * n_dir + cells), "sky view"))) return st;
+    double* d_pw = static_cast<double*>(ctx->w.sky.ptr);
+    double* d_dirs = d_pw + 2 * n_dir + 2;
+    double* d_svf = d_dirs + 3 * n_dir;
+    pv3d_outputs o;
+    memset(&o, 0, sizeof(o));
+    o.power = d_pw;
+    o.power_ref = d_pw + n_dir;
+    o.energy = d_pw + 2 * n_dir;
+    o.on_device = 1;
+    if ((st = pv3d_evaluate(ctx, scene, gen, dirs, in.data(), in.data() + n_dir, in.data() + n_dir, n_dir, &p, &o,
+                            nullptr)))
+        return st;
+    hipStream_t s = ctx->stream;
+    bool ovf = false;
+    if ((st = ctx->read_overflow(n_dir, s, &ovf))) return st;
+    if (ovf) return fail(PV3D_ERANGE, "internal buffer overflow");
+    hipError_t e;
+    if ((e = hipMemcpyAsync(d_dirs, dirs, 24 * (size_t)n_dir, hipMemcpyHostToDevice, s))) return hip_fail(e, "copy directions");
+    if ((e = launch_svf(g.mods, g.n_cu * g.n_cv, cells, d_dirs, n_dir, static_cast<const uint32_t*>(ctx->w.counts.ptr),
+                        p.k, d_svf, s)))
+        return hip_fail(e, "sky view launch");
+    if ((e = hipMemcpyAsync(svf_out, d_svf, 8 * (size_t)cells, hipMemcpyDeviceToHost, s))) return hip_fail(e, "copy sky view");
+    if ((e = hipStreamSynchronize(s))) return hip_fail(e, "sky view");
     return PV3D_OK;
 }
 

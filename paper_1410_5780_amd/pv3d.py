@@ -85,6 +85,8 @@ def lib():
                                                     ctypes.POINTER(_u64)]
         L.pv3d_generator_release.argtypes = [_P, _u64]
         L.pv3d_generator_set_diode.argtypes = [_P, _u64, ctypes.POINTER(Diode)]
+        L.pv3d_generator_set_sky.argtypes = [_P, _u64, _P]
+        L.pv3d_sky_view.argtypes = [_P, _u64, _u64, _P, _i64, ctypes.POINTER(Params), _P]
         L.pv3d_sun_cooper.argtypes = [_f64, _P, _P, _i64, _P]
         L.pv3d_evaluate.argtypes = [_P, _u64, _u64, _P, _P, _P, _P, _i64, ctypes.POINTER(Params),
                                     ctypes.POINTER(Outputs), _P]
@@ -100,7 +102,8 @@ def lib():
         L.pv3d_profile_enable.argtypes = [_P, _u32]
         L.pv3d_profile_read.argtypes = [_P, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
         for f in ("pv3d_profile_enable", "pv3d_profile_read", "pv3d_create", "pv3d_scene_load", "pv3d_scene_release", "pv3d_generator_define",
-                  "pv3d_generator_define_tracked", "pv3d_generator_release", "pv3d_generator_set_diode", "pv3d_sun_cooper", "pv3d_evaluate", "pv3d_evaluate_batched",
+                  "pv3d_generator_define_tracked", "pv3d_generator_release", "pv3d_generator_set_diode", "pv3d_generator_set_sky", "pv3d_sky_view",
+                  "pv3d_sun_cooper", "pv3d_evaluate", "pv3d_evaluate_batched",
                   "pv3d_autotune", "pv3d_batch_stats", "pv3d_batch_limits", "pv3d_serve_stats",
                   "pv3d_submit", "pv3d_poll", "pv3d_wait", "pv3d_cancel"):
             getattr(L, f).restype = _i32
@@ -240,14 +243,29 @@ class Context:
         return self._with_diode(h.value, gen)
 
     def _with_diode(self, h: int, gen) -> int:
-        d = getattr(gen, "diode", None)
-        if d is not None:
-            try:
+        d, svf = getattr(gen, "diode", None), getattr(gen, "sky_view", None)
+        try:
+            if d is not None:
                 self.set_diode(h, d)
-            except Pv3dError:
-                self.release_generator(h)
-                raise
+            if svf is not None:
+                self.set_sky(h, svf)
+        except Pv3dError:
+            self.release_generator(h)
+            raise
         return h
+
+    def set_sky(self, gen_h: int, svf):
+        """Per-cell sky view factors [n_cells] scaling each cell's diffuse, or None to detach them."""
+        a = None if svf is None else _c(svf, np.float64).reshape(-1)
+        _check(lib().pv3d_generator_set_sky(self.h, gen_h, _ptr(a)), self.h)
+
+    def sky_view(self, scene_h: int, gen_h: int, gen, dirs, map_n: int, k: int, tile: int = 0) -> np.ndarray:
+        """Sky view factor of every cell over the sky directions dirs [n, 3] (computed on the GPU)."""
+        d = _c(dirs, np.float64).reshape(-1, 3)
+        out = np.zeros(gen.n_cells)
+        p = self.params(map_n, k, tile=tile)
+        _check(lib().pv3d_sky_view(self.h, scene_h, gen_h, _ptr(d), d.shape[0], ctypes.byref(p), _ptr(out)), self.h)
+        return out
 
     def set_diode(self, gen_h: int, d):
         """Single-diode cell model for the generator: d = (Isc_ref, G_ref, I0, a, Rs, Rsh, Vb), or None

@@ -81,6 +81,9 @@ class Generator:
     # cell parameters [7] = Isc_ref (A), G_ref (W/m^2), I0 (A), a = n k T / q (V),
     # Rs (ohm), Rsh (ohm) and the bypass diode's forward voltage Vb (V)
     diode: Optional[np.ndarray] = None
+    # diffuse shading: per-cell sky view factors [n_cells] in [0, 1] scaling the
+    # diffuse irradiance (None: every cell sees the whole sky)
+    sky_view: Optional[np.ndarray] = None
 
     @property
     def n_mod(self) -> int:
@@ -593,6 +596,16 @@ def c7_stadium_small(sweep: Optional[Sweep] = None) -> List[Workload]:
         yr = year_sweep()
         sweep = yr.subset(np.arange(0, yr.n, 37))
     return c7_stadium(sweep=sweep, n_gen=10, n_u=2, n_v=4, map_n=256, k=2, ring=(30.0, 24.0))
+
+
+def sky_directions(n: int) -> np.ndarray:
+    """n directions over the sky hemisphere, each standing for an equal solid angle: a golden-angle
+    spiral with heights z_j = (j + 1/2) / n (equal bands of height hold equal solid angle)."""
+    j = np.arange(n, dtype=np.float64)
+    z = (j + 0.5) / n
+    phi = j * math.pi * (3.0 - math.sqrt(5.0))
+    r = np.sqrt(1.0 - z * z)
+    return np.stack([r * np.cos(phi), r * np.sin(phi), z], 1)
 
 
 # --------------------------------------------------------------------------

@@ -8,6 +8,7 @@ import pytest
 from oracle import oracle as O
 from tests import test_oracle_pins as pins
 from tests import test_oracle_diode as dpins
+from tests import test_oracle_sky as spins
 from tests import test_oracle_trackers as tpins
 
 SRC = open(O.SRC).read()
@@ -26,7 +27,7 @@ MUTANTS = {
     "window_without_margin": ("V->itx = (double)(n - 2) / su;", "V->itx = (double)(n) / su;"),
     "clip_midpoint": ("out[m][k] = p[k] + (r[k] - p[k]) * t;", "out[m][k] = p[k] + (r[k] - p[k]) * 0.5;"),
     "string_count_off_by_one": ("double p = (double)(j + 1) * caps[j];", "double p = (double)(j) * caps[j];"),
-    "diffuse_dropped": ("double g = beam[m] * (1.0 - f) + d_poa;", "double g = beam[m] * (1.0 - f);"),
+    "diffuse_dropped": ("double g = beam[m] * (1.0 - f) + d_poa * sky;", "double g = beam[m] * (1.0 - f);"),
     "back_lit_tested": ("if (!(cm > 0.0) || !V.valid) continue;\n        double nx = dot3(nh, V.e1), ny = dot3(nh, V.e2), nz = dot3(nh, V.d);\n        double gxs",
                         "if (!V.valid) continue;\n        double nx = dot3(nh, V.e1), ny = dot3(nh, V.e2), nz = dot3(nh, V.d);\n        double gxs"),
     "far_cull_inverted": ("if (zmin > (double)OR_DMAX) return;", "if (zmin < (double)OR_DMAX) return;"),
@@ -42,6 +43,12 @@ MUTANTS = {
     "diode_photocurrent_unscaled": ("double iph = d[0] * G / d[1];", "double iph = d[0];"),
     "bypass_diode_missing": ("if (vs < -d[6]) vs = -d[6];", ""),
     "mpp_not_refined": ("for (int it = 0; it < OR_MPP_REFINE; it++) {", "for (int it = 0; it < 0; it++) {"),
+    "sky_weight_uniform": ("double w = dot3(nh, ld3(dirs + 3 * j));", "double w = 1.0;"),
+    "sky_back_directions_counted": ("if (!(w > 0.0)) continue;", ""),
+    "sky_lit_share_flipped": ("num += w * (1.0 - f);", "num += w * f;"),
+    "sky_reference_obstructed": ("double sky = counts && P->svf ? P->svf[m * cpm + c] : 1.0;   /* reference: whole sky */\n"
+                                 "                    g[nc++]",
+                                 "double sky = P->svf ? P->svf[m * cpm + c] : 1.0;\n                    g[nc++]"),
     "mpp_first_maximum_only": ("        if (!(p[q] >= p[q - 1]) || (q < OR_MPP_GRID && !(p[q] >= p[q + 1]))) continue;",
                                "        if (best > 0.0) break;\n"
                                "        if (!(p[q] >= p[q - 1]) || (q < OR_MPP_GRID && !(p[q] >= p[q + 1]))) continue;"),
@@ -70,6 +77,9 @@ PINS = [
     (dpins.test_uniform_string_is_cells_times_cell_maximum, {"G": 800.0}),
     (dpins.test_partial_shading_matches_brute_force, {"case": "one_shaded_substring"}),
     (dpins.test_partial_shading_matches_brute_force, {"case": "two_maxima_later_higher"}),
+    (spins.test_wall_matches_the_infinite_wall_closed_form, {"tilt": 0.0, "north": True}),
+    (spins.test_wall_matches_the_infinite_wall_closed_form, {"tilt": 30.0, "north": True}),
+    (spins.test_sky_view_scales_only_the_diffuse, {}),
 ]
 
 
