@@ -71,7 +71,7 @@ struct PathSizes {
 };
 
 // The buffers one stream of the per-sun path works in; consecutive suns
-// alternate between two lanes on two streams.
+// take turns on the lanes, one stream each.
 struct Lane {
     Buf rec, large, bins, tile_count, tile_start, tile_cursor, tile_list, pitems, pchunk, modbox, map;
     void release_all(Ctx* c) {
@@ -81,13 +81,20 @@ struct Lane {
     }
 };
 
+// Streams the per-sun path spreads consecutive suns over (lane 0 is the
+// caller's stream); a lane whose buffers do not fit the budget is left out.
+#ifndef PV3D_LANES
+#define PV3D_LANES 4
+#endif
+constexpr int kLanes = PV3D_LANES;
+static_assert(kLanes >= 1 && kLanes <= 4, "1 to 4 lanes");
+
 struct Work {
-    Lane lane[2];
+    Lane lane[kLanes];
     Buf views, ctr, beam, bias, sweep, sphere, partial, fu, fv, tmask, posed;
     Buf counts, outd, maps, bits, sky;
     void release_all(Ctx* c) {
-        lane[0].release_all(c);
-        lane[1].release_all(c);
+        for (Lane& L : lane) L.release_all(c);
         Buf* all[] = {&views, &ctr, &beam, &bias, &sweep, &sphere, &partial, &fu, &fv, &tmask, &posed, &counts, &outd,
                       &maps, &bits, &sky};
         for (Buf* b : all) b->release(c);
@@ -131,8 +138,8 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t stream_in_use = nullptr;
-    hipStream_t stream2 = nullptr;          // the per-sun path's second lane
-    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    hipStream_t lane_st[kLanes] = {};       // the per-sun path's further lanes ([0] unused)
+    hipEvent_t fork_ev = nullptr, join_ev[kLanes] = {};
     uint64_t budget = 0;
     uint64_t used = 0;
     size_t max_lds = 65536;

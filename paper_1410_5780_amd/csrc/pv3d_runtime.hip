@@ -416,15 +416,18 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
 
     if ((e = hipMemsetAsync(ctr, 0, sizeof(SunCounters) * (size_t)std::max<int64_t>(n_sun, 1), st)))
         return hip_fail(e, "clear counters");
-    // a second lane when its buffers fit the budget: consecutive suns then
-    // alternate between two streams, so that one sun's set-up and binning
-    // kernels, which leave most of the GPU idle, run beside the other's tile
-    // pass and the drain at its end
+    // further lanes when their buffers fit the budget: consecutive suns then
+    // take turns on up to kLanes streams, so that one sun's set-up and binning
+    // kernels, which leave most of the GPU idle, run beside other suns' tile
+    // passes and the drains at their ends
     const bool own_map = maps == nullptr && (p.flags & PV3D_SEPARATE_TEST);
     int n_lanes = 1;
-    if (stream2 && n_sun > 1) {
-        if (ensure_lane(w.lane[1], z, g, p.map_n, own_map) == PV3D_OK) n_lanes = 2;
-        else w.lane[1].release_all(this);
+    while (n_lanes < kLanes && n_lanes < n_sun && lane_st[n_lanes]) {
+        if (ensure_lane(w.lane[n_lanes], z, g, p.map_n, own_map) != PV3D_OK) {
+            w.lane[n_lanes].release_all(this);
+            break;
+        }
+        n_lanes++;
     }
     // tile counts start at zero; the scan of every sun leaves them at zero again
     for (int l = 0; l < n_lanes; l++)
@@ -461,10 +464,9 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
     if (z.mask_words > 512) tmask = nullptr;
     if ((e = timed(prof, PV3D_STAGE_SETUP, st, [&] { return launch_setup(d_sun, n_sun, d_dni, gd, sphere, p.map_n, views, beam, bias, tg, tmask, st); })))
         return hip_fail(e, "setup");
-    if (n_lanes == 2) {
-        if ((e = hipEventRecord(fork_ev, st)) || (e = hipStreamWaitEvent(stream2, fork_ev, 0)))
-            return hip_fail(e, "fork the second lane");
-    }
+    if (n_lanes > 1 && (e = hipEventRecord(fork_ev, st))) return hip_fail(e, "fork the lanes");
+    for (int l = 1; l < n_lanes; l++)
+        if ((e = hipStreamWaitEvent(lane_st[l], fork_ev, 0))) return hip_fail(e, "fork the lanes");
     int64_t done = 0;
     for (int64_t s = 0; s < n_sun; s++) {
         if (!(sun_host[3 * s + 2] > 0.0)) continue;        // below the horizon: outputs stay zero
@@ -472,13 +474,12 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
         const int lane = (int)(done++ % n_lanes);
         if ((rs = run_sun(s, z, sd, gd, p, views, ctr, bias, beam, map, counts + s * z.cells,
                           bits ? bits + s * z.cells * z.words : nullptr, tmask ? tmask + s * z.mask_words : nullptr,
-                          lane, lane ? stream2 : st)))
+                          lane, lane ? lane_st[lane] : st)))
             return rs;
     }
-    if (n_lanes == 2) {
-        if ((e = hipEventRecord(join_ev, stream2)) || (e = hipStreamWaitEvent(st, join_ev, 0)))
-            return hip_fail(e, "join the second lane");
-    }
+    for (int l = 1; l < n_lanes; l++)
+        if ((e = hipEventRecord(join_ev[l], lane_st[l])) || (e = hipStreamWaitEvent(st, join_ev[l], 0)))
+            return hip_fail(e, "join the lanes");
     if ((e = timed(prof, PV3D_STAGE_LOSS, st, [&] { return launch_loss(n_sun, d_sun, beam, counts, d_dpoa, gd, p.k, power, power_ref, st); })))
         return hip_fail(e, "loss");
     if ((e = launch_energy(n_sun, power, power_ref, d_dt, energy, st))) return hip_fail(e, "energy");
@@ -587,10 +588,13 @@ pv3d_status pv3d_create(int32_t device, uint64_t hbm_budget_bytes, pv3d_ctx** ou
     if ((e = hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming)) != hipSuccess)
         return hip_fail(e, "hipEventCreate");
     c->stream_in_use = c->stream;
-    if ((e = hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking)) != hipSuccess)
-        return hip_fail(e, "hipStreamCreate");
-    if ((e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming)) != hipSuccess)
+    for (int l = 1; l < kLanes; l++) {
+        if ((e = hipStreamCreateWithFlags(&c->lane_st[l], hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "hipStreamCreate");
+        if ((e = hipEventCreateWithFlags(&c->join_ev[l], hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "hipEventCreate");
+    }
+    if ((e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming)) != hipSuccess)
         return hip_fail(e, "hipEventCreate");
     {
         hipDeviceProp_t prop;
@@ -620,9 +624,11 @@ void pv3d_destroy(pv3d_ctx* ctx) {
     for (hipEvent_t ev : ctx->prof.pool) (void)hipEventDestroy(ev);
     (void)hipEventDestroy(ctx->staging_done);
     (void)hipStreamDestroy(ctx->stream);
-    if (ctx->stream2) (void)hipStreamDestroy(ctx->stream2);
+    for (int l = 1; l < kLanes; l++) {
+        if (ctx->lane_st[l]) (void)hipStreamDestroy(ctx->lane_st[l]);
+        if (ctx->join_ev[l]) (void)hipEventDestroy(ctx->join_ev[l]);
+    }
     if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
-    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
     delete ctx;
 }
 
