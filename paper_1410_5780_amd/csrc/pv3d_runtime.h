@@ -122,6 +122,7 @@ struct Profiler {
     int64_t launches[PV3D_N_STAGES] = {};
     bool on(int stage) const { return (mask >> stage) & 1u; }
     hipError_t begin(int stage, hipStream_t st, size_t* slot);
+    hipError_t reserve(int stage, size_t* slot);   // a pair of events that a launch fills itself
     hipError_t end(size_t slot, hipStream_t st);
     hipError_t collect();
     void reset();

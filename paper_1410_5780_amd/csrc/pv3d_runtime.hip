@@ -153,6 +153,12 @@ pv3d_status Ctx::stage_done(hipStream_t st) {
 // stage timing
 // ---------------------------------------------------------------------------
 hipError_t Profiler::begin(int stage, hipStream_t st, size_t* slot) {
+    hipError_t e = reserve(stage, slot);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(pool[*slot], st);
+}
+
+hipError_t Profiler::reserve(int stage, size_t* slot) {
     if (used + 2 > pool.size()) {
         size_t grow = std::max<size_t>(1024, pool.size());
         for (size_t i = 0; i < grow; i++) {
@@ -165,7 +171,7 @@ hipError_t Profiler::begin(int stage, hipStream_t st, size_t* slot) {
     *slot = used;
     used += 2;
     pending.emplace_back(stage, *slot);
-    return hipEventRecord(pool[*slot], st);
+    return hipSuccess;
 }
 
 hipError_t Profiler::end(size_t slot, hipStream_t st) { return hipEventRecord(pool[slot + 1], st); }
@@ -420,9 +426,14 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
     // take turns on up to kLanes streams, so that one sun's set-up and binning
     // kernels, which leave most of the GPU idle, run beside other suns' tile
     // passes and the drains at their ends
+    // Once a serving loop runs, its resident kernel holds a hardware queue that
+    // further streams could share (there are fewer queues than streams); work
+    // queued behind it would wait for the loop to go idle, so the per-sun path
+    // then keeps to the caller's stream.
     const bool own_map = maps == nullptr && (p.flags & PV3D_SEPARATE_TEST);
+    const int max_lanes = server ? 1 : kLanes;
     int n_lanes = 1;
-    while (n_lanes < kLanes && n_lanes < n_sun && lane_st[n_lanes]) {
+    while (n_lanes < max_lanes && n_lanes < n_sun && lane_st[n_lanes]) {
         if (ensure_lane(w.lane[n_lanes], z, g, p.map_n, own_map) != PV3D_OK) {
             w.lane[n_lanes].release_all(this);
             break;
@@ -526,10 +537,17 @@ pv3d_status Ctx::run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, cons
         return hip_fail(e, "bin_scan");
     if ((e = timed(prof, PV3D_STAGE_BIN_SCATTER, st, [&] { return launch_pair_scatter(bb, tmask_s, pair_grid, st); })))
         return hip_fail(e, "bin_scatter");
-    if ((e = timed(prof, PV3D_STAGE_RASTER, st, [&] {
-             return launch_raster(s, views, bb, ctr, p.map_n, gd, bias, static_cast<double*>(w.fu.ptr),
-                                  static_cast<double*>(w.fv.ptr), p.k, to, tmask_s, n_cu, st);
-         })))
+    // the tile kernel, the dominant one, is timed by its own start and end
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (prof.on(PV3D_STAGE_RASTER)) {
+        if (prof.used >= 1u << 16 && (e = prof.collect())) return hip_fail(e, "profile");
+        size_t slot = 0;
+        if ((e = prof.reserve(PV3D_STAGE_RASTER, &slot))) return hip_fail(e, "profile");
+        ev0 = prof.pool[slot];
+        ev1 = prof.pool[slot + 1];
+    }
+    if ((e = launch_raster(s, views, bb, ctr, p.map_n, gd, bias, static_cast<double*>(w.fu.ptr),
+                           static_cast<double*>(w.fv.ptr), p.k, to, tmask_s, n_cu, st, ev0, ev1)))
         return hip_fail(e, "raster");
     if (separate &&
         (e = timed(prof, PV3D_STAGE_SAMPLE_TEST, st, [&] {
