@@ -439,7 +439,6 @@ def main():
         line["c4_batched"] = c4_leg(ctx, a.c4_every, log)
         line["trackers"] = tracker_leg(ctx, log)
         line["stadium"] = stadium_leg(ctx, log, a.stadium_every)
-        # last: once the serving loop runs, the per-sun path keeps to one stream
         line["serving"] = serving_leg(ctx, log, a.serve_rate, a.serve_seconds, a.light_rate, a.light_seconds)
     if not a.no_cpu:
         print("[bench] cpu oracle leg ...", file=sys.stderr, flush=True)

@@ -221,9 +221,8 @@ typedef struct {
  * dni: [n_sun] direct normal irradiance; d_poa: [n_sun] diffuse irradiance on
  * the module plane; dt_h: [n_sun] hours each sun stands for. Host memory.
  * hip_stream: a hipStream_t of this device, or NULL for the context stream.
- * Consecutive suns take turns on up to four streams (hip_stream and three of
- * the context's), joined back into hip_stream; once the context's serving
- * loop has started, only hip_stream is used.
+ * Consecutive suns take turns on two streams (hip_stream and one of the
+ * context's), joined back into hip_stream.
  * EINVAL: bad params or inputs; ENOENT: bad handle; ENOMEM: budget. */
 pv3d_status pv3d_evaluate(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const double* sun_xyz,
                           const double* dni, const double* d_poa, const double* dt_h,

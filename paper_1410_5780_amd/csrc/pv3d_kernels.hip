@@ -2905,10 +2905,11 @@ hipError_t launch_bin_scatter(int64_t s, const BinBuffers& bb, int32_t n_mod, Su
 }
 
 // Workgroups of the tile kernel: one per tile, or, with the work list, as
-// many as stay resident (at most one per possible item), each taking items
-// until the list is empty.
+// many as stay resident (at most one per possible item, and at most
+// cap_per_cu per CU when cap_per_cu > 0), each taking items until the list is
+// empty.
 template <int TS, int CAP>
-static hipError_t tile_launch(dim3 (&grid), const BinBuffers& bb, int32_t n_cu) {
+static hipError_t tile_launch(dim3 (&grid), const BinBuffers& bb, int32_t n_cu, int32_t cap_per_cu) {
     grid = dim3((unsigned)bb.n_tiles);
     if (!bb.tile_list) return hipSuccess;
     static int per_cu = 0;                     // the same code object on every device of one architecture
@@ -2918,8 +2919,9 @@ static hipError_t tile_launch(dim3 (&grid), const BinBuffers& bb, int32_t n_cu) 
         if (e != hipSuccess) return e;
         per_cu = nb > 0 ? nb : 1;
     }
+    const int32_t use = cap_per_cu > 0 ? std::min(cap_per_cu, per_cu) : per_cu;
     const int64_t most = 4 * (int64_t)bb.n_tiles;
-    grid = dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(most, (int64_t)n_cu * per_cu)));
+    grid = dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(most, (int64_t)n_cu * use)));
     return hipSuccess;
 }
 
@@ -2929,11 +2931,11 @@ static hipError_t tile_launch(dim3 (&grid), const BinBuffers& bb, int32_t n_cu) 
 template <int TS, int CAP>
 static hipError_t tile_go(int64_t s, const View* views, const BinBuffers& bb, const SunCounters* ctr, int32_t n,
                           const GenDev& g, const int32_t* bias, const double* fu, const double* fv, int32_t k,
-                          const TileOut& out, const uint32_t* tmask, int32_t n_cu, hipStream_t st, hipEvent_t ev0,
-                          hipEvent_t ev1) {
+                          const TileOut& out, const uint32_t* tmask, int32_t n_cu, int32_t cap_per_cu, hipStream_t st,
+                          hipEvent_t ev0, hipEvent_t ev1) {
     dim3 grid;
     hipError_t e;
-    if ((e = tile_launch<TS, CAP>(grid, bb, n_cu))) return e;
+    if ((e = tile_launch<TS, CAP>(grid, bb, n_cu, cap_per_cu))) return e;
     if (ev0)
         hipExtLaunchKernelGGL((k_tile<TS, CAP>), grid, dim3(256), 0, st, ev0, ev1, 0, s, views, bb, ctr, n, g, bias, fu,
                               fv, k, out, out.sparse, tmask);
@@ -2945,12 +2947,12 @@ static hipError_t tile_go(int64_t s, const View* views, const BinBuffers& bb, co
 
 hipError_t launch_raster(int64_t s, const View* views, const BinBuffers& bb, const SunCounters* ctr, int32_t n,
                          const GenDev& g, const int32_t* bias, const double* fu, const double* fv, int32_t k,
-                         const TileOut& out, const uint32_t* tmask, int32_t n_cu, hipStream_t st, hipEvent_t ev0,
-                         hipEvent_t ev1) {
+                         const TileOut& out, const uint32_t* tmask, int32_t n_cu, int32_t cap_per_cu, hipStream_t st,
+                         hipEvent_t ev0, hipEvent_t ev1) {
     switch (bb.tile) {
-        case 32: return tile_go<32, kCap32>(s, views, bb, ctr, n, g, bias, fu, fv, k, out, tmask, n_cu, st, ev0, ev1);
-        case 64: return tile_go<64, kCap64>(s, views, bb, ctr, n, g, bias, fu, fv, k, out, tmask, n_cu, st, ev0, ev1);
-        case 128: return tile_go<128, kCap128>(s, views, bb, ctr, n, g, bias, fu, fv, k, out, tmask, n_cu, st, ev0, ev1);
+        case 32: return tile_go<32, kCap32>(s, views, bb, ctr, n, g, bias, fu, fv, k, out, tmask, n_cu, cap_per_cu, st, ev0, ev1);
+        case 64: return tile_go<64, kCap64>(s, views, bb, ctr, n, g, bias, fu, fv, k, out, tmask, n_cu, cap_per_cu, st, ev0, ev1);
+        case 128: return tile_go<128, kCap128>(s, views, bb, ctr, n, g, bias, fu, fv, k, out, tmask, n_cu, cap_per_cu, st, ev0, ev1);
         default: return hipErrorInvalidValue;
     }
 }

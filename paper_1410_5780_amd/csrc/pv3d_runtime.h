@@ -83,11 +83,9 @@ struct Lane {
 
 // Streams the per-sun path spreads consecutive suns over (lane 0 is the
 // caller's stream); a lane whose buffers do not fit the budget is left out.
-#ifndef PV3D_LANES
-#define PV3D_LANES 4
-#endif
-constexpr int kLanes = PV3D_LANES;
-static_assert(kLanes >= 1 && kLanes <= 4, "1 to 4 lanes");
+// Two: with four (faster alone) a serving loop started in the same context
+// after the per-sun path had run stalled, with the cause not found.
+constexpr int kLanes = 2;
 
 struct Work {
     Lane lane[kLanes];
@@ -174,7 +172,8 @@ struct Ctx {
     pv3d_status ensure_lane(Lane& L, const PathSizes& z, const Gen& g, int32_t map_n, bool own_map);
     pv3d_status run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, const GenDev& gd, const pv3d_params& p,
                         const View* views, SunCounters* ctr, const int32_t* bias, const double* beam, uint32_t* map,
-                        uint32_t* counts_s, uint32_t* bits_s, const uint32_t* tmask_s, int lane, hipStream_t st);
+                        uint32_t* counts_s, uint32_t* bits_s, const uint32_t* tmask_s, int lane, int n_lanes,
+                        hipStream_t st);
     pv3d_status ensure_tables(const Gen& g, int32_t k);
     BinBuffers bin_buffers(const PathSizes& z, int lane);
     pv3d_status run_path(const Scene& sc, const Gen& g, const pv3d_params& p, const double* sun_host, int64_t n_sun,

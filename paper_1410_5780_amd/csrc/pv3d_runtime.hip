@@ -426,14 +426,9 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
     // take turns on up to kLanes streams, so that one sun's set-up and binning
     // kernels, which leave most of the GPU idle, run beside other suns' tile
     // passes and the drains at their ends
-    // Once a serving loop runs, its resident kernel holds a hardware queue that
-    // further streams could share (there are fewer queues than streams); work
-    // queued behind it would wait for the loop to go idle, so the per-sun path
-    // then keeps to the caller's stream.
     const bool own_map = maps == nullptr && (p.flags & PV3D_SEPARATE_TEST);
-    const int max_lanes = server ? 1 : kLanes;
     int n_lanes = 1;
-    while (n_lanes < max_lanes && n_lanes < n_sun && lane_st[n_lanes]) {
+    while (n_lanes < kLanes && n_lanes < n_sun && lane_st[n_lanes]) {
         if (ensure_lane(w.lane[n_lanes], z, g, p.map_n, own_map) != PV3D_OK) {
             w.lane[n_lanes].release_all(this);
             break;
@@ -485,7 +480,7 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
         const int lane = (int)(done++ % n_lanes);
         if ((rs = run_sun(s, z, sd, gd, p, views, ctr, bias, beam, map, counts + s * z.cells,
                           bits ? bits + s * z.cells * z.words : nullptr, tmask ? tmask + s * z.mask_words : nullptr,
-                          lane, lane ? lane_st[lane] : st)))
+                          lane, n_lanes, lane ? lane_st[lane] : st)))
             return rs;
     }
     for (int l = 1; l < n_lanes; l++)
@@ -505,7 +500,8 @@ constexpr int32_t kSplitEntries = 64;
 // The launch sequence of one sun.
 pv3d_status Ctx::run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, const GenDev& g_all, const pv3d_params& p,
                          const View* views, SunCounters* ctr, const int32_t* bias, const double* beam, uint32_t* map,
-                         uint32_t* counts_s, uint32_t* bits_s, const uint32_t* tmask_s, int lane, hipStream_t st) {
+                         uint32_t* counts_s, uint32_t* bits_s, const uint32_t* tmask_s, int lane, int n_lanes,
+                         hipStream_t st) {
     hipError_t e;
     GenDev gd = g_all;                                   // trackers: this sun's posed modules
     if (g_all.mods_sun) gd.mods = g_all.mods_sun + s * g_all.n_mod;
@@ -546,8 +542,10 @@ pv3d_status Ctx::run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, cons
         ev0 = prof.pool[slot];
         ev1 = prof.pool[slot + 1];
     }
+    // with several lanes the tile pass keeps to two workgroups per CU, leaving room for the other
+    // lane's set-up and binning kernels beside it
     if ((e = launch_raster(s, views, bb, ctr, p.map_n, gd, bias, static_cast<double*>(w.fu.ptr),
-                           static_cast<double*>(w.fv.ptr), p.k, to, tmask_s, n_cu, st, ev0, ev1)))
+                           static_cast<double*>(w.fv.ptr), p.k, to, tmask_s, n_cu, n_lanes > 1 ? 2 : 0, st, ev0, ev1)))
         return hip_fail(e, "raster");
     if (separate &&
         (e = timed(prof, PV3D_STAGE_SAMPLE_TEST, st, [&] {

@@ -178,3 +178,23 @@ def test_device_outputs(ctx):
         assert np.array_equal(g.counts.cpu().numpy().view(np.uint32), a.counts)
         assert np.array_equal(g.power.cpu().numpy(), a.power)
         assert np.array_equal(g.energy.cpu().numpy(), a.energy)
+
+
+def test_serving_after_the_per_sun_path_in_the_same_context(ctx):
+    """A context that has run the per-sun path on its lanes, then starts its serving loop:
+    a burst of the configured request stream completes promptly, and the per-sun path
+    still gives the same results with the loop running."""
+    from paper_1410_5780_amd import serve
+    yr = W.year_sweep()
+    w = W.c2_row_plant(sweep=yr.subset(np.arange(0, yr.n, 10)))
+    sh, gh = ctx.load_scene(w.scene), ctx.define_generator(w.gen)
+    first = ctx.evaluate(sh, gh, w.gen, w.sweep, w.map_n, w.k)
+    reqs = W.serving_stream(seed=5, rate_hz=200.0, duration_s=0.1)
+    t0 = time.perf_counter()
+    res = serve.run_stream(ctx, reqs, seed=5, log=_say)
+    wall = time.perf_counter() - t0
+    _say(f"[serve] after the per-sun path: {res['requests']} requests in {wall:.2f} s, p99 {res['p99_ms']:.0f} ms")
+    assert res["requests"] == len(reqs)
+    assert res["p99_ms"] < 10000.0, "a request waited more than 10 s"
+    again = ctx.evaluate(sh, gh, w.gen, w.sweep, w.map_n, w.k)
+    _same(again, first, "per-sun path with the serving loop started")
