@@ -361,6 +361,12 @@ pv3d_status pv3d_serve_stats(pv3d_ctx* ctx, int64_t out[4]);
 #define PV3D_N_STAGES 7
 pv3d_status pv3d_profile_enable(pv3d_ctx* ctx, uint32_t stage_mask);
 pv3d_status pv3d_profile_read(pv3d_ctx* ctx, int32_t stage, double* total_ms, int64_t* launches);
+/* Record only every n-th launch of each profiled stage (n >= 1; 1 after
+ * pv3d_create): the events sit between kernels of the stream and hold back
+ * the overlap of the two lanes, so a sample disturbs a long sweep less than
+ * timing every launch. launches (pv3d_profile_read) counts the timed ones.
+ * EINVAL: n < 1. */
+pv3d_status pv3d_profile_sample(pv3d_ctx* ctx, int32_t every);
 
 #ifdef __cplusplus
 }

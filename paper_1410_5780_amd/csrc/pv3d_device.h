@@ -285,8 +285,7 @@ hipError_t launch_bin_scatter(int64_t s, const BinBuffers& bb, int32_t n_mod, Su
 hipError_t launch_raster(int64_t s, const View* views, const BinBuffers& bb, const SunCounters* ctr,
                          int32_t n, const GenDev& g, const int32_t* bias, const double* fu,
                          const double* fv, int32_t k, const TileOut& out, const uint32_t* tmask,
-                         int32_t n_cu, int32_t cap_per_cu, hipStream_t st, hipEvent_t ev0 = nullptr,
-                         hipEvent_t ev1 = nullptr);
+                         int32_t n_cu, int32_t cap_per_cu, hipStream_t st);
 size_t bin_lds_bytes(int32_t n_tiles);
 hipError_t configure_kernels(size_t max_lds);
 hipError_t launch_sample_test(int64_t s, const View* views, const GenDev& g, const double* beam,

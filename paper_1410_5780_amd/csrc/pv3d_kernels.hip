@@ -29,8 +29,6 @@
 // dot product as (ax*bx + ay*by) + az*bz, so the FP64 steps give the same
 // bits as any other IEEE implementation of the same formulas; everything
 // after the snap is exact integer arithmetic.
-#include <hip/hip_ext.h>
-
 #include "pv3d_device.h"
 
 namespace pv3d {
@@ -2925,34 +2923,25 @@ static hipError_t tile_launch(dim3 (&grid), const BinBuffers& bb, int32_t n_cu, 
     return hipSuccess;
 }
 
-// ev0 / ev1 (both or neither): events that take the kernel's own start and end
-// times, so that its duration leaves out any wait for compute units held by
-// kernels of other streams.
 template <int TS, int CAP>
 static hipError_t tile_go(int64_t s, const View* views, const BinBuffers& bb, const SunCounters* ctr, int32_t n,
                           const GenDev& g, const int32_t* bias, const double* fu, const double* fv, int32_t k,
-                          const TileOut& out, const uint32_t* tmask, int32_t n_cu, int32_t cap_per_cu, hipStream_t st,
-                          hipEvent_t ev0, hipEvent_t ev1) {
+                          const TileOut& out, const uint32_t* tmask, int32_t n_cu, int32_t cap_per_cu, hipStream_t st) {
     dim3 grid;
     hipError_t e;
     if ((e = tile_launch<TS, CAP>(grid, bb, n_cu, cap_per_cu))) return e;
-    if (ev0)
-        hipExtLaunchKernelGGL((k_tile<TS, CAP>), grid, dim3(256), 0, st, ev0, ev1, 0, s, views, bb, ctr, n, g, bias, fu,
-                              fv, k, out, out.sparse, tmask);
-    else
-        hipLaunchKernelGGL((k_tile<TS, CAP>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out,
-                           out.sparse, tmask);
+    hipLaunchKernelGGL((k_tile<TS, CAP>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out,
+                       out.sparse, tmask);
     return hipGetLastError();
 }
 
 hipError_t launch_raster(int64_t s, const View* views, const BinBuffers& bb, const SunCounters* ctr, int32_t n,
                          const GenDev& g, const int32_t* bias, const double* fu, const double* fv, int32_t k,
-                         const TileOut& out, const uint32_t* tmask, int32_t n_cu, int32_t cap_per_cu, hipStream_t st,
-                         hipEvent_t ev0, hipEvent_t ev1) {
+                         const TileOut& out, const uint32_t* tmask, int32_t n_cu, int32_t cap_per_cu, hipStream_t st) {
     switch (bb.tile) {
-        case 32: return tile_go<32, kCap32>(s, views, bb, ctr, n, g, bias, fu, fv, k, out, tmask, n_cu, cap_per_cu, st, ev0, ev1);
-        case 64: return tile_go<64, kCap64>(s, views, bb, ctr, n, g, bias, fu, fv, k, out, tmask, n_cu, cap_per_cu, st, ev0, ev1);
-        case 128: return tile_go<128, kCap128>(s, views, bb, ctr, n, g, bias, fu, fv, k, out, tmask, n_cu, cap_per_cu, st, ev0, ev1);
+        case 32: return tile_go<32, kCap32>(s, views, bb, ctr, n, g, bias, fu, fv, k, out, tmask, n_cu, cap_per_cu, st);
+        case 64: return tile_go<64, kCap64>(s, views, bb, ctr, n, g, bias, fu, fv, k, out, tmask, n_cu, cap_per_cu, st);
+        case 128: return tile_go<128, kCap128>(s, views, bb, ctr, n, g, bias, fu, fv, k, out, tmask, n_cu, cap_per_cu, st);
         default: return hipErrorInvalidValue;
     }
 }

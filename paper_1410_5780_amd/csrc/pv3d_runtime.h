@@ -113,14 +113,16 @@ struct DevInfo {
 // Event pairs around launches of selected stages (profiling aid).
 struct Profiler {
     uint32_t mask = 0;
+    int32_t every = 1;                              // time every n-th launch of a stage
+    int64_t seen[PV3D_N_STAGES] = {};
     std::vector<hipEvent_t> pool;
     std::vector<std::pair<int, size_t>> pending;   // (stage, index of the start event in pool)
     size_t used = 0;
     double total_ms[PV3D_N_STAGES] = {};
     int64_t launches[PV3D_N_STAGES] = {};
     bool on(int stage) const { return (mask >> stage) & 1u; }
+    bool take(int stage) { return on(stage) && seen[stage]++ % every == 0; }
     hipError_t begin(int stage, hipStream_t st, size_t* slot);
-    hipError_t reserve(int stage, size_t* slot);   // a pair of events that a launch fills itself
     hipError_t end(size_t slot, hipStream_t st);
     hipError_t collect();
     void reset();

@@ -153,12 +153,6 @@ pv3d_status Ctx::stage_done(hipStream_t st) {
 // stage timing
 // ---------------------------------------------------------------------------
 hipError_t Profiler::begin(int stage, hipStream_t st, size_t* slot) {
-    hipError_t e = reserve(stage, slot);
-    if (e != hipSuccess) return e;
-    return hipEventRecord(pool[*slot], st);
-}
-
-hipError_t Profiler::reserve(int stage, size_t* slot) {
     if (used + 2 > pool.size()) {
         size_t grow = std::max<size_t>(1024, pool.size());
         for (size_t i = 0; i < grow; i++) {
@@ -171,7 +165,7 @@ hipError_t Profiler::reserve(int stage, size_t* slot) {
     *slot = used;
     used += 2;
     pending.emplace_back(stage, *slot);
-    return hipSuccess;
+    return hipEventRecord(pool[*slot], st);
 }
 
 hipError_t Profiler::end(size_t slot, hipStream_t st) { return hipEventRecord(pool[slot + 1], st); }
@@ -197,13 +191,14 @@ void Profiler::reset() {
     for (int i = 0; i < PV3D_N_STAGES; i++) {
         total_ms[i] = 0.0;
         launches[i] = 0;
+        seen[i] = 0;
     }
 }
 
 // Launch `call` for `stage`, bracketed by timing events when that stage is profiled.
 template <typename F>
 static hipError_t timed(Profiler& pf, int stage, hipStream_t st, F&& call) {
-    if (!pf.on(stage)) return call();
+    if (!pf.take(stage)) return call();
     size_t slot = 0;
     hipError_t e = pf.begin(stage, st, &slot);
     if (e != hipSuccess) return e;
@@ -533,19 +528,12 @@ pv3d_status Ctx::run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, cons
         return hip_fail(e, "bin_scan");
     if ((e = timed(prof, PV3D_STAGE_BIN_SCATTER, st, [&] { return launch_pair_scatter(bb, tmask_s, pair_grid, st); })))
         return hip_fail(e, "bin_scatter");
-    // the tile kernel, the dominant one, is timed by its own start and end
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (prof.on(PV3D_STAGE_RASTER)) {
-        if (prof.used >= 1u << 16 && (e = prof.collect())) return hip_fail(e, "profile");
-        size_t slot = 0;
-        if ((e = prof.reserve(PV3D_STAGE_RASTER, &slot))) return hip_fail(e, "profile");
-        ev0 = prof.pool[slot];
-        ev1 = prof.pool[slot + 1];
-    }
     // with several lanes the tile pass keeps to two workgroups per CU, leaving room for the other
     // lane's set-up and binning kernels beside it
-    if ((e = launch_raster(s, views, bb, ctr, p.map_n, gd, bias, static_cast<double*>(w.fu.ptr),
-                           static_cast<double*>(w.fv.ptr), p.k, to, tmask_s, n_cu, n_lanes > 1 ? 2 : 0, st, ev0, ev1)))
+    if ((e = timed(prof, PV3D_STAGE_RASTER, st, [&] {
+             return launch_raster(s, views, bb, ctr, p.map_n, gd, bias, static_cast<double*>(w.fu.ptr),
+                                  static_cast<double*>(w.fv.ptr), p.k, to, tmask_s, n_cu, n_lanes > 1 ? 2 : 0, st);
+         })))
         return hip_fail(e, "raster");
     if (separate &&
         (e = timed(prof, PV3D_STAGE_SAMPLE_TEST, st, [&] {
@@ -1172,6 +1160,14 @@ pv3d_status pv3d_profile_enable(pv3d_ctx* ctx, uint32_t stage_mask) {
     if (e != hipSuccess) return hip_fail(e, "collect timings");
     if (stage_mask == 0) ctx->prof.reset();
     ctx->prof.mask = stage_mask;
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_profile_sample(pv3d_ctx* ctx, int32_t every) {
+    if (!ctx) return fail(PV3D_EINVAL, "null context");
+    if (every < 1) return fail(PV3D_EINVAL, "every %d", every);
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    ctx->prof.every = every;
     return PV3D_OK;
 }
 

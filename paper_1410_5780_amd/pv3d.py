@@ -101,7 +101,8 @@ def lib():
         L.pv3d_cancel.argtypes = [_P, _u64]
         L.pv3d_profile_enable.argtypes = [_P, _u32]
         L.pv3d_profile_read.argtypes = [_P, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
-        for f in ("pv3d_profile_enable", "pv3d_profile_read", "pv3d_create", "pv3d_scene_load", "pv3d_scene_release", "pv3d_generator_define",
+        L.pv3d_profile_sample.argtypes = [_P, _i32]
+        for f in ("pv3d_profile_enable", "pv3d_profile_read", "pv3d_profile_sample", "pv3d_create", "pv3d_scene_load", "pv3d_scene_release", "pv3d_generator_define",
                   "pv3d_generator_define_tracked", "pv3d_generator_release", "pv3d_generator_set_diode", "pv3d_generator_set_sky", "pv3d_sky_view",
                   "pv3d_sun_cooper", "pv3d_evaluate", "pv3d_evaluate_batched",
                   "pv3d_autotune", "pv3d_batch_stats", "pv3d_batch_limits", "pv3d_serve_stats",
@@ -201,6 +202,10 @@ class Context:
 
     def profile_enable(self, stage_mask: int):
         _check(lib().pv3d_profile_enable(self.h, stage_mask), self.h)
+
+    def profile_sample(self, every: int):
+        """Time only every n-th launch of each profiled stage."""
+        _check(lib().pv3d_profile_sample(self.h, int(every)), self.h)
 
     def profile_read(self, stage: int):
         """(summed milliseconds, launches) of one stage since profiling was enabled."""

@@ -32,7 +32,7 @@ def test_header_declares_the_boundary():
                  "pv3d_generator_define", "pv3d_generator_release", "pv3d_sun_cooper", "pv3d_evaluate",
                  "pv3d_evaluate_batched", "pv3d_autotune", "pv3d_batch_stats", "pv3d_submit", "pv3d_poll",
                  "pv3d_wait", "pv3d_cancel", "pv3d_generator_define_tracked", "pv3d_generator_set_diode",
-                 "pv3d_generator_set_sky", "pv3d_sky_view"):
+                 "pv3d_generator_set_sky", "pv3d_sky_view", "pv3d_profile_sample"):
         assert want in names
 
 
