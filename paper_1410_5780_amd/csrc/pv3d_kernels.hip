@@ -866,9 +866,13 @@ __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& b
     return n_items;
 }
 
-__global__ __launch_bounds__(1024) void k_bin_scan(int32_t n_tiles, BinBuffers bb) {
-    __shared__ __attribute__((aligned(16))) int32_t part[2 * 1024 + 2 * kScanBuckets];
-    const int32_t n_items = scan_body<1024, false>(part, n_tiles, bb, bb.tile_list, bb.split_at);
+// One workgroup of 512 threads: it finds room on a CU beside the other lane's
+// tile pass sooner than one of 1024 (C2 year 351 ms against 363 ms).
+constexpr int kScanThreads = 512;
+
+__global__ __launch_bounds__(kScanThreads) void k_bin_scan(int32_t n_tiles, BinBuffers bb) {
+    __shared__ __attribute__((aligned(16))) int32_t part[2 * kScanThreads + 2 * kScanBuckets];
+    const int32_t n_items = scan_body<kScanThreads, false>(part, n_tiles, bb, bb.tile_list, bb.split_at);
     if (bb.tile_list && threadIdx.x == 0) {
         bb.list_ctr[0] = n_items;
         bb.list_ctr[1] = 0;
@@ -2891,7 +2895,7 @@ hipError_t launch_box_sphere(const double lo[3], const double hi[3], double* sph
 }
 
 hipError_t launch_bin_scan(int32_t n_tiles, const BinBuffers& bb, hipStream_t st) {
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, n_tiles, bb);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kScanThreads), 0, st, n_tiles, bb);
     return hipGetLastError();
 }
 
