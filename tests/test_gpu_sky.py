@@ -135,3 +135,22 @@ def test_sky_errors(ctx):
     finally:
         ctx.release_scene(sh)
         ctx.release_generator(gh)
+
+
+def test_sky_view_edge_directions(ctx, oracle_lib):
+    """One direction only, directions a hair above the horizon (a near-horizontal view), and
+    k = 1: the factors stay bit-identical to the oracle's."""
+    w = W.c1_tiny()
+    low = np.array([[np.cos(e) * np.cos(a), np.cos(e) * np.sin(a), np.sin(e)]
+                    for e in (0.01, 0.05) for a in [*np.linspace(0.0, 2.0 * np.pi, 7, endpoint=False), 1.5 * np.pi]])
+    cases = [(np.array([[0.0, 0.0, 1.0]]), 512, 4), (low, 1024, 8), (W.sky_directions(64), 256, 1)]
+    sh, gh = ctx.load_scene(w.scene), ctx.define_generator(w.gen)
+    try:
+        for dirs, n, k in cases:
+            got = ctx.sky_view(sh, gh, w.gen, dirs, n, k)
+            ref = oracle_lib.sky_view(w.scene, w.gen, dirs, n, k)
+            assert np.array_equal(got, ref), (dirs.shape[0], n, k)
+            _say(f"[sky] {dirs.shape[0]} directions, N={n}, k={k}: identical, svf {ref.min():.4f}..{ref.max():.4f}")
+    finally:
+        ctx.release_scene(sh)
+        ctx.release_generator(gh)
