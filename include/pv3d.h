@@ -248,9 +248,10 @@ pv3d_status pv3d_sky_view(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const dou
  * [0, 1], copied) to a generator: from then on a cell's diffuse irradiance in
  * the shaded power is d_poa * svf[cell]; the reference power keeps the whole
  * sky. svf = NULL detaches them. Applies to evaluations started after the
- * call (per-sun, batched and serving). EINVAL: a value outside [0, 1], a
- * tracked generator; ENOENT: unknown generator; EBUSY: a running serving job
- * reads the generator. */
+ * call (per-sun, batched and serving); the call first waits for the device's
+ * queued work, which may still read the factors it replaces. EINVAL: a value
+ * outside [0, 1], a tracked generator; ENOENT: unknown generator; EBUSY: a
+ * running serving job reads the generator. */
 pv3d_status pv3d_generator_set_sky(pv3d_ctx* ctx, uint64_t gen, const double* svf);
 
 /* One job = one (scene, generator, sweep) evaluation. Its input arrays must
