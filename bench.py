@@ -16,6 +16,7 @@ workload.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -47,7 +48,7 @@ def parse():
                          "sun's full picture written to HBM and read back by a separate depth-check kernel")
     ap.add_argument("--no-materialised", action="store_true",
                     help="skip the extra one-step run of the materialised route")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched, C4, serving, tracker and stadium legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched, C4, serving, tracker, stadium, electrical and sky legs")
     ap.add_argument("--c4-every", type=int, default=50, help="C4 leg: every n-th sun of the year")
     ap.add_argument("--stadium-every", type=int, default=4, help="stadium leg: every n-th sun of the year")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="serving leg: arrivals per second")
@@ -273,6 +274,70 @@ def stadium_leg(ctx, log, every):
             "energy_loss_max": float(loss.max())}
 
 
+def electrical_leg(ctx, log):
+    """The C2 year with the single-diode cell model (bypass diodes, a maximum power point per string)
+    against the ideal string model: whole year and the loss stage alone (HIP events)."""
+    import torch
+    from paper_1410_5780_amd import pv3d, workloads as W
+    w = W.c2_row_plant()
+    sh = ctx.load_scene(w.scene)
+    out = {}
+    for name, d in (("ideal", None), ("single_diode", W.DIODE_CELL)):
+        g = dataclasses.replace(w.gen, diode=d)
+        gh = ctx.define_generator(g)
+        best = None
+        for i in range(2):
+            if i == 1:
+                ctx.profile_enable(1 << pv3d.STAGE["loss"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.evaluate_device(sh, gh, g, w.sweep, w.map_n, w.k)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        ms, n = ctx.profile_read(pv3d.STAGE["loss"])
+        ctx.profile_enable(0)
+        out[name] = {"year_seconds": best, "loss_stage_ms": ms / max(n, 1), "energy_loss": r.loss,
+                     "energy_wh": float(r.energy.cpu().numpy()[0])}
+        ctx.release_generator(gh)
+    ctx.release_scene(sh)
+    log(f"[bench] electrical: ideal year {out['ideal']['year_seconds']:.3f} s (loss stage "
+        f"{out['ideal']['loss_stage_ms']:.2f} ms), single-diode {out['single_diode']['year_seconds']:.3f} s "
+        f"(loss stage {out['single_diode']['loss_stage_ms']:.2f} ms), losses {out['ideal']['energy_loss']:.4f} / "
+        f"{out['single_diode']['energy_loss']:.4f}")
+    return {"workload": f"{w.name}: {w.note}; 20 strings of 1,200 cells, 4,379 suns", **out}
+
+
+def sky_leg(ctx, log, n_dir=145):
+    """Diffuse shading: per-cell sky view factors of C2 from n_dir sky directions (each evaluated as a
+    sun), then the year with the factors attached."""
+    import torch
+    from paper_1410_5780_amd import workloads as W
+    w = W.c2_row_plant()
+    sh, gh = ctx.load_scene(w.scene), ctx.define_generator(w.gen)
+    dirs = W.sky_directions(n_dir)
+    best = None
+    for _ in range(2):
+        t0 = time.perf_counter()
+        svf = ctx.sky_view(sh, gh, w.gen, dirs, w.map_n, w.k)
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    base = ctx.evaluate_device(sh, gh, w.gen, w.sweep, w.map_n, w.k)
+    ctx.set_sky(gh, svf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.evaluate_device(sh, gh, w.gen, w.sweep, w.map_n, w.k)
+    torch.cuda.synchronize()
+    year = time.perf_counter() - t0
+    ctx.release_scene(sh)
+    ctx.release_generator(gh)
+    log(f"[bench] sky view: {n_dir} directions in {best:.3f} s, svf {svf.min():.3f}..{svf.max():.3f} "
+        f"(mean {svf.mean():.3f}); year with it {year:.3f} s, loss {base.loss:.4f} -> {r.loss:.4f}")
+    return {"workload": f"{w.name}: {w.note}", "directions": n_dir, "sky_view_seconds": best,
+            "svf_min": float(svf.min()), "svf_mean": float(svf.mean()), "year_seconds_with_svf": year,
+            "energy_loss_beam_only": base.loss, "energy_loss_with_diffuse": r.loss}
+
+
 def serving_leg(ctx, log, rate_hz, duration_s, light_rate, light_s):
     """Poisson request streams through the serving loop: latency from arrival to completion."""
     from paper_1410_5780_amd import serve, workloads as W
@@ -447,6 +512,8 @@ def main():
         line["c4_batched"] = c4_leg(ctx, a.c4_every, log)
         line["trackers"] = tracker_leg(ctx, log)
         line["stadium"] = stadium_leg(ctx, log, a.stadium_every)
+        line["electrical"] = electrical_leg(ctx, log)
+        line["sky"] = sky_leg(ctx, log)
         line["serving"] = serving_leg(ctx, log, a.serve_rate, a.serve_seconds, a.light_rate, a.light_seconds)
     if not a.no_cpu:
         print("[bench] cpu oracle leg ...", file=sys.stderr, flush=True)
