@@ -88,10 +88,10 @@ def test_random_tiny_ragged(ctx, oracle_lib, seed, n, k, tile):
 
 @pytest.mark.parametrize("seed,n", [(61, 256), (62, 200)])
 def test_dense_tiles_split_in_quadrants(ctx, oracle_lib, seed, n):
-    """Thousands of loose triangles over the generator: every 64-texel tile holds
-    far more than 64 bin entries, so the tile pass takes each as four quadrant
-    items (a ragged map at n = 200)."""
-    w = W.random_tiny(seed, n_boxes=4, n_loose=2500, n_mod_side=3, map_n=n, k=4, n_sun=5)
+    """Thousands of loose triangles over the generator: 64-texel tiles hold far
+    more than the 128 bin entries above which the tile pass takes a tile as four
+    quadrant items (a ragged map at n = 200)."""
+    w = W.random_tiny(seed, n_boxes=4, n_loose=6000, n_mod_side=3, map_n=n, k=4, n_sun=5)
     compare(ctx, oracle_lib, w, tile=64)
 
 
