@@ -314,7 +314,8 @@ class Context:
         return Result(counts, pw, pr, en, maps, bits)
 
     def evaluate_device(self, scene_h: int, gen_h: int, gen, sweep, map_n: int, k: int, stream=None,
-                        counts=None, tile: int = 0, separate_test=False, full_raster=False) -> Result:
+                        counts=None, tile: int = 0, separate_test=False, full_raster=False,
+                        bin_limit: int = 0) -> Result:
         """Device outputs as torch tensors, asynchronous on `stream` (default: torch's current stream)."""
         import torch
         s = _c(sweep.sun_xyz, np.float64)
@@ -325,7 +326,7 @@ class Context:
         pr = torch.empty(n, dtype=torch.float64, device=dev)
         en = torch.empty(2, dtype=torch.float64, device=dev)
         out = Outputs(_ptr(counts), _ptr(pw), _ptr(pr), _ptr(en), None, None, 1)
-        p = self.params(map_n, k, tile=tile, separate_test=separate_test, full_raster=full_raster)
+        p = self.params(map_n, k, tile=tile, separate_test=separate_test, full_raster=full_raster, bin_limit=bin_limit)
         st = stream if stream is not None else torch.cuda.current_stream()
         _check(lib().pv3d_evaluate(self.h, scene_h, gen_h, _ptr(s), _ptr(dni), _ptr(dp), _ptr(dt), n,
                                    ctypes.byref(p), ctypes.byref(out), ctypes.c_void_p(st.cuda_stream)), self.h)
