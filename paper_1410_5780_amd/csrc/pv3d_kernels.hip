@@ -2523,6 +2523,10 @@ __device__ void advance(const PLaunch& P, PCtl& ctl, double* stage, int32_t slot
                 if (!P.serve) {
                     const uint32_t q = atomicAdd(&P.sched->n_overflow, 1u);
                     P.overflow_items[q] = item;
+                } else {
+                    // serving: the host evaluates the suns marked so again (the job's tag,
+                    // released after every item of the job, orders this store before it)
+                    J.power[ld_dev(&st.sun)] = __builtin_nan("");
                 }
                 atomicAdd(reinterpret_cast<uint32_t*>(&P.job_overflow[job]), 1u);
             }

@@ -356,16 +356,29 @@ static void finish(Server* S, std::unique_lock<std::mutex>& lk, SJob* J, bool ov
             memcpy(h.job.out.energy, zero, 16);
         }
     } else if (overflow) {
-        // a sun exceeded a slot's capacity: the per-sun path evaluates the job again
+        // suns that exceeded a slot's capacity (their power marked NaN by the kernel): the
+        // per-sun path evaluates each of them again, one sun per call, and the job's energy
+        // is summed again
         lk.unlock();
         {
             std::lock_guard<std::recursive_mutex> cl(S->c->mu);
             S->c->stream_in_use = S->cstream;
             pv3d_params p1 = h.job.params;
             p1.tile = h.tile;
-            st = S->c->run_path(*h.sc, *h.g, p1, h.job.sun_xyz, ns, h.d_sun, h.d_dni, h.d_dpoa, h.d_dt, h.d_counts,
-                                h.d_power, h.d_pref, h.d_energy, nullptr, nullptr, S->cstream);
-            if (!st) e = hipStreamSynchronize(S->cstream);
+            std::vector<double> pw((size_t)ns);
+            if ((st = ensure_staging(S, 8 * (size_t)ns)) == PV3D_OK) {
+                e = copy_nocu(S->staging_dev, h.d_power, 8 * (size_t)ns, S->cstream);
+                if (!e) e = hipStreamSynchronize(S->cstream);
+                if (!e) memcpy(pw.data(), S->staging, 8 * (size_t)ns);
+            }
+            for (int64_t t = 0; t < ns && !st && !e; t++) {
+                if (!std::isnan(pw[(size_t)t])) continue;
+                st = S->c->run_path(*h.sc, *h.g, p1, h.job.sun_xyz + 3 * t, 1, h.d_sun + 3 * t, h.d_dni + t,
+                                    h.d_dpoa + t, h.d_dt + t, h.d_counts + t * h.cells, h.d_power + t, h.d_pref + t,
+                                    h.d_energy, nullptr, nullptr, S->cstream);
+            }
+            if (!st && !e) e = launch_energy(ns, h.d_power, h.d_pref, h.d_dt, h.d_energy, S->cstream);
+            if (!st && !e) e = hipStreamSynchronize(S->cstream);
             uint32_t ov = 0;
             if (!st && !e && (st = ensure_staging(S, 4)) == PV3D_OK) {
                 e = copy_nocu(S->staging_dev, static_cast<uint32_t*>(S->counters.ptr) + kServeJobs + j, 4, S->cstream);

@@ -200,3 +200,16 @@ def test_serving_after_the_per_sun_path_in_the_same_context(ctx):
     assert res["p99_ms"] < 120000.0, "a request waited more than 2 minutes"
     again = ctx.evaluate(sh, gh, w.gen, w.sweep, w.map_n, w.k)
     _same(again, first, "per-sun path with the serving loop started")
+
+
+def test_suns_beyond_slot_capacity_are_evaluated_again(ctx):
+    """Slots of 64 records: the suns of a scene with hundreds of loose triangles overflow them,
+    and the host evaluates just those suns again on the per-sun path. Every served result
+    equals the per-sun path's, next to a job whose suns fit."""
+    ctx.batch_limits(slot_records=64)
+    ws = [W.random_tiny(95, n_boxes=6, n_loose=400, n_mod_side=3, map_n=192, k=4, n_sun=8), W.c1_tiny(d_poa=100.0)]
+    specs = [_spec(ctx, w) for w in ws]
+    served = [ctx.wait(t) for t in [ctx.submit(sp) for sp in specs]]
+    for w, sp, got in zip(ws, specs, served):
+        _same(got, _alone(ctx, sp), f"{w.name} served with slots of 64 records")
+    _say(f"[serve] overflow stats {ctx.serve_stats()}")
