@@ -324,8 +324,11 @@ pv3d_status pv3d_batch_stats(pv3d_ctx* ctx, int64_t out[7]);
  * that the loop keeps running while work is in flight, so jobs that arrive
  * while others run share the GPU with them (continuous batching). Per job,
  * results are identical to pv3d_evaluate with the same params (same rules
- * as pv3d_evaluate_batched: flags 0 or FULL_RASTER, tile 0/32/64). The job's
- * input arrays are copied before the call returns. Host outputs are written
+ * as pv3d_evaluate_batched: flags 0 or FULL_RASTER, tile 0/32/64). A sun
+ * whose set-up records or bin entries exceed a slot's capacity is evaluated
+ * again, alone, with the per-sun path when its job completes (its device power
+ * reads NaN until then). The job's input arrays are copied before the call
+ * returns. Host outputs are written
  * when the job completes; device outputs are written by the device while the
  * job runs. The job's scene and generator cannot be released until it ends
  * (EBUSY). Limits: at most 4096 modules and 65536 raster tiles per job.
