@@ -2034,10 +2034,93 @@ __device__ double sub_voltage(const DiodeString& S, int32_t q, double I) {
     return vs < -g.diode.vb ? -g.diode.vb : vs;
 }
 
+// Levels of a string whose cells differ only by their shaded count (one beam
+// for all its modules, no sky view factors, at most 128 counts): the counts
+// present, as a 128-bit mask the whole wave holds, and lane j solving for the
+// j-th of them. A cell then takes its voltage from that lane by a shuffle, so
+// that every level is solved once per current instead of wherever some lane's
+// irradiance changes; the values, and the order in which cells add up, are
+// those of sub_voltage.
+struct Levels {
+    unsigned long long m0, m1;    // counts 0..63 and 64..127 present in the string
+    double g;                     // this lane's level irradiance (lane < n)
+    int32_t n, maxc;              // levels; most cells of a substring
+    bool on;
+};
+
+__device__ __forceinline__ int32_t level_rank(const Levels& L, int32_t cn) {
+    return cn < 64 ? __popcll(L.m0 & ((1ull << cn) - 1ull))
+                   : __popcll(L.m0) + __popcll(L.m1 & ((1ull << (cn - 64)) - 1ull));
+}
+
 template <bool COHERENT>
-__device__ double string_power_at(const DiodeString& S, int lane, double I) {
+__device__ void string_levels(const DiodeString& S, int lane, Levels& L) {
+    const GenDev& g = *S.g;
+    L.on = false;
+    L.n = 0;
+    L.g = 0.0;
+    L.m0 = L.m1 = 0ull;
+    if (S.svf || S.kk > 127.5) return;                                  // uniform over the wave
+    double bmin = INFINITY, bmax = -INFINITY;
+    int32_t maxc = 0;
+    for (int32_t q = lane; q < S.nq; q += 64) {
+        const int32_t mi = q / g.n_sub, sq = q % g.n_sub;
+        const int32_t m = g.str_mods[S.p0 + mi];
+        const double bm = S.beam_s[m];
+        bmin = fmin(bmin, bm);
+        bmax = fmax(bmax, bm);
+        maxc = max(maxc, g.sub_start[sq + 1] - g.sub_start[sq]);
+        for (int32_t i = g.sub_start[sq]; i < g.sub_start[sq + 1]; i++) {
+            const int32_t cn = diode_count<COHERENT>(S, mi, m, i);
+            if (cn < 64) L.m0 |= 1ull << cn;
+            else L.m1 |= 1ull << (cn - 64);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        bmin = fmin(bmin, __shfl_xor(bmin, off, 64));
+        bmax = fmax(bmax, __shfl_xor(bmax, off, 64));
+        maxc = max(maxc, __shfl_xor(maxc, off, 64));
+        L.m0 |= __shfl_xor(L.m0, off, 64);
+        L.m1 |= __shfl_xor(L.m1, off, 64);
+    }
+    L.n = __popcll(L.m0) + __popcll(L.m1);
+    if (!(bmin == bmax) || L.n > 64) return;
+    L.maxc = maxc;
+    L.on = true;
+    if (lane < L.n) {                                   // this lane's level: the lane-th count present
+        int32_t cn = -1, seen = -1;
+        for (int32_t c = 0; c < 128 && cn < 0; c++) {
+            const bool present = c < 64 ? ((L.m0 >> c) & 1ull) : ((L.m1 >> (c - 64)) & 1ull);
+            if (present && ++seen == lane) cn = c;
+        }
+        L.g = bmin * (1.0 - (double)cn / S.kk) + S.dp * 1.0;   // as diode_irradiance forms it
+    }
+}
+
+template <bool COHERENT>
+__device__ double string_power_at(const DiodeString& S, const Levels& L, int lane, double I) {
     double v = 0.0;
-    for (int32_t q = lane; q < S.nq; q += 64) v += sub_voltage<COHERENT>(S, q, I);
+    if (!L.on) {
+        for (int32_t q = lane; q < S.nq; q += 64) v += sub_voltage<COHERENT>(S, q, I);
+        return I * wave_sum(v);
+    }
+    const GenDev& g = *S.g;
+    const double vl = lane < L.n ? cell_voltage(g.diode, L.g, I) : 0.0;
+    for (int32_t q0 = 0; q0 < S.nq; q0 += 64) {        // uniform: every lane takes part in the shuffles
+        const int32_t q = q0 + lane;
+        const bool act = q < S.nq;
+        const int32_t mi = act ? q / g.n_sub : 0, sq = act ? q % g.n_sub : 0;
+        const int32_t m = act ? g.str_mods[S.p0 + mi] : 0;
+        const int32_t c0 = act ? g.sub_start[sq] : 0, nc = act ? g.sub_start[sq + 1] - c0 : 0;
+        double vs = 0.0;
+        for (int32_t i = 0; i < L.maxc; i++) {
+            const int32_t cn = i < nc ? diode_count<COHERENT>(S, mi, m, c0 + i) : 0;
+            const double vc = __shfl(vl, level_rank(L, cn), 64);
+            if (i < nc) vs += vc;
+        }
+        vs = vs < -g.diode.vb ? -g.diode.vb : vs;
+        if (act) v += vs;
+    }
     return I * wave_sum(v);
 }
 
@@ -2062,31 +2145,33 @@ __device__ double string_mpp_wave(const DiodeString& S, int lane) {
     }
     for (int off = 32; off > 0; off >>= 1) imax = fmax(imax, __shfl_xor(imax, off, 64));
     if (!(imax > 0.0)) return 0.0;
+    Levels L;
+    string_levels<COHERENT>(S, lane, L);
     const double r = 0.6180339887498949;       // (sqrt(5) - 1) / 2
     double best = 0.0;
-    double pm = string_power_at<COHERENT>(S, lane, imax * 0.0 / (double)kMppGrid);
-    double pc = string_power_at<COHERENT>(S, lane, imax * 1.0 / (double)kMppGrid);
+    double pm = string_power_at<COHERENT>(S, L, lane, imax * 0.0 / (double)kMppGrid);
+    double pc = string_power_at<COHERENT>(S, L, lane, imax * 1.0 / (double)kMppGrid);
     for (int q = 1; q <= kMppGrid; q++) {
-        const double pn = q < kMppGrid ? string_power_at<COHERENT>(S, lane, imax * (double)(q + 1) / (double)kMppGrid)
+        const double pn = q < kMppGrid ? string_power_at<COHERENT>(S, L, lane, imax * (double)(q + 1) / (double)kMppGrid)
                                        : 0.0;
         if (pc >= pm && (q == kMppGrid || pc >= pn)) {
             if (pc > best) best = pc;
             double lo = imax * (double)(q - 1) / (double)kMppGrid;
             double hi = imax * (double)(q < kMppGrid ? q + 1 : q) / (double)kMppGrid;
             double xc = hi - r * (hi - lo), xd = lo + r * (hi - lo);
-            double fc = string_power_at<COHERENT>(S, lane, xc), fd = string_power_at<COHERENT>(S, lane, xd);
+            double fc = string_power_at<COHERENT>(S, L, lane, xc), fd = string_power_at<COHERENT>(S, L, lane, xd);
             if (fc > best) best = fc;
             if (fd > best) best = fd;
             for (int it = 0; it < kMppRefine; it++) {
                 if (fc >= fd) {
                     hi = xd; xd = xc; fd = fc;
                     xc = hi - r * (hi - lo);
-                    fc = string_power_at<COHERENT>(S, lane, xc);
+                    fc = string_power_at<COHERENT>(S, L, lane, xc);
                     if (fc > best) best = fc;
                 } else {
                     lo = xc; xc = xd; fc = fd;
                     xd = lo + r * (hi - lo);
-                    fd = string_power_at<COHERENT>(S, lane, xd);
+                    fd = string_power_at<COHERENT>(S, L, lane, xd);
                     if (fd > best) best = fd;
                 }
             }
