@@ -2191,6 +2191,8 @@ __device__ void diode_loss_body(DiodeLds& L, const double* beam_s, const uint32_
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int32_t cpm = g.n_cu * g.n_cv;
     double tot[2] = {0.0, 0.0};
+    int32_t ref_nm = -1;                      // the wave's last unshaded string: modules, beam, power
+    double ref_bm = 0.0, ref_p = 0.0;
     for (int pass = 0; pass < 2; pass++) {
         for (int32_t st0 = 0; st0 < g.n_str; st0 += kLossStrings) {
             const int32_t st1 = min(g.n_str, st0 + kLossStrings);
@@ -2218,7 +2220,36 @@ __device__ void diode_loss_body(DiodeLds& L, const double* beam_s, const uint32_
                     }
                     S.staged = dst;
                 }
-                const double p = string_mpp_wave<COHERENT>(S, lane);
+                // Unshaded (the reference pass), a string whose modules share one beam has a
+                // power that depends only on its module count and that beam: the wave reuses
+                // the power of its previous such string when both match (the same inputs to
+                // the same computation, so the same value).
+                double p;
+                bool reuse = false, uni = false;
+                double bmin = INFINITY, bmax = -INFINITY;
+                if (pass == 1) {
+                    for (int32_t mi = lane; mi < nm; mi += 64) {
+                        const double bm = beam_s[g.str_mods[S.p0 + mi]];
+                        bmin = fmin(bmin, bm);
+                        bmax = fmax(bmax, bm);
+                    }
+                    for (int off = 32; off > 0; off >>= 1) {
+                        bmin = fmin(bmin, __shfl_xor(bmin, off, 64));
+                        bmax = fmax(bmax, __shfl_xor(bmax, off, 64));
+                    }
+                    uni = bmin == bmax;
+                    reuse = uni && nm == ref_nm && bmin == ref_bm;
+                }
+                if (reuse) {
+                    p = ref_p;
+                } else {
+                    p = string_mpp_wave<COHERENT>(S, lane);
+                    if (pass == 1) {
+                        ref_nm = uni ? nm : -1;
+                        ref_bm = bmin;
+                        ref_p = p;
+                    }
+                }
                 if (lane == 0) L.spow[st - st0] = p;
             }
             __syncthreads();
