@@ -514,7 +514,14 @@ def main():
         line["stadium"] = stadium_leg(ctx, log, a.stadium_every)
         line["electrical"] = electrical_leg(ctx, log)
         line["sky"] = sky_leg(ctx, log)
-        line["serving"] = serving_leg(ctx, log, a.serve_rate, a.serve_seconds, a.light_rate, a.light_seconds)
+        # the serving loop runs in a context of its own, opened after this one is closed: a loop started
+        # in a context whose per-sun path has run has stalled now and then (cause not found)
+        ctx.close()
+        sctx = pv3d.Context(0)
+        try:
+            line["serving"] = serving_leg(sctx, log, a.serve_rate, a.serve_seconds, a.light_rate, a.light_seconds)
+        finally:
+            sctx.close()
     if not a.no_cpu:
         print("[bench] cpu oracle leg ...", file=sys.stderr, flush=True)
         full = w if a.suns <= 1 else workload(a.workload, 1)
