@@ -1420,7 +1420,8 @@ struct TriSlot {
 };
 
 constexpr int kTriChunk = 64;     // triangles staged in LDS at a time
-constexpr int kStampList = 48;    // triangle slots listed per 8x8 stamp
+constexpr int kStampList = 48;    // triangle slots listed per 8x8 stamp (even: the test reads them in pairs)
+static_assert(kStampList % 2 == 0, "stamp lists are read two bytes at a time");
 
 struct TriBins {
     TriSlot* slot;      // [kTriChunk]
@@ -1666,16 +1667,27 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
             const bool all = nl > kStampList;
             const int32_t nt = all ? ns : nl;
             // only whether the sample is shaded is kept, and a covering depth
-            // below its threshold settles that: the search stops there
+            // below its threshold settles that: the search stops there. The
+            // triangles go two at a time (their list bytes read together, both
+            // slot reads in flight at once); testing the second after the first
+            // has hit changes nothing (C2 year 328 -> 322 ms)
             const int32_t thr = sp.thr[e];
             bool shaded = false;
-            for (int32_t u = 0; u < nt; u++) {
-                const int32_t q = all ? u : (int32_t)tb.list[st * kStampList + u];
-                const TriSlot& T = tb.slot[q];
-                const int64_t E0 = edge_at(T.ex[0], T.A[0], T.B[0], li256, lj256);
-                const int64_t E1 = edge_at(T.ex[1], T.A[1], T.B[1], li256, lj256);
-                const int64_t E2 = edge_at(T.ex[2], T.A[2], T.B[2], li256, lj256);
-                if ((E0 | E1 | E2) >= 0 && thr > (int32_t)depth_q(T.zx + T.gx * li + T.gy * lj)) {
+            for (int32_t u0 = 0; u0 < nt; u0 += 2) {
+                const uint32_t qp = all ? ((uint32_t)u0 | ((uint32_t)(u0 + 1) << 8))
+                                        : (uint32_t)*reinterpret_cast<const uint16_t*>(&tb.list[st * kStampList + u0]);
+                bool hit = false;
+#pragma unroll
+                for (int v = 0; v < 2; v++) {
+                    if (u0 + v < nt) {
+                        const TriSlot& T = tb.slot[(qp >> (8 * v)) & 255u];
+                        const int64_t E0 = edge_at(T.ex[0], T.A[0], T.B[0], li256, lj256);
+                        const int64_t E1 = edge_at(T.ex[1], T.A[1], T.B[1], li256, lj256);
+                        const int64_t E2 = edge_at(T.ex[2], T.A[2], T.B[2], li256, lj256);
+                        hit |= (E0 | E1 | E2) >= 0 && thr > (int32_t)depth_q(T.zx + T.gx * li + T.gy * lj);
+                    }
+                }
+                if (hit) {
                     shaded = true;
                     break;
                 }
@@ -1736,7 +1748,7 @@ struct TileLds {
     Rect todo[kMaxRects], failed[kMaxRects];
     TriSlot tslots[kTriChunk];
     int32_t tcnt[64];
-    uint8_t tlist[64 * kStampList];
+    alignas(4) uint8_t tlist[64 * kStampList];   // read two bytes at a time
     int32_t next, n_mods, mods_overflow, n_todo, n_failed;
     SparseShared sh;
 };
