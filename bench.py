@@ -30,6 +30,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+LEGS = ("batched", "c4", "trackers", "stadium", "electrical", "sky", "serving")
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,6 +52,9 @@ def parse():
     ap.add_argument("--no-materialised", action="store_true",
                     help="skip the extra one-step run of the materialised route")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched, C4, serving, tracker, stadium, electrical and sky legs")
+    ap.add_argument("--extra-legs", default="all",
+                    help="comma-separated extra legs to run (batched, c4, trackers, stadium, electrical, sky, serving); "
+                         "default all")
     ap.add_argument("--c4-every", type=int, default=50, help="C4 leg: every n-th sun of the year")
     ap.add_argument("--stadium-every", type=int, default=4, help="stadium leg: every n-th sun of the year")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="serving leg: arrivals per second")
@@ -507,21 +513,32 @@ def main():
     if not a.no_extra and a.route == "sparse" and a.suns <= 1 and a.workload == "c2":
         def log(msg):
             print(msg, file=sys.stderr, flush=True)
-        line["batched"] = batched_leg(ctx, w, sh, gh, res.energy.cpu().numpy(), res.power.cpu().numpy(),
-                                      line["year_seconds"], log)
-        line["c4_batched"] = c4_leg(ctx, a.c4_every, log)
-        line["trackers"] = tracker_leg(ctx, log)
-        line["stadium"] = stadium_leg(ctx, log, a.stadium_every)
-        line["electrical"] = electrical_leg(ctx, log)
-        line["sky"] = sky_leg(ctx, log)
-        # the serving loop runs in a context of its own, opened after this one is closed: a loop started
-        # in a context whose per-sun path has run has stalled now and then (cause not found)
-        ctx.close()
-        sctx = pv3d.Context(0)
-        try:
-            line["serving"] = serving_leg(sctx, log, a.serve_rate, a.serve_seconds, a.light_rate, a.light_seconds)
-        finally:
-            sctx.close()
+        legs = set(LEGS) if a.extra_legs == "all" else set(a.extra_legs.split(","))
+        if legs - set(LEGS):
+            raise SystemExit(f"unknown legs {sorted(legs - set(LEGS))}; known: {', '.join(LEGS)}")
+        if "batched" in legs:
+            line["batched"] = batched_leg(ctx, w, sh, gh, res.energy.cpu().numpy(), res.power.cpu().numpy(),
+                                          line["year_seconds"], log)
+        if "c4" in legs:
+            line["c4_batched"] = c4_leg(ctx, a.c4_every, log)
+        if "trackers" in legs:
+            line["trackers"] = tracker_leg(ctx, log)
+        if "stadium" in legs:
+            line["stadium"] = stadium_leg(ctx, log, a.stadium_every)
+        if "electrical" in legs:
+            line["electrical"] = electrical_leg(ctx, log)
+        if "sky" in legs:
+            line["sky"] = sky_leg(ctx, log)
+        if "serving" in legs:
+            # the serving loop runs in a context of its own, opened after this one is closed: a loop started
+            # in a context whose per-sun path has run has stalled now and then (cause not found)
+            ctx.close()
+            sctx = pv3d.Context(0)
+            try:
+                line["serving"] = serving_leg(sctx, log, a.serve_rate, a.serve_seconds, a.light_rate,
+                                              a.light_seconds)
+            finally:
+                sctx.close()
     if not a.no_cpu:
         print("[bench] cpu oracle leg ...", file=sys.stderr, flush=True)
         full = w if a.suns <= 1 else workload(a.workload, 1)
