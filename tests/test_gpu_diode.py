@@ -110,3 +110,11 @@ def test_set_diode_errors_and_reset(ctx):
     finally:
         ctx.release_scene(sh)
         ctx.release_generator(gh)
+
+
+def test_most_samples_per_cell_diode(ctx, oracle_lib):
+    """k = 255 (65,025 samples per cell): too many shaded-count levels for one solve per level, so
+    every string takes the per-lane form."""
+    w = W.random_tiny(81, n_boxes=6, n_loose=6, n_mod_side=2, map_n=256, k=255, n_sun=2)
+    got, ref = _compare(ctx, oracle_lib, _diode(w))
+    assert ref.counts.sum() > 100000 and got.energy[0] < got.energy[1]
