@@ -197,3 +197,23 @@ def test_c2_row_plant_sampled_suns_batched(ctx, oracle_lib):
     assert np.array_equal(g.counts, ref.counts)
     np.testing.assert_allclose(g.power, ref.power, rtol=1e-6, atol=0)
     _same(g, _plain(ctx, sp), "C2 batched vs per-sun path")
+
+
+def test_batched_at_the_largest_sizes(ctx, oracle_lib):
+    """The ABI's largest sizes in one launch: N = 16384, and k = 255 with ideal strings and with the
+    single-diode model. Every job equals the per-sun path, and its counts equal the oracle's."""
+    import dataclasses
+    big = W.random_tiny(81, n_boxes=6, n_loose=40, n_mod_side=3, map_n=16384, k=8, n_sun=2)
+    dense = W.random_tiny(81, n_boxes=6, n_loose=6, n_mod_side=2, map_n=256, k=255, n_sun=2)
+    diode = dataclasses.replace(dense, gen=dataclasses.replace(dense.gen, diode=W.DIODE_CELL), name="tiny81_diode")
+    ws = [big, dense, diode]
+    specs = [_spec(ctx, w) for w in ws]
+    got = ctx.evaluate_batched(specs)
+    for w, sp, g in zip(ws, specs, got):
+        # the per-sun path at its own tile size (128 texels at N = 16384): results do not depend on it
+        alone = ctx.evaluate(sp["scene"], sp["gen"], sp["generator"], sp["sweep"], sp["map_n"], sp["k"])
+        _same(g, alone, f"{w.name} N={w.map_n} k={w.k}")
+        ref = oracle_lib.evaluate(w.scene, w.gen, w.sweep, w.map_n, w.k)
+        assert np.array_equal(np.asarray(g.counts), ref.counts), w.name
+        assert int(ref.counts.sum()) > 1000
+    _say(f"[batched] largest sizes: identical to the per-sun path; stats {ctx.batch_stats()}")
