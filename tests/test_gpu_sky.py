@@ -154,3 +154,11 @@ def test_sky_view_edge_directions(ctx, oracle_lib):
     finally:
         ctx.release_scene(sh)
         ctx.release_generator(gh)
+
+
+def test_sky_view_most_samples_per_cell(ctx, oracle_lib):
+    """k = 255 (65,025 samples per cell): each direction's shaded share is a count over k^2 near its
+    largest; the factors stay bit-identical to the oracle's."""
+    w = W.random_tiny(81, n_boxes=6, n_loose=6, n_mod_side=2, map_n=256, k=255, n_sun=2)
+    svf = _sky(ctx, oracle_lib, w, 8, 256, 255)
+    assert svf.min() < 0.9
