@@ -74,3 +74,11 @@ def test_batched_trackers_match_the_per_sun_path(ctx):
         assert np.array_equal(np.asarray(b.power), a.power), w.name
         assert np.array_equal(np.asarray(b.energy), a.energy), w.name
         _say(f"[trackers] batched {w.name}: identical, shaded {int(a.counts.sum())}")
+
+
+def test_tracker_pair_most_samples_per_cell(ctx, oracle_lib):
+    """Two-axis trackers at k = 255 (65,025 samples per cell) on low winter suns, when the southern
+    tracker shades the northern one: each sun's posed modules, flags and counts as in the oracle."""
+    sw = W.make_sweep(W.LAT_DEG, [355], [8.5, 9.5, 14.5, 15.5], up_only=True)
+    got, ref = compare(ctx, oracle_lib, W.tracker_pair(kind=2, k=255, sweep=sw), maps=False, bits=True)
+    assert (ref.counts.sum(axis=1) > 0).sum() >= 2
