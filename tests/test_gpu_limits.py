@@ -1,4 +1,4 @@
-"""Parity at the largest sizes the C ABI accepts (needs an MI355X).
+"""Parity at the largest sizes the C ABI accepts, and for degenerate suns (needs an MI355X).
 
 - **N = 16384**, the largest depth picture. The full pictures are exported
   and compared texel by texel: 2 suns of 268 M texels.
@@ -28,3 +28,21 @@ def test_most_samples_per_cell(ctx, oracle_lib):
     assert w.k * w.gen.n_cv <= 4095 and w.k * w.gen.n_cu <= 4095
     got, ref = compare(ctx, oracle_lib, w, maps=True, bits=True)
     assert ref.counts.sum() > 100000
+
+
+def test_zenith_sun_horizon_sun_and_basis_switch(ctx, oracle_lib):
+    """Degenerate suns over a horizontal generator:
+    - exactly at the zenith: every box wall is edge-on, with no area in the picture, and the sun
+      lies along the modules' normal;
+    - exactly on the horizon: not up, so every output is zero;
+    - either side of the image basis switch (|d_z| = 0.9 and a hair below): both sides take the same
+      branch from the same input."""
+    import numpy as np
+    w = W.random_tiny(91, n_boxes=8, n_loose=10, n_mod_side=3, tilt_deg=0.0, map_n=256, k=4, n_sun=1)
+    a, b = np.sqrt(1.0 - 0.9 ** 2), 0.9 - 1e-9
+    dirs = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0], [a, 0.0, 0.9], [np.sqrt(1.0 - b * b), 0.0, b]])
+    n = len(dirs)
+    sw = W.Sweep(dirs, np.full(n, 800.0), np.full(n, 50.0), np.ones(n), np.zeros(n, np.int32), np.zeros(n))
+    got, ref = compare(ctx, oracle_lib, W.Workload("degenerate_suns", w.scene, w.gen, sw, 256, 4))
+    assert got.counts[0].sum() > 0 and got.counts[2].sum() > 0
+    assert got.counts[1].sum() == 0 and got.power[1] == 0.0 and got.power_ref[1] == 0.0
