@@ -46,3 +46,16 @@ def test_zenith_sun_horizon_sun_and_basis_switch(ctx, oracle_lib):
     got, ref = compare(ctx, oracle_lib, W.Workload("degenerate_suns", w.scene, w.gen, sw, 256, 4))
     assert got.counts[0].sum() > 0 and got.counts[2].sum() > 0
     assert got.counts[1].sum() == 0 and got.power[1] == 0.0 and got.power_ref[1] == 0.0
+
+
+@pytest.mark.parametrize("n_cu,n_cv", [(4095, 1), (1, 4095)])
+def test_most_cells_per_module_side(ctx, oracle_lib, n_cu, n_cv):
+    """4,095 cells along one module side at k = 1, the most the ABI takes: a module has more cells
+    than the tile kernel's per-wave LDS cell counters, so counts go to device memory directly."""
+    import dataclasses
+    import numpy as np
+    base = W.random_tiny(94, n_boxes=8, n_loose=30, n_mod_side=2, map_n=512, k=1, n_sun=4)
+    g = dataclasses.replace(base.gen, n_cu=n_cu, n_cv=n_cv, n_sub=3,
+                            cell_substring=(np.arange(n_cu * n_cv) % 3).astype(np.int32))
+    got, ref = compare(ctx, oracle_lib, W.Workload(f"cells_{n_cu}x{n_cv}", base.scene, g, base.sweep, 512, 1))
+    assert ref.counts.sum() > 1000
