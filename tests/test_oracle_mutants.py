@@ -10,6 +10,7 @@ from tests import test_oracle_pins as pins
 from tests import test_oracle_diode as dpins
 from tests import test_oracle_sky as spins
 from tests import test_oracle_trackers as tpins
+from tests import test_oracle_depth_origin as zpins
 
 SRC = open(O.SRC).read()
 
@@ -49,12 +50,17 @@ MUTANTS = {
     "sky_reference_obstructed": ("double sky = counts && P->svf ? P->svf[m * cpm + c] : 1.0;   /* reference: whole sky */\n"
                                  "                    g[nc++]",
                                  "double sky = P->svf ? P->svf[m * cpm + c] : 1.0;\n                    g[nc++]"),
+    "sphere_radius_full_diagonal": ("*radius = 0.5 * sqrt(dot3(dg, dg));\n}\n\nstatic v3 unit_normal",
+                                    "*radius = sqrt(dot3(dg, dg));\n}\n\nstatic v3 unit_normal"),
+    "depth_origin_shifted": ("V->znear = dot3(centre, V->d) - radius;", "V->znear = dot3(centre, V->d) - 0.25 * radius;"),
     "mpp_first_maximum_only": ("        if (!(p[q] >= p[q - 1]) || (q < OR_MPP_GRID && !(p[q] >= p[q + 1]))) continue;",
                                "        if (best > 0.0) break;\n"
                                "        if (!(p[q] >= p[q - 1]) || (q < OR_MPP_GRID && !(p[q] >= p[q + 1]))) continue;"),
 }
 
 PINS = [
+    (zpins.test_zenith_depths_of_horizontal_planes, {}),
+    (zpins.test_oblique_depths_of_planes_facing_the_sun, {}),
     (pins.test_c1_matches_exact_ray_casting, {}),
     (pins.test_c1_loss_closed_form, {"d_poa": 100.0, "want": 0.04670964}),
     (pins.test_string_power_is_best_operating_current, {}),
