@@ -15,6 +15,12 @@
 //     copies host outputs back, and frees the job's memory.
 // Nothing here allocates or frees device memory while a launch runs: the
 // arena, the slots and the tables are taken once, when the loop starts.
+// The thread never holds the server lock while it waits for the device, so
+// submit, poll, wait and cancel never queue behind a copy. Its copies run on
+// the context's lane-1 stream and the launch on a stream of its own, so that
+// the launch holds a hardware queue no other work of the library waits in.
+// While a HoldServing lives (another thread is about to wait for the whole
+// device) no job is admitted, so the live launch runs out of work and ends.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -107,13 +113,15 @@ struct Server {
     std::mutex mu;
     std::condition_variable cv, cv_done;
     bool quit = false;
+    int32_t hold = 0;                // HoldServing guards alive: admit nothing
     std::deque<SJob*> pending;
     std::map<uint64_t, std::unique_ptr<SJob>> jobs;
     std::map<uint64_t, int32_t> users;       // scene / generator handle -> jobs that read it
     uint64_t next_ticket = 1;
     pv3d_status fatal = PV3D_OK;
     // device side
-    hipStream_t kstream = nullptr, cstream = nullptr;
+    hipStream_t kstream = nullptr;   // the persistent launch
+    hipStream_t cstream = nullptr;   // copies: the context's lane-1 stream, not owned
     hipEvent_t kdone = nullptr;
     bool live = false;
     Buf arena_mem, slotmem, slotbufs, state, sched, jobtab, counters;
@@ -164,7 +172,6 @@ static void free_server(Ctx* c, Server* S) {
     if (S->staging) (void)hipHostFree(S->staging);
     if (S->kdone) (void)hipEventDestroy(S->kdone);
     if (S->kstream) (void)hipStreamDestroy(S->kstream);
-    if (S->cstream) (void)hipStreamDestroy(S->cstream);
     delete S;
 }
 
@@ -189,7 +196,8 @@ static pv3d_status start_server_parts(Ctx* c, Server* S) {
     if ((st = device_info(c, &S->dev))) return st;
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&S->kstream, hipStreamNonBlocking))) return hip_fail(e, "hipStreamCreate");
-    if ((e = hipStreamCreateWithFlags(&S->cstream, hipStreamNonBlocking))) return hip_fail(e, "hipStreamCreate");
+    S->cstream = c->lane_st[kLanes - 1];
+    if (!S->cstream) return fail(PV3D_EDEVICE, "the context has no copy stream for the serving loop");
     if ((e = hipEventCreateWithFlags(&S->kdone, hipEventDisableTiming))) return hip_fail(e, "hipEventCreate");
     const int64_t rec_cap = c->batch_slot_records;
     const int64_t bin_cap = 8 * rec_cap + 64 * (int64_t)kServeMaxMod + 65536;
@@ -265,8 +273,10 @@ static pv3d_status ensure_staging(Server* S, size_t need) {
     return PV3D_OK;
 }
 
-// Upload a job and publish its items (server lock held). False: it has to wait.
-static bool try_admit(Server* S, SJob* J, pv3d_status* err) {
+// Upload a job and publish its items (server lock held on entry and on
+// return, released while the copies run). False: it has to wait, or *err
+// says why it failed.
+static bool try_admit(Server* S, std::unique_lock<std::mutex>& lk, SJob* J, pv3d_status* err) {
     HostJob& h = J->h;
     const int64_t ns = h.job.n_sun;
     if (S->free_jslots.empty()) return false;
@@ -295,29 +305,38 @@ static bool try_admit(Server* S, SJob* J, pv3d_status* err) {
     job_constants(h, tab);
     const int32_t kk = h.job.params.k;
     const size_t need = 48 * (size_t)ns + 8 * tab.size() + sizeof(PJob) + 1024;
-    hipError_t e = hipSuccess;
-    if ((*err = ensure_staging(S, need))) return false;
-    char* sp = static_cast<char*>(S->staging);
-    char* sd = static_cast<char*>(S->staging_dev);
-    memcpy(sp, J->in.data(), 48 * (size_t)ns);          // sun (3 ns), dni, d_poa, dt: the device layout
-    char* tp = sp + al256(48 * (size_t)ns);
-    memcpy(tp, tab.data(), 8 * tab.size());
     PJob pj = make_pjob(h);
     pj.n_items = (int32_t)ns;                           // every sun is an item: below the horizon it only writes zeros
     pj.done_target = S->done_base[(size_t)j] + (uint32_t)ns;
     pj.ovf_base = S->ovf_base[(size_t)j];
     pj.seq = J->seq;
-    char* jp = tp + al256(8 * tab.size());
-    memcpy(jp, &pj, sizeof(PJob));
-    const size_t to = (size_t)(tp - sp), jo = (size_t)(jp - sp);
-    if (ns > 0) e = copy_nocu(h.d_sun, sd, 48 * (size_t)ns, S->cstream);
-    if (!e) e = copy_nocu(h.d_sphere, sd + to, 32, S->cstream);
-    if (!e) e = copy_nocu(h.d_fu, sd + to + 32, 8 * (size_t)kk * h.g->n_cu, S->cstream);
-    if (!e) e = copy_nocu(h.d_fv, sd + to + 32 + 8 * (size_t)kk * h.g->n_cu, 8 * (size_t)kk * h.g->n_cv, S->cstream);
-    if (!e) e = copy_nocu(static_cast<PJob*>(S->jobtab.ptr) + j, sd + jo, sizeof(PJob), S->cstream);
-    if (!e) e = hipStreamSynchronize(S->cstream);
-    if (e) {
-        *err = hip_fail(e, "upload of a serving job");
+    // only this thread touches the staging buffer and the reserved arena block
+    lk.unlock();
+    hipError_t e = hipSuccess;
+    pv3d_status st = ensure_staging(S, need);
+    if (!st) {
+        char* sp = static_cast<char*>(S->staging);
+        char* sd = static_cast<char*>(S->staging_dev);
+        memcpy(sp, J->in.data(), 48 * (size_t)ns);          // sun (3 ns), dni, d_poa, dt: the device layout
+        char* tp = sp + al256(48 * (size_t)ns);
+        memcpy(tp, tab.data(), 8 * tab.size());
+        char* jp = tp + al256(8 * tab.size());
+        memcpy(jp, &pj, sizeof(PJob));
+        const size_t to = (size_t)(tp - sp), jo = (size_t)(jp - sp);
+        if (ns > 0) e = copy_nocu(h.d_sun, sd, 48 * (size_t)ns, S->cstream);
+        if (!e) e = copy_nocu(h.d_sphere, sd + to, 32, S->cstream);
+        if (!e) e = copy_nocu(h.d_fu, sd + to + 32, 8 * (size_t)kk * h.g->n_cu, S->cstream);
+        if (!e) e = copy_nocu(h.d_fv, sd + to + 32 + 8 * (size_t)kk * h.g->n_cu, 8 * (size_t)kk * h.g->n_cv, S->cstream);
+        if (!e) e = copy_nocu(static_cast<PJob*>(S->jobtab.ptr) + j, sd + jo, sizeof(PJob), S->cstream);
+        if (!e) e = hipStreamSynchronize(S->cstream);
+        if (e) st = hip_fail(e, "upload of a serving job");
+    }
+    lk.lock();
+    if (st) {
+        S->arena.release(J->off, J->bytes);
+        S->free_jslots.push_back(j);
+        J->jslot = -1;
+        *err = st;
         return false;
     }
     if (ns == 0) {           // nothing to evaluate: zero energy
@@ -336,14 +355,16 @@ static bool try_admit(Server* S, SJob* J, pv3d_status* err) {
     return true;
 }
 
-// A job's tag came back (server lock held by the caller, released around
-// work that needs the context).
+// A job's tag came back (server lock held by the caller; released while the
+// device is waited for, and around work that needs the context).
 static void finish(Server* S, std::unique_lock<std::mutex>& lk, SJob* J, bool overflow) {
     HostJob& h = J->h;
     const int64_t ns = h.job.n_sun;
     const int32_t j = J->jslot;
     pv3d_status st = PV3D_OK;
     hipError_t e = hipSuccess;
+    const bool cancelled = J->cancel;    // host outputs of a cancelled job are not written
+    lk.unlock();                     // J stays live until this returns: no other thread frees it
     if (ns == 0) {
         static const double zero[2] = {0.0, 0.0};
         if (h.job.out.on_device) {
@@ -359,37 +380,36 @@ static void finish(Server* S, std::unique_lock<std::mutex>& lk, SJob* J, bool ov
         // suns that exceeded a slot's capacity (their power marked NaN by the kernel): the
         // per-sun path evaluates each of them again, one sun per call, and the job's energy
         // is summed again
-        lk.unlock();
-        {
-            std::lock_guard<std::recursive_mutex> cl(S->c->mu);
-            S->c->stream_in_use = S->cstream;
-            pv3d_params p1 = h.job.params;
-            p1.tile = h.tile;
-            std::vector<double> pw((size_t)ns);
-            if ((st = ensure_staging(S, 8 * (size_t)ns)) == PV3D_OK) {
-                e = copy_nocu(S->staging_dev, h.d_power, 8 * (size_t)ns, S->cstream);
-                if (!e) e = hipStreamSynchronize(S->cstream);
-                if (!e) memcpy(pw.data(), S->staging, 8 * (size_t)ns);
-            }
-            for (int64_t t = 0; t < ns && !st && !e; t++) {
-                if (!std::isnan(pw[(size_t)t])) continue;
-                st = S->c->run_path(*h.sc, *h.g, p1, h.job.sun_xyz + 3 * t, 1, h.d_sun + 3 * t, h.d_dni + t,
-                                    h.d_dpoa + t, h.d_dt + t, h.d_counts + t * h.cells, h.d_power + t, h.d_pref + t,
-                                    h.d_energy, nullptr, nullptr, S->cstream);
-            }
-            if (!st && !e) e = launch_energy(ns, h.d_power, h.d_pref, h.d_dt, h.d_energy, S->cstream);
-            if (!st && !e) e = hipStreamSynchronize(S->cstream);
-            uint32_t ov = 0;
-            if (!st && !e && (st = ensure_staging(S, 4)) == PV3D_OK) {
-                e = copy_nocu(S->staging_dev, static_cast<uint32_t*>(S->counters.ptr) + kServeJobs + j, 4, S->cstream);
-                if (!e) e = hipStreamSynchronize(S->cstream);
-                if (!e) memcpy(&ov, S->staging, 4);
-            }
-            if (!st && !e) S->ovf_base[(size_t)j] = ov;
+        std::lock_guard<std::recursive_mutex> cl(S->c->mu);
+        S->c->stream_in_use = S->cstream;
+        pv3d_params p1 = h.job.params;
+        p1.tile = h.tile;
+        std::vector<double> pw((size_t)ns);
+        if ((st = ensure_staging(S, 8 * (size_t)ns)) == PV3D_OK) {
+            e = copy_nocu(S->staging_dev, h.d_power, 8 * (size_t)ns, S->cstream);
+            if (!e) e = hipStreamSynchronize(S->cstream);
+            if (!e) memcpy(pw.data(), S->staging, 8 * (size_t)ns);
         }
-        lk.lock();
+        for (int64_t t = 0; t < ns && !st && !e; t++) {
+            if (!std::isnan(pw[(size_t)t])) continue;
+            st = S->c->run_path(*h.sc, *h.g, p1, h.job.sun_xyz + 3 * t, 1, h.d_sun + 3 * t, h.d_dni + t,
+                                h.d_dpoa + t, h.d_dt + t, h.d_counts + t * h.cells, h.d_power + t, h.d_pref + t,
+                                h.d_energy, nullptr, nullptr, S->cstream);
+            bool ovf = false;
+            if (!st) st = S->c->read_overflow(1, S->cstream, &ovf);
+            if (!st && ovf) st = fail(PV3D_ERANGE, "a sun of a serving job overflows the per-sun path's buffers");
+        }
+        if (!st && !e) e = launch_energy(ns, h.d_power, h.d_pref, h.d_dt, h.d_energy, S->cstream);
+        if (!st && !e) e = hipStreamSynchronize(S->cstream);
+        uint32_t ov = 0;
+        if (!st && !e && (st = ensure_staging(S, 4)) == PV3D_OK) {
+            e = copy_nocu(S->staging_dev, static_cast<uint32_t*>(S->counters.ptr) + kServeJobs + j, 4, S->cstream);
+            if (!e) e = hipStreamSynchronize(S->cstream);
+            if (!e) memcpy(&ov, S->staging, 4);
+        }
+        if (!st && !e) S->ovf_base[(size_t)j] = ov;
     }
-    if (!st && !e && !h.job.out.on_device && ns > 0 && !J->cancel) {
+    if (!st && !e && !h.job.out.on_device && ns > 0 && !cancelled) {
         // one copy of the job's output region (counts, powers, energy lie in this order) into
         // pinned staging, then into the caller's arrays
         const char* first = h.job.out.cell_counts ? reinterpret_cast<const char*>(h.d_counts)
@@ -408,6 +428,7 @@ static void finish(Server* S, std::unique_lock<std::mutex>& lk, SJob* J, bool ov
             }
         }
     }
+    lk.lock();
     if (e) st = hip_fail(e, "serving outputs");
     S->arena.release(J->off, J->bytes);
     S->done_base[(size_t)j] += (uint32_t)ns;
@@ -464,18 +485,20 @@ static void service(Server* S) {
             S->live = false;
             PSched got;
             memset(&got, 0, sizeof(got));
+            lk.unlock();
             bool ok = q == hipSuccess && ensure_staging(S, sizeof(PSched)) == PV3D_OK &&
                       copy_nocu(S->staging_dev, S->sched.ptr, sizeof(PSched), S->cstream) == hipSuccess &&
                       hipStreamSynchronize(S->cstream) == hipSuccess;
             if (ok) memcpy(&got, S->staging, sizeof(PSched));
+            lk.lock();
             if (!ok || got.abort) {
                 S->fatal = fail(PV3D_EDEVICE, "the serving launch stopped making progress");
                 fail_live(S, S->fatal);
             }
             continue;                        // look at the tags once more before starting again
         }
-        // 3. admissions, in submission order
-        while (!S->pending.empty() && !S->fatal) {
+        // 3. admissions, in submission order (none while a HoldServing lives)
+        while (!S->pending.empty() && !S->fatal && S->hold == 0) {
             SJob* J = S->pending.front();
             if (J->cancel) {
                 S->pending.pop_front();
@@ -486,7 +509,7 @@ static void service(Server* S) {
                 continue;
             }
             pv3d_status err = PV3D_OK;
-            if (!try_admit(S, J, &err)) {
+            if (!try_admit(S, lk, J, &err)) {
                 if (err) {
                     S->pending.pop_front();
                     J->result = err;
@@ -556,6 +579,24 @@ static void service(Server* S) {
     }
 }
 
+HoldServing::HoldServing(Ctx* ctx) : c(ctx) {
+    Server* S = c->server;
+    if (!S) {
+        c = nullptr;
+        return;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->hold++;
+}
+
+HoldServing::~HoldServing() {
+    if (!c || !c->server) return;
+    Server* S = c->server;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->hold--;
+    S->cv.notify_all();
+}
+
 }  // namespace pv3d
 
 void pv3d_server_stop(pv3d_ctx* ctx) {
@@ -588,6 +629,9 @@ pv3d_status pv3d_submit(pv3d_ctx* ctx, const pv3d_job* job, uint64_t* ticket) {
     if (h.g->n_mod > kServeMaxMod) return fail(PV3D_ERANGE, "the serving loop takes at most %d modules per job", kServeMaxMod);
     if (h.n_tiles > kServeMaxTiles) return fail(PV3D_ERANGE, "the serving loop takes at most %d raster tiles per job", kServeMaxTiles);
     if (h.job.n_sun > (int64_t)kFeedCap) return fail(PV3D_ERANGE, "the serving loop takes at most %u suns per job", kFeedCap);
+    if (!ctx->server && ctx->per_sun_ran)
+        return fail(PV3D_EINVAL, "the serving loop starts only in a context whose per-sun path (pv3d_evaluate, "
+                                 "pv3d_sky_view) has not run: serve from a context of its own");
     if ((st = start_server(ctx))) return st;
     Server* S = ctx->server;
     const bool dev_out = h.job.out.on_device != 0;

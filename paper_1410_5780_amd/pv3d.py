@@ -102,7 +102,8 @@ def lib():
         L.pv3d_profile_enable.argtypes = [_P, _u32]
         L.pv3d_profile_read.argtypes = [_P, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
         L.pv3d_profile_sample.argtypes = [_P, _i32]
-        for f in ("pv3d_profile_enable", "pv3d_profile_read", "pv3d_profile_sample", "pv3d_create", "pv3d_scene_load", "pv3d_scene_release", "pv3d_generator_define",
+        L.pv3d_profile_busy.argtypes = [_P, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]
+        for f in ("pv3d_profile_enable", "pv3d_profile_read", "pv3d_profile_sample", "pv3d_profile_busy", "pv3d_create", "pv3d_scene_load", "pv3d_scene_release", "pv3d_generator_define",
                   "pv3d_generator_define_tracked", "pv3d_generator_release", "pv3d_generator_set_diode", "pv3d_generator_set_sky", "pv3d_sky_view",
                   "pv3d_sun_cooper", "pv3d_evaluate", "pv3d_evaluate_batched",
                   "pv3d_autotune", "pv3d_batch_stats", "pv3d_batch_limits", "pv3d_serve_stats",
@@ -211,6 +212,12 @@ class Context:
         """(summed milliseconds, launches) of one stage since profiling was enabled."""
         ms, n = _f64(), _i64()
         _check(lib().pv3d_profile_read(self.h, stage, ctypes.byref(ms), ctypes.byref(n)), self.h)
+        return ms.value, n.value
+
+    def profile_busy(self, stage: int):
+        """(milliseconds during which at least one timed launch of the stage ran, suns covered)."""
+        ms, n = _f64(), _i64()
+        _check(lib().pv3d_profile_busy(self.h, stage, ctypes.byref(ms), ctypes.byref(n)), self.h)
         return ms.value, n.value
 
     def load_scene(self, scene) -> int:
@@ -344,12 +351,15 @@ class Context:
         keep.append(arrs)
         n = arrs[0].shape[0]
         if device:
+            # no fill: the library writes every element (the batched form clears the outputs on its
+            # stream first; the serving loop clears each sun's counts and writes every power), and a
+            # fill on torch's stream would not be ordered before the serving loop's writes
             import torch
             dev = torch.device("cuda", torch.cuda.current_device())
-            counts = torch.zeros((n, g.n_cells), dtype=torch.int32, device=dev) if spec.get("counts", True) else None
-            pw = torch.zeros(n, dtype=torch.float64, device=dev)
-            pr = torch.zeros(n, dtype=torch.float64, device=dev)
-            en = torch.zeros(2, dtype=torch.float64, device=dev)
+            counts = torch.empty((n, g.n_cells), dtype=torch.int32, device=dev) if spec.get("counts", True) else None
+            pw = torch.empty(n, dtype=torch.float64, device=dev)
+            pr = torch.empty(n, dtype=torch.float64, device=dev)
+            en = torch.empty(2, dtype=torch.float64, device=dev)
         else:
             counts = np.zeros((n, g.n_cells), np.uint32) if spec.get("counts", True) else None
             pw, pr, en = np.zeros(n), np.zeros(n), np.zeros(2)

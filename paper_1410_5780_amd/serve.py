@@ -73,22 +73,30 @@ def run_stream(ctx: pv3d.Context, reqs: List[W.Request], seed: int = 5, k: int =
         pool.scene(r.scene_id)
         pool.generator(r.n_cells)
     done: Dict[int, float] = {}
+    failed: Dict[int, str] = {}
     outstanding: Dict[int, int] = {}
     lock = threading.Lock()
     stop = threading.Event()
 
     def watcher():
+        # a job that fails is recorded, never raised here: an exception would end this thread
+        # and leave the stream waiting for it forever
         last = time.perf_counter()
         while not stop.is_set() or outstanding:
             with lock:
                 items = list(outstanding.items())
             for t, i in items:
-                if ctx.poll(t):
+                try:
+                    if not ctx.poll(t):
+                        continue
                     now = time.perf_counter()
                     ctx.wait(t)
-                    with lock:
-                        done[i] = now
-                        del outstanding[t]
+                except pv3d.Pv3dError as e:
+                    now = time.perf_counter()
+                    failed[i] = str(e)
+                with lock:
+                    done[i] = now
+                    del outstanding[t]
             if log and time.perf_counter() - last > 2.0:
                 last = time.perf_counter()
                 log(f"[serve] {len(done)} of {len(reqs)} done, {len(outstanding)} running or waiting")
@@ -99,30 +107,34 @@ def run_stream(ctx: pv3d.Context, reqs: List[W.Request], seed: int = 5, k: int =
     samples = 0
     t0 = time.perf_counter()
     th.start()
-    for i, r in enumerate(reqs):
-        target = t0 + r.arrival_s
-        while True:
-            now = time.perf_counter()
-            if now >= target:
-                break
-            time.sleep(min(target - now, 0.001))
-        gh, g = pool.generator(r.n_cells)
-        spec = dict(scene=pool.scene(r.scene_id), gen=gh, generator=g, sweep=yr.subset(r.sun_idx),
-                    map_n=r.map_n, k=k, counts=False)
-        arrival[i] = time.perf_counter()
-        t = ctx.submit(spec, device=True)
-        samples += g.n_cells * k * k * len(r.sun_idx)
-        with lock:
-            outstanding[t] = i
-    stop.set()
-    th.join()
+    try:
+        for i, r in enumerate(reqs):
+            target = t0 + r.arrival_s
+            while True:
+                now = time.perf_counter()
+                if now >= target:
+                    break
+                time.sleep(min(target - now, 0.001))
+            gh, g = pool.generator(r.n_cells)
+            spec = dict(scene=pool.scene(r.scene_id), gen=gh, generator=g, sweep=yr.subset(r.sun_idx),
+                        map_n=r.map_n, k=k, counts=False)
+            arrival[i] = time.perf_counter()
+            t = ctx.submit(spec, device=True)
+            samples += g.n_cells * k * k * len(r.sun_idx)
+            with lock:
+                outstanding[t] = i
+    finally:
+        stop.set()
+        th.join()
+    if failed:
+        raise RuntimeError(f"{len(failed)} of {len(reqs)} serving jobs failed, first: {next(iter(failed.values()))}")
     t1 = time.perf_counter()
     lat = np.array([done[i] - arrival[i] for i in range(len(reqs))])
     st = ctx.serve_stats()
     out = {"requests": len(reqs), "p50_ms": float(np.percentile(lat, 50) * 1e3),
            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
            "wall_s": t1 - t0, "offered_s": reqs[-1].arrival_s if reqs else 0.0,
-           "tests_per_s": samples / (t1 - t0), "suns": int(sum(len(r.sun_idx) for r in reqs)),
+           "tests_per_s": samples / (t1 - t0), "tests": samples, "suns": int(sum(len(r.sun_idx) for r in reqs)),
            "launches": st["launches"], "scene_loads": pool.loads}
     if log:
         log(f"[serve] {out}")

@@ -1,6 +1,7 @@
 """Serving loop: jobs submitted while others run share one live persistent
 launch. Each job's result must be the same, bit for bit, alone (the per-sun
-path) and in the mix (needs an MI355X)."""
+path) and in the mix, and must match the CPU oracle: counts equal, powers and
+energies within 1e-6 relative (needs an MI355X)."""
 import sys
 import time
 
@@ -51,6 +52,21 @@ def _same(a, b, what):
     assert np.array_equal(np.asarray(a.energy), np.asarray(b.energy)), f"{what}: energy differs"
 
 
+def _oracle_same(got, w, oracle_lib, what, ref=None):
+    """Served result against the oracle on the same inputs: counts bit-exact, powers and
+    energy within 1e-6 relative (they are in fact identical)."""
+    if ref is None:
+        ref = oracle_lib.evaluate(w.scene, w.gen, w.sweep, w.map_n, w.k)
+    c = np.asarray(got.counts.cpu().numpy().view(np.uint32) if hasattr(got.counts, "cpu") else got.counts)
+    if not np.array_equal(c, ref.counts):
+        bad = np.argwhere(c != ref.counts)
+        raise AssertionError(f"{what}: counts differ from the oracle at {len(bad)} cells, first {bad[:5].tolist()}")
+    for name in ("power", "power_ref", "energy"):
+        a = getattr(got, name)
+        a = a.cpu().numpy() if hasattr(a, "cpu") else np.asarray(a)
+        assert np.allclose(a, getattr(ref, name), rtol=1e-6, atol=0), f"{what}: {name} differs from the oracle"
+
+
 def _mix():
     ws = [W.random_tiny(80 + i, n_boxes=6 + i, n_loose=20 + 5 * i, n_mod_side=2 + i % 2, map_n=128 + 40 * i,
                         k=2 + i % 3, n_sun=5 + i) for i in range(6)]
@@ -60,13 +76,14 @@ def _mix():
     return ws
 
 
-def test_results_same_alone_and_in_the_mix(ctx):
+def test_results_same_alone_and_in_the_mix(ctx, oracle_lib):
     ws = _mix()
     specs = [_spec(ctx, w, tile=(32 if i % 3 == 1 else 0)) for i, w in enumerate(ws)]
     _say(f"[serve] {len(specs)} jobs submitted together")
     tickets = [ctx.submit(sp) for sp in specs]
     got = [ctx.wait(t) for t in tickets]
-    for i, (sp, g) in enumerate(zip(specs, got)):
+    for i, (w, sp, g) in enumerate(zip(ws, specs, got)):
+        _oracle_same(g, w, oracle_lib, f"job {i} ({w.name})")
         _same(g, _alone(ctx, sp), f"job {i}")
     st = ctx.serve_stats()
     _say(f"[serve] stats {st}")
@@ -126,17 +143,21 @@ def _tiny_year(c, seed=90, every=2):
     return w, _spec(c, w)
 
 
-def test_admission_by_hbm_budget(small_ctx):
-    """Jobs that fit the arena a few at a time wait for memory and all complete with the same
-    results; a job that can never fit is refused with ENOMEM."""
+def _oracle_ref(w, oracle_lib):
+    return oracle_lib.evaluate(w.scene, w.gen, w.sweep, w.map_n, w.k)
+
+
+def test_admission_by_hbm_budget(small_ctx, oracle_lib):
+    """Jobs that fit the arena a few at a time wait for memory and all complete with the
+    oracle's results; a job that can never fit is refused with ENOMEM."""
     from paper_1410_5780_amd import pv3d
     c = small_ctx
     w, sp = _tiny_year(c)
-    ref = _alone(c, sp)
+    ref = _oracle_ref(w, oracle_lib)
     tickets = [c.submit(sp) for _ in range(6)]
     got = [c.wait(t) for t in tickets]
     for g in got:
-        _same(g, ref, "budget-limited job")
+        _oracle_same(g, w, oracle_lib, "budget-limited job", ref)
     yr = W.year_sweep()
     many = W.Sweep(*(np.tile(a, (200,) + (1,) * (a.ndim - 1)) for a in (yr.sun_xyz, yr.dni, yr.d_poa, yr.dt_h,
                                                                           yr.day, yr.hour)))
@@ -146,12 +167,12 @@ def test_admission_by_hbm_budget(small_ctx):
     _say(f"[serve] budget stats {c.serve_stats()}")
 
 
-def test_cancel(small_ctx):
+def test_cancel(small_ctx, oracle_lib):
     """A job waiting for memory is cancelled before it runs; the others are unaffected."""
     from paper_1410_5780_amd import pv3d
     c = small_ctx
     w, sp = _tiny_year(c, every=1)                       # about 9.5 MB of counts: two fill the arena
-    ref = _alone(c, sp)
+    ref = _oracle_ref(w, oracle_lib)
     ta, tb, tc, td = (c.submit(sp) for _ in range(4))
     c.cancel(td)                                          # still waiting for memory
     ra = c.wait(ta)
@@ -159,36 +180,48 @@ def test_cancel(small_ctx):
         c.wait(td)
     assert e.value.code == pv3d.ECANCELED
     for t in (tb, tc):
-        _same(c.wait(t), ref, "job next to a cancelled one")
-    _same(ra, ref, "first job")
+        _oracle_same(c.wait(t), w, oracle_lib, "job next to a cancelled one", ref)
+    _oracle_same(ra, w, oracle_lib, "first job", ref)
     with pytest.raises(pv3d.Pv3dError) as e:
         c.wait(td)                                        # forgotten
     assert e.value.code == pv3d.ENOENT
 
 
-def test_device_outputs(ctx):
+def test_device_outputs(ctx, oracle_lib):
     import torch
     ws = _mix()[:4]
     specs = [_spec(ctx, w) for w in ws]
     tickets = [ctx.submit(sp, device=True) for sp in specs]
     got = [ctx.wait(t) for t in tickets]
     torch.cuda.synchronize()
-    for sp, g in zip(specs, got):
+    for w, sp, g in zip(ws, specs, got):
+        _oracle_same(g, w, oracle_lib, f"device outputs of {w.name}")
         a = _alone(ctx, sp)
         assert np.array_equal(g.counts.cpu().numpy().view(np.uint32), a.counts)
         assert np.array_equal(g.power.cpu().numpy(), a.power)
         assert np.array_equal(g.energy.cpu().numpy(), a.energy)
 
 
-@pytest.mark.skip(reason="in one run this sequence waited more than 180 s and was stopped; the cause of the "
-                         "serving stall after the per-sun path in the same context is not found, so the case "
-                         "stays off the GPU until it is")
+def test_serving_is_refused_after_the_per_sun_path(ctx):
+    """A context whose per-sun path has run does not start a serving loop: submit returns
+    EINVAL and names the remedy, a context of its own."""
+    from paper_1410_5780_amd import pv3d
+    w = W.c1_tiny(d_poa=100.0)
+    sp = _spec(ctx, w)
+    _alone(ctx, sp)
+    with pytest.raises(pv3d.Pv3dError) as e:
+        ctx.submit(sp)
+    assert e.value.code == pv3d.EINVAL and "context of its own" in str(e.value)
+
+
+@pytest.mark.skip(reason="switched off: after the per-sun path had run in the same context, one request of "
+                         "this burst waited 173 s and held the submission of the next one that long (all "
+                         "results correct); the cause is not found, so pv3d_submit refuses to start the loop "
+                         "in such a context")
 def test_serving_after_the_per_sun_path_in_the_same_context(ctx):
     """A context that has run the per-sun path on its lanes, then starts its serving loop:
     every request of a burst of the configured stream completes, and the per-sun path
-    still gives the same results with the loop running. (Now and then one job of the
-    burst waits about 20 s in this sequence, a stall whose cause is not found; the bound
-    below catches a loop that stops for good.)"""
+    still gives the same results with the loop running."""
     from paper_1410_5780_amd import serve
     yr = W.year_sweep()
     w = W.c2_row_plant(sweep=yr.subset(np.arange(0, yr.n, 10)))
@@ -205,7 +238,7 @@ def test_serving_after_the_per_sun_path_in_the_same_context(ctx):
     _same(again, first, "per-sun path with the serving loop started")
 
 
-def test_suns_beyond_slot_capacity_are_evaluated_again(ctx):
+def test_suns_beyond_slot_capacity_are_evaluated_again(ctx, oracle_lib):
     """Slots of 64 records: the suns of a scene with hundreds of loose triangles overflow them,
     and the host evaluates just those suns again on the per-sun path. Every served result
     equals the per-sun path's, next to a job whose suns fit."""
@@ -215,4 +248,5 @@ def test_suns_beyond_slot_capacity_are_evaluated_again(ctx):
     served = [ctx.wait(t) for t in [ctx.submit(sp) for sp in specs]]
     for w, sp, got in zip(ws, specs, served):
         _same(got, _alone(ctx, sp), f"{w.name} served with slots of 64 records")
+        _oracle_same(got, w, oracle_lib, f"{w.name} served with slots of 64 records")
     _say(f"[serve] overflow stats {ctx.serve_stats()}")
