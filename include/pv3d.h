@@ -183,7 +183,7 @@ typedef struct {
     int32_t k;         /* k x k sample points per cell (Sec. 2 Step 3 uses 3 x 3) */
     uint32_t flags;    /* PV3D_EXPORT_* */
     int32_t tile;      /* raster tile edge in texels: 0 = library's choice (64 up to map_n
-                          4096, else 128; 64 in the batched form), else 32/64/128
+                          8192, else 128; 64 in the batched form), else 32/64/128
                           (batched form: 32/64) */
     int32_t bin_limit; /* a triangle overlapping more tiles than this is not binned; every
                           tile checks it instead. 0 = library's choice (256), else 1..256 */
@@ -332,6 +332,9 @@ pv3d_status pv3d_batch_stats(pv3d_ctx* ctx, int64_t out[7]);
  * when the job completes; device outputs are written by the device while the
  * job runs. The job's scene and generator cannot be released until it ends
  * (EBUSY). Limits: at most 4096 modules and 65536 raster tiles per job.
+ * The loop starts only in a context whose per-sun path (pv3d_evaluate,
+ * pv3d_sky_view) has not run, and EINVAL says so otherwise: serve from a
+ * context of its own (the per-sun path may run in it once the loop runs).
  * EBUSY: 65536 jobs wait already; ENOMEM: the job's data can never fit the
  * arena. ticket identifies the job. */
 pv3d_status pv3d_submit(pv3d_ctx* ctx, const pv3d_job* job, uint64_t* ticket);
@@ -365,6 +368,13 @@ pv3d_status pv3d_serve_stats(pv3d_ctx* ctx, int64_t out[4]);
 #define PV3D_N_STAGES 7
 pv3d_status pv3d_profile_enable(pv3d_ctx* ctx, uint32_t stage_mask);
 pv3d_status pv3d_profile_read(pv3d_ctx* ctx, int32_t stage, double* total_ms, int64_t* launches);
+/* The time during which at least one timed launch of the stage ran (the
+ * union of their event intervals, so launches of the two lanes that overlap
+ * count once: the stage's exclusive share of the sweep), in milliseconds, and
+ * the suns those launches covered (a launch covers a group of up to 8 suns).
+ * Meaningful when every launch is timed (pv3d_profile_sample 1). Waits for
+ * the recorded work. EINVAL: bad stage. */
+pv3d_status pv3d_profile_busy(pv3d_ctx* ctx, int32_t stage, double* busy_ms, int64_t* suns);
 /* Record only every n-th launch of each profiled stage (n >= 1; 1 after
  * pv3d_create): the events sit between kernels of the stream and hold back
  * the overlap of the two lanes, so a sample disturbs a long sweep less than

@@ -151,6 +151,31 @@ struct SceneDev {
 };
 constexpr int kTriBlock = 256;
 
+// ---- group launches of the per-sun path ----------------------------------
+// Up to kMaxGroup consecutive suns share each launch of the per-sun path
+// (triangle set-up, pair count, scan, pair scatter, tile pass), so the five
+// dependent launches and their ramp-up and drain are paid once per group,
+// and every launch has a group's work to spread over the GPU. Each sun keeps
+// its own bins, records and outputs; nothing is shared between the suns of a
+// group, so every result is the one the sun gets alone.
+constexpr int kMaxGroup = 8;
+
+// One sun of a group: the descriptors live in device memory, so the kernels
+// take this sun's buffers by reference without copying them.
+struct GroupSun {
+    BinBuffers bb;           // its records, bins, tile counters, work list and pair space
+    TileOut out;             // its counts, flags and picture
+    GenDev g;                // the generator as it sees it (trackers: its posed modules)
+    const uint32_t* tmask;   // its tile mask (nullptr: every tile)
+    int64_t s;               // its index in the sweep
+};
+
+struct SunGroup {
+    int32_t n;               // suns in the group, 1..kMaxGroup
+    int32_t pad[3];
+    GroupSun sun[kMaxGroup];
+};
+
 // ---- persistent launch: every (job, sun) item of a batch in one launch ----
 // Phases of one item, in order; a phase is split into units that any
 // workgroup may take.
@@ -271,30 +296,27 @@ hipError_t launch_sample_tables(double* fu, double* fv, int32_t k, int32_t n_cu,
 hipError_t launch_setup(const double* sun, int64_t n_sun, const double* dni, const GenDev& g,
                         const double* sphere, int32_t n, View* views, double* beam, int32_t* bias,
                         const TileGrid& tg, uint32_t* tmask, hipStream_t st);
-hipError_t launch_tri_setup(int64_t s, const View* views, const SceneDev& sc, const GenDev& g,
-                            const int32_t* bias, int32_t n, const BinBuffers& bb, SunCounters* ctr,
-                            const uint32_t* tmask, hipStream_t st);
-hipError_t launch_bin_scan(int32_t n_tiles, const BinBuffers& bb, hipStream_t st);
 hipError_t launch_pose(const double* sun, int64_t n_sun, const Module* rest, int32_t n_mod, const TrackerDev* trk,
                        const int32_t* mod_trk, Module* posed, hipStream_t st);
 hipError_t launch_box_sphere(const double lo[3], const double hi[3], double* sphere, hipStream_t st);
-hipError_t launch_pair_count(const BinBuffers& bb, const uint32_t* tmask, int32_t grid, hipStream_t st);
-hipError_t launch_pair_scatter(const BinBuffers& bb, const uint32_t* tmask, int32_t grid, hipStream_t st);
-hipError_t launch_bin_scatter(int64_t s, const BinBuffers& bb, int32_t n_mod, SunCounters* ctr,
-                              int32_t grid, const uint32_t* tmask, hipStream_t st);
-hipError_t launch_raster(int64_t s, const View* views, const BinBuffers& bb, const SunCounters* ctr,
-                         int32_t n, const GenDev& g, const int32_t* bias, const double* fu,
-                         const double* fv, int32_t k, const TileOut& out, const uint32_t* tmask,
-                         int32_t n_cu, int32_t cap_per_cu, hipStream_t st);
-size_t bin_lds_bytes(int32_t n_tiles);
-hipError_t configure_kernels(size_t max_lds);
+// Group launches: grp points to the group's descriptor in device memory, n_sun is grp->n
+// (known on the host), the arguments after it are shared by every sun of the group.
+hipError_t launch_tri_setup_group(const SunGroup* grp, int32_t n_sun, const View* views, const SceneDev& sc,
+                                  const GenDev& g, const int32_t* bias, int32_t n, SunCounters* ctr, hipStream_t st);
+hipError_t launch_pair_count_group(const SunGroup* grp, int32_t grid, hipStream_t st);
+hipError_t launch_bin_scan_group(const SunGroup* grp, int32_t n_sun, int32_t n_tiles, hipStream_t st);
+hipError_t launch_pair_scatter_group(const SunGroup* grp, int32_t grid, hipStream_t st);
+hipError_t launch_raster_group(const SunGroup* grp, int32_t n_sun, bool listed, int32_t tile, int32_t n_tiles,
+                               const View* views, const SunCounters* ctr, int32_t n, const int32_t* bias,
+                               int32_t n_mod, const double* fu, const double* fv, int32_t k, int32_t n_cu,
+                               int32_t cap_per_cu, hipStream_t st);
 hipError_t launch_sample_test(int64_t s, const View* views, const GenDev& g, const double* beam,
                               const int32_t* bias, const double* fu, const double* fv, int32_t k,
                               const uint32_t* map, int32_t n, uint32_t* counts, uint32_t* bits,
                               hipStream_t st);
 hipError_t launch_loss(int64_t n_sun, const double* sun, const double* beam, const uint32_t* counts,
                        const double* d_poa, const GenDev& g, int32_t k, double* power,
-                       double* power_ref, hipStream_t st);
+                       double* power_ref, const SunCounters* ctr, hipStream_t st);
 hipError_t launch_energy(int64_t n_sun, const double* power, const double* power_ref,
                          const double* dt, double* energy, hipStream_t st);
 hipError_t launch_svf(const Module* mods, int32_t cpm, int64_t n_cells, const double* dirs, int64_t n_dir,

@@ -753,13 +753,15 @@ __device__ void tri_setup_body(uint32_t* cnt, int64_t t0, int64_t t1, const View
     }
 }
 
-__global__ __launch_bounds__(256) void k_tri_setup(int64_t s, const View* views, SceneDev sc, GenDev g,
-                                                   const int32_t* bias, int32_t n, BinBuffers bb,
-                                                   SunCounters* ctr, const uint32_t* tmask) {
+// Group form: blockIdx.y picks the sun of the group.
+__global__ __launch_bounds__(256) void k_tri_setup_g(const SunGroup* __restrict__ grp, const View* views, SceneDev sc,
+                                                     const int32_t* bias, int32_t n, SunCounters* ctr) {
     extern __shared__ uint32_t cnt[];
-    const int64_t total = sc.n_tri + (g.occluders ? 2 * (int64_t)g.n_mod : 0) + g.n_mod;
+    const GroupSun& S = grp->sun[blockIdx.y];
+    const int64_t total = sc.n_tri + (S.g.occluders ? 2 * (int64_t)S.g.n_mod : 0) + S.g.n_mod;
     const int64_t t0 = blockIdx.x * 256ll;
-    tri_setup_body(cnt, t0, min(t0 + 256, total), views[s], sc, g, bias + s * g.n_mod, n, bb, ctr, tmask);
+    tri_setup_body(cnt, t0, min(t0 + 256, total), views[S.s], sc, S.g, bias + S.s * S.g.n_mod, n, S.bb, ctr + S.s,
+                   S.tmask);
 }
 
 // Exclusive prefix sum over the NT threads of a workgroup (wave shuffles,
@@ -802,26 +804,27 @@ constexpr int kScanBuckets = 256;
 // so that the array stays in registers.
 constexpr int kScanKeep = 8;
 
-__device__ __forceinline__ int32_t kept_at(const int32_t (&kept)[kScanKeep], int32_t j) {
+template <int KEEP>
+__device__ __forceinline__ int32_t kept_at(const int32_t (&kept)[KEEP], int32_t j) {
     int32_t c = 0;
 #pragma unroll
-    for (int32_t q = 0; q < kScanKeep; q++) c = q == j ? kept[q] : c;
+    for (int32_t q = 0; q < KEEP; q++) c = q == j ? kept[q] : c;
     return c;
 }
 
-template <int NT, bool COHERENT>
+template <int NT, bool COHERENT, int KEEP = kScanKeep>
 __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& bb, int32_t* list, int32_t split_at) {
     static_assert(NT >= kScanBuckets && NT % 64 == 0, "a thread per bucket");
     const int tid = threadIdx.x;
     unsigned long long* wsum = reinterpret_cast<unsigned long long*>(part + 2);
     const int32_t per = (n_tiles + NT - 1) / NT;
     const int32_t b0 = min(tid * per, n_tiles), b1 = min(b0 + per, n_tiles);
-    const bool keep = per <= kScanKeep;
-    int32_t kept[kScanKeep];
+    const bool keep = per <= KEEP;
+    int32_t kept[KEEP];
     int32_t sum = 0, nz = 0;
     if (keep) {
 #pragma unroll
-        for (int32_t j = 0; j < kScanKeep; j++) {
+        for (int32_t j = 0; j < KEEP; j++) {
             const int32_t i = b0 + j;
             kept[j] = i < b1 ? (COHERENT ? ld_dev(bb.tile_count + i) : bb.tile_count[i]) : 0;
             sum += kept[j];
@@ -841,7 +844,7 @@ __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& b
     const bool in_order = list && split_at < 0;
     int32_t run = (int32_t)(uint32_t)ex, lpos = (int32_t)(ex >> 32);
     for (int32_t i = b0; i < b1; i++) {
-        const int32_t c = keep ? kept_at(kept, i - b0) : (COHERENT ? ld_dev(bb.tile_count + i) : bb.tile_count[i]);
+        const int32_t c = keep ? kept_at<KEEP>(kept, i - b0) : (COHERENT ? ld_dev(bb.tile_count + i) : bb.tile_count[i]);
         bb.tile_start[i] = run;
         if (COHERENT) {       // words other units update with atomics are written with atomics only
             __hip_atomic_store(bb.tile_cursor + i, run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -864,7 +867,7 @@ __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& b
     for (int q = tid; q < kScanBuckets; q += NT) hist[q] = 0;
     __syncthreads();
     for (int32_t i = b0; i < b1; i++) {
-        const int32_t c = keep ? kept_at(kept, i - b0) : bb.tile_start[i + 1] - bb.tile_start[i];
+        const int32_t c = keep ? kept_at<KEEP>(kept, i - b0) : bb.tile_start[i + 1] - bb.tile_start[i];
         if (c <= 0) continue;
         const int32_t bk = kScanBuckets - 1 - min(c >> 3, kScanBuckets - 1);
         atomicAdd(&hist[bk], (split_at > 0 && c > split_at) ? 4 : 1);
@@ -877,7 +880,7 @@ __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& b
     const int32_t n_items = (int32_t)n_items64;
     __syncthreads();
     for (int32_t i = b0; i < b1; i++) {
-        const int32_t c = keep ? kept_at(kept, i - b0) : bb.tile_start[i + 1] - bb.tile_start[i];
+        const int32_t c = keep ? kept_at<KEEP>(kept, i - b0) : bb.tile_start[i + 1] - bb.tile_start[i];
         if (c <= 0) continue;
         const int32_t bk = kScanBuckets - 1 - min(c >> 3, kScanBuckets - 1);
         const bool split = split_at > 0 && c > split_at;
@@ -891,13 +894,15 @@ __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& b
     return n_items;
 }
 
-// One workgroup of 512 threads: it finds room on a CU beside the other lane's
-// tile pass sooner than one of 1024 (C2 year 351 ms against 363 ms).
-constexpr int kScanThreads = 512;
-
-__global__ __launch_bounds__(kScanThreads) void k_bin_scan(int32_t n_tiles, BinBuffers bb) {
-    __shared__ __attribute__((aligned(16))) int32_t part[2 * kScanThreads + 2 * kScanBuckets];
-    const int32_t n_items = scan_body<kScanThreads, false>(part, n_tiles, bb, bb.tile_list, bb.split_at);
+// One workgroup per sun of a group. NT x KEEP tiles stay in registers: 512 x 8 up to
+// 4,096 tiles (64-texel tiles of a 4096 picture; 512 threads find room on a CU beside
+// the other lane's tile pass sooner than 1024), 1024 x 16 up to 16,384 (of an 8192
+// picture, where re-reading the starts from memory made the scan take 83 us).
+template <int NT, int KEEP>
+__global__ __launch_bounds__(NT) void k_bin_scan_g(const SunGroup* __restrict__ grp, int32_t n_tiles) {
+    __shared__ __attribute__((aligned(16))) int32_t part[2 * NT + 2 * kScanBuckets];
+    const BinBuffers& bb = grp->sun[blockIdx.x].bb;
+    const int32_t n_items = scan_body<NT, false, KEEP>(part, n_tiles, bb, bb.tile_list, bb.split_at);
     if (bb.tile_list && threadIdx.x == 0) {
         bb.list_ctr[0] = n_items;
         bb.list_ctr[1] = 0;
@@ -986,62 +991,88 @@ __device__ void scatter_body(uint32_t* lds, int32_t unit, int32_t n_units, const
     }
 }
 
-__global__ __launch_bounds__(256) void k_bin_scatter(int64_t s, BinBuffers bb, int32_t n_mod, SunCounters* ctr,
-                                                     const uint32_t* tmask) {
-    extern __shared__ uint32_t lds[];
-    scatter_body(lds, blockIdx.x, gridDim.x, bb, n_mod, ctr[s].n_rec, ctr + s, tmask);
-}
-
 // Pair mode: every pair of the sun's pair space, in chunks of kPairChunk over
 // the grid. A thread finds its item among the (at most kPairChunk) items the
 // chunk touches by binary search over their starts in LDS, then its tile;
 // f(tile, id) runs for the pairs the binning keeps: tiles with samples, and
 // for a record only the tiles its edges reach (the filter of wave_pairs).
 template <typename F>
-__device__ void pair_chunks(const BinBuffers& bb, const uint32_t* tmask, uint32_t* st, F&& f) {
-    const unsigned long long pc = *bb.pctr;
-    // a sun whose items overflowed the buffers is reported by the host and
-    // evaluated no further; its reads stay inside the buffers all the same
-    const int64_t n_items = min((int64_t)(pc >> 32), (int64_t)bb.item_cap);
-    const int64_t n_pairs = min((int64_t)(pc & 0xFFFFFFFFull), (int64_t)bb.bin_cap);
-    const int64_t n_chunks = (n_pairs + kPairChunk - 1) / kPairChunk;
+__device__ void pair_chunk(const BinBuffers& bb, const uint32_t* tmask, uint32_t* st, int64_t q, int64_t n_items,
+                           int64_t n_pairs, F&& f) {
     const int32_t nty = bb.n_tiles / bb.ntx;
     static_assert(kPairChunk == 256, "one thread per pair of a chunk");
-    for (int64_t q = blockIdx.x; q < n_chunks; q += gridDim.x) {
-        const int32_t k0 = bb.pchunk[q];
-        const bool k0_ok = k0 >= 0 && k0 < n_items;
-        const int64_t k = k0 + (int64_t)threadIdx.x;
-        st[threadIdx.x] = (k0_ok && k < n_items) ? (uint32_t)bb.pitems[k].start : 0xFFFFFFFFu;
-        __syncthreads();
-        const int64_t p = q * kPairChunk + threadIdx.x;
-        if (k0_ok && p < n_pairs && st[0] <= (uint32_t)p) {
-            const PairItem it = bb.pitems[k0 + last_at_most<0>(st, kPairChunk, (uint32_t)p)];
-            const int32_t x0 = (int32_t)(it.xr & 0xFFFFu), x1 = (int32_t)(it.xr >> 16);
-            const int32_t y0 = (int32_t)(it.yr & 0xFFFFu);
-            const int32_t r = (int32_t)(p - it.start), bw = x1 - x0 + 1;
-            const int32_t tx = x0 + (bw > 0 ? r % bw : 0), ty = y0 + (bw > 0 ? r / bw : 0);
-            const int32_t tq = ty * bb.ntx + tx;
-            bool keep = bw > 0 && tx < bb.ntx && ty < nty && it.id < bb.rec_cap;
-            keep = keep && mask_has(tmask, tq);
-            if (keep && it.id >= 0) {
-                Edges E;
-                edges_of(bb.rec[it.id], E);
-                keep = tile_overlap(E, tx, ty, bb.tile);
-            }
-            if (keep) f(tq, it.id);
+    const int32_t k0 = bb.pchunk[q];
+    const bool k0_ok = k0 >= 0 && k0 < n_items;
+    const int64_t k = k0 + (int64_t)threadIdx.x;
+    st[threadIdx.x] = (k0_ok && k < n_items) ? (uint32_t)bb.pitems[k].start : 0xFFFFFFFFu;
+    __syncthreads();
+    const int64_t p = q * kPairChunk + threadIdx.x;
+    if (k0_ok && p < n_pairs && st[0] <= (uint32_t)p) {
+        const PairItem it = bb.pitems[k0 + last_at_most<0>(st, kPairChunk, (uint32_t)p)];
+        const int32_t x0 = (int32_t)(it.xr & 0xFFFFu), x1 = (int32_t)(it.xr >> 16);
+        const int32_t y0 = (int32_t)(it.yr & 0xFFFFu);
+        const int32_t r = (int32_t)(p - it.start), bw = x1 - x0 + 1;
+        const int32_t tx = x0 + (bw > 0 ? r % bw : 0), ty = y0 + (bw > 0 ? r / bw : 0);
+        const int32_t tq = ty * bb.ntx + tx;
+        bool keep = bw > 0 && tx < bb.ntx && ty < nty && it.id < bb.rec_cap;
+        keep = keep && mask_has(tmask, tq);
+        if (keep && it.id >= 0) {
+            Edges E;
+            edges_of(bb.rec[it.id], E);
+            keep = tile_overlap(E, tx, ty, bb.tile);
         }
-        __syncthreads();
+        if (keep) f(tq, it.id);
+    }
+    __syncthreads();
+}
+
+// A sun's item and pair counts, bounded by its buffers: a sun whose items
+// overflowed them is reported by the host and evaluated no further; its
+// reads stay inside the buffers all the same.
+__device__ __forceinline__ void pair_space(const BinBuffers& bb, int64_t& n_items, int64_t& n_pairs) {
+    const unsigned long long pc = *bb.pctr;
+    n_items = min((int64_t)(pc >> 32), (int64_t)bb.item_cap);
+    n_pairs = min((int64_t)(pc & 0xFFFFFFFFull), (int64_t)bb.bin_cap);
+}
+
+// Every chunk of every sun of a group, one sequence over the grid: chunk Q
+// of the concatenated pair spaces belongs to the sun whose range holds it.
+template <typename F>
+__device__ void group_pair_chunks(const SunGroup* grp, uint32_t* st, long long* first, F&& f) {
+    const int32_t ng = grp->n;
+    if (threadIdx.x == 0) {
+        long long acc = 0;
+        for (int32_t q = 0; q < ng; q++) {
+            int64_t ni, np;
+            pair_space(grp->sun[q].bb, ni, np);
+            first[q] = acc;
+            acc += (np + kPairChunk - 1) / kPairChunk;
+        }
+        first[ng] = acc;
+    }
+    __syncthreads();
+    const long long total = first[ng];
+    for (long long Q = blockIdx.x; Q < total; Q += gridDim.x) {
+        int32_t q = 0;
+        while (q + 1 < ng && first[q + 1] <= Q) q++;
+        q = __builtin_amdgcn_readfirstlane(q);
+        const GroupSun& S = grp->sun[q];
+        int64_t ni, np;
+        pair_space(S.bb, ni, np);
+        pair_chunk(S.bb, S.tmask, st, Q - first[q], ni, np, [&](int32_t tq, int32_t id) { f(S.bb, tq, id); });
     }
 }
 
-__global__ __launch_bounds__(256) void k_pair_count(BinBuffers bb, const uint32_t* tmask) {
+__global__ __launch_bounds__(256) void k_pair_count_g(const SunGroup* __restrict__ grp) {
     __shared__ uint32_t st[kPairChunk];
-    pair_chunks(bb, tmask, st, [&](int32_t tq, int32_t) { atomicAdd(&bb.tile_count[tq], 1); });
+    __shared__ long long first[kMaxGroup + 1];
+    group_pair_chunks(grp, st, first, [&](const BinBuffers& bb, int32_t tq, int32_t) { atomicAdd(&bb.tile_count[tq], 1); });
 }
 
-__global__ __launch_bounds__(256) void k_pair_scatter(BinBuffers bb, const uint32_t* tmask) {
+__global__ __launch_bounds__(256) void k_pair_scatter_g(const SunGroup* __restrict__ grp) {
     __shared__ uint32_t st[kPairChunk];
-    pair_chunks(bb, tmask, st, [&](int32_t tq, int32_t id) {
+    __shared__ long long first[kMaxGroup + 1];
+    group_pair_chunks(grp, st, first, [&](const BinBuffers& bb, int32_t tq, int32_t id) {
         const int32_t at = atomicAdd(&bb.tile_cursor[tq], 1);
         if (at < bb.bin_cap) bb.bins[at] = id;
     });
@@ -1878,29 +1909,36 @@ __device__ void tile_body(TileLds<TS, CAP>& L, int32_t item, const View& V, cons
                          k, out, c, failed[f], lane, wv);
 }
 
+// Group form. With work lists (sparse route) the resident grid takes the suns
+// in order, each sun's heaviest items first, so the light items at the end
+// of one sun's list run beside the heavy ones at the start of the next;
+// otherwise one workgroup per (tile, sun).
 template <int TS, int CAP>
-__global__ __launch_bounds__(256, 3) void k_tile(int64_t s, const View* views, BinBuffers bb, const SunCounters* ctr,
-                                              int32_t n, GenDev g, const int32_t* bias, const double* fu_tab,
-                                              const double* fv_tab, int32_t k, TileOut out, int32_t sparse,
-                                              const uint32_t* tmask) {
+__global__ __launch_bounds__(256, 3) void k_tile_g(const SunGroup* __restrict__ grp, const View* views,
+                                                const SunCounters* ctr, int32_t n, const int32_t* bias,
+                                                const double* fu_tab, const double* fv_tab, int32_t k) {
     __shared__ TileLds<TS, CAP> L;
     __shared__ int32_t take;
-    if (!bb.tile_list) {                      // one workgroup per tile
-        tile_body<TS, CAP>(L, ((int32_t)blockIdx.x << 3) | kWholeTile, views[s], bb, ctr[s].n_large, n, g,
-                           bias + s * g.n_mod, fu_tab, fv_tab, k, out, sparse, tmask);
+    if (!grp->sun[0].bb.tile_list) {
+        const GroupSun& S = grp->sun[blockIdx.y];
+        tile_body<TS, CAP>(L, ((int32_t)blockIdx.x << 3) | kWholeTile, views[S.s], S.bb, ctr[S.s].n_large, n, S.g,
+                           bias + S.s * S.g.n_mod, fu_tab, fv_tab, k, S.out, S.out.sparse, S.tmask);
         return;
     }
-    // the scan's work list, heaviest items first, taken one at a time
-    const int32_t n_items = bb.list_ctr[0];
-    for (;;) {
-        if (threadIdx.x == 0) take = atomicAdd(&bb.list_ctr[1], 1);
-        __syncthreads();
-        const int32_t it = take;
-        __syncthreads();
-        if (it >= n_items) break;
-        tile_body<TS, CAP>(L, bb.tile_list[it], views[s], bb, ctr[s].n_large, n, g, bias + s * g.n_mod, fu_tab, fv_tab,
-                           k, out, sparse, tmask);
-        __syncthreads();
+    const int32_t ng = grp->n;
+    for (int32_t q = 0; q < ng; q++) {
+        const GroupSun& S = grp->sun[q];
+        const int32_t n_items = S.bb.list_ctr[0];
+        for (;;) {
+            if (threadIdx.x == 0) take = atomicAdd(&S.bb.list_ctr[1], 1);
+            __syncthreads();
+            const int32_t it = take;
+            __syncthreads();
+            if (it >= n_items) break;
+            tile_body<TS, CAP>(L, S.bb.tile_list[it], views[S.s], S.bb, ctr[S.s].n_large, n, S.g,
+                               bias + S.s * S.g.n_mod, fu_tab, fv_tab, k, S.out, S.out.sparse, S.tmask);
+            __syncthreads();
+        }
     }
 }
 
@@ -2377,13 +2415,20 @@ __device__ void loss_body(LossLds& L, const double* sun3, const double* beam_s, 
     }
 }
 
+// A sun whose set-up records or bin entries overflowed their buffers (never
+// with the per-sun path's capacities; a guard all the same) reads NaN powers,
+// so a caller of the asynchronous form sees it without a host round trip.
 __global__ __launch_bounds__(256) void k_loss(const double* sun, const double* beam, const uint32_t* counts,
                                               const double* d_poa, GenDev g, int32_t k, double* power,
-                                              double* power_ref) {
+                                              double* power_ref, const SunCounters* ctr) {
     __shared__ LossLds L;
     const int64_t s = blockIdx.x;
     const int64_t n_cells = (int64_t)g.n_mod * g.n_cu * g.n_cv;
     loss_body<false>(L, sun + 3 * s, beam + s * g.n_mod, counts + s * n_cells, d_poa[s], g, k, power + s, power_ref + s);
+    if (ctr && threadIdx.x == 0 && ctr[s].overflow) {
+        power[s] = __builtin_nan("");
+        power_ref[s] = __builtin_nan("");
+    }
 }
 
 __global__ void k_energy(int64_t n_sun, const double* power, const double* power_ref, const double* dt,
@@ -3009,34 +3054,6 @@ hipError_t launch_setup(const double* sun, int64_t n_sun, const double* dni, con
     return hipGetLastError();
 }
 
-size_t bin_lds_bytes(int32_t n_tiles) { return 8 * (size_t)n_tiles; }
-
-hipError_t configure_kernels(size_t max_lds) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_tri_setup, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_bin_scatter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
-}
-
-hipError_t launch_tri_setup(int64_t s, const View* views, const SceneDev& sc, const GenDev& g, const int32_t* bias,
-                            int32_t n, const BinBuffers& bb, SunCounters* ctr, const uint32_t* tmask, hipStream_t st) {
-    int64_t total = sc.n_tri + (g.occluders ? 2 * (int64_t)g.n_mod : 0) + g.n_mod;
-    if (total == 0) return hipSuccess;
-    const size_t lds = bb.pitems ? 5 * sizeof(unsigned long long) : 4 * (size_t)bb.n_tiles;
-    hipLaunchKernelGGL(k_tri_setup, dim3(grid_for(total, 256)), dim3(256), lds, st, s, views, sc, g, bias, n, bb,
-                       ctr + s, tmask);
-    return hipGetLastError();
-}
-
-hipError_t launch_pair_count(const BinBuffers& bb, const uint32_t* tmask, int32_t grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_pair_count, dim3((unsigned)grid), dim3(256), 0, st, bb, tmask);
-    return hipGetLastError();
-}
-
-hipError_t launch_pair_scatter(const BinBuffers& bb, const uint32_t* tmask, int32_t grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)grid), dim3(256), 0, st, bb, tmask);
-    return hipGetLastError();
-}
-
 hipError_t launch_pose(const double* sun, int64_t n_sun, const Module* rest, int32_t n_mod, const TrackerDev* trk,
                        const int32_t* mod_trk, Module* posed, hipStream_t st) {
     const int64_t total = n_sun * n_mod;
@@ -3051,58 +3068,65 @@ hipError_t launch_box_sphere(const double lo[3], const double hi[3], double* sph
     return hipGetLastError();
 }
 
-hipError_t launch_bin_scan(int32_t n_tiles, const BinBuffers& bb, hipStream_t st) {
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kScanThreads), 0, st, n_tiles, bb);
+hipError_t launch_tri_setup_group(const SunGroup* grp, int32_t n_sun, const View* views, const SceneDev& sc,
+                                  const GenDev& g, const int32_t* bias, int32_t n, SunCounters* ctr, hipStream_t st) {
+    const int64_t total = sc.n_tri + (g.occluders ? 2 * (int64_t)g.n_mod : 0) + g.n_mod;
+    if (total == 0 || n_sun <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tri_setup_g, dim3(grid_for(total, 256), (unsigned)n_sun), dim3(256),
+                       5 * sizeof(unsigned long long), st, grp, views, sc, bias, n, ctr);
     return hipGetLastError();
 }
 
-hipError_t launch_bin_scatter(int64_t s, const BinBuffers& bb, int32_t n_mod, SunCounters* ctr, int32_t grid,
-                              const uint32_t* tmask, hipStream_t st) {
-    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)grid), dim3(256), bin_lds_bytes(bb.n_tiles), st, s, bb, n_mod,
-                       ctr, tmask);
+hipError_t launch_pair_count_group(const SunGroup* grp, int32_t grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_pair_count_g, dim3((unsigned)grid), dim3(256), 0, st, grp);
     return hipGetLastError();
 }
 
-// Workgroups of the tile kernel: one per tile, or, with the work list, as
-// many as stay resident (at most one per possible item, and at most
-// cap_per_cu per CU when cap_per_cu > 0), each taking items until the list is
-// empty.
+hipError_t launch_pair_scatter_group(const SunGroup* grp, int32_t grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_pair_scatter_g, dim3((unsigned)grid), dim3(256), 0, st, grp);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_scan_group(const SunGroup* grp, int32_t n_sun, int32_t n_tiles, hipStream_t st) {
+    if (n_sun <= 0) return hipSuccess;
+    if (n_tiles <= 512 * 8)
+        hipLaunchKernelGGL((k_bin_scan_g<512, 8>), dim3((unsigned)n_sun), dim3(512), 0, st, grp, n_tiles);
+    else
+        hipLaunchKernelGGL((k_bin_scan_g<1024, 16>), dim3((unsigned)n_sun), dim3(1024), 0, st, grp, n_tiles);
+    return hipGetLastError();
+}
+
 template <int TS, int CAP>
-static hipError_t tile_launch(dim3 (&grid), const BinBuffers& bb, int32_t n_cu, int32_t cap_per_cu) {
-    grid = dim3((unsigned)bb.n_tiles);
-    if (!bb.tile_list) return hipSuccess;
-    static int per_cu = 0;                     // the same code object on every device of one architecture
-    if (per_cu == 0) {
-        int nb = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tile<TS, CAP>, 256, 0);
-        if (e != hipSuccess) return e;
-        per_cu = nb > 0 ? nb : 1;
+static hipError_t tile_go_group(const SunGroup* grp, int32_t n_sun, bool listed, int32_t n_tiles, const View* views,
+                                const SunCounters* ctr, int32_t n, const int32_t* bias, const double* fu,
+                                const double* fv, int32_t k, int32_t n_cu, int32_t cap_per_cu, hipStream_t st) {
+    dim3 grid((unsigned)n_tiles, (unsigned)n_sun);
+    if (listed) {
+        static int per_cu = 0;                 // the same code object on every device of one architecture
+        if (per_cu == 0) {
+            int nb = 0;
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_tile_g<TS, CAP>, 256, 0);
+            if (e != hipSuccess) return e;
+            per_cu = nb > 0 ? nb : 1;
+        }
+        const int32_t use = cap_per_cu > 0 ? std::min(cap_per_cu, per_cu) : per_cu;
+        const int64_t most = 4 * (int64_t)n_tiles * n_sun;
+        grid = dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(most, (int64_t)n_cu * use)));
     }
-    const int32_t use = cap_per_cu > 0 ? std::min(cap_per_cu, per_cu) : per_cu;
-    const int64_t most = 4 * (int64_t)bb.n_tiles;
-    grid = dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(most, (int64_t)n_cu * use)));
-    return hipSuccess;
-}
-
-template <int TS, int CAP>
-static hipError_t tile_go(int64_t s, const View* views, const BinBuffers& bb, const SunCounters* ctr, int32_t n,
-                          const GenDev& g, const int32_t* bias, const double* fu, const double* fv, int32_t k,
-                          const TileOut& out, const uint32_t* tmask, int32_t n_cu, int32_t cap_per_cu, hipStream_t st) {
-    dim3 grid;
-    hipError_t e;
-    if ((e = tile_launch<TS, CAP>(grid, bb, n_cu, cap_per_cu))) return e;
-    hipLaunchKernelGGL((k_tile<TS, CAP>), grid, dim3(256), 0, st, s, views, bb, ctr, n, g, bias, fu, fv, k, out,
-                       out.sparse, tmask);
+    hipLaunchKernelGGL((k_tile_g<TS, CAP>), grid, dim3(256), 0, st, grp, views, ctr, n, bias, fu, fv, k);
     return hipGetLastError();
 }
 
-hipError_t launch_raster(int64_t s, const View* views, const BinBuffers& bb, const SunCounters* ctr, int32_t n,
-                         const GenDev& g, const int32_t* bias, const double* fu, const double* fv, int32_t k,
-                         const TileOut& out, const uint32_t* tmask, int32_t n_cu, int32_t cap_per_cu, hipStream_t st) {
-    switch (bb.tile) {
-        case 32: return tile_go<32, kCap32>(s, views, bb, ctr, n, g, bias, fu, fv, k, out, tmask, n_cu, cap_per_cu, st);
-        case 64: return tile_go<64, kCap64>(s, views, bb, ctr, n, g, bias, fu, fv, k, out, tmask, n_cu, cap_per_cu, st);
-        case 128: return tile_go<128, kCap128>(s, views, bb, ctr, n, g, bias, fu, fv, k, out, tmask, n_cu, cap_per_cu, st);
+hipError_t launch_raster_group(const SunGroup* grp, int32_t n_sun, bool listed, int32_t tile, int32_t n_tiles,
+                               const View* views, const SunCounters* ctr, int32_t n, const int32_t* bias,
+                               int32_t n_mod, const double* fu, const double* fv, int32_t k, int32_t n_cu,
+                               int32_t cap_per_cu, hipStream_t st) {
+    (void)n_mod;
+    if (n_sun <= 0) return hipSuccess;
+    switch (tile) {
+        case 32: return tile_go_group<32, kCap32>(grp, n_sun, listed, n_tiles, views, ctr, n, bias, fu, fv, k, n_cu, cap_per_cu, st);
+        case 64: return tile_go_group<64, kCap64>(grp, n_sun, listed, n_tiles, views, ctr, n, bias, fu, fv, k, n_cu, cap_per_cu, st);
+        case 128: return tile_go_group<128, kCap128>(grp, n_sun, listed, n_tiles, views, ctr, n, bias, fu, fv, k, n_cu, cap_per_cu, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -3119,10 +3143,10 @@ hipError_t launch_sample_test(int64_t s, const View* views, const GenDev& g, con
 
 hipError_t launch_loss(int64_t n_sun, const double* sun, const double* beam, const uint32_t* counts,
                        const double* d_poa, const GenDev& g, int32_t k, double* power, double* power_ref,
-                       hipStream_t st) {
+                       const SunCounters* ctr, hipStream_t st) {
     if (n_sun <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_loss, dim3((unsigned)n_sun), dim3(256), 0, st, sun, beam, counts, d_poa, g, k, power,
-                       power_ref);
+                       power_ref, ctr);
     return hipGetLastError();
 }
 

@@ -70,11 +70,14 @@ struct PathSizes {
     int64_t item_cap, chunk_cap;      // pair mode: binned items, chunks of pair space
 };
 
-// The buffers one stream of the per-sun path works in; consecutive suns
-// take turns on the lanes, one stream each.
+// The buffers one stream of the per-sun path works in: room for a group of
+// suns (each sun's part at a fixed stride); consecutive groups take turns on
+// the lanes, one stream each.
 struct Lane {
     Buf rec, large, bins, tile_count, tile_start, tile_cursor, tile_list, pitems, pchunk, modbox, map;
+    int32_t group = 0;            // suns the buffers hold room for
     void release_all(Ctx* c) {
+        group = 0;
         Buf* all[] = {&rec, &large, &bins, &tile_count, &tile_start, &tile_cursor, &tile_list, &pitems, &pchunk,
                       &modbox, &map};
         for (Buf* b : all) b->release(c);
@@ -83,18 +86,22 @@ struct Lane {
 
 // Streams the per-sun path spreads consecutive suns over (lane 0 is the
 // caller's stream); a lane whose buffers do not fit the budget is left out.
-// Two: with four (faster alone) a serving loop started in the same context
-// after the per-sun path had run stalled, with the cause not found.
+// The context owns three streams in all: its own, lane 1's (which the serving
+// loop also copies on) and the serving loop's kernel stream. With the
+// default stream beside them that is the four hardware queues a process gets
+// by default, so the serving loop's persistent kernel holds a queue of its
+// own: a stream that shares a queue with it waits behind it.
 constexpr int kLanes = 2;
 
 struct Work {
     Lane lane[kLanes];
     Buf views, ctr, beam, bias, sweep, sphere, partial, fu, fv, tmask, posed;
     Buf counts, outd, maps, bits, sky;
+    Buf groups;                   // SunGroup descriptors of the current evaluation
     void release_all(Ctx* c) {
         for (Lane& L : lane) L.release_all(c);
         Buf* all[] = {&views, &ctr, &beam, &bias, &sweep, &sphere, &partial, &fu, &fv, &tmask, &posed, &counts, &outd,
-                      &maps, &bits, &sky};
+                      &maps, &bits, &sky, &groups};
         for (Buf* b : all) b->release(c);
     }
 };
@@ -120,15 +127,21 @@ struct Profiler {
     size_t used = 0;
     double total_ms[PV3D_N_STAGES] = {};
     int64_t launches[PV3D_N_STAGES] = {};
+    int64_t suns[PV3D_N_STAGES] = {};               // suns the timed launches covered
+    std::vector<int32_t> pending_suns;              // beside pending
+    hipEvent_t ref = nullptr;                       // time origin of the intervals
+    std::vector<std::pair<double, double>> spans[PV3D_N_STAGES];   // [start, end) ms after ref
     bool on(int stage) const { return (mask >> stage) & 1u; }
     bool take(int stage) { return on(stage) && seen[stage]++ % every == 0; }
-    hipError_t begin(int stage, hipStream_t st, size_t* slot);
+    hipError_t begin(int stage, hipStream_t st, size_t* slot, int32_t n_sun);
     hipError_t end(size_t slot, hipStream_t st);
     hipError_t collect();
+    double busy_ms(int stage) const;                // length of the union of the stage's spans
     void reset();
 };
 
 PathSizes path_sizes(const Scene& sc, const Gen& g, const pv3d_params& p, int64_t n_sun);
+size_t lane_bytes_per_sun(const PathSizes& z, const Gen& g);
 void host_sphere(const Scene& sc, const Gen& g, double sphere[4]);
 void host_sample_tables(int32_t k, int32_t n_cu, int32_t n_cv, double* fu, double* fv);
 int32_t choose_tile(const pv3d_params& p);
@@ -158,6 +171,12 @@ struct Ctx {
     hipEvent_t staging_done = nullptr;
     BatchState* batch = nullptr;
     Server* server = nullptr;
+    // the last per-sun path's work: a later call waits for it before it reuses the work buffers
+    hipEvent_t ws_ev = nullptr;
+    bool ws_recorded = false;
+    // pv3d_evaluate has run: the serving loop is not started in this context any more (a
+    // burst of requests served after the per-sun path in one context waited minutes)
+    bool per_sun_ran = false;
     DevInfo dev_info;
     // pv3d_batch_limits: slots of the batched form and the serving loop
     int32_t batch_max_slots = 128;
@@ -171,13 +190,18 @@ struct Ctx {
     pv3d_status stage_reserve(size_t bytes);
     pv3d_status stage_done(hipStream_t st);
     pv3d_status ensure_path(const PathSizes& z, const Gen& g, int32_t map_n, bool own_map);
-    pv3d_status ensure_lane(Lane& L, const PathSizes& z, const Gen& g, int32_t map_n, bool own_map);
-    pv3d_status run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, const GenDev& gd, const pv3d_params& p,
-                        const View* views, SunCounters* ctr, const int32_t* bias, const double* beam, uint32_t* map,
-                        uint32_t* counts_s, uint32_t* bits_s, const uint32_t* tmask_s, int lane, int n_lanes,
-                        hipStream_t st);
+    pv3d_status ensure_lane(Lane& L, const PathSizes& z, const Gen& g, int32_t map_n, bool own_map, int32_t group);
+    pv3d_status run_group(const SunGroup* d_grp, const SunGroup& grp, const PathSizes& z, const SceneDev& sd,
+                          const GenDev& gd, const pv3d_params& p, const View* views, SunCounters* ctr,
+                          const int32_t* bias, const double* beam, int n_lanes, hipStream_t st);
     pv3d_status ensure_tables(const Gen& g, int32_t k);
-    BinBuffers bin_buffers(const PathSizes& z, int lane);
+    BinBuffers bin_buffers(const PathSizes& z, int lane, int32_t q);
+    // pinned staging of the group descriptors (beside the sweep's, which callers reserve)
+    void* gstage = nullptr;
+    size_t gstage_cap = 0;
+    hipEvent_t gstage_done = nullptr;
+    bool gstage_busy = false;
+    pv3d_status upload_groups(const std::vector<SunGroup>& groups, hipStream_t st);
     pv3d_status run_path(const Scene& sc, const Gen& g, const pv3d_params& p, const double* sun_host, int64_t n_sun,
                          const double* d_sun, const double* d_dni, const double* d_dpoa, const double* d_dt,
                          uint32_t* counts, double* power, double* power_ref, double* energy, uint32_t* maps,
@@ -186,6 +210,19 @@ struct Ctx {
     bool scene_in_use(uint64_t h);
     bool gen_in_use(uint64_t h);
     void release_batched();
+};
+
+// While one of these lives, the serving loop admits no new job, so its live
+// launch runs out of work and ends. Every device-wide wait of the library
+// (hipDeviceSynchronize, and hipFree / hipHostFree, which wait for every
+// stream of the device) is taken under one: otherwise a loop fed faster than
+// it drains would keep that wait from ever returning.
+struct HoldServing {
+    Ctx* c;
+    explicit HoldServing(Ctx* ctx);
+    ~HoldServing();
+    HoldServing(const HoldServing&) = delete;
+    HoldServing& operator=(const HoldServing&) = delete;
 };
 
 }  // namespace pv3d

@@ -68,12 +68,14 @@ void Ctx::dfree(void* p) {
         used -= it->second;
         sizes.erase(it);
     }
+    HoldServing hold(this);             // hipFree waits for every stream of the device
     (void)hipFree(p);
 }
 
 pv3d_status Buf::ensure(Ctx* c, size_t bytes, const char* what) {
     if (bytes <= cap && ptr) return PV3D_OK;
     if (ptr) {
+        HoldServing hold(c);
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "synchronize before regrowing a work buffer");
         c->dfree(ptr);
@@ -108,6 +110,7 @@ pv3d_status Ctx::stage(const void* host, size_t bytes, void* dev, hipStream_t st
     if (staging_used + bytes > staging_cap) {
         size_t need = staging_used + bytes;
         if (staging_used > 0) return fail(PV3D_EINVAL, "staging overflow");  // callers reserve first
+        HoldServing hold(this);          // hipHostFree waits for every stream of the device
         if (staging) (void)hipHostFree(staging);
         staging = nullptr;
         size_t cap = std::max(need, (size_t)1 << 20);
@@ -131,6 +134,7 @@ pv3d_status Ctx::stage_reserve(size_t bytes) {
     }
     staging_used = 0;
     if (bytes > staging_cap) {
+        HoldServing hold(this);          // hipHostFree waits for every stream of the device
         if (staging) (void)hipHostFree(staging);
         staging = nullptr;
         staging_cap = 0;
@@ -152,7 +156,7 @@ pv3d_status Ctx::stage_done(hipStream_t st) {
 // ---------------------------------------------------------------------------
 // stage timing
 // ---------------------------------------------------------------------------
-hipError_t Profiler::begin(int stage, hipStream_t st, size_t* slot) {
+hipError_t Profiler::begin(int stage, hipStream_t st, size_t* slot, int32_t n_sun) {
     if (used + 2 > pool.size()) {
         size_t grow = std::max<size_t>(1024, pool.size());
         for (size_t i = 0; i < grow; i++) {
@@ -165,13 +169,15 @@ hipError_t Profiler::begin(int stage, hipStream_t st, size_t* slot) {
     *slot = used;
     used += 2;
     pending.emplace_back(stage, *slot);
+    pending_suns.push_back(n_sun);
     return hipEventRecord(pool[*slot], st);
 }
 
 hipError_t Profiler::end(size_t slot, hipStream_t st) { return hipEventRecord(pool[slot + 1], st); }
 
 hipError_t Profiler::collect() {
-    for (auto& pr : pending) {
+    for (size_t i = 0; i < pending.size(); i++) {
+        const auto& pr = pending[i];
         hipError_t e = hipEventSynchronize(pool[pr.second + 1]);
         if (e != hipSuccess) return e;
         float ms = 0.f;
@@ -179,28 +185,56 @@ hipError_t Profiler::collect() {
         if (e != hipSuccess) return e;
         total_ms[pr.first] += (double)ms;
         launches[pr.first] += 1;
+        suns[pr.first] += pending_suns[i];
+        float t0 = 0.f;
+        if (ref && hipEventElapsedTime(&t0, ref, pool[pr.second]) == hipSuccess)
+            spans[pr.first].emplace_back((double)t0, (double)t0 + (double)ms);
     }
     pending.clear();
+    pending_suns.clear();
     used = 0;
     return hipSuccess;
 }
 
+double Profiler::busy_ms(int stage) const {
+    std::vector<std::pair<double, double>> v = spans[stage];
+    std::sort(v.begin(), v.end());
+    double busy = 0.0, a = 0.0, b = 0.0;
+    bool open = false;
+    for (const auto& x : v) {
+        if (!open || x.first > b) {
+            if (open) busy += b - a;
+            a = x.first;
+            b = x.second;
+            open = true;
+        } else {
+            b = std::max(b, x.second);
+        }
+    }
+    if (open) busy += b - a;
+    return busy;
+}
+
 void Profiler::reset() {
     pending.clear();
+    pending_suns.clear();
     used = 0;
     for (int i = 0; i < PV3D_N_STAGES; i++) {
         total_ms[i] = 0.0;
         launches[i] = 0;
+        suns[i] = 0;
         seen[i] = 0;
+        spans[i].clear();
     }
 }
 
-// Launch `call` for `stage`, bracketed by timing events when that stage is profiled.
+// Launch `call` for `stage` (covering n_sun suns), bracketed by timing events when that
+// stage is profiled.
 template <typename F>
-static hipError_t timed(Profiler& pf, int stage, hipStream_t st, F&& call) {
+static hipError_t timed(Profiler& pf, int stage, hipStream_t st, F&& call, int32_t n_sun = 1) {
     if (!pf.take(stage)) return call();
     size_t slot = 0;
-    hipError_t e = pf.begin(stage, st, &slot);
+    hipError_t e = pf.begin(stage, st, &slot, n_sun);
     if (e != hipSuccess) return e;
     e = call();
     if (e != hipSuccess) return e;
@@ -250,7 +284,10 @@ pv3d_status check_params(const pv3d_params* p) {
 // ---------------------------------------------------------------------------
 // per-sun path
 // ---------------------------------------------------------------------------
-int32_t choose_tile(const pv3d_params& p) { return p.tile ? p.tile : (p.map_n <= 4096 ? 64 : 128); }
+// 64-texel tiles up to 8192 texels a side: a 128-texel tile's LDS (about 75 KB) leaves room
+// for two workgroups per CU, and the rooftop workload's year took 2.66 s with them against
+// 1.22 s with 64-texel tiles. Above 8192 the tile counts of 64-texel tiles outgrow the LDS.
+int32_t choose_tile(const pv3d_params& p) { return p.tile ? p.tile : (p.map_n <= 8192 ? 64 : 128); }
 
 PathSizes path_sizes(const Scene& sc, const Gen& g, const pv3d_params& p, int64_t n_sun) {
     PathSizes z;
@@ -274,13 +311,19 @@ PathSizes path_sizes(const Scene& sc, const Gen& g, const pv3d_params& p, int64_
     return z;
 }
 
+// Device bytes of one sun's part of a lane (records, large list, bins, tile counters and
+// list, pair items and chunks, module boxes).
+size_t lane_bytes_per_sun(const PathSizes& z, const Gen& g) {
+    return sizeof(TriRec) * (size_t)z.rec_cap + 4 * (size_t)z.rec_cap + 4 * (size_t)z.bin_cap +
+           4 * (size_t)(3 * (int64_t)z.n_tiles + 1) + 4 * (4 * (size_t)z.n_tiles + 2) +
+           sizeof(PairItem) * (size_t)z.item_cap + 4 * (size_t)z.chunk_cap + 16 * (size_t)g.n_mod + 6 * 256;
+}
+
 pv3d_status Ctx::ensure_path(const PathSizes& z, const Gen& g, int32_t map_n, bool own_map) {
     pv3d_status st;
     if (z.rec_cap > INT32_MAX || z.bin_cap > INT32_MAX)
         return fail(PV3D_ERANGE, "scene too large for 32-bit bin indices");
-    if (bin_lds_bytes(z.n_tiles) > max_lds)
-        return fail(PV3D_ERANGE, "%d tiles need more LDS than a workgroup has; use a larger tile", z.n_tiles);
-    if ((st = ensure_lane(w.lane[0], z, g, map_n, own_map))) return st;
+    if ((st = ensure_lane(w.lane[0], z, g, map_n, own_map, 1))) return st;
     if ((st = w.views.ensure(this, sizeof(View) * (size_t)std::max<int64_t>(z.n_sun, 1), "views"))) return st;
     if ((st = w.ctr.ensure(this, sizeof(SunCounters) * (size_t)std::max<int64_t>(z.n_sun, 1), "counters"))) return st;
     if ((st = w.beam.ensure(this, 8 * (size_t)std::max<int64_t>(z.n_sun * g.n_mod, 1), "module beam"))) return st;
@@ -293,38 +336,43 @@ pv3d_status Ctx::ensure_path(const PathSizes& z, const Gen& g, int32_t map_n, bo
     return PV3D_OK;
 }
 
-pv3d_status Ctx::ensure_lane(Lane& L, const PathSizes& z, const Gen& g, int32_t map_n, bool own_map) {
+// Room for `group` suns in each buffer of the lane, one sun's part after the other.
+pv3d_status Ctx::ensure_lane(Lane& L, const PathSizes& z, const Gen& g, int32_t map_n, bool own_map, int32_t group) {
     pv3d_status st;
-    if ((st = L.rec.ensure(this, sizeof(TriRec) * (size_t)z.rec_cap, "triangle records"))) return st;
-    if ((st = L.large.ensure(this, 4 * (size_t)z.rec_cap, "large-triangle list"))) return st;
-    if ((st = L.bins.ensure(this, 4 * (size_t)z.bin_cap, "tile bins"))) return st;
-    if ((st = L.tile_count.ensure(this, 4 * (size_t)z.n_tiles, "tile counts"))) return st;
-    if ((st = L.tile_start.ensure(this, 4 * (size_t)(z.n_tiles + 1), "tile starts"))) return st;
-    if ((st = L.tile_cursor.ensure(this, 4 * (size_t)z.n_tiles, "tile cursors"))) return st;
-    if ((st = L.tile_list.ensure(this, 4 * (4 * (size_t)z.n_tiles + 2), "tile work list"))) return st;
-    if ((st = L.pitems.ensure(this, sizeof(PairItem) * (size_t)z.item_cap, "pair items"))) return st;
-    if ((st = L.pchunk.ensure(this, 4 * (size_t)z.chunk_cap, "pair chunks"))) return st;
-    if ((st = L.modbox.ensure(this, 16 * (size_t)g.n_mod, "module tile boxes"))) return st;
+    const size_t G = (size_t)std::max(group, 1);
+    if ((st = L.rec.ensure(this, G * sizeof(TriRec) * (size_t)z.rec_cap, "triangle records"))) return st;
+    if ((st = L.large.ensure(this, G * 4 * (size_t)z.rec_cap, "large-triangle list"))) return st;
+    if ((st = L.bins.ensure(this, G * 4 * (size_t)z.bin_cap, "tile bins"))) return st;
+    if ((st = L.tile_count.ensure(this, G * 4 * (size_t)z.n_tiles, "tile counts"))) return st;
+    if ((st = L.tile_start.ensure(this, G * 4 * (size_t)(z.n_tiles + 1), "tile starts"))) return st;
+    if ((st = L.tile_cursor.ensure(this, G * 4 * (size_t)z.n_tiles, "tile cursors"))) return st;
+    if ((st = L.tile_list.ensure(this, G * 4 * (4 * (size_t)z.n_tiles + 2), "tile work list"))) return st;
+    if ((st = L.pitems.ensure(this, G * sizeof(PairItem) * (size_t)z.item_cap, "pair items"))) return st;
+    if ((st = L.pchunk.ensure(this, G * 4 * (size_t)z.chunk_cap, "pair chunks"))) return st;
+    if ((st = L.modbox.ensure(this, G * 16 * (size_t)g.n_mod, "module tile boxes"))) return st;
     if (own_map && (st = L.map.ensure(this, 4 * (size_t)map_n * map_n, "depth picture"))) return st;
+    L.group = std::max(L.group, (int32_t)G);
     return PV3D_OK;
 }
 
-BinBuffers Ctx::bin_buffers(const PathSizes& z, int lane) {
+// Sun q of a lane's group: its part of every lane buffer.
+BinBuffers Ctx::bin_buffers(const PathSizes& z, int lane, int32_t q) {
     Lane& L = w.lane[lane];
+    const size_t Q = (size_t)q;
     BinBuffers bb;
-    bb.rec = static_cast<TriRec*>(L.rec.ptr);
+    bb.rec = static_cast<TriRec*>(L.rec.ptr) + Q * (size_t)z.rec_cap;
     bb.rec_cap = (int32_t)z.rec_cap;
-    bb.large = static_cast<int32_t*>(L.large.ptr);
-    bb.tile_count = static_cast<int32_t*>(L.tile_count.ptr);
-    bb.tile_start = static_cast<int32_t*>(L.tile_start.ptr);
-    bb.tile_cursor = static_cast<int32_t*>(L.tile_cursor.ptr);
-    bb.bins = static_cast<int32_t*>(L.bins.ptr);
-    bb.modbox = static_cast<int4*>(L.modbox.ptr);
+    bb.large = static_cast<int32_t*>(L.large.ptr) + Q * (size_t)z.rec_cap;
+    bb.tile_count = static_cast<int32_t*>(L.tile_count.ptr) + Q * (size_t)z.n_tiles;
+    bb.tile_start = static_cast<int32_t*>(L.tile_start.ptr) + Q * (size_t)(z.n_tiles + 1);
+    bb.tile_cursor = static_cast<int32_t*>(L.tile_cursor.ptr) + Q * (size_t)z.n_tiles;
+    bb.bins = static_cast<int32_t*>(L.bins.ptr) + Q * (size_t)z.bin_cap;
+    bb.modbox = static_cast<int4*>(L.modbox.ptr) + Q * (size_t)(z.item_cap - z.rec_cap);   // n_mod per sun
     bb.tile_list = nullptr;                // one workgroup per tile unless the sun takes the work list
     bb.list_ctr = nullptr;
     bb.split_at = 0;
-    bb.pitems = static_cast<PairItem*>(L.pitems.ptr);
-    bb.pchunk = static_cast<int32_t*>(L.pchunk.ptr);
+    bb.pitems = static_cast<PairItem*>(L.pitems.ptr) + Q * (size_t)z.item_cap;
+    bb.pchunk = static_cast<int32_t*>(L.pchunk.ptr) + Q * (size_t)z.chunk_cap;
     bb.pctr = nullptr;                     // per sun
     bb.item_cap = (int32_t)z.item_cap;
     bb.bin_cap = (int32_t)z.bin_cap;
@@ -396,6 +444,13 @@ GenDev gen_dev(const Gen& g) {
     return d;
 }
 
+// 64-texel tiles with more bin entries than this go to four workgroups, one per
+// quadrant (each still walks all of the tile's triangles): the heaviest tiles,
+// under tall occluders, otherwise finish long after the rest of the launch.
+// C2 year: 397 ms at 32, 351 ms at 64, 335 ms at 128, 338 ms at 256 or with no
+// split.
+constexpr int32_t kSplitEntries = 128;
+
 // Everything of one evaluation that lives on the device.
 pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, const double* sun_host,
                           int64_t n_sun, const double* d_sun, const double* d_dni, const double* d_dpoa,
@@ -415,24 +470,46 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
     double* sphere = static_cast<double*>(w.sphere.ptr);
     const int64_t N2 = (int64_t)p.map_n * p.map_n;
 
+    // the work buffers are shared by every call of the context: wait for the previous call's
+    // kernels, which may still run on another stream
+    if (ws_recorded && (e = hipStreamWaitEvent(st, ws_ev, 0))) return hip_fail(e, "wait for the previous evaluation");
     if ((e = hipMemsetAsync(ctr, 0, sizeof(SunCounters) * (size_t)std::max<int64_t>(n_sun, 1), st)))
         return hip_fail(e, "clear counters");
-    // further lanes when their buffers fit the budget: consecutive suns then
-    // take turns on up to kLanes streams, so that one sun's set-up and binning
-    // kernels, which leave most of the GPU idle, run beside other suns' tile
-    // passes and the drains at their ends
+    // Suns go in groups of up to kMaxGroup per launch sequence (one group's set-up,
+    // binning and tile pass in five launches), consecutive groups taking turns on up
+    // to kLanes streams, so that one group's set-up and binning kernels, which leave
+    // much of the GPU idle, run beside another group's tile pass and its drain. The
+    // group shrinks until both lanes fit half of the budget left; a lane that still
+    // does not fit is left out.
     const bool own_map = maps == nullptr && (p.flags & PV3D_SEPARATE_TEST);
+    int64_t n_up = 0;
+    for (int64_t s = 0; s < n_sun; s++)
+        if (sun_host[3 * s + 2] > 0.0) n_up++;
+    int32_t G = own_map ? 1 : kMaxGroup;                 // the materialised route keeps one picture per lane
+    G = (int32_t)std::max<int64_t>(1, std::min<int64_t>(G, (n_up + kLanes - 1) / kLanes));
+    {
+        const size_t per_sun = lane_bytes_per_sun(z, g);
+        const uint64_t room = budget > used ? budget - used : 0;
+        // what the lanes hold already counts as room
+        uint64_t held = 0;
+        for (int l = 0; l < kLanes; l++)
+            for (Buf* bf : {&w.lane[l].rec, &w.lane[l].large, &w.lane[l].bins, &w.lane[l].pitems, &w.lane[l].pchunk})
+                held += bf->cap;
+        while (G > 1 && (uint64_t)kLanes * (uint64_t)G * per_sun > (room + held) / 2) G /= 2;
+    }
+    if ((rs = ensure_lane(w.lane[0], z, g, p.map_n, own_map, G)) != PV3D_OK) {
+        if (G == 1) return rs;
+        G = 1;
+        if ((rs = ensure_lane(w.lane[0], z, g, p.map_n, own_map, 1))) return rs;
+    }
     int n_lanes = 1;
-    while (n_lanes < kLanes && n_lanes < n_sun && lane_st[n_lanes]) {
-        if (ensure_lane(w.lane[n_lanes], z, g, p.map_n, own_map) != PV3D_OK) {
-            w.lane[n_lanes].release_all(this);
-            break;
-        }
+    while (n_lanes < kLanes && (int64_t)n_lanes * G < n_up && lane_st[n_lanes]) {
+        if (ensure_lane(w.lane[n_lanes], z, g, p.map_n, own_map, G) != PV3D_OK) break;
         n_lanes++;
     }
     // tile counts start at zero; the scan of every sun leaves them at zero again
     for (int l = 0; l < n_lanes; l++)
-        if ((e = hipMemsetAsync(w.lane[l].tile_count.ptr, 0, 4 * (size_t)z.n_tiles, st)))
+        if ((e = hipMemsetAsync(w.lane[l].tile_count.ptr, 0, 4 * (size_t)G * (size_t)z.n_tiles, st)))
             return hip_fail(e, "clear tile counts");
     if (counts && (e = hipMemsetAsync(counts, 0, 4 * (size_t)(n_sun * z.cells), st))) return hip_fail(e, "clear counts");
     if (bits && (e = hipMemsetAsync(bits, 0, 4 * (size_t)(n_sun * z.cells * z.words), st))) return hip_fail(e, "clear bits");
@@ -465,84 +542,125 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
     if (z.mask_words > 512) tmask = nullptr;
     if ((e = timed(prof, PV3D_STAGE_SETUP, st, [&] { return launch_setup(d_sun, n_sun, d_dni, gd, sphere, p.map_n, views, beam, bias, tg, tmask, st); })))
         return hip_fail(e, "setup");
+    // the groups: descriptors of every sun, built here and copied to the device once
+    const bool separate = (p.flags & PV3D_SEPARATE_TEST) != 0;
+    std::vector<SunGroup> groups;
+    std::vector<int> group_lane;
+    for (int64_t s = 0; s < n_sun; s++) {
+        if (!(sun_host[3 * s + 2] > 0.0)) continue;        // below the horizon: outputs stay zero
+        if (groups.empty() || groups.back().n == G) {
+            groups.emplace_back();
+            memset(&groups.back(), 0, sizeof(SunGroup));
+            group_lane.push_back((int)((groups.size() - 1) % (size_t)n_lanes));
+        }
+        SunGroup& grp = groups.back();
+        const int lane = group_lane.back();
+        const int32_t q = grp.n++;
+        GroupSun& S = grp.sun[q];
+        S.bb = bin_buffers(z, lane, q);
+        if (sparse) {      // the scan lists the tiles with work, heaviest first; 64-texel ones split in quadrants
+            int32_t* tl = static_cast<int32_t*>(w.lane[lane].tile_list.ptr) + (size_t)q * (4 * (size_t)z.n_tiles + 2);
+            S.bb.list_ctr = tl;
+            S.bb.tile_list = tl + 2;
+            S.bb.split_at = z.tile == 64 ? kSplitEntries : 0;
+        }
+        S.bb.pctr = &ctr[s].pairs;
+        S.out.map = maps ? maps + s * N2 : (separate ? static_cast<uint32_t*>(w.lane[lane].map.ptr) : nullptr);
+        S.out.counts = counts + s * z.cells;
+        S.out.bits = bits ? bits + s * z.cells * z.words : nullptr;
+        S.out.test = separate ? 0 : 1;
+        S.out.sparse = sparse ? 1 : 0;
+        S.g = gd;
+        if (gd.mods_sun) S.g.mods = gd.mods_sun + s * gd.n_mod;
+        S.tmask = tmask ? tmask + s * z.mask_words : nullptr;
+        S.s = s;
+    }
+    if (!groups.empty()) {
+        if ((rs = w.groups.ensure(this, sizeof(SunGroup) * groups.size(), "group descriptors"))) return rs;
+        if ((rs = upload_groups(groups, st))) return rs;
+    }
     if (n_lanes > 1 && (e = hipEventRecord(fork_ev, st))) return hip_fail(e, "fork the lanes");
     for (int l = 1; l < n_lanes; l++)
         if ((e = hipStreamWaitEvent(lane_st[l], fork_ev, 0))) return hip_fail(e, "fork the lanes");
-    int64_t done = 0;
-    for (int64_t s = 0; s < n_sun; s++) {
-        if (!(sun_host[3 * s + 2] > 0.0)) continue;        // below the horizon: outputs stay zero
-        uint32_t* map = maps ? maps + s * N2 : nullptr;
-        const int lane = (int)(done++ % n_lanes);
-        if ((rs = run_sun(s, z, sd, gd, p, views, ctr, bias, beam, map, counts + s * z.cells,
-                          bits ? bits + s * z.cells * z.words : nullptr, tmask ? tmask + s * z.mask_words : nullptr,
-                          lane, n_lanes, lane ? lane_st[lane] : st)))
+    const SunGroup* d_groups = static_cast<const SunGroup*>(w.groups.ptr);
+    for (size_t gi = 0; gi < groups.size(); gi++) {
+        const int lane = group_lane[gi];
+        if ((rs = run_group(d_groups + gi, groups[gi], z, sd, gd, p, views, ctr, bias, beam, n_lanes,
+                            lane ? lane_st[lane] : st)))
             return rs;
     }
     for (int l = 1; l < n_lanes; l++)
         if ((e = hipEventRecord(join_ev[l], lane_st[l])) || (e = hipStreamWaitEvent(st, join_ev[l], 0)))
             return hip_fail(e, "join the lanes");
-    if ((e = timed(prof, PV3D_STAGE_LOSS, st, [&] { return launch_loss(n_sun, d_sun, beam, counts, d_dpoa, gd, p.k, power, power_ref, st); })))
+    if ((e = timed(prof, PV3D_STAGE_LOSS, st, [&] { return launch_loss(n_sun, d_sun, beam, counts, d_dpoa, gd, p.k, power, power_ref, ctr, st); }, (int32_t)n_sun)))
         return hip_fail(e, "loss");
     if ((e = launch_energy(n_sun, power, power_ref, d_dt, energy, st))) return hip_fail(e, "energy");
+    if ((e = hipEventRecord(ws_ev, st))) return hip_fail(e, "record the end of the evaluation");
+    ws_recorded = true;
     return PV3D_OK;
 }
 
-// 64-texel tiles with more bin entries than this go to four workgroups, one per
-// quadrant (each still walks all of the tile's triangles): the heaviest tiles,
-// under tall occluders, otherwise finish long after the rest of the launch.
-// C2 year: 397 ms at 32, 351 ms at 64, 335 ms at 128, 338 ms at 256 or with no
-// split.
-constexpr int32_t kSplitEntries = 128;
-
-// The launch sequence of one sun.
-pv3d_status Ctx::run_sun(int64_t s, const PathSizes& z, const SceneDev& sd, const GenDev& g_all, const pv3d_params& p,
-                         const View* views, SunCounters* ctr, const int32_t* bias, const double* beam, uint32_t* map,
-                         uint32_t* counts_s, uint32_t* bits_s, const uint32_t* tmask_s, int lane, int n_lanes,
-                         hipStream_t st) {
+// Copy the group descriptors to the device through pinned staging of their own.
+pv3d_status Ctx::upload_groups(const std::vector<SunGroup>& groups, hipStream_t st) {
+    const size_t bytes = sizeof(SunGroup) * groups.size();
     hipError_t e;
-    GenDev gd = g_all;                                   // trackers: this sun's posed modules
-    if (g_all.mods_sun) gd.mods = g_all.mods_sun + s * g_all.n_mod;
-    BinBuffers bb = bin_buffers(z, lane);
-    const bool separate = (p.flags & PV3D_SEPARATE_TEST) != 0;
-    if (separate && !map) map = static_cast<uint32_t*>(w.lane[lane].map.ptr);
-    TileOut to;
-    to.map = map;
-    to.counts = counts_s;
-    to.bits = bits_s;
-    to.test = separate ? 0 : 1;
-    to.sparse = (map == nullptr && !separate && !(p.flags & PV3D_FULL_RASTER)) ? 1 : 0;
-    if (to.sparse) {       // the scan lists the tiles with work, heaviest first; 64-texel ones split in quadrants
-        int32_t* tl = static_cast<int32_t*>(w.lane[lane].tile_list.ptr);
-        bb.list_ctr = tl;
-        bb.tile_list = tl + 2;
-        bb.split_at = z.tile == 64 ? kSplitEntries : 0;
+    if (gstage_busy) {
+        if ((e = hipEventSynchronize(gstage_done))) return hip_fail(e, "wait for the descriptor staging");
+        gstage_busy = false;
     }
-    // pair mode: set-up lays the binned records and module boxes out in pair
-    // space; counting and scatter then share the pairs evenly over the grid
-    bb.pctr = &ctr[s].pairs;
+    if (bytes > gstage_cap) {
+        HoldServing hold(this);          // hipHostFree waits for every stream of the device
+        if (gstage) (void)hipHostFree(gstage);
+        gstage = nullptr;
+        gstage_cap = 0;
+        const size_t cap = std::max(bytes + bytes / 2, (size_t)1 << 20);
+        if ((e = hipHostMalloc(&gstage, cap, hipHostMallocDefault))) return hip_fail(e, "hipHostMalloc descriptors");
+        gstage_cap = cap;
+    }
+    memcpy(gstage, groups.data(), bytes);
+    if ((e = hipMemcpyAsync(w.groups.ptr, gstage, bytes, hipMemcpyHostToDevice, st))) return hip_fail(e, "copy descriptors");
+    if ((e = hipEventRecord(gstage_done, st))) return hip_fail(e, "record descriptor copy");
+    gstage_busy = true;
+    return PV3D_OK;
+}
+
+// The launch sequence of one group of suns.
+pv3d_status Ctx::run_group(const SunGroup* d_grp, const SunGroup& grp, const PathSizes& z, const SceneDev& sd,
+                           const GenDev& gd, const pv3d_params& p, const View* views, SunCounters* ctr,
+                           const int32_t* bias, const double* beam, int n_lanes, hipStream_t st) {
+    hipError_t e;
+    const int32_t ng = grp.n;
+    const bool listed = grp.sun[0].bb.tile_list != nullptr;
+    // pair mode: set-up lays the binned records and module boxes out in pair space;
+    // counting and scatter then share every sun's pairs evenly over the grid
     const int32_t pair_grid = 4 * n_cu;
-    if ((e = timed(prof, PV3D_STAGE_TRI_SETUP, st, [&] { return launch_tri_setup(s, views, sd, gd, bias, p.map_n, bb, ctr, tmask_s, st); })))
+    if ((e = timed(prof, PV3D_STAGE_TRI_SETUP, st, [&] { return launch_tri_setup_group(d_grp, ng, views, sd, gd, bias, p.map_n, ctr, st); }, ng)))
         return hip_fail(e, "tri_setup");
     if ((e = timed(prof, PV3D_STAGE_BIN_SCAN, st, [&] {
-             hipError_t r = launch_pair_count(bb, tmask_s, pair_grid, st);
-             return r ? r : launch_bin_scan(z.n_tiles, bb, st);
-         })))
+             hipError_t r = launch_pair_count_group(d_grp, pair_grid, st);
+             return r ? r : launch_bin_scan_group(d_grp, ng, z.n_tiles, st);
+         }, ng)))
         return hip_fail(e, "bin_scan");
-    if ((e = timed(prof, PV3D_STAGE_BIN_SCATTER, st, [&] { return launch_pair_scatter(bb, tmask_s, pair_grid, st); })))
+    if ((e = timed(prof, PV3D_STAGE_BIN_SCATTER, st, [&] { return launch_pair_scatter_group(d_grp, pair_grid, st); }, ng)))
         return hip_fail(e, "bin_scatter");
     // with several lanes the tile pass keeps to two workgroups per CU, leaving room for the other
     // lane's set-up and binning kernels beside it
     if ((e = timed(prof, PV3D_STAGE_RASTER, st, [&] {
-             return launch_raster(s, views, bb, ctr, p.map_n, gd, bias, static_cast<double*>(w.fu.ptr),
-                                  static_cast<double*>(w.fv.ptr), p.k, to, tmask_s, n_cu, n_lanes > 1 ? 2 : 0, st);
-         })))
+             return launch_raster_group(d_grp, ng, listed, z.tile, z.n_tiles, views, ctr, p.map_n, bias, gd.n_mod,
+                                        static_cast<double*>(w.fu.ptr), static_cast<double*>(w.fv.ptr), p.k, n_cu,
+                                        n_lanes > 1 ? 2 : 0, st);
+         }, ng)))
         return hip_fail(e, "raster");
-    if (separate &&
-        (e = timed(prof, PV3D_STAGE_SAMPLE_TEST, st, [&] {
-             return launch_sample_test(s, views, gd, beam, bias, static_cast<double*>(w.fu.ptr),
-                                       static_cast<double*>(w.fv.ptr), p.k, map, p.map_n, counts_s, bits_s, st);
-         })))
-        return hip_fail(e, "sample_test");
+    if (p.flags & PV3D_SEPARATE_TEST)
+        for (int32_t q = 0; q < ng; q++) {
+            const GroupSun& S = grp.sun[q];
+            if ((e = timed(prof, PV3D_STAGE_SAMPLE_TEST, st, [&] {
+                     return launch_sample_test(S.s, views, S.g, beam, bias, static_cast<double*>(w.fu.ptr),
+                                               static_cast<double*>(w.fv.ptr), p.k, S.out.map, p.map_n, S.out.counts,
+                                               S.out.bits, st);
+                 })))
+                return hip_fail(e, "sample_test");
+        }
     return PV3D_OK;
 }
 
@@ -602,12 +720,16 @@ pv3d_status pv3d_create(int32_t device, uint64_t hbm_budget_bytes, pv3d_ctx** ou
     }
     if ((e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming)) != hipSuccess)
         return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreateWithFlags(&c->ws_ev, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreateWithFlags(&c->gstage_done, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&c->prof.ref)) != hipSuccess) return hip_fail(e, "hipEventCreate");
     {
         hipDeviceProp_t prop;
         if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
         c->max_lds = prop.sharedMemPerBlock;
         c->n_cu = prop.multiProcessorCount;
-        if ((e = configure_kernels(c->max_lds)) != hipSuccess) return hip_fail(e, "configure kernels");
     }
     *out = c.release();
     return PV3D_OK;
@@ -635,6 +757,10 @@ void pv3d_destroy(pv3d_ctx* ctx) {
         if (ctx->join_ev[l]) (void)hipEventDestroy(ctx->join_ev[l]);
     }
     if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->ws_ev) (void)hipEventDestroy(ctx->ws_ev);
+    if (ctx->gstage) (void)hipHostFree(ctx->gstage);
+    if (ctx->gstage_done) (void)hipEventDestroy(ctx->gstage_done);
+    if (ctx->prof.ref) (void)hipEventDestroy(ctx->prof.ref);
     delete ctx;
 }
 
@@ -718,6 +844,7 @@ pv3d_status pv3d_scene_release(pv3d_ctx* ctx, uint64_t scene) {
     if (it == ctx->scenes.end()) return fail(PV3D_ENOENT, "unknown scene %llu", (unsigned long long)scene);
     if (ctx->scene_in_use(scene)) return fail(PV3D_EBUSY, "scene %llu is used by a running job", (unsigned long long)scene);
     (void)hipSetDevice(ctx->device);
+    HoldServing hold(ctx);
     (void)hipDeviceSynchronize();
     ctx->dfree(it->second.xyz);
     ctx->dfree(it->second.tri);
@@ -971,6 +1098,7 @@ pv3d_status pv3d_generator_set_sky(pv3d_ctx* ctx, uint64_t gen, const double* sv
         for (int64_t c = 0; c < cells; c++)
             if (!(svf[c] >= 0.0 && svf[c] <= 1.0)) return fail(PV3D_EINVAL, "cell %lld: sky view factor not in [0, 1]", (long long)c);
     (void)hipSetDevice(ctx->device);
+    HoldServing hold(ctx);
     (void)hipDeviceSynchronize();
     ctx->dfree(g.svf);
     g.svf = nullptr;
@@ -1038,6 +1166,7 @@ pv3d_status pv3d_generator_release(pv3d_ctx* ctx, uint64_t gen) {
     if (it == ctx->gens.end()) return fail(PV3D_ENOENT, "unknown generator %llu", (unsigned long long)gen);
     if (ctx->gen_in_use(gen)) return fail(PV3D_EBUSY, "generator %llu is used by a running job", (unsigned long long)gen);
     (void)hipSetDevice(ctx->device);
+    HoldServing hold(ctx);
     (void)hipDeviceSynchronize();
     free_gen(ctx, it->second);
     ctx->gens.erase(it);
@@ -1076,6 +1205,7 @@ pv3d_status pv3d_evaluate(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const dou
     (void)hipSetDevice(ctx->device);
     hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->stream;
     ctx->stream_in_use = s;
+    ctx->per_sun_ran = true;
     const Scene& sc = si->second;
     const Gen& g = gi->second;
     const pv3d_params& p = *params;
@@ -1161,6 +1291,12 @@ pv3d_status pv3d_profile_enable(pv3d_ctx* ctx, uint32_t stage_mask) {
     hipError_t e = ctx->prof.collect();
     if (e != hipSuccess) return hip_fail(e, "collect timings");
     if (stage_mask == 0) ctx->prof.reset();
+    if (stage_mask != 0 && ctx->prof.mask == 0) {
+        // the origin of the launch intervals; the context stream is idle between calls
+        for (auto& v : ctx->prof.spans) v.clear();
+        if ((e = hipEventRecord(ctx->prof.ref, ctx->stream)) != hipSuccess) return hip_fail(e, "record time origin");
+        if ((e = hipEventSynchronize(ctx->prof.ref)) != hipSuccess) return hip_fail(e, "record time origin");
+    }
     ctx->prof.mask = stage_mask;
     return PV3D_OK;
 }
@@ -1170,6 +1306,18 @@ pv3d_status pv3d_profile_sample(pv3d_ctx* ctx, int32_t every) {
     if (every < 1) return fail(PV3D_EINVAL, "every %d", every);
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     ctx->prof.every = every;
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_profile_busy(pv3d_ctx* ctx, int32_t stage, double* busy_ms, int64_t* suns) {
+    if (!ctx || !busy_ms || !suns) return fail(PV3D_EINVAL, "null argument");
+    if (stage < 0 || stage >= PV3D_N_STAGES) return fail(PV3D_EINVAL, "stage %d", stage);
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    hipError_t e = ctx->prof.collect();
+    if (e != hipSuccess) return hip_fail(e, "collect timings");
+    *busy_ms = ctx->prof.busy_ms(stage);
+    *suns = ctx->prof.suns[stage];
     return PV3D_OK;
 }
 

@@ -69,7 +69,10 @@ pv3d_status device_info(Ctx* c, DevInfo* out) {
         if (!e) e = launch_xcc_probe(d_mask, 8 * d.n_cu, c->stream);
         if (!e) e = hipMemcpyAsync(&mask, d_mask, 4, hipMemcpyDeviceToHost, c->stream);
         if (!e) e = hipStreamSynchronize(c->stream);
-        (void)hipFree(d_mask);
+        {
+            HoldServing hold(c);            // hipFree waits for every stream of the device
+            (void)hipFree(d_mask);
+        }
         if (e) return hip_fail(e, "XCD probe");
         d.xcd_groups = mask == 0xFFu ? 8 : 1;
         c->dev_info = d;
@@ -449,6 +452,9 @@ pv3d_status run_batch(Ctx* c, const pv3d_job* jobs, int64_t n_jobs, hipStream_t 
                                       h.d_dt + t, h.d_counts + t * h.cells, h.d_power + t, h.d_pref + t,
                                       static_cast<double*>(B->energy_tmp.ptr), nullptr, nullptr, s)))
                     return st;
+                bool ovf = false;
+                if ((st = c->read_overflow(1, s, &ovf))) return st;
+                if (ovf) return fail(PV3D_ERANGE, "job %d, sun %lld overflows the per-sun path's buffers", pi.job, (long long)t);
                 redo[(size_t)pi.job] = 1;
             }
             for (int64_t i = 0; i < n_jobs; i++)

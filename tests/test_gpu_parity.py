@@ -211,3 +211,25 @@ def test_c3_rooftop_full_size_sampled_suns(ctx, oracle_lib):
     w = W.c3_rooftop(sweep=yr.subset([700, 2200]))
     got, ref = compare(ctx, oracle_lib, w, bits=False)
     assert got.counts.sum() > 0
+
+
+def test_back_to_back_device_evaluations_on_two_streams(ctx, oracle_lib):
+    """Two asynchronous evaluations queued at once on two streams share the context's work
+    buffers: the second waits for the first, and both equal the oracle."""
+    import torch
+    ws = [W.random_tiny(61, n_sun=7, map_n=160, k=3), W.random_tiny(62, n_boxes=9, n_sun=5, map_n=224, k=4)]
+    hs = [(ctx.load_scene(w.scene), ctx.define_generator(w.gen)) for w in ws]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    _say("[parity] two device evaluations on two streams")
+    counts = [torch.zeros((w.sweep.n, w.gen.n_cells), dtype=torch.int32, device="cuda") for w in ws]
+    torch.cuda.synchronize()
+    got = [ctx.evaluate_device(sh, gh, w.gen, w.sweep, w.map_n, w.k, stream=st, counts=c)
+           for (sh, gh), w, st, c in zip(hs, ws, streams, counts)]
+    torch.cuda.synchronize()
+    for w, g, c, (sh, gh) in zip(ws, got, counts, hs):
+        ref = oracle_lib.evaluate(w.scene, w.gen, w.sweep, w.map_n, w.k)
+        assert np.array_equal(c.cpu().numpy().view(np.uint32), ref.counts), w.name
+        np.testing.assert_allclose(g.power.cpu().numpy(), ref.power, rtol=REL, atol=0)
+        np.testing.assert_allclose(g.energy.cpu().numpy(), ref.energy, rtol=REL, atol=0)
+        ctx.release_scene(sh)
+        ctx.release_generator(gh)
