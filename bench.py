@@ -1,17 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the shadow-map shading path on one MI355X.
 
-A step is one whole year of the row-plant workload (20 x 20 fixed-tilt rows,
-24,000 cells, 50 lattice pylons, 101,602 triangles, 4096 x 4096 depth
-picture, 8 x 8 samples per cell, 4,379 suns above the horizon), evaluated one
-sun position at a time through the C ABI (pv3d_evaluate) with device-resident
-inputs and outputs: view set-up, triangle set-up and binning, raster, sample
-depth check, bypass-diode losses and the energy sums all run on the GPU.
+A step is one whole year of the rooftop BIPV workload (2,000 flat modules,
+120,000 cells, on a roof among 200 buildings and 1,000 trees, 522,010
+triangles, 8192 x 8192 depth picture, 8 x 8 samples per cell, the 4,379 suns
+above the horizon at 40.4 N), evaluated through the C ABI (pv3d_evaluate,
+suns in groups of up to eight per launch sequence) with device-resident inputs
+and outputs: view set-up, triangle set-up and binning, raster, sample depth
+check, bypass-diode losses and the energy sums all run on the GPU.
 
 Prints one JSON line with the throughput (sample x sun shadow tests per
 second; triangles rasterized per second beside it), the roofline of the
-dominant kernel, and the CPU oracle timed on a bounded sample of the same
-workload.
+dominant kernel (priced on its exclusive time: the union of its launches'
+intervals), the CPU oracle timed on a bounded sample of the same workload,
+and legs: the row plant year, the batched and serving forms, trackers, many
+generators, the single-diode model and sky view factors.
 """
 from __future__ import annotations
 
@@ -30,7 +33,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-LEGS = ("batched", "c4", "trackers", "stadium", "electrical", "sky", "serving")
+LEGS = ("row_plant", "batched", "c4", "trackers", "stadium", "electrical", "sky", "serving")
+WORKLOAD_KEY = {"c1": "c1_tiny", "c2": "c2_row_plant", "c3": "c3_rooftop"}
 
 
 def parse():
@@ -38,12 +42,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
     ap.add_argument("--suns", type=int, default=0,
                     help="profiling runs only: use every n-th sun of the year (0 = all)")
     ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--cpu-every", type=int, default=20, help="oracle leg: every n-th sun of the year")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
+    ap.add_argument("--cpu-every", type=int, default=100, help="oracle leg: every n-th sun of the year")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     ap.add_argument("--route", default="sparse", choices=["sparse", "materialised"],
@@ -51,16 +55,17 @@ def parse():
                          "sun's full picture written to HBM and read back by a separate depth-check kernel")
     ap.add_argument("--no-materialised", action="store_true",
                     help="skip the extra one-step run of the materialised route")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched, C4, serving, tracker, stadium, electrical and sky legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip every leg")
     ap.add_argument("--extra-legs", default="all",
-                    help="comma-separated extra legs to run (batched, c4, trackers, stadium, electrical, sky, serving); "
-                         "default all")
-    ap.add_argument("--c4-every", type=int, default=50, help="C4 leg: every n-th sun of the year")
+                    help="comma-separated legs to run (" + ", ".join(LEGS) + "); default all")
+    ap.add_argument("--c4-every", type=int, default=1, help="C4 leg: every n-th sun of the year (1 = full year)")
     ap.add_argument("--stadium-every", type=int, default=4, help="stadium leg: every n-th sun of the year")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="serving leg: arrivals per second")
-    ap.add_argument("--serve-seconds", type=float, default=0.1, help="serving leg: seconds of arrivals")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="serving leg: seconds of arrivals")
     ap.add_argument("--light-rate", type=float, default=4.0, help="serving leg: light-load arrivals per second")
     ap.add_argument("--light-seconds", type=float, default=3.0, help="serving leg: light-load seconds of arrivals")
+    ap.add_argument("--sweep-requests", type=int, default=40,
+                    help="serving leg: requests per rate of the rate sweep (0 = no sweep)")
     return ap.parse_args()
 
 
@@ -76,14 +81,6 @@ def workload(name, every):
     return W.c3_rooftop(sweep=yr)
 
 
-def algorithmic_bytes(w):
-    """Per sun: FP64 vertices and int32 indices read once, the 24-bit depth picture written
-    once in 32-bit words, one 32-bit count per cell (samples are procedural)."""
-    V = w.scene.n_vert + 4 * w.gen.n_mod
-    T = w.n_tri_submitted
-    return 24 * V + 12 * T + 4 * w.map_n * w.map_n + 4 * w.gen.n_cells
-
-
 # Peaks of one MI355X: HBM3E 8 TB/s; VALU lane operations (int32 / fp32 / fp64
 # non-packed: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -96,7 +93,7 @@ SAMPLE_LANE_OPS = 88
 
 
 def stage_roofline(stage, w, route):
-    """(bound, algorithmic units per launch, unit, peak) of one launch of a stage (one sun)."""
+    """(bound, algorithmic units per sun, unit, peak) of a stage."""
     V = w.scene.n_vert + 4 * w.gen.n_mod
     if stage == "raster" and route == "materialised":
         return "hbm", 4 * w.map_n * w.map_n, "GB/s", HBM_PEAK_GBS        # the picture, written once
@@ -109,22 +106,106 @@ def stage_roofline(stage, w, route):
     return "hbm", 0, "GB/s", HBM_PEAK_GBS
 
 
-def measured_traffic(kernel, route):
-    """HBM bytes per launch of the tile kernel from the committed rocprofv3 counter summary, or
-    None when the kernel source changed since the counters were taken."""
+def profile_path(wname):
+    return os.path.join(ROOT, "profiles", f"tile_{wname}.md")
+
+
+def measured_traffic(kernel, route, wname="c2_row_plant"):
+    """HBM bytes per sun of the tile kernel from the committed rocprofv3 counter summary of
+    that workload, or None when the kernel source changed since the counters were taken."""
     import hashlib
     if kernel != "raster" or route != "sparse":
         return None
-    prof = os.path.join(ROOT, "profiles", "tile_c2_row_plant.md")
+    prof = profile_path(wname)
     src = os.path.join(ROOT, "paper_1410_5780_amd", "csrc", "pv3d_kernels.hip")
     try:
         kv = dict(line.split(" = ", 1) for line in open(prof).read().splitlines() if " = " in line)
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
-    if kv.get("kernel_source_sha256_16", "").strip() != sha:
+    if kv.get("kernel_source_sha256_16", "").strip() != sha or "tile_traffic_bytes_per_sun" not in kv:
         return None
-    return int(kv["tile_traffic_bytes_per_launch"])
+    return int(kv["tile_traffic_bytes_per_sun"])
+
+
+def timed_year(ctx, w, sh, gh, steps, warmup, route="sparse", tile=0, log=None):
+    """Warm-up passes (the first times every stage), then `steps` timed passes of the sweep
+    with every launch of the dominant stage bracketed by events: seconds per pass, the
+    stage table, and the dominant stage's event time and exclusive (union) time per sun."""
+    import torch
+    from paper_1410_5780_amd import pv3d
+    counts = torch.empty((w.sweep.n, w.gen.n_cells), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(r=route):
+        return ctx.evaluate_device(sh, gh, w.gen, w.sweep, w.map_n, w.k, stream=stream, counts=counts, tile=tile,
+                                   separate_test=(r == "materialised"))
+
+    stage_ms = {}
+    res = None
+    for i in range(max(warmup, 1)):
+        if i == 0:
+            ctx.profile_enable((1 << pv3d.N_STAGES) - 1)
+        res = step()
+        torch.cuda.synchronize()
+        if i == 0:
+            for nm, sid in pv3d.STAGE.items():
+                ms, n = ctx.profile_read(sid)
+                busy, suns = ctx.profile_busy(sid)
+                stage_ms[nm] = {"total_ms": ms, "launches": n, "busy_ms": busy, "suns": suns,
+                                "busy_us_per_sun": 1e3 * busy / max(suns, 1)}
+            ctx.profile_enable(0)
+        if log:
+            log(f"[bench] {w.name}: warmup {i} done")
+    dominant = max(stage_ms, key=lambda k: stage_ms[k]["busy_ms"])
+    sid = pv3d.STAGE[dominant]
+    ctx.profile_sample(1)
+    ctx.profile_enable(1 << sid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_n = ctx.profile_read(sid)
+    busy_ms, suns = ctx.profile_busy(sid)
+    ctx.profile_enable(0)
+    if log:
+        log(f"[bench] {w.name}: timed {steps} passes in {t1 - t0:.3f} s")
+    return {"sec_per_step": (t1 - t0) / steps, "stage_ms": stage_ms, "dominant": dominant,
+            "event_ms": k_ms, "launches": k_n, "busy_ms": busy_ms, "suns": suns, "result": res, "step": step}
+
+
+def roofline_of(t, w, route):
+    bound, units, unit, peak = stage_roofline(t["dominant"], w, route)
+    scale = 1e9 if unit == "GB/s" else 1e12
+    busy_s = t["busy_ms"] * 1e-3
+    achieved = units * t["suns"] / busy_s / scale if units and busy_s > 0 else None
+    return {"kernel": t["dominant"], "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": (achieved / peak) if achieved else None,
+            "traffic": measured_traffic(t["dominant"], route, w.name.split(":")[0]),
+            "exclusive_us_per_sun": 1e3 * t["busy_ms"] / max(t["suns"], 1),
+            "event_us_per_launch": 1e3 * t["event_ms"] / max(t["launches"], 1),
+            "launches": t["launches"], "suns": t["suns"], "units_per_sun": units,
+            "model": ("88 lane-ops per sample (FP64 light-space map, floors, two covering surfaces' edge and "
+                      "depth evaluations), over the union of the kernel's launch intervals" if bound == "alu"
+                      else "algorithmic bytes over the union of the kernel's launch intervals")}
+
+
+def row_plant_leg(ctx, log, steps):
+    """The row plant year (C2) through the same per-sun path, with its own roofline."""
+    from paper_1410_5780_amd import workloads as W
+    w = W.c2_row_plant()
+    sh, gh = ctx.load_scene(w.scene), ctx.define_generator(w.gen)
+    t = timed_year(ctx, w, sh, gh, steps, 1, log=log)
+    res = t["result"]
+    out = {"workload": f"{w.name}: {w.note}; {w.sweep.n} suns", "year_seconds": t["sec_per_step"],
+           "value": w.n_samples * w.sweep.n / t["sec_per_step"], "unit": "sample-sun tests/s",
+           "triangles_per_s": w.n_tri_submitted * w.sweep.n / t["sec_per_step"],
+           "roofline": roofline_of(t, w, "sparse"), "energy_loss": res.loss,
+           "stage_busy_us_per_sun": {k: round(v["busy_us_per_sun"], 3) for k, v in t["stage_ms"].items()}}
+    log(f"[bench] row plant year {t['sec_per_step']:.3f} s")
+    return out, (w, sh, gh, res)
 
 
 def batched_leg(ctx, w, sh, gh, plain_energy, plain_power, plain_year_s, log):
@@ -167,7 +248,7 @@ def c4_leg(ctx, every, log):
     tune_s = time.perf_counter() - t0
     log(f"[bench] c4: {len(ws)} sites x {sub.n} suns, autotuned {len(tuned)} classes in {tune_s:.2f} s")
     best_p = best_b = None
-    for _ in range(2):
+    for _ in range(1 if every == 1 else 2):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         plain = [ctx.evaluate_device(sp["scene"], sp["gen"], sp["generator"], sp["sweep"], sp["map_n"], sp["k"])
@@ -344,39 +425,60 @@ def sky_leg(ctx, log, n_dir=145):
             "energy_loss_beam_only": base.loss, "energy_loss_with_diffuse": r.loss}
 
 
-def serving_leg(ctx, log, rate_hz, duration_s, light_rate, light_s):
-    """Poisson request streams through the serving loop: latency from arrival to completion."""
+def serving_leg(ctx, log, rate_hz, duration_s, light_rate, light_s, sweep_n):
+    """Poisson request streams through the serving loop: latency from arrival to completion.
+    The configured stream (200 req/s) offers more than one GPU evaluates, so it reports the
+    offered and the sustained rates; a sweep below the sustained rate finds the highest
+    arrival rate at which p99 stays within twice its value at the lightest swept rate."""
     from paper_1410_5780_amd import serve, workloads as W
     out = {}
-    for name, rate, dur, seed in (("configured_rate", rate_hz, duration_s, 5), ("light_load", light_rate, light_s, 6)):
-        reqs = W.serving_stream(seed=seed, rate_hz=rate, duration_s=dur)
-        if not reqs:
-            continue
-        log(f"[bench] serving {name}: {len(reqs)} requests at {rate} /s")
-        r = serve.run_stream(ctx, reqs, seed=seed, log=log)
-        r.update({"rate_hz": rate, "duration_s": dur})
-        log(f"[bench] serving {name}: {r['requests']} requests, p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms")
-        out[name] = r
+    reqs = W.serving_stream(seed=5, rate_hz=rate_hz, duration_s=duration_s)
+    log(f"[bench] serving configured: {len(reqs)} requests at {rate_hz} /s")
+    r = serve.run_stream(ctx, reqs, seed=5, log=log)
+    r.update({"rate_hz": rate_hz, "duration_s": duration_s,
+              "offered_req_per_s": len(reqs) / duration_s, "sustained_req_per_s": len(reqs) / r["wall_s"],
+              "offered_tests_per_s": r["tests"] / duration_s, "sustained_tests_per_s": r["tests"] / r["wall_s"]})
+    log(f"[bench] serving configured: {r['requests']} requests, p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms, "
+        f"sustained {r['sustained_req_per_s']:.1f} of {r['offered_req_per_s']:.1f} req/s offered")
+    out["configured_rate"] = r
+    lr = W.serving_stream(seed=6, rate_hz=light_rate, duration_s=light_s)
+    if lr:
+        r2 = serve.run_stream(ctx, lr, seed=6, log=log)
+        r2.update({"rate_hz": light_rate, "duration_s": light_s})
+        out["light_load"] = r2
+        log(f"[bench] serving light load: {r2['requests']} requests, p50 {r2['p50_ms']:.1f} ms, p99 {r2['p99_ms']:.1f} ms")
+    if sweep_n > 0:
+        cap = out["configured_rate"]["sustained_req_per_s"]
+        sweep = []
+        for i, f in enumerate((0.25, 0.5, 0.75)):
+            rate = f * cap
+            rq = W.serving_stream(seed=20 + i, rate_hz=rate, duration_s=sweep_n / rate)
+            if not rq:
+                continue
+            rs = serve.run_stream(ctx, rq, seed=20 + i, log=log)
+            sweep.append({"rate_hz": rate, "requests": rs["requests"], "p50_ms": rs["p50_ms"], "p99_ms": rs["p99_ms"],
+                          "sustained_req_per_s": rs["requests"] / rs["wall_s"]})
+            log(f"[bench] serving sweep {rate:.1f} req/s: p50 {rs['p50_ms']:.1f} ms, p99 {rs['p99_ms']:.1f} ms")
+        flat = [x for x in sweep if sweep and x["p99_ms"] <= 2.0 * sweep[0]["p99_ms"]]
+        out["rate_sweep"] = sweep
+        out["highest_flat_p99_rate_hz"] = max(x["rate_hz"] for x in flat) if flat else None
     return out
 
 
-def cpu_baseline(w_full, every):
+def cpu_baseline(w_full, every, threads=0):
     from oracle import oracle as O
     sw = w_full.sweep.subset(np.arange(0, w_full.sweep.n, every))
-    cores = os.cpu_count() or 1
+    cores = threads or (os.cpu_count() or 1)
     t0 = time.perf_counter()
     r = O.evaluate(w_full.scene, w_full.gen, sw, w_full.map_n, w_full.k, threads=cores)
     dt = time.perf_counter() - t0
     tests = w_full.n_samples * sw.n
     return {"value": tests / dt, "unit": "sample-sun tests/s", "cores": cores, "kind": "oracle",
-            "sample": f"every {every}th sun of the year ({sw.n} suns) of the same workload, "
+            "sample": f"{w_full.name}: every {every}th sun of the year ({sw.n} suns) of the same workload, "
                       f"{dt:.1f} s wall on {cores} threads; per-sun time extrapolates to "
-                      f"{dt / sw.n * w_full.sweep.n:.0f} s for the year",
-            "seconds": dt, "triangles_per_s": w_full.n_tri_submitted * sw.n / dt,
+                      f"{dt / sw.n * 4379:.0f} s for the year",
+            "seconds": dt, "suns": sw.n, "triangles_per_s": w_full.n_tri_submitted * sw.n / dt,
             "loss_sample": r.loss}
-
-
-SAMPLE = 8      # the timed region times every SAMPLE-th launch of the dominant kernel
 
 
 def main():
@@ -391,51 +493,19 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     w = workload(a.workload, a.suns)
     n_sun = w.sweep.n
-    print(f"[bench] workload {w.name}: {w.n_tri_submitted} triangles, {w.gen.n_cells} cells, "
-          f"{n_sun} suns, N={w.map_n}, k={w.k}", file=sys.stderr, flush=True)
+    log(f"[bench] workload {w.name}: {w.n_tri_submitted} triangles, {w.gen.n_cells} cells, "
+        f"{n_sun} suns, N={w.map_n}, k={w.k}")
     ctx = pv3d.Context(0)
     sh = ctx.load_scene(w.scene)
     gh = ctx.define_generator(w.gen)
-    counts = torch.empty((n_sun, w.gen.n_cells), dtype=torch.int32, device="cuda")
-    stream = torch.cuda.current_stream()
-
-    def step(route=a.route):
-        return ctx.evaluate_device(sh, gh, w.gen, w.sweep, w.map_n, w.k, stream=stream, counts=counts, tile=a.tile,
-                                   separate_test=(route == "materialised"))
-
-    # warmup; the first warmup pass also times every stage to find the dominant kernel
-    stage_ms = {}
-    for i in range(max(a.warmup, 1)):
-        if i == 0:
-            ctx.profile_enable((1 << pv3d.N_STAGES) - 1)
-        res = step()
-        torch.cuda.synchronize()
-        if i == 0:
-            for nm, sid in pv3d.STAGE.items():
-                ms, n = ctx.profile_read(sid)
-                stage_ms[nm] = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / max(n, 1)}
-            ctx.profile_enable(0)
-        print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
-    dominant = max(stage_ms, key=lambda k: stage_ms[k]["total_ms"])
-    sid = pv3d.STAGE[dominant]
-
-    # timed region: K steps, events around every SAMPLE-th launch of the dominant kernel on the
-    # stream it runs on (events between the kernels hold back the lanes' overlap; a uniform
-    # sample measures the same average while disturbing the year less)
-    ctx.profile_sample(SAMPLE)
-    ctx.profile_enable(1 << sid)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        res = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    k_ms, k_n = ctx.profile_read(sid)
-    ctx.profile_enable(0)
-    ctx.profile_sample(1)
-    print(f"[bench] timed {a.steps} steps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
+    t = timed_year(ctx, w, sh, gh, a.steps, a.warmup, a.route, a.tile, log)
+    res = t["result"]
 
     if a.calib_copy_mb:
         nb = a.calib_copy_mb << 20
@@ -444,38 +514,36 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(f"[bench] calibration copy of {nb} bytes done", file=sys.stderr, flush=True)
+        log(f"[bench] calibration copy of {nb} bytes done")
 
-    sec_per_step = (t1 - t0) / a.steps
+    sec_per_step = t["sec_per_step"]
     tests = w.n_samples * n_sun
     tris = w.n_tri_submitted * n_sun
-    avg_s = k_ms * 1e-3 / max(k_n, 1)
-    bound, units, unit, peak = stage_roofline(dominant, w, a.route)
-    achieved = units / avg_s / (1e9 if unit == "GB/s" else 1e12) if units else None
-    loss = res.loss
 
     mat = None
     if not a.no_materialised and a.route != "materialised":
-        # the same year with the picture materialised in HBM: raster writes it, a second kernel reads it
+        # every 10th sun with the picture materialised in HBM: raster writes it, a second kernel reads it
+        sub = w.sweep.subset(np.arange(0, n_sun, 10))
+        ctx.profile_sample(1)
         ctx.profile_enable((1 << pv3d.STAGE["raster"]) | (1 << pv3d.STAGE["sample_test"]))
         torch.cuda.synchronize()
         m0 = time.perf_counter()
-        mres = step("materialised")
+        mres = ctx.evaluate_device(sh, gh, w.gen, sub, w.map_n, w.k, separate_test=True)
         torch.cuda.synchronize()
         m1 = time.perf_counter()
-        r_ms, r_n = ctx.profile_read(pv3d.STAGE["raster"])
-        t_ms, t_n = ctx.profile_read(pv3d.STAGE["sample_test"])
+        r_busy, r_suns = ctx.profile_busy(pv3d.STAGE["raster"])
+        t_busy, _ = ctx.profile_busy(pv3d.STAGE["sample_test"])
         ctx.profile_enable(0)
-        r_avg = r_ms * 1e-3 / max(r_n, 1)
+        lean = ctx.evaluate_device(sh, gh, w.gen, sub, w.map_n, w.k)
         mb = 4 * w.map_n * w.map_n
-        mat = {"year_seconds": (m1 - m0) * (4379.0 / n_sun), "identical_energy": bool(
-                   np.array_equal(mres.energy.cpu().numpy(), res.energy.cpu().numpy())),
-               "raster_avg_us": r_avg * 1e6, "sample_test_avg_us": t_ms * 1e3 / max(t_n, 1),
-               "raster_roofline": {"bound": "hbm", "achieved": mb / r_avg / 1e9, "peak": HBM_PEAK_GBS,
-                                   "unit": "GB/s", "frac": mb / r_avg / 1e9 / HBM_PEAK_GBS,
-                                   "bytes_per_launch": mb}}
-        print(f"[bench] materialised route: {m1 - m0:.3f} s", file=sys.stderr, flush=True)
-    path_bytes = algorithmic_bytes(w) * n_sun
+        r_per = r_busy * 1e-3 / max(r_suns, 1)
+        mat = {"suns": sub.n, "year_seconds": (m1 - m0) * (n_sun / sub.n), "identical_energy": bool(
+                   np.array_equal(mres.energy.cpu().numpy(), lean.energy.cpu().numpy())),
+               "raster_exclusive_us_per_sun": r_per * 1e6, "sample_test_exclusive_us_per_sun": t_busy * 1e3 / max(r_suns, 1),
+               "raster_roofline": {"bound": "hbm", "achieved": mb / r_per / 1e9, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": mb / r_per / 1e9 / HBM_PEAK_GBS,
+                                   "bytes_per_sun": mb}}
+        log(f"[bench] materialised route: {sub.n} suns in {m1 - m0:.3f} s")
     line = {
         "metric": "sample x sun shadow tests/s (+ triangles rasterized/s)",
         "value": tests / sec_per_step,
@@ -489,36 +557,30 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {w.note}; {n_sun} suns per step, plain per-sun launch loop",
+        "config": {"workload": f"{w.name}: {w.note}; {n_sun} suns per step, per-sun path (groups of up to 8 suns "
+                               f"per launch sequence)",
                    "route": a.route,
                    "triangles": w.n_tri_submitted, "cells": w.gen.n_cells, "samples_per_sun": w.n_samples,
                    "suns": n_sun, "map_n": w.map_n, "k": w.k},
         "triangles_per_s": tris / sec_per_step,
         "year_seconds": sec_per_step * (4379.0 / n_sun),
-        "path_hbm_roofline": {"algorithmic_bytes_per_sun": algorithmic_bytes(w),
-                              "achieved_GBs": path_bytes / sec_per_step / 1e9,
-                              "frac": path_bytes / sec_per_step / 1e9 / HBM_PEAK_GBS},
-        "roofline": {"kernel": dominant, "bound": bound, "achieved": achieved, "peak": peak,
-                     "unit": unit, "frac": (achieved / peak) if achieved else None,
-                     "traffic": measured_traffic(dominant, a.route), "avg_launch_us": avg_s * 1e6, "launches": k_n,
-                     "timed_every": SAMPLE,
-                     "units_per_launch": units,
-                     "model": ("88 lane-ops per sample (FP64 light-space map, floors, two covering surfaces' "
-                               "edge and depth evaluations)" if bound == "alu" else "algorithmic bytes")},
+        "roofline": roofline_of(t, w, a.route),
         "route": a.route,
         "materialised_route": mat,
-        "stage_avg_us": {k: round(v["avg_us"], 3) for k, v in stage_ms.items()},
-        "energy_loss": loss,
+        "stage_busy_us_per_sun": {k: round(v["busy_us_per_sun"], 3) for k, v in t["stage_ms"].items()},
+        "energy_loss": res.loss,
     }
-    if not a.no_extra and a.route == "sparse" and a.suns <= 1 and a.workload == "c2":
-        def log(msg):
-            print(msg, file=sys.stderr, flush=True)
+    if not a.no_extra and a.route == "sparse" and a.suns <= 1:
         legs = set(LEGS) if a.extra_legs == "all" else set(a.extra_legs.split(","))
         if legs - set(LEGS):
             raise SystemExit(f"unknown legs {sorted(legs - set(LEGS))}; known: {', '.join(LEGS)}")
+        rp = None
+        if "row_plant" in legs or "batched" in legs:
+            line["row_plant"], rp = row_plant_leg(ctx, log, max(1, min(a.steps, 10)))
         if "batched" in legs:
-            line["batched"] = batched_leg(ctx, w, sh, gh, res.energy.cpu().numpy(), res.power.cpu().numpy(),
-                                          line["year_seconds"], log)
+            w2, sh2, gh2, r2 = rp
+            line["batched"] = batched_leg(ctx, w2, sh2, gh2, r2.energy.cpu().numpy(), r2.power.cpu().numpy(),
+                                          line["row_plant"]["year_seconds"], log)
         if "c4" in legs:
             line["c4_batched"] = c4_leg(ctx, a.c4_every, log)
         if "trackers" in legs:
@@ -530,19 +592,21 @@ def main():
         if "sky" in legs:
             line["sky"] = sky_leg(ctx, log)
         if "serving" in legs:
-            # the serving loop runs in a context of its own, opened after this one is closed: a loop started
-            # in a context whose per-sun path has run has stalled now and then (cause not found)
+            # the serving loop starts only in a context whose per-sun path has not run
             ctx.close()
             sctx = pv3d.Context(0)
             try:
                 line["serving"] = serving_leg(sctx, log, a.serve_rate, a.serve_seconds, a.light_rate,
-                                              a.light_seconds)
+                                              a.light_seconds, a.sweep_requests)
             finally:
                 sctx.close()
     if not a.no_cpu:
-        print("[bench] cpu oracle leg ...", file=sys.stderr, flush=True)
+        log("[bench] cpu oracle legs ...")
         full = w if a.suns <= 1 else workload(a.workload, 1)
         line["cpu_baseline"] = cpu_baseline(full, a.cpu_every)
+        from paper_1410_5780_amd import workloads as W
+        line["cpu_single_thread"] = {"c1_tiny": cpu_baseline(W.c1_tiny(d_poa=100.0), 1, threads=1),
+                                     "c2_row_plant": cpu_baseline(W.c2_row_plant(), 100, threads=1)}
     ctx.close()
     print(json.dumps(line), flush=True)
 

@@ -16,7 +16,8 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 KERNELS = os.path.join("paper_1410_5780_amd", "csrc", "pv3d_kernels.hip")
-PROFILE = os.path.join("profiles", "tile_c2_row_plant.md")
+WL = "c3_rooftop_bipv"
+PROFILE = os.path.join("profiles", f"tile_{WL}.md")
 
 
 def _run(*args):
@@ -51,17 +52,17 @@ def test_traffic_only_for_the_profiled_kernel_source(tmp_path, monkeypatch):
     text = prof.read_text()
     lines = [ln for ln in text.splitlines() if not ln.startswith("kernel_source_sha256_16 = ")]
     prof.write_text("\n".join(lines + [f"kernel_source_sha256_16 = {sha}", ""]))
-    got = bench.measured_traffic("raster", "sparse")
+    got = bench.measured_traffic("raster", "sparse", WL)
     assert isinstance(got, int) and got > 0
-    assert bench.measured_traffic("raster", "materialised") is None
+    assert bench.measured_traffic("raster", "materialised", WL) is None
     src.write_bytes(src.read_bytes() + b"\n")          # the kernel changed since the counters were taken
-    assert bench.measured_traffic("raster", "sparse") is None
+    assert bench.measured_traffic("raster", "sparse", WL) is None
     prof.unlink()
-    assert bench.measured_traffic("raster", "sparse") is None
+    assert bench.measured_traffic("raster", "sparse", WL) is None
 
 
 def test_committed_profile_matches_the_kernel_source():
     """The committed rocprofv3 summary was made from the kernels as they stand, so the benchmark's
     traffic figure is a measured one (regenerate the summary after any change to the kernels)."""
-    got = bench.measured_traffic("raster", "sparse")
+    got = bench.measured_traffic("raster", "sparse", WL)
     assert isinstance(got, int) and got > 0
