@@ -77,7 +77,7 @@ struct BinBuffers {
     int32_t* bins;         // [bin_cap]
     int4* modbox;          // [n_mod] tile range (x0, x1, y0, y1) of each module's samples; x0 > x1: none
     int32_t* tile_list;    // [4 n_tiles] work items of the tile pass, heaviest first (nullptr: one per tile)
-    int32_t* list_ctr;     // [2] items listed, next item to take (the scan sets both)
+    int32_t* list_ctr;     // [3] items listed, next item to take, first light item (the scan sets all three)
     int32_t split_at;      // list order: < 0 tile order; else heaviest first, tiles with more
                            // entries than split_at > 0 as four quadrant items
     // pair mode (pitems != nullptr): the triangle set-up only lays out items

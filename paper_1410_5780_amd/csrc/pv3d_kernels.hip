@@ -797,6 +797,10 @@ __device__ __forceinline__ unsigned long long scan_excl64(unsigned long long v, 
 // its four quadrants. part holds 2 NT + 2 kScanBuckets ints; the count total
 // is left in part[0].
 constexpr int kScanBuckets = 256;
+// Tiles with fewer than 8 kLightBuckets bin entries (the last kLightBuckets
+// buckets of the heaviest-first order, so the tail of the work list) are
+// light: the group tile kernel takes them one wave each.
+constexpr int kLightBuckets = 6;
 
 // A thread with at most kScanKeep tiles keeps their counts in registers for
 // the later passes instead of reading the starts back from memory (C2 year
@@ -907,6 +911,7 @@ __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& b
     unsigned long long n_items64;
     const unsigned long long first = scan_excl64<NT>(own, wsum, n_items64);
     if (tid < kScanBuckets) cur[tid] = (int32_t)first;
+    if (tid == kScanBuckets - kLightBuckets) part[1] = (int32_t)first;   // light tiles are the list's tail
     const int32_t n_items = (int32_t)n_items64;
     __syncthreads();
     for (int32_t j = 0; j < per; j++) {
@@ -938,6 +943,7 @@ __global__ __launch_bounds__(NT) void k_bin_scan_g(const SunGroup* __restrict__ 
     if (bb.tile_list && threadIdx.x == 0) {
         bb.list_ctr[0] = n_items;
         bb.list_ctr[1] = 0;
+        bb.list_ctr[2] = bb.split_at >= 0 ? part[1] : n_items;   // first light item
     }
 }
 
@@ -1125,7 +1131,25 @@ constexpr int kMaxTileCells = 1024;     // (module slot, cell) counters of the s
 
 struct TileCtx {
     int32_t x0, y0, n, bs, be, n_large;
+    const TriRec* lrec;     // the first n_lrec records of the large list, kept in LDS
+    int32_t n_lrec;
+    const double* fu_l;     // sample fractions along edge_u and edge_v (LDS copies when they fit)
+    const double* fv_l;
 };
+
+// Sample fractions (k n_cu along edge_u, then k n_cv along edge_v) a workgroup
+// of the group tile kernel keeps in LDS when they fit.
+constexpr int kFracCache = 256;
+
+// Records of a sun's large list (triangles every tile checks) that a
+// workgroup of the group tile kernel keeps in LDS while it takes that sun's
+// tiles: the list is the same for every tile, and reading its records from
+// memory for each tile was a large part of the tile pass on the rooftop
+// workload (about 21 large triangles per tile).
+constexpr int kLargeCache = 32;
+// Triangle slots a wave of a light tile stages: kLargeCache + 8 kLightBuckets - 1
+// candidates at most.
+constexpr int kWaveSlots = 80;
 
 // Waves take triangles in chunks; the lanes of the wave load the chunk's
 // records at once, then the wave walks them one by one from registers.
@@ -1503,6 +1527,8 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
                             const TileOut& out, const TileCtx& c, int tid, int lane, int wv) {
     const int32_t cpm = g.n_cu * g.n_cv;
     const int32_t knu = k * g.n_cu, knv = k * g.n_cv;
+    const double* const fu_l = c.fu_l;
+    const double* const fv_l = c.fv_l;
     double xl, xh, yl, yh;
     rect_bounds(r, c.n, xl, xh, yl, yh);
     if (tid == 0) { sh.n_ent = 0; sh.ent_overflow = 0; sh.max_thr = INT32_MIN; sh.next = 0; }
@@ -1512,7 +1538,11 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
     //    module finds its light-space map and conservative row range; a thread
     //    per row finds the row's column range; the (row, column) candidates are
     //    then spread evenly over all threads, each finding its row by binary
-    //    search, and the entries are allocated once per wave.
+    //    search, and the entries are allocated once per wave. The fractions come
+    //    from the sample tables (the same correctly rounded quotients
+    //    (q + 1/2) / (k n)), in LDS when the workgroup holds a copy: one division
+    //    per sample coordinate was part of what made listing half of the rooftop
+    //    workload's tile time.
     //    Meanwhile `cells` holds the row tables, the triangle slots the map
     //    cache and the (not yet used) entry order the module biases.
     uint32_t* const mstart = cells;            // [256] (first row << 12) | first row index qb0, per module slot
@@ -1523,7 +1553,6 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
     int32_t* const mbias = reinterpret_cast<int32_t*>(sp.order);
     static_assert(sizeof(ModMap) * kMapCache <= sizeof(TriSlot) * kTriChunk, "map cache exceeds the slot area");
     static_assert(kMaxTileMods <= 256 && 4 * kMaxTileMods <= 2 * CAP, "one thread per module slot, biases in the order area");
-    const double dknu = (double)knu, dknv = (double)knv;
     int32_t my_max = INT32_MIN;
     int32_t n_rows;
     {
@@ -1555,7 +1584,7 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
             ModMap mm;
             if (mi < kMapCache) mm = mcache[mi];
             else module_map(V, g.mods[mods[mi]], mm);
-            const double fv = ((double)qb + 0.5) / dknv;     // the sample's fraction along edge_v
+            const double fv = fv_l[qb];                      // the sample's fraction along edge_v
             int32_t qa0, qa1;
             col_range(mm, fv, knu, xl, xh, yl, yh, qa0, qa1);
             cnt = qa0 <= qa1 ? qa1 - qa0 + 1 : 0;
@@ -1583,8 +1612,8 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
                 const int32_t bm = mbias[mi];
                 if (mi < kMapCache) mm = mcache[mi];
                 else module_map(V, g.mods[mods[mi]], mm);
-                const double fv = ((double)qb + 0.5) / dknv;
-                const double fu = ((double)qa + 0.5) / dknu;     // the sample's fraction along edge_u
+                const double fv = fv_l[qb];
+                const double fu = fu_l[qa];                      // the sample's fraction along edge_u
                 int32_t zs;
                 ok = sample_in_rect(mm, fu, fv, r, c.n, &li, &lj, &zs);
                 if (ok) {
@@ -1659,9 +1688,17 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
             TriRec R;
             TriClip t;
             if (item < total) {
-                const int32_t rid = item < c.n_large ? bb.large[item] : bb.bins[c.bs + item - c.n_large];
-                if (rid >= 0) {
-                    R = bb.rec[rid];
+                bool have = item < c.n_lrec;
+                if (have) {
+                    R = c.lrec[item];
+                } else {
+                    const int32_t rid = item < c.n_large ? bb.large[item] : bb.bins[c.bs + item - c.n_large];
+                    if (rid >= 0) {
+                        R = bb.rec[rid];
+                        have = true;
+                    }
+                }
+                if (have) {
                     if (clip_to_rect(R, r, t)) {
                         const int64_t zmin = R.z0 + R.gx * (R.gx > 0 ? t.ilo : t.ihi) + R.gy * (R.gy > 0 ? t.jlo : t.jhi);
                         keep = (int64_t)depth_q(zmin) < (int64_t)mthr;
@@ -1814,13 +1851,16 @@ struct TileLds {
     alignas(4) uint8_t tlist[64 * kStampList];   // read two bytes at a time
     int32_t next, n_mods, mods_overflow, n_todo, n_failed;
     SparseShared sh;
+    TriRec lcache[kLargeCache];
+    double ftab[kFracCache];
+    static_assert(TS != 64 || 4 * kWaveSlots * sizeof(TriSlot) <= POOL, "wave slots of four waves fit the pool");
 };
 
 // One work item of one sun: a tile, or a quadrant of it (the tile's samples
 // in that quadrant, against every triangle binned to the tile). V, bias_s and
 // n_large are this sun's view, module biases and count of unbinned triangles.
 template <int TS, int CAP>
-__device__ __attribute__((always_inline)) void tile_body(TileLds<TS, CAP>& L, int32_t item, const View& V, const BinBuffers& bb, int32_t n_large,
+__device__ __attribute__((always_inline)) void tile_body(TileLds<TS, CAP>& L, int32_t item, int32_t n_lcache, bool lds_tables, const View& V, const BinBuffers& bb, int32_t n_large,
                           int32_t n, const GenDev& g, const int32_t* bias, const double* fu_tab,
                           const double* fv_tab, int32_t k, const TileOut& out, int32_t sparse,
                           const uint32_t* tmask) {
@@ -1860,6 +1900,10 @@ __device__ __attribute__((always_inline)) void tile_body(TileLds<TS, CAP>& L, in
     c.bs = min(bb.tile_start[tile], bb.bin_cap);
     c.be = min(bb.tile_start[tile + 1], bb.bin_cap);
     c.n_large = n_large;
+    c.lrec = L.lcache;
+    c.n_lrec = n_lcache;
+    c.fu_l = lds_tables ? L.ftab : fu_tab;
+    c.fv_l = lds_tables ? L.ftab + k * g.n_cu : fv_tab;
     if (tid == 0) { next = 0; n_mods = 0; mods_overflow = 0; n_todo = 0; n_failed = 0; }
     __syncthreads();
     for (int32_t q = c.bs + tid; q < c.be; q += 256) {   // module entries of this tile
@@ -1941,6 +1985,210 @@ __device__ __attribute__((always_inline)) void tile_body(TileLds<TS, CAP>& L, in
                          k, out, c, failed[f], lane, wv);
 }
 
+// ---------------------------------------------------------------------------
+// Light tiles, one wave each. A tile with few bin entries (its modules and a
+// few triangles) and a short large list is evaluated by a single wave with no
+// workgroup barrier and no sample list: the wave stages the tile's triangles
+// that can shade a sample in its own LDS slots, then its lanes take the
+// tile's samples straight from each module's row and column ranges and test
+// each against every staged triangle. The samples, the triangles tested and
+// the test itself are those of the workgroup route, so every count is the
+// same; only the order of the work differs.
+// ---------------------------------------------------------------------------
+
+// Inclusive prefix sum over the lanes of a wave.
+__device__ __forceinline__ int32_t wave_incl(int32_t x, int lane) {
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// The number of lanes whose (non-decreasing) incl is at most x, at most 63.
+__device__ __forceinline__ int32_t wave_count_le(int32_t incl, int32_t x) {
+    int32_t lo = 0;
+    for (int step = 32; step >= 1; step >>= 1) {
+        const int32_t v = __shfl(incl, lo + step - 1, 64);
+        if (v <= x) lo += step;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int32_t wave_max(int32_t v) {
+    for (int off = 1; off < 64; off <<= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <int TS>
+__device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const BinBuffers& bb, const TriRec* lrec,
+                          int32_t n_large, int32_t n, const GenDev& g, const int32_t* bias, const double* fu_l,
+                          const double* fv_l, int32_t k, const TileOut& out, const uint32_t* tmask, int lane) {
+    if (!V.valid || !mask_has(tmask, tile)) return;        // no sample can fall in this tile
+    const Rect r{(tile % bb.ntx) * TS, (tile / bb.ntx) * TS, TS};
+    const int32_t bs = min(bb.tile_start[tile], bb.bin_cap), be = min(bb.tile_start[tile + 1], bb.bin_cap);
+    const int32_t ne = be - bs;                            // below 8 kLightBuckets: one entry per lane
+    const int32_t id = lane < ne ? bb.bins[bs + lane] : 0;
+    const bool is_mod = lane < ne && id < 0;
+    const unsigned long long mb = __ballot(is_mod);
+    if (mb == 0ull) return;                                // no module here: nothing to test
+    // an upper bound of the samples' thresholds: the module's farthest corner, floored,
+    // plus two, less its bias (a sample lies inside its module's corners)
+    int32_t bound = INT32_MIN;
+    if (is_mod) {
+        const int32_t m = -id - 1;
+        const int32_t bm = bias[m];
+        if (bm >= 0) {
+            double zmax = -INFINITY;
+            for (int q = 0; q < 4; q++) {
+                d3 p;
+                module_corner(g.mods[m], q, p);
+                zmax = fmax(zmax, to_light(V, p).z);
+            }
+            const double b = floor(zmax) + 2.0 - (double)bm;
+            bound = b >= 2147483647.0 ? INT32_MAX : (b <= -2147483648.0 ? INT32_MIN : (int32_t)b);
+        }
+    }
+    const int32_t mthr = wave_max(bound);
+    if (mthr == INT32_MIN) return;                         // every module here is back-lit
+    // the triangles that reach the tile in front of some sample, in this wave's slots
+    int32_t ns = 0;
+    const int32_t n_cand = n_large + ne;                   // n_large <= kLargeCache: all in LDS
+    for (int32_t c0 = 0; c0 < n_cand; c0 += 64) {
+        const int32_t ci = c0 + lane;
+        const int32_t rid = __shfl(id, (ci - n_large) & 63, 64);   // every lane takes part in the shuffle
+        bool keep = false;
+        TriRec R;
+        TriClip t;
+        if (ci < n_large) {
+            R = lrec[ci];
+            keep = true;
+        } else if (ci < n_cand && rid >= 0) {
+            R = bb.rec[rid];
+            keep = true;
+        }
+        if (keep) {
+            keep = clip_to_rect(R, r, t);
+            if (keep) {
+                const int64_t zmin = R.z0 + R.gx * (R.gx > 0 ? t.ilo : t.ihi) + R.gy * (R.gy > 0 ? t.jlo : t.jhi);
+                keep = (int64_t)depth_q(zmin) < (int64_t)mthr;
+            }
+        }
+        const unsigned long long kb = __ballot(keep);
+        if (keep) {
+            TriSlot& T = slots[ns + lanes_below(kb)];
+            for (int e = 0; e < 3; e++) {
+                T.ex[e] = edge_at(R.e0[e], R.a[e], R.b[e], 256 * r.x, 256 * r.y);
+                T.A[e] = R.a[e];
+                T.B[e] = R.b[e];
+            }
+            T.zx = R.z0 + R.gx * r.x + R.gy * r.y;
+            T.gx = R.gx;
+            T.gy = R.gy;
+            T.box = (uint32_t)(t.ilo - r.x) | ((uint32_t)(t.ihi - r.x) << 8) | ((uint32_t)(t.jlo - r.y) << 16) |
+                    ((uint32_t)(t.jhi - r.y) << 24);
+        }
+        ns += __popcll(kb);
+    }
+    if (ns == 0) return;                                   // nothing can shade a sample here
+    // lane s holds the slots that reach 8 x 8 stamp s of the tile (the stamp's box
+    // against the triangle's box, then each edge at the stamp corner farthest inside)
+    static_assert(TS == 64 && kWaveSlots <= 128, "a lane per stamp, two mask words");
+    unsigned long long sm0 = 0ull, sm1 = 0ull;
+    {
+        const int32_t sx = (lane & 7) * 8, sy = (lane >> 3) * 8;
+        for (int32_t u = 0; u < ns; u++) {
+            const TriSlot& T = slots[u];
+            const uint32_t bx = T.box;
+            const int32_t i0 = max(sx, (int32_t)(bx & 255)), i1 = min(sx + 7, (int32_t)((bx >> 8) & 255));
+            const int32_t j0 = max(sy, (int32_t)((bx >> 16) & 255)), j1 = min(sy + 7, (int32_t)(bx >> 24));
+            bool hit = i0 <= i1 && j0 <= j1;
+            for (int e = 0; e < 3 && hit; e++) {
+                const int64_t emax = edge_at(T.ex[e], T.A[e], T.B[e], 256 * (T.A[e] > 0 ? i1 : i0),
+                                             256 * (T.B[e] > 0 ? j1 : j0));
+                hit = emax >= 0;
+            }
+            if (hit) {
+                if (u < 64) sm0 |= 1ull << u;
+                else sm1 |= 1ull << (u - 64);
+            }
+        }
+    }
+    // the samples of each module, 64 at a time
+    const int32_t cpm = g.n_cu * g.n_cv;
+    const int32_t knu = k * g.n_cu, knv = k * g.n_cv;
+    const int32_t words = (k * k + 31) / 32;
+    double xl, xh, yl, yh;
+    rect_bounds(r, n, xl, xh, yl, yh);
+    unsigned long long todo = mb;
+    while (todo) {
+        const int src = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        const int32_t m = -__shfl(id, src, 64) - 1;
+        const int32_t bm = bias[m];
+        if (bm < 0) continue;                              // back-lit: not tested
+        ModMap mm;
+        module_map(V, g.mods[m], mm);
+        int32_t qb0, qb1;
+        row_range(mm, knv, xl, xh, yl, yh, qb0, qb1);
+        for (int32_t rb = qb0; rb <= qb1; rb += 64) {
+            const int32_t qb_l = rb + lane;
+            int32_t qa0 = 0, cnt = 0;
+            if (qb_l <= qb1) {
+                int32_t qa1;
+                col_range(mm, fv_l[qb_l], knu, xl, xh, yl, yh, qa0, qa1);
+                cnt = qa0 <= qa1 ? qa1 - qa0 + 1 : 0;
+            }
+            const int32_t incl = wave_incl(cnt, lane);
+            const int32_t total = __shfl(incl, 63, 64);
+            for (int32_t c0 = 0; c0 < total; c0 += 64) {
+                const int32_t ci = c0 + lane;
+                const int32_t row = wave_count_le(incl, ci);
+                const int32_t before = __shfl(incl - cnt, row, 64);
+                const int32_t qa = __shfl(qa0, row, 64) + (ci - before);
+                const int32_t qb = rb + row;
+                bool live = false;
+                int32_t li = 0, lj = 0, thr = 0;
+                if (ci < total) {
+                    int32_t zs;
+                    live = sample_in_rect(mm, fu_l[qa], fv_l[qb], r, n, &li, &lj, &zs);
+                    const int64_t th64 = (int64_t)zs - (int64_t)bm;
+                    thr = th64 < (int64_t)INT32_MIN ? INT32_MIN : (int32_t)th64;
+                }
+                // the slots of the sample's stamp (every lane takes part in the shuffles)
+                const int32_t st = (lj >> 3) * 8 + (li >> 3);
+                unsigned long long m0 = __shfl(sm0, st, 64), m1 = __shfl(sm1, st, 64);
+                if (!live) m0 = m1 = 0ull;
+                bool shaded = false;
+                const int32_t li256 = li * 256, lj256 = lj * 256;
+                while ((m0 | m1) != 0ull && !shaded) {
+                    int32_t u;
+                    if (m0) {
+                        u = __ffsll((long long)m0) - 1;
+                        m0 &= m0 - 1;
+                    } else {
+                        u = 64 + __ffsll((long long)m1) - 1;
+                        m1 &= m1 - 1;
+                    }
+                    const TriSlot& T = slots[u];
+                    const int64_t E0 = edge_at(T.ex[0], T.A[0], T.B[0], li256, lj256);
+                    const int64_t E1 = edge_at(T.ex[1], T.A[1], T.B[1], li256, lj256);
+                    const int64_t E2 = edge_at(T.ex[2], T.A[2], T.B[2], li256, lj256);
+                    shaded = (E0 | E1 | E2) >= 0 && thr > (int32_t)depth_q(T.zx + T.gx * li + T.gy * lj);
+                }
+                if (shaded) {
+                    const int32_t cu = qa / k, cv = qb / k, cell = cv * g.n_cu + cu;
+                    atomicAdd(&out.counts[(int64_t)m * cpm + cell], 1u);
+                    if (out.bits) {
+                        const int32_t si = (qb - cv * k) * k + (qa - cu * k);
+                        atomicOr(&out.bits[((int64_t)m * cpm + cell) * words + si / 32], 1u << (si % 32));
+                    }
+                }
+            }
+        }
+    }
+}
+
 // Group form. With work lists (sparse route) the resident grid takes the suns
 // in order, each sun's heaviest items first, so the light items at the end
 // of one sun's list run beside the heavy ones at the start of the next;
@@ -1953,23 +2201,63 @@ __global__ __launch_bounds__(256, 3) void k_tile_g(const SunGroup* __restrict__ 
     __shared__ int32_t take;
     if (!grp->sun[0].bb.tile_list) {
         const GroupSun& S = grp->sun[blockIdx.y];
-        tile_body<TS, CAP>(L, ((int32_t)blockIdx.x << 3) | kWholeTile, views[S.s], S.bb, ctr[S.s].n_large, n, S.g,
+        tile_body<TS, CAP>(L, ((int32_t)blockIdx.x << 3) | kWholeTile, 0, false, views[S.s], S.bb, ctr[S.s].n_large, n, S.g,
                            bias + S.s * S.g.n_mod, fu_tab, fv_tab, k, S.out, S.out.sparse, S.tmask);
         return;
     }
     const int32_t ng = grp->n;
+    // the sample fractions are the same for every sun of the evaluation
+    const int32_t knu = k * grp->sun[0].g.n_cu, knv = k * grp->sun[0].g.n_cv;
+    const bool lds_tables = knu + knv <= kFracCache;
+    if (lds_tables)
+        for (int32_t u = threadIdx.x; u < knu + knv; u += 256) L.ftab[u] = u < knu ? fu_tab[u] : fv_tab[u - knu];
     for (int32_t q = 0; q < ng; q++) {
         const GroupSun& S = grp->sun[q];
         const int32_t n_items = S.bb.list_ctr[0];
+        const int32_t n_large = ctr[S.s].n_large;
+        const int32_t n_lc = min(n_large, kLargeCache);
+        __syncthreads();                              // the previous sun's tiles are done with the cache
+        static_assert(sizeof(TriRec) % 16 == 0, "records copy in 16-byte pieces");
+        constexpr int kPieces = sizeof(TriRec) / 16;
+        for (int32_t u = threadIdx.x; u < n_lc * kPieces; u += 256)
+            reinterpret_cast<uint4*>(L.lcache)[u] =
+                reinterpret_cast<const uint4*>(S.bb.rec + S.bb.large[u / kPieces])[u % kPieces];
+        __syncthreads();
+        // light tiles (the list's tail) go one wave each when their large list is in LDS
+        const int32_t light = (TS == 64 && n_large <= kLargeCache) ? S.bb.list_ctr[2] : n_items;
         for (;;) {
             if (threadIdx.x == 0) take = atomicAdd(&S.bb.list_ctr[1], 1);
             __syncthreads();
             const int32_t it = take;
             __syncthreads();
             if (it >= n_items) break;
-            tile_body<TS, CAP>(L, S.bb.tile_list[it], views[S.s], S.bb, ctr[S.s].n_large, n, S.g,
-                               bias + S.s * S.g.n_mod, fu_tab, fv_tab, k, S.out, S.out.sparse, S.tmask);
-            __syncthreads();
+            if (it < light) {
+                tile_body<TS, CAP>(L, S.bb.tile_list[it], n_lc, lds_tables, views[S.s], S.bb, n_large, n, S.g,
+                                   bias + S.s * S.g.n_mod, fu_tab, fv_tab, k, S.out, S.out.sparse, S.tmask);
+                __syncthreads();
+                continue;
+            }
+            // from here on every wave takes its own light tiles; wave 0 starts with `it`
+            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+            TriSlot* slots = reinterpret_cast<TriSlot*>(L.pool) + wv * kWaveSlots;
+            const double* fu_l = lds_tables ? L.ftab : fu_tab;
+            const double* fv_l = lds_tables ? L.ftab + knu : fv_tab;
+            int32_t my = it;
+            if (wv != 0) {
+                int32_t got = 0;
+                if (lane == 0) got = atomicAdd(&S.bb.list_ctr[1], 1);
+                my = __builtin_amdgcn_readfirstlane(got);
+            }
+            if constexpr (TS == 64) {
+                while (my < n_items) {
+                    wave_tile<TS>(slots, S.bb.tile_list[my] >> 3, views[S.s], S.bb, L.lcache, n_large, n, S.g,
+                                  bias + S.s * S.g.n_mod, fu_l, fv_l, k, S.out, S.tmask, lane);
+                    int32_t got = 0;
+                    if (lane == 0) got = atomicAdd(&S.bb.list_ctr[1], 1);
+                    my = __builtin_amdgcn_readfirstlane(got);
+                }
+            }
+            break;
         }
     }
 }
@@ -2606,10 +2894,10 @@ __device__ __noinline__ void unit_tile(unsigned char* raw, const PJob& J, const 
     out.sparse = J.sparse;
     const uint32_t* tmask = J.use_mask ? B.tmask : nullptr;
     if (J.tile == 64)
-        tile_body<64, kCap64>(*reinterpret_cast<TileLds<64, kCap64>*>(raw), item, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, gs,
+        tile_body<64, kCap64>(*reinterpret_cast<TileLds<64, kCap64>*>(raw), item, 0, false, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, gs,
                             B.bias, J.fu, J.fv, J.k, out, J.sparse, tmask);
     else
-        tile_body<32, kCap32>(*reinterpret_cast<TileLds<32, kCap32>*>(raw), item, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, gs,
+        tile_body<32, kCap32>(*reinterpret_cast<TileLds<32, kCap32>*>(raw), item, 0, false, *B.view, bb, ld_dev(&B.ctr->n_large), J.n, gs,
                             B.bias, J.fu, J.fv, J.k, out, J.sparse, tmask);
 }
 

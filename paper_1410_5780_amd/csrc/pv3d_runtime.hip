@@ -315,7 +315,7 @@ PathSizes path_sizes(const Scene& sc, const Gen& g, const pv3d_params& p, int64_
 // list, pair items and chunks, module boxes).
 size_t lane_bytes_per_sun(const PathSizes& z, const Gen& g) {
     return sizeof(TriRec) * (size_t)z.rec_cap + 4 * (size_t)z.rec_cap + 4 * (size_t)z.bin_cap +
-           4 * (size_t)(3 * (int64_t)z.n_tiles + 1) + 4 * (4 * (size_t)z.n_tiles + 2) +
+           4 * (size_t)(3 * (int64_t)z.n_tiles + 1) + 4 * (4 * (size_t)z.n_tiles + 4) +
            sizeof(PairItem) * (size_t)z.item_cap + 4 * (size_t)z.chunk_cap + 16 * (size_t)g.n_mod + 6 * 256;
 }
 
@@ -346,7 +346,7 @@ pv3d_status Ctx::ensure_lane(Lane& L, const PathSizes& z, const Gen& g, int32_t 
     if ((st = L.tile_count.ensure(this, G * 4 * (size_t)z.n_tiles, "tile counts"))) return st;
     if ((st = L.tile_start.ensure(this, G * 4 * (size_t)(z.n_tiles + 1), "tile starts"))) return st;
     if ((st = L.tile_cursor.ensure(this, G * 4 * (size_t)z.n_tiles, "tile cursors"))) return st;
-    if ((st = L.tile_list.ensure(this, G * 4 * (4 * (size_t)z.n_tiles + 2), "tile work list"))) return st;
+    if ((st = L.tile_list.ensure(this, G * 4 * (4 * (size_t)z.n_tiles + 4), "tile work list"))) return st;
     if ((st = L.pitems.ensure(this, G * sizeof(PairItem) * (size_t)z.item_cap, "pair items"))) return st;
     if ((st = L.pchunk.ensure(this, G * 4 * (size_t)z.chunk_cap, "pair chunks"))) return st;
     if ((st = L.modbox.ensure(this, G * 16 * (size_t)g.n_mod, "module tile boxes"))) return st;
@@ -559,9 +559,9 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
         GroupSun& S = grp.sun[q];
         S.bb = bin_buffers(z, lane, q);
         if (sparse) {      // the scan lists the tiles with work, heaviest first; 64-texel ones split in quadrants
-            int32_t* tl = static_cast<int32_t*>(w.lane[lane].tile_list.ptr) + (size_t)q * (4 * (size_t)z.n_tiles + 2);
+            int32_t* tl = static_cast<int32_t*>(w.lane[lane].tile_list.ptr) + (size_t)q * (4 * (size_t)z.n_tiles + 4);
             S.bb.list_ctr = tl;
-            S.bb.tile_list = tl + 2;
+            S.bb.tile_list = tl + 4;          // list_ctr: items, next item, first light item
             S.bb.split_at = z.tile == 64 ? kSplitEntries : 0;
         }
         S.bb.pctr = &ctr[s].pairs;
