@@ -810,30 +810,29 @@ constexpr int kScanKeep = 8;
 
 // slot[key] += w for every lane with ok, the lanes of a wave that share a key
 // with one atomic between them; each such lane gets the slot's value before
-// its own share (lanes of one key in lane order). Every lane of the wave
-// calls it.
+// its own share (lanes of one key in lane order). key < 2^BITS, w is 1 or 4.
+// The lanes that share a key are found one key bit at a time (a ballot per
+// bit), so the cost does not grow with the number of distinct keys in the
+// wave; the first lane of every key then adds for its group, all groups in
+// one atomic instruction on distinct slots. Every lane of the wave calls it.
+template <int BITS>
 __device__ __forceinline__ int32_t wave_add(int32_t* slot, bool ok, int32_t key, int32_t w) {
-    const int lane = threadIdx.x & 63;
-    unsigned long long todo = __ballot(ok);
-    int32_t res = 0;
-    while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int32_t k = __shfl(key, leader, 64);
-        const bool mine = ok && key == k;
-        const int32_t x = mine ? w : 0;
-        int32_t incl = x;
-        for (int off = 1; off < 64; off <<= 1) {
-            const int32_t y = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += y;
-        }
-        const int32_t total = __shfl(incl, 63, 64);
-        int32_t base = 0;
-        if (lane == leader) base = atomicAdd(&slot[k], total);
-        base = __shfl(base, leader, 64);
-        if (mine) res = base + incl - x;
-        todo &= ~__ballot(mine);
+    unsigned long long peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < BITS; b++) {
+        const unsigned long long set = __ballot((key >> b) & 1);
+        peers &= ((key >> b) & 1) ? set : ~set;
     }
-    return res;
+    const unsigned long long four = peers & __ballot(w != 1);
+    const unsigned long long one = peers & ~four;
+    const int32_t before = lanes_below(one) + 4 * lanes_below(four);
+    const int32_t total = __popcll(one) + 4 * __popcll(four);
+    const int leader = peers ? __ffsll((long long)peers) - 1 : 0;
+    const int lane = threadIdx.x & 63;
+    int32_t base = 0;
+    if (ok && lane == leader) base = atomicAdd(&slot[key], total);
+    base = __shfl(base, leader, 64);
+    return ok ? base + before : 0;
 }
 
 template <int KEEP>
@@ -847,6 +846,7 @@ __device__ __forceinline__ int32_t kept_at(const int32_t (&kept)[KEEP], int32_t 
 template <int NT, bool COHERENT, int KEEP = kScanKeep>
 __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& bb, int32_t* list, int32_t split_at) {
     static_assert(NT >= kScanBuckets && NT % 64 == 0, "a thread per bucket");
+    static_assert(kScanBuckets == 256, "bucket keys take eight bits");
     const int tid = threadIdx.x;
     unsigned long long* wsum = reinterpret_cast<unsigned long long*>(part + 2);
     const int32_t per = (n_tiles + NT - 1) / NT;
@@ -904,7 +904,7 @@ __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& b
         const int32_t i = b0 + j;
         const int32_t c = i < b1 ? (keep ? kept_at<KEEP>(kept, j) : bb.tile_start[i + 1] - bb.tile_start[i]) : 0;
         const int32_t bk = kScanBuckets - 1 - min(c >> 3, kScanBuckets - 1);
-        (void)wave_add(hist, c > 0, bk, (split_at > 0 && c > split_at) ? 4 : 1);
+        (void)wave_add<8>(hist, c > 0, bk, (split_at > 0 && c > split_at) ? 4 : 1);
     }
     __syncthreads();
     const unsigned long long own = tid < kScanBuckets ? (unsigned long long)hist[tid] : 0ull;
@@ -919,7 +919,7 @@ __device__ int32_t scan_body(int32_t* part, int32_t n_tiles, const BinBuffers& b
         const int32_t c = i < b1 ? (keep ? kept_at<KEEP>(kept, j) : bb.tile_start[i + 1] - bb.tile_start[i]) : 0;
         const int32_t bk = kScanBuckets - 1 - min(c >> 3, kScanBuckets - 1);
         const bool split = split_at > 0 && c > split_at;
-        const int32_t pos = wave_add(cur, c > 0, bk, split ? 4 : 1);
+        const int32_t pos = wave_add<8>(cur, c > 0, bk, split ? 4 : 1);
         if (c > 0) {
             if (split)
                 for (int32_t q = 0; q < 4; q++) list[pos + q] = (i << 3) | q;
@@ -3411,8 +3411,10 @@ hipError_t launch_bin_scan_group(const SunGroup* grp, int32_t n_sun, int32_t n_t
     if (n_sun <= 0) return hipSuccess;
     if (n_tiles <= 512 * 8)
         hipLaunchKernelGGL((k_bin_scan_g<512, 8>), dim3((unsigned)n_sun), dim3(512), 0, st, grp, n_tiles);
+    else if (n_tiles <= 512 * 32)
+        hipLaunchKernelGGL((k_bin_scan_g<512, 32>), dim3((unsigned)n_sun), dim3(512), 0, st, grp, n_tiles);
     else
-        hipLaunchKernelGGL((k_bin_scan_g<1024, 16>), dim3((unsigned)n_sun), dim3(1024), 0, st, grp, n_tiles);
+        hipLaunchKernelGGL((k_bin_scan_g<512, 8>), dim3((unsigned)n_sun), dim3(512), 0, st, grp, n_tiles);
     return hipGetLastError();
 }
 
