@@ -178,6 +178,9 @@ struct Ctx {
     // burst of requests served after the per-sun path in one context waited minutes)
     bool per_sun_ran = false;
     DevInfo dev_info;
+    // the stream waits for the end of the context's previous evaluation, whose kernels
+    // may still read the work buffers on another stream
+    pv3d_status wait_previous(hipStream_t st);
     // pv3d_batch_limits: slots of the batched form and the serving loop
     int32_t batch_max_slots = 128;
     int64_t batch_slot_records = 1 << 20;

@@ -99,6 +99,12 @@ void Buf::release(Ctx* c) {
     cap = 0;
 }
 
+pv3d_status Ctx::wait_previous(hipStream_t st) {
+    if (!ws_recorded) return PV3D_OK;
+    hipError_t e = hipStreamWaitEvent(st, ws_ev, 0);
+    return e == hipSuccess ? PV3D_OK : hip_fail(e, "wait for the previous evaluation");
+}
+
 pv3d_status Ctx::stage(const void* host, size_t bytes, void* dev, hipStream_t st) {
     // pinned staging so the caller's host arrays can be reused once we return
     if (staging_busy) {
@@ -1248,6 +1254,8 @@ pv3d_status pv3d_evaluate(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const dou
     if ((st = ctx->ensure_path(z, g, p.map_n, !want_maps && (p.flags & PV3D_SEPARATE_TEST)))) return st;
     double* d_sweep = static_cast<double*>(ctx->w.sweep.ptr);
     double *d_sun = d_sweep, *d_dni = d_sweep + 3 * n_sun, *d_dpoa = d_dni + n_sun, *d_dt = d_dpoa + n_sun;
+    // the previous evaluation (perhaps on another stream) may still read the sweep buffer
+    if ((st = ctx->wait_previous(s))) return st;
     if (n_sun > 0) {
         if ((st = ctx->stage_reserve(8 * 6 * (size_t)n_sun + 4 * 256))) return st;
         if ((st = ctx->stage(sun_xyz, 24 * (size_t)n_sun, d_sun, s))) return st;
