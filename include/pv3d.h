@@ -229,6 +229,31 @@ pv3d_status pv3d_evaluate(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const dou
                           int64_t n_sun, const pv3d_params* params, pv3d_outputs* out,
                           void* hip_stream);
 
+/* pv3d_evaluate for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same evaluation with identical results, in work memory taken from a static
+ * device array of 128 MiB (PV3D_NOALLOC_SCRATCH_BYTES) that the library holds
+ * on every GPU it runs on until the process ends. The call itself allocates
+ * nothing: no hipMalloc, hipFree, pinned host memory or events (stage timing
+ * is off during the call). Scene and generator are loaded beforehand as
+ * usual; the caller passes the inputs (host memory, copied before the call
+ * returns) and the outputs, which must be device memory (out->on_device = 1;
+ * EINVAL otherwise). The call is asynchronous on hip_stream (NULL: the
+ * context stream) like pv3d_evaluate's device form.
+ * The work memory grows with the scene's triangles times bin_limit and with
+ * n_sun: an evaluation that does not fit even one sun at a time returns
+ * ERANGE before anything is queued (a smaller bin_limit, which leaves the
+ * results unchanged, or fewer suns per call fit more). Every call on one GPU,
+ * from any context, shares the array and finds the last call's contents; the
+ * library clears what must start at zero. Calls of one context are ordered
+ * (each waits for the previous evaluation's kernels); calls from different
+ * contexts on one GPU that overlap in time race on the array. */
+#define PV3D_NOALLOC_SCRATCH_BYTES (128ull << 20)
+pv3d_status pv3d_evaluate_noalloc(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const double* sun_xyz,
+                                  const double* dni, const double* d_poa, const double* dt_h,
+                                  int64_t n_sun, const pv3d_params* params, pv3d_outputs* out,
+                                  void* hip_stream);
+
 /* Diffuse shading (Sec. 4: obstacles also hide part of the diffuse sky, which
  * the paper's evaluation leaves out). An isotropic sky is seen through n_dir
  * fixed directions above the horizon, each standing for an equal share of it

@@ -142,6 +142,14 @@ struct Profiler {
 
 PathSizes path_sizes(const Scene& sc, const Gen& g, const pv3d_params& p, int64_t n_sun);
 size_t lane_bytes_per_sun(const PathSizes& z, const Gen& g);
+// Device memory of pv3d_evaluate_noalloc: one static array per GPU, whose address
+// pv3d_create looks up once per device.
+constexpr size_t kScratchBytes = PV3D_NOALLOC_SCRATCH_BYTES;
+// Bytes an evaluation takes from that array: the per-sun arrays and tables, the
+// counts when the caller passes none, n_groups group descriptors and n_lanes lanes
+// of room for `group` suns, every buffer 256-byte aligned.
+size_t carve_bytes(const PathSizes& z, const Gen& g, int32_t k, int32_t map_n, bool own_map, bool own_counts,
+                   int32_t group, int n_lanes, int64_t n_groups);
 void host_sphere(const Scene& sc, const Gen& g, double sphere[4]);
 void host_sample_tables(int32_t k, int32_t n_cu, int32_t n_cv, double* fu, double* fv);
 int32_t choose_tile(const pv3d_params& p);
@@ -178,6 +186,13 @@ struct Ctx {
     // burst of requests served after the per-sun path in one context waited minutes)
     bool per_sun_ran = false;
     DevInfo dev_info;
+    // pv3d_evaluate_noalloc: while `carving`, every work buffer the evaluation ensures
+    // is taken from the device's static scratch array (carve_base, kScratchBytes bytes)
+    // by bumping carve_used; nothing is allocated and nothing is freed
+    void* scratch = nullptr;
+    bool carving = false;
+    size_t carve_used = 0;
+    pv3d_status carve(Buf& b, size_t bytes, const char* what);
     // the stream waits for the end of the context's previous evaluation, whose kernels
     // may still read the work buffers on another stream
     pv3d_status wait_previous(hipStream_t st);

@@ -74,6 +74,7 @@ void Ctx::dfree(void* p) {
 
 pv3d_status Buf::ensure(Ctx* c, size_t bytes, const char* what) {
     if (bytes <= cap && ptr) return PV3D_OK;
+    if (c->carving) return c->carve(*this, bytes, what);
     if (ptr) {
         HoldServing hold(c);
         hipError_t e = hipDeviceSynchronize();
@@ -97,6 +98,19 @@ void Buf::release(Ctx* c) {
     if (ptr) c->dfree(ptr);
     ptr = nullptr;
     cap = 0;
+}
+
+static size_t align256(size_t b) { return (std::max<size_t>(b, 1) + 255) & ~(size_t)255; }
+
+pv3d_status Ctx::carve(Buf& b, size_t bytes, const char* what) {
+    const size_t want = align256(bytes);
+    if (!scratch || carve_used + want > kScratchBytes)
+        return fail(PV3D_ERANGE, "%s: %zu bytes do not fit the static scratch (%zu of %zu bytes taken)", what, want,
+                    carve_used, kScratchBytes);
+    b.ptr = static_cast<char*>(scratch) + carve_used;
+    b.cap = want;
+    carve_used += want;
+    return PV3D_OK;
 }
 
 pv3d_status Ctx::wait_previous(hipStream_t st) {
@@ -325,39 +339,90 @@ size_t lane_bytes_per_sun(const PathSizes& z, const Gen& g) {
            sizeof(PairItem) * (size_t)z.item_cap + 4 * (size_t)z.chunk_cap + 16 * (size_t)g.n_mod + 6 * 256;
 }
 
+// The per-sun arrays of an evaluation (views, counters, beam, bias, sweep, sphere,
+// tile masks, bounds partials), in bytes.
+constexpr int kPathBufs = 8;
+static void path_buf_sizes(const PathSizes& z, const Gen& g, size_t b[kPathBufs]) {
+    const size_t S = (size_t)std::max<int64_t>(z.n_sun, 1);
+    b[0] = sizeof(View) * S;
+    b[1] = sizeof(SunCounters) * S;
+    b[2] = 8 * (size_t)std::max<int64_t>(z.n_sun * g.n_mod, 1);
+    b[3] = 4 * (size_t)std::max<int64_t>(z.n_sun * g.n_mod, 1);
+    b[4] = 8 * 6 * S;
+    b[5] = 64;
+    b[6] = 4 * (size_t)z.mask_words * S;
+    b[7] = 8 * 6 * 1024;
+}
+
+// The buffers of a lane with room for `group` suns, one sun's part after the other, in bytes.
+constexpr int kLaneBufs = 11;
+static void lane_buf_sizes(const PathSizes& z, const Gen& g, int32_t map_n, bool own_map, int32_t group,
+                           size_t b[kLaneBufs]) {
+    const size_t G = (size_t)std::max(group, 1);
+    b[0] = G * sizeof(TriRec) * (size_t)z.rec_cap;
+    b[1] = G * 4 * (size_t)z.rec_cap;
+    b[2] = G * 4 * (size_t)z.bin_cap;
+    b[3] = G * 4 * (size_t)z.n_tiles;
+    b[4] = G * 4 * (size_t)(z.n_tiles + 1);
+    b[5] = G * 4 * (size_t)z.n_tiles;
+    b[6] = G * 4 * (4 * (size_t)z.n_tiles + 4);
+    b[7] = G * sizeof(PairItem) * (size_t)z.item_cap;
+    b[8] = G * 4 * (size_t)z.chunk_cap;
+    b[9] = G * 16 * (size_t)g.n_mod;
+    b[10] = own_map ? 4 * (size_t)map_n * map_n : 0;
+}
+
+// Bytes of the static scratch one lane with room for `group` suns takes.
+static size_t lane_carve_bytes(const PathSizes& z, const Gen& g, int32_t map_n, bool own_map, int32_t group) {
+    size_t lb[kLaneBufs], lane = 0;
+    lane_buf_sizes(z, g, map_n, own_map, group, lb);
+    for (int i = 0; i < kLaneBufs; i++)
+        if (i < kLaneBufs - 1 || own_map) lane += align256(lb[i]);
+    return lane;
+}
+
+size_t carve_bytes(const PathSizes& z, const Gen& g, int32_t k, int32_t map_n, bool own_map, bool own_counts,
+                   int32_t group, int n_lanes, int64_t n_groups) {
+    size_t pb[kPathBufs], total = 0;
+    path_buf_sizes(z, g, pb);
+    for (size_t x : pb) total += align256(x);
+    const size_t n_tab = (size_t)k * std::max(g.n_cu, g.n_cv);
+    total += 2 * align256(8 * n_tab);                                  // sample tables
+    if (g.n_trk > 0) total += align256(sizeof(Module) * (size_t)std::max<int64_t>(z.n_sun * g.n_mod, 1));
+    if (own_counts) total += align256(4 * (size_t)std::max<int64_t>(z.n_sun * z.cells, 1));
+    total += align256(sizeof(SunGroup) * (size_t)std::max<int64_t>(n_groups, 1));
+    return total + (size_t)n_lanes * lane_carve_bytes(z, g, map_n, own_map, group);
+}
+
 pv3d_status Ctx::ensure_path(const PathSizes& z, const Gen& g, int32_t map_n, bool own_map) {
     pv3d_status st;
     if (z.rec_cap > INT32_MAX || z.bin_cap > INT32_MAX)
         return fail(PV3D_ERANGE, "scene too large for 32-bit bin indices");
-    if ((st = ensure_lane(w.lane[0], z, g, map_n, own_map, 1))) return st;
-    if ((st = w.views.ensure(this, sizeof(View) * (size_t)std::max<int64_t>(z.n_sun, 1), "views"))) return st;
-    if ((st = w.ctr.ensure(this, sizeof(SunCounters) * (size_t)std::max<int64_t>(z.n_sun, 1), "counters"))) return st;
-    if ((st = w.beam.ensure(this, 8 * (size_t)std::max<int64_t>(z.n_sun * g.n_mod, 1), "module beam"))) return st;
-    if ((st = w.bias.ensure(this, 4 * (size_t)std::max<int64_t>(z.n_sun * g.n_mod, 1), "module bias"))) return st;
-    if ((st = w.sweep.ensure(this, 8 * 6 * (size_t)std::max<int64_t>(z.n_sun, 1), "sweep"))) return st;
-    if ((st = w.sphere.ensure(this, 64, "bounding sphere"))) return st;
-    if ((st = w.tmask.ensure(this, 4 * (size_t)z.mask_words * (size_t)std::max<int64_t>(z.n_sun, 1), "tile masks")))
-        return st;
-    if ((st = w.partial.ensure(this, 8 * 6 * 1024, "bounds partials"))) return st;
+    // (from the static scratch the lanes are taken once their group size is known)
+    if (!carving && (st = ensure_lane(w.lane[0], z, g, map_n, own_map, 1))) return st;
+    size_t b[kPathBufs];
+    path_buf_sizes(z, g, b);
+    Buf* bufs[kPathBufs] = {&w.views, &w.ctr, &w.beam, &w.bias, &w.sweep, &w.sphere, &w.tmask, &w.partial};
+    static const char* const names[kPathBufs] = {"views", "counters", "module beam", "module bias", "sweep",
+                                                 "bounding sphere", "tile masks", "bounds partials"};
+    for (int i = 0; i < kPathBufs; i++)
+        if ((st = bufs[i]->ensure(this, b[i], names[i]))) return st;
     return PV3D_OK;
 }
 
 // Room for `group` suns in each buffer of the lane, one sun's part after the other.
 pv3d_status Ctx::ensure_lane(Lane& L, const PathSizes& z, const Gen& g, int32_t map_n, bool own_map, int32_t group) {
     pv3d_status st;
-    const size_t G = (size_t)std::max(group, 1);
-    if ((st = L.rec.ensure(this, G * sizeof(TriRec) * (size_t)z.rec_cap, "triangle records"))) return st;
-    if ((st = L.large.ensure(this, G * 4 * (size_t)z.rec_cap, "large-triangle list"))) return st;
-    if ((st = L.bins.ensure(this, G * 4 * (size_t)z.bin_cap, "tile bins"))) return st;
-    if ((st = L.tile_count.ensure(this, G * 4 * (size_t)z.n_tiles, "tile counts"))) return st;
-    if ((st = L.tile_start.ensure(this, G * 4 * (size_t)(z.n_tiles + 1), "tile starts"))) return st;
-    if ((st = L.tile_cursor.ensure(this, G * 4 * (size_t)z.n_tiles, "tile cursors"))) return st;
-    if ((st = L.tile_list.ensure(this, G * 4 * (4 * (size_t)z.n_tiles + 4), "tile work list"))) return st;
-    if ((st = L.pitems.ensure(this, G * sizeof(PairItem) * (size_t)z.item_cap, "pair items"))) return st;
-    if ((st = L.pchunk.ensure(this, G * 4 * (size_t)z.chunk_cap, "pair chunks"))) return st;
-    if ((st = L.modbox.ensure(this, G * 16 * (size_t)g.n_mod, "module tile boxes"))) return st;
-    if (own_map && (st = L.map.ensure(this, 4 * (size_t)map_n * map_n, "depth picture"))) return st;
-    L.group = std::max(L.group, (int32_t)G);
+    size_t b[kLaneBufs];
+    lane_buf_sizes(z, g, map_n, own_map, group, b);
+    Buf* bufs[kLaneBufs] = {&L.rec, &L.large, &L.bins, &L.tile_count, &L.tile_start, &L.tile_cursor,
+                            &L.tile_list, &L.pitems, &L.pchunk, &L.modbox, &L.map};
+    static const char* const names[kLaneBufs] = {"triangle records", "large-triangle list", "tile bins",
+                                                 "tile counts", "tile starts", "tile cursors", "tile work list",
+                                                 "pair items", "pair chunks", "module tile boxes", "depth picture"};
+    for (int i = 0; i < kLaneBufs; i++)
+        if ((i < kLaneBufs - 1 || own_map) && (st = bufs[i]->ensure(this, b[i], names[i]))) return st;
+    L.group = std::max(L.group, std::max(group, 1));
     return PV3D_OK;
 }
 
@@ -493,7 +558,23 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
         if (sun_host[3 * s + 2] > 0.0) n_up++;
     int32_t G = own_map ? 1 : kMaxGroup;                 // the materialised route keeps one picture per lane
     G = (int32_t)std::max<int64_t>(1, std::min<int64_t>(G, (n_up + kLanes - 1) / kLanes));
-    {
+    if (carving) {
+        // from the static scratch: the largest group whose lanes fit beside what is taken;
+        // the descriptors and tracker poses first, so that a lane left out cannot starve them
+        const size_t poses = g.n_trk > 0 ? align256(sizeof(Module) * (size_t)std::max<int64_t>(n_sun * g.n_mod, 1)) : 0;
+        auto need = [&](int32_t Gc) {
+            const int64_t n_groups = std::max<int64_t>((n_up + Gc - 1) / Gc, 1);
+            return carve_used + align256(sizeof(SunGroup) * (size_t)n_groups) + poses +
+                   (size_t)kLanes * lane_carve_bytes(z, g, p.map_n, own_map, Gc);
+        };
+        while (G > 1 && need(G) > kScratchBytes) G /= 2;
+        if ((rs = w.groups.ensure(this, sizeof(SunGroup) * (size_t)std::max<int64_t>((n_up + G - 1) / G, 1),
+                                  "group descriptors")))
+            return rs;
+        if (g.n_trk > 0 &&
+            (rs = w.posed.ensure(this, sizeof(Module) * (size_t)std::max<int64_t>(n_sun * g.n_mod, 1), "posed modules")))
+            return rs;
+    } else {
         const size_t per_sun = lane_bytes_per_sun(z, g);
         const uint64_t room = budget > used ? budget - used : 0;
         // what the lanes hold already counts as room
@@ -510,7 +591,14 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
     }
     int n_lanes = 1;
     while (n_lanes < kLanes && (int64_t)n_lanes * G < n_up && lane_st[n_lanes]) {
-        if (ensure_lane(w.lane[n_lanes], z, g, p.map_n, own_map, G) != PV3D_OK) break;
+        const size_t taken = carve_used;
+        if (ensure_lane(w.lane[n_lanes], z, g, p.map_n, own_map, G) != PV3D_OK) {
+            if (carving) {                // give back what the lane took of the static scratch
+                carve_used = taken;
+                w.lane[n_lanes] = Lane{};
+            }
+            break;
+        }
         n_lanes++;
     }
     // tile counts start at zero; the scan of every sun leaves them at zero again
@@ -610,6 +698,11 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
 pv3d_status Ctx::upload_groups(const std::vector<SunGroup>& groups, hipStream_t st) {
     const size_t bytes = sizeof(SunGroup) * groups.size();
     hipError_t e;
+    if (carving) {   // no pinned staging to grow: a copy from pageable memory, staged before it returns
+        if ((e = hipMemcpyAsync(w.groups.ptr, groups.data(), bytes, hipMemcpyHostToDevice, st)))
+            return hip_fail(e, "copy descriptors");
+        return PV3D_OK;
+    }
     if (gstage_busy) {
         if ((e = hipEventSynchronize(gstage_done))) return hip_fail(e, "wait for the descriptor staging");
         gstage_busy = false;
@@ -693,6 +786,28 @@ pv3d_status Ctx::read_overflow(int64_t n_sun, hipStream_t st, bool* overflow) {
     return PV3D_OK;
 }
 
+// The work buffers of pv3d_evaluate_noalloc. Host code never passes `scratch`
+// itself to the device (in host code the name stands for a host-side shadow):
+// it uses the address hipGetSymbolAddress gives for each device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_at;   // device -> address of its copy of scratch
+
+// Address of the current device's copy of the static scratch, looked up once per device.
+static pv3d_status scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_at.find(device);
+    if (it == g_scratch_at.end()) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "address of the static scratch");
+        if (!ptr) return fail(PV3D_EDEVICE, "the static scratch has no device address");
+        it = g_scratch_at.emplace(device, ptr).first;
+    }
+    *out = it->second;
+    return PV3D_OK;
+}
+
 }  // namespace pv3d
 
 // ===========================================================================
@@ -731,6 +846,10 @@ pv3d_status pv3d_create(int32_t device, uint64_t hbm_budget_bytes, pv3d_ctx** ou
     if ((e = hipEventCreateWithFlags(&c->gstage_done, hipEventDisableTiming)) != hipSuccess)
         return hip_fail(e, "hipEventCreate");
     if ((e = hipEventCreate(&c->prof.ref)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    {
+        pv3d_status st = scratch_address(device, &c->scratch);   // device is current
+        if (st != PV3D_OK) return st;
+    }
     {
         hipDeviceProp_t prop;
         if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
@@ -1288,6 +1407,92 @@ pv3d_status pv3d_evaluate(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const dou
     } else {
         if ((e = hipGetLastError())) return hip_fail(e, "launch");
     }
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_evaluate_noalloc(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const double* sun_xyz,
+                                  const double* dni, const double* d_poa, const double* dt_h, int64_t n_sun,
+                                  const pv3d_params* params, pv3d_outputs* out, void* hip_stream) {
+    if (!ctx || !out) return fail(PV3D_EINVAL, "null argument");
+    pv3d_status st;
+    if ((st = check_params(params))) return st;
+    if ((st = check_sweep(sun_xyz, dni, d_poa, dt_h, n_sun))) return st;
+    if (!out->on_device) return fail(PV3D_EINVAL, "the no-allocation form writes device outputs only (on_device = 1)");
+    if (!out->power || !out->power_ref || !out->energy) return fail(PV3D_EINVAL, "power, power_ref and energy are required");
+    if ((params->flags & PV3D_EXPORT_DEPTH) && !out->depth_maps) return fail(PV3D_EINVAL, "EXPORT_DEPTH needs depth_maps");
+    if ((params->flags & PV3D_EXPORT_BITS) && !out->shaded_bits) return fail(PV3D_EINVAL, "EXPORT_BITS needs shaded_bits");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto si = ctx->scenes.find(scene);
+    if (si == ctx->scenes.end()) return fail(PV3D_ENOENT, "unknown scene %llu", (unsigned long long)scene);
+    auto gi = ctx->gens.find(gen);
+    if (gi == ctx->gens.end()) return fail(PV3D_ENOENT, "unknown generator %llu", (unsigned long long)gen);
+    const Scene& sc = si->second;
+    const Gen& g = gi->second;
+    const pv3d_params& p = *params;
+    if ((int64_t)p.k * g.n_cu > 4095 || (int64_t)p.k * g.n_cv > 4095)
+        return fail(PV3D_ERANGE, "k * cells per module side exceeds 4095 samples");
+    const bool want_maps = (p.flags & PV3D_EXPORT_DEPTH) != 0, want_bits = (p.flags & PV3D_EXPORT_BITS) != 0;
+    const bool own_map = !want_maps && (p.flags & PV3D_SEPARATE_TEST);
+    const bool own_counts = out->cell_counts == nullptr;
+    PathSizes z = path_sizes(sc, g, p, n_sun);
+    if (z.rec_cap > INT32_MAX || z.bin_cap > INT32_MAX) return fail(PV3D_ERANGE, "scene too large for 32-bit bin indices");
+    int64_t n_up = 0;
+    for (int64_t i = 0; i < n_sun; i++)
+        if (sun_xyz[3 * i + 2] > 0.0) n_up++;
+    // the smallest layout: one lane with room for one sun
+    const size_t least = carve_bytes(z, g, p.k, p.map_n, own_map, own_counts, 1, 1, n_up);
+    if (least > kScratchBytes)
+        return fail(PV3D_ERANGE,
+                    "the evaluation needs %zu bytes of work memory and the static scratch holds %zu "
+                    "(a smaller bin_limit, fewer triangles or fewer suns per call need less)",
+                    least, kScratchBytes);
+    (void)hipSetDevice(ctx->device);
+    if (!ctx->scratch) return fail(PV3D_EDEVICE, "no static scratch on device %d", ctx->device);
+    hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->stream;
+    ctx->stream_in_use = s;
+    ctx->per_sun_ran = true;
+    // the evaluation works in buffers carved from the scratch; the context's own
+    // work buffers are set aside and come back untouched. No timing: its events
+    // would be created here.
+    struct Carved {
+        Ctx* c;
+        Work saved;
+        uint32_t mask;
+        explicit Carved(Ctx* ctx) : c(ctx), saved(ctx->w), mask(ctx->prof.mask) {
+            c->w = Work{};
+            c->prof.mask = 0;
+            c->carving = true;
+            c->carve_used = 0;
+        }
+        ~Carved() {
+            c->carving = false;
+            c->w = saved;
+            c->prof.mask = mask;
+        }
+    } carved(ctx);
+    hipError_t e;
+    uint32_t* d_counts = out->cell_counts;
+    if (own_counts) {
+        if ((st = ctx->w.counts.ensure(ctx, 4 * (size_t)std::max<int64_t>(n_sun * z.cells, 1), "counts"))) return st;
+        d_counts = static_cast<uint32_t*>(ctx->w.counts.ptr);
+    }
+    if ((st = ctx->ensure_path(z, g, p.map_n, own_map))) return st;
+    double* d_sweep = static_cast<double*>(ctx->w.sweep.ptr);
+    double *d_sun = d_sweep, *d_dni = d_sweep + 3 * n_sun, *d_dpoa = d_dni + n_sun, *d_dt = d_dpoa + n_sun;
+    // the scratch is the previous call's work memory until that call's kernels end
+    if ((st = ctx->wait_previous(s))) return st;
+    if (n_sun > 0) {
+        const double* src[4] = {sun_xyz, dni, d_poa, dt_h};
+        double* dst[4] = {d_sun, d_dni, d_dpoa, d_dt};
+        const size_t bytes[4] = {24 * (size_t)n_sun, 8 * (size_t)n_sun, 8 * (size_t)n_sun, 8 * (size_t)n_sun};
+        for (int i = 0; i < 4; i++)
+            if ((e = hipMemcpyAsync(dst[i], src[i], bytes[i], hipMemcpyHostToDevice, s))) return hip_fail(e, "copy the sweep");
+    }
+    if ((st = ctx->run_path(sc, g, p, sun_xyz, n_sun, d_sun, d_dni, d_dpoa, d_dt, d_counts, out->power,
+                            out->power_ref, out->energy, want_maps ? out->depth_maps : nullptr,
+                            want_bits ? out->shaded_bits : nullptr, s)))
+        return st;
+    if ((e = hipGetLastError())) return hip_fail(e, "launch");
     return PV3D_OK;
 }
 

@@ -90,6 +90,8 @@ def lib():
         L.pv3d_sun_cooper.argtypes = [_f64, _P, _P, _i64, _P]
         L.pv3d_evaluate.argtypes = [_P, _u64, _u64, _P, _P, _P, _P, _i64, ctypes.POINTER(Params),
                                     ctypes.POINTER(Outputs), _P]
+        L.pv3d_evaluate_noalloc.argtypes = [_P, _u64, _u64, _P, _P, _P, _P, _i64, ctypes.POINTER(Params),
+                                            ctypes.POINTER(Outputs), _P]
         L.pv3d_evaluate_batched.argtypes = [_P, ctypes.POINTER(Job), _i64, _P]
         L.pv3d_autotune.argtypes = [_P, ctypes.POINTER(Job), _i32, ctypes.POINTER(_f64)]
         L.pv3d_batch_stats.argtypes = [_P, ctypes.POINTER(_i64 * 7)]
@@ -338,6 +340,21 @@ class Context:
         _check(lib().pv3d_evaluate(self.h, scene_h, gen_h, _ptr(s), _ptr(dni), _ptr(dp), _ptr(dt), n,
                                    ctypes.byref(p), ctypes.byref(out), ctypes.c_void_p(st.cuda_stream)), self.h)
         return Result(counts, pw, pr, en)
+
+    def evaluate_noalloc(self, scene_h: int, gen_h: int, gen, sweep, map_n: int, k: int, counts, power, power_ref,
+                         energy, stream=None, tile: int = 0, bin_limit: int = 0, separate_test=False) -> Result:
+        """pv3d_evaluate_noalloc into caller-owned device tensors (counts may be None), asynchronous on
+        `stream` (default: torch's current stream); the library allocates nothing for the call."""
+        import torch
+        s = _c(sweep.sun_xyz, np.float64)
+        dni, dp, dt = (_c(a, np.float64) for a in (sweep.dni, sweep.d_poa, sweep.dt_h))
+        out = Outputs(_ptr(counts), _ptr(power), _ptr(power_ref), _ptr(energy), None, None, 1)
+        p = self.params(map_n, k, tile=tile, separate_test=separate_test, bin_limit=bin_limit)
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().pv3d_evaluate_noalloc(self.h, scene_h, gen_h, _ptr(s), _ptr(dni), _ptr(dp), _ptr(dt),
+                                           s.shape[0], ctypes.byref(p), ctypes.byref(out),
+                                           ctypes.c_void_p(st.cuda_stream)), self.h)
+        return Result(counts, power, power_ref, energy)
 
     # ------------------------------------------------------------------
     # batched form
