@@ -195,7 +195,17 @@ static pv3d_status start_server_parts(Ctx* c, Server* S) {
     pv3d_status st;
     if ((st = device_info(c, &S->dev))) return st;
     hipError_t e;
-    if ((e = hipStreamCreateWithFlags(&S->kstream, hipStreamNonBlocking))) return hip_fail(e, "hipStreamCreate");
+    {
+        // The persistent kernel's stream takes a hardware queue of its own (a stream made
+        // with a CU mask always does; this one enables every CU). Beyond the few queues a
+        // process gets, streams share queues, and a stream whose queue holds a live launch
+        // waits behind it: the loop's copy stream landing there made every admission wait
+        // for the launch to run dry (copies of up to 2 s, request rates down to 2 per s).
+        std::vector<uint32_t> mask((size_t)(c->n_cu + 31) / 32, 0u);
+        for (int32_t i = 0; i < c->n_cu; i++) mask[(size_t)i / 32] |= 1u << (i % 32);
+        if ((e = hipExtStreamCreateWithCUMask(&S->kstream, (uint32_t)mask.size(), mask.data())))
+            return hip_fail(e, "hipExtStreamCreateWithCUMask");
+    }
     S->cstream = c->lane_st[kLanes - 1];
     if (!S->cstream) return fail(PV3D_EDEVICE, "the context has no copy stream for the serving loop");
     if ((e = hipEventCreateWithFlags(&S->kdone, hipEventDisableTiming))) return hip_fail(e, "hipEventCreate");
