@@ -220,7 +220,12 @@ typedef struct {
  * sun_xyz: [n_sun][3] unit vectors toward the sun (|s| = 1 within 1e-9);
  * dni: [n_sun] direct normal irradiance; d_poa: [n_sun] diffuse irradiance on
  * the module plane; dt_h: [n_sun] hours each sun stands for. Host memory.
- * hip_stream: a hipStream_t of this device, or NULL for the context stream.
+ * hip_stream: a stream created on this device, or NULL for the context stream.
+ * NULL is not the null stream: the context stream is non-blocking, so work on
+ * the null stream is not ordered with it. A caller working on the null stream
+ * passes a stream of its own, made to wait for the null stream's work before
+ * the call, and makes the null stream wait for it afterwards. The special
+ * handles hipStreamLegacy and hipStreamPerThread are not accepted.
  * Consecutive suns take turns on two streams (hip_stream and one of the
  * context's), joined back into hip_stream.
  * EINVAL: bad params or inputs; ENOENT: bad handle; ENOMEM: budget. */

@@ -115,6 +115,35 @@ def lib():
     return _lib
 
 
+_side: dict = {}
+
+
+class _Ordered:
+    """The stream an asynchronous call runs on, in the order of torch stream `st`. torch's
+    default stream is the null stream (handle 0), which the C ABI would read as the context's
+    own stream, not ordered with torch's work: such calls run on a side stream that first waits
+    for `st`, and `st` waits for the side stream afterwards."""
+
+    def __init__(self, st):
+        import torch
+        self.st, self.run = st, st
+        if int(st.cuda_stream) == 0:
+            dev = st.device
+            if dev not in _side:
+                _side[dev] = torch.cuda.Stream(device=dev)
+            self.run = _side[dev]
+
+    def __enter__(self) -> ctypes.c_void_p:
+        if self.run is not self.st:
+            self.run.wait_stream(self.st)
+        return ctypes.c_void_p(int(self.run.cuda_stream))
+
+    def __exit__(self, *exc):
+        if self.run is not self.st:
+            self.st.wait_stream(self.run)
+        return False
+
+
 def _ptr(a) -> Optional[int]:
     if a is None:
         return None
@@ -337,8 +366,9 @@ class Context:
         out = Outputs(_ptr(counts), _ptr(pw), _ptr(pr), _ptr(en), None, None, 1)
         p = self.params(map_n, k, tile=tile, separate_test=separate_test, full_raster=full_raster, bin_limit=bin_limit)
         st = stream if stream is not None else torch.cuda.current_stream()
-        _check(lib().pv3d_evaluate(self.h, scene_h, gen_h, _ptr(s), _ptr(dni), _ptr(dp), _ptr(dt), n,
-                                   ctypes.byref(p), ctypes.byref(out), ctypes.c_void_p(st.cuda_stream)), self.h)
+        with _Ordered(st) as hs:
+            _check(lib().pv3d_evaluate(self.h, scene_h, gen_h, _ptr(s), _ptr(dni), _ptr(dp), _ptr(dt), n,
+                                       ctypes.byref(p), ctypes.byref(out), hs), self.h)
         return Result(counts, pw, pr, en)
 
     def evaluate_noalloc(self, scene_h: int, gen_h: int, gen, sweep, map_n: int, k: int, counts, power, power_ref,
@@ -351,9 +381,9 @@ class Context:
         out = Outputs(_ptr(counts), _ptr(power), _ptr(power_ref), _ptr(energy), None, None, 1)
         p = self.params(map_n, k, tile=tile, separate_test=separate_test, bin_limit=bin_limit)
         st = stream if stream is not None else torch.cuda.current_stream()
-        _check(lib().pv3d_evaluate_noalloc(self.h, scene_h, gen_h, _ptr(s), _ptr(dni), _ptr(dp), _ptr(dt),
-                                           s.shape[0], ctypes.byref(p), ctypes.byref(out),
-                                           ctypes.c_void_p(st.cuda_stream)), self.h)
+        with _Ordered(st) as hs:
+            _check(lib().pv3d_evaluate_noalloc(self.h, scene_h, gen_h, _ptr(s), _ptr(dni), _ptr(dp), _ptr(dt),
+                                               s.shape[0], ctypes.byref(p), ctypes.byref(out), hs), self.h)
         return Result(counts, power, power_ref, energy)
 
     # ------------------------------------------------------------------

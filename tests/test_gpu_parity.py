@@ -166,6 +166,25 @@ def test_device_outputs_match_host_outputs(ctx):
     assert np.array_equal(dev.energy.cpu().numpy(), host.energy)
 
 
+def test_device_outputs_on_torch_default_stream_are_ordered_with_it(ctx):
+    """Device outputs of a call made on torch's default (null) stream are read by torch right
+    away, with no device-wide synchronization: the reads must come after the library's writes."""
+    import torch
+    w = W.random_tiny(52, n_boxes=10, n_loose=300, n_mod_side=4, map_n=768, k=6, n_sun=48)
+    sh, gh = ctx.load_scene(w.scene), ctx.define_generator(w.gen)
+    host = ctx.evaluate(sh, gh, w.gen, w.sweep, w.map_n, w.k)
+    assert torch.cuda.current_stream().cuda_stream == 0
+    for _ in range(3):
+        counts = torch.full((w.sweep.n, w.gen.n_cells), -1, dtype=torch.int32, device="cuda")
+        dev = ctx.evaluate_device(sh, gh, w.gen, w.sweep, w.map_n, w.k, counts=counts)
+        got_energy = dev.energy.cpu().numpy()          # ordered on torch's stream only
+        got_counts = counts.cpu().numpy().view(np.uint32)
+        assert np.array_equal(got_energy, host.energy)
+        assert np.array_equal(got_counts, host.counts)
+    ctx.release_scene(sh)
+    ctx.release_generator(gh)
+
+
 def test_argument_errors(ctx):
     from paper_1410_5780_amd import pv3d
     w = W.c1_tiny()
