@@ -314,7 +314,8 @@ hipError_t launch_sample_test(int64_t s, const View* views, const GenDev& g, con
                               const int32_t* bias, const double* fu, const double* fv, int32_t k,
                               const uint32_t* map, int32_t n, uint32_t* counts, uint32_t* bits,
                               hipStream_t st);
-hipError_t launch_loss(int64_t n_sun, const double* sun, const double* beam, const uint32_t* counts,
+// Losses of suns [s0, s1) (every array indexed by the sun's own index).
+hipError_t launch_loss(int64_t s0, int64_t s1, const double* sun, const double* beam, const uint32_t* counts,
                        const double* d_poa, const GenDev& g, int32_t k, double* power,
                        double* power_ref, const SunCounters* ctr, hipStream_t st);
 hipError_t launch_energy(int64_t n_sun, const double* power, const double* power_ref,

@@ -2176,13 +2176,22 @@ __device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const Bin
                     const int64_t E2 = edge_at(T.ex[2], T.A[2], T.B[2], li256, lj256);
                     shaded = (E0 | E1 | E2) >= 0 && thr > (int32_t)depth_q(T.zx + T.gx * li + T.gy * lj);
                 }
-                if (shaded) {
-                    const int32_t cu = qa / k, cv = qb / k, cell = cv * g.n_cu + cu;
-                    atomicAdd(&out.counts[(int64_t)m * cpm + cell], 1u);
-                    if (out.bits) {
-                        const int32_t si = (qb - cv * k) * k + (qa - cu * k);
-                        atomicOr(&out.bits[((int64_t)m * cpm + cell) * words + si / 32], 1u << (si % 32));
-                    }
+                // the candidates of one cell lie on consecutive lanes (up to k of a row): the first
+                // lane of each such run adds the run's shaded samples in one atomic
+                const int32_t cu = qa / k, cv = qb / k;
+                const int32_t key = live ? cv * g.n_cu + cu : -1 - lane;
+                const int32_t below = __shfl_up(key, 1, 64);
+                const bool head = lane == 0 || key != below;
+                const unsigned long long heads = __ballot(head), shaded_lanes = __ballot(shaded);
+                if (head && live) {
+                    const unsigned long long above = lane == 63 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
+                    const unsigned long long run = (above & (~above + 1ull)) - (1ull << lane);   // lanes [lane, next head)
+                    const uint32_t n_shaded = (uint32_t)__popcll(shaded_lanes & run);
+                    if (n_shaded) atomicAdd(&out.counts[(int64_t)m * cpm + key], n_shaded);
+                }
+                if (shaded && out.bits) {
+                    const int32_t si = (qb - cv * k) * k + (qa - cu * k);
+                    atomicOr(&out.bits[((int64_t)m * cpm + key) * words + si / 32], 1u << (si % 32));
                 }
             }
         }
@@ -2738,11 +2747,11 @@ __device__ void loss_body(LossLds& L, const double* sun3, const double* beam_s, 
 // A sun whose set-up records or bin entries overflowed their buffers (never
 // with the per-sun path's capacities; a guard all the same) reads NaN powers,
 // so a caller of the asynchronous form sees it without a host round trip.
-__global__ __launch_bounds__(256) void k_loss(const double* sun, const double* beam, const uint32_t* counts,
-                                              const double* d_poa, GenDev g, int32_t k, double* power,
-                                              double* power_ref, const SunCounters* ctr) {
+__global__ __launch_bounds__(256) void k_loss(int64_t s0, const double* sun, const double* beam,
+                                              const uint32_t* counts, const double* d_poa, GenDev g, int32_t k,
+                                              double* power, double* power_ref, const SunCounters* ctr) {
     __shared__ LossLds L;
-    const int64_t s = blockIdx.x;
+    const int64_t s = s0 + blockIdx.x;
     const int64_t n_cells = (int64_t)g.n_mod * g.n_cu * g.n_cv;
     loss_body<false>(L, sun + 3 * s, beam + s * g.n_mod, counts + s * n_cells, d_poa[s], g, k, power + s, power_ref + s);
     if (ctr && threadIdx.x == 0 && ctr[s].overflow) {
@@ -3463,12 +3472,12 @@ hipError_t launch_sample_test(int64_t s, const View* views, const GenDev& g, con
     return hipGetLastError();
 }
 
-hipError_t launch_loss(int64_t n_sun, const double* sun, const double* beam, const uint32_t* counts,
+hipError_t launch_loss(int64_t s0, int64_t s1, const double* sun, const double* beam, const uint32_t* counts,
                        const double* d_poa, const GenDev& g, int32_t k, double* power, double* power_ref,
                        const SunCounters* ctr, hipStream_t st) {
-    if (n_sun <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_loss, dim3((unsigned)n_sun), dim3(256), 0, st, sun, beam, counts, d_poa, g, k, power,
-                       power_ref, ctr);
+    if (s1 <= s0) return hipSuccess;
+    hipLaunchKernelGGL(k_loss, dim3((unsigned)(s1 - s0)), dim3(256), 0, st, s0, sun, beam, counts, d_poa, g, k,
+                       power, power_ref, ctr);
     return hipGetLastError();
 }
 
