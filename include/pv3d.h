@@ -362,10 +362,9 @@ pv3d_status pv3d_batch_stats(pv3d_ctx* ctx, int64_t out[7]);
  * when the job completes; device outputs are written by the device while the
  * job runs. The job's scene and generator cannot be released until it ends
  * (EBUSY). Limits: at most 4096 modules and 65536 raster tiles per job.
- * The loop starts only in a context whose per-sun path (pv3d_evaluate,
- * pv3d_sky_view) has not run, and EINVAL says so otherwise: serve from a
- * context of its own (the per-sun path may run in it once the loop runs).
- * EBUSY: 65536 jobs wait already; ENOMEM: the job's data can never fit the
+ * The loop's persistent kernel runs on a stream with a hardware queue of its
+ * own, so the loop's copies and the context's other streams never wait behind
+ * a live launch. EBUSY: 65536 jobs wait already; ENOMEM: the job's data can never fit the
  * arena. ticket identifies the job. */
 pv3d_status pv3d_submit(pv3d_ctx* ctx, const pv3d_job* job, uint64_t* ticket);
 /* done = 1 once the job has ended (outputs in place, cancelled or failed). */

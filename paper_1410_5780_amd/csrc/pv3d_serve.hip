@@ -639,9 +639,6 @@ pv3d_status pv3d_submit(pv3d_ctx* ctx, const pv3d_job* job, uint64_t* ticket) {
     if (h.g->n_mod > kServeMaxMod) return fail(PV3D_ERANGE, "the serving loop takes at most %d modules per job", kServeMaxMod);
     if (h.n_tiles > kServeMaxTiles) return fail(PV3D_ERANGE, "the serving loop takes at most %d raster tiles per job", kServeMaxTiles);
     if (h.job.n_sun > (int64_t)kFeedCap) return fail(PV3D_ERANGE, "the serving loop takes at most %u suns per job", kFeedCap);
-    if (!ctx->server && ctx->per_sun_ran)
-        return fail(PV3D_EINVAL, "the serving loop starts only in a context whose per-sun path (pv3d_evaluate, "
-                                 "pv3d_sky_view) has not run: serve from a context of its own");
     if ((st = start_server(ctx))) return st;
     Server* S = ctx->server;
     const bool dev_out = h.job.out.on_device != 0;
