@@ -238,14 +238,20 @@ def c4_leg(ctx, every, log):
     ws = W.c4_batched(sweep=sub)
     specs = [dict(scene=ctx.load_scene(x.scene), gen=ctx.define_generator(x.gen), generator=x.gen, sweep=x.sweep,
                   map_n=x.map_n, k=x.k, counts=False) for x in ws]
+    # every site goes through the autotuner; the library times one site per class (map size, k,
+    # triangle and cell decades) and hands the others its cached choice
+    import json as _json
+    import tempfile
+    from paper_1410_5780_amd import pv3d
+    ctx.tuning_cache(pv3d.TUNE_CLEAR)
     t0 = time.perf_counter()
-    tuned = {}
-    for sp, x in zip(specs, ws):
-        key = (x.map_n, int(np.log10(max(x.scene.n_tri, 1))))
-        if key not in tuned:
-            tuned[key] = ctx.autotune(sp, n_probe=4)[:2]
-        sp["tile"], sp["bin_limit"] = tuned[key]
+    for sp in specs:
+        sp["tile"], sp["bin_limit"] = ctx.autotune(sp, n_probe=4)[:2]
     tune_s = time.perf_counter() - t0
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "tuning.json")
+        ctx.tuning_cache(pv3d.TUNE_SAVE, path)
+        tuned = _json.load(open(path))
     log(f"[bench] c4: {len(ws)} sites x {sub.n} suns, autotuned {len(tuned)} classes in {tune_s:.2f} s")
     best_p = best_b = None
     for _ in range(1 if every == 1 else 2):
@@ -274,7 +280,9 @@ def c4_leg(ctx, every, log):
                         f"year ({sub.n} suns each, {st['items']} items)",
             "plain_loop_s": best_p, "batched_s": best_b, "speedup": best_p / best_b, "identical": same,
             "batched_tests_per_s": samples / best_b, "batched_triangles_per_s": tris / best_b,
-            "autotune_s": tune_s, "autotuned": {f"N{k[0]}_1e{k[1]}tri": list(v) for k, v in tuned.items()},
+            "autotune_s": tune_s,
+            "autotuned": {f"N{e['map_n']}_1e{e['tri_decade']}tri_1e{e['cell_decade']}cells": [e["tile"], e["bin_limit"]]
+                          for e in tuned},
             "units": st["units"], "slots": st["slots"], "redone_per_sun": st["redone"]}
 
 

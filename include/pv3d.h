@@ -317,13 +317,31 @@ pv3d_status pv3d_evaluate_batched(pv3d_ctx* ctx, const pv3d_job* jobs, int64_t n
                                   void* hip_stream);
 
 /* Autotuner of the batched form: times every candidate (tile edge 32 or 64 x
- * bin_limit 16, 64 or 256) on up to n_probe of the job's suns above the
- * horizon (evenly spaced), through the persistent launch, and writes the
- * fastest into job->params.tile and job->params.bin_limit. Every candidate
- * gives identical results; only time differs. best_ms_out (may be NULL)
- * receives the winner's time for the probe suns. The job's outputs are
- * not written. */
+ * bin_limit, the number of tiles above which a triangle is not binned but
+ * checked by every tile, 8, 16, 32, 64, 128 or 256) on up to n_probe of the
+ * job's suns above the horizon (evenly spaced), through the persistent launch,
+ * and writes the fastest into job->params.tile and job->params.bin_limit.
+ * Every candidate gives identical results; only time differs. best_ms_out
+ * (may be NULL) receives the winner's time for the probe suns. The job's
+ * outputs are not written.
+ * The choice is cached in the context by the job's class: map_n, k, flags,
+ * the decade of its triangles (scene, plus the generator's modules when they
+ * occlude) and the decade of its cells. A job of a class already tuned (or
+ * loaded with pv3d_autotune_cache) takes the cached choice without timing,
+ * and best_ms_out receives the time cached with it. */
 pv3d_status pv3d_autotune(pv3d_ctx* ctx, pv3d_job* job, int32_t n_probe, double* best_ms_out);
+
+/* The autotuner's cache: mode PV3D_TUNE_SAVE writes every cached class to the
+ * JSON file at path (an array of objects with the keys map_n, k, flags,
+ * tri_decade, cell_decade, tile, bin_limit, ms), PV3D_TUNE_LOAD adds the
+ * classes of such a file to the context's cache (replacing classes it already
+ * holds), PV3D_TUNE_CLEAR empties the cache (path may be NULL). ENOENT: the
+ * file cannot be opened; EINVAL: unknown mode, a malformed file, or values
+ * outside the autotuner's candidates. */
+#define PV3D_TUNE_LOAD 0
+#define PV3D_TUNE_SAVE 1
+#define PV3D_TUNE_CLEAR 2
+pv3d_status pv3d_autotune_cache(pv3d_ctx* ctx, const char* path, int32_t mode);
 
 /* Memory and placement of the batched form: at most max_slots (item) slots
  * in flight, each with room for slot_records triangle set-up records (and 8

@@ -117,6 +117,23 @@ struct DevInfo {
     int rate_khz = 100000;        // wall clock of the device
 };
 
+// A class of jobs for the autotuner's cache, and the choice made for it.
+struct TuneKey {
+    int32_t map_n, k, tri_decade, cell_decade;
+    uint32_t flags;
+    bool operator<(const TuneKey& o) const {
+        if (map_n != o.map_n) return map_n < o.map_n;
+        if (k != o.k) return k < o.k;
+        if (tri_decade != o.tri_decade) return tri_decade < o.tri_decade;
+        if (cell_decade != o.cell_decade) return cell_decade < o.cell_decade;
+        return flags < o.flags;
+    }
+};
+struct TuneChoice {
+    int32_t tile, bin_limit;
+    double ms;
+};
+
 // Event pairs around launches of selected stages (profiling aid).
 struct Profiler {
     uint32_t mask = 0;
@@ -201,6 +218,7 @@ struct Ctx {
     int64_t batch_slot_records = 1 << 20;
     bool batch_any_xcd = false;
     Profiler prof;
+    std::map<TuneKey, TuneChoice> tune_cache;   // pv3d_autotune's choices by job class
 
     pv3d_status dalloc(void** p, size_t bytes, const char* what);
     void dfree(void* p);

@@ -16,7 +16,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <iterator>
+#include <string>
 #include <memory>
 #include <vector>
 
@@ -497,6 +501,28 @@ pv3d_status pv3d_evaluate_batched(pv3d_ctx* ctx, const pv3d_job* jobs, int64_t n
     return run_batch(ctx, jobs, n_jobs, s);
 }
 
+}  // extern "C"
+
+namespace pv3d {
+// The autotuner's candidates: tile edges of the persistent launch, and bin limits.
+constexpr int32_t kTuneTiles[2] = {32, 64};
+constexpr int32_t kTuneLimits[6] = {8, 16, 32, 64, 128, 256};
+
+static int32_t decade(int64_t n) {
+    int32_t d = 0;
+    for (int64_t v = std::max<int64_t>(n, 1); v >= 10; v /= 10) d++;
+    return d;
+}
+
+// The class of a job: map size, samples per cell side, flags, and the decades of its
+// triangles and cells.
+static TuneKey tune_key(const pv3d_job& j, const HostJob& h) {
+    return TuneKey{j.params.map_n, j.params.k, decade(h.tri_all), decade(h.cells), j.params.flags};
+}
+}  // namespace pv3d
+
+extern "C" {
+
 pv3d_status pv3d_autotune(pv3d_ctx* ctx, pv3d_job* job, int32_t n_probe, double* best_ms_out) {
     if (!ctx || !job) return fail(PV3D_EINVAL, "null argument");
     if (n_probe < 1) return fail(PV3D_EINVAL, "n_probe %d < 1", n_probe);
@@ -506,6 +532,14 @@ pv3d_status pv3d_autotune(pv3d_ctx* ctx, pv3d_job* job, int32_t n_probe, double*
     ctx->stream_in_use = ctx->stream;
     pv3d_status st;
     if ((st = check_job(ctx, *job, 0, h, true))) return st;
+    const TuneKey key = tune_key(*job, h);
+    auto hit = ctx->tune_cache.find(key);
+    if (hit != ctx->tune_cache.end()) {
+        job->params.tile = hit->second.tile;
+        job->params.bin_limit = hit->second.bin_limit;
+        if (best_ms_out) *best_ms_out = hit->second.ms;
+        return PV3D_OK;
+    }
     // probe suns: evenly spaced among those above the horizon
     std::vector<int64_t> up;
     for (int64_t t = 0; t < job->n_sun; t++)
@@ -538,12 +572,10 @@ pv3d_status pv3d_autotune(pv3d_ctx* ctx, pv3d_job* job, int32_t n_probe, double*
     probe.out.depth_maps = nullptr;
     probe.out.shaded_bits = nullptr;
     probe.out.on_device = 0;
-    const int32_t tiles[2] = {32, 64};
-    const int32_t limits[3] = {16, 64, 256};
     double best = INFINITY;
     int32_t bt = 64, bl = kMaxBinLimit;
-    for (int32_t tile : tiles)
-        for (int32_t lim : limits) {
+    for (int32_t tile : kTuneTiles)
+        for (int32_t lim : kTuneLimits) {
             probe.params.tile = tile;
             probe.params.bin_limit = lim;
             if ((st = run_batch(ctx, &probe, 1, ctx->stream))) return st;     // warm
@@ -557,7 +589,80 @@ pv3d_status pv3d_autotune(pv3d_ctx* ctx, pv3d_job* job, int32_t n_probe, double*
         }
     job->params.tile = bt;
     job->params.bin_limit = bl;
+    ctx->tune_cache[key] = TuneChoice{bt, bl, best};
     if (best_ms_out) *best_ms_out = best;
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_autotune_cache(pv3d_ctx* ctx, const char* path, int32_t mode) {
+    if (!ctx) return fail(PV3D_EINVAL, "null context");
+    if (mode != PV3D_TUNE_LOAD && mode != PV3D_TUNE_SAVE && mode != PV3D_TUNE_CLEAR)
+        return fail(PV3D_EINVAL, "unknown cache mode %d", mode);
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (mode == PV3D_TUNE_CLEAR) {
+        ctx->tune_cache.clear();
+        return PV3D_OK;
+    }
+    if (!path) return fail(PV3D_EINVAL, "null path");
+    if (mode == PV3D_TUNE_SAVE) {
+        FILE* f = fopen(path, "w");
+        if (!f) return fail(PV3D_ENOENT, "cannot open %s for writing", path);
+        fprintf(f, "[\n");
+        size_t i = 0;
+        for (const auto& kv : ctx->tune_cache) {
+            const TuneKey& k = kv.first;
+            const TuneChoice& c = kv.second;
+            fprintf(f, "  {\"map_n\": %d, \"k\": %d, \"flags\": %u, \"tri_decade\": %d, \"cell_decade\": %d, "
+                       "\"tile\": %d, \"bin_limit\": %d, \"ms\": %.17g}%s\n",
+                    k.map_n, k.k, k.flags, k.tri_decade, k.cell_decade, c.tile, c.bin_limit, c.ms,
+                    ++i < ctx->tune_cache.size() ? "," : "");
+        }
+        fprintf(f, "]\n");
+        const bool bad = ferror(f) != 0;
+        if (fclose(f) != 0 || bad) return fail(PV3D_ENOENT, "writing %s failed", path);
+        return PV3D_OK;
+    }
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(PV3D_ENOENT, "cannot open %s", path);
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+    fclose(f);
+    // the objects of the array, in the layout PV3D_TUNE_SAVE writes (any spacing)
+    std::map<TuneKey, TuneChoice> add;
+    size_t at = text.find('[');
+    if (at == std::string::npos) return fail(PV3D_EINVAL, "%s: no JSON array", path);
+    for (;;) {
+        const size_t open = text.find('{', at), close = text.find('}', at);
+        if (open == std::string::npos) break;
+        if (close == std::string::npos || close < open) return fail(PV3D_EINVAL, "%s: unbalanced object", path);
+        const std::string obj = text.substr(open, close - open + 1);
+        auto field = [&](const char* name, double* v) {
+            const std::string pat = std::string("\"") + name + "\"";
+            const size_t p = obj.find(pat);
+            if (p == std::string::npos) return false;
+            const size_t colon = obj.find(':', p + pat.size());
+            if (colon == std::string::npos) return false;
+            char* end = nullptr;
+            *v = strtod(obj.c_str() + colon + 1, &end);
+            return end != obj.c_str() + colon + 1 && std::isfinite(*v);
+        };
+        double v[8];
+        const char* names[8] = {"map_n", "k", "flags", "tri_decade", "cell_decade", "tile", "bin_limit", "ms"};
+        for (int i = 0; i < 8; i++)
+            if (!field(names[i], &v[i])) return fail(PV3D_EINVAL, "%s: an entry lacks \"%s\"", path, names[i]);
+        TuneKey key{(int32_t)v[0], (int32_t)v[1], (int32_t)v[3], (int32_t)v[4], (uint32_t)v[2]};
+        TuneChoice c{(int32_t)v[5], (int32_t)v[6], v[7]};
+        const bool tile_ok = std::find(std::begin(kTuneTiles), std::end(kTuneTiles), c.tile) != std::end(kTuneTiles);
+        const bool lim_ok =
+            std::find(std::begin(kTuneLimits), std::end(kTuneLimits), c.bin_limit) != std::end(kTuneLimits);
+        if (!tile_ok || !lim_ok || key.map_n < 16 || key.map_n > 16384 || key.k < 1 || key.k > 255 || c.ms < 0.0)
+            return fail(PV3D_EINVAL, "%s: an entry holds values outside the autotuner's candidates", path);
+        add[key] = c;
+        at = close + 1;
+    }
+    for (const auto& kv : add) ctx->tune_cache[kv.first] = kv.second;
     return PV3D_OK;
 }
 

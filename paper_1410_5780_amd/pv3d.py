@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpv3d.so")
 
 OK, EINVAL, ENOMEM, ENOENT, EDEVICE, ERANGE, EBUSY, ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7
+TUNE_LOAD, TUNE_SAVE, TUNE_CLEAR = 0, 1, 2
 EXPORT_DEPTH, EXPORT_BITS, SEPARATE_TEST, FULL_RASTER = 1, 2, 4, 8
 BATCH_ANY_XCD = 1
 STAGES = ("tri_setup", "bin_scan", "bin_scatter", "raster", "sample_test", "setup", "loss")
@@ -94,6 +95,7 @@ def lib():
                                             ctypes.POINTER(Outputs), _P]
         L.pv3d_evaluate_batched.argtypes = [_P, ctypes.POINTER(Job), _i64, _P]
         L.pv3d_autotune.argtypes = [_P, ctypes.POINTER(Job), _i32, ctypes.POINTER(_f64)]
+        L.pv3d_autotune_cache.argtypes = [_P, ctypes.c_char_p, _i32]
         L.pv3d_batch_stats.argtypes = [_P, ctypes.POINTER(_i64 * 7)]
         L.pv3d_batch_limits.argtypes = [_P, _i32, _i64, _u32]
         L.pv3d_serve_stats.argtypes = [_P, ctypes.POINTER(_i64 * 4)]
@@ -436,6 +438,11 @@ class Context:
         ms = _f64()
         _check(lib().pv3d_autotune(self.h, ctypes.byref(job), n_probe, ctypes.byref(ms)), self.h)
         return job.params.tile, job.params.bin_limit, ms.value
+
+    def tuning_cache(self, mode: int, path: Optional[str] = None):
+        """The autotuner's cache: TUNE_SAVE writes it to the JSON file at path, TUNE_LOAD adds a
+        saved file's classes, TUNE_CLEAR empties it."""
+        _check(lib().pv3d_autotune_cache(self.h, path.encode() if path is not None else None, mode), self.h)
 
     def batch_limits(self, max_slots: int = 0, slot_records: int = 0, any_xcd: bool = False):
         _check(lib().pv3d_batch_limits(self.h, max_slots, slot_records, BATCH_ANY_XCD if any_xcd else 0), self.h)

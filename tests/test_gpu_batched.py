@@ -157,9 +157,53 @@ def test_autotune_picks_a_candidate_with_identical_results(ctx):
     sp = _spec(ctx, w)
     tile, lim, ms = ctx.autotune(sp, n_probe=4)
     _say(f"[autotune] tile={tile} bin_limit={lim} probe={ms:.3f} ms")
-    assert tile in (32, 64) and lim in (16, 64, 256) and ms > 0
+    assert tile in (32, 64) and lim in (8, 16, 32, 64, 128, 256) and ms > 0
     a = ctx.evaluate_batched([dict(sp, tile=tile, bin_limit=lim)])[0]
     _same(a, _plain(ctx, sp), "autotuned batch")
+
+
+def test_autotune_cache_by_job_class(ctx, tmp_path):
+    """A job of a class already tuned takes the cached choice without a launch; the cache
+    survives a save and a load into another context; a cleared cache times again; a missing
+    or malformed file is refused."""
+    import json
+    from paper_1410_5780_amd import pv3d
+    ctx.tuning_cache(pv3d.TUNE_CLEAR)
+    w1 = W.random_tiny(73, n_boxes=10, n_loose=40, n_mod_side=3, map_n=320, k=4, n_sun=8)
+    w2 = W.random_tiny(74, n_boxes=9, n_loose=45, n_mod_side=3, map_n=320, k=4, n_sun=6)   # same class
+    s1, s2 = _spec(ctx, w1), _spec(ctx, w2)
+    first = ctx.autotune(s1, n_probe=4)
+    stats = ctx.batch_stats()
+    second = ctx.autotune(s2, n_probe=4)
+    assert second == first and ctx.batch_stats() == stats      # cached: no launch
+    path = str(tmp_path / "tuning.json")
+    ctx.tuning_cache(pv3d.TUNE_SAVE, path)
+    saved = json.load(open(path))
+    assert len(saved) == 1 and saved[0]["map_n"] == 320 and saved[0]["k"] == 4
+    assert (saved[0]["tile"], saved[0]["bin_limit"]) == first[:2]
+    with pv3d.Context(0) as other:
+        o2 = _spec(other, w2)
+        other.tuning_cache(pv3d.TUNE_LOAD, path)
+        assert other.autotune(o2, n_probe=4) == first
+        assert other.batch_stats()["launch_us"] == 0                   # never launched
+        other.tuning_cache(pv3d.TUNE_CLEAR)
+        tile, lim, ms = other.autotune(o2, n_probe=4)
+        assert other.batch_stats()["launch_us"] > 0 and tile in (32, 64)
+    with pytest.raises(pv3d.Pv3dError) as e:
+        ctx.tuning_cache(pv3d.TUNE_LOAD, str(tmp_path / "missing.json"))
+    assert e.value.code == pv3d.ENOENT
+    bad = tmp_path / "bad.json"
+    bad.write_text(json.dumps([dict(saved[0], tile=128)]))
+    with pytest.raises(pv3d.Pv3dError) as e:
+        ctx.tuning_cache(pv3d.TUNE_LOAD, str(bad))
+    assert e.value.code == pv3d.EINVAL
+    bad.write_text('[{"map_n": 320}]')
+    with pytest.raises(pv3d.Pv3dError) as e:
+        ctx.tuning_cache(pv3d.TUNE_LOAD, str(bad))
+    assert e.value.code == pv3d.EINVAL
+    with pytest.raises(pv3d.Pv3dError) as e:
+        ctx.tuning_cache(7)
+    assert e.value.code == pv3d.EINVAL
 
 
 def test_batched_argument_errors(ctx):
