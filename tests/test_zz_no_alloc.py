@@ -102,6 +102,19 @@ def test_scene_too_large_is_refused_and_fits_with_a_smaller_bin_limit(ctx):
     _check_same(ctx, w, bin_limit=8)
 
 
+def test_dark_sweep_and_mixed_sweep(ctx):
+    """Every sun below the horizon (nothing is drawn, every power zero), then a sweep whose up
+    suns are split by night hours (groups skip the down suns in between)."""
+    import dataclasses
+    base = W.random_tiny(76, n_boxes=8, n_loose=50, n_mod_side=3, map_n=256, k=4, n_sun=2)
+    night = W.make_sweep(40.4, [10, 200], [0.0, 1.0, 2.0, 22.0, 23.0])
+    assert (night.sun_xyz[:, 2] <= 0.0).all()
+    _check_same(ctx, dataclasses.replace(base, sweep=night, name="night"))
+    mixed = W.make_sweep(40.4, [30, 172, 300], np.arange(0.0, 24.0, 1.0))
+    assert (mixed.sun_xyz[:, 2] > 0.0).any() and (mixed.sun_xyz[:, 2] <= 0.0).any()
+    _check_same(ctx, dataclasses.replace(base, sweep=mixed, name="day and night"))
+
+
 def test_host_outputs_are_refused(ctx):
     from paper_1410_5780_amd import pv3d
     import ctypes
