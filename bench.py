@@ -553,7 +553,7 @@ def main():
                                    "bytes_per_sun": mb}}
         log(f"[bench] materialised route: {sub.n} suns in {m1 - m0:.3f} s")
     line = {
-        "metric": "sample x sun shadow tests/s (+ triangles rasterized/s)",
+        "metric": "sample\u00d7sun shadow tests/s + triangles rasterized/s; p50/p99 request latency",
         "value": tests / sec_per_step,
         "unit": "sample-sun tests/s",
         "n_gpus": 1,
@@ -600,7 +600,7 @@ def main():
         if "sky" in legs:
             line["sky"] = sky_leg(ctx, log)
         if "serving" in legs:
-            # the serving loop starts only in a context whose per-sun path has not run
+            # the serving loop in a context of its own, with the GPU to itself
             ctx.close()
             sctx = pv3d.Context(0)
             try:
@@ -608,6 +608,11 @@ def main():
                                               a.light_seconds, a.sweep_requests)
             finally:
                 sctx.close()
+            cr = line["serving"]["configured_rate"]
+            line["request_latency_ms"] = {"p50": cr["p50_ms"], "p99": cr["p99_ms"], "requests": cr["requests"],
+                                          "offered_req_per_s": cr["offered_req_per_s"],
+                                          "sustained_req_per_s": cr["sustained_req_per_s"],
+                                          "stream": "the configured Poisson stream through the serving loop"}
     if not a.no_cpu:
         log("[bench] cpu oracle legs ...")
         full = w if a.suns <= 1 else workload(a.workload, 1)
