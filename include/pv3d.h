@@ -215,8 +215,10 @@ typedef struct {
     int32_t on_device;
 } pv3d_outputs;
 
-/* Evaluate one generator in one scene for a sweep of sun positions, one sun
- * at a time (a launch sequence per sun).
+/* Evaluate one generator in one scene for a sweep of sun positions: the suns
+ * above the horizon in groups of up to eight per launch sequence (set-up,
+ * binning, tile pass), then one loss launch over the sweep and the energy sums
+ * in sun order. Results do not depend on the grouping.
  * sun_xyz: [n_sun][3] unit vectors toward the sun (|s| = 1 within 1e-9);
  * dni: [n_sun] direct normal irradiance; d_poa: [n_sun] diffuse irradiance on
  * the module plane; dt_h: [n_sun] hours each sun stands for. Host memory.
@@ -226,8 +228,10 @@ typedef struct {
  * passes a stream of its own, made to wait for the null stream's work before
  * the call, and makes the null stream wait for it afterwards. The special
  * handles hipStreamLegacy and hipStreamPerThread are not accepted.
- * Consecutive suns take turns on two streams (hip_stream and one of the
- * context's), joined back into hip_stream.
+ * Consecutive groups take turns on two streams (hip_stream and one of the
+ * context's), joined back into hip_stream. Calls of one context are ordered:
+ * each waits for the previous evaluation's kernels before it reuses the
+ * context's work buffers, whatever streams the two calls use.
  * EINVAL: bad params or inputs; ENOENT: bad handle; ENOMEM: budget. */
 pv3d_status pv3d_evaluate(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const double* sun_xyz,
                           const double* dni, const double* d_poa, const double* dt_h,
