@@ -232,6 +232,30 @@ def test_c3_rooftop_full_size_sampled_suns(ctx, oracle_lib):
     assert got.counts.sum() > 0
 
 
+@pytest.mark.parametrize("which", ["c3", "c2"])
+def test_full_size_production_route_on_24_suns(ctx, oracle_lib, which):
+    """The production route (nothing exported but the shaded flags) on every 183rd sun of the
+    year at full size: three groups of eight suns over the two lanes, against the oracle."""
+    yr = W.year_sweep()
+    sub = yr.subset(np.arange(0, yr.n, 183))
+    w = W.c3_rooftop(sweep=sub) if which == "c3" else W.c2_row_plant(sweep=sub)
+    _say(f"[parity] {w.name} production route: {sub.n} suns")
+    sh, gh = ctx.load_scene(w.scene), ctx.define_generator(w.gen)
+    try:
+        got = ctx.evaluate(sh, gh, w.gen, w.sweep, w.map_n, w.k, export_bits=True)
+    finally:
+        ctx.release_scene(sh)
+        ctx.release_generator(gh)
+    ref = oracle_lib.evaluate(w.scene, w.gen, w.sweep, w.map_n, w.k, export_bits=True)
+    bad = np.nonzero((got.counts != ref.counts).any(axis=1))[0]
+    assert bad.size == 0, f"counts differ at suns {bad[:10]}"
+    assert np.array_equal(got.bits, ref.bits)
+    np.testing.assert_allclose(got.power, ref.power, rtol=REL, atol=0)
+    np.testing.assert_allclose(got.power_ref, ref.power_ref, rtol=REL, atol=0)
+    np.testing.assert_allclose(got.energy, ref.energy, rtol=REL, atol=0)
+    assert ref.outside == 0 and got.counts.sum() > 0
+
+
 def test_back_to_back_device_evaluations_on_two_streams(ctx, oracle_lib):
     """Two asynchronous evaluations queued at once on two streams share the context's work
     buffers: the second waits for the first, and both equal the oracle."""
