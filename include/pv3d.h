@@ -386,7 +386,10 @@ pv3d_status pv3d_batch_stats(pv3d_ctx* ctx, int64_t out[7]);
  * (EBUSY). Limits: at most 4096 modules and 65536 raster tiles per job.
  * The loop's persistent kernel runs on a stream with a hardware queue of its
  * own, so the loop's copies and the context's other streams never wait behind
- * a live launch. EBUSY: 65536 jobs wait already; ENOMEM: the job's data can never fit the
+ * a live launch. That stream (made with a CU mask, which takes no flags) is a
+ * blocking one: work the caller puts on the null stream while a launch is
+ * live waits for that launch to end, so a caller serving and computing at once
+ * works on streams of its own. EBUSY: 65536 jobs wait already; ENOMEM: the job's data can never fit the
  * arena. ticket identifies the job. */
 pv3d_status pv3d_submit(pv3d_ctx* ctx, const pv3d_job* job, uint64_t* ticket);
 /* done = 1 once the job has ended (outputs in place, cancelled or failed). */
