@@ -172,7 +172,8 @@ def timed_year(ctx, w, sh, gh, steps, warmup, route="sparse", tile=0, log=None):
     ctx.profile_enable(0)
     if log:
         log(f"[bench] {w.name}: timed {steps} passes in {t1 - t0:.3f} s")
-    return {"sec_per_step": (t1 - t0) / steps, "stage_ms": stage_ms, "dominant": dominant,
+    work = ctx.path_stats()                # the last timed pass: set-up records and binned pairs
+    return {"sec_per_step": (t1 - t0) / steps, "stage_ms": stage_ms, "dominant": dominant, "work": work,
             "event_ms": k_ms, "launches": k_n, "busy_ms": busy_ms, "suns": suns, "result": res, "step": step}
 
 
@@ -571,6 +572,9 @@ def main():
                    "triangles": w.n_tri_submitted, "cells": w.gen.n_cells, "samples_per_sun": w.n_samples,
                    "suns": n_sun, "map_n": w.map_n, "k": w.k},
         "triangles_per_s": tris / sec_per_step,
+        "in_window_records_per_s": t["work"]["records"] / sec_per_step,
+        "work_per_step": dict(t["work"], note="set-up records: triangles inside the window after culling, a "
+                                              "triangle cut at the guard band once per piece"),
         "year_seconds": sec_per_step * (4379.0 / n_sun),
         "roofline": roofline_of(t, w, a.route),
         "route": a.route,

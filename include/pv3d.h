@@ -263,6 +263,15 @@ pv3d_status pv3d_evaluate_noalloc(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, c
                                   int64_t n_sun, const pv3d_params* params, pv3d_outputs* out,
                                   void* hip_stream);
 
+/* Work counts of the context's last pv3d_evaluate (waits for it to end):
+ * out[0] suns, out[1] triangle set-up records summed over the suns (the scene
+ * and module triangles inside the window after culling; a triangle cut at the
+ * guard band counts once per piece), out[2] records handled by every tile
+ * instead of binned, out[3] (record, tile) pairs binned. All zero before any
+ * evaluation; the batched, serving and allocation-free forms do not update
+ * them. */
+pv3d_status pv3d_path_stats(pv3d_ctx* ctx, int64_t out[4]);
+
 /* Diffuse shading (Sec. 4: obstacles also hide part of the diffuse sky, which
  * the paper's evaluation leaves out). An isotropic sky is seen through n_dir
  * fixed directions above the horizon, each standing for an equal share of it

@@ -202,6 +202,7 @@ struct Ctx {
     // pv3d_evaluate has run: the serving loop is not started in this context any more (a
     // burst of requests served after the per-sun path in one context waited minutes)
     bool per_sun_ran = false;
+    int64_t last_n_sun = 0;                 // suns of the last per-sun evaluation (pv3d_path_stats)
     DevInfo dev_info;
     // pv3d_evaluate_noalloc: while `carving`, every work buffer the evaluation ensures
     // is taken from the device's static scratch array (carve_base, kScratchBytes bytes)

@@ -1390,6 +1390,7 @@ pv3d_status pv3d_evaluate(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, const dou
     if ((st = ctx->run_path(sc, g, p, sun_xyz, n_sun, d_sun, d_dni, d_dpoa, d_dt, d_counts, d_pw, d_pr, d_en,
                             d_maps, d_bits, s)))
         return st;
+    ctx->last_n_sun = n_sun;
     if (!out->on_device) {
         bool ovf = false;
         if ((st = ctx->read_overflow(n_sun, s, &ovf))) return st;
@@ -1497,6 +1498,27 @@ pv3d_status pv3d_evaluate_noalloc(pv3d_ctx* ctx, uint64_t scene, uint64_t gen, c
                             want_bits ? out->shaded_bits : nullptr, s)))
         return st;
     if ((e = hipGetLastError())) return hip_fail(e, "launch");
+    return PV3D_OK;
+}
+
+pv3d_status pv3d_path_stats(pv3d_ctx* ctx, int64_t out[4]) {
+    if (!ctx || !out) return fail(PV3D_EINVAL, "null argument");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    for (int i = 0; i < 4; i++) out[i] = 0;
+    const int64_t n = ctx->last_n_sun;
+    if (n <= 0 || !ctx->w.ctr.ptr) return PV3D_OK;
+    (void)hipSetDevice(ctx->device);
+    hipError_t e;
+    if (ctx->ws_recorded && (e = hipEventSynchronize(ctx->ws_ev))) return hip_fail(e, "wait for the evaluation");
+    std::vector<SunCounters> h((size_t)n);
+    if ((e = hipMemcpy(h.data(), ctx->w.ctr.ptr, sizeof(SunCounters) * (size_t)n, hipMemcpyDeviceToHost)))
+        return hip_fail(e, "read the sun counters");
+    out[0] = n;
+    for (const SunCounters& c : h) {
+        out[1] += c.n_rec;
+        out[2] += c.n_large;
+        out[3] += (int64_t)(c.pairs & 0xFFFFFFFFull);
+    }
     return PV3D_OK;
 }
 

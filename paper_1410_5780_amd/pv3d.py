@@ -91,6 +91,7 @@ def lib():
         L.pv3d_sun_cooper.argtypes = [_f64, _P, _P, _i64, _P]
         L.pv3d_evaluate.argtypes = [_P, _u64, _u64, _P, _P, _P, _P, _i64, ctypes.POINTER(Params),
                                     ctypes.POINTER(Outputs), _P]
+        L.pv3d_path_stats.argtypes = [_P, ctypes.POINTER(_i64 * 4)]
         L.pv3d_evaluate_noalloc.argtypes = [_P, _u64, _u64, _P, _P, _P, _P, _i64, ctypes.POINTER(Params),
                                             ctypes.POINTER(Outputs), _P]
         L.pv3d_evaluate_batched.argtypes = [_P, ctypes.POINTER(Job), _i64, _P]
@@ -446,6 +447,12 @@ class Context:
 
     def batch_limits(self, max_slots: int = 0, slot_records: int = 0, any_xcd: bool = False):
         _check(lib().pv3d_batch_limits(self.h, max_slots, slot_records, BATCH_ANY_XCD if any_xcd else 0), self.h)
+
+    def path_stats(self) -> dict:
+        """Work counts of the last per-sun evaluation (waits for it to end)."""
+        a = (_i64 * 4)()
+        _check(lib().pv3d_path_stats(self.h, ctypes.byref(a)), self.h)
+        return dict(zip(("suns", "records", "large", "pairs"), list(a)))
 
     def batch_stats(self) -> dict:
         a = (_i64 * 7)()

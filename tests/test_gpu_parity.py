@@ -185,6 +185,21 @@ def test_device_outputs_on_torch_default_stream_are_ordered_with_it(ctx):
     ctx.release_generator(gh)
 
 
+def test_path_stats_count_the_last_evaluation():
+    """Zero before any evaluation; after one, the suns and the set-up records of the up suns:
+    at least one record per triangle the window keeps, at most five (a clipped triangle's fan)."""
+    from paper_1410_5780_amd import pv3d
+    w = W.c1_tiny(d_poa=100.0)
+    with pv3d.Context(0) as c:
+        assert c.path_stats() == {"suns": 0, "records": 0, "large": 0, "pairs": 0}
+        sh, gh = c.load_scene(w.scene), c.define_generator(w.gen)
+        c.evaluate(sh, gh, w.gen, w.sweep, w.map_n, w.k)
+        st = c.path_stats()
+    n_up = int((w.sweep.sun_xyz[:, 2] > 0).sum())
+    tris = w.scene.n_tri + 2 * w.gen.n_mod
+    assert st["suns"] == w.sweep.n and 0 < st["records"] <= 5 * tris * n_up and st["pairs"] > 0
+
+
 def test_argument_errors(ctx):
     from paper_1410_5780_amd import pv3d
     w = W.c1_tiny()
