@@ -41,6 +41,14 @@ pv3d_status hip_fail(hipError_t e, const char* what) {
     return fail(PV3D_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// A synchronous host-to-device copy on the context's own stream. hipMemcpy would go on the
+// null stream, which waits for every blocking stream, the serving loop's kernel stream among
+// them: a scene loaded while a launch is live would wait for that launch to end.
+static hipError_t copy_in(Ctx* c, void* dev, const void* host, size_t bytes) {
+    hipError_t e = hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, c->stream);
+    return e != hipSuccess ? e : hipStreamSynchronize(c->stream);
+}
+
 // ---------------------------------------------------------------------------
 // device memory with budget accounting
 // ---------------------------------------------------------------------------
@@ -956,9 +964,9 @@ pv3d_status pv3d_scene_load(pv3d_ctx* ctx, const double* xyz, int64_t n_vert, co
         return st;
     }
     hipError_t e;
-    if (n_vert && (e = hipMemcpy(s.xyz, xyz, 24 * (size_t)n_vert, hipMemcpyHostToDevice))) return hip_fail(e, "copy vertices");
-    if (n_tri && (e = hipMemcpy(s.tri, tri, 12 * (size_t)n_tri, hipMemcpyHostToDevice))) return hip_fail(e, "copy triangles");
-    if (n_blk && (e = hipMemcpy(s.cbox, cbox.data(), 48 * (size_t)n_blk, hipMemcpyHostToDevice)))
+    if (n_vert && (e = copy_in(ctx, s.xyz, xyz, 24 * (size_t)n_vert))) return hip_fail(e, "copy vertices");
+    if (n_tri && (e = copy_in(ctx, s.tri, tri, 12 * (size_t)n_tri))) return hip_fail(e, "copy triangles");
+    if (n_blk && (e = copy_in(ctx, s.cbox, cbox.data(), 48 * (size_t)n_blk)))
         return hip_fail(e, "copy block boxes");
     uint64_t h = ++ctx->next_handle;
     ctx->scenes[h] = s;
@@ -1142,13 +1150,13 @@ static pv3d_status define_upload(pv3d_ctx* ctx, Gen& g, const std::vector<Module
     if ((st = ctx->dalloc((void**)&g.sub_start, 4 * (size_t)(n_sub + 1), "substring starts"))) return st;
     if ((st = ctx->dalloc((void**)&g.sub_cell, 4 * (size_t)(n_cu * n_cv), "substring cells"))) return st;
     hipError_t e;
-    if ((e = hipMemcpy(g.mods, hm.data(), sizeof(Module) * (size_t)n_mod, hipMemcpyHostToDevice))) return hip_fail(e, "copy modules");
-    if ((e = hipMemcpy(g.cell_sub, cell_substring, 4 * (size_t)(n_cu * n_cv), hipMemcpyHostToDevice))) return hip_fail(e, "copy cell map");
-    if ((e = hipMemcpy(g.str_start, start.data(), 4 * (size_t)(n_str + 1), hipMemcpyHostToDevice))) return hip_fail(e, "copy strings");
-    if ((e = hipMemcpy(g.str_mods, order.data(), 4 * (size_t)n_mod, hipMemcpyHostToDevice))) return hip_fail(e, "copy strings");
-    if ((e = hipMemcpy(g.sub_start, sub_start.data(), 4 * (size_t)(n_sub + 1), hipMemcpyHostToDevice)))
+    if ((e = copy_in(ctx, g.mods, hm.data(), sizeof(Module) * (size_t)n_mod))) return hip_fail(e, "copy modules");
+    if ((e = copy_in(ctx, g.cell_sub, cell_substring, 4 * (size_t)(n_cu * n_cv)))) return hip_fail(e, "copy cell map");
+    if ((e = copy_in(ctx, g.str_start, start.data(), 4 * (size_t)(n_str + 1)))) return hip_fail(e, "copy strings");
+    if ((e = copy_in(ctx, g.str_mods, order.data(), 4 * (size_t)n_mod))) return hip_fail(e, "copy strings");
+    if ((e = copy_in(ctx, g.sub_start, sub_start.data(), 4 * (size_t)(n_sub + 1))))
         return hip_fail(e, "copy substrings");
-    if ((e = hipMemcpy(g.sub_cell, sub_cell.data(), 4 * (size_t)(n_cu * n_cv), hipMemcpyHostToDevice)))
+    if ((e = copy_in(ctx, g.sub_cell, sub_cell.data(), 4 * (size_t)(n_cu * n_cv))))
         return hip_fail(e, "copy substrings");
     if (n_trk > 0) {
         std::vector<TrackerDev> td((size_t)n_trk);
@@ -1162,9 +1170,9 @@ static pv3d_status define_upload(pv3d_ctx* ctx, Gen& g, const std::vector<Module
         }
         if ((st = ctx->dalloc((void**)&g.trk, sizeof(TrackerDev) * (size_t)n_trk, "trackers"))) return st;
         if ((st = ctx->dalloc((void**)&g.mod_trk, 4 * (size_t)n_mod, "module trackers"))) return st;
-        if ((e = hipMemcpy(g.trk, td.data(), sizeof(TrackerDev) * (size_t)n_trk, hipMemcpyHostToDevice)))
+        if ((e = copy_in(ctx, g.trk, td.data(), sizeof(TrackerDev) * (size_t)n_trk)))
             return hip_fail(e, "copy trackers");
-        if ((e = hipMemcpy(g.mod_trk, module_tracker, 4 * (size_t)n_mod, hipMemcpyHostToDevice)))
+        if ((e = copy_in(ctx, g.mod_trk, module_tracker, 4 * (size_t)n_mod)))
             return hip_fail(e, "copy module trackers");
         g.n_trk = n_trk;
     }
@@ -1234,7 +1242,7 @@ pv3d_status pv3d_generator_set_sky(pv3d_ctx* ctx, uint64_t gen, const double* sv
     if (!svf) return PV3D_OK;
     pv3d_status st;
     if ((st = ctx->dalloc((void**)&g.svf, 8 * (size_t)cells, "sky view factors"))) return st;
-    hipError_t e = hipMemcpy(g.svf, svf, 8 * (size_t)cells, hipMemcpyHostToDevice);
+    hipError_t e = copy_in(ctx, g.svf, svf, 8 * (size_t)cells);
     if (e) {
         ctx->dfree(g.svf);
         g.svf = nullptr;
@@ -1511,7 +1519,10 @@ pv3d_status pv3d_path_stats(pv3d_ctx* ctx, int64_t out[4]) {
     hipError_t e;
     if (ctx->ws_recorded && (e = hipEventSynchronize(ctx->ws_ev))) return hip_fail(e, "wait for the evaluation");
     std::vector<SunCounters> h((size_t)n);
-    if ((e = hipMemcpy(h.data(), ctx->w.ctr.ptr, sizeof(SunCounters) * (size_t)n, hipMemcpyDeviceToHost)))
+    // on the context's own stream: the null stream would also wait for a live serving launch
+    if ((e = hipMemcpyAsync(h.data(), ctx->w.ctr.ptr, sizeof(SunCounters) * (size_t)n, hipMemcpyDeviceToHost,
+                            ctx->stream)) ||
+        (e = hipStreamSynchronize(ctx->stream)))
         return hip_fail(e, "read the sun counters");
     out[0] = n;
     for (const SunCounters& c : h) {

@@ -444,7 +444,9 @@ pv3d_status run_batch(Ctx* c, const pv3d_job* jobs, int64_t n_jobs, hipStream_t 
         // --- suns beyond a slot's capacity: the per-sun path, then the job's energy again
         if (got.n_overflow > 0) {
             std::vector<int32_t> ov(got.n_overflow);
-            if ((e = hipMemcpy(ov.data(), B->overflow.ptr, 4 * ov.size(), hipMemcpyDeviceToHost))) return hip_fail(e, "read overflow list");
+            if ((e = hipMemcpyAsync(ov.data(), B->overflow.ptr, 4 * ov.size(), hipMemcpyDeviceToHost, s)) ||
+                (e = hipStreamSynchronize(s)))
+                return hip_fail(e, "read overflow list");
             std::vector<char> redo((size_t)n_jobs, 0);
             for (int32_t it : ov) {
                 const PItem pi = items[(size_t)it];

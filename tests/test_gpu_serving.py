@@ -222,6 +222,21 @@ def test_serving_after_the_per_sun_path_in_the_same_context(ctx):
     _same(again, first, "per-sun path with the serving loop started")
 
 
+def test_scene_loads_while_a_launch_is_live(ctx, oracle_lib):
+    """Loading a scene and defining a generator while the loop serves a long job return without
+    waiting for the live launch (their copies go on the context's own stream): the job is still
+    running when they return, and both the job and a job on the new scene come out right."""
+    big = W.c2_row_plant()                         # a year of the row plant: a few tenths of a second
+    sp = _spec(ctx, big)
+    t = ctx.submit(sp)
+    small = W.random_tiny(97, n_boxes=6, n_loose=30, n_mod_side=2, map_n=160, k=3, n_sun=4)
+    sp2 = _spec(ctx, small)                        # load_scene and define_generator during the job
+    assert not ctx.poll(t), "the loads waited for the live launch"
+    got = ctx.wait(t)
+    _same(got, _alone(ctx, sp), "served while scenes were loaded")
+    _oracle_same(ctx.wait(ctx.submit(sp2)), small, oracle_lib, "job on the scene loaded mid-run")
+
+
 def test_suns_beyond_slot_capacity_are_evaluated_again(ctx, oracle_lib):
     """Slots of 64 records: the suns of a scene with hundreds of loose triangles overflow them,
     and the host evaluates just those suns again on the per-sun path. Every served result
