@@ -2707,8 +2707,8 @@ __device__ void loss_body(LossLds& L, const double* sun3, const double* beam_s, 
                 const int32_t m = g.str_mods[p0 + q / g.n_sub], sq = q % g.n_sub;
                 const double bm = beam_s[m];
                 double cmin = INFINITY;
-                for (int32_t c = 0; c < cpm; c++) {
-                    if (g.cell_sub[c] != sq) continue;
+                for (int32_t i = g.sub_start[sq]; i < g.sub_start[sq + 1]; i++) {   // the substring's cells
+                    const int32_t c = g.sub_cell[i];
                     const uint32_t sh = pass == 0 ? (COHERENT ? ld_dev(counts_s + (int64_t)m * cpm + c)
                                                               : counts_s[(int64_t)m * cpm + c])
                                                   : 0u;
@@ -2760,16 +2760,33 @@ __global__ __launch_bounds__(256) void k_loss(int64_t s0, const double* sun, con
     }
 }
 
-__global__ void k_energy(int64_t n_sun, const double* power, const double* power_ref, const double* dt,
-                         double* energy) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// The sums over suns, in sun order by one thread; the workgroup stages the
+// arrays in LDS a chunk at a time, so that the sequential sum reads LDS
+// instead of waiting on a global load per sun.
+constexpr int kEnergyChunk = 1024;
+__global__ __launch_bounds__(256) void k_energy(int64_t n_sun, const double* power, const double* power_ref,
+                                                const double* dt, double* energy) {
+    __shared__ double pw[kEnergyChunk], pr[kEnergyChunk], dl[kEnergyChunk];
     double e = 0.0, er = 0.0;
-    for (int64_t t = 0; t < n_sun; t++) {
-        e += power[t] * dt[t];
-        er += power_ref[t] * dt[t];
+    for (int64_t t0 = 0; t0 < n_sun; t0 += kEnergyChunk) {
+        const int32_t m = (int32_t)min<int64_t>(kEnergyChunk, n_sun - t0);
+        for (int32_t i = threadIdx.x; i < m; i += blockDim.x) {
+            pw[i] = power[t0 + i];
+            pr[i] = power_ref[t0 + i];
+            dl[i] = dt[t0 + i];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int32_t i = 0; i < m; i++) {
+                e += pw[i] * dl[i];
+                er += pr[i] * dl[i];
+            }
+        __syncthreads();
     }
-    energy[0] = e;
-    energy[1] = er;
+    if (threadIdx.x == 0) {
+        energy[0] = e;
+        energy[1] = er;
+    }
 }
 
 // Diffuse shading: sky view factor of every cell from the shaded counts of
@@ -3491,7 +3508,7 @@ hipError_t launch_svf(const Module* mods, int32_t cpm, int64_t n_cells, const do
 
 hipError_t launch_energy(int64_t n_sun, const double* power, const double* power_ref, const double* dt,
                          double* energy, hipStream_t st) {
-    hipLaunchKernelGGL(k_energy, dim3(1), dim3(64), 0, st, n_sun, power, power_ref, dt, energy);
+    hipLaunchKernelGGL(k_energy, dim3(1), dim3(256), 0, st, n_sun, power, power_ref, dt, energy);
     return hipGetLastError();
 }
 
