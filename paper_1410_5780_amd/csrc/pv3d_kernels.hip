@@ -2349,14 +2349,26 @@ struct LossLds {
 // in series, and each string works at its maximum power point. One wave per
 // string; lanes take the string's substrings.
 // ---------------------------------------------------------------------------
-constexpr int kDiodeCells = 4096;     // shaded counts of one string staged per wave
+constexpr int kDiodeCells = 2048;     // shaded counts of one string staged per wave
+constexpr int kDiodeLevels = 128;     // slots of the level route's voltage table: two per lane
+constexpr int kDiodeStrings = 512;    // strings per chunk of the single-diode loss
 constexpr int kMppGrid = 64;          // current grid of the maximum power search
 constexpr int kMppRefine = 40;        // golden-section steps around each grid maximum
 
 struct DiodeLds {
-    uint16_t cnt[4][kDiodeCells];     // per wave: its string's counts, module by module, substring-major
-    double spow[kLossStrings];        // string powers of a chunk of strings
+    uint16_t cnt[4][kDiodeCells];     // per wave: its string's counts (level ranks on the level route),
+                                      // module by module, substring-major
+    unsigned long long rk[4][4][64];  // per wave: each lane's cells' level ranks, eight to a word, word-major
+    double vt[4][kDiodeLevels];       // per wave: the level route's voltage table
+    double spow[2][kDiodeStrings];    // shaded and unshaded powers of a chunk of strings
 };
+
+// Orders a wave's LDS stores before its own later loads from other lanes (one
+// wave: no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
 
 // Cell voltage at current I and irradiance G. In the diode voltage x = V + I Rs
 // the equation is f(x) = c - I0 exp(x / a) - x / Rsh = 0 with c = Iph + I0 - I;
@@ -2394,7 +2406,9 @@ struct DiodeString {
     const GenDev* g;
     const double* beam_s;         // per-module beam of the sun
     const uint32_t* counts_s;     // per-cell shaded counts (nullptr: none shaded)
-    const uint16_t* staged;       // the string's counts staged in LDS, or nullptr
+    uint16_t* staged;             // the string's counts staged in LDS, or nullptr
+    unsigned long long* rk;       // the wave's rank words in LDS ([4][64])
+    double* vt;                   // the wave's table of level voltages in LDS
     const double* svf;            // per-cell sky view factors, or nullptr (whole sky)
     double dp, kk;                // diffuse irradiance, samples per cell
     int32_t p0, nq, cpm;          // first module of the string in str_mods, substrings, cells per module
@@ -2440,16 +2454,21 @@ __device__ double sub_voltage(const DiodeString& S, int32_t q, double I) {
 
 // Levels of a string whose cells differ only by their shaded count (one beam
 // for all its modules, no sky view factors, at most 128 counts): the counts
-// present, as a 128-bit mask the whole wave holds, and lane j solving for the
-// j-th of them. A cell then takes its voltage from that lane by a shuffle, so
-// that every level is solved once per current instead of wherever some lane's
-// irradiance changes; the values, and the order in which cells add up, are
-// those of sub_voltage.
+// present, as a 128-bit mask the whole wave holds. The wave's table has 128
+// slots, two per lane (lane and lane + 64); slot s holds the cell voltage of
+// level s % n at the (s / n)-th current of a batch, so that one round of
+// solves serves 128 / n currents, and every level is solved once per current
+// instead of wherever some lane's irradiance changes. Each cell then reads its
+// level's value from the table. The values, and the order in which cells add
+// up, are those of sub_voltage.
 struct Levels {
     unsigned long long m0, m1;    // counts 0..63 and 64..127 present in the string
-    double g;                     // this lane's level irradiance (lane < n)
-    int32_t n, maxc;              // levels; most cells of a substring
-    bool on;
+    double g0, g1;                // irradiances of the lane's two slots' levels
+    int32_t n;                    // levels
+    int32_t c0, c1;               // the lane's two slots' currents within a batch
+    int32_t maxc;                 // most cells of a substring
+    int32_t nc;                   // cells of the lane's substring when ranks are in words (0: none)
+    bool on, words;               // level route; ranks in words (at most 64 substrings of at most 32 cells)
 };
 
 __device__ __forceinline__ int32_t level_rank(const Levels& L, int32_t cn) {
@@ -2457,12 +2476,24 @@ __device__ __forceinline__ int32_t level_rank(const Levels& L, int32_t cn) {
                    : __popcll(L.m0) + __popcll(L.m1 & ((1ull << (cn - 64)) - 1ull));
 }
 
+// The count of level r (r < n): the r-th set bit of the mask.
+__device__ int32_t level_count(const Levels& L, int32_t r) {
+    const int32_t n0 = __popcll(L.m0);
+    unsigned long long m = r < n0 ? L.m0 : L.m1;
+    for (int32_t t = r < n0 ? r : r - n0; t > 0; t--) m &= m - 1ull;
+    return (r < n0 ? 0 : 64) + __builtin_ctzll(m);
+}
+
+// The string's levels. On the level route, staged counts become level ranks
+// (each lane converts the cells of its own substrings, the only ones it reads),
+// and a string of at most 64 substrings of at most 32 cells also packs each
+// lane's ranks into words, so that a lane reads eight cells' ranks at once.
 template <bool COHERENT>
 __device__ void string_levels(const DiodeString& S, int lane, Levels& L) {
     const GenDev& g = *S.g;
-    L.on = false;
-    L.n = 0;
-    L.g = 0.0;
+    L.on = L.words = false;
+    L.n = L.c0 = L.c1 = L.maxc = L.nc = 0;
+    L.g0 = L.g1 = 0.0;
     L.m0 = L.m1 = 0ull;
     if (S.svf || S.kk > 127.5) return;                                  // uniform over the wave
     double bmin = INFINITY, bmax = -INFINITY;
@@ -2488,43 +2519,86 @@ __device__ void string_levels(const DiodeString& S, int lane, Levels& L) {
         L.m1 |= __shfl_xor(L.m1, off, 64);
     }
     L.n = __popcll(L.m0) + __popcll(L.m1);
-    if (!(bmin == bmax) || L.n > 64) return;
-    L.maxc = maxc;
+    if (!(bmin == bmax)) return;
     L.on = true;
-    if (lane < L.n) {                                   // this lane's level: the lane-th count present
-        int32_t cn = -1, seen = -1;
-        for (int32_t c = 0; c < 128 && cn < 0; c++) {
-            const bool present = c < 64 ? ((L.m0 >> c) & 1ull) : ((L.m1 >> (c - 64)) & 1ull);
-            if (present && ++seen == lane) cn = c;
+    L.maxc = maxc;
+    L.c0 = lane / L.n;
+    L.c1 = (lane + 64) / L.n;
+    // as diode_irradiance forms them
+    L.g0 = bmin * (1.0 - (double)level_count(L, lane % L.n) / S.kk) + S.dp * 1.0;
+    L.g1 = bmin * (1.0 - (double)level_count(L, (lane + 64) % L.n) / S.kk) + S.dp * 1.0;
+    if (S.staged)
+        for (int32_t q = lane; q < S.nq; q += 64) {
+            const int32_t mi = q / g.n_sub, sq = q % g.n_sub;
+            for (int32_t i = g.sub_start[sq]; i < g.sub_start[sq + 1]; i++) {
+                uint16_t& c = S.staged[mi * S.cpm + i];
+                c = (uint16_t)level_rank(L, c);
+            }
         }
-        L.g = bmin * (1.0 - (double)cn / S.kk) + S.dp * 1.0;   // as diode_irradiance forms it
+    L.words = S.nq <= 64 && maxc <= 32;
+    if (!L.words || lane >= S.nq) return;
+    const int32_t mi = lane / g.n_sub, sq = lane % g.n_sub;
+    const int32_t m = g.str_mods[S.p0 + mi];
+    const int32_t c0 = g.sub_start[sq];
+    L.nc = g.sub_start[sq + 1] - c0;
+    for (int32_t w = 0; 8 * w < L.nc; w++) {
+        unsigned long long word = 0ull;
+        for (int32_t t = 0; t < 8 && 8 * w + t < L.nc; t++) {
+            const int32_t i = c0 + 8 * w + t;
+            const unsigned long long r = S.staged ? (unsigned long long)S.staged[mi * S.cpm + i]
+                                                  : (unsigned long long)level_rank(L, diode_count<COHERENT>(S, mi, m, i));
+            word |= r << (8 * t);
+        }
+        S.rk[w * 64 + lane] = word;
     }
 }
 
+// The lane's share of the string voltage on the level route, its cells reading
+// the table from slot o on: the sum of its substrings' clamped voltages.
+template <bool COHERENT>
+__device__ __forceinline__ double level_volts(const DiodeString& S, const Levels& L, int32_t lane, int32_t o) {
+    const GenDev& g = *S.g;
+    const double* vt = S.vt + o;
+    if (L.words) {
+        if (L.nc == 0) return 0.0;
+        double vs = 0.0;
+        for (int32_t w = 0; 8 * w < L.nc; w++) {
+            const unsigned long long word = S.rk[w * 64 + lane];
+            double x[8];
+#pragma unroll
+            for (int t = 0; t < 8; t++) x[t] = vt[(word >> (8 * t)) & 0xffull];    // past the end: rank 0
+#pragma unroll
+            for (int t = 0; t < 8; t++) vs = 8 * w + t < L.nc ? vs + x[t] : vs;
+        }
+        return vs < -g.diode.vb ? -g.diode.vb : vs;
+    }
+    double v = 0.0;
+    for (int32_t q = lane; q < S.nq; q += 64) {
+        const int32_t mi = q / g.n_sub, sq = q % g.n_sub;
+        const int32_t m = g.str_mods[S.p0 + mi];
+        double vs = 0.0;
+        for (int32_t i = g.sub_start[sq]; i < g.sub_start[sq + 1]; i++)
+            vs += vt[S.staged ? (int32_t)S.staged[mi * S.cpm + i] : level_rank(L, diode_count<COHERENT>(S, mi, m, i))];
+        vs = vs < -g.diode.vb ? -g.diode.vb : vs;
+        v += vs;
+    }
+    return v;
+}
+
+// String power at current I.
 template <bool COHERENT>
 __device__ double string_power_at(const DiodeString& S, const Levels& L, int lane, double I) {
-    double v = 0.0;
     if (!L.on) {
+        double v = 0.0;
         for (int32_t q = lane; q < S.nq; q += 64) v += sub_voltage<COHERENT>(S, q, I);
         return I * wave_sum(v);
     }
     const GenDev& g = *S.g;
-    const double vl = lane < L.n ? cell_voltage(g.diode, L.g, I) : 0.0;
-    for (int32_t q0 = 0; q0 < S.nq; q0 += 64) {        // uniform: every lane takes part in the shuffles
-        const int32_t q = q0 + lane;
-        const bool act = q < S.nq;
-        const int32_t mi = act ? q / g.n_sub : 0, sq = act ? q % g.n_sub : 0;
-        const int32_t m = act ? g.str_mods[S.p0 + mi] : 0;
-        const int32_t c0 = act ? g.sub_start[sq] : 0, nc = act ? g.sub_start[sq + 1] - c0 : 0;
-        double vs = 0.0;
-        for (int32_t i = 0; i < L.maxc; i++) {
-            const int32_t cn = i < nc ? diode_count<COHERENT>(S, mi, m, c0 + i) : 0;
-            const double vc = __shfl(vl, level_rank(L, cn), 64);
-            if (i < nc) vs += vc;
-        }
-        vs = vs < -g.diode.vb ? -g.diode.vb : vs;
-        if (act) v += vs;
-    }
+    if (lane < L.n) S.vt[lane] = cell_voltage(g.diode, L.g0, I);
+    if (lane + 64 < L.n) S.vt[lane + 64] = cell_voltage(g.diode, L.g1, I);
+    wave_lds_sync();
+    const double v = level_volts<COHERENT>(S, L, lane, 0);
+    wave_lds_sync();                                  // the table is rewritten at the next current
     return I * wave_sum(v);
 }
 
@@ -2532,9 +2606,13 @@ __device__ double string_power_at(const DiodeString& S, const Levels& L, int lan
 // photocurrent: the power at kMppGrid + 1 evenly spaced currents, then a
 // golden-section search over the two grid steps around every sample that is
 // not below its neighbours; the largest value seen, at least 0. Every lane
-// holds the same powers, so the search's branches are uniform.
+// holds the same powers, so the search's branches are uniform. The grid powers
+// come first (in batches on the level route), lane j keeping the j-th; the
+// largest value seen does not depend on the order in which values are seen. A
+// string on the level route whose only count is 0 has the inputs of its
+// unshaded self: with that power known (has_clear), the search returns it.
 template <bool COHERENT>
-__device__ double string_mpp_wave(const DiodeString& S, int lane) {
+__device__ double string_mpp_wave(const DiodeString& S, int lane, bool has_clear, double clear) {
     const GenDev& g = *S.g;
     const DiodeDev& d = g.diode;
     double imax = 0.0;
@@ -2551,116 +2629,147 @@ __device__ double string_mpp_wave(const DiodeString& S, int lane) {
     if (!(imax > 0.0)) return 0.0;
     Levels L;
     string_levels<COHERENT>(S, lane, L);
+    if (has_clear && L.on && L.n == 1 && L.m0 == 1ull) return clear;
+    // grid powers: lane j holds the power at current j Imax / kMppGrid (j < kMppGrid), gtop at Imax
+    double gp = 0.0, gtop = 0.0;
+    if (L.on) {
+        const int32_t per = min(kMppGrid + 1, kDiodeLevels / L.n);     // currents per round of solves
+        for (int32_t base = 0; base <= kMppGrid; base += per) {
+            const int32_t nb = min(per, kMppGrid + 1 - base);
+            if (L.c0 < nb) S.vt[lane] = cell_voltage(d, L.g0, imax * (double)(base + L.c0) / (double)kMppGrid);
+            if (L.c1 < nb) S.vt[lane + 64] = cell_voltage(d, L.g1, imax * (double)(base + L.c1) / (double)kMppGrid);
+            wave_lds_sync();
+            for (int32_t c = 0; c < nb; c++) {
+                const int32_t q = base + c;
+                const double p = imax * (double)q / (double)kMppGrid * wave_sum(level_volts<COHERENT>(S, L, lane, c * L.n));
+                if (q == lane) gp = p;
+                if (q == kMppGrid) gtop = p;
+            }
+            wave_lds_sync();
+        }
+    } else {
+        for (int32_t q = 0; q <= kMppGrid; q++) {
+            const double p = string_power_at<COHERENT>(S, L, lane, imax * (double)q / (double)kMppGrid);
+            if (q == lane) gp = p;
+            if (q == kMppGrid) gtop = p;
+        }
+    }
     const double r = 0.6180339887498949;       // (sqrt(5) - 1) / 2
     double best = 0.0;
-    double pm = string_power_at<COHERENT>(S, L, lane, imax * 0.0 / (double)kMppGrid);
-    double pc = string_power_at<COHERENT>(S, L, lane, imax * 1.0 / (double)kMppGrid);
     for (int q = 1; q <= kMppGrid; q++) {
-        const double pn = q < kMppGrid ? string_power_at<COHERENT>(S, L, lane, imax * (double)(q + 1) / (double)kMppGrid)
-                                       : 0.0;
+        const double pm = __shfl(gp, q - 1, 64);
+        const double pc = q < kMppGrid ? __shfl(gp, q, 64) : gtop;
+        const double pn = q < kMppGrid - 1 ? __shfl(gp, q + 1, 64) : gtop;
         if (pc >= pm && (q == kMppGrid || pc >= pn)) {
             if (pc > best) best = pc;
             double lo = imax * (double)(q - 1) / (double)kMppGrid;
             double hi = imax * (double)(q < kMppGrid ? q + 1 : q) / (double)kMppGrid;
             double xc = hi - r * (hi - lo), xd = lo + r * (hi - lo);
-            double fc = string_power_at<COHERENT>(S, L, lane, xc), fd = string_power_at<COHERENT>(S, L, lane, xd);
-            if (fc > best) best = fc;
-            if (fd > best) best = fd;
-            for (int it = 0; it < kMppRefine; it++) {
-                if (fc >= fd) {
+            double fc = 0.0, fd = 0.0;
+            // the two inner points, then kMppRefine steps, each evaluating the point it moves
+            for (int it = -2; it < kMppRefine; it++) {
+                bool left;
+                double x;
+                if (it == -2) {
+                    x = xc; left = true;
+                } else if (it == -1) {
+                    x = xd; left = false;
+                } else if (fc >= fd) {
                     hi = xd; xd = xc; fd = fc;
                     xc = hi - r * (hi - lo);
-                    fc = string_power_at<COHERENT>(S, L, lane, xc);
-                    if (fc > best) best = fc;
+                    x = xc; left = true;
                 } else {
                     lo = xc; xc = xd; fc = fd;
                     xd = lo + r * (hi - lo);
-                    fd = string_power_at<COHERENT>(S, L, lane, xd);
-                    if (fd > best) best = fd;
+                    x = xd; left = false;
                 }
+                const double f = string_power_at<COHERENT>(S, L, lane, x);
+                if (left) fc = f;
+                else fd = f;
+                if (f > best) best = f;
             }
         }
-        pm = pc;
-        pc = pn;
     }
     return best;
 }
 
-// One sun with the single-diode model: the shaded powers, then the unshaded
-// reference; per pass, strings in chunks of kLossStrings, a wave per string,
-// the string powers added in string order.
+// One sun with the single-diode model: strings in chunks of kDiodeStrings, a
+// wave per string for its unshaded power (the reference) and then its shaded
+// power, the powers of each kind added in string order. The unshaded power of
+// a string whose modules share one beam depends only on its module count and
+// that beam: the wave reuses its previous such string's power when both match
+// (the same inputs to the same computation, so the same value).
 template <bool COHERENT>
 __device__ void diode_loss_body(DiodeLds& L, const double* beam_s, const uint32_t* counts_s, double dp,
                                 const GenDev& g, int32_t k, double* power_s, double* power_ref_s) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int32_t cpm = g.n_cu * g.n_cv;
     double tot[2] = {0.0, 0.0};
-    int32_t ref_nm = -1;                      // the wave's last unshaded string: modules, beam, power
+    int32_t ref_nm = -1;                      // the wave's last uniform-beam string: modules, beam, power
     double ref_bm = 0.0, ref_p = 0.0;
-    for (int pass = 0; pass < 2; pass++) {
-        for (int32_t st0 = 0; st0 < g.n_str; st0 += kLossStrings) {
-            const int32_t st1 = min(g.n_str, st0 + kLossStrings);
-            for (int32_t st = st0 + wv; st < st1; st += 4) {
-                DiodeString S;
-                S.g = &g;
-                S.beam_s = beam_s;
-                S.counts_s = pass == 0 ? counts_s : nullptr;
-                S.staged = nullptr;
-                S.svf = pass == 0 ? g.svf : nullptr;
-                S.dp = dp;
-                S.kk = (double)(k * k);
-                S.p0 = g.str_start[st];
-                S.cpm = cpm;
-                const int32_t nm = g.str_start[st + 1] - S.p0;
-                S.nq = nm * g.n_sub;
-                if (pass == 0 && nm * cpm <= kDiodeCells) {
-                    // each lane stages the cells of its own substrings, and reads only those
-                    uint16_t* dst = L.cnt[wv];
-                    for (int32_t q = lane; q < S.nq; q += 64) {
-                        const int32_t mi = q / g.n_sub, sq = q % g.n_sub;
-                        const int32_t m = g.str_mods[S.p0 + mi];
-                        for (int32_t i = g.sub_start[sq]; i < g.sub_start[sq + 1]; i++)
-                            dst[mi * cpm + i] = (uint16_t)diode_count<COHERENT>(S, mi, m, i);
-                    }
-                    S.staged = dst;
-                }
-                // Unshaded (the reference pass), a string whose modules share one beam has a
-                // power that depends only on its module count and that beam: the wave reuses
-                // the power of its previous such string when both match (the same inputs to
-                // the same computation, so the same value).
-                double p;
-                bool reuse = false, uni = false;
-                double bmin = INFINITY, bmax = -INFINITY;
-                if (pass == 1) {
-                    for (int32_t mi = lane; mi < nm; mi += 64) {
-                        const double bm = beam_s[g.str_mods[S.p0 + mi]];
-                        bmin = fmin(bmin, bm);
-                        bmax = fmax(bmax, bm);
-                    }
-                    for (int off = 32; off > 0; off >>= 1) {
-                        bmin = fmin(bmin, __shfl_xor(bmin, off, 64));
-                        bmax = fmax(bmax, __shfl_xor(bmax, off, 64));
-                    }
-                    uni = bmin == bmax;
-                    reuse = uni && nm == ref_nm && bmin == ref_bm;
-                }
-                if (reuse) {
-                    p = ref_p;
-                } else {
-                    p = string_mpp_wave<COHERENT>(S, lane);
-                    if (pass == 1) {
-                        ref_nm = uni ? nm : -1;
-                        ref_bm = bmin;
-                        ref_p = p;
-                    }
-                }
-                if (lane == 0) L.spow[st - st0] = p;
+    for (int32_t st0 = 0; st0 < g.n_str; st0 += kDiodeStrings) {
+        const int32_t st1 = min(g.n_str, st0 + kDiodeStrings);
+        for (int32_t st = st0 + wv; st < st1; st += 4) {
+            DiodeString S;
+            S.g = &g;
+            S.beam_s = beam_s;
+            S.counts_s = nullptr;
+            S.staged = nullptr;
+            S.rk = &L.rk[wv][0][0];
+            S.vt = L.vt[wv];
+            S.svf = nullptr;
+            S.dp = dp;
+            S.kk = (double)(k * k);
+            S.p0 = g.str_start[st];
+            S.cpm = cpm;
+            const int32_t nm = g.str_start[st + 1] - S.p0;
+            S.nq = nm * g.n_sub;
+            double bmin = INFINITY, bmax = -INFINITY;
+            for (int32_t mi = lane; mi < nm; mi += 64) {
+                const double bm = beam_s[g.str_mods[S.p0 + mi]];
+                bmin = fmin(bmin, bm);
+                bmax = fmax(bmax, bm);
             }
-            __syncthreads();
-            if (tid == 0)
-                for (int32_t st = st0; st < st1; st++) tot[pass] += L.spow[st - st0];
-            __syncthreads();
+            for (int off = 32; off > 0; off >>= 1) {
+                bmin = fmin(bmin, __shfl_xor(bmin, off, 64));
+                bmax = fmax(bmax, __shfl_xor(bmax, off, 64));
+            }
+            const bool uni = bmin == bmax;
+            double pu;
+            if (uni && nm == ref_nm && bmin == ref_bm) {
+                pu = ref_p;
+            } else {
+                pu = string_mpp_wave<COHERENT>(S, lane, false, 0.0);
+                ref_nm = uni ? nm : -1;
+                ref_bm = bmin;
+                ref_p = pu;
+            }
+            S.counts_s = counts_s;
+            S.svf = g.svf;
+            if (nm * cpm <= kDiodeCells) {
+                // each lane stages the cells of its own substrings, and reads only those
+                uint16_t* dst = L.cnt[wv];
+                for (int32_t q = lane; q < S.nq; q += 64) {
+                    const int32_t mi = q / g.n_sub, sq = q % g.n_sub;
+                    const int32_t m = g.str_mods[S.p0 + mi];
+                    for (int32_t i = g.sub_start[sq]; i < g.sub_start[sq + 1]; i++)
+                        dst[mi * cpm + i] = (uint16_t)diode_count<COHERENT>(S, mi, m, i);
+                }
+                S.staged = dst;
+            }
+            const double ps = string_mpp_wave<COHERENT>(S, lane, true, pu);
+            if (lane == 0) {
+                L.spow[0][st - st0] = ps;
+                L.spow[1][st - st0] = pu;
+            }
         }
+        __syncthreads();
+        if (tid == 0)
+            for (int32_t st = st0; st < st1; st++) {
+                tot[0] += L.spow[0][st - st0];
+                tot[1] += L.spow[1][st - st0];
+            }
+        __syncthreads();
     }
     if (tid == 0) {
         *power_s = tot[0];
@@ -2747,7 +2856,7 @@ __device__ void loss_body(LossLds& L, const double* sun3, const double* beam_s, 
 // A sun whose set-up records or bin entries overflowed their buffers (never
 // with the per-sun path's capacities; a guard all the same) reads NaN powers,
 // so a caller of the asynchronous form sees it without a host round trip.
-__global__ __launch_bounds__(256) void k_loss(int64_t s0, const double* sun, const double* beam,
+__global__ __launch_bounds__(256, 3) void k_loss(int64_t s0, const double* sun, const double* beam,
                                               const uint32_t* counts, const double* d_poa, GenDev g, int32_t k,
                                               double* power, double* power_ref, const SunCounters* ctr) {
     __shared__ LossLds L;
