@@ -451,6 +451,18 @@ __device__ __forceinline__ int32_t lanes_below(unsigned long long bal) {
     return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
 }
 
+// Relaxed device-scope atomics on device memory (the count and flag arrays),
+// issued as global rather than flat instructions: a flat access may address
+// LDS, so it also holds the LDS counter, and the next wait for an LDS result
+// (a shuffle, a staged triangle) would wait for the atomic's round trip.
+typedef __attribute__((address_space(1))) uint32_t global_u32;
+__device__ __forceinline__ void dev_add(uint32_t* p, uint32_t v) {
+    __hip_atomic_fetch_add((global_u32*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void dev_or(uint32_t* p, uint32_t v) {
+    __hip_atomic_fetch_or((global_u32*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Last index i in [0, n) with key(a[i]) <= x, for keys that do not decrease
 // and key(a[0]) <= x.
 template <int SHIFT>
@@ -1133,9 +1145,19 @@ struct TileCtx {
     int32_t x0, y0, n, bs, be, n_large;
     const TriRec* lrec;     // the first n_lrec records of the large list, kept in LDS
     int32_t n_lrec;
-    const double* fu_l;     // sample fractions along edge_u and edge_v (LDS copies when they fit)
-    const double* fv_l;
+    const double* ftab;     // sample fractions, k n_cu along edge_u then k n_cv along edge_v, in LDS (when lds)
+    const double* fu_g;     // the same fractions in device memory
+    const double* fv_g;
+    int32_t knu;
+    bool lds;
 };
+
+// A sample's fractions along edge_u and edge_v. The two sources are read on
+// separate branches, so that each load keeps its own address space.
+__device__ __forceinline__ double frac_u(const TileCtx& c, int32_t qa) { return c.lds ? c.ftab[qa] : c.fu_g[qa]; }
+__device__ __forceinline__ double frac_v(const TileCtx& c, int32_t qb) {
+    return c.lds ? c.ftab[c.knu + qb] : c.fv_g[qb];
+}
 
 // Sample fractions (k n_cu along edge_u, then k n_cv along edge_v) a workgroup
 // of the group tile kernel keeps in LDS when they fit.
@@ -1453,10 +1475,10 @@ __device__ void samples_full(const uint32_t* zt, const int32_t* mods, int32_t nm
                     const int32_t cu = qa / k, cv = qb / k;
                     const int32_t cell = cv * g.n_cu + cu;
                     if (lds_cells) atomicAdd(&cc[cell], 1u);
-                    else atomicAdd(&out.counts[(int64_t)m * cpm + cell], 1u);
+                    else dev_add(&out.counts[(int64_t)m * cpm + cell], 1u);
                     if (out.bits) {
                         const int32_t si = (qb - cv * k) * k + (qa - cu * k);
-                        atomicOr(&out.bits[((int64_t)m * cpm + cell) * words + si / 32], 1u << (si % 32));
+                        dev_or(&out.bits[((int64_t)m * cpm + cell) * words + si / 32], 1u << (si % 32));
                     }
                 }
             }
@@ -1466,7 +1488,7 @@ __device__ void samples_full(const uint32_t* zt, const int32_t* mods, int32_t nm
         if (lds_cells)
             for (int32_t q = lane; q < cpm; q += 64) {
                 const uint32_t v = cc[q];
-                if (v) atomicAdd(&out.counts[(int64_t)m * cpm + q], v);
+                if (v) dev_add(&out.counts[(int64_t)m * cpm + q], v);
             }
         __builtin_amdgcn_wave_barrier();
     }
@@ -1527,8 +1549,6 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
                             const TileOut& out, const TileCtx& c, int tid, int lane, int wv) {
     const int32_t cpm = g.n_cu * g.n_cv;
     const int32_t knu = k * g.n_cu, knv = k * g.n_cv;
-    const double* const fu_l = c.fu_l;
-    const double* const fv_l = c.fv_l;
     double xl, xh, yl, yh;
     rect_bounds(r, c.n, xl, xh, yl, yh);
     if (tid == 0) { sh.n_ent = 0; sh.ent_overflow = 0; sh.max_thr = INT32_MIN; sh.next = 0; }
@@ -1584,7 +1604,7 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
             ModMap mm;
             if (mi < kMapCache) mm = mcache[mi];
             else module_map(V, g.mods[mods[mi]], mm);
-            const double fv = fv_l[qb];                      // the sample's fraction along edge_v
+            const double fv = frac_v(c, qb);                 // the sample's fraction along edge_v
             int32_t qa0, qa1;
             col_range(mm, fv, knu, xl, xh, yl, yh, qa0, qa1);
             cnt = qa0 <= qa1 ? qa1 - qa0 + 1 : 0;
@@ -1612,8 +1632,8 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
                 const int32_t bm = mbias[mi];
                 if (mi < kMapCache) mm = mcache[mi];
                 else module_map(V, g.mods[mods[mi]], mm);
-                const double fv = fv_l[qb];
-                const double fu = fu_l[qa];                      // the sample's fraction along edge_u
+                const double fv = frac_v(c, qb);
+                const double fu = frac_u(c, qa);                 // the sample's fraction along edge_u
                 int32_t zs;
                 ok = sample_in_rect(mm, fu, fv, r, c.n, &li, &lj, &zs);
                 if (ok) {
@@ -1810,17 +1830,17 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
         const int32_t cu = qa / k, cv = qb / k, cell = cv * g.n_cu + cu;
         const int32_t m = mods[slot];
         if (lds_cells) atomicAdd(&cells[slot * cpm + cell], 1u);
-        else atomicAdd(&out.counts[(int64_t)m * cpm + cell], 1u);
+        else dev_add(&out.counts[(int64_t)m * cpm + cell], 1u);
         if (out.bits) {
             const int32_t si = (qb - cv * k) * k + (qa - cu * k);
-            atomicOr(&out.bits[((int64_t)m * cpm + cell) * words + si / 32], 1u << (si % 32));
+            dev_or(&out.bits[((int64_t)m * cpm + cell) * words + si / 32], 1u << (si % 32));
         }
     }
     __syncthreads();
     if (lds_cells)
         for (int32_t q = tid; q < n_mods * cpm; q += 256) {
             const uint32_t v = cells[q];
-            if (v) atomicAdd(&out.counts[(int64_t)mods[q / cpm] * cpm + q % cpm], v);
+            if (v) dev_add(&out.counts[(int64_t)mods[q / cpm] * cpm + q % cpm], v);
         }
     __syncthreads();
     return true;
@@ -1902,8 +1922,11 @@ __device__ __attribute__((always_inline)) void tile_body(TileLds<TS, CAP>& L, in
     c.n_large = n_large;
     c.lrec = L.lcache;
     c.n_lrec = n_lcache;
-    c.fu_l = lds_tables ? L.ftab : fu_tab;
-    c.fv_l = lds_tables ? L.ftab + k * g.n_cu : fv_tab;
+    c.ftab = L.ftab;
+    c.fu_g = fu_tab;
+    c.fv_g = fv_tab;
+    c.knu = k * g.n_cu;
+    c.lds = lds_tables;
     if (tid == 0) { next = 0; n_mods = 0; mods_overflow = 0; n_todo = 0; n_failed = 0; }
     __syncthreads();
     for (int32_t q = c.bs + tid; q < c.be; q += 256) {   // module entries of this tile
@@ -1995,6 +2018,9 @@ __device__ __attribute__((always_inline)) void tile_body(TileLds<TS, CAP>& L, in
 // the test itself are those of the workgroup route, so every count is the
 // same; only the order of the work differs.
 // ---------------------------------------------------------------------------
+
+// DPP control of a move from lane i - 1 to lane i across the whole wave (wave_shr:1).
+constexpr int kDppWaveShr1 = 0x138;
 
 // Inclusive prefix sum over the lanes of a wave.
 __device__ __forceinline__ int32_t wave_incl(int32_t x, int lane) {
@@ -2140,7 +2166,7 @@ __device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const Bin
                 cnt = qa0 <= qa1 ? qa1 - qa0 + 1 : 0;
             }
             const int32_t incl = wave_incl(cnt, lane);
-            const int32_t total = __shfl(incl, 63, 64);
+            const int32_t total = __builtin_amdgcn_readlane(incl, 63);
             for (int32_t c0 = 0; c0 < total; c0 += 64) {
                 const int32_t ci = c0 + lane;
                 const int32_t row = wave_count_le(incl, ci);
@@ -2180,18 +2206,18 @@ __device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const Bin
                 // lane of each such run adds the run's shaded samples in one atomic
                 const int32_t cu = qa / k, cv = qb / k;
                 const int32_t key = live ? cv * g.n_cu + cu : -1 - lane;
-                const int32_t below = __shfl_up(key, 1, 64);
+                const int32_t below = __builtin_amdgcn_update_dpp(0, key, kDppWaveShr1, 0xf, 0xf, false);   // lane - 1's key
                 const bool head = lane == 0 || key != below;
                 const unsigned long long heads = __ballot(head), shaded_lanes = __ballot(shaded);
                 if (head && live) {
                     const unsigned long long above = lane == 63 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
                     const unsigned long long run = (above & (~above + 1ull)) - (1ull << lane);   // lanes [lane, next head)
                     const uint32_t n_shaded = (uint32_t)__popcll(shaded_lanes & run);
-                    if (n_shaded) atomicAdd(&out.counts[(int64_t)m * cpm + key], n_shaded);
+                    if (n_shaded) dev_add(&out.counts[(int64_t)m * cpm + key], n_shaded);
                 }
                 if (shaded && out.bits) {
                     const int32_t si = (qb - cv * k) * k + (qa - cu * k);
-                    atomicOr(&out.bits[((int64_t)m * cpm + key) * words + si / 32], 1u << (si % 32));
+                    dev_or(&out.bits[((int64_t)m * cpm + key) * words + si / 32], 1u << (si % 32));
                 }
             }
         }
@@ -2232,8 +2258,9 @@ __global__ __launch_bounds__(256, 3) void k_tile_g(const SunGroup* __restrict__ 
             reinterpret_cast<uint4*>(L.lcache)[u] =
                 reinterpret_cast<const uint4*>(S.bb.rec + S.bb.large[u / kPieces])[u % kPieces];
         __syncthreads();
-        // light tiles (the list's tail) go one wave each when their large list is in LDS
-        const int32_t light = (TS == 64 && n_large <= kLargeCache) ? S.bb.list_ctr[2] : n_items;
+        // light tiles (the list's tail) go one wave each when their large list and the sample
+        // fractions are in LDS
+        const int32_t light = (TS == 64 && n_large <= kLargeCache && lds_tables) ? S.bb.list_ctr[2] : n_items;
         for (;;) {
             if (threadIdx.x == 0) take = atomicAdd(&S.bb.list_ctr[1], 1);
             __syncthreads();
@@ -2249,8 +2276,6 @@ __global__ __launch_bounds__(256, 3) void k_tile_g(const SunGroup* __restrict__ 
             // from here on every wave takes its own light tiles; wave 0 starts with `it`
             const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
             TriSlot* slots = reinterpret_cast<TriSlot*>(L.pool) + wv * kWaveSlots;
-            const double* fu_l = lds_tables ? L.ftab : fu_tab;
-            const double* fv_l = lds_tables ? L.ftab + knu : fv_tab;
             int32_t my = it;
             if (wv != 0) {
                 int32_t got = 0;
@@ -2260,7 +2285,7 @@ __global__ __launch_bounds__(256, 3) void k_tile_g(const SunGroup* __restrict__ 
             if constexpr (TS == 64) {
                 while (my < n_items) {
                     wave_tile<TS>(slots, S.bb.tile_list[my] >> 3, views[S.s], S.bb, L.lcache, n_large, n, S.g,
-                                  bias + S.s * S.g.n_mod, fu_l, fv_l, k, S.out, S.tmask, lane);
+                                  bias + S.s * S.g.n_mod, L.ftab, L.ftab + knu, k, S.out, S.tmask, lane);
                     int32_t got = 0;
                     if (lane == 0) got = atomicAdd(&S.bb.list_ctr[1], 1);
                     my = __builtin_amdgcn_readfirstlane(got);
