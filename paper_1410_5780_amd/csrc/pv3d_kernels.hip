@@ -451,6 +451,19 @@ __device__ __forceinline__ int32_t lanes_below(unsigned long long bal) {
     return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
 }
 
+// floor(q / k) for 0 <= q < 2^32 / k: the high word of q m with m = ceil(2^32 / k).
+// With m = (2^32 + e) / k, 0 <= e < k, the product carries an excess of q e / 2^32 < 1
+// over q / k, too little to reach the next integer (k = 1: m = 0 marks the identity).
+struct DivK {
+    uint32_t m;
+};
+__device__ __forceinline__ DivK div_by(int32_t k) {
+    return DivK{k > 1 ? (uint32_t)((0x100000000ull + (unsigned long long)(k - 1)) / (unsigned long long)k) : 0u};
+}
+__device__ __forceinline__ int32_t div_k(DivK d, int32_t q) {
+    return d.m ? (int32_t)__umulhi((uint32_t)q, d.m) : q;
+}
+
 // Relaxed device-scope atomics on device memory (the count and flag arrays),
 // issued as global rather than flat instructions: a flat access may address
 // LDS, so it also holds the LDS counter, and the next wait for an LDS result
@@ -1823,11 +1836,13 @@ __device__ bool sparse_rect(const Rect& r, SparseLds& sp, SparseShared& sh, TriB
         for (int32_t q = tid; q < n_mods * cpm; q += 256) cells[q] = 0;
     __syncthreads();
     const int32_t words = (k * k + 31) / 32;
+    const DivK dk = div_by(k);
+    const int32_t n_cu = g.n_cu;
     for (int32_t e = tid; e < ne; e += 256) {
         if (!(sp.texel[e] & kShadedBit)) continue;
         const uint32_t code = sp.code[e];
         const int32_t slot = (int32_t)(code >> 24), qb = (int32_t)((code >> 12) & 0xFFF), qa = (int32_t)(code & 0xFFF);
-        const int32_t cu = qa / k, cv = qb / k, cell = cv * g.n_cu + cu;
+        const int32_t cu = div_k(dk, qa), cv = div_k(dk, qb), cell = cv * n_cu + cu;
         const int32_t m = mods[slot];
         if (lds_cells) atomicAdd(&cells[slot * cpm + cell], 1u);
         else dev_add(&out.counts[(int64_t)m * cpm + cell], 1u);
@@ -2140,10 +2155,15 @@ __device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const Bin
             }
         }
     }
-    // the samples of each module, 64 at a time
-    const int32_t cpm = g.n_cu * g.n_cv;
-    const int32_t knu = k * g.n_cu, knv = k * g.n_cv;
+    // the samples of each module, 64 at a time (fields read once: stores through the output
+    // pointers may alias them as far as the compiler knows)
+    const int32_t n_cu = g.n_cu;
+    const int32_t cpm = n_cu * g.n_cv;
+    const int32_t knu = k * n_cu, knv = k * g.n_cv;
     const int32_t words = (k * k + 31) / 32;
+    const DivK dk = div_by(k);
+    uint32_t* const counts = out.counts;
+    uint32_t* const bits = out.bits;
     double xl, xh, yl, yh;
     rect_bounds(r, n, xl, xh, yl, yh);
     unsigned long long todo = mb;
@@ -2204,8 +2224,8 @@ __device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const Bin
                 }
                 // the candidates of one cell lie on consecutive lanes (up to k of a row): the first
                 // lane of each such run adds the run's shaded samples in one atomic
-                const int32_t cu = qa / k, cv = qb / k;
-                const int32_t key = live ? cv * g.n_cu + cu : -1 - lane;
+                const int32_t cu = div_k(dk, qa), cv = div_k(dk, qb);
+                const int32_t key = live ? cv * n_cu + cu : -1 - lane;
                 const int32_t below = __builtin_amdgcn_update_dpp(0, key, kDppWaveShr1, 0xf, 0xf, false);   // lane - 1's key
                 const bool head = lane == 0 || key != below;
                 const unsigned long long heads = __ballot(head), shaded_lanes = __ballot(shaded);
@@ -2213,11 +2233,11 @@ __device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const Bin
                     const unsigned long long above = lane == 63 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
                     const unsigned long long run = (above & (~above + 1ull)) - (1ull << lane);   // lanes [lane, next head)
                     const uint32_t n_shaded = (uint32_t)__popcll(shaded_lanes & run);
-                    if (n_shaded) dev_add(&out.counts[(int64_t)m * cpm + key], n_shaded);
+                    if (n_shaded) dev_add(&counts[(int64_t)m * cpm + key], n_shaded);
                 }
-                if (shaded && out.bits) {
+                if (shaded && bits) {
                     const int32_t si = (qb - cv * k) * k + (qa - cu * k);
-                    dev_or(&out.bits[((int64_t)m * cpm + key) * words + si / 32], 1u << (si % 32));
+                    dev_or(&bits[((int64_t)m * cpm + key) * words + si / 32], 1u << (si % 32));
                 }
             }
         }
