@@ -632,7 +632,7 @@ __device__ void reserve_pair_items(unsigned long long* lds, const BinBuffers& bb
     if (c > 0) put_pair_item(bb, ctr, at, c, id, box);
 }
 
-__device__ __noinline__ void clip_and_emit(d3 t0, d3 t1, d3 t2, int32_t n, BinBuffers bb, SunCounters* ctr,
+__device__ __noinline__ void clip_and_emit(d3 t0, d3 t1, d3 t2, int32_t n, const BinBuffers& bb, SunCounters* ctr,
                                            uint32_t* cnt, const uint32_t* mask) {
     d3 a[8], b[8];
     a[0] = t0; a[1] = t1; a[2] = t2;
@@ -1244,6 +1244,7 @@ __device__ __forceinline__ void module_map(const View& V, const Module& M, ModMa
     mm.dv = d3{dot(W, e1) * V.itx, dot(W, e2) * V.ity, dot(W, dd) * V.izd};
 }
 
+
 // Light-space extent of a rect for sample selection: texels clamp to the map,
 // so at a map border the rect reaches to infinity.
 __device__ __forceinline__ void rect_bounds(const Rect& r, int32_t n, double& xl, double& xh, double& yl, double& yh) {
@@ -1540,6 +1541,56 @@ struct TriSlot {
     int64_t zx, gx, gy;
     uint32_t box, pad;
 };
+
+// A module's plane in light space, P(x, y) = z0 + a (x - x0) + b (y - y0) (x, y
+// in texels, P in depth units), the plane its samples lie on, with the margin
+// lim by which a slot's depth must exceed P for the slot to shade none of the
+// module's samples. A sample s is tested at the centre c of its texel (|s - c|
+// <= 1/2 in x and in y), so its depth z is at most P(c) + (|a| + |b|) / 2. A
+// slot's depth there is floor(Q(c)) for its exact affine Q (clamped to [0,
+// 2^24 - 1]: the clamp at 0 only raises it, and no sample depth exceeds the
+// other end). The sample is lit, floor(z) - bias <= floor(Q(c)), whenever
+// z - bias < Q(c), which holds when Q(c) - P(c) > (|a| + |b|) / 2 - bias + e,
+// e the rounding of z and of P here. lim adds 0.01 plus a bound of that
+// rounding; a bias at the cap leaves every sample lit. A module seen too nearly
+// edge-on for a well-conditioned solve drops nothing (ok = false).
+struct ModPlane {
+    double x0, y0, z0, a, b, lim;
+    bool ok, lit;
+};
+
+__device__ __forceinline__ ModPlane mod_plane(const ModMap& mm, int32_t bias, int32_t n) {
+    ModPlane P;
+    const double det = mm.du.x * mm.dv.y - mm.du.y * mm.dv.x;
+    const double scale = (fabs(mm.du.x) + fabs(mm.du.y)) * (fabs(mm.dv.x) + fabs(mm.dv.y));
+    P.a = (mm.du.z * mm.dv.y - mm.dv.z * mm.du.y) / det;
+    P.b = (mm.dv.z * mm.du.x - mm.du.z * mm.dv.x) / det;
+    P.x0 = mm.p0.x;
+    P.y0 = mm.p0.y;
+    P.z0 = mm.p0.z;
+    const double big = fabs(mm.p0.z) + (fabs(P.a) + fabs(P.b)) * (2.0 * (double)n + fabs(mm.p0.x) + fabs(mm.p0.y));
+    P.lim = 0.5 * (fabs(P.a) + fabs(P.b)) - (double)bias + 0.01 + 1e-9 * big;
+    P.ok = fabs(det) >= 1e-5 * scale && isfinite(P.lim);
+    P.lit = bias >= (int32_t)kDepthMax;
+    return P;
+}
+
+// True when slot T shades no sample of the module: over the slot's texel box in
+// the rect, where Q - P is smallest at a corner (both are affine), Q - P >= lim.
+__device__ __forceinline__ bool slot_behind(const TriSlot& T, const ModPlane& P, const Rect& r) {
+    if (P.lit) return true;
+    if (!P.ok) return false;
+    const uint32_t bx = T.box;
+    double dmin = INFINITY;
+    for (int q = 0; q < 4; q++) {
+        const int32_t li = (q & 1) ? (int32_t)((bx >> 8) & 255u) : (int32_t)(bx & 255u);
+        const int32_t lj = (q & 2) ? (int32_t)(bx >> 24) : (int32_t)((bx >> 16) & 255u);
+        const double Q = (double)(T.zx + T.gx * li + T.gy * lj) / 65536.0;     // exact: below 2^53
+        const double Pc = P.z0 + P.a * ((double)(r.x + li) + 0.5 - P.x0) + P.b * ((double)(r.y + lj) + 0.5 - P.y0);
+        dmin = fmin(dmin, Q - Pc);
+    }
+    return dmin >= P.lim;
+}
 
 constexpr int kTriChunk = 64;     // triangles staged in LDS at a time
 constexpr int kStampList = 48;    // triangle slots listed per 8x8 stamp (even: the test reads them in pairs)
@@ -2177,6 +2228,11 @@ __device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const Bin
         module_map(V, g.mods[m], mm);
         int32_t qb0, qb1;
         row_range(mm, knv, xl, xh, yl, yh, qb0, qb1);
+        // the slots that lie far enough behind the module's plane over their box to shade none of its
+        // samples (its own triangles, a roof under it): its samples leave them out
+        const ModPlane mp = mod_plane(mm, bm, n);
+        const unsigned long long own0 = __ballot(lane < ns && slot_behind(slots[lane], mp, r));
+        const unsigned long long own1 = __ballot(lane + 64 < ns && slot_behind(slots[lane + 64], mp, r));
         for (int32_t rb = qb0; rb <= qb1; rb += 64) {
             const int32_t qb_l = rb + lane;
             int32_t qa0 = 0, cnt = 0;
@@ -2203,7 +2259,7 @@ __device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const Bin
                 }
                 // the slots of the sample's stamp (every lane takes part in the shuffles)
                 const int32_t st = (lj >> 3) * 8 + (li >> 3);
-                unsigned long long m0 = __shfl(sm0, st, 64), m1 = __shfl(sm1, st, 64);
+                unsigned long long m0 = __shfl(sm0, st, 64) & ~own0, m1 = __shfl(sm1, st, 64) & ~own1;
                 if (!live) m0 = m1 = 0ull;
                 bool shaded = false;
                 const int32_t li256 = li * 256, lj256 = lj * 256;

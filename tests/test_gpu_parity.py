@@ -136,6 +136,43 @@ def test_empty_scene_and_backlit_and_below_horizon(ctx, oracle_lib):
     assert got.counts.sum() == 0 and np.all(got.maps == (1 << 24) - 1)
 
 
+def _parallel_occluders(seed, n_sun=16):
+    """Six tilted modules, each with two quads parallel to it over part of its face, offset along its
+    normal by a few millimetres to a few centimetres either way and by a few micrometres (a depth unit
+    here is about 1 um): the cases around the depth bias, where a triangle just in front of a module or
+    the module's own triangles must not shade it and one farther in front must."""
+    rng = np.random.default_rng(seed)
+    gen = W.module_rows(2, 3, tilt_deg=float(rng.uniform(10, 40)), pitch=3.0, z0=0.4, modules_per_string=3)
+    n = np.cross(gen.edge_u, gen.edge_v)
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    offs = np.concatenate([rng.uniform(-0.06, 0.06, 8), rng.choice([-1, 1], 4) * rng.uniform(1e-6, 2e-5, 4)])
+    rng.shuffle(offs)
+    quads = []
+    for m in range(gen.n_mod):
+        for q in range(2):
+            a0, a1 = np.sort(rng.uniform(0.0, 1.0, 2))
+            b0, b1 = np.sort(rng.uniform(0.0, 1.0, 2))
+            o = gen.origin[m] + offs[2 * m + q] * n[m]
+            u, v = gen.edge_u[m], gen.edge_v[m]
+            quads.append([o + a0 * u + b0 * v, o + a1 * u + b0 * v, o + a1 * u + b1 * v, o + a0 * u + b1 * v])
+    mesh = W._Mesh()
+    mesh.add(np.array(quads), np.array([[0, 1, 2], [0, 2, 3]]))
+    days = rng.integers(1, 366, n_sun)
+    hours = rng.uniform(6.5, 17.5, n_sun)
+    s = W.cooper_sun(W.LAT_DEG, days, hours)
+    sw = W.Sweep(np.ascontiguousarray(s), np.full(n_sun, 900.0), np.full(n_sun, 80.0), np.full(n_sun, 1.0),
+                 days.astype(np.int32), hours)
+    return W.Workload(f"parallel{seed}", mesh.scene(), gen, sw, 256, 4, "occluders parallel to the modules")
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13, 14])
+def test_occluders_parallel_to_the_modules_near_the_bias(ctx, oracle_lib, seed):
+    """The tile pass leaves out of a module's tests the triangles that lie far enough behind its plane
+    (its own, one just in front within the bias, one behind it); the oracle tests every triangle."""
+    got, _ = compare(ctx, oracle_lib, _parallel_occluders(seed), maps=False, bits=True)
+    assert got.counts.sum() > 0
+
+
 def test_guard_band_clip_path(ctx, oracle_lib):
     """A vertical module seen almost edge-on makes the window very thin, so scene geometry a
     few metres away lies millions of texels out and goes through the guard-band clip."""
