@@ -1182,6 +1182,16 @@ constexpr int kFracCache = 256;
 // memory for each tile was a large part of the tile pass on the rooftop
 // workload (about 21 large triangles per tile).
 constexpr int kLargeCache = 32;
+// Light tiles a wave claims from the work list at a time: one counter per sun
+// serves every wave of the launch, and its device-scope atomics, not the tiles'
+// work, set the pace when waves claim tile by tile. A claim takes one tile per
+// kLightPerClaim light tiles of the sun (rounded up), at most kLightClaimMax, so
+// that a sun takes about a thousand claims: the rooftop year (8,900 light tiles
+// per sun) is fastest at 8 tiles a claim, the row plant (1,400) at 2, and larger
+// claims leave waves idle at the end of a short list.
+constexpr int32_t kLightPerClaim = 1024;
+constexpr int32_t kLightClaimMax = 8;
+
 // Triangle slots a wave of a light tile stages: kLargeCache + 8 kLightBuckets - 1
 // candidates at most.
 constexpr int kWaveSlots = 80;
@@ -2233,6 +2243,8 @@ __device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const Bin
         const ModPlane mp = mod_plane(mm, bm, n);
         const unsigned long long own0 = __ballot(lane < ns && slot_behind(slots[lane], mp, r));
         const unsigned long long own1 = __ballot(lane + 64 < ns && slot_behind(slots[lane + 64], mp, r));
+        const unsigned long long any0 = __ballot(lane < ns), any1 = __ballot(lane + 64 < ns);
+        if (((any0 & ~own0) | (any1 & ~own1)) == 0ull) continue;   // nothing left can shade its samples
         for (int32_t rb = qb0; rb <= qb1; rb += 64) {
             const int32_t qb_l = rb + lane;
             int32_t qa0 = 0, cnt = 0;
@@ -2352,19 +2364,25 @@ __global__ __launch_bounds__(256, 3) void k_tile_g(const SunGroup* __restrict__ 
             // from here on every wave takes its own light tiles; wave 0 starts with `it`
             const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
             TriSlot* slots = reinterpret_cast<TriSlot*>(L.pool) + wv * kWaveSlots;
-            int32_t my = it;
+            // light tiles are claimed several at a time (see kLightPerClaim)
+            const int32_t claim = min(kLightClaimMax, max(1, (n_items - light + kLightPerClaim - 1) / kLightPerClaim));
+            int32_t my = it, end = it + 1;
             if (wv != 0) {
                 int32_t got = 0;
-                if (lane == 0) got = atomicAdd(&S.bb.list_ctr[1], 1);
+                if (lane == 0) got = atomicAdd(&S.bb.list_ctr[1], claim);
                 my = __builtin_amdgcn_readfirstlane(got);
+                end = my + claim;
             }
             if constexpr (TS == 64) {
                 while (my < n_items) {
                     wave_tile<TS>(slots, S.bb.tile_list[my] >> 3, views[S.s], S.bb, L.lcache, n_large, n, S.g,
                                   bias + S.s * S.g.n_mod, L.ftab, L.ftab + knu, k, S.out, S.tmask, lane);
-                    int32_t got = 0;
-                    if (lane == 0) got = atomicAdd(&S.bb.list_ctr[1], 1);
-                    my = __builtin_amdgcn_readfirstlane(got);
+                    if (++my == end) {
+                        int32_t got = 0;
+                        if (lane == 0) got = atomicAdd(&S.bb.list_ctr[1], claim);
+                        my = __builtin_amdgcn_readfirstlane(got);
+                        end = my + claim;
+                    }
                 }
             }
             break;
