@@ -158,7 +158,7 @@ constexpr int kTriBlock = 256;
 // and every launch has a group's work to spread over the GPU. Each sun keeps
 // its own bins, records and outputs; nothing is shared between the suns of a
 // group, so every result is the one the sun gets alone.
-constexpr int kMaxGroup = 8;
+constexpr int kMaxGroup = 16;
 
 // One sun of a group: the descriptors live in device memory, so the kernels
 // take this sun's buffers by reference without copying them.

@@ -287,7 +287,7 @@ def test_c3_rooftop_full_size_sampled_suns(ctx, oracle_lib):
 @pytest.mark.parametrize("which", ["c3", "c2"])
 def test_full_size_production_route_on_24_suns(ctx, oracle_lib, which):
     """The production route (nothing exported but the shaded flags) on every 183rd sun of the
-    year at full size: three groups of eight suns over the two lanes, against the oracle."""
+    year at full size: two groups of twelve suns, one on each lane, against the oracle."""
     yr = W.year_sweep()
     sub = yr.subset(np.arange(0, yr.n, 183))
     w = W.c3_rooftop(sweep=sub) if which == "c3" else W.c2_row_plant(sweep=sub)
