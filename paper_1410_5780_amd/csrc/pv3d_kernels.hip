@@ -2125,8 +2125,9 @@ __device__ __forceinline__ int32_t wave_max(int32_t v) {
 template <int TS>
 __device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const BinBuffers& bb, const TriRec* lrec,
                           int32_t n_large, int32_t n, const GenDev& g, const int32_t* bias, const double* fu_l,
-                          const double* fv_l, int32_t k, const TileOut& out, const uint32_t* tmask, int lane) {
-    if (!V.valid || !mask_has(tmask, tile)) return;        // no sample can fall in this tile
+                          const double* fv_l, int32_t k, const TileOut& out, int lane) {
+    // a listed tile holds bin entries, which only tiles of the tile mask get
+    if (!V.valid) return;
     const Rect r{(tile % bb.ntx) * TS, (tile / bb.ntx) * TS, TS};
     const int32_t bs = min(bb.tile_start[tile], bb.bin_cap), be = min(bb.tile_start[tile + 1], bb.bin_cap);
     const int32_t ne = be - bs;                            // below 8 kLightBuckets: one entry per lane
@@ -2136,18 +2137,20 @@ __device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const Bin
     if (mb == 0ull) return;                                // no module here: nothing to test
     // an upper bound of the samples' thresholds: the module's farthest corner, floored,
     // plus two, less its bias (a sample lies inside its module's corners)
-    int32_t bound = INT32_MIN;
+    // (the corners are read whatever the bias, so both loads are in flight together; a module
+    // lane keeps its bias for the module loops below)
+    int32_t bound = INT32_MIN, bias_l = -1;
     if (is_mod) {
         const int32_t m = -id - 1;
-        const int32_t bm = bias[m];
-        if (bm >= 0) {
-            double zmax = -INFINITY;
-            for (int q = 0; q < 4; q++) {
-                d3 p;
-                module_corner(g.mods[m], q, p);
-                zmax = fmax(zmax, to_light(V, p).z);
-            }
-            const double b = floor(zmax) + 2.0 - (double)bm;
+        double zmax = -INFINITY;
+        for (int q = 0; q < 4; q++) {
+            d3 p;
+            module_corner(g.mods[m], q, p);
+            zmax = fmax(zmax, to_light(V, p).z);
+        }
+        bias_l = bias[m];
+        if (bias_l >= 0) {
+            const double b = floor(zmax) + 2.0 - (double)bias_l;
             bound = b >= 2147483647.0 ? INT32_MAX : (b <= -2147483648.0 ? INT32_MIN : (int32_t)b);
         }
     }
@@ -2202,7 +2205,7 @@ __device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const Bin
             const int src = __ffsll((long long)todo) - 1;
             todo &= todo - 1;
             const int32_t m = -__shfl(id, src, 64) - 1;
-            const int32_t bm = bias[m];
+            const int32_t bm = __shfl(bias_l, src, 64);
             if (bm < 0) continue;
             ModMap mm;
             module_map(V, g.mods[m], mm);
@@ -2252,7 +2255,7 @@ __device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const Bin
         const int src = __ffsll((long long)todo) - 1;
         todo &= todo - 1;
         const int32_t m = -__shfl(id, src, 64) - 1;
-        const int32_t bm = bias[m];
+        const int32_t bm = __shfl(bias_l, src, 64);
         if (bm < 0) continue;                              // back-lit: not tested
         ModMap mm;
         module_map(V, g.mods[m], mm);
@@ -2396,7 +2399,7 @@ __global__ __launch_bounds__(256, 3) void k_tile_g(const SunGroup* __restrict__ 
             if constexpr (TS == 64) {
                 while (my < n_items) {
                     wave_tile<TS>(slots, S.bb.tile_list[my] >> 3, views[S.s], S.bb, L.lcache, n_large, n, S.g,
-                                  bias + S.s * S.g.n_mod, L.ftab, L.ftab + knu, k, S.out, S.tmask, lane);
+                                  bias + S.s * S.g.n_mod, L.ftab, L.ftab + knu, k, S.out, lane);
                     if (++my == end) {
                         int32_t got = 0;
                         if (lane == 0) got = atomicAdd(&S.bb.list_ctr[1], claim);
