@@ -2197,24 +2197,18 @@ __device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const Bin
     }
     if (ns == 0) return;                                   // nothing can shade a sample here
     // nothing either when every staged slot lies behind the plane of every module tested here (its
-    // own triangles, a roof under it; see ModPlane): the common case, settled before the stamp masks
+    // own triangles, a roof under it; see ModPlane): the common case, settled before the stamp masks.
+    // Each module lane tests its own module's plane against every slot (the slot reads are the same
+    // address on every lane), so the modules' terms are read and solved side by side.
     {
-        const unsigned long long any0 = __ballot(lane < ns), any1 = __ballot(lane + 64 < ns);
         bool front = false;
-        for (unsigned long long todo = mb; todo && !front;) {
-            const int src = __ffsll((long long)todo) - 1;
-            todo &= todo - 1;
-            const int32_t m = -__shfl(id, src, 64) - 1;
-            const int32_t bm = __shfl(bias_l, src, 64);
-            if (bm < 0) continue;
+        if (is_mod && bias_l >= 0) {
             ModMap mm;
-            module_map(V, g.mods[m], mm);
-            const ModPlane mp = mod_plane(mm, bm, n);
-            const unsigned long long b0 = __ballot(lane < ns && slot_behind(slots[lane], mp, r));
-            const unsigned long long b1 = __ballot(lane + 64 < ns && slot_behind(slots[lane + 64], mp, r));
-            front = ((any0 & ~b0) | (any1 & ~b1)) != 0ull;
+            module_map(V, g.mods[-id - 1], mm);
+            const ModPlane mp = mod_plane(mm, bias_l, n);
+            for (int32_t u = 0; u < ns && !front; u++) front = !slot_behind(slots[u], mp, r);
         }
-        if (!front) return;
+        if (__ballot(front) == 0ull) return;
     }
     // lane s holds the slots that reach 8 x 8 stamp s of the tile (the stamp's box
     // against the triangle's box, then each edge at the stamp corner farthest inside)
