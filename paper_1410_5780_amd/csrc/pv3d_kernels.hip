@@ -2028,6 +2028,61 @@ __device__ __attribute__((always_inline)) void tile_body(TileLds<TS, CAP>& L, in
         tb.slot = tslots;
         tb.cnt = tcnt;
         tb.list = tlist;
+        // Nothing to count when every triangle that reaches the item's rect lies far enough behind the
+        // plane of every module here (its own triangles, a roof under it; see ModPlane), over the
+        // triangle's box in the rect: settled before any sample is listed. A sub-rect of a later split
+        // holds a part of each box, where the bound still holds.
+        {
+            const int32_t h = TS / 2;
+            const Rect er = part == kWholeTile ? whole : Rect{c.x0 + (part & 1) * h, c.y0 + (part >> 1) * h, h};
+            ModPlane* const planes = reinterpret_cast<ModPlane*>(pool);
+            static_assert(sizeof(ModPlane) * kMaxTileMods <= sizeof(pool), "a plane per module slot in the pool");
+            if (tid < n_mods) {
+                const int32_t m = mods[tid];
+                const int32_t bm = bias[m];
+                ModPlane mp{};
+                mp.lit = true;                            // back-lit: none of its samples is tested
+                if (bm >= 0) {
+                    ModMap mm;
+                    module_map(V, g.mods[m], mm);
+                    mp = mod_plane(mm, bm, n);
+                }
+                planes[tid] = mp;
+            }
+            __syncthreads();
+            const int32_t total = c.n_large + (c.be - c.bs);
+            bool front = false;
+            for (int32_t b0 = 0; b0 < total && !front; b0 += 256) {
+                const int32_t it = b0 + tid;
+                bool fr = false;
+                if (it < total) {
+                    TriRec R;
+                    bool have = it < c.n_lrec;
+                    if (have) {
+                        R = c.lrec[it];
+                    } else {
+                        const int32_t rid = it < c.n_large ? bb.large[it] : bb.bins[c.bs + it - c.n_large];
+                        if (rid >= 0) {
+                            R = bb.rec[rid];
+                            have = true;
+                        }
+                    }
+                    TriClip t;
+                    if (have && clip_to_rect(R, er, t)) {
+                        TriSlot T;
+                        T.zx = R.z0 + R.gx * er.x + R.gy * er.y;
+                        T.gx = R.gx;
+                        T.gy = R.gy;
+                        T.box = (uint32_t)(t.ilo - er.x) | ((uint32_t)(t.ihi - er.x) << 8) |
+                                ((uint32_t)(t.jlo - er.y) << 16) | ((uint32_t)(t.jhi - er.y) << 24);
+                        for (int32_t mi = 0; mi < n_mods && !fr; mi++) fr = !slot_behind(T, planes[mi], er);
+                    }
+                }
+                front = __syncthreads_or(fr) != 0;
+            }
+            if (!front) return;
+            __syncthreads();                              // the pool takes the sample lists next
+        }
         if (tid == 0) {                               // rects of at most 64 x 64 texels (one lane per 8x8 stamp)
             n_todo = 0;
             if (part != kWholeTile) {
