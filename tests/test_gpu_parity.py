@@ -136,11 +136,13 @@ def test_empty_scene_and_backlit_and_below_horizon(ctx, oracle_lib):
     assert got.counts.sum() == 0 and np.all(got.maps == (1 << 24) - 1)
 
 
-def _parallel_occluders(seed, n_sun=16):
+def _parallel_occluders(seed, n_sun=16, split=1):
     """Six tilted modules, each with two quads parallel to it over part of its face, offset along its
     normal by a few millimetres to a few centimetres either way and by a few micrometres (a depth unit
     here is about 1 um): the cases around the depth bias, where a triangle just in front of a module or
-    the module's own triangles must not shade it and one farther in front must."""
+    the module's own triangles must not shade it and one farther in front must. With split > 1 every
+    quad is cut into split x split smaller ones, so that a tile holds enough entries to go to the
+    workgroup route."""
     rng = np.random.default_rng(seed)
     gen = W.module_rows(2, 3, tilt_deg=float(rng.uniform(10, 40)), pitch=3.0, z0=0.4, modules_per_string=3)
     n = np.cross(gen.edge_u, gen.edge_v)
@@ -154,7 +156,11 @@ def _parallel_occluders(seed, n_sun=16):
             b0, b1 = np.sort(rng.uniform(0.0, 1.0, 2))
             o = gen.origin[m] + offs[2 * m + q] * n[m]
             u, v = gen.edge_u[m], gen.edge_v[m]
-            quads.append([o + a0 * u + b0 * v, o + a1 * u + b0 * v, o + a1 * u + b1 * v, o + a0 * u + b1 * v])
+            ga, gb = np.linspace(a0, a1, split + 1), np.linspace(b0, b1, split + 1)
+            for i in range(split):
+                for j in range(split):
+                    quads.append([o + ga[i] * u + gb[j] * v, o + ga[i + 1] * u + gb[j] * v,
+                                  o + ga[i + 1] * u + gb[j + 1] * v, o + ga[i] * u + gb[j + 1] * v])
     mesh = W._Mesh()
     mesh.add(np.array(quads), np.array([[0, 1, 2], [0, 2, 3]]))
     days = rng.integers(1, 366, n_sun)
@@ -162,7 +168,7 @@ def _parallel_occluders(seed, n_sun=16):
     s = W.cooper_sun(W.LAT_DEG, days, hours)
     sw = W.Sweep(np.ascontiguousarray(s), np.full(n_sun, 900.0), np.full(n_sun, 80.0), np.full(n_sun, 1.0),
                  days.astype(np.int32), hours)
-    return W.Workload(f"parallel{seed}", mesh.scene(), gen, sw, 256, 4, "occluders parallel to the modules")
+    return W.Workload(f"parallel{seed}x{split}", mesh.scene(), gen, sw, 256, 4, "occluders parallel to the modules")
 
 
 @pytest.mark.parametrize("seed", [11, 12, 13, 14])
@@ -170,6 +176,15 @@ def test_occluders_parallel_to_the_modules_near_the_bias(ctx, oracle_lib, seed):
     """The tile pass leaves out of a module's tests the triangles that lie far enough behind its plane
     (its own, one just in front within the bias, one behind it); the oracle tests every triangle."""
     got, _ = compare(ctx, oracle_lib, _parallel_occluders(seed), maps=False, bits=True)
+    assert got.counts.sum() > 0
+
+
+@pytest.mark.parametrize("seed", [21, 22])
+def test_dense_occluders_parallel_to_the_modules_near_the_bias(ctx, oracle_lib, seed):
+    """The same occluders cut into 64 quads each (up to about 256 bin entries per tile): the
+    workgroup route's early return, which drops a tile when every triangle reaching it lies behind
+    the plane of every module there, against the oracle."""
+    got, _ = compare(ctx, oracle_lib, _parallel_occluders(seed, split=8), maps=False, bits=True)
     assert got.counts.sum() > 0
 
 
