@@ -160,6 +160,13 @@ constexpr int kTriBlock = 256;
 // group, so every result is the one the sun gets alone.
 constexpr int kMaxGroup = 16;
 
+// Head of a sun's work list: item count, next item, first light item (words 0-2), then a
+// light-tile counter per XCD at words kXcdStride (j + 1), 128 bytes apart; the items follow
+// at word kListHead.
+constexpr int kXcds = 8;
+constexpr int kXcdStride = 32;
+constexpr int kListHead = kXcdStride * (kXcds + 1);
+
 // One sun of a group: the descriptors live in device memory, so the kernels
 // take this sun's buffers by reference without copying them.
 struct GroupSun {

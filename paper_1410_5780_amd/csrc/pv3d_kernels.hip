@@ -446,6 +446,9 @@ __device__ __forceinline__ int32_t block_scan_excl(int32_t v, int32_t* wsum, int
     return base + x - v;
 }
 
+// The XCD the wave runs on.
+__device__ __forceinline__ int32_t xcc_id() { return (int32_t)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20); }
+
 // Lanes of the wave below this one whose bit is set.
 __device__ __forceinline__ int32_t lanes_below(unsigned long long bal) {
     return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
@@ -969,6 +972,7 @@ __global__ __launch_bounds__(NT) void k_bin_scan_g(const SunGroup* __restrict__ 
         bb.list_ctr[0] = n_items;
         bb.list_ctr[1] = 0;
         bb.list_ctr[2] = bb.split_at >= 0 ? part[1] : n_items;   // first light item
+        for (int j = 0; j < kXcds; j++) bb.list_ctr[kXcdStride * (j + 1)] = 0;
     }
 }
 
@@ -1182,15 +1186,17 @@ constexpr int kFracCache = 256;
 // memory for each tile was a large part of the tile pass on the rooftop
 // workload (about 21 large triangles per tile).
 constexpr int kLargeCache = 32;
-// Light tiles a wave claims from the work list at a time: one counter per sun
-// serves every wave of the launch, and its device-scope atomics, not the tiles'
-// work, set the pace when waves claim tile by tile. A claim takes one tile per
-// kLightPerClaim light tiles of the sun (rounded up), at most kLightClaimMax, so
-// that a sun takes about a thousand claims: the rooftop year (8,900 light tiles
-// per sun) is fastest at 8 tiles a claim, the row plant (1,400) at 2, and larger
-// claims leave waves idle at the end of a short list.
-constexpr int32_t kLightPerClaim = 1024;
-constexpr int32_t kLightClaimMax = 8;
+// Light tiles a wave claims at a time. A sun's light tiles form kXcds strided
+// sub-lists with a counter each (128 bytes apart): the waves of an XCD claim
+// from their own sub-list, then help with the others. With one counter for every
+// wave of the launch its device-scope atomics, not the tiles' work, set the
+// pace when waves claimed tile by tile; each claim's round trip also stalls its
+// wave, and large claims leave waves idle at the end of a short list. A claim
+// takes one tile per kLightPerClaim tiles of the sub-list (rounded up), at most
+// kLightClaimMax: 9 on the rooftop (about 1,100 light tiles per sub-list and
+// sun), 2 on the row plant (about 180).
+constexpr int32_t kLightPerClaim = 128;
+constexpr int32_t kLightClaimMax = 16;
 
 // Triangle slots a wave of a light tile stages: kLargeCache + 8 kLightBuckets - 1
 // candidates at most.
@@ -2433,27 +2439,30 @@ __global__ __launch_bounds__(256, 3) void k_tile_g(const SunGroup* __restrict__ 
                 __syncthreads();
                 continue;
             }
-            // from here on every wave takes its own light tiles; wave 0 starts with `it`
+            // from here on every wave takes its own light tiles from the XCD sub-lists (an item
+            // taken above from the shared counter is left to them)
             const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
             TriSlot* slots = reinterpret_cast<TriSlot*>(L.pool) + wv * kWaveSlots;
-            // light tiles are claimed several at a time (see kLightPerClaim)
-            const int32_t claim = min(kLightClaimMax, max(1, (n_items - light + kLightPerClaim - 1) / kLightPerClaim));
-            int32_t my = it, end = it + 1;
-            if (wv != 0) {
-                int32_t got = 0;
-                if (lane == 0) got = atomicAdd(&S.bb.list_ctr[1], claim);
-                my = __builtin_amdgcn_readfirstlane(got);
-                end = my + claim;
-            }
             if constexpr (TS == 64) {
-                while (my < n_items) {
-                    wave_tile<TS>(slots, S.bb.tile_list[my] >> 3, views[S.s], S.bb, L.lcache, n_large, n, S.g,
-                                  bias + S.s * S.g.n_mod, L.ftab, L.ftab + knu, k, S.out, lane);
-                    if (++my == end) {
+                const int32_t n_light = n_items - light;
+                const int32_t per_sub = (n_light + kXcds - 1) / kXcds;
+                const int32_t claim = min(kLightClaimMax, max(1, (per_sub + kLightPerClaim - 1) / kLightPerClaim));
+                const int32_t x0 = xcc_id();
+                for (int32_t d = 0; d < kXcds; d++) {
+                    const int32_t j = (x0 + d) % kXcds;
+                    const int32_t n_j = n_light > j ? (n_light - j + kXcds - 1) / kXcds : 0;   // items light + j + kXcds i
+                    int32_t* const ctr_j = &S.bb.list_ctr[kXcdStride * (j + 1)];
+                    if (ld_dev(ctr_j) >= n_j) continue;           // taken already: no atomic
+                    for (;;) {
                         int32_t got = 0;
-                        if (lane == 0) got = atomicAdd(&S.bb.list_ctr[1], claim);
-                        my = __builtin_amdgcn_readfirstlane(got);
-                        end = my + claim;
+                        if (lane == 0) got = atomicAdd(ctr_j, claim);
+                        const int32_t my0 = __builtin_amdgcn_readfirstlane(got);
+                        if (my0 >= n_j) break;
+                        const int32_t my1 = min(my0 + claim, n_j);
+                        for (int32_t i = my0; i < my1; i++)
+                            wave_tile<TS>(slots, S.bb.tile_list[light + j + kXcds * i] >> 3, views[S.s], S.bb, L.lcache,
+                                          n_large, n, S.g, bias + S.s * S.g.n_mod, L.ftab, L.ftab + knu, k, S.out, lane);
+                        if (my1 == n_j) break;                    // this claim reached the end
                     }
                 }
             }
@@ -3248,7 +3257,6 @@ constexpr int kWaitVmem = 0x0F70;
 constexpr int32_t kPollers = 8;
 constexpr long long kPollTicks = 200;
 
-__device__ __forceinline__ int32_t xcc_id() { return (int32_t)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20); }
 
 struct PCtl {
     int32_t slot, unit, phase, units;

@@ -343,7 +343,7 @@ PathSizes path_sizes(const Scene& sc, const Gen& g, const pv3d_params& p, int64_
 // list, pair items and chunks, module boxes).
 size_t lane_bytes_per_sun(const PathSizes& z, const Gen& g) {
     return sizeof(TriRec) * (size_t)z.rec_cap + 4 * (size_t)z.rec_cap + 4 * (size_t)z.bin_cap +
-           4 * (size_t)(3 * (int64_t)z.n_tiles + 1) + 4 * (4 * (size_t)z.n_tiles + 4) +
+           4 * (size_t)(3 * (int64_t)z.n_tiles + 1) + 4 * (4 * (size_t)z.n_tiles + kListHead) +
            sizeof(PairItem) * (size_t)z.item_cap + 4 * (size_t)z.chunk_cap + 16 * (size_t)g.n_mod + 6 * 256;
 }
 
@@ -373,7 +373,7 @@ static void lane_buf_sizes(const PathSizes& z, const Gen& g, int32_t map_n, bool
     b[3] = G * 4 * (size_t)z.n_tiles;
     b[4] = G * 4 * (size_t)(z.n_tiles + 1);
     b[5] = G * 4 * (size_t)z.n_tiles;
-    b[6] = G * 4 * (4 * (size_t)z.n_tiles + 4);
+    b[6] = G * 4 * (4 * (size_t)z.n_tiles + kListHead);
     b[7] = G * sizeof(PairItem) * (size_t)z.item_cap;
     b[8] = G * 4 * (size_t)z.chunk_cap;
     b[9] = G * 16 * (size_t)g.n_mod;
@@ -661,9 +661,9 @@ pv3d_status Ctx::run_path(const Scene& sc, const Gen& g, const pv3d_params& p, c
         GroupSun& S = grp.sun[q];
         S.bb = bin_buffers(z, lane, q);
         if (sparse) {      // the scan lists the tiles with work, heaviest first; 64-texel ones split in quadrants
-            int32_t* tl = static_cast<int32_t*>(w.lane[lane].tile_list.ptr) + (size_t)q * (4 * (size_t)z.n_tiles + 4);
+            int32_t* tl = static_cast<int32_t*>(w.lane[lane].tile_list.ptr) + (size_t)q * (4 * (size_t)z.n_tiles + kListHead);
             S.bb.list_ctr = tl;
-            S.bb.tile_list = tl + 4;          // list_ctr: items, next item, first light item
+            S.bb.tile_list = tl + kListHead;  // list_ctr: items, next item, first light item, XCD counters
             S.bb.split_at = z.tile == 64 ? kSplitEntries : 0;
         }
         S.bb.pctr = &ctr[s].pairs;
