@@ -2453,16 +2453,20 @@ __global__ __launch_bounds__(256, 3) void k_tile_g(const SunGroup* __restrict__ 
                     const int32_t n_j = n_light > j ? (n_light - j + kXcds - 1) / kXcds : 0;   // items light + j + kXcds i
                     int32_t* const ctr_j = &S.bb.list_ctr[kXcdStride * (j + 1)];
                     if (ld_dev(ctr_j) >= n_j) continue;           // taken already: no atomic
-                    for (;;) {
-                        int32_t got = 0;
-                        if (lane == 0) got = atomicAdd(ctr_j, claim);
-                        const int32_t my0 = __builtin_amdgcn_readfirstlane(got);
-                        if (my0 >= n_j) break;
+                    int32_t got = 0;
+                    if (lane == 0) got = atomicAdd(ctr_j, claim);
+                    int32_t my0 = __builtin_amdgcn_readfirstlane(got);
+                    while (my0 < n_j) {
                         const int32_t my1 = min(my0 + claim, n_j);
-                        for (int32_t i = my0; i < my1; i++)
+                        // the next claim goes out with the claim's last tile, so that its round trip
+                        // overlaps the tile's own reads (none when this claim reached the end)
+                        for (int32_t i = my0; i < my1; i++) {
+                            if (i == my1 - 1 && my1 < n_j && lane == 0) got = atomicAdd(ctr_j, claim);
                             wave_tile<TS>(slots, S.bb.tile_list[light + j + kXcds * i] >> 3, views[S.s], S.bb, L.lcache,
                                           n_large, n, S.g, bias + S.s * S.g.n_mod, L.ftab, L.ftab + knu, k, S.out, lane);
-                        if (my1 == n_j) break;                    // this claim reached the end
+                        }
+                        if (my1 == n_j) break;
+                        my0 = __builtin_amdgcn_readfirstlane(got);
                     }
                 }
             }
