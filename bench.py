@@ -434,11 +434,20 @@ def sky_leg(ctx, log, n_dir=145):
             "energy_loss_beam_only": base.loss, "energy_loss_with_diffuse": r.loss}
 
 
+def highest_flat_rate(sweep):
+    """The highest swept arrival rate whose p99 stays within twice the lowest p99 of the sweep
+    (a straggler at one rate does not move the reference of the others)."""
+    if not sweep:
+        return None
+    ref = min(x["p99_ms"] for x in sweep)
+    return max(x["rate_hz"] for x in sweep if x["p99_ms"] <= 2.0 * ref)
+
+
 def serving_leg(ctx, log, rate_hz, duration_s, light_rate, light_s, sweep_n):
     """Poisson request streams through the serving loop: latency from arrival to completion.
     The configured stream (200 req/s) offers more than one GPU evaluates, so it reports the
     offered and the sustained rates; a sweep below the sustained rate finds the highest
-    arrival rate at which p99 stays within twice its value at the lightest swept rate."""
+    arrival rate at which p99 stays within twice the lowest p99 of the sweep."""
     from paper_1410_5780_amd import serve, workloads as W
     out = {}
     reqs = W.serving_stream(seed=5, rate_hz=rate_hz, duration_s=duration_s)
@@ -468,9 +477,8 @@ def serving_leg(ctx, log, rate_hz, duration_s, light_rate, light_s, sweep_n):
             sweep.append({"rate_hz": rate, "requests": rs["requests"], "p50_ms": rs["p50_ms"], "p99_ms": rs["p99_ms"],
                           "sustained_req_per_s": rs["requests"] / rs["wall_s"]})
             log(f"[bench] serving sweep {rate:.1f} req/s: p50 {rs['p50_ms']:.1f} ms, p99 {rs['p99_ms']:.1f} ms")
-        flat = [x for x in sweep if sweep and x["p99_ms"] <= 2.0 * sweep[0]["p99_ms"]]
         out["rate_sweep"] = sweep
-        out["highest_flat_p99_rate_hz"] = max(x["rate_hz"] for x in flat) if flat else None
+        out["highest_flat_p99_rate_hz"] = highest_flat_rate(sweep)
     return out
 
 

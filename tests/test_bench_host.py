@@ -66,3 +66,12 @@ def test_committed_profile_matches_the_kernel_source():
     traffic figure is a measured one (regenerate the summary after any change to the kernels)."""
     got = bench.measured_traffic("raster", "sparse", WL)
     assert isinstance(got, int) and got > 0
+
+
+def test_highest_flat_rate_ignores_a_straggler_at_the_lightest_rate():
+    import bench
+    sweep = [{"rate_hz": 20.0, "p99_ms": 22313.0}, {"rate_hz": 40.0, "p99_ms": 39.7},
+             {"rate_hz": 60.0, "p99_ms": 154.8}]
+    assert bench.highest_flat_rate(sweep) == 40.0
+    assert bench.highest_flat_rate([{"rate_hz": 10.0, "p99_ms": 5.0}, {"rate_hz": 30.0, "p99_ms": 9.9}]) == 30.0
+    assert bench.highest_flat_rate([]) is None
