@@ -2184,7 +2184,7 @@ __device__ __forceinline__ int32_t wave_max(int32_t v) {
 }
 
 template <int TS>
-__device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const BinBuffers& bb, const TriRec* lrec,
+__device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const BinBuffers& bb,
                           int32_t n_large, int32_t n, const GenDev& g, const int32_t* bias, const double* fu_l,
                           const double* fv_l, int32_t k, const TileOut& out, int lane) {
     // a listed tile holds bin entries, which only tiles of the tile mask get
@@ -2227,7 +2227,7 @@ __device__ void wave_tile(TriSlot* slots, int32_t tile, const View& V, const Bin
         TriRec R;
         TriClip t;
         if (ci < n_large) {
-            R = lrec[ci];
+            R = bb.rec[bb.large[ci]];
             keep = true;
         } else if (ci < n_cand && rid >= 0) {
             R = bb.rec[rid];
@@ -2412,65 +2412,72 @@ __global__ __launch_bounds__(256, 3) void k_tile_g(const SunGroup* __restrict__ 
     const bool lds_tables = knu + knv <= kFracCache;
     if (lds_tables)
         for (int32_t u = threadIdx.x; u < knu + knv; u += 256) L.ftab[u] = u < knu ? fu_tab[u] : fv_tab[u - knu];
+    // The heavy items of every sun first, a workgroup each; then the light tiles of every sun, a
+    // wave each, with no barrier between suns: the light route reads the sun's large triangles
+    // from memory, so nothing in LDS changes with the sun.
     for (int32_t q = 0; q < ng; q++) {
         const GroupSun& S = grp->sun[q];
         const int32_t n_items = S.bb.list_ctr[0];
         const int32_t n_large = ctr[S.s].n_large;
         const int32_t n_lc = min(n_large, kLargeCache);
-        __syncthreads();                              // the previous sun's tiles are done with the cache
+        // light tiles (the list's tail) go one wave each when the sample fractions are in LDS and
+        // the large list is short enough for a wave's slots
+        const int32_t light = (TS == 64 && n_large <= kLargeCache && lds_tables) ? S.bb.list_ctr[2] : n_items;
+        if (light == 0) continue;
+        __syncthreads();                              // the previous sun's items are done with the cache
         static_assert(sizeof(TriRec) % 16 == 0, "records copy in 16-byte pieces");
         constexpr int kPieces = sizeof(TriRec) / 16;
         for (int32_t u = threadIdx.x; u < n_lc * kPieces; u += 256)
             reinterpret_cast<uint4*>(L.lcache)[u] =
                 reinterpret_cast<const uint4*>(S.bb.rec + S.bb.large[u / kPieces])[u % kPieces];
         __syncthreads();
-        // light tiles (the list's tail) go one wave each when their large list and the sample
-        // fractions are in LDS
-        const int32_t light = (TS == 64 && n_large <= kLargeCache && lds_tables) ? S.bb.list_ctr[2] : n_items;
         for (;;) {
             if (threadIdx.x == 0) take = atomicAdd(&S.bb.list_ctr[1], 1);
             __syncthreads();
             const int32_t it = take;
             __syncthreads();
-            if (it >= n_items) break;
-            if (it < light) {
-                tile_body<TS, CAP>(L, S.bb.tile_list[it], n_lc, lds_tables, views[S.s], S.bb, n_large, n, S.g,
-                                   bias + S.s * S.g.n_mod, fu_tab, fv_tab, k, S.out, S.out.sparse, S.tmask);
-                __syncthreads();
-                continue;
-            }
-            // from here on every wave takes its own light tiles from the XCD sub-lists (an item
-            // taken above from the shared counter is left to them)
-            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-            TriSlot* slots = reinterpret_cast<TriSlot*>(L.pool) + wv * kWaveSlots;
-            if constexpr (TS == 64) {
-                const int32_t n_light = n_items - light;
-                const int32_t per_sub = (n_light + kXcds - 1) / kXcds;
-                const int32_t claim = min(kLightClaimMax, max(1, (per_sub + kLightPerClaim - 1) / kLightPerClaim));
-                const int32_t x0 = xcc_id();
-                for (int32_t d = 0; d < kXcds; d++) {
-                    const int32_t j = (x0 + d) % kXcds;
-                    const int32_t n_j = n_light > j ? (n_light - j + kXcds - 1) / kXcds : 0;   // items light + j + kXcds i
-                    int32_t* const ctr_j = &S.bb.list_ctr[kXcdStride * (j + 1)];
-                    if (ld_dev(ctr_j) >= n_j) continue;           // taken already: no atomic
-                    int32_t got = 0;
-                    if (lane == 0) got = atomicAdd(ctr_j, claim);
-                    int32_t my0 = __builtin_amdgcn_readfirstlane(got);
-                    while (my0 < n_j) {
-                        const int32_t my1 = min(my0 + claim, n_j);
-                        // the next claim goes out with the claim's last tile, so that its round trip
-                        // overlaps the tile's own reads (none when this claim reached the end)
-                        for (int32_t i = my0; i < my1; i++) {
-                            if (i == my1 - 1 && my1 < n_j && lane == 0) got = atomicAdd(ctr_j, claim);
-                            wave_tile<TS>(slots, S.bb.tile_list[light + j + kXcds * i] >> 3, views[S.s], S.bb, L.lcache,
-                                          n_large, n, S.g, bias + S.s * S.g.n_mod, L.ftab, L.ftab + knu, k, S.out, lane);
-                        }
-                        if (my1 == n_j) break;
-                        my0 = __builtin_amdgcn_readfirstlane(got);
+            if (it >= light) break;                   // the rest are the light pass's
+            tile_body<TS, CAP>(L, S.bb.tile_list[it], n_lc, lds_tables, views[S.s], S.bb, n_large, n, S.g,
+                               bias + S.s * S.g.n_mod, fu_tab, fv_tab, k, S.out, S.out.sparse, S.tmask);
+            __syncthreads();
+        }
+    }
+    if constexpr (TS == 64) {
+        if (!lds_tables) return;
+        __syncthreads();                              // the fraction tables are in place (no barrier above when no sun had heavy items)
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        TriSlot* slots = reinterpret_cast<TriSlot*>(L.pool) + wv * kWaveSlots;
+        const int32_t x0 = xcc_id();
+        for (int32_t q = 0; q < ng; q++) {
+            const GroupSun& S = grp->sun[q];
+            const int32_t n_items = S.bb.list_ctr[0];
+            if (ctr[S.s].n_large > kLargeCache) continue;   // every item was the workgroups'
+            const int32_t light = S.bb.list_ctr[2];
+            // the light items from their XCD sub-lists
+            const int32_t n_light = n_items - light;
+            const int32_t per_sub = (n_light + kXcds - 1) / kXcds;
+            const int32_t claim = min(kLightClaimMax, max(1, (per_sub + kLightPerClaim - 1) / kLightPerClaim));
+            for (int32_t d = 0; d < kXcds; d++) {
+                const int32_t j = (x0 + d) % kXcds;
+                const int32_t n_j = n_light > j ? (n_light - j + kXcds - 1) / kXcds : 0;   // items light + j + kXcds i
+                int32_t* const ctr_j = &S.bb.list_ctr[kXcdStride * (j + 1)];
+                if (ld_dev(ctr_j) >= n_j) continue;           // taken already: no atomic
+                int32_t got = 0;
+                if (lane == 0) got = atomicAdd(ctr_j, claim);
+                int32_t my0 = __builtin_amdgcn_readfirstlane(got);
+                while (my0 < n_j) {
+                    const int32_t my1 = min(my0 + claim, n_j);
+                    // the next claim goes out with the claim's last tile, so that its round trip
+                    // overlaps the tile's own reads (none when this claim reached the end)
+                    for (int32_t i = my0; i < my1; i++) {
+                        if (i == my1 - 1 && my1 < n_j && lane == 0) got = atomicAdd(ctr_j, claim);
+                        wave_tile<TS>(slots, S.bb.tile_list[light + j + kXcds * i] >> 3, views[S.s], S.bb, ctr[S.s].n_large,
+                                      n, S.g, bias + S.s * S.g.n_mod, L.ftab, L.ftab + knu, k, S.out, lane);
                     }
+                    if (my1 == n_j) break;
+                    my0 = __builtin_amdgcn_readfirstlane(got);
                 }
             }
-            break;
         }
     }
 }
