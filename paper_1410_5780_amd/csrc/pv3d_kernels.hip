@@ -2414,8 +2414,11 @@ __global__ __launch_bounds__(256, 3) void k_tile_g(const SunGroup* __restrict__ 
         for (int32_t u = threadIdx.x; u < knu + knv; u += 256) L.ftab[u] = u < knu ? fu_tab[u] : fv_tab[u - knu];
     // The heavy items of every sun first, a workgroup each; then the light tiles of every sun, a
     // wave each, with no barrier between suns: the light route reads the sun's large triangles
-    // from memory, so nothing in LDS changes with the sun.
-    for (int32_t q = 0; q < ng; q++) {
+    // from memory, so nothing in LDS changes with the sun. Each workgroup starts at a sun of its
+    // own (its index modulo the group), so the suns' counters share the claims of the moment.
+    const int32_t q0 = (int32_t)blockIdx.x % ng;
+    for (int32_t qq = 0; qq < ng; qq++) {
+        const int32_t q = (q0 + qq) % ng;
         const GroupSun& S = grp->sun[q];
         const int32_t n_items = S.bb.list_ctr[0];
         const int32_t n_large = ctr[S.s].n_large;
@@ -2448,7 +2451,8 @@ __global__ __launch_bounds__(256, 3) void k_tile_g(const SunGroup* __restrict__ 
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         TriSlot* slots = reinterpret_cast<TriSlot*>(L.pool) + wv * kWaveSlots;
         const int32_t x0 = xcc_id();
-        for (int32_t q = 0; q < ng; q++) {
+        for (int32_t qq = 0; qq < ng; qq++) {
+            const int32_t q = (q0 + qq) % ng;
             const GroupSun& S = grp->sun[q];
             const int32_t n_items = S.bb.list_ctr[0];
             if (ctr[S.s].n_large > kLargeCache) continue;   // every item was the workgroups'
