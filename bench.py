@@ -5,7 +5,7 @@ A step is one whole year of the rooftop BIPV workload (2,000 flat modules,
 120,000 cells, on a roof among 200 buildings and 1,000 trees, 522,010
 triangles, 8192 x 8192 depth picture, 8 x 8 samples per cell, the 4,379 suns
 above the horizon at 40.4 N), evaluated through the C ABI (pv3d_evaluate,
-suns in groups of up to sixteen per launch sequence) with device-resident inputs
+suns in groups of up to 32 per launch sequence) with device-resident inputs
 and outputs: view set-up, triangle set-up and binning, raster, sample depth
 check, bypass-diode losses and the energy sums all run on the GPU.
 
@@ -574,7 +574,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {w.note}; {n_sun} suns per step, per-sun path (groups of up to 16 suns "
+        "config": {"workload": f"{w.name}: {w.note}; {n_sun} suns per step, per-sun path (groups of up to 32 suns "
                                f"per launch sequence)",
                    "route": a.route,
                    "triangles": w.n_tri_submitted, "cells": w.gen.n_cells, "samples_per_sun": w.n_samples,

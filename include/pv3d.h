@@ -216,7 +216,7 @@ typedef struct {
 } pv3d_outputs;
 
 /* Evaluate one generator in one scene for a sweep of sun positions: the suns
- * above the horizon in groups of up to sixteen per launch sequence (set-up,
+ * above the horizon in groups of up to 32 per launch sequence (set-up,
  * binning, tile pass), then one loss launch over the sweep and the energy sums
  * in sun order. Results do not depend on the grouping.
  * sun_xyz: [n_sun][3] unit vectors toward the sun (|s| = 1 within 1e-9);
@@ -434,7 +434,7 @@ pv3d_status pv3d_profile_read(pv3d_ctx* ctx, int32_t stage, double* total_ms, in
 /* The time during which at least one timed launch of the stage ran (the
  * union of their event intervals, so launches of the two lanes that overlap
  * count once: the stage's exclusive share of the sweep), in milliseconds, and
- * the suns those launches covered (a launch covers a group of up to 16 suns).
+ * the suns those launches covered (a launch covers a group of up to 32 suns).
  * Meaningful when every launch is timed (pv3d_profile_sample 1). Waits for
  * the recorded work. EINVAL: bad stage. */
 pv3d_status pv3d_profile_busy(pv3d_ctx* ctx, int32_t stage, double* busy_ms, int64_t* suns);

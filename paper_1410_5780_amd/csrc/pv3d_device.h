@@ -158,7 +158,7 @@ constexpr int kTriBlock = 256;
 // and every launch has a group's work to spread over the GPU. Each sun keeps
 // its own bins, records and outputs; nothing is shared between the suns of a
 // group, so every result is the one the sun gets alone.
-constexpr int kMaxGroup = 16;
+constexpr int kMaxGroup = 32;
 
 // Head of a sun's work list: item count, next item, first light item (words 0-2), then a
 // light-tile counter per XCD at words kXcdStride (j + 1), 128 bytes apart; the items follow
