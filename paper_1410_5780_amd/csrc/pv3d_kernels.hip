@@ -1192,10 +1192,11 @@ constexpr int kLargeCache = 32;
 // wave of the launch its device-scope atomics, not the tiles' work, set the
 // pace when waves claimed tile by tile; each claim's round trip also stalls its
 // wave, and large claims leave waves idle at the end of a short list. A claim
-// takes one tile per kLightPerClaim tiles of the sub-list (rounded up), at most
-// kLightClaimMax: 9 on the rooftop (about 1,100 light tiles per sub-list and
-// sun), 2 on the row plant (about 180).
-constexpr int32_t kLightPerClaim = 128;
+// takes one tile per kLightPerClaim tiles of the sub-list (rounded up), at least
+// kLightClaimMin and at most kLightClaimMax: 5 on the rooftop (about 1,100
+// light tiles per sub-list and sun), 2 on the row plant (about 180).
+constexpr int32_t kLightPerClaim = 256;
+constexpr int32_t kLightClaimMin = 2;
 constexpr int32_t kLightClaimMax = 16;
 
 // Triangle slots a wave of a light tile stages: kLargeCache + 8 kLightBuckets - 1
@@ -2460,7 +2461,7 @@ __global__ __launch_bounds__(256, 3) void k_tile_g(const SunGroup* __restrict__ 
             // the light items from their XCD sub-lists
             const int32_t n_light = n_items - light;
             const int32_t per_sub = (n_light + kXcds - 1) / kXcds;
-            const int32_t claim = min(kLightClaimMax, max(1, (per_sub + kLightPerClaim - 1) / kLightPerClaim));
+            const int32_t claim = min(kLightClaimMax, max(kLightClaimMin, (per_sub + kLightPerClaim - 1) / kLightPerClaim));
             for (int32_t d = 0; d < kXcds; d++) {
                 const int32_t j = (x0 + d) % kXcds;
                 const int32_t n_j = n_light > j ? (n_light - j + kXcds - 1) / kXcds : 0;   // items light + j + kXcds i
