@@ -99,7 +99,10 @@ def run_stream(ctx: pv3d.Context, reqs: List[W.Request], seed: int = 5, k: int =
                     del outstanding[t]
             if log and time.perf_counter() - last > 2.0:
                 last = time.perf_counter()
-                log(f"[serve] {len(done)} of {len(reqs)} done, {len(outstanding)} running or waiting")
+                st = ctx.serve_stats()
+                log(f"[serve] {len(done)} of {len(reqs)} done, {len(outstanding)} running or waiting; loop: "
+                    f"{st['jobs_done']} jobs done, {st['launches']} launches, {st['items']} items, "
+                    f"{st['pending']} pending admission")
             time.sleep(poll_s)
 
     th = threading.Thread(target=watcher, daemon=True)
